@@ -1,0 +1,137 @@
+"""Pins of oracle.constraints, oracle.lowprec, oracle.costmodel, oracle.polish."""
+import math
+
+import numpy as np
+import pytest
+
+import tlsgen
+from oracle import constraints, lowprec, costmodel, polish, exact, rqi
+
+
+# values printed in Section 4 for constraints (5) and (6) on the model problems
+PRINTED = {
+    "paper_random": (2e-2, 4e-3),
+    "paper_delta": (9e-3, 1e-3),
+    "paper_bjorck": (4e-2, None),      # (6) depends on the instance's gap
+    "paper_vanhuffel": (2e-1, 5e-3),
+}
+
+
+@pytest.mark.parametrize("gen", sorted(PRINTED))
+def test_constraint_magnitudes_match_printed(gen):
+    A, b = getattr(tlsgen, gen)()
+    bd = constraints.bounds(A, b)
+    p5, p6 = PRINTED[gen]
+    assert abs(math.log10(bd.bound5 / p5)) < math.log10(3.0)
+    if p6 is not None:
+        assert abs(math.log10(bd.bound6 / p6)) < math.log10(3.0)
+    # (6) is never looser than (5)'s kappa_F analogue
+    assert bd.bound6 <= 1.0 / bd.kappa_F * (1 + 1e-12)
+    # half precision passes both constraints on these problems (Section 4)
+    if p6 is not None:
+        assert constraints.UNIT_ROUNDOFF["fp16"] < bd.bound6
+
+
+def test_unit_roundoffs_table2():
+    u = constraints.UNIT_ROUNDOFF
+    assert abs(u["fp16"] - 4.88e-4) < 0.01e-4
+    assert abs(u["fp32"] - 5.96e-8) < 0.01e-8
+    assert abs(u["fp64"] - 1.11e-16) < 0.01e-16
+    assert abs(u["fp128"] - 9.63e-35) < 0.01e-35
+
+
+def test_round_fp16_is_ieee_rne():
+    g = np.random.default_rng(0)
+    x = np.concatenate([g.standard_normal(20000) * 10.0 ** g.uniform(-9, 5, 20000),
+                        # exact ties between fp16 neighbours
+                        (np.arange(1, 2000) + 0.5) * 2.0 ** -10,
+                        np.array([65504.0, 65519.0, 65520.0, 1e6, 5.96e-8, 2.98e-8, 2.99e-8])])
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).astype(np.float64)
+    got = lowprec.round_to(x, "fp16")
+    assert np.array_equal(got, ref)
+
+
+def test_round_bf16_nearest_even():
+    g = np.random.default_rng(1)
+    x = g.standard_normal(20000) * 10.0 ** g.uniform(-30, 30, 20000)
+    got = lowprec.round_to(x, "bf16")
+    bits = got.astype(np.float32).view(np.uint32)
+    assert np.all(bits & 0xFFFF == 0)                    # representable in bf16
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+    up = (bits + 0x10000).view(np.float32).astype(np.float64)
+    dn = (bits - 0x10000).view(np.float32).astype(np.float64)
+    e = np.abs(got - x)
+    assert np.all(e <= np.abs(up - x)) and np.all(e <= np.abs(dn - x))
+    # ties go to the even significand
+    t = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8])
+    assert np.array_equal(lowprec.round_to(t, "bf16"), [1.0, 1.0 + 2.0 ** -6])
+
+
+def test_scaled_factor_backward_error():
+    A, b, _, _ = tlsgen.sparse_scaled(2000, 100, seed=3)
+    for fmt, u in (("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
+        Rh, d = lowprec.scaled_factor(A, fmt)
+        Ad = A.to_dense() / d
+        H = Ad.T @ Ad
+        err = np.linalg.norm(Rh.T @ Rh - H, 2)
+        # input rounding, float32 Cholesky and storage rounding: a few u
+        assert err < 20 * u * np.linalg.norm(H, 2)
+        assert err > 0.01 * u * np.linalg.norm(H, 2)     # really is low precision
+
+
+def test_costmodel_sums_algorithm4_lines():
+    # per-line counts annotated in Algorithm 4, built from Table 1
+    m, n, r = 5000, 300, 7
+    T = costmodel.TABLE1
+    line_r = T["matvec"](m, n) + 2 * m                  # r = b - A x
+    line_sigma = T["vecmul"](m) + T["vecmul"](n)        # sigma^2
+    init = line_r + line_sigma + 2 * T["subs"](n) + T["vecupdate"](n)
+    line_f = 2 * m * n + 2 * n
+    line_g = T["vecmul"](m)
+    line_z = n
+    line_beta = 2 * T["vecmul"](n)
+    line_x = T["vecupdate"](n)
+    per = line_r + line_sigma + line_f + line_g + line_z + line_beta + line_x
+    pcg_setup = T["subs"](n) + T["vecmul"](n)
+    # two substitutions, three inner products, four vector updates
+    pcg_iter = 2 * T["subs"](n) + 3 * T["vecmul"](n) + 4 * T["vecupdate"](n) - 2 * n + 2 * n
+    assert pcg_iter == 2 * n * n + 14 * n - 3
+    steps = sum(2 * (k + 1) for k in range(1, r + 1))
+    assert steps == r * r + 3 * r
+    total = init + r * per + 2 * r * pcg_setup + steps * pcg_iter + T["qr"](m, n)
+    assert abs(total - costmodel.cost(m, n, r)) / total < 1e-12
+
+
+def test_costmodel_speedup_limits():
+    assert costmodel.speedup(10 ** 12, 10 ** 7, 5) > 3.99
+    assert costmodel.speedup(10 ** 12, 10 ** 7, 5) < 4.0
+    for m, n, r in [(200, 20, 50), (10 ** 4, 10, 1000), (10 ** 6, 10 ** 3, 2000)]:
+        assert costmodel.speedup(m, n, r) >= 1.0
+        assert costmodel.speedup(m, n, r, 1.0, 1.0, 1.0) == 1.0
+    # tall-skinny: more than 2x at a moderate number of RQIs
+    assert costmodel.speedup(10 ** 6, 500, 5) > 2.0
+
+
+def test_polish_rayleigh_quotient_is_stationary():
+    A, b, _ = tlsgen.dense_gaussian(200, 20, seed=7)
+    s = exact.svd_tls(A, b)
+    mp = exact.mp_svd_tls(A[:30, :4], b[:30])
+    sig = polish.rayleigh_ld(A[:30, :4], b[:30], mp.x)
+    assert abs(sig - mp.sigma) / mp.sigma < 1e-15
+    # a perturbation eps of x changes sigma only at second order:
+    # ten times the perturbation gives a hundred times the change
+    d = np.random.default_rng(2).standard_normal(20)
+    d /= np.linalg.norm(d)
+    ch = [polish.rayleigh_ld(A, b, s.x + e * d * np.linalg.norm(s.x)) - s.sigma for e in (1e-6, 1e-5)]
+    assert ch[0] > 0 and ch[1] > 0
+    assert 80 < ch[1] / ch[0] < 120
+
+
+def test_polish_refines_x():
+    A, b = tlsgen.paper_vanhuffel()
+    sol = exact.svd_tls(A, b)
+    x0 = sol.x * (1 + 1e-7)
+    x1, sig = polish.polish(A, b, x0)
+    assert np.linalg.norm(x1 - sol.x) / np.linalg.norm(sol.x) < 1e-13
+    assert abs(sig - sol.sigma) / sol.sigma < 1e-14
