@@ -48,7 +48,8 @@ def round_to(x, fmt: str) -> np.ndarray:
     r = np.ldexp(np.rint(np.ldexp(x[nz], -q)), q)   # np.rint: ties to even
     r[np.abs(r) > fmax] = np.copysign(np.inf, r[np.abs(r) > fmax])
     out[nz] = r
-    out[~np.isfinite(x)] = x[~np.isfinite(x)]
+    keep = ~nz                      # zeros keep their sign; Inf and NaN pass through
+    out[keep] = x[keep]
     return out
 
 

@@ -1,0 +1,168 @@
+"""GPU parity of the individual kernels through the C ABI against the CPU
+oracle / plain NumPy on the same seeded inputs."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import tlsgen
+from oracle import lowprec, rqi
+
+pytestmark = pytest.mark.gpu
+
+
+def _tls():
+    from paper_2305_19028_amd import tls
+    return tls
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32"])
+def test_round_bit_exact(fmt):
+    tls = _tls()
+    g = np.random.default_rng(5)
+    x = np.concatenate([
+        g.standard_normal(50000) * 10.0 ** g.uniform(-40, 40, 50000),
+        (np.arange(1, 3000) + 0.5) * 2.0 ** -10,          # fp16 ties
+        1.0 + (np.arange(0, 3000) + 0.5) * 2.0 ** -7,     # bf16 ties
+        np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 6.0e-8, 2.98e-8, 1e-45, 3.4e38, 3.5e38]),
+    ])
+    got = _tls().tls_round(x, fmt).cpu().numpy()
+    ref = lowprec.round_to(x, fmt)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("m,n", [(70, 3), (1000, 65), (4097, 130)])
+def test_matvec(kind, m, n):
+    tls = _tls()
+    print(f"matvec {kind} {m}x{n}", flush=True)
+    if kind == "dense":
+        A, b, _ = tlsgen.dense_gaussian(m, n, seed=m + n)
+        Ad = tls.dense(A)
+        P = None
+        Af = A
+    else:
+        A, b, _, _ = tlsgen.sparse_scaled(m, n, density=0.05, seed=m + n)
+        Ad = tls.from_tlsgen(A)
+        P, _ = tls.tls_factor_precond(Ad, "fp64")
+        Af = A.to_dense()
+    x = np.random.default_rng(1).standard_normal(n)
+    y = tls.tls_matvec(Ad, P, 0, x).cpu().numpy()
+    assert np.allclose(y, Af @ x, rtol=1e-12, atol=1e-12 * np.abs(Af).max() * np.abs(x).sum())
+    if P is None and kind == "csr":
+        return
+    if kind == "dense":
+        P = None
+    z = tls.tls_matvec(Ad, P, 1, b).cpu().numpy()
+    ref = Af.T @ b
+    assert np.allclose(z, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def _tri(n, seed, cond=10.0):
+    g = np.random.default_rng(seed)
+    A = g.standard_normal((n + 20, n))
+    R = np.linalg.qr(A, mode="r")
+    R = R * np.sign(np.diag(R))[:, None]
+    return R
+
+
+@pytest.mark.parametrize("n", [5, 64, 100, 257, 1000])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_triangular_solves_fp64(n, nrhs):
+    tls = _tls()
+    print(f"trsv n={n} nrhs={nrhs}", flush=True)
+    R = _tri(n, n)
+    d = np.exp(np.random.default_rng(2).uniform(-2, 2, n))
+    P = tls.tls_precond_import(R, d, "fp64")
+    V = np.random.default_rng(3).standard_normal((nrhs, n))
+    Rfull = R * d[None, :]          # R = R_hat diag(d)
+    for trans in (0, 1):
+        out = tls.tls_apply_precond(P, trans, V).cpu().numpy()
+        for r in range(nrhs):
+            ref = sla.solve_triangular(Rfull, V[r], lower=False, trans="T" if trans else "N")
+            assert np.linalg.norm(out[r] - ref) <= 1e-12 * np.linalg.norm(ref), (trans, r)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("u_p", ["fp64", "fp32"])
+def test_triangular_solves_low_storage(storage, u_p):
+    tls = _tls()
+    n = 300
+    R = _tri(n, 7)
+    R = R / np.abs(R).max()
+    P = tls.tls_precond_import(R, None, storage)
+    Rq = np.triu(lowprec.round_to(R, storage))      # what the library stores
+    V = np.random.default_rng(4).standard_normal((2, n))
+    tol = 1e-12 if u_p == "fp64" else 1e-4
+    for trans in (0, 1):
+        out = tls.tls_apply_precond(P, trans, V, u_p).cpu().numpy()
+        for r in range(2):
+            ref = sla.solve_triangular(Rq, V[r], lower=False, trans="T" if trans else "N")
+            assert np.linalg.norm(out[r] - ref) <= tol * np.linalg.norm(ref) * 10, (trans, r)
+
+
+@pytest.mark.parametrize("n,l", [(20, 0), (20, 3), (130, 5), (700, 8)])
+def test_pcg_step_matches_algorithm3(n, l):
+    tls = _tls()
+    print(f"pcg n={n} l={l}", flush=True)
+    A, b, _ = tlsgen.dense_gaussian(3 * n, n, seed=n)
+    R = rqi.cholesky_R(A)
+    P = tls.tls_precond_import(R, None, "fp64")
+    sR, sRT = rqi._tri_solvers(R)
+    s_n = np.linalg.svd(A, compute_uv=False)[-1]
+    sig2 = (0.7 * s_n) ** 2
+    F = np.random.default_rng(n).standard_normal((2, n))
+    out, tr = tls.tls_pcg_step(P, sig2, F, l, "fp64", trace=True)
+    out = out.cpu().numpy()
+    for r in range(2):
+        w, t = rqi.pcgtls(sR, sRT, sig2, F[r], l, trace=True)
+        assert np.linalg.norm(out[r] - w) <= 1e-11 * np.linalg.norm(w)
+        k = len(t.delta)
+        assert np.allclose(tr["delta"][r][:k], t.delta, rtol=1e-10)
+        assert np.allclose(tr["eta"][r][:k], t.eta[:k], rtol=1e-10)
+    # FP32 arithmetic: same iteration to single precision
+    out32, _ = tls.tls_pcg_step(P, sig2, F, l, "fp32")
+    out32 = out32.cpu().numpy()
+    for r in range(2):
+        w = rqi.pcgtls(sR, sRT, sig2, F[r], l)
+        assert np.linalg.norm(out32[r] - w) <= 1e-4 * np.linalg.norm(w)
+
+
+def test_pcg_sigma_zero_and_single_rhs():
+    tls = _tls()
+    A, b, _ = tlsgen.dense_gaussian(90, 30, seed=3)
+    R = rqi.cholesky_R(A)
+    P = tls.tls_precond_import(R, None, "fp64")
+    f = np.random.default_rng(9).standard_normal(30)
+    out, tr = tls.tls_pcg_step(P, 0.0, f, 4, trace=True)
+    ref = sla.solve_triangular(R, sla.solve_triangular(R, f, trans="T"))
+    assert np.allclose(out.cpu().numpy()[0], ref, rtol=1e-12)
+    assert tr["delta"][0][1] == 0.0        # the loop ends at j = 1
+
+
+@pytest.mark.parametrize("case", ["dense_small", "dense_ragged", "sparse"])
+@pytest.mark.parametrize("u_q", ["fp64"])
+def test_factor_matches_cholesky(case, u_q):
+    tls = _tls()
+    print(f"factor {case} {u_q}", flush=True)
+    if case == "dense_small":
+        A, b, _ = tlsgen.dense_gaussian(200, 20, seed=1000)
+        Ad = tls.dense(A)
+        Af = A
+    elif case == "dense_ragged":
+        A, b, _ = tlsgen.dense_gaussian(700, 150, seed=12)
+        Ad = tls.dense(A)
+        Af = A
+    else:
+        A, b, _, _ = tlsgen.sparse_scaled(3000, 200, density=0.02, seed=7)
+        Ad = tls.from_tlsgen(A)
+        Af = A.to_dense()
+    P, rep = tls.tls_factor_precond(Ad, u_q)
+    Rh, d = tls.tls_precond_export(P)
+    dref = np.linalg.norm(Af, axis=0)
+    assert np.allclose(d, dref, rtol=1e-14)
+    H = (Af / dref).T @ (Af / dref)
+    Rref = sla.cholesky(H, lower=False)
+    assert np.max(np.abs(Rh - Rref)) < 1e-12 * 10
+    # gate estimates: sigma'_n of A within Lanczos accuracy
+    sA = np.linalg.svd(Af, compute_uv=False)
+    assert abs(rep["sigma_n_est"] - sA[-1]) / sA[-1] < 0.2

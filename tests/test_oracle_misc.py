@@ -43,13 +43,17 @@ def test_unit_roundoffs_table2():
 def test_round_fp16_is_ieee_rne():
     g = np.random.default_rng(0)
     x = np.concatenate([g.standard_normal(20000) * 10.0 ** g.uniform(-9, 5, 20000),
+                        np.array([-0.0, 0.0]),
                         # exact ties between fp16 neighbours
                         (np.arange(1, 2000) + 0.5) * 2.0 ** -10,
                         np.array([65504.0, 65519.0, 65520.0, 1e6, 5.96e-8, 2.98e-8, 2.99e-8])])
     with np.errstate(over="ignore"):
         ref = x.astype(np.float16).astype(np.float64)
     got = lowprec.round_to(x, "fp16")
-    assert np.array_equal(got, ref)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    # signed zeros survive rounding (IEEE 754)
+    z = lowprec.round_to(np.array([-0.0, 0.0, -1e-30]), "fp16")
+    assert np.array_equal(z.view(np.uint64), np.array([-0.0, 0.0, -0.0]).view(np.uint64))
 
 
 def test_round_bf16_nearest_even():
