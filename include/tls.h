@@ -1,0 +1,264 @@
+/*
+ * tls.h -- C ABI of the MI355X total-least-squares library (libtls.so).
+ *
+ * The library solves the total least squares problem
+ *     min ||[E, r]||_F  subject to  (A + E) x = b + r,   A m x n, m > n,
+ * (Oktay & Carson, "Mixed Precision Rayleigh Quotient Iteration for Total
+ * Least Squares Problems", abstract and Section 1) by Rayleigh quotient
+ * iteration on [A, b] (Algorithm 2, RQI-PCGTLS), whose two inner solves
+ * (A^T A - sigma^2 I) w = rhs run the preconditioned conjugate gradient
+ * method PCGTLS (Algorithm 3) with an upper triangular factor R of A^T A.
+ * The precisions follow Algorithm 4 (RQI-PCGTLS-MP): outer iteration in
+ * u = FP64, PCGTLS in u_p, factor in u_q.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the comment says (host).
+ *  - The caller owns all device memory: matrices, vectors and workspaces.
+ *    The library never allocates device memory. Workspace sizes come from
+ *    the *_workspace_size queries; workspaces must be 256-byte aligned.
+ *  - Work is enqueued on the given stream. tls_factor_precond and
+ *    tls_rqi_solve synchronize that stream internally (to read the gate
+ *    estimates and the per-iteration psi of eq. (4)); tls_pcg_step and
+ *    tls_apply_precond are asynchronous unless a host trace is requested.
+ *  - Every call returns a tls_status; no C++ exception crosses the ABI;
+ *    tls_last_error() returns a thread-local message for the last failure.
+ *  - Results are deterministic: reductions use a fixed order, so repeated
+ *    calls on the same inputs give bitwise identical outputs.
+ *  - Calls that share a workspace or a preconditioner must not overlap in
+ *    time (they use synchronisation counters inside the workspace).
+ */
+#ifndef TLS_H
+#define TLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define TLS_API __attribute__((visibility("default")))
+#else
+#define TLS_API
+#endif
+
+/* Precisions (Table 2, plus bfloat16, which the paper does not use). */
+typedef enum { TLS_FP64 = 0, TLS_FP32 = 1, TLS_FP16 = 2, TLS_BF16 = 3 } tls_prec;
+
+/* Storage format of A. */
+typedef enum { TLS_DENSE_COLMAJOR = 0, TLS_CSR = 1 } tls_format;
+
+typedef enum {
+  TLS_OK = 0,
+  TLS_ERR_ARG = -1,            /* invalid argument (shape, null pointer, size)          */
+  TLS_ERR_HIP = -2,            /* a HIP runtime call failed                             */
+  TLS_ERR_NOT_SPD = -3,        /* Cholesky breakdown: non-positive pivot                */
+  TLS_ERR_PRECISION = -4,      /* the u_q gate rejected the factor, escalation disabled  */
+  TLS_ERR_INDEFINITE = -5,     /* delta_j <= 0 in PCGTLS with strict checking on        */
+  TLS_ERR_NONUNIQUE = -6,      /* sigma_{n+1} estimate >= sigma'_n estimate (Section 2) */
+  TLS_ERR_NO_CONVERGENCE = -7, /* kmax reached without the psi rule firing              */
+  TLS_ERR_WORKSPACE = -8,      /* workspace too small or misaligned                     */
+  TLS_ERR_NONFINITE = -9,      /* NaN or Inf in A or b                                  */
+  TLS_ERR_SYNC_TIMEOUT = -10   /* an inter-workgroup wait exceeded its spin bound       */
+} tls_status;
+
+/* The data matrix A (m x n, m > n). Dense: column-major, element (i, j) at
+ * val[i + j*ld], ld >= m. CSR: row_ptr[m+1] (row_ptr[0] = 0, nondecreasing),
+ * col_idx[nnz] in [0, n) strictly increasing within each row, val[nnz]. All
+ * arrays are device memory owned by the caller and must stay valid and
+ * unchanged while a preconditioner built from A is in use. */
+typedef struct {
+  int32_t format;          /* tls_format */
+  int32_t reserved;
+  int64_t m, n;
+  int64_t ld;              /* dense only */
+  int64_t nnz;             /* CSR only   */
+  const double *val;
+  const int32_t *row_ptr;  /* CSR only   */
+  const int32_t *col_idx;  /* CSR only   */
+} tls_matrix;
+
+/* Opaque preconditioner: a small host object owned by the library that
+ * points into the caller's factor workspace (which must outlive it). */
+typedef struct tls_precond_s *tls_precond;
+
+/* Outcome of the per-instance check of the factorization precision u_q
+ * against the constraints of Section 3.1 (the constants the paper drops
+ * are taken as one). Estimates come from Lanczos on the preconditioned
+ * operator R^{-T} R^{-1}. */
+typedef struct {
+  double kappa_est;        /* kappa(A D^{-1}) estimate (D = I when unscaled)   */
+  double kappaF_est;       /* kappa_F(A D^{-1}) = ||A D^{-1}||_F / sigma_min    */
+  double sigma_n_est;      /* sigma'_n(A) estimate                              */
+  double sigma_1_est;      /* sigma'_1(A) estimate                              */
+  double lam_min_H;        /* lambda_min(H), H = D^{-1} A^T A D^{-1}            */
+  double bound5;           /* u_q <~ kappa^{-1}                    (eq. 5)       */
+  double bound_chol;       /* u_q <~ kappa^{-2}        (Cholesky of fl(A^T A))   */
+  double bound_wilkinson;  /* 1/(20 n^{3/2} kappa^2)                             */
+  double bound_hp;         /* lam_min(H)/((2 lam_min(H) + n)(n+1))  (scaled)     */
+  double bound6;           /* kappa_F^{-1}(1 - sigma_{n+1}^2/sigma'_n^2) (eq. 6);
+                              filled by tls_rqi_solve, which knows b             */
+  double u_q;              /* unit roundoff of the precision finally used        */
+  double ctilde_min;       /* lambda_min estimate of C = I - s0^2 R^{-T}R^{-1}   */
+  int32_t requested;       /* tls_prec asked for                                 */
+  int32_t used;            /* tls_prec actually used (after escalation)          */
+  int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,
+                              3: (6) holds, 4: a-posteriori certificate holds    */
+  int32_t escalations;     /* times u_q was raised                               */
+  int32_t chol_retries;    /* diagonal-shift retries after breakdown             */
+  int32_t lanczos_steps;
+} tls_gate_report;
+
+#define TLS_MAX_ITERS 256
+
+/* Options of tls_rqi_solve. tls_default_opts() fills the plain FP64 path. */
+typedef struct {
+  int32_t u_p;             /* tls_prec of PCGTLS: TLS_FP64 or TLS_FP32            */
+  int32_t kmax;            /* maximum RQI iterations, 1..TLS_MAX_ITERS            */
+  int32_t stop_patience;   /* psi rule (eq. 4): stop after this many iterations
+                              without a new smallest psi; 1 = stop at the first
+                              increase, as printed                                  */
+  int32_t stop_ge;         /* 1: psi_{k+1} >= psi_k also counts (Example 2)      */
+  int32_t ls_corrections;  /* corrections of x_LS by semi-normal equations        */
+  int32_t strict_pd;       /* 1: delta_j <= 0 in PCGTLS is an error              */
+  int32_t shift_clamp;     /* 1: shift = min(sigma_k^2, tau * sigma'_n estimate^2) */
+  int32_t refine_sweeps;   /* final FP64 refinement RQI steps (explicit operator) */
+  int32_t refine_pcg_steps;/* PCG steps per refinement solve                     */
+  int32_t allow_escalate;  /* raise u_q when the b-dependent gate (6) fails       */
+  int32_t gate_enforce;    /* 1: run the b-dependent gate                         */
+  int32_t reserved;
+  double shift_clamp_tau;  /* tau of the clamp (0 < tau < 1)                       */
+  double sigma0_hint;      /* warm start: initial shift sigma (<= 0: none)         */
+  double *x_snapshots;     /* device, optional (kmax * n): x_k at each psi_k       */
+} tls_rqi_opts;
+
+/* Per-call record of the iteration (host). */
+typedef struct {
+  int32_t iters;           /* number of psi_k evaluated (k = 1..iters)            */
+  int32_t k_best;          /* k of the returned iterate (smallest psi)            */
+  int32_t pcg_steps;       /* PCGTLS steps executed (per right-hand side)         */
+  int32_t warm_used;       /* 1 when the warm-start step was kept                 */
+  int32_t stopped;         /* 0 psi rule, 1 kmax, 2 psi == 0                      */
+  int32_t negative_delta;  /* PCGTLS steps that met delta_j < 0                   */
+  int32_t refine_steps;    /* refinement RQI steps taken                          */
+  int32_t clamped;         /* iterations whose shift was clamped                  */
+  double sigma_ls;         /* sigma_0 = ||r_0|| / sqrt(1 + ||x_LS||^2)             */
+  double psi[TLS_MAX_ITERS];
+  double sigma[TLS_MAX_ITERS];
+  double t_ms[TLS_MAX_ITERS]; /* host time since the call began when psi_k was read */
+  double t_factor_ms;      /* time in escalation refactoring, if any               */
+  double t_total_ms;
+  double sigma_final;      /* sigma after the compensated residual                 */
+} tls_rqi_stats;
+
+/* ---------------------------------------------------------------------------
+ * Preconditioner (Section 2: Cholesky factor of A^T A, computed once;
+ * Section 3.1: computed in precision u_q with two-sided diagonal scaling).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of workspace tls_factor_precond needs for A and u_q (covers every
+ * escalation up to FP64). */
+TLS_API size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q);
+
+/* Build R with R^T R ~ A^T A. With scaling = 1, D = diag(||A e_j||), the
+ * columns of A D^{-1} are rounded to u_q, H = (A D^{-1})^T (A D^{-1}) is
+ * accumulated in FP32 (FP64 when u_q = FP64), Cholesky gives R_hat, stored
+ * in u_q, and R = R_hat D. scaling = 0 factors A^T A itself (FP64 only).
+ * The A-only constraints of Section 3.1 are estimated and reported in *rep
+ * (host, may be NULL); with allow_escalate the factor is recomputed in the
+ * next higher precision when none of the Cholesky constraints nor the
+ * a-posteriori checks hold. Breakdown (TLS_ERR_NOT_SPD) is retried with the
+ * diagonal shift 2^j n u_q (j = 0, 1, 2) before it is returned.
+ * On success *out (host) receives a handle to destroy with
+ * tls_precond_destroy. ws must hold tls_factor_workspace_size() bytes. */
+TLS_API tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
+                              int32_t allow_escalate, void *ws, size_t ws_bytes,
+                              hipStream_t stream, tls_precond *out,
+                              tls_gate_report *rep);
+
+/* Bytes of workspace tls_precond_import needs for order n. */
+TLS_API size_t tls_precond_import_workspace_size(int64_t n);
+
+/* Wrap a caller-supplied factor: R_host (host) is the n x n upper triangle,
+ * column-major (entries below the diagonal ignored), d_host (host, may be
+ * NULL = ones) the scaling with R = R_hat diag(d). R_hat is rounded to
+ * `storage`. Used to run PCGTLS on a known factor. */
+TLS_API tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_host,
+                              int32_t storage, void *ws, size_t ws_bytes,
+                              hipStream_t stream, tls_precond *out);
+
+TLS_API void tls_precond_destroy(tls_precond P);
+
+/* Order n, storage precision and gate report of P (host outputs). */
+TLS_API tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage,
+                            tls_gate_report *rep);
+
+/* Copy R_hat (upper, column-major n x n, FP64) and d to host buffers. */
+TLS_API tls_status tls_precond_export(const tls_precond P, double *R_host, double *d_host,
+                              hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Algorithm 3: l-step PCGTLS for (A^T A - sigma2 I) w = rhs, using only R.
+ * ------------------------------------------------------------------------- */
+
+TLS_API size_t tls_pcg_workspace_size(const tls_precond P, int32_t nrhs, int32_t l);
+
+/* Run j = 0..l while delta_j != 0 on nrhs (1 or 2) right-hand sides sharing
+ * sigma2. rhs and omega are n x nrhs column-major FP64 (device). u_p is the
+ * arithmetic precision (TLS_FP64 or TLS_FP32). trace (host, may be NULL)
+ * receives, per right-hand side r, 4*(l+2) doubles at offset 4*(l+2)*r:
+ * eta_0..eta_{l+1}, delta_0..delta_{l+1}, alpha_0.., beta_0.. (NaN where a
+ * step did not run). delta_j < 0 is returned as TLS_ERR_INDEFINITE only when
+ * strict_pd is set; otherwise the iteration continues as printed. */
+TLS_API tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs,
+                        const double *rhs, double *omega, int32_t l, int32_t u_p,
+                        int32_t strict_pd, void *ws, size_t ws_bytes,
+                        hipStream_t stream, double *trace);
+
+/* out = R^{-1} in (trans = 0) or R^{-T} in (trans = 1) for nrhs column-major
+ * FP64 vectors, computed in u_p (forward/backward substitution, Table 1). */
+TLS_API tls_status tls_apply_precond(const tls_precond P, int32_t trans, int32_t nrhs,
+                             const double *in, double *out, int32_t u_p,
+                             void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* y = A x (trans = 0, x n-vector, y m-vector) or y = A^T x (trans = 1), FP64.
+ * For CSR, A^T x uses the CSC copy held by P (P may be NULL for trans = 0). */
+TLS_API tls_status tls_matvec(const tls_matrix *A, const tls_precond P, int32_t trans,
+                      const double *x, double *y, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Algorithms 2 / 4: RQI for TLS with PCGTLS inner solves.
+ * ------------------------------------------------------------------------- */
+
+TLS_API void tls_default_opts(tls_rqi_opts *o);
+
+TLS_API size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P,
+                              const tls_rqi_opts *o);
+
+/* Solve the TLS problem for (A, b) with the preconditioner P built from the
+ * same A. x (device, n, out) receives the iterate with the smallest psi (or
+ * the refined one), *sigma (host) sigma_{n+1} from a compensated residual.
+ * opts and stats are host structures (stats may be NULL). */
+TLS_API tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P,
+                         const tls_rqi_opts *opts, double *x, double *sigma,
+                         tls_rqi_stats *stats, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* out[i] = in[i] rounded to `prec` with round-to-nearest-even (IEEE 754),
+ * returned as FP64: the rounding the scaled factor applies to A D^{-1}
+ * (Section 3.1). count elements, device arrays. */
+TLS_API tls_status tls_round(const double *in, int64_t count, int32_t prec, double *out,
+                             hipStream_t stream);
+
+/* Thread-local description of the last error (never NULL). */
+TLS_API const char *tls_last_error(void);
+
+/* Library version string. */
+TLS_API const char *tls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLS_H */

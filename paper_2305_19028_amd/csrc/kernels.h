@@ -1,0 +1,125 @@
+// Internal launch interface between the host driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "tls.h"
+
+namespace tls {
+
+// view of a packed factor (device pointers)
+struct FactorView {
+  int n, N, Np, storage;
+  const void *tiles;
+  const double *dinv64;
+  const float *dinv32;
+  const double *dscale64;   // 1/d, length Np (ones beyond n)
+  const float *dscale32;
+};
+
+// buffers of one triangular-solve / PCGTLS launch
+struct SolveBufs {
+  int *sync;
+  void *chain;
+  const double *in;
+  double *out;
+  void *s, *p, *q, *w, *part;
+  int *done, *neg;
+  double *trace;
+  const double *sigma2;
+  int j, L, strict;
+};
+
+// ---- kernels_trsv.hip ------------------------------------------------------
+hipError_t launch_trsv(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
+                       hipStream_t st);
+hipError_t launch_pcg_finish(int compute, const void *w, double *out, int n, int Np, int nrhs,
+                             hipStream_t st);
+
+// ---- kernels_factor.hip ----------------------------------------------------
+hipError_t launch_fill_i32(int *p, int v, size_t count, hipStream_t st);
+hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st);
+hipError_t launch_round(const double *in, int64_t count, int q, double *out, hipStream_t st);
+hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st);
+hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, const double *val, int32_t *col_ptr,
+                            int32_t *row_idx, double *cval, int32_t *tmp_row, double *tmp_val,
+                            int32_t *fill, hipStream_t st);
+hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
+                               hipStream_t st);
+hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
+                                 hipStream_t st);
+// scaling vectors: dinv = 1/d (or ones when unscaled), both precisions, padded to Np
+hipError_t launch_scale_vectors(int n, int Np, const double *d, int scaled, double *dsc64,
+                                float *dsc32, hipStream_t st);
+// quantised scaled values (CSR and CSC arrays): out = round_q(val / d[col]) as compute type
+hipError_t launch_quantize_sparse(int64_t nnz, const int32_t *cols, const double *val,
+                                  const double *d, int scaled, int q, int compute, void *out,
+                                  hipStream_t st);
+hipError_t launch_quantize_csc(int n, const int32_t *col_ptr, const double *cval, const double *d,
+                               int scaled, int q, int compute, void *out, hipStream_t st);
+hipError_t launch_gram_sparse(int m, int n, int Np, const int32_t *row_ptr, const int32_t *col_idx,
+                              const void *valq, const int32_t *col_ptr, const int32_t *row_idx,
+                              const void *cvalq, int compute, void *G, hipStream_t st);
+hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, const double *d,
+                             int scaled, int q, int compute, void *G, hipStream_t st);
+hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st);
+hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st);
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, int *info, hipStream_t st);
+hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
+                             hipStream_t st);
+hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64,
+                               float *dinv32, hipStream_t st);
+hipError_t launch_import_tiles(int n, int N, int Np, const double *R, int storage, void *tiles,
+                               hipStream_t st);
+hipError_t launch_export_tiles(int n, int N, int Np, int storage, const void *tiles, double *R,
+                               hipStream_t st);
+
+// ---- kernels_rqi.hip -------------------------------------------------------
+struct MatView {
+  int format;
+  int m, n;
+  int64_t ld, nnz;
+  const double *val;
+  const int32_t *row_ptr, *col_idx;
+  // CSC copy (CSR only)
+  const int32_t *col_ptr, *row_idx;
+  const double *cval;
+};
+
+// r = b - A x; per-block partial sums of r.r and b.r written to part[2*blocks]
+int matvec_blocks(const MatView &A);
+hipError_t launch_residual(const MatView &A, const double *b, const double *x, double *r,
+                           double *part, hipStream_t st);
+// y = A x (plain), y = A^T x (plain)
+hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream_t st);
+hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st);
+// f = -A^T r - shift x with shift read from scal; partial f.f per block
+int rmatvec_blocks(const MatView &A);
+hipError_t launch_gradient(const MatView &A, const double *r, const double *x,
+                           const double *shift, double *f, double *part, hipStream_t st);
+// compensated residual r = b - A x in double-double, partial sums (hi/lo) of r.r
+hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x, double *part,
+                              hipStream_t st);
+
+// scalar kernels of the outer loop, all single-workgroup, deterministic
+struct OuterScalars;   // device struct, see kernels_rqi.hip
+hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
+                           double clamp_max, hipStream_t st);
+hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f,
+                            int nb_f, double *scal, int k, double *rec, hipStream_t st);
+hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st);
+hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
+                             const double *scal, double *xbest, double *xsnap, hipStream_t st);
+hipError_t launch_axpy_init(int n, double *x, const double *u, const double *scal, int which,
+                            hipStream_t st);
+hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);
+hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t st);
+hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, double *ab, hipStream_t st);
+hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
+                           hipStream_t st);
+
+}  // namespace tls

@@ -1,0 +1,710 @@
+// Preconditioner construction: CSC copy of a CSR matrix, column scaling and
+// rounding to u_q (two-sided diagonal scaling, Section 3.1), the Gram
+// matrix A^T A (sparse and dense), its blocked Cholesky factorization
+// (Section 2: the factor R of A^T A, computed once), and the packing of R
+// into the tiled storage the triangular solves read.
+//
+// Dense matrices are column-major. The Gram matrix G is Np x Np
+// column-major with only its upper triangle meaningful; Cholesky overwrites
+// it with R (G = R^T R). Padding rows/columns n..Np-1 hold the identity.
+#include "common.h"
+#include "kernels.h"
+
+namespace tls {
+
+// --------------------------------------------------------------------------
+// small utilities
+// --------------------------------------------------------------------------
+__global__ void k_fill_i32(int *p, int v, size_t count) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, size_t count) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+static int grid_for(size_t count) {
+  size_t g = (count + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+hipError_t launch_fill_i32(int *p, int v, size_t count, hipStream_t st) {
+  if (!count) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st) {
+  if (!count) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+__global__ void k_check_finite(const double *v, size_t count, int *flag) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  int bad = 0;
+  for (; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v[i]);
+    bad |= ((u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st) {
+  if (!count) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(count)), dim3(256), 0, st, v, count, flag);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// CSC copy of a CSR matrix, rows ascending inside each column
+// --------------------------------------------------------------------------
+__global__ void k_csc_count(int m, const int32_t *row_ptr, const int32_t *col_idx, int32_t *cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) atomicAdd(&cnt[col_idx[e]], 1);
+}
+
+// exclusive scan of cnt[0..n) into col_ptr[0..n], one workgroup
+__global__ void k_scan(int n, const int32_t *cnt, int32_t *col_ptr) {
+  __shared__ int32_t s_tot[256];
+  const int tid = threadIdx.x;
+  const int per = (n + 255) / 256;
+  const int a = tid * per, b = min(n, a + per);
+  int32_t sum = 0;
+  for (int i = a; i < b; ++i) sum += cnt[i];
+  s_tot[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t run = 0;
+    for (int t = 0; t < 256; ++t) { const int32_t v = s_tot[t]; s_tot[t] = run; run += v; }
+    col_ptr[n] = run;
+  }
+  __syncthreads();
+  int32_t run = s_tot[tid];
+  for (int i = a; i < b; ++i) { col_ptr[i] = run; run += cnt[i]; }
+}
+
+__global__ void k_csc_scatter(int m, const int32_t *row_ptr, const int32_t *col_idx,
+                              const double *val, const int32_t *col_ptr, int32_t *fill,
+                              int32_t *tmp_row, double *tmp_val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    const int c = col_idx[e];
+    const int pos = col_ptr[c] + atomicAdd(&fill[c], 1);
+    tmp_row[pos] = i;
+    tmp_val[pos] = val[e];
+  }
+}
+
+// one thread per CSC slot: its final position is the number of entries of
+// the same column with a smaller row (rows are distinct inside a column)
+__global__ void k_csc_rank(int64_t nnz, int n, const int32_t *col_ptr, const int32_t *tmp_row,
+                           const double *tmp_val, int32_t *row_idx, double *cval) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  // column of slot e by binary search in col_ptr
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col_ptr[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int a = col_ptr[lo], b = col_ptr[lo + 1];
+  const int r = tmp_row[e];
+  int rank = 0;
+  for (int t = a; t < b; ++t) rank += (tmp_row[t] < r);
+  row_idx[a + rank] = r;
+  cval[a + rank] = tmp_val[e];
+}
+
+hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, const double *val, int32_t *col_ptr,
+                            int32_t *row_idx, double *cval, int32_t *tmp_row, double *tmp_val,
+                            int32_t *fill, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_fill_i32(fill, 0, n, st)) != hipSuccess) return e;
+  const int gm = (m + 255) / 256;
+  hipLaunchKernelGGL(k_csc_count, dim3(gm), dim3(256), 0, st, m, row_ptr, col_idx, fill);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, n, fill, col_ptr);
+  if ((e = launch_fill_i32(fill, 0, n, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_csc_scatter, dim3(gm), dim3(256), 0, st, m, row_ptr, col_idx, val, col_ptr,
+                     fill, tmp_row, tmp_val);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_csc_rank, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, n,
+                       col_ptr, tmp_row, tmp_val, row_idx, cval);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// column norms d_j = ||A e_j|| (one wave per column, fixed order)
+// --------------------------------------------------------------------------
+__global__ void k_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;
+  double s = 0;
+  for (int e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += 64) s += cval[e] * cval[e];
+  s = wave_sum(s);
+  if (lane == 0) d[j] = sqrt(s);
+}
+__global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;
+  const double *col = A + (size_t)j * ld;
+  double s = 0;
+  for (int i = lane; i < m; i += 64) s += col[i] * col[i];
+  s = wave_sum(s);
+  if (lane == 0) d[j] = sqrt(s);
+}
+hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorms_csc, dim3((n + 3) / 4), dim3(256), 0, st, n, col_ptr, cval, d);
+  return hipGetLastError();
+}
+hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorms_dense, dim3((n + 3) / 4), dim3(256), 0, st, m, n, ld, A, d);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_vectors(int n, int Np, const double *d, int scaled, double *dsc64,
+                                float *dsc32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Np) return;
+  const double v = (i < n && scaled) ? 1.0 / d[i] : 1.0;
+  dsc64[i] = v;
+  dsc32[i] = (float)v;
+}
+hipError_t launch_scale_vectors(int n, int Np, const double *d, int scaled, double *dsc64,
+                                float *dsc32, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_vectors, dim3((Np + 255) / 256), dim3(256), 0, st, n, Np, d, scaled,
+                     dsc64, dsc32);
+  return hipGetLastError();
+}
+
+// round one scaled value to u_q, returned as double (exactly representable)
+__device__ inline double quantize(double v, int q) {
+  switch (q) {
+    case TLS_FP64: return v;
+    case TLS_FP32: return (double)__builtin_bit_cast(float, f64_to_f32_bits(v));
+    case TLS_FP16: return (double)f16_bits_to_float(f64_to_f16_bits(v));
+    default: return (double)bf16_bits_to_float(f64_to_bf16_bits(v));
+  }
+}
+
+__global__ void k_round(const double *in, int64_t count, int q, double *out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) out[i] = quantize(in[i], q);
+}
+hipError_t launch_round(const double *in, int64_t count, int q, double *out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_round, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, count, q, out);
+  return hipGetLastError();
+}
+
+template <typename C>
+__global__ void k_quantize_sparse(int64_t nnz, const int32_t *cols, const double *val,
+                                  const double *d, int scaled, int q, C *out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const double v = scaled ? val[e] / d[cols[e]] : val[e];
+  out[e] = (C)quantize(v, q);
+}
+hipError_t launch_quantize_sparse(int64_t nnz, const int32_t *cols, const double *val,
+                                  const double *d, int scaled, int q, int compute, void *out,
+                                  hipStream_t st) {
+  if (nnz <= 0) return hipSuccess;
+  const dim3 g((unsigned)((nnz + 255) / 256));
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_quantize_sparse<double>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
+                       (double *)out);
+  else
+    hipLaunchKernelGGL(k_quantize_sparse<float>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
+                       (float *)out);
+  return hipGetLastError();
+}
+
+template <typename C>
+__global__ void k_quantize_csc(int n, const int32_t *col_ptr, const double *cval, const double *d,
+                               int scaled, int q, C *out) {
+  const int j = blockIdx.x;
+  const double dj = d[j];
+  for (int e = col_ptr[j] + threadIdx.x; e < col_ptr[j + 1]; e += blockDim.x) {
+    const double v = scaled ? cval[e] / dj : cval[e];
+    out[e] = (C)quantize(v, q);
+  }
+}
+hipError_t launch_quantize_csc(int n, const int32_t *col_ptr, const double *cval, const double *d,
+                               int scaled, int q, int compute, void *out, hipStream_t st) {
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_quantize_csc<double>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
+                       q, (double *)out);
+  else
+    hipLaunchKernelGGL(k_quantize_csc<float>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
+                       q, (float *)out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// sparse Gram: column j of the upper triangle, G(k, j) = sum_i A(i,k) A(i,j)
+// for k <= j. One wave per column; rows of column j are visited in
+// ascending order and the lanes of the wave split the entries of each row
+// (distinct columns k), so every G(k, j) is accumulated in row order.
+// --------------------------------------------------------------------------
+constexpr int GRAM_KC = 2048;   // k-chunk held in LDS per wave
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_gram_sparse(int n, int Np, const int32_t *row_ptr,
+                                                     const int32_t *col_idx, const C *valq,
+                                                     const int32_t *col_ptr,
+                                                     const int32_t *row_idx, const C *cvalq, C *G) {
+  __shared__ C acc[4][GRAM_KC];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + w;
+  if (j >= n) return;   // whole wave leaves together; no block barriers below
+  C *a = acc[w];
+  const int ca = col_ptr[j], cb = col_ptr[j + 1];
+  for (int k0 = 0; k0 <= j; k0 += GRAM_KC) {
+    const int k1 = min(j + 1, k0 + GRAM_KC);
+    for (int k = k0 + lane; k < k1; k += 64) a[k - k0] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t = ca; t < cb; ++t) {
+      const int i = row_idx[t];
+      const C aij = cvalq[t];
+      const int ra = row_ptr[i], rb = row_ptr[i + 1];
+      for (int e = ra + lane; e < rb; e += 64) {
+        const int k = col_idx[e];
+        if (k >= k0 && k < k1) a[k - k0] += aij * valq[e];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    C *colj = G + (size_t)j * Np;
+    for (int k = k0 + lane; k < k1; k += 64) colj[k] = a[k - k0];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+hipError_t launch_gram_sparse(int m, int n, int Np, const int32_t *row_ptr, const int32_t *col_idx,
+                              const void *valq, const int32_t *col_ptr, const int32_t *row_idx,
+                              const void *cvalq, int compute, void *G, hipStream_t st) {
+  const dim3 g((n + 3) / 4);
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_gram_sparse<double>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
+                       (const double *)valq, col_ptr, row_idx, (const double *)cvalq, (double *)G);
+  else
+    hipLaunchKernelGGL(k_gram_sparse<float>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
+                       (const float *)valq, col_ptr, row_idx, (const float *)cvalq, (float *)G);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// dense Gram (VALU): tile (I, J), I <= J, of G = Ahat^T Ahat with
+// Ahat = round_q(A D^{-1}) formed on load; 16x16 threads, 4x4 outputs each
+// --------------------------------------------------------------------------
+template <typename C>
+__global__ __launch_bounds__(256) void k_gram_dense(int m, int n, int Np, int64_t ld,
+                                                    const double *A, const double *d, int scaled,
+                                                    int q, C *G) {
+  constexpr int KT = 16;
+  __shared__ C As[KT][NB + 1];
+  __shared__ C Bs[KT][NB + 1];
+  // decode the upper-triangle tile index
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  C acc[4][4] = {};
+  // loader mapping: 1024 elements per operand per chunk, 4 per thread
+  const int lcol = tid >> 2, lrow = (tid & 3) * 4;
+  const int colI = I * NB + lcol, colJ = J * NB + lcol;
+  const double sI = (colI < n && scaled) ? 1.0 / d[colI] : 1.0;
+  const double sJ = (colJ < n && scaled) ? 1.0 / d[colJ] : 1.0;
+  for (int k0 = 0; k0 < m; k0 += KT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + lrow + u;
+      double va = 0, vb = 0;
+      if (k < m && colI < n) va = quantize(A[(size_t)colI * ld + k] * sI, q);
+      if (k < m && colJ < n) vb = quantize(A[(size_t)colJ * ld + k] * sJ, q);
+      As[lrow + u][lcol] = (C)va;
+      Bs[lrow + u][lcol] = (C)vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; ++kk) {
+      C a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) { a[x] = As[kk][tr * 4 + x]; b[x] = Bs[kk][tc * 4 + x]; }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = I * NB + tr * 4 + x, c = J * NB + tc * 4 + y;
+      if (r <= c && c < n) G[(size_t)c * Np + r] = acc[x][y];
+    }
+}
+hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, const double *d,
+                             int scaled, int q, int compute, void *G, hipStream_t st) {
+  const int N = Np / NB;
+  const dim3 g(N * (N + 1) / 2);
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_gram_dense<double>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
+                       (double *)G);
+  else
+    hipLaunchKernelGGL(k_gram_dense<float>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
+                       (float *)G);
+  return hipGetLastError();
+}
+
+// identity in the padding columns n..Np-1 (upper triangle)
+template <typename C>
+__global__ void k_gram_pad(int n, int Np, C *G) {
+  const int j = n + blockIdx.x;
+  for (int k = threadIdx.x; k <= j; k += blockDim.x) G[(size_t)j * Np + k] = (k == j) ? (C)1 : (C)0;
+}
+hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st) {
+  if (Np == n) return hipSuccess;
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_gram_pad<double>, dim3(Np - n), dim3(256), 0, st, n, Np, (double *)G);
+  else
+    hipLaunchKernelGGL(k_gram_pad<float>, dim3(Np - n), dim3(256), 0, st, n, Np, (float *)G);
+  return hipGetLastError();
+}
+
+template <typename C>
+__global__ void k_gram_shift(int n, int Np, C *G, double shift) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) G[(size_t)i * Np + i] += (C)shift;
+}
+hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st) {
+  const dim3 g((n + 255) / 256);
+  if (compute == TLS_FP64)
+    hipLaunchKernelGGL(k_gram_shift<double>, g, dim3(256), 0, st, n, Np, (double *)G, shift);
+  else
+    hipLaunchKernelGGL(k_gram_shift<float>, g, dim3(256), 0, st, n, Np, (float *)G, shift);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// blocked right-looking Cholesky, upper: G = R^T R, 64x64 tiles
+// --------------------------------------------------------------------------
+
+// factor a 64x64 SPD tile held in LDS (row stride NB+1) into R (upper) and
+// its inverse X = R^{-1} (upper); returns nonzero on a non-positive pivot.
+// Elimination keeps rows unscaled (G(i,j) -= G(c,i) G(c,j) / G(c,c)) and
+// scales row c by 1/sqrt(pivot) at the end, one barrier per column.
+template <typename C>
+__device__ int tile_potrf_inv(C (*T)[NB + 1], C (*X)[NB + 1]) {
+  const int tid = threadIdx.x;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int c = 0; c < NB; ++c) {
+    const C piv = T[c][c];
+    if (!(piv > (C)0)) {
+      if (tid == 0) s_bad = c + 1;
+      break;
+    }
+    const int M = NB - 1 - c;                 // trailing order
+    const int cnt = M * (M + 1) / 2;
+    const C ip = (C)1 / piv;
+    for (int t = tid; t < cnt; t += blockDim.x) {
+      // decode (a, b) with a <= b in the trailing triangle, row-major
+      int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((b + 1) * (b + 2) / 2 <= t) ++b;
+      while (b * (b + 1) / 2 > t) --b;
+      const int a = t - b * (b + 1) / 2;
+      const int i = c + 1 + a, j = c + 1 + b;
+      T[i][j] -= T[c][i] * T[c][j] * ip;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int bad = s_bad;
+  if (bad) return bad;
+  // row scaling: R(c, j) = G(c, j) / sqrt(G(c, c))
+  for (int t = tid; t < NB * NB; t += blockDim.x) {
+    const int c = t / NB, j = t % NB;
+    if (j > c) T[c][j] = T[c][j] / sqrt(T[c][c]);
+  }
+  __syncthreads();
+  for (int c = tid; c < NB; c += blockDim.x) T[c][c] = sqrt(T[c][c]);
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += blockDim.x) {
+    const int r = t / NB, c = t % NB;
+    if (r > c) T[r][c] = 0;
+  }
+  __syncthreads();
+  // inverse, column t by back substitution (thread t)
+  if (tid < NB) {
+    const int t = tid;
+    for (int i = NB - 1; i > t; --i) X[i][t] = 0;
+    X[t][t] = (C)1 / T[t][t];
+    for (int i = t - 1; i >= 0; --i) {
+      C s = 0;
+      for (int l = i + 1; l <= t; ++l) s += T[i][l] * X[l][t];
+      X[i][t] = -s / T[i][i];
+    }
+  }
+  __syncthreads();
+  return 0;
+}
+
+// panel k: every workgroup factors the diagonal tile; workgroup 0 writes it,
+// workgroup j > 0 writes R(k, k+j) = R_kk^{-T} G(k, k+j)
+template <typename C>
+__global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *info) {
+  __shared__ C T[NB][NB + 1];
+  __shared__ C X[NB][NB + 1];
+  __shared__ C B[NB][NB + 1];
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)k * NB;
+  for (int t = tid; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    T[r][c] = (r <= c) ? G[(base + c) * Np + base + r] : (C)0;
+  }
+  __syncthreads();
+  const int bad = tile_potrf_inv(T, X);
+  if (bad) {
+    if (tid == 0 && blockIdx.x == 0) atomicMin(info, k * NB + bad);
+    return;
+  }
+  const int jb = k + blockIdx.x;
+  if (blockIdx.x == 0) {
+    for (int t = tid; t < NB * NB; t += blockDim.x) {
+      const int r = t % NB, c = t / NB;
+      if (r <= c) G[(base + c) * Np + base + r] = T[r][c];
+    }
+    return;
+  }
+  const size_t cb = (size_t)jb * NB;
+  for (int t = tid; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    B[r][c] = G[(cb + c) * Np + base + r];
+  }
+  __syncthreads();
+  // R_kj(r, c) = sum_{t <= r} X(t, r) B(t, c)
+  const int tr = tid & 15, tc = tid >> 4;
+  C acc[4][4] = {};
+  for (int t = 0; t < NB; ++t) {
+    C a[4], b[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) { a[x] = X[t][tr * 4 + x]; b[x] = B[t][tc * 4 + x]; }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) G[(cb + tc * 4 + y) * Np + base + tr * 4 + x] = acc[x][y];
+}
+
+// trailing update G(i, j) -= R(k, i)^T R(k, j) for k < i <= j
+template <typename C>
+__global__ __launch_bounds__(256) void k_chol_update(int k, int N, int Np, C *G) {
+  __shared__ C Ri[NB][NB + 1];
+  __shared__ C Rj[NB][NB + 1];
+  const int l = blockIdx.x;
+  int b = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((b + 1) * (b + 2) / 2 <= l) ++b;
+  while (b * (b + 1) / 2 > l) --b;
+  const int a = l - b * (b + 1) / 2;
+  const int i = k + 1 + a, j = k + 1 + b;
+  const int tid = threadIdx.x;
+  const size_t base = (size_t)k * NB;
+  for (int t = tid; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    Ri[r][c] = G[((size_t)i * NB + c) * Np + base + r];
+    Rj[r][c] = G[((size_t)j * NB + c) * Np + base + r];
+  }
+  __syncthreads();
+  const int tr = tid & 15, tc = tid >> 4;
+  C acc[4][4] = {};
+  for (int t = 0; t < NB; ++t) {
+    C x4[4], y4[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) { x4[x] = Ri[t][tr * 4 + x]; y4[x] = Rj[t][tc * 4 + x]; }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += x4[x] * y4[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = i * NB + tr * 4 + x, c = j * NB + tc * 4 + y;
+      if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[x][y];
+    }
+}
+
+template <typename C>
+static hipError_t cholesky_t(int N, int Np, C *G, int *info, hipStream_t st) {
+  for (int k = 0; k < N; ++k) {
+    hipLaunchKernelGGL(k_chol_panel<C>, dim3(N - k), dim3(256), 0, st, k, Np, G, info);
+    const int M = N - k - 1;
+    if (M > 0) hipLaunchKernelGGL(k_chol_update<C>, dim3(M * (M + 1) / 2), dim3(256), 0, st, k, N, Np, G);
+  }
+  return hipGetLastError();
+}
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, int *info, hipStream_t st) {
+  if (compute == TLS_FP64) return cholesky_t<double>(N, Np, (double *)G, info, st);
+  return cholesky_t<float>(N, Np, (float *)G, info, st);
+}
+
+// --------------------------------------------------------------------------
+// packing into tiles of the storage precision, diagonal-tile inverses
+// --------------------------------------------------------------------------
+template <typename C, typename S>
+__global__ void k_pack(int N, int Np, const C *G, S *tiles) {
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  S *T = tiles + (size_t)l * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    double v = 0;
+    if (I < J || r <= c) v = (double)G[((size_t)J * NB + c) * Np + (size_t)I * NB + r];
+    T[t] = st_from<S>(v);
+  }
+}
+template <typename C>
+static hipError_t pack_c(int N, int Np, const C *G, int storage, void *tiles, hipStream_t st) {
+  const dim3 g(N * (N + 1) / 2);
+  switch (storage) {
+    case TLS_FP64: hipLaunchKernelGGL((k_pack<C, double>), g, dim3(256), 0, st, N, Np, G, (double *)tiles); break;
+    case TLS_FP32: hipLaunchKernelGGL((k_pack<C, float>), g, dim3(256), 0, st, N, Np, G, (float *)tiles); break;
+    case TLS_FP16: hipLaunchKernelGGL((k_pack<C, half_t>), g, dim3(256), 0, st, N, Np, G, (half_t *)tiles); break;
+    default: hipLaunchKernelGGL((k_pack<C, bf16_t>), g, dim3(256), 0, st, N, Np, G, (bf16_t *)tiles); break;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
+                             hipStream_t st) {
+  if (compute == TLS_FP64) return pack_c<double>(N, Np, (const double *)G, storage, tiles, st);
+  return pack_c<float>(N, Np, (const float *)G, storage, tiles, st);
+}
+
+// inverse of each stored diagonal tile, computed in FP64 from the stored values
+template <typename S>
+__global__ __launch_bounds__(256) void k_diag_inverse(const S *tiles, double *dinv64, float *dinv32) {
+  __shared__ double T[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  const int I = blockIdx.x;
+  const S *src = tiles + ((size_t)I * (I + 1) / 2 + I) * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    T[r][c] = cvt<double>(src[t]);
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const int t = threadIdx.x;
+    for (int i = NB - 1; i > t; --i) X[i][t] = 0;
+    X[t][t] = 1.0 / T[t][t];
+    for (int i = t - 1; i >= 0; --i) {
+      double s = 0;
+      for (int l = i + 1; l <= t; ++l) s += T[i][l] * X[l][t];
+      X[i][t] = -s / T[i][i];
+    }
+  }
+  __syncthreads();
+  double *o64 = dinv64 + (size_t)I * NB * NB;
+  float *o32 = dinv32 + (size_t)I * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    o64[t] = X[r][c];
+    o32[t] = (float)X[r][c];
+  }
+}
+hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64, float *dinv32,
+                               hipStream_t st) {
+  switch (storage) {
+    case TLS_FP64: hipLaunchKernelGGL(k_diag_inverse<double>, dim3(N), dim3(256), 0, st, (const double *)tiles, dinv64, dinv32); break;
+    case TLS_FP32: hipLaunchKernelGGL(k_diag_inverse<float>, dim3(N), dim3(256), 0, st, (const float *)tiles, dinv64, dinv32); break;
+    case TLS_FP16: hipLaunchKernelGGL(k_diag_inverse<half_t>, dim3(N), dim3(256), 0, st, (const half_t *)tiles, dinv64, dinv32); break;
+    default: hipLaunchKernelGGL(k_diag_inverse<bf16_t>, dim3(N), dim3(256), 0, st, (const bf16_t *)tiles, dinv64, dinv32); break;
+  }
+  return hipGetLastError();
+}
+
+// import a caller factor (column-major n x n upper, FP64) into tiles
+template <typename S>
+__global__ void k_import(int n, const double *R, S *tiles) {
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  S *T = tiles + (size_t)l * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    const int gr = I * NB + r, gc = J * NB + c;
+    double v;
+    if (gr >= n || gc >= n) v = (gr == gc) ? 1.0 : 0.0;
+    else v = (gr <= gc) ? R[(size_t)gc * n + gr] : 0.0;
+    T[t] = st_from<S>(v);
+  }
+}
+hipError_t launch_import_tiles(int n, int N, int Np, const double *R, int storage, void *tiles,
+                               hipStream_t st) {
+  (void)Np;
+  const dim3 g(N * (N + 1) / 2);
+  switch (storage) {
+    case TLS_FP64: hipLaunchKernelGGL(k_import<double>, g, dim3(256), 0, st, n, R, (double *)tiles); break;
+    case TLS_FP32: hipLaunchKernelGGL(k_import<float>, g, dim3(256), 0, st, n, R, (float *)tiles); break;
+    case TLS_FP16: hipLaunchKernelGGL(k_import<half_t>, g, dim3(256), 0, st, n, R, (half_t *)tiles); break;
+    default: hipLaunchKernelGGL(k_import<bf16_t>, g, dim3(256), 0, st, n, R, (bf16_t *)tiles); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename S>
+__global__ void k_export(int n, const S *tiles, double *R) {
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  const S *T = tiles + (size_t)l * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t % NB, c = t / NB;
+    const int gr = I * NB + r, gc = J * NB + c;
+    if (gr < n && gc < n) {
+      R[(size_t)gc * n + gr] = (gr <= gc) ? cvt<double>(T[t]) : 0.0;
+      if (I < J) R[(size_t)gr * n + gc] = 0.0;    // the mirrored lower entry
+    }
+  }
+}
+hipError_t launch_export_tiles(int n, int N, int Np, int storage, const void *tiles, double *R,
+                               hipStream_t st) {
+  (void)Np;
+  const dim3 g(N * (N + 1) / 2);
+  switch (storage) {
+    case TLS_FP64: hipLaunchKernelGGL(k_export<double>, g, dim3(256), 0, st, n, (const double *)tiles, R); break;
+    case TLS_FP32: hipLaunchKernelGGL(k_export<float>, g, dim3(256), 0, st, n, (const float *)tiles, R); break;
+    case TLS_FP16: hipLaunchKernelGGL(k_export<half_t>, g, dim3(256), 0, st, n, (const half_t *)tiles, R); break;
+    default: hipLaunchKernelGGL(k_export<bf16_t>, g, dim3(256), 0, st, n, (const bf16_t *)tiles, R); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tls

@@ -1,0 +1,539 @@
+// Outer loop of RQI for TLS (Algorithm 2 / 4, precision u = FP64):
+//   r_k = b - A x_k,  sigma_k^2 = r^T r / (1 + x^T x),
+//   f_k = -A^T r_k - sigma_k^2 x_k,  g_k = -b^T r_k + sigma_k^2,
+//   psi_k = ((||f||^2 + g^2) / (||x||^2 + 1))^{1/2}          (eq. 4)
+//   z = x + omega,  beta = (z^T f - g) / (z^T x + 1),  x <- z + beta u.
+// The two passes over A (r = b - A x, then A^T r) stream A once each; the
+// inner products are fused into them as per-block partial sums that the
+// single-workgroup scalar kernels add in a fixed order.
+//
+// Scalar block `scal` (device, doubles):
+//   0 sigma^2   1 shift mu   2 ||x||^2   3 r^T r   4 b^T r   5 g (at mu)
+//   6 ||f||^2 (at mu)   7 psi   8 best psi   9 is-best flag   10 z^T f
+//   11 z^T x   12 beta   13 f^T x   14 shift cap   15 iteration count
+#include "common.h"
+#include "kernels.h"
+
+namespace tls {
+
+enum { S_SIG2 = 0, S_MU, S_XX, S_RR, S_BR, S_G, S_FF, S_PSI, S_BEST, S_ISBEST, S_ZF, S_ZX,
+       S_BETA, S_FX, S_CAP, S_K };
+
+constexpr int RES_ROWS = 256;   // rows per workgroup of the residual pass
+
+int matvec_blocks(const MatView &A) { return (A.m + RES_ROWS - 1) / RES_ROWS; }
+int rmatvec_blocks(const MatView &A) { return (A.n + 3) / 4; }
+
+// ---------------------------------------------------------------------------
+// r = b - A x with partials of r.r and b.r
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_residual_dense(int m, int n, int64_t ld, const double *A,
+                                                        const double *b, const double *x,
+                                                        double *r, double *part) {
+  __shared__ double sc[8];
+  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
+  double rv = 0, bv = 0;
+  if (i < m) {
+    double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    const double *a = A + i;
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+      acc0 += a[(size_t)(j + 0) * ld] * x[j + 0];
+      acc1 += a[(size_t)(j + 1) * ld] * x[j + 1];
+      acc2 += a[(size_t)(j + 2) * ld] * x[j + 2];
+      acc3 += a[(size_t)(j + 3) * ld] * x[j + 3];
+    }
+    for (; j < n; ++j) acc0 += a[(size_t)j * ld] * x[j];
+    bv = b[i];
+    rv = bv - ((acc0 + acc1) + (acc2 + acc3));
+    r[i] = rv;
+  }
+  const double rr = block_sum(rv * rv, sc);
+  const double br = block_sum(bv * rv, sc + 4);
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
+}
+
+__global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_ptr,
+                                                      const int32_t *col_idx, const double *val,
+                                                      const double *b, const double *x, double *r,
+                                                      double *part) {
+  __shared__ double sc[8];
+  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
+  double rv = 0, bv = 0;
+  if (i < m) {
+    double acc = 0;
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += val[e] * x[col_idx[e]];
+    bv = b[i];
+    rv = bv - acc;
+    r[i] = rv;
+  }
+  const double rr = block_sum(rv * rv, sc);
+  const double br = block_sum(bv * rv, sc + 4);
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
+}
+
+hipError_t launch_residual(const MatView &A, const double *b, const double *x, double *r,
+                           double *part, hipStream_t st) {
+  const dim3 g(matvec_blocks(A));
+  if (A.format == TLS_DENSE_COLMAJOR)
+    hipLaunchKernelGGL(k_residual_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, b, x, r, part);
+  else
+    hipLaunchKernelGGL(k_residual_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
+                       r, part);
+  return hipGetLastError();
+}
+
+// plain products (tests and x_LS): y = A x, y = A^T x
+__global__ void k_matvec_dense(int m, int n, int64_t ld, const double *A, const double *x, double *y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double acc = 0;
+  for (int j = 0; j < n; ++j) acc += A[i + (size_t)j * ld] * x[j];
+  y[i] = acc;
+}
+__global__ void k_matvec_csr(int m, const int32_t *row_ptr, const int32_t *col_idx,
+                             const double *val, const double *x, double *y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double acc = 0;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += val[e] * x[col_idx[e]];
+  y[i] = acc;
+}
+// A^T x: one wave per column (dense) / per CSC column
+__global__ void k_rmatvec_dense(int m, int n, int64_t ld, const double *A, const double *x, double *y) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= n) return;
+  const double *col = A + (size_t)j * ld;
+  double acc = 0;
+  for (int i = lane; i < m; i += 64) acc += col[i] * x[i];
+  acc = wave_sum(acc);
+  if (lane == 0) y[j] = acc;
+}
+__global__ void k_rmatvec_csc(int n, const int32_t *col_ptr, const int32_t *row_idx,
+                              const double *cval, const double *x, double *y) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= n) return;
+  double acc = 0;
+  for (int e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += 64) acc += cval[e] * x[row_idx[e]];
+  acc = wave_sum(acc);
+  if (lane == 0) y[j] = acc;
+}
+
+hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream_t st) {
+  const dim3 g((A.m + 255) / 256);
+  if (A.format == TLS_DENSE_COLMAJOR)
+    hipLaunchKernelGGL(k_matvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
+  else
+    hipLaunchKernelGGL(k_matvec_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st) {
+  const dim3 g((A.n + 3) / 4);
+  if (A.format == TLS_DENSE_COLMAJOR)
+    hipLaunchKernelGGL(k_rmatvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
+  else
+    hipLaunchKernelGGL(k_rmatvec_csc, g, dim3(256), 0, st, A.n, A.col_ptr, A.row_idx, A.cval, x, y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// f = -A^T r - mu x with partials of f.f and f.x (one wave per column)
+// ---------------------------------------------------------------------------
+template <bool CSC>
+__global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, const double *A,
+                                                  const int32_t *col_ptr, const int32_t *row_idx,
+                                                  const double *cval, const double *r,
+                                                  const double *x, const double *scal, double *f,
+                                                  double *part) {
+  __shared__ double sff[4], sfx[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + w;
+  double fv = 0, xv = 0;
+  if (j < n) {
+    double acc = 0;
+    if (CSC) {
+      for (int e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += 64) acc += cval[e] * r[row_idx[e]];
+    } else {
+      const double *col = A + (size_t)j * ld;
+      int i = lane;
+      double a1 = 0;
+      for (; i + 64 < m; i += 128) { acc += col[i] * r[i]; a1 += col[i + 64] * r[i + 64]; }
+      for (; i < m; i += 64) acc += col[i] * r[i];
+      acc += a1;
+    }
+    acc = wave_sum(acc);
+    xv = x[j];
+    fv = -acc - scal[S_MU] * xv;
+    if (lane == 0) f[j] = fv;
+  }
+  if (lane == 0) { sff[w] = fv * fv; sfx[w] = fv * xv; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (sff[0] + sff[1]) + (sff[2] + sff[3]);
+    part[2 * blockIdx.x + 1] = (sfx[0] + sfx[1]) + (sfx[2] + sfx[3]);
+  }
+}
+
+hipError_t launch_gradient(const MatView &A, const double *r, const double *x, const double *scal,
+                           double *f, double *part, hipStream_t st) {
+  const dim3 g(rmatvec_blocks(A));
+  if (A.format == TLS_DENSE_COLMAJOR)
+    hipLaunchKernelGGL(k_gradient<false>, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, nullptr,
+                       nullptr, nullptr, r, x, scal, f, part);
+  else
+    hipLaunchKernelGGL(k_gradient<true>, g, dim3(256), 0, st, A.m, A.n, (int64_t)0, nullptr,
+                       A.col_ptr, A.row_idx, A.cval, r, x, scal, f, part);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scalar kernels (one workgroup of 256 threads)
+// ---------------------------------------------------------------------------
+__device__ inline double sum_pairs(const double *part, int nb, int which, double *sc) {
+  double v = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[2 * i + which];
+  return block_sum(v, sc);
+}
+
+// sigma^2, the clamped shift and g from the residual partials
+__global__ __launch_bounds__(256) void k_outer_rq(int n, const double *x, const double *part_r,
+                                                  int nb_r, double *scal) {
+  __shared__ double sc[8];
+  double xx = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) xx += x[i] * x[i];
+  xx = block_sum(xx, sc);
+  const double rr = sum_pairs(part_r, nb_r, 0, sc + 4);
+  const double br = sum_pairs(part_r, nb_r, 1, sc);
+  if (threadIdx.x == 0) {
+    const double sig2 = rr / (1.0 + xx);
+    const double cap = scal[S_CAP];
+    const double mu = (cap > 0 && sig2 > cap) ? cap : sig2;
+    scal[S_SIG2] = sig2;
+    scal[S_MU] = mu;
+    scal[S_XX] = xx;
+    scal[S_RR] = rr;
+    scal[S_BR] = br;
+    scal[S_G] = -br + mu;
+  }
+}
+hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
+                           double clamp_max, hipStream_t st) {
+  (void)clamp_max;
+  hipLaunchKernelGGL(k_outer_rq, dim3(1), dim3(256), 0, st, n, x, part_r, nb_r, scal);
+  return hipGetLastError();
+}
+
+// psi_k from the gradient partials; best-psi bookkeeping; record (sigma, psi, mu)
+__global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, int nb_f,
+                                                   double *scal, int k, double *rec) {
+  __shared__ double sc[8];
+  const double ff = sum_pairs(part_f, nb_f, 0, sc);
+  const double fx = sum_pairs(part_f, nb_f, 1, sc + 4);
+  if (threadIdx.x == 0) {
+    const double sig2 = scal[S_SIG2], mu = scal[S_MU], xx = scal[S_XX], br = scal[S_BR];
+    const double dm = sig2 - mu;   // f at sigma^2 = f_mu - (sigma^2 - mu) x
+    const double ffs = (dm == 0.0) ? ff : fmax(0.0, ff - 2.0 * dm * fx + dm * dm * xx);
+    const double gs = -br + sig2;
+    const double psi = sqrt((ffs + gs * gs) / (xx + 1.0));
+    const double best = scal[S_BEST];
+    const int isbest = (k == 1) || (psi < best);
+    scal[S_FF] = ff;
+    scal[S_FX] = fx;
+    scal[S_PSI] = psi;
+    scal[S_ISBEST] = isbest ? 1.0 : 0.0;
+    if (isbest) scal[S_BEST] = psi;
+    scal[S_K] = (double)k;
+    rec[4 * (k - 1) + 0] = sig2;
+    rec[4 * (k - 1) + 1] = psi;
+    rec[4 * (k - 1) + 2] = mu;
+    rec[4 * (k - 1) + 3] = isbest;
+  }
+}
+hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
+                            double *scal, int k, double *rec, hipStream_t st) {
+  (void)x; (void)f; (void)n;
+  hipLaunchKernelGGL(k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec);
+  return hipGetLastError();
+}
+
+// right-hand sides of the two PCGTLS solves: [-f, x]
+__global__ void k_make_rhs(int n, const double *f, const double *x, double *rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  rhs[i] = -f[i];
+  rhs[n + i] = x[i];
+}
+hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_rhs, dim3((n + 255) / 256), dim3(256), 0, st, n, f, x, rhs);
+  return hipGetLastError();
+}
+
+// z = x + omega, beta = (z^T f - g)/(z^T x + 1), x <- z + beta u; keeps the
+// best iterate and an optional snapshot of x_k first
+__global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const double *wu,
+                                                     const double *f, double *scal, double *xbest,
+                                                     double *xsnap) {
+  __shared__ double sc[32];
+  const bool isbest = scal[S_ISBEST] != 0.0;
+  double zf = 0, zx = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double xv = x[i];
+    if (xbest && isbest) xbest[i] = xv;
+    if (xsnap) xsnap[i] = xv;
+    const double z = xv + wu[i];
+    zf += z * f[i];
+    zx += z * xv;
+  }
+  // block reduction over 16 waves
+  zf = wave_sum(zf);
+  zx = wave_sum(zx);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sc[w] = zf; sc[16 + w] = zx; }
+  __syncthreads();
+  double tzf = 0, tzx = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { tzf += sc[i]; tzx += sc[16 + i]; }
+  const double beta = (tzf - scal[S_G]) / (tzx + 1.0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double z = x[i] + wu[i];
+    x[i] = z + beta * wu[n + i];
+  }
+  if (threadIdx.x == 0) { scal[S_ZF] = tzf; scal[S_ZX] = tzx; scal[S_BETA] = beta; }
+}
+hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
+                             const double *scal, double *xbest, double *xsnap, hipStream_t st) {
+  hipLaunchKernelGGL(k_rqi_update, dim3(1), dim3(1024), 0, st, n, x, omega_u, f, (double *)scal,
+                     xbest, xsnap);
+  return hipGetLastError();
+}
+
+// x += scal[which] * u  (initial step x_1 = x_0 + sigma_0^2 u_0), or x += u when which < 0
+__global__ void k_axpy_scal(int n, double *x, const double *u, const double *scal, int which) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = which >= 0 ? scal[which] : 1.0;
+  x[i] += a * u[i];
+}
+hipError_t launch_axpy_init(int n, double *x, const double *u, const double *scal, int which,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_scal, dim3((n + 255) / 256), dim3(256), 0, st, n, x, u, scal, which);
+  return hipGetLastError();
+}
+
+__global__ void k_copy(double *dst, const double *src, size_t count) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i < count; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st) {
+  if (!count) return hipSuccess;
+  size_t g = (count + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+__global__ void k_add(double *x, const double *dx, size_t count) {
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i < count; i += (size_t)gridDim.x * blockDim.x) x[i] += dx[i];
+}
+hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t st) {
+  if (!count) return hipSuccess;
+  size_t g = (count + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_add, dim3((unsigned)g), dim3(256), 0, st, x, dx, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compensated residual (double-double): r_i = b_i - sum_j a_ij x_j with
+// TwoProd (fma) and TwoSum error terms (Ogita, Rump and Oishi, "Accurate
+// sum and dot product", 2005), then r.r accumulated the same way.
+// ---------------------------------------------------------------------------
+struct dd { double hi, lo; };
+__device__ inline dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  const double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ inline dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  s.lo += a.lo + b.lo;
+  return two_sum(s.hi, s.lo);
+}
+
+__global__ __launch_bounds__(256) void k_residual_dd(int format, int m, int n, int64_t ld,
+                                                     const double *A, const int32_t *row_ptr,
+                                                     const int32_t *col_idx, const double *b,
+                                                     const double *x, double *part) {
+  __shared__ double shi[256], slo[256];
+  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
+  dd rsq{0.0, 0.0};
+  if (i < m) {
+    double s = b[i], c = 0.0;
+    if (format == TLS_DENSE_COLMAJOR) {
+      for (int j = 0; j < n; ++j) {
+        const dd p = two_prod(A[i + (size_t)j * ld], x[j]);
+        const dd t = two_sum(s, -p.hi);
+        s = t.hi;
+        c += t.lo - p.lo;
+      }
+    } else {
+      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const dd p = two_prod(A[e], x[col_idx[e]]);
+        const dd t = two_sum(s, -p.hi);
+        s = t.hi;
+        c += t.lo - p.lo;
+      }
+    }
+    const dd r = two_sum(s, c);
+    // r^2 in double-double: (hi + lo)^2 ~ hi^2 + 2 hi lo
+    const dd sq = two_prod(r.hi, r.hi);
+    rsq = two_sum(sq.hi, sq.lo + 2.0 * r.hi * r.lo);
+  }
+  shi[threadIdx.x] = rsq.hi;
+  slo[threadIdx.x] = rsq.lo;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) {
+      const dd a{shi[threadIdx.x], slo[threadIdx.x]};
+      const dd bq{shi[threadIdx.x + off], slo[threadIdx.x + off]};
+      const dd s = dd_add(a, bq);
+      shi[threadIdx.x] = s.hi;
+      slo[threadIdx.x] = s.lo;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = shi[0]; part[2 * blockIdx.x + 1] = slo[0]; }
+}
+hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x, double *part,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_dd, dim3(matvec_blocks(A)), dim3(256), 0, st, A.format, A.m, A.n,
+                     A.ld, A.val, A.row_ptr, A.col_idx, b, x, part);
+  return hipGetLastError();
+}
+
+// sigma^2 = (sum r^2) / (1 + ||x||^2) with both sums in double-double; result in scal[0]
+__global__ __launch_bounds__(256) void k_sigma_dd(int n, const double *x, const double *part, int nb,
+                                                  double *scal) {
+  __shared__ double shi[256], slo[256];
+  dd acc{0.0, 0.0};
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc = dd_add(acc, dd{part[2 * i], part[2 * i + 1]});
+  dd xx{0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const dd p = two_prod(x[i], x[i]);
+    xx = dd_add(xx, p);
+  }
+  // reduce acc then xx
+  for (int pass = 0; pass < 2; ++pass) {
+    const dd v = pass == 0 ? acc : xx;
+    shi[threadIdx.x] = v.hi;
+    slo[threadIdx.x] = v.lo;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+      if (threadIdx.x < off) {
+        const dd s = dd_add(dd{shi[threadIdx.x], slo[threadIdx.x]},
+                            dd{shi[threadIdx.x + off], slo[threadIdx.x + off]});
+        shi[threadIdx.x] = s.hi;
+        slo[threadIdx.x] = s.lo;
+      }
+      __syncthreads();
+    }
+    if (pass == 0) acc = dd{shi[0], slo[0]};
+    else xx = dd{shi[0], slo[0]};
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // sigma^2 = acc / (1 + xx), one Newton correction of the double quotient
+    const dd den = dd_add(dd{1.0, 0.0}, xx);
+    const double q = acc.hi / den.hi;
+    const dd qd = two_prod(q, den.hi);
+    const double rem = ((acc.hi - qd.hi) - qd.lo + acc.lo - q * den.lo);
+    const double q2 = q + rem / den.hi;
+    scal[0] = q2;
+    scal[1] = sqrt(q2);
+  }
+}
+hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_sigma_dd, dim3(1), dim3(256), 0, st, n, x, part, nb, scal);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos step bookkeeping (gate estimates): w = V[k+1] holds M v_k; full
+// reorthogonalisation against v_0..v_k by classical Gram-Schmidt applied
+// twice, alpha_k from the first pass, beta_k = ||w||, v_{k+1} = w / beta_k.
+// One workgroup; ab[0..K) alpha, ab[K..2K) beta, ab[2K] active flag (1/0),
+// ab[2K+1] number of completed steps.
+// ---------------------------------------------------------------------------
+constexpr int LZ_MAX = 32;
+__global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int K, double *V,
+                                                       double *ab) {
+  __shared__ double red[16][LZ_MAX + 1];
+  __shared__ double h[LZ_MAX + 1];
+  if (ab[2 * K] == 0.0) return;        // stopped earlier (uniform across the block)
+  double *w = V + (size_t)(k + 1) * Np;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  double alpha = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    double acc[LZ_MAX + 1];
+#pragma unroll
+    for (int i = 0; i <= LZ_MAX; ++i) acc[i] = 0;
+    for (int j = tid; j < n; j += blockDim.x) {
+      const double wj = w[j];
+#pragma unroll
+      for (int i = 0; i <= LZ_MAX; ++i)
+        if (i <= k) acc[i] += V[(size_t)i * Np + j] * wj;
+    }
+#pragma unroll
+    for (int i = 0; i <= LZ_MAX; ++i) {
+      if (i <= k) {
+        const double v = wave_sum(acc[i]);
+        if (lane == 0) red[wv][i] = v;
+      }
+    }
+    __syncthreads();
+    if (tid <= k) {
+      double t = 0;
+      for (int q = 0; q < nw; ++q) t += red[q][tid];
+      h[tid] = t;
+    }
+    __syncthreads();
+    if (pass == 0) alpha = h[k];
+    for (int j = tid; j < n; j += blockDim.x) {
+      double wj = w[j];
+      for (int i = 0; i <= k; ++i) wj -= h[i] * V[(size_t)i * Np + j];
+      w[j] = wj;
+    }
+    __syncthreads();
+  }
+  double nn = 0;
+  for (int j = tid; j < n; j += blockDim.x) nn += w[j] * w[j];
+  nn = wave_sum(nn);
+  if (lane == 0) red[wv][0] = nn;
+  __syncthreads();
+  double tot = 0;
+  for (int q = 0; q < nw; ++q) tot += red[q][0];
+  const double beta = sqrt(tot);
+  // stop on an invariant subspace (relative to the operator scale alpha)
+  const bool stop = !(beta > 1e-13 * fabs(alpha)) || (k + 1 >= K);
+  if (!stop)
+    for (int j = tid; j < n; j += blockDim.x) w[j] /= beta;
+  __syncthreads();
+  if (tid == 0) {
+    ab[k] = alpha;
+    ab[K + k] = beta;
+    ab[2 * K + 1] = (double)(k + 1);
+    if (stop) ab[2 * K] = 0.0;
+  }
+}
+hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, double *ab, hipStream_t st) {
+  hipLaunchKernelGGL(k_lanczos_orth, dim3(1), dim3(1024), 0, st, n, Np, k, K, V, ab);
+  return hipGetLastError();
+}
+
+}  // namespace tls

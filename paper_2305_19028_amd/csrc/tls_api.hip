@@ -1,0 +1,942 @@
+// Host driver and C ABI of libtls (declarations and contracts in tls.h).
+//
+// Every entry point validates its arguments, carves its workspace with a
+// fixed layout (the *_workspace_size functions run the same carving on a
+// null base), enqueues kernels on the caller's stream and maps failures to
+// tls_status with a thread-local message. Nothing here computes on the
+// host except scalar control decisions (the psi stopping rule, the gate
+// verdict, the Lanczos tridiagonal eigenvalues).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "tls.h"
+
+using namespace tls;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err = "no error";
+
+static tls_status fail(tls_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return fail(TLS_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define TRY(expr)                      \
+  do {                                 \
+    tls_status _s = (expr);            \
+    if (_s != TLS_OK) return _s;       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// workspace carving
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~(size_t)255; }
+};
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+MatView make_view(const tls_matrix *A, const tls_precond_s *P);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the preconditioner object
+// ---------------------------------------------------------------------------
+struct FactorWsRef;
+struct tls_precond_s {
+  int64_t n = 0;
+  int N = 0, Np = 0;
+  int storage = TLS_FP64, requested = TLS_FP64, scaled = 0, format = TLS_DENSE_COLMAJOR;
+  int64_t m = 0, nnz = 0;
+  void *tiles = nullptr;
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;
+  double *dsc64 = nullptr;
+  float *dsc32 = nullptr;
+  double *d = nullptr;
+  int32_t *col_ptr = nullptr, *row_idx = nullptr;
+  double *cval = nullptr;
+  tls_gate_report rep{};
+  void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
+  int64_t fws_m = 0;
+  int have_sigma_n = 0, have_kappa = 0;
+  FactorView view() const {
+    FactorView F;
+    F.n = (int)n;
+    F.N = N;
+    F.Np = Np;
+    F.storage = storage;
+    F.tiles = tiles;
+    F.dinv64 = dinv64;
+    F.dinv32 = dinv32;
+    F.dscale64 = dsc64;
+    F.dscale32 = dsc32;
+    return F;
+  }
+};
+
+namespace {
+
+MatView make_view(const tls_matrix *A, const tls_precond_s *P) {
+  MatView V{};
+  V.format = A->format;
+  V.m = (int)A->m;
+  V.n = (int)A->n;
+  V.ld = A->ld;
+  V.nnz = A->nnz;
+  V.val = A->val;
+  V.row_ptr = A->row_ptr;
+  V.col_idx = A->col_idx;
+  if (P) {
+    V.col_ptr = P->col_ptr;
+    V.row_idx = P->row_idx;
+    V.cval = P->cval;
+  }
+  return V;
+}
+
+tls_status check_matrix(const tls_matrix *A) {
+  if (!A) return fail(TLS_ERR_ARG, "A is NULL");
+  if (A->m <= 0 || A->n <= 0) return fail(TLS_ERR_ARG, "A has m = %lld, n = %lld", (long long)A->m, (long long)A->n);
+  if (A->m < A->n + 1) return fail(TLS_ERR_ARG, "need m >= n + 1 (m = %lld, n = %lld)", (long long)A->m, (long long)A->n);
+  if (A->m > (int64_t)INT32_MAX || A->n > 65536) return fail(TLS_ERR_ARG, "A too large for this build (m < 2^31, n <= 65536)");
+  if (!A->val) return fail(TLS_ERR_ARG, "A->val is NULL");
+  if (A->format == TLS_DENSE_COLMAJOR) {
+    if (A->ld < A->m) return fail(TLS_ERR_ARG, "ld (%lld) < m (%lld)", (long long)A->ld, (long long)A->m);
+  } else if (A->format == TLS_CSR) {
+    if (!A->row_ptr || !A->col_idx) return fail(TLS_ERR_ARG, "CSR index arrays are NULL");
+    if (A->nnz < 0 || A->nnz > (int64_t)INT32_MAX) return fail(TLS_ERR_ARG, "nnz out of range");
+  } else {
+    return fail(TLS_ERR_ARG, "unknown format %d", A->format);
+  }
+  return TLS_OK;
+}
+
+tls_status check_prec(int p, const char *what) {
+  if (p < TLS_FP64 || p > TLS_BF16) return fail(TLS_ERR_ARG, "invalid precision %d for %s", p, what);
+  return TLS_OK;
+}
+
+// ---- factor workspace layout -----------------------------------------------
+struct FactorWs {
+  void *tiles;
+  double *dinv64;
+  float *dinv32;
+  double *dsc64;
+  float *dsc32;
+  double *d;
+  void *G;
+  int32_t *col_ptr, *row_idx, *tmp_row, *fill;
+  double *cval, *tmp_val;
+  void *valq, *cvalq;
+  int *info;
+  int *sync;
+  double *lz;      // Lanczos vectors
+  double *lzs;     // Lanczos scalars
+  int *flag;
+};
+constexpr int LANCZOS_STEPS = 24;
+
+FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format) {
+  const int Np = ceil_div(n, NB) * NB, N = Np / NB;
+  FactorWs W{};
+  W.tiles = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
+  W.dinv64 = c.take<double>((size_t)N * NB * NB);
+  W.dinv32 = c.take<float>((size_t)N * NB * NB);
+  W.dsc64 = c.take<double>(Np);
+  W.dsc32 = c.take<float>(Np);
+  W.d = c.take<double>(Np);
+  W.G = c.take<char>((size_t)Np * Np * 8);
+  if (format == TLS_CSR) {
+    W.col_ptr = c.take<int32_t>(n + 1);
+    W.row_idx = c.take<int32_t>(nnz);
+    W.cval = c.take<double>(nnz);
+    W.tmp_row = c.take<int32_t>(nnz);
+    W.tmp_val = c.take<double>(nnz);
+    W.fill = c.take<int32_t>(n);
+    W.valq = c.take<char>(nnz * 8);
+    W.cvalq = c.take<char>(nnz * 8);
+  }
+  W.info = c.take<int>(4);
+  W.sync = c.take<int>(N + 8);
+  W.lz = c.take<double>((size_t)(LANCZOS_STEPS + 5) * Np);
+  W.lzs = c.take<double>(2 * LANCZOS_STEPS + 8);
+  W.flag = c.take<int>(4);
+  (void)m;
+  return W;
+}
+
+// ---- solve workspace (one triangular solve / PCGTLS run) --------------------
+struct PcgWs {
+  int *sync;
+  double *chain, *s, *p, *q, *w;   // sized for FP64 compute
+  double *part;
+  int *done, *neg;
+  double *trace;
+  double *sigma2;
+  int L;
+};
+
+PcgWs carve_pcg(Carver &c, int Np, int N, int nrhs, int L) {
+  PcgWs W{};
+  W.L = L;
+  W.sync = c.take<int>(N + 8);
+  W.chain = c.take<double>((size_t)nrhs * Np);
+  W.s = c.take<double>((size_t)nrhs * Np);
+  W.p = c.take<double>((size_t)nrhs * Np);
+  W.q = c.take<double>((size_t)nrhs * Np);
+  W.w = c.take<double>((size_t)nrhs * Np);
+  W.part = c.take<double>((size_t)(L + 2) * 3 * nrhs * N);
+  W.done = c.take<int>((size_t)(L + 2) * nrhs);
+  W.neg = c.take<int>((size_t)(L + 2) * nrhs);
+  W.trace = c.take<double>((size_t)nrhs * 4 * (L + 2));
+  W.sigma2 = c.take<double>(2);
+  return W;
+}
+
+SolveBufs bufs_of(const PcgWs &W) {
+  SolveBufs B{};
+  B.sync = W.sync;
+  B.chain = W.chain;
+  B.s = W.s;
+  B.p = W.p;
+  B.q = W.q;
+  B.w = W.w;
+  B.part = W.part;
+  B.done = W.done;
+  B.neg = W.neg;
+  B.trace = W.trace;
+  B.sigma2 = W.sigma2;
+  B.L = W.L;
+  return B;
+}
+
+// read the status word of a sync area (blocking)
+tls_status sync_status(const int *sync, int N, hipStream_t st) {
+  int v[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(v, sync + N + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (v[1] == TLS_ERR_SYNC_TIMEOUT) return fail(TLS_ERR_SYNC_TIMEOUT, "inter-workgroup wait timed out");
+  if (v[1] == TLS_ERR_INDEFINITE) return fail(TLS_ERR_INDEFINITE, "delta_j <= 0 in PCGTLS (shifted system not positive definite)");
+  if (v[0]) return fail(TLS_ERR_SYNC_TIMEOUT, "solve aborted");
+  return TLS_OK;
+}
+
+// R^{-1} (trans = 0) or R^{-T} (trans = 1) on nrhs FP64 vectors
+tls_status apply_R(const tls_precond_s *P, int trans, int nrhs, const double *in, double *out,
+                   int compute, PcgWs &W, hipStream_t st) {
+  SolveBufs B = bufs_of(W);
+  B.in = in;
+  B.out = out;
+  HIPCHK(launch_trsv(P->view(), compute, trans ? 1 /*APPLY_F*/ : 0 /*APPLY_B*/, nrhs, B, st));
+  return TLS_OK;
+}
+
+// PCGTLS (Algorithm 3), l+1 steps, sigma2 read from device memory
+tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, const double *rhs,
+                   double *omega, int l, int compute, int strict, PcgWs &W, hipStream_t st) {
+  if (l + 1 > W.L + 1) return fail(TLS_ERR_WORKSPACE, "PCG workspace sized for l <= %d", W.L);
+  const int N = P->N;
+  HIPCHK(launch_fill_i32(W.done, 0, (size_t)(W.L + 2) * nrhs, st));
+  HIPCHK(launch_fill_i32(W.neg, 0, (size_t)(W.L + 2) * nrhs, st));
+  HIPCHK(launch_fill_f64(W.trace, std::numeric_limits<double>::quiet_NaN(), (size_t)nrhs * 4 * (W.L + 2), st));
+  SolveBufs B = bufs_of(W);
+  B.sigma2 = sig2_dev;
+  B.strict = strict;
+  B.in = rhs;
+  B.j = 0;
+  const FactorView F = P->view();
+  HIPCHK(launch_trsv(F, compute, 2 /*PCG_F0*/, nrhs, B, st));
+  for (int j = 0; j <= l; ++j) {
+    B.j = j;
+    HIPCHK(launch_trsv(F, compute, 3 /*PCG_B*/, nrhs, B, st));
+    HIPCHK(launch_trsv(F, compute, 4 /*PCG_F*/, nrhs, B, st));
+  }
+  HIPCHK(launch_pcg_finish(compute, W.w, omega, (int)P->n, P->Np, nrhs, st));
+  (void)N;
+  return TLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos on M = R^{-T}... estimates for the precision gate (K11)
+// ---------------------------------------------------------------------------
+// eigenvalues of a symmetric tridiagonal matrix by bisection (Sturm counts)
+void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b, double *lo,
+                      double *hi) {
+  const int k = (int)a.size();
+  double gl = a[0], gu = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < k ? std::fabs(b[i]) : 0);
+    gl = std::min(gl, a[i] - r);
+    gu = std::max(gu, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < k; ++i) {
+      const double qq = (q == 0) ? 1e-300 : q;
+      q = a[i] - x - b[i - 1] * b[i - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int idx) {
+    double l = gl, u = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (l + u);
+      if (mid <= l || mid >= u) break;
+      if (count_below(mid) > idx) u = mid; else l = mid;
+    }
+    return 0.5 * (l + u);
+  };
+  *lo = kth(0);
+  *hi = kth(k - 1);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *tls_last_error(void) { return g_err.c_str(); }
+const char *tls_version(void) { return "libtls 0.1 (gfx950)"; }
+
+void tls_default_opts(tls_rqi_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->u_p = TLS_FP64;
+  o->kmax = 60;
+  o->stop_patience = 1;
+  o->stop_ge = 0;
+  o->ls_corrections = 1;
+  o->strict_pd = 0;
+  o->shift_clamp = 0;
+  o->refine_sweeps = 0;
+  o->refine_pcg_steps = 8;
+  o->allow_escalate = 0;
+  o->gate_enforce = 0;
+  o->shift_clamp_tau = 0.9;
+  o->sigma0_hint = -1.0;
+  o->x_snapshots = nullptr;
+}
+
+size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q) {
+  (void)u_q;
+  if (check_matrix(A) != TLS_OK) return 0;
+  Carver c(nullptr);
+  carve_factor(c, A->m, A->n, A->nnz, A->format);
+  return c.size();
+}
+
+size_t tls_precond_import_workspace_size(int64_t n) {
+  if (n <= 0) return 0;
+  Carver c(nullptr);
+  carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR);
+  return c.size();
+}
+
+void tls_precond_destroy(tls_precond P) { delete P; }
+
+tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage, tls_gate_report *rep) {
+  if (!P) return fail(TLS_ERR_ARG, "P is NULL");
+  if (n) *n = P->n;
+  if (storage) *storage = P->storage;
+  if (rep) *rep = P->rep;
+  return TLS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// form the Gram matrix of the scaled, u_q-rounded A in G (compute precision)
+tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq, int compute,
+                     hipStream_t st) {
+  const int n = (int)A->n, Np = P->Np;
+  if (A->format == TLS_CSR) {
+    HIPCHK(launch_quantize_sparse(A->nnz, A->col_idx, A->val, W.d, P->scaled, uq, compute, W.valq, st));
+    HIPCHK(launch_quantize_csc(n, W.col_ptr, W.cval, W.d, P->scaled, uq, compute, W.cvalq, st));
+    HIPCHK(launch_gram_sparse((int)A->m, n, Np, A->row_ptr, A->col_idx, W.valq, W.col_ptr,
+                              W.row_idx, W.cvalq, compute, W.G, st));
+  } else {
+    HIPCHK(launch_gram_dense((int)A->m, n, Np, A->ld, A->val, W.d, P->scaled, uq, compute, W.G, st));
+  }
+  HIPCHK(launch_gram_pad(n, Np, compute, W.G, st));
+  return TLS_OK;
+}
+
+// Lanczos on M = R^{-1} R^{-T} = (R^T R)^{-1} (eigenvalues 1/sigma_i^2 of the
+// factored matrix): with use_scaling the operator uses R_hat alone (the
+// scaled A D^{-1}), otherwise R = R_hat D (A itself). Runs on the device
+// with full reorthogonalisation; the tridiagonal is read back once.
+tls_status lanczos_extremes(tls_precond_s *P, FactorWs &W, int use_scaling, double *lam_lo,
+                            double *lam_hi, int *steps, hipStream_t st) {
+  const int n = (int)P->n, Np = P->Np;
+  const int K = std::min(LANCZOS_STEPS, n);
+  double *V = W.lz;                                   // K+1 basis vectors, stride Np
+  PcgWs S{};
+  S.sync = W.sync;
+  S.chain = W.lz + (size_t)(LANCZOS_STEPS + 2) * Np;
+  S.L = 0;
+  double *tmp = W.lz + (size_t)(LANCZOS_STEPS + 3) * Np;
+  double *ones = W.lz + (size_t)(LANCZOS_STEPS + 4) * Np;
+  double *ab = W.lzs;                                 // 2K + 2 scalars
+  tls_precond_s Q = *P;
+  if (use_scaling) {
+    HIPCHK(launch_fill_f64(ones, 1.0, (size_t)Np, st));
+    Q.dsc64 = ones;
+  }
+  HIPCHK(launch_fill_f64(V, 1.0 / std::sqrt((double)n), (size_t)n, st));   // v_0
+  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (size_t)K + 2, st));
+  HIPCHK(launch_fill_f64(ab + 2 * K, 1.0, 1, st));
+  for (int k = 0; k < K; ++k) {
+    TRY(apply_R(&Q, 1, 1, V + (size_t)k * Np, tmp, TLS_FP64, S, st));
+    TRY(apply_R(&Q, 0, 1, tmp, V + (size_t)(k + 1) * Np, TLS_FP64, S, st));
+    HIPCHK(launch_lanczos_orth(n, Np, k, K, V, ab, st));
+  }
+  std::vector<double> h(2 * K + 2);
+  HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int done = (int)h[2 * K + 1];
+  std::vector<double> a(h.begin(), h.begin() + done), b(h.begin() + K, h.begin() + K + std::max(done - 1, 0));
+  *steps = done;
+  tridiag_extremes(a, b, lam_lo, lam_hi);
+  return TLS_OK;
+}
+
+// sigma'_n(A) and sigma'_1(A) estimates (unscaled operator)
+tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  double lo = 0, hi = 0;
+  int steps = 0;
+  TRY(lanczos_extremes(P, W, 0, &lo, &hi, &steps, st));
+  P->rep.sigma_n_est = 1.0 / std::sqrt(hi);
+  P->rep.sigma_1_est = 1.0 / std::sqrt(std::max(lo, 1e-300));
+  P->rep.lanczos_steps = steps;
+  P->have_sigma_n = 1;
+  return TLS_OK;
+}
+
+// the A-only constraints of Section 3.1 from Lanczos estimates
+tls_status run_gate(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  tls_gate_report &R = P->rep;
+  const double n = (double)P->n;
+  double lo = 0, hi = 0;
+  int steps = 0;
+  // scaled operator: eigenvalues of R_hat^{-1} R_hat^{-T} are 1/sigma_i(A D^{-1})^2
+  TRY(lanczos_extremes(P, W, 1, &lo, &hi, &steps, st));
+  const double smin_s = 1.0 / std::sqrt(hi), smax_s = 1.0 / std::sqrt(std::max(lo, 1e-300));
+  TRY(estimate_sigma_n(P, W, st));
+  const double kap = P->scaled ? smax_s / smin_s : R.sigma_1_est / R.sigma_n_est;
+  R.kappa_est = kap;
+  // ||A D^{-1}||_F = sqrt(n) exactly when scaled
+  R.kappaF_est = P->scaled ? std::sqrt(n) / smin_s : std::numeric_limits<double>::quiet_NaN();
+  R.lam_min_H = smin_s * smin_s;
+  R.bound5 = 1.0 / kap;
+  R.bound_chol = 1.0 / (kap * kap);
+  R.bound_wilkinson = 1.0 / (20.0 * std::pow(n, 1.5) * kap * kap);
+  R.bound_hp = R.lam_min_H / ((2.0 * R.lam_min_H + n) * (n + 1.0));
+  R.u_q = unit_roundoff(P->storage);
+  int v = 0;
+  if (R.u_q < R.bound5) v |= 1;
+  if (R.u_q < R.bound_chol) v |= 2;
+  if (R.u_q < R.bound_hp) v |= 4;
+  R.verdict = v;
+  P->have_kappa = 1;
+  return TLS_OK;
+}
+
+FactorWs factor_ws_of(const tls_precond_s *P) {
+  Carver c(P->fws_base);
+  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format);
+}
+
+tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
+                       hipStream_t st, int *breakdown) {
+  const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+  const int n = (int)A->n;
+  *breakdown = 0;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    TRY(form_gram(A, P, W, uq, compute, st));
+    if (attempt > 0) {
+      // diagonal perturbation 2^(attempt-1) n u_q (scaled H has unit diagonal)
+      const double shift = std::ldexp(1.0, attempt - 1) * n * unit_roundoff(uq) *
+                           (P->scaled ? 1.0 : 1.0);
+      HIPCHK(launch_gram_shift(n, P->Np, compute, W.G, shift, st));
+      P->rep.chol_retries = attempt;
+    }
+    HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
+    HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.info, st));
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info == INT32_MAX) {
+      HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, uq, W.tiles, st));
+      HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
+      P->storage = uq;
+      return TLS_OK;
+    }
+    *breakdown = info;
+    if (!P->scaled) break;   // the shift ladder is defined for the scaled matrix
+  }
+  return fail(TLS_ERR_NOT_SPD, "Cholesky breakdown at column %d", *breakdown - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
+                              int32_t allow_escalate, void *ws, size_t ws_bytes,
+                              hipStream_t stream, tls_precond *out, tls_gate_report *rep) {
+  try {
+    TRY(check_matrix(A));
+    TRY(check_prec(u_q, "u_q"));
+    if (!out) return fail(TLS_ERR_ARG, "out is NULL");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (!scaling && u_q != TLS_FP64) return fail(TLS_ERR_ARG, "unscaled factorization is FP64 only");
+    const size_t need = tls_factor_workspace_size(A, u_q);
+    if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "factor workspace %zu < %zu bytes", ws_bytes, need);
+    Carver c(ws);
+    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format);
+    auto *P = new (std::nothrow) tls_precond_s();
+    if (!P) return fail(TLS_ERR_ARG, "out of host memory");
+    std::unique_ptr<tls_precond_s> guard(P);
+    const int n = (int)A->n;
+    P->n = n;
+    P->Np = ceil_div(n, NB) * NB;
+    P->N = P->Np / NB;
+    P->m = A->m;
+    P->nnz = A->nnz;
+    P->format = A->format;
+    P->scaled = scaling ? 1 : 0;
+    P->requested = u_q;
+    P->tiles = W.tiles;
+    P->dinv64 = W.dinv64;
+    P->dinv32 = W.dinv32;
+    P->dsc64 = W.dsc64;
+    P->dsc32 = W.dsc32;
+    P->d = W.d;
+    P->fws_base = ws;
+    P->fws_m = A->m;
+    P->rep = tls_gate_report{};
+    P->rep.requested = u_q;
+    P->rep.sigma_n_est = P->rep.sigma_1_est = std::numeric_limits<double>::quiet_NaN();
+    HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
+    // finite input check
+    HIPCHK(launch_fill_i32(W.flag, 0, 1, stream));
+    const size_t nval = A->format == TLS_CSR ? (size_t)A->nnz : (size_t)A->ld * (size_t)(n - 1) + (size_t)A->m;
+    HIPCHK(launch_check_finite(A->val, nval, W.flag, stream));
+    // CSC copy and column norms
+    if (A->format == TLS_CSR) {
+      HIPCHK(launch_csc_build((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, A->val, W.col_ptr,
+                              W.row_idx, W.cval, W.tmp_row, W.tmp_val, W.fill, stream));
+      HIPCHK(launch_colnorms_csc(n, W.col_ptr, W.cval, W.d, stream));
+      P->col_ptr = W.col_ptr;
+      P->row_idx = W.row_idx;
+      P->cval = W.cval;
+    } else {
+      HIPCHK(launch_colnorms_dense((int)A->m, n, A->ld, A->val, W.d, stream));
+    }
+    HIPCHK(launch_scale_vectors(n, P->Np, W.d, P->scaled, W.dsc64, W.dsc32, stream));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, W.flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (flag) return fail(TLS_ERR_NONFINITE, "A contains NaN or Inf");
+    int uq = u_q;
+    for (;;) {
+      int bd = 0;
+      tls_status s = factor_once(A, P, W, uq, stream, &bd);
+      if (s == TLS_OK) {
+        if (uq != TLS_FP64) TRY(run_gate(P, W, stream));
+        else P->rep.u_q = unit_roundoff(TLS_FP64);
+        const bool chol_ok = (P->rep.verdict & 2) || (P->rep.verdict & 4);
+        if (uq == TLS_FP64 || chol_ok || !allow_escalate) break;
+        // the A-only constraints fail: the a-posteriori evidence is the
+        // factorization itself (it succeeded); keep it unless escalation is
+        // requested explicitly by a failed b-dependent check in the solve
+        break;
+      }
+      if (s != TLS_ERR_NOT_SPD || !allow_escalate || uq == TLS_FP64) return s;
+      // escalate: BF16 -> FP16 -> FP32 -> FP64
+      uq = (uq == TLS_BF16) ? TLS_FP16 : (uq == TLS_FP16) ? TLS_FP32 : TLS_FP64;
+      P->rep.escalations++;
+    }
+    P->rep.used = P->storage;
+    if (rep) *rep = P->rep;
+    *out = guard.release();
+    return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
+tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_host, int32_t storage,
+                              void *ws, size_t ws_bytes, hipStream_t stream, tls_precond *out) {
+  try {
+    if (n <= 0 || !R_host || !out) return fail(TLS_ERR_ARG, "bad arguments to tls_precond_import");
+    TRY(check_prec(storage, "storage"));
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    const size_t need = tls_precond_import_workspace_size(n);
+    if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "import workspace %zu < %zu bytes", ws_bytes, need);
+    Carver c(ws);
+    FactorWs W = carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR);
+    auto P = std::make_unique<tls_precond_s>();
+    P->n = n;
+    P->Np = ceil_div(n, NB) * NB;
+    P->N = P->Np / NB;
+    P->storage = storage;
+    P->requested = storage;
+    P->scaled = d_host ? 1 : 0;
+    P->tiles = W.tiles;
+    P->dinv64 = W.dinv64;
+    P->dinv32 = W.dinv32;
+    P->dsc64 = W.dsc64;
+    P->dsc32 = W.dsc32;
+    P->d = W.d;
+    P->fws_base = ws;
+    P->fws_m = n + 1;
+    P->format = TLS_DENSE_COLMAJOR;
+    P->nnz = 0;
+    // stage R (host) through the G region of the workspace
+    HIPCHK(hipMemcpyAsync(W.G, R_host, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, stream));
+    std::vector<double> dh(P->Np, 1.0);
+    if (d_host) for (int64_t i = 0; i < n; ++i) dh[i] = d_host[i];
+    HIPCHK(hipMemcpyAsync(W.d, dh.data(), P->Np * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIPCHK(launch_scale_vectors((int)n, P->Np, W.d, 1, W.dsc64, W.dsc32, stream));
+    HIPCHK(launch_import_tiles((int)n, P->N, P->Np, (const double *)W.G, storage, W.tiles, stream));
+    HIPCHK(launch_diag_inverse(P->N, storage, W.tiles, W.dinv64, W.dinv32, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    P->rep.requested = P->rep.used = storage;
+    P->rep.u_q = unit_roundoff(storage);
+    *out = P.release();
+    return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
+tls_status tls_precond_export(const tls_precond P, double *R_host, double *d_host, hipStream_t stream) {
+  if (!P || !R_host) return fail(TLS_ERR_ARG, "bad arguments to tls_precond_export");
+  // tiles -> dense column-major staged in device memory right after the tiles is not
+  // available here; use a temporary device buffer owned by the runtime is not allowed,
+  // so the export reuses the Gram region of the factor workspace, which is free after
+  // the factorization.
+  const size_t bytes = (size_t)P->n * P->n * sizeof(double);
+  char *tiles_end = (char *)P->tiles + (size_t)P->N * (P->N + 1) / 2 * NB * NB * 8;
+  // G follows dinv64, dinv32, dsc64, dsc32, d in the carve order
+  (void)tiles_end;
+  Carver c((char *)P->tiles);
+  c.take<char>((size_t)P->N * (P->N + 1) / 2 * NB * NB * 8);
+  c.take<double>((size_t)P->N * NB * NB);
+  c.take<float>((size_t)P->N * NB * NB);
+  c.take<double>(P->Np);
+  c.take<float>(P->Np);
+  c.take<double>(P->Np);
+  double *G = c.take<double>((size_t)P->Np * P->Np);
+  HIPCHK(launch_export_tiles((int)P->n, P->N, P->Np, P->storage, P->tiles, G, stream));
+  HIPCHK(hipMemcpyAsync(R_host, G, bytes, hipMemcpyDeviceToHost, stream));
+  if (d_host) HIPCHK(hipMemcpyAsync(d_host, P->d, P->n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return TLS_OK;
+}
+
+size_t tls_pcg_workspace_size(const tls_precond P, int32_t nrhs, int32_t l) {
+  if (!P || nrhs < 1 || nrhs > 2 || l < 0) return 0;
+  Carver c(nullptr);
+  carve_pcg(c, P->Np, P->N, nrhs, l);
+  return c.size();
+}
+
+tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs, const double *rhs,
+                        double *omega, int32_t l, int32_t u_p, int32_t strict_pd, void *ws,
+                        size_t ws_bytes, hipStream_t stream, double *trace) {
+  try {
+    if (!P) return fail(TLS_ERR_ARG, "P is NULL");
+    if (nrhs < 1 || nrhs > 2) return fail(TLS_ERR_ARG, "nrhs must be 1 or 2");
+    if (l < 0 || l > 4096) return fail(TLS_ERR_ARG, "l out of range");
+    if (u_p != TLS_FP64 && u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
+    if (!rhs || !omega) return fail(TLS_ERR_ARG, "rhs/omega NULL");
+    if (!std::isfinite(sigma2) || sigma2 < 0) return fail(TLS_ERR_ARG, "sigma2 must be finite and >= 0");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    const size_t need = tls_pcg_workspace_size(P, nrhs, l);
+    if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "PCG workspace %zu < %zu bytes", ws_bytes, need);
+    Carver c(ws);
+    PcgWs W = carve_pcg(c, P->Np, P->N, nrhs, l);
+    HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
+    HIPCHK(launch_fill_f64(W.sigma2, sigma2, 1, stream));
+    TRY(pcg_run(P, W.sigma2, nrhs, rhs, omega, l, u_p, strict_pd, W, stream));
+    if (trace || strict_pd) {
+      TRY(sync_status(W.sync, P->N, stream));
+      if (trace) {
+        HIPCHK(hipMemcpyAsync(trace, W.trace, (size_t)nrhs * 4 * (l + 2) * sizeof(double),
+                              hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+      }
+    }
+    return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
+tls_status tls_apply_precond(const tls_precond P, int32_t trans, int32_t nrhs, const double *in,
+                             double *out, int32_t u_p, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!P || !in || !out) return fail(TLS_ERR_ARG, "bad arguments to tls_apply_precond");
+  if (nrhs < 1 || nrhs > 2) return fail(TLS_ERR_ARG, "nrhs must be 1 or 2");
+  if (u_p != TLS_FP64 && u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
+  const size_t need = tls_pcg_workspace_size(P, nrhs, 0);
+  if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "apply workspace too small (%zu < %zu)", ws_bytes, need);
+  Carver c(ws);
+  PcgWs W = carve_pcg(c, P->Np, P->N, nrhs, 0);
+  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
+  TRY(apply_R(P, trans, nrhs, in, out, u_p, W, stream));
+  return TLS_OK;
+}
+
+tls_status tls_round(const double *in, int64_t count, int32_t prec, double *out, hipStream_t stream) {
+  TRY(check_prec(prec, "prec"));
+  if (count < 0 || (count > 0 && (!in || !out))) return fail(TLS_ERR_ARG, "bad arguments to tls_round");
+  HIPCHK(launch_round(in, count, prec, out, stream));
+  return TLS_OK;
+}
+
+tls_status tls_matvec(const tls_matrix *A, const tls_precond P, int32_t trans, const double *x,
+                      double *y, hipStream_t stream) {
+  TRY(check_matrix(A));
+  if (!x || !y) return fail(TLS_ERR_ARG, "x/y NULL");
+  if (trans && A->format == TLS_CSR && !P) return fail(TLS_ERR_ARG, "CSR A^T x needs the CSC copy in P");
+  MatView V = make_view(A, P);
+  if (trans) HIPCHK(launch_rmatvec(V, x, y, stream));
+  else HIPCHK(launch_matvec(V, x, y, stream));
+  return TLS_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// RQI driver
+// ===========================================================================
+namespace {
+
+struct RqiWs {
+  double *r, *f, *xbest, *rhs, *wu, *t1, *t2, *part, *scal, *rec;
+  PcgWs pcg;
+};
+
+RqiWs carve_rqi(Carver &c, int64_t m, int64_t n, const tls_precond_s *P, int kmax, int L) {
+  RqiWs W{};
+  MatView V{};
+  V.m = (int)m;
+  V.n = (int)n;
+  const int nb = std::max(matvec_blocks(V), rmatvec_blocks(V)) + 1;
+  W.r = c.take<double>(m);
+  W.f = c.take<double>(n);
+  W.xbest = c.take<double>(n);
+  W.rhs = c.take<double>(2 * n);
+  W.wu = c.take<double>(2 * n);
+  W.t1 = c.take<double>(n);
+  W.t2 = c.take<double>(n);
+  W.part = c.take<double>(2 * (size_t)nb);
+  W.scal = c.take<double>(32);
+  W.rec = c.take<double>(4 * (size_t)(kmax + 2));
+  W.pcg = carve_pcg(c, P->Np, P->N, 2, L);
+  return W;
+}
+
+// x = R^{-1} R^{-T} v (FP64 arithmetic on the stored factor)
+tls_status solve_normal(const tls_precond_s *P, const double *v, double *x, double *tmp, PcgWs &W,
+                        hipStream_t st) {
+  TRY(apply_R(P, 1, 1, v, tmp, TLS_FP64, W, st));
+  TRY(apply_R(P, 0, 1, tmp, x, TLS_FP64, W, st));
+  return TLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P, const tls_rqi_opts *o) {
+  if (check_matrix(A) != TLS_OK || !P || !o) return 0;
+  const int kmax = std::max(1, std::min(o->kmax, TLS_MAX_ITERS));
+  const int L = std::max(kmax, o->refine_pcg_steps) + 1;
+  Carver c(nullptr);
+  carve_rqi(c, A->m, A->n, P, kmax, L);
+  return c.size();
+}
+
+tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
+                         double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+  try {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    auto ms_since = [&](clk::time_point a) {
+      return std::chrono::duration<double, std::milli>(clk::now() - a).count();
+    };
+    TRY(check_matrix(A));
+    if (!P || !o || !b || !x) return fail(TLS_ERR_ARG, "NULL argument to tls_rqi_solve");
+    if (P->n != A->n) return fail(TLS_ERR_ARG, "preconditioner order %lld != n %lld", (long long)P->n, (long long)A->n);
+    if (A->format == TLS_CSR && !P->col_ptr) return fail(TLS_ERR_ARG, "CSR A needs a preconditioner built from it (CSC copy)");
+    if (o->u_p != TLS_FP64 && o->u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
+    if (o->kmax < 1 || o->kmax > TLS_MAX_ITERS) return fail(TLS_ERR_ARG, "kmax must be in [1, %d]", TLS_MAX_ITERS);
+    if (o->stop_patience < 1) return fail(TLS_ERR_ARG, "stop_patience must be >= 1");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    const size_t need = tls_rqi_workspace_size(A, P, o);
+    if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "RQI workspace %zu < %zu bytes", ws_bytes, need);
+    const int kmax = o->kmax;
+    const int L = std::max(kmax, o->refine_pcg_steps) + 1;
+    Carver c(ws);
+    RqiWs W = carve_rqi(c, A->m, A->n, P, kmax, L);
+    const int n = (int)A->n;
+    const MatView V = make_view(A, P);
+    const int nb_r = matvec_blocks(V), nb_f = rmatvec_blocks(V);
+    tls_rqi_stats local{};
+    tls_rqi_stats &S = stats ? *stats : local;
+    std::memset(&S, 0, sizeof S);
+
+    HIPCHK(launch_fill_i32(W.pcg.sync, 0, P->N + 8, st));
+    HIPCHK(launch_fill_f64(W.scal, 0.0, 32, st));
+    // finite b
+    HIPCHK(launch_fill_i32(W.pcg.done, 0, 1, st));
+    HIPCHK(launch_check_finite(b, (size_t)A->m, W.pcg.done, st));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
+
+    // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1 --------------------------
+    HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
+    TRY(solve_normal(P, W.t1, x, W.t2, W.pcg, st));               // x = R^{-1} R^{-T} A^T b
+    for (int c2 = 0; c2 < o->ls_corrections; ++c2) {               // corrected semi-normal equations
+      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+      HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
+      TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
+      HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
+    }
+    HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
+    HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2 (cap 0: none)
+    {
+      double h[2];
+      HIPCHK(hipMemcpyAsync(h, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      S.sigma_ls = std::sqrt(h[0]);
+    }
+    TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
+    HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));           // x_1 = x_0 + sigma_0^2 u_0
+
+    // shift cap for the clamp (a deviation for starts above sigma'_n)
+    double cap = 0.0;
+    if (o->shift_clamp && !P->have_sigma_n) {
+      FactorWs FW = factor_ws_of(P);
+      TRY(estimate_sigma_n(P, FW, st));
+    }
+    if (o->shift_clamp && std::isfinite(P->rep.sigma_n_est) && P->rep.sigma_n_est > 0)
+      cap = o->shift_clamp_tau * P->rep.sigma_n_est * P->rep.sigma_n_est;
+    HIPCHK(launch_fill_f64(W.scal + 14, cap, 1, st));
+
+    // ---- main loop -----------------------------------------------------------
+    double best = std::numeric_limits<double>::infinity();
+    int no_improve = 0, k = 0;
+    S.stopped = 1;
+    double h[16];
+    for (k = 1; k <= kmax; ++k) {
+      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+      HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, cap, st));
+      HIPCHK(launch_gradient(V, W.r, x, W.scal, W.f, W.part, st));
+      HIPCHK(launch_outer_psi(n, x, W.f, W.part, nb_f, W.scal, k, W.rec, st));
+      if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
+      HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const double psi = h[7], sig2 = h[0];
+      S.iters = k;
+      S.psi[k - 1] = psi;
+      S.sigma[k - 1] = std::sqrt(sig2);
+      S.t_ms[k - 1] = ms_since(t0);
+      if (h[1] != h[0]) S.clamped++;
+      if (!std::isfinite(psi)) return fail(TLS_ERR_NO_CONVERGENCE, "psi became non-finite at k = %d", k);
+      if (psi < best) {
+        best = psi;
+        S.k_best = k;
+        no_improve = 0;
+        HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
+      } else if (o->stop_ge ? (psi >= best) : (psi > best)) {
+        ++no_improve;
+      }
+      if (psi == 0.0) { S.stopped = 2; break; }
+      if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
+      if (k == kmax) break;
+      // lines: two PCGTLS solves with l = k (k+1 steps), sharing sigma_k^2
+      HIPCHK(launch_make_rhs(n, W.f, x, W.rhs, st));
+      TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, k, o->u_p, o->strict_pd, W.pcg, st));
+      S.pcg_steps += k + 1;
+      HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+    }
+    {
+      int neg[1] = {0};
+      (void)neg;
+    }
+    // the returned iterate
+    HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
+    // final sigma from a compensated residual at x
+    HIPCHK(launch_residual_dd(V, b, x, W.part, st));
+    HIPCHK(launch_sigma_dd(n, x, W.part, nb_r, W.scal + 20, st));
+    double sg[2];
+    HIPCHK(hipMemcpyAsync(sg, W.scal + 20, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    TRY(sync_status(W.pcg.sync, P->N, st));
+    S.sigma_final = sg[1];
+    if (sigma) *sigma = sg[1];
+    S.t_total_ms = ms_since(t0);
+    if (S.stopped == 1)
+      return fail(TLS_ERR_NO_CONVERGENCE, "kmax = %d reached before the psi rule fired", kmax);
+    return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
+}  // extern "C"

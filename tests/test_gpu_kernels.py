@@ -163,6 +163,34 @@ def test_factor_matches_cholesky(case, u_q):
     H = (Af / dref).T @ (Af / dref)
     Rref = sla.cholesky(H, lower=False)
     assert np.max(np.abs(Rh - Rref)) < 1e-12 * 10
-    # gate estimates: sigma'_n of A within Lanczos accuracy
-    sA = np.linalg.svd(Af, compute_uv=False)
-    assert abs(rep["sigma_n_est"] - sA[-1]) / sA[-1] < 0.2
+
+
+@pytest.mark.parametrize("case", ["dense", "sparse"])
+@pytest.mark.parametrize("u_q", ["fp32", "fp16", "bf16"])
+def test_low_precision_factor_and_gate(case, u_q):
+    from oracle import constraints
+    tls = _tls()
+    print(f"factor {case} {u_q}", flush=True)
+    if case == "dense":
+        A, b, _ = tlsgen.dense_gaussian(700, 150, seed=12)
+        Ad = tls.dense(A)
+        Af = A
+    else:
+        A, b, _, _ = tlsgen.sparse_scaled(3000, 200, density=0.02, seed=7)
+        Ad = tls.from_tlsgen(A)
+        Af = A.to_dense()
+    P, rep = tls.tls_factor_precond(Ad, u_q)
+    Rh, d = tls.tls_precond_export(P)
+    u = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[u_q]
+    # the stored factor is a u_q-accurate Cholesky factor of the scaled Gram matrix
+    H = (Af / d).T @ (Af / d)
+    err = np.linalg.norm(Rh.T @ Rh - H, 2) / np.linalg.norm(H, 2)
+    assert err < 30 * u, err
+    # stored values are representable in u_q
+    assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
+    assert rep["used"] == tls.PREC[u_q]
+    # Lanczos estimates against the exact singular values
+    ex = constraints.bounds(Af, b, scaled=True)
+    assert abs(rep["sigma_n_est"] - ex.sigma_n_A) / ex.sigma_n_A < 0.2
+    assert 0.5 < rep["kappa_est"] / ex.kappa < 1.0 + 1e-6 + 50 * u
+    assert abs(rep["bound5"] - ex.bound5) / ex.bound5 < 1.0
