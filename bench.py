@@ -1,0 +1,239 @@
+"""Benchmark: time to sigma_min / x_TLS at 1e-10 relative error on MI355X,
+mixed-precision path vs the plain FP64 GPU path, with the roofline of the
+dominant kernel and the CPU oracle timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Workload: sparse CSR A 20000 x 2000 with 0.5% nonzeros at uniformly random
+positions, N(0,1) values times log-uniform column scales in [1, 1e4],
+b = A x_true + 1e-4 N(0,1) (seed 2000), resident on the device.
+
+One step = one whole solve: tls_factor_precond (CSC copy, scaling, Gram,
+Cholesky, packing, gate) + tls_rqi_solve (x_LS, initial inverse step, the
+RQI loop with two PCGTLS solves per iteration, final compensated sigma).
+  plain FP64 path : u_q = FP64 factor, u_p = FP64 PCGTLS
+  mixed path      : u_q = FP16 factor (scaled), u_p = FP32 PCGTLS, FP64 outer
+Both use the same stopping rule (psi, patience 2). Errors are checked
+against the stored oracle reference (tests/golden/sparse_c2_ref.json).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "sparse_c2"
+TOL = 1e-10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="a few solves of each path, no CPU leg (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+def load_ref():
+    with open(os.path.join(ROOT, "tests", "golden", f"{WORKLOAD}_ref.json")) as f:
+        ref = json.load(f)
+    return np.array(ref["x"]), float(ref["sigma"])
+
+
+def make_problem():
+    import tlsgen
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    return A, b
+
+
+PATHS = {
+    "fp64": dict(u_q="fp64", u_p="fp64"),
+    "mixed": dict(u_q="fp16", u_p="fp32"),
+}
+
+
+def one_solve(tls, torch, Ad, bd, path, snaps=None):
+    cfg = PATHS[path]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P, rep = tls.tls_factor_precond(Ad, cfg["u_q"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    opts = tls.default_opts(u_p=cfg["u_p"], stop_patience=2, kmax=40, x_snapshots=snaps)
+    x, sigma, st = tls.tls_rqi_solve(Ad, bd, P, opts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return P, x, sigma, st, (t1 - t0) * 1e3, (t2 - t1) * 1e3, rep
+
+
+def rel_errs(x, sigma, xref, sref):
+    return abs(sigma - sref) / sref, float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
+
+
+def run_path(tls, torch, Ad, bd, path, steps, warmup, xref, sref):
+    n = Ad.n
+    snaps = torch.zeros((40, n), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        one_solve(tls, torch, Ad, bd, path)
+    totals, ttts, factors = [], [], []
+    last = None
+    for _ in range(steps):
+        P, x, sigma, st, tf, ts, rep = one_solve(tls, torch, Ad, bd, path, snaps)
+        totals.append(tf + ts)
+        factors.append(tf)
+        # first iterate whose x is within TOL (sigma at such an x is accurate to
+        # second order; the final sigma is checked separately)
+        xs = snaps[: st["iters"]].cpu().numpy()
+        kstar = None
+        for k in range(st["iters"]):
+            if np.linalg.norm(xs[k] - xref) / np.linalg.norm(xref) <= TOL:
+                kstar = k
+                break
+        ttts.append(tf + st["t_ms"][kstar] if kstar is not None else float("nan"))
+        last = (x.cpu().numpy(), sigma, st, rep)
+    x, sigma, st, rep = last
+    es, ex = rel_errs(x, sigma, xref, sref)
+    return {
+        "ms_median": statistics.median(totals), "ms_min": min(totals),
+        "time_to_tol_ms": statistics.median(ttts) if all(math.isfinite(t) for t in ttts) else None,
+        "factor_ms": statistics.median(factors),
+        "rqi_iters": st["iters"], "pcg_steps": st["pcg_steps"], "k_best": st["k_best"],
+        "err_sigma": es, "err_x": ex, "gate_verdict": rep["verdict"],
+        "kappa_est": rep["kappa_est"],
+    }
+
+
+def kernel_profile(tls, torch, Ad, bd, path, reps=3):
+    """Per-kernel-class launch counts and average durations (HIP events on the
+    launch stream), over `reps` full solves."""
+    tls.tls_profile_start()
+    for _ in range(reps):
+        one_solve(tls, torch, Ad, bd, path)
+    prof = tls.tls_profile_stop()
+    return {k: {"launches": v[0] // reps, "ms_per_solve": v[1] / reps,
+                "avg_us": (v[1] / v[0] * 1e3) if v[0] else 0.0} for k, v in prof.items() if v[0]}
+
+
+def trsv_bytes(n, storage_bytes, nrhs=2, compute_bytes=4):
+    """Algorithmic bytes of one triangular solve with R (Table 1: n^2 flops
+    per substitution): the n(n+1)/2 stored entries of the triangle, plus the
+    right-hand sides read and solutions written."""
+    return n * (n + 1) // 2 * storage_bytes + 2 * nrhs * n * compute_bytes
+
+
+def cpu_baseline(A, b, seconds):
+    """The oracle's plain FP64 RQI-PCGTLS (NumPy/SciPy, multithreaded BLAS) on
+    the same workload, repeated for about `seconds` of wall time."""
+    from oracle import rqi
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    times = []
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end or len(times) < 2:
+        t0 = time.perf_counter()
+        rqi.rqi_pcgtls(A, b, patience=2)
+        times.append((time.perf_counter() - t0) * 1e3)
+        if len(times) >= 200:
+            break
+    return {"value": statistics.median(times), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{len(times)} full solves of the sparse 20000x2000 workload "
+                      f"(oracle.rqi.rqi_pcgtls: scipy Gram, LAPACK Cholesky, Algorithms 2+3 "
+                      f"in float64); median"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not "
+                                   "part of it (see the sharding design notes)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2305_19028_amd import tls
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    A, b = make_problem()
+    xref, sref = load_ref()
+    Ad = tls.from_tlsgen(A)
+    bd = tls.device_vector(b)
+
+    if args.profile_only:
+        for path in ("fp64", "mixed"):
+            for _ in range(max(args.steps, 1)):
+                one_solve(tls, torch, Ad, bd, path)
+            torch.cuda.synchronize()
+            print(f"profiled {path}", flush=True)
+        return
+
+    print(f"# warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    res = {}
+    for path in ("fp64", "mixed"):
+        res[path] = run_path(tls, torch, Ad, bd, path, args.steps, args.warmup, xref, sref)
+        print(f"# {path}: {res[path]}", file=sys.stderr, flush=True)
+    prof = {p: kernel_profile(tls, torch, Ad, bd, p) for p in ("fp64", "mixed")}
+    print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)
+
+    # dominant kernel class of the mixed path
+    pm = prof["mixed"]
+    dom = max(pm, key=lambda k: pm[k]["ms_per_solve"])
+    n = A.n
+    roof = None
+    if dom == "pcg_trsv":
+        per_launch = trsv_bytes(n, 2, nrhs=2, compute_bytes=4)
+        achieved = per_launch / (pm[dom]["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_trsv (PCGTLS step, FP16 factor, FP32, 2 RHS)",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": per_launch, "avg_us": pm[dom]["avg_us"]}
+    else:
+        roof = {"bound": "latency", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "avg_us": pm[dom]["avg_us"]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(A, b, args.cpu_seconds)
+
+    mixed = res["mixed"]
+    line = {
+        "metric": "time to sigma_min/x_TLS at 1e-10 rel err, mixed vs FP64 GPU path; % roofline",
+        "value": mixed["ms_median"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_median"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 factor / f32 PCG / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": "sparse CSR 20000x2000, 0.5% nnz, column scales logU[1,1e4], "
+                               "b noise 1e-4, seed 2000",
+                   "paths": {"mixed": PATHS["mixed"], "fp64": PATHS["fp64"]}},
+        "fp64_path_ms": res["fp64"]["ms_median"],
+        "speedup_vs_fp64": res["fp64"]["ms_median"] / mixed["ms_median"],
+        "time_to_tol_ms": {"mixed": mixed["time_to_tol_ms"], "fp64": res["fp64"]["time_to_tol_ms"]},
+        "errors": {p: {"sigma": res[p]["err_sigma"], "x": res[p]["err_x"]} for p in res},
+        "rqi_iters": {p: res[p]["rqi_iters"] for p in res},
+        "roofline": roof,
+        "kernel_classes": prof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

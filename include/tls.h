@@ -195,6 +195,14 @@ TLS_API void tls_precond_destroy(tls_precond P);
 TLS_API tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage,
                             tls_gate_report *rep);
 
+/* How R^{-1} and R^{-T} are applied inside PCGTLS, the gate and x_LS:
+ *   0 (default) GEMV with the explicit inverse X = R_hat^{-1}, formed once
+ *     per factorization by recursive block inversion (stored in FP64 for an
+ *     FP64 factor, FP32 otherwise);
+ *   1 blocked forward/backward substitution with the stored tiles of R_hat
+ *     (Table 1), one workgroup per 64-row block, inter-workgroup flags. */
+TLS_API tls_status tls_precond_set_apply(tls_precond P, int32_t mode);
+
 /* Copy R_hat (upper, column-major n x n, FP64) and d to host buffers. */
 TLS_API tls_status tls_precond_export(const tls_precond P, double *R_host, double *d_host,
                               hipStream_t stream);
@@ -251,6 +259,23 @@ TLS_API tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_preco
  * (Section 3.1). count elements, device arrays. */
 TLS_API tls_status tls_round(const double *in, int64_t count, int32_t prec, double *out,
                              hipStream_t stream);
+
+/* Kernel-class timing. While profiling is on, the library records a pair of
+ * HIP events on the caller's stream around every kernel it launches and
+ * accumulates the elapsed time per kernel class. Process-wide state, not
+ * thread-safe; meant for benchmarks. Classes (index: name):
+ *   0 precond_apply  1 pcg_step  2 gram  3 chol_panel  4 chol_update
+ *   5 residual  6 gradient  7 outer_scalars  8 setup  9 lanczos
+ *   10 pack  11 residual_dd  12 invert */
+#define TLS_PROF_CLASSES 13
+typedef struct {
+  int32_t launches[TLS_PROF_CLASSES];
+  double total_ms[TLS_PROF_CLASSES];
+} tls_kernel_times;
+
+TLS_API tls_status tls_profile_start(void);
+/* Synchronizes the recorded events, fills *out (host) and stops profiling. */
+TLS_API tls_status tls_profile_stop(tls_kernel_times *out);
 
 /* Thread-local description of the last error (never NULL). */
 TLS_API const char *tls_last_error(void);

@@ -10,6 +10,21 @@
 
 namespace tls {
 
+// kernel classes of the profiling hooks (order as in tls.h)
+enum ProfClass { PC_TRSV_APPLY = 0, PC_PCG, PC_GRAM, PC_CHOL_PANEL, PC_CHOL_UPDATE, PC_RESIDUAL,
+                 PC_GRADIENT, PC_SCALARS, PC_SETUP, PC_LANCZOS, PC_PACK, PC_RESID_DD, PC_INVERT };
+// no-ops unless profiling is on (see tls_profile_start)
+void prof_begin(int cls, hipStream_t st);
+void prof_end(hipStream_t st);
+
+// a kernel launch on stream `st`, bracketed by the profiling hooks; one statement
+#define TLS_LAUNCH(cls, ...)          \
+  do {                                \
+    ::tls::prof_begin((cls), st);     \
+    hipLaunchKernelGGL(__VA_ARGS__);  \
+    ::tls::prof_end(st);              \
+  } while (0)
+
 // view of a packed factor (device pointers)
 struct FactorView {
   int n, N, Np, storage;
@@ -18,6 +33,9 @@ struct FactorView {
   const float *dinv32;
   const double *dscale64;   // 1/d, length Np (ones beyond n)
   const float *dscale32;
+  // explicit inverse X = R_hat^{-1} (row-packed tiles of X and of X^T)
+  const void *xr, *xc;
+  int xstorage;
 };
 
 // buffers of one triangular-solve / PCGTLS launch
@@ -31,11 +49,22 @@ struct SolveBufs {
   double *trace;
   const double *sigma2;
   int j, L, strict;
+  int ldi = 0, ldo = 0;   // stride between right-hand sides of in/out (0: n)
+  void *cpart;   // chunk partials of the inverse-apply kernels
+  int *cnt;      // per-block arrival counters (zero between launches)
 };
 
 // ---- kernels_trsv.hip ------------------------------------------------------
 hipError_t launch_trsv(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
                        hipStream_t st);
+// ---- kernels_inv.hip --------------------------------------------------------
+hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, double *W,
+                         double *Y, int xstorage, void *XR, void *XC, hipStream_t st);
+size_t invert_scratch_doubles(int N);
+hipError_t launch_xapply(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
+                         hipStream_t st);
+size_t xapply_chunk_count(int N);
+
 hipError_t launch_pcg_finish(int compute, const void *w, double *out, int n, int Np, int nrhs,
                              hipStream_t st);
 
@@ -118,7 +147,8 @@ hipError_t launch_axpy_init(int n, double *x, const double *u, const double *sca
                             hipStream_t st);
 hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);
 hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t st);
-hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, double *ab, hipStream_t st);
+hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const double *Wout,
+                               double *nxt, const double *dsc, double *ab, hipStream_t st);
 hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
                            hipStream_t st);
 

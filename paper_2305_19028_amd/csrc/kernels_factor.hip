@@ -31,12 +31,12 @@ static int grid_for(size_t count) {
 }
 hipError_t launch_fill_i32(int *p, int v, size_t count, hipStream_t st) {
   if (!count) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  TLS_LAUNCH(PC_SETUP, k_fill_i32, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
   return hipGetLastError();
 }
 hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st) {
   if (!count) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
+  TLS_LAUNCH(PC_SETUP, k_fill_f64, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
   return hipGetLastError();
 }
 
@@ -51,17 +51,16 @@ __global__ void k_check_finite(const double *v, size_t count, int *flag) {
 }
 hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st) {
   if (!count) return hipSuccess;
-  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(count)), dim3(256), 0, st, v, count, flag);
+  TLS_LAUNCH(PC_SETUP, k_check_finite, dim3(grid_for(count)), dim3(256), 0, st, v, count, flag);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
 // CSC copy of a CSR matrix, rows ascending inside each column
 // --------------------------------------------------------------------------
-__global__ void k_csc_count(int m, const int32_t *row_ptr, const int32_t *col_idx, int32_t *cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) atomicAdd(&cnt[col_idx[e]], 1);
+__global__ void k_csc_count(int64_t nnz, const int32_t *col_idx, int32_t *cnt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[col_idx[e]], 1);
 }
 
 // exclusive scan of cnt[0..n) into col_ptr[0..n], one workgroup
@@ -84,17 +83,21 @@ __global__ void k_scan(int n, const int32_t *cnt, int32_t *col_ptr) {
   for (int i = a; i < b; ++i) { col_ptr[i] = run; run += cnt[i]; }
 }
 
-__global__ void k_csc_scatter(int m, const int32_t *row_ptr, const int32_t *col_idx,
+// one thread per nonzero; its row by binary search in row_ptr
+__global__ void k_csc_scatter(int m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                               const double *val, const int32_t *col_ptr, int32_t *fill,
                               int32_t *tmp_row, double *tmp_val) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-    const int c = col_idx[e];
-    const int pos = col_ptr[c] + atomicAdd(&fill[c], 1);
-    tmp_row[pos] = i;
-    tmp_val[pos] = val[e];
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int lo = 0, hi = m;            // row_ptr[lo] <= e < row_ptr[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (row_ptr[mid] <= e) lo = mid; else hi = mid;
   }
+  const int c = col_idx[e];
+  const int pos = col_ptr[c] + atomicAdd(&fill[c], 1);
+  tmp_row[pos] = lo;
+  tmp_val[pos] = val[e];
 }
 
 // one thread per CSC slot: its final position is the number of entries of
@@ -123,14 +126,15 @@ hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
                             int32_t *fill, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_i32(fill, 0, n, st)) != hipSuccess) return e;
-  const int gm = (m + 255) / 256;
-  hipLaunchKernelGGL(k_csc_count, dim3(gm), dim3(256), 0, st, m, row_ptr, col_idx, fill);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, st, n, fill, col_ptr);
+  const unsigned ge = (unsigned)((nnz + 255) / 256);
+  if (nnz > 0) TLS_LAUNCH(PC_SETUP, k_csc_count, dim3(ge), dim3(256), 0, st, nnz, col_idx, fill);
+  TLS_LAUNCH(PC_SETUP, k_scan, dim3(1), dim3(256), 0, st, n, fill, col_ptr);
   if ((e = launch_fill_i32(fill, 0, n, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_csc_scatter, dim3(gm), dim3(256), 0, st, m, row_ptr, col_idx, val, col_ptr,
-                     fill, tmp_row, tmp_val);
   if (nnz > 0)
-    hipLaunchKernelGGL(k_csc_rank, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, n,
+    TLS_LAUNCH(PC_SETUP, k_csc_scatter, dim3(ge), dim3(256), 0, st, m, nnz, row_ptr, col_idx, val,
+               col_ptr, fill, tmp_row, tmp_val);
+  if (nnz > 0)
+    TLS_LAUNCH(PC_SETUP, k_csc_rank, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, n,
                        col_ptr, tmp_row, tmp_val, row_idx, cval);
   return hipGetLastError();
 }
@@ -159,12 +163,12 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
 }
 hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_colnorms_csc, dim3((n + 3) / 4), dim3(256), 0, st, n, col_ptr, cval, d);
+  TLS_LAUNCH(PC_SETUP, k_colnorms_csc, dim3((n + 3) / 4), dim3(256), 0, st, n, col_ptr, cval, d);
   return hipGetLastError();
 }
 hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_colnorms_dense, dim3((n + 3) / 4), dim3(256), 0, st, m, n, ld, A, d);
+  TLS_LAUNCH(PC_SETUP, k_colnorms_dense, dim3((n + 3) / 4), dim3(256), 0, st, m, n, ld, A, d);
   return hipGetLastError();
 }
 
@@ -178,7 +182,7 @@ __global__ void k_scale_vectors(int n, int Np, const double *d, int scaled, doub
 }
 hipError_t launch_scale_vectors(int n, int Np, const double *d, int scaled, double *dsc64,
                                 float *dsc32, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_vectors, dim3((Np + 255) / 256), dim3(256), 0, st, n, Np, d, scaled,
+  TLS_LAUNCH(PC_SETUP, k_scale_vectors, dim3((Np + 255) / 256), dim3(256), 0, st, n, Np, d, scaled,
                      dsc64, dsc32);
   return hipGetLastError();
 }
@@ -199,7 +203,7 @@ __global__ void k_round(const double *in, int64_t count, int q, double *out) {
 }
 hipError_t launch_round(const double *in, int64_t count, int q, double *out, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_round, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, count, q, out);
+  TLS_LAUNCH(PC_SETUP, k_round, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, in, count, q, out);
   return hipGetLastError();
 }
 
@@ -217,10 +221,10 @@ hipError_t launch_quantize_sparse(int64_t nnz, const int32_t *cols, const double
   if (nnz <= 0) return hipSuccess;
   const dim3 g((unsigned)((nnz + 255) / 256));
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_quantize_sparse<double>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
+    TLS_LAUNCH(PC_SETUP, k_quantize_sparse<double>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
                        (double *)out);
   else
-    hipLaunchKernelGGL(k_quantize_sparse<float>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
+    TLS_LAUNCH(PC_SETUP, k_quantize_sparse<float>, g, dim3(256), 0, st, nnz, cols, val, d, scaled, q,
                        (float *)out);
   return hipGetLastError();
 }
@@ -238,10 +242,10 @@ __global__ void k_quantize_csc(int n, const int32_t *col_ptr, const double *cval
 hipError_t launch_quantize_csc(int n, const int32_t *col_ptr, const double *cval, const double *d,
                                int scaled, int q, int compute, void *out, hipStream_t st) {
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_quantize_csc<double>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
+    TLS_LAUNCH(PC_SETUP, k_quantize_csc<double>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
                        q, (double *)out);
   else
-    hipLaunchKernelGGL(k_quantize_csc<float>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
+    TLS_LAUNCH(PC_SETUP, k_quantize_csc<float>, dim3(n), dim3(64), 0, st, n, col_ptr, cval, d, scaled,
                        q, (float *)out);
   return hipGetLastError();
 }
@@ -295,10 +299,10 @@ hipError_t launch_gram_sparse(int m, int n, int Np, const int32_t *row_ptr, cons
                               const void *cvalq, int compute, void *G, hipStream_t st) {
   const dim3 g((n + 3) / 4);
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_gram_sparse<double>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
+    TLS_LAUNCH(PC_GRAM, k_gram_sparse<double>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
                        (const double *)valq, col_ptr, row_idx, (const double *)cvalq, (double *)G);
   else
-    hipLaunchKernelGGL(k_gram_sparse<float>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
+    TLS_LAUNCH(PC_GRAM, k_gram_sparse<float>, g, dim3(256), 0, st, n, Np, row_ptr, col_idx,
                        (const float *)valq, col_ptr, row_idx, (const float *)cvalq, (float *)G);
   return hipGetLastError();
 }
@@ -363,10 +367,10 @@ hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, 
   const int N = Np / NB;
   const dim3 g(N * (N + 1) / 2);
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_gram_dense<double>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
+    TLS_LAUNCH(PC_GRAM, k_gram_dense<double>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
                        (double *)G);
   else
-    hipLaunchKernelGGL(k_gram_dense<float>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
+    TLS_LAUNCH(PC_GRAM, k_gram_dense<float>, g, dim3(256), 0, st, m, n, Np, ld, A, d, scaled, q,
                        (float *)G);
   return hipGetLastError();
 }
@@ -380,9 +384,9 @@ __global__ void k_gram_pad(int n, int Np, C *G) {
 hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st) {
   if (Np == n) return hipSuccess;
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_gram_pad<double>, dim3(Np - n), dim3(256), 0, st, n, Np, (double *)G);
+    TLS_LAUNCH(PC_GRAM, k_gram_pad<double>, dim3(Np - n), dim3(256), 0, st, n, Np, (double *)G);
   else
-    hipLaunchKernelGGL(k_gram_pad<float>, dim3(Np - n), dim3(256), 0, st, n, Np, (float *)G);
+    TLS_LAUNCH(PC_GRAM, k_gram_pad<float>, dim3(Np - n), dim3(256), 0, st, n, Np, (float *)G);
   return hipGetLastError();
 }
 
@@ -394,9 +398,9 @@ __global__ void k_gram_shift(int n, int Np, C *G, double shift) {
 hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st) {
   const dim3 g((n + 255) / 256);
   if (compute == TLS_FP64)
-    hipLaunchKernelGGL(k_gram_shift<double>, g, dim3(256), 0, st, n, Np, (double *)G, shift);
+    TLS_LAUNCH(PC_GRAM, k_gram_shift<double>, g, dim3(256), 0, st, n, Np, (double *)G, shift);
   else
-    hipLaunchKernelGGL(k_gram_shift<float>, g, dim3(256), 0, st, n, Np, (float *)G, shift);
+    TLS_LAUNCH(PC_GRAM, k_gram_shift<float>, g, dim3(256), 0, st, n, Np, (float *)G, shift);
   return hipGetLastError();
 }
 
@@ -404,116 +408,132 @@ hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, 
 // blocked right-looking Cholesky, upper: G = R^T R, 64x64 tiles
 // --------------------------------------------------------------------------
 
-// factor a 64x64 SPD tile held in LDS (row stride NB+1) into R (upper) and
-// its inverse X = R^{-1} (upper); returns nonzero on a non-positive pivot.
-// Elimination keeps rows unscaled (G(i,j) -= G(c,i) G(c,j) / G(c,c)) and
-// scales row c by 1/sqrt(pivot) at the end, one barrier per column.
-template <typename C>
-__device__ int tile_potrf_inv(C (*T)[NB + 1], C (*X)[NB + 1]) {
-  const int tid = threadIdx.x;
-  __shared__ int s_bad;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int c = 0; c < NB; ++c) {
-    const C piv = T[c][c];
-    if (!(piv > (C)0)) {
-      if (tid == 0) s_bad = c + 1;
-      break;
-    }
-    const int M = NB - 1 - c;                 // trailing order
-    const int cnt = M * (M + 1) / 2;
-    const C ip = (C)1 / piv;
-    for (int t = tid; t < cnt; t += blockDim.x) {
-      // decode (a, b) with a <= b in the trailing triangle, row-major
-      int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while ((b + 1) * (b + 2) / 2 <= t) ++b;
-      while (b * (b + 1) / 2 > t) --b;
-      const int a = t - b * (b + 1) / 2;
-      const int i = c + 1 + a, j = c + 1 + b;
-      T[i][j] -= T[c][i] * T[c][j] * ip;
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  const int bad = s_bad;
-  if (bad) return bad;
-  // row scaling: R(c, j) = G(c, j) / sqrt(G(c, c))
-  for (int t = tid; t < NB * NB; t += blockDim.x) {
-    const int c = t / NB, j = t % NB;
-    if (j > c) T[c][j] = T[c][j] / sqrt(T[c][c]);
-  }
-  __syncthreads();
-  for (int c = tid; c < NB; c += blockDim.x) T[c][c] = sqrt(T[c][c]);
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += blockDim.x) {
-    const int r = t / NB, c = t % NB;
-    if (r > c) T[r][c] = 0;
-  }
-  __syncthreads();
-  // inverse, column t by back substitution (thread t)
-  if (tid < NB) {
-    const int t = tid;
-    for (int i = NB - 1; i > t; --i) X[i][t] = 0;
-    X[t][t] = (C)1 / T[t][t];
-    for (int i = t - 1; i >= 0; --i) {
-      C s = 0;
-      for (int l = i + 1; l <= t; ++l) s += T[i][l] * X[l][t];
-      X[i][t] = -s / T[i][i];
-    }
-  }
-  __syncthreads();
-  return 0;
-}
-
-// panel k: every workgroup factors the diagonal tile; workgroup 0 writes it,
-// workgroup j > 0 writes R(k, k+j) = R_kk^{-T} G(k, k+j)
+// Panel k of the blocked Cholesky. Every workgroup factors the diagonal tile
+// G(k, k) = R_kk^T R_kk itself (so no workgroup waits for another):
+// 256 threads hold 4x4 register blocks of the tile; step c publishes the
+// current row c through a double-buffered LDS row and eliminates with
+// G(r, c') -= G(c, r) G(c, c') / G(c, c) (rows kept unscaled, one barrier per
+// step); rows are scaled by 1/sqrt(pivot) at the end. Workgroup 0 writes
+// R_kk; workgroup j > 0 then solves R_kk^T Y = G(k, k+j) by forward
+// substitution in the same layout and writes Y = R(k, k+j).
+// (Measured alternatives: one wave with the tile in registers and fully
+// unrolled updates is instruction-fetch bound; one wave with the tile in
+// LDS is bound by the latency of its read-modify-write chain. The barrier
+// per step of this version costs about 160 ns.)
 template <typename C>
 __global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *info) {
   __shared__ C T[NB][NB + 1];
-  __shared__ C X[NB][NB + 1];
-  __shared__ C B[NB][NB + 1];
-  const int tid = threadIdx.x;
+  __shared__ C rowbuf[2][NB];
+  __shared__ C piv[NB];
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
   const size_t base = (size_t)k * NB;
-  for (int t = tid; t < NB * NB; t += blockDim.x) {
-    const int r = t % NB, c = t / NB;
-    T[r][c] = (r <= c) ? G[(base + c) * Np + base + r] : (C)0;
-  }
-  __syncthreads();
-  const int bad = tile_potrf_inv(T, X);
-  if (bad) {
-    if (tid == 0 && blockIdx.x == 0) atomicMin(info, k * NB + bad);
-    return;
-  }
-  const int jb = k + blockIdx.x;
-  if (blockIdx.x == 0) {
-    for (int t = tid; t < NB * NB; t += blockDim.x) {
-      const int r = t % NB, c = t / NB;
-      if (r <= c) G[(base + c) * Np + base + r] = T[r][c];
-    }
-    return;
-  }
-  const size_t cb = (size_t)jb * NB;
-  for (int t = tid; t < NB * NB; t += blockDim.x) {
-    const int r = t % NB, c = t / NB;
-    B[r][c] = G[(cb + c) * Np + base + r];
-  }
-  __syncthreads();
-  // R_kj(r, c) = sum_{t <= r} X(t, r) B(t, c)
-  const int tr = tid & 15, tc = tid >> 4;
-  C acc[4][4] = {};
-  for (int t = 0; t < NB; ++t) {
-    C a[4], b[4];
+  C v[4][4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) { a[x] = X[t][tr * 4 + x]; b[x] = B[t][tc * 4 + x]; }
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = 4 * tr + x, c = 4 * tc + y;
+      v[x][y] = (r <= c) ? G[(base + c) * Np + base + r] : (C)0;
+    }
+  int bad = 0;
+  for (int c = 0; c < NB; ++c) {
+    const int buf = c & 1;
+    if (tr == (c >> 2)) {
+      const int x = c & 3;
+#pragma unroll
+      for (int xx = 0; xx < 4; ++xx)
+        if (xx == x) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) rowbuf[buf][4 * tc + y] = v[xx][y];
+        }
+    }
+    __syncthreads();
+    const C p = rowbuf[buf][c];
+    if (!(p > (C)0)) { bad = c + 1; break; }
+    if (tid == 0) piv[c] = p;
+    const C ip = (C)1 / p;
+    C rr[4], rc[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) { rr[x] = rowbuf[buf][4 * tr + x]; rc[x] = rowbuf[buf][4 * tc + x]; }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+      for (int y = 0; y < 4; ++y) {
+        const int r = 4 * tr + x, cc = 4 * tc + y;
+        if (r > c && cc >= r) v[x][y] -= rr[x] * rc[y] * ip;
+      }
+  }
+  if (bad) {
+    if (tid == 0 && blockIdx.x == 0) atomicMin(info, k * NB + bad);
+    return;   // uniform: every thread read the same pivot
+  }
+  __syncthreads();
+  // R(r, c') = G(r, c') / sqrt(piv_r), R(r, r) = sqrt(piv_r)
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int r = 4 * tr + x;
+    const C sr = sqrt(piv[r]);
+    const C isr = (C)1 / sr;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int c = 4 * tc + y;
+      const C val = (c > r) ? v[x][y] * isr : (c == r ? sr : (C)0);
+      v[x][y] = val;
+      T[r][c] = val;
+    }
+  }
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int r = 4 * tr + x, c = 4 * tc + y;
+        if (r <= c) G[(base + c) * Np + base + r] = v[x][y];
+      }
+    return;
+  }
+  __syncthreads();
+  // forward substitution R_kk^T Y = B, B = G(k, jb) (rows of block k, columns of block jb)
+  const size_t cb = (size_t)(k + blockIdx.x) * NB;
+  C b[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) b[x][y] = G[(cb + 4 * tc + y) * Np + base + 4 * tr + x];
+  for (int i = 0; i < NB; ++i) {
+    const int buf = i & 1;
+    if (tr == (i >> 2)) {
+      const int x = i & 3;
+      const C id = (C)1 / T[i][i];
+#pragma unroll
+      for (int xx = 0; xx < 4; ++xx)
+        if (xx == x) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            b[xx][y] *= id;                      // Y(i, c') final
+            rowbuf[buf][4 * tc + y] = b[xx][y];
+          }
+        }
+    }
+    __syncthreads();
+    C yr[4], rt[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) yr[y] = rowbuf[buf][4 * tc + y];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) rt[x] = T[i][4 * tr + x];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int r = 4 * tr + x;
+      if (r > i) {
+#pragma unroll
+        for (int y = 0; y < 4; ++y) b[x][y] -= rt[x] * yr[y];
+      }
+    }
   }
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) G[(cb + tc * 4 + y) * Np + base + tr * 4 + x] = acc[x][y];
+    for (int y = 0; y < 4; ++y) G[(cb + 4 * tc + y) * Np + base + 4 * tr + x] = b[x][y];
 }
 
 // trailing update G(i, j) -= R(k, i)^T R(k, j) for k < i <= j
@@ -558,9 +578,10 @@ __global__ __launch_bounds__(256) void k_chol_update(int k, int N, int Np, C *G)
 template <typename C>
 static hipError_t cholesky_t(int N, int Np, C *G, int *info, hipStream_t st) {
   for (int k = 0; k < N; ++k) {
-    hipLaunchKernelGGL(k_chol_panel<C>, dim3(N - k), dim3(256), 0, st, k, Np, G, info);
+    TLS_LAUNCH(PC_CHOL_PANEL, k_chol_panel<C>, dim3(N - k), dim3(256), 0, st, k, Np, G, info);
     const int M = N - k - 1;
-    if (M > 0) hipLaunchKernelGGL(k_chol_update<C>, dim3(M * (M + 1) / 2), dim3(256), 0, st, k, N, Np, G);
+    if (M > 0)
+      TLS_LAUNCH(PC_CHOL_UPDATE, k_chol_update<C>, dim3(M * (M + 1) / 2), dim3(256), 0, st, k, N, Np, G);
   }
   return hipGetLastError();
 }
@@ -591,10 +612,10 @@ template <typename C>
 static hipError_t pack_c(int N, int Np, const C *G, int storage, void *tiles, hipStream_t st) {
   const dim3 g(N * (N + 1) / 2);
   switch (storage) {
-    case TLS_FP64: hipLaunchKernelGGL((k_pack<C, double>), g, dim3(256), 0, st, N, Np, G, (double *)tiles); break;
-    case TLS_FP32: hipLaunchKernelGGL((k_pack<C, float>), g, dim3(256), 0, st, N, Np, G, (float *)tiles); break;
-    case TLS_FP16: hipLaunchKernelGGL((k_pack<C, half_t>), g, dim3(256), 0, st, N, Np, G, (half_t *)tiles); break;
-    default: hipLaunchKernelGGL((k_pack<C, bf16_t>), g, dim3(256), 0, st, N, Np, G, (bf16_t *)tiles); break;
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, (k_pack<C, double>), g, dim3(256), 0, st, N, Np, G, (double *)tiles); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, (k_pack<C, float>), g, dim3(256), 0, st, N, Np, G, (float *)tiles); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, (k_pack<C, half_t>), g, dim3(256), 0, st, N, Np, G, (half_t *)tiles); break;
+    default: TLS_LAUNCH(PC_PACK, (k_pack<C, bf16_t>), g, dim3(256), 0, st, N, Np, G, (bf16_t *)tiles); break;
   }
   return hipGetLastError();
 }
@@ -638,10 +659,10 @@ __global__ __launch_bounds__(256) void k_diag_inverse(const S *tiles, double *di
 hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64, float *dinv32,
                                hipStream_t st) {
   switch (storage) {
-    case TLS_FP64: hipLaunchKernelGGL(k_diag_inverse<double>, dim3(N), dim3(256), 0, st, (const double *)tiles, dinv64, dinv32); break;
-    case TLS_FP32: hipLaunchKernelGGL(k_diag_inverse<float>, dim3(N), dim3(256), 0, st, (const float *)tiles, dinv64, dinv32); break;
-    case TLS_FP16: hipLaunchKernelGGL(k_diag_inverse<half_t>, dim3(N), dim3(256), 0, st, (const half_t *)tiles, dinv64, dinv32); break;
-    default: hipLaunchKernelGGL(k_diag_inverse<bf16_t>, dim3(N), dim3(256), 0, st, (const bf16_t *)tiles, dinv64, dinv32); break;
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, k_diag_inverse<double>, dim3(N), dim3(256), 0, st, (const double *)tiles, dinv64, dinv32); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, k_diag_inverse<float>, dim3(N), dim3(256), 0, st, (const float *)tiles, dinv64, dinv32); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, k_diag_inverse<half_t>, dim3(N), dim3(256), 0, st, (const half_t *)tiles, dinv64, dinv32); break;
+    default: TLS_LAUNCH(PC_PACK, k_diag_inverse<bf16_t>, dim3(N), dim3(256), 0, st, (const bf16_t *)tiles, dinv64, dinv32); break;
   }
   return hipGetLastError();
 }

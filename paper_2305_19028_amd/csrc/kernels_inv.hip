@@ -1,0 +1,524 @@
+// Explicit inverse of the triangular factor and its application.
+//
+// Applying R^{-1} and R^{-T} (the forward/backward substitutions of
+// Table 1) is the inner operation of every PCGTLS step (Algorithm 3). A
+// substitution is a chain of n/64 dependent block steps; on a GPU with
+// eight L2 domains each hop costs microseconds. Since R is fixed for the
+// whole solve (it is computed once, Section 2), X = R_hat^{-1} is formed
+// once here (n^3/3 flops, the cost of the Cholesky factorization itself)
+// and every application becomes a GEMV with the upper triangle of X: fully
+// parallel, bandwidth-bound, deterministic.
+//
+// Inversion: recursive 2x2 block inversion of the upper triangular matrix,
+//   inv([A B; 0 C]) = [inv(A), -inv(A) B inv(C); 0, inv(C)],
+// bottom-up over block sizes 64, 128, 256, ...: level L combines pairs of
+// inverted diagonal blocks of order h = 64*2^(L-1) with two tiled GEMM
+// phases (Y = B inv(C), then X12 = -inv(A) Y), all pairs and output tiles
+// of a level in one launch. Arithmetic in FP64 on the stored R_hat values.
+//
+// Storage of X (precision SX): two packed copies of 64x64 row-major tiles,
+//   XR: tiles (I, K), K >= I, packed by block row   (for X v)
+//   XC: tiles (J, I) of X^T, I <= J, packed by block row of X^T (for X^T v)
+// so that in both products a lane reads one contiguous 64-element row.
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tls {
+
+// packed index helpers (N blocks)
+__host__ __device__ inline size_t up_tile(int I, int J) {   // R tiles: column-packed upper
+  return (size_t)J * (J + 1) / 2 + I;
+}
+__host__ __device__ inline size_t xr_tile(int I, int K, int N) {   // X row-packed upper
+  return (size_t)I * N - (size_t)I * (I - 1) / 2 + (K - I);
+}
+__host__ __device__ inline size_t xc_tile(int J, int I) {    // X^T row-packed lower
+  return (size_t)J * (J + 1) / 2 + I;
+}
+
+// ---------------------------------------------------------------------------
+// inversion, FP64 working copy W: full upper tiles in column-packed order
+// (tile (I, J) at up_tile(I, J)), column-major inside a tile
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_inv_init(int N, const S *Rt, const double *dinv64,
+                                                  double *W) {
+  // diagonal tiles of W = stored diagonal inverses; off-diagonal tiles = R_hat (FP64)
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  double *dst = W + (size_t)l * NB * NB;
+  if (I == J) {
+    const double *src = dinv64 + (size_t)I * NB * NB;
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = src[t];
+  } else {
+    const S *src = Rt + (size_t)l * NB * NB;
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = cvt<double>(src[t]);
+  }
+}
+
+// 64x64x64 FP64 tile product accumulated by 256 threads (4x4 outputs each):
+// acc += A_tile * B_tile, both column-major in global memory
+__device__ inline void tile_mac(const double *A, const double *B, double (*As)[NB + 1],
+                                double (*Bs)[NB + 1], double acc[4][4]) {
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int r = t % NB, c = t / NB;
+    As[r][c] = A[t];
+    Bs[r][c] = B[t];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < NB; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) { a[x] = As[tr * 4 + x][k]; b[x] = Bs[k][tc * 4 + x]; }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+  }
+}
+
+// phase 1 of level L: Y = B inv(C) for every pair p; Y tile (a, b), a, b in [0, hb)
+// B tile (a, k) = W(I0 + a, J0 + k) (still R_hat), inv(C) tile (k, b) = W(J0 + k, J0 + b), k <= b
+__global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, double *Y) {
+  __shared__ double As[NB][NB + 1], Bs[NB][NB + 1];
+  const int per = hb * hb;
+  const int pair = blockIdx.x / per, rem = blockIdx.x % per;
+  const int a = rem % hb, b = rem / hb;
+  const int I0 = pair * 2 * hb, J0 = I0 + hb;
+  if (J0 + b >= N || I0 + a >= N) return;      // partial pair at the end (uniform)
+  double acc[4][4] = {};
+  for (int k = 0; k <= b; ++k) {
+    if (J0 + k >= N) break;
+    tile_mac(W + up_tile(I0 + a, J0 + k) * NB * NB, W + up_tile(J0 + k, J0 + b) * NB * NB, As,
+             Bs, acc);
+  }
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  double *dst = Y + ((size_t)pair * per + rem) * NB * NB;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) dst[(tc * 4 + y) * NB + tr * 4 + x] = acc[x][y];
+}
+
+// phase 2: W(I0 + a, J0 + b) = - sum_{k >= a} inv(A)(a, k) Y(k, b)
+__global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, const double *Y) {
+  __shared__ double As[NB][NB + 1], Bs[NB][NB + 1];
+  const int per = hb * hb;
+  const int pair = blockIdx.x / per, rem = blockIdx.x % per;
+  const int a = rem % hb, b = rem / hb;
+  const int I0 = pair * 2 * hb, J0 = I0 + hb;
+  if (J0 + b >= N || I0 + a >= N) return;
+  double acc[4][4] = {};
+  for (int k = a; k < hb; ++k) {
+    if (I0 + k >= N) break;
+    tile_mac(W + up_tile(I0 + a, I0 + k) * NB * NB, Y + ((size_t)pair * per + b * hb + k) * NB * NB,
+             As, Bs, acc);
+  }
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  double *dst = W + up_tile(I0 + a, J0 + b) * NB * NB;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) dst[(tc * 4 + y) * NB + tr * 4 + x] = -acc[x][y];
+}
+
+// pack W (FP64, column-packed, column-major tiles) into XR and XC of precision SX
+template <typename SX>
+__global__ __launch_bounds__(256) void k_inv_pack(int N, const double *W, SX *XR, SX *XC) {
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  const double *src = W + (size_t)l * NB * NB;
+  SX *xr = XR + xr_tile(I, J, N) * NB * NB;
+  SX *xc = XC + xc_tile(J, I) * NB * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t / NB, c = t % NB;     // row-major target index t = r*64 + c
+    double v = src[c * NB + r];           // X(I*64 + r, J*64 + c)
+    if (I == J && r > c) v = 0.0;
+    xr[t] = st_from<SX>(v);
+    // X^T tile (J, I): element (c', r') = X(r', c'); row-major index c*64 + r below
+    xc[c * NB + r] = st_from<SX>(v);
+  }
+}
+
+hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, double *W,
+                         double *Y, int xstorage, void *XR, void *XC, hipStream_t st) {
+  const int T = N * (N + 1) / 2;
+  switch (storage) {
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, k_inv_init<double>, dim3(T), dim3(256), 0, st, N, (const double *)Rt, dinv64, W); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, k_inv_init<float>, dim3(T), dim3(256), 0, st, N, (const float *)Rt, dinv64, W); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, k_inv_init<half_t>, dim3(T), dim3(256), 0, st, N, (const half_t *)Rt, dinv64, W); break;
+    default: TLS_LAUNCH(PC_PACK, k_inv_init<bf16_t>, dim3(T), dim3(256), 0, st, N, (const bf16_t *)Rt, dinv64, W); break;
+  }
+  for (int hb = 1; hb < N; hb *= 2) {
+    const int pairs = (N + 2 * hb - 1) / (2 * hb);
+    const dim3 g(pairs * hb * hb);
+    TLS_LAUNCH(PC_INVERT, k_inv_phase1, g, dim3(256), 0, st, N, hb, W, Y);
+    TLS_LAUNCH(PC_INVERT, k_inv_phase2, g, dim3(256), 0, st, N, hb, W, (const double *)Y);
+  }
+  switch (xstorage) {
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, k_inv_pack<double>, dim3(T), dim3(256), 0, st, N, W, (double *)XR, (double *)XC); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, k_inv_pack<float>, dim3(T), dim3(256), 0, st, N, W, (float *)XR, (float *)XC); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, k_inv_pack<half_t>, dim3(T), dim3(256), 0, st, N, W, (half_t *)XR, (half_t *)XC); break;
+    default: TLS_LAUNCH(PC_PACK, k_inv_pack<bf16_t>, dim3(T), dim3(256), 0, st, N, W, (bf16_t *)XR, (bf16_t *)XC); break;
+  }
+  return hipGetLastError();
+}
+
+size_t invert_scratch_doubles(int N) {
+  // Y of the largest level: pairs * hb^2 tiles
+  size_t best = 0;
+  for (int hb = 1; hb < N; hb *= 2) {
+    const size_t pairs = (N + 2 * hb - 1) / (2 * hb);
+    best = std::max(best, pairs * hb * hb);
+  }
+  return std::max<size_t>(best, 1) * NB * NB;
+}
+
+// ---------------------------------------------------------------------------
+// application: out = X v (TRANS = 0) or X^T v (TRANS = 1), fused PCG modes
+// grid (N, CH): workgroup (I, s) covers the tiles of output block I in chunk
+// s; the last workgroup to finish a block reduces the chunk partials in
+// chunk order and runs the epilogue.
+// ---------------------------------------------------------------------------
+template <typename SX, typename C>
+struct XParams {
+  const SX *X;          // XR (TRANS = 0) or XC (TRANS = 1)
+  const C *dscale;      // 1/d, Np
+  int N, Np, n, chunk;  // chunk: tiles per workgroup
+  // apply
+  const double *in;
+  double *out;
+  int ldi, ldo;
+  // PCG state, [NR][Np]
+  C *s, *pb0, *pb1, *q, *w;
+  C *part;              // [(L+2)][3][NR][N]
+  int *done, *neg;
+  double *trace;
+  const double *sigma2;
+  int j, L, strict;
+  // chunk reduction
+  C *cpart;             // [N][CH][NR][64]
+  int *cnt;             // [N]
+  int *status;
+};
+
+template <typename C>
+__device__ inline C *xpart_ptr(C *part, int j, int kind, int r, int NR, int N) {
+  return part + (((size_t)j * 3 + kind) * NR + r) * N;
+}
+
+template <typename C>
+__device__ inline C xsum_parts(const C *p, int N) {
+  const int lane = threadIdx.x & 63;
+  C v = 0;
+  for (int i = lane; i < N; i += 64) v += p[i];
+  return wave_sum(v);
+}
+
+enum XMode { XA = 0, XF0 = 2, XB = 3, XF = 4 };   // XA: plain apply
+
+template <typename SX, typename C, int NR, int MODE, int TRANS>
+__global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
+  __shared__ C s_v[4][NR][NB];       // per-wave input block
+  __shared__ C s_acc[4][NR][NB];
+  __shared__ C s_scal[NR][4];
+  __shared__ int s_live[NR], s_last, s_skip;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int N = P.N, Np = P.Np;
+  const int I = blockIdx.x, sidx = blockIdx.y, CH = gridDim.y;
+  // pbuf of the current p (step j) and of the previous one
+  C *p_cur = (P.j & 1) ? P.pb1 : P.pb0;
+  C *p_old = (P.j & 1) ? P.pb0 : P.pb1;
+
+  if (tid == 0) {
+    int all_done = 1;
+    for (int r = 0; r < NR; ++r) {
+      int d = 0;
+      if constexpr (MODE == XB || MODE == XF) d = (P.j > 0) ? P.done[(P.j - 1) * NR + r] : 0;
+      s_live[r] = !d;
+      all_done &= d;
+    }
+    s_skip = all_done;
+    if constexpr (MODE == XF) {
+      if (all_done && I == 0 && sidx == 0)
+        for (int r = 0; r < NR; ++r) P.done[P.j * NR + r] = 1;
+    }
+  }
+  __syncthreads();
+  if (s_skip) return;   // uniform for the whole grid
+
+  // ---- step scalars (recomputed identically by every workgroup) -----------
+  if constexpr (MODE == XB || MODE == XF) {
+    if (w == 0) {
+      for (int r = 0; r < NR; ++r) {
+        const C eta = xsum_parts(xpart_ptr(P.part, P.j, 0, r, NR, N), N);
+        if constexpr (MODE == XB) {
+          C beta = 0;
+          if (P.j > 0) beta = eta / xsum_parts(xpart_ptr(P.part, P.j - 1, 0, r, NR, N), N);
+          if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; }
+        } else {
+          const C pp = xsum_parts(xpart_ptr(P.part, P.j, 1, r, NR, N), N);
+          const C qq = xsum_parts(xpart_ptr(P.part, P.j, 2, r, NR, N), N);
+          const C sig2 = (C)(*P.sigma2);
+          const C delta = pp - sig2 * qq;
+          if (lane == 0) {
+            s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = eta / delta; s_scal[r][3] = sig2;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- tiles of this chunk: wave w takes tiles w, w+4, ... ---------------
+  const int K_lo = TRANS ? 0 : I;               // input blocks feeding output block I
+  const int K_hi = TRANS ? I + 1 : N;
+  const int k0 = K_lo + sidx * P.chunk;
+  const int k1 = min(K_hi, k0 + P.chunk);
+  C acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0;
+  for (int K = k0 + w; K < k1; K += 4) {
+    // input block K (prologue transform), staged in this wave's LDS slot
+    const int row = K * NB + lane;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      C v;
+      const size_t vi = (size_t)r * Np + row;
+      if constexpr (MODE == XA) {
+        const C iv = (row < P.n) ? (C)P.in[(size_t)r * P.ldi + row] : (C)0;
+        v = TRANS ? P.dscale[row] * iv : iv;
+      } else if constexpr (MODE == XF0) {
+        v = (row < P.n) ? P.dscale[row] * (C)P.in[(size_t)r * P.ldi + row] : (C)0;
+      } else if constexpr (MODE == XB) {
+        v = (P.j > 0) ? P.s[vi] + s_scal[r][1] * p_old[vi] : p_cur[vi];
+      } else {
+        v = P.dscale[row] * P.q[vi];
+      }
+      s_v[w][r][lane] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const SX *T = P.X + (TRANS ? xc_tile(I, K) : xr_tile(I, K, N)) * NB * NB + (size_t)lane * NB;
+#pragma unroll 8
+    for (int c = 0; c < NB; ++c) {
+      const C t = cvt<C>(T[c]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += t * s_v[w][r][c];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) s_acc[w][r][lane] = acc[r];
+  __syncthreads();
+
+  // ---- chunk reduction ----------------------------------------------------
+  C res[NR];
+  if (CH == 1) {
+    if (w == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        res[r] = (s_acc[0][r][lane] + s_acc[1][r][lane]) + (s_acc[2][r][lane] + s_acc[3][r][lane]);
+    }
+  } else {
+    C *mine = P.cpart + (((size_t)I * CH + sidx) * NR) * NB;
+    if (w == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        mine[r * NB + lane] =
+            (s_acc[0][r][lane] + s_acc[1][r][lane]) + (s_acc[2][r][lane] + s_acc[3][r][lane]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&P.cnt[I], 1) == CH - 1);
+    __syncthreads();
+    if (!s_last) return;
+    if (w == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const C *base = P.cpart + ((size_t)I * CH * NR) * NB;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        C v = 0;
+        for (int c = 0; c < CH; ++c) v += base[((size_t)c * NR + r) * NB + lane];
+        res[r] = v;
+      }
+      if (lane == 0) P.cnt[I] = 0;
+    }
+  }
+  if (w != 0) return;
+
+  // ---- epilogue (wave 0, lane = row of block I) --------------------------
+  const int row = I * NB + lane;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const C x = res[r];
+    const size_t vi = (size_t)r * Np + row;
+    if constexpr (MODE == XA) {
+      if (row < P.n) P.out[(size_t)r * P.ldo + row] = (double)(TRANS ? x : P.dscale[row] * x);
+    } else if constexpr (MODE == XF0) {
+      P.s[vi] = x;
+      P.pb0[vi] = x;
+      P.w[vi] = 0;
+      const C ss = wave_sum(x * x);
+      if (lane == 0) xpart_ptr(P.part, 0, 0, r, NR, N)[I] = ss;
+    } else if constexpr (MODE == XB) {
+      const C qv = P.dscale[row] * x;                 // q = D^{-1} X p
+      C pv = p_cur[vi];
+      if (P.j > 0) pv = P.s[vi] + s_scal[r][1] * p_old[vi];
+      if (s_live[r]) {
+        P.q[vi] = qv;
+        if (P.j > 0) p_cur[vi] = pv;
+      }
+      const C pp = wave_sum(pv * pv), qq = wave_sum(qv * qv);
+      if (lane == 0) {
+        xpart_ptr(P.part, P.j, 1, r, NR, N)[I] = pp;
+        xpart_ptr(P.part, P.j, 2, r, NR, N)[I] = qq;
+      }
+    } else {   // XF: x = t = X^T D^{-1} q
+      const C delta = s_scal[r][1];
+      C sv = P.s[vi];
+      if (s_live[r] && delta != (C)0) {
+        P.w[vi] += s_scal[r][2] * P.q[vi];                        // omega_{j+1}
+        sv = sv - s_scal[r][2] * (p_cur[vi] - s_scal[r][3] * x);  // s_{j+1}
+        P.s[vi] = sv;
+      }
+      const C ss = wave_sum(sv * sv);
+      if (lane == 0) xpart_ptr(P.part, P.j + 1, 0, r, NR, N)[I] = ss;
+    }
+  }
+  // step bookkeeping: block 0's finishing workgroup
+  if constexpr (MODE == XB || MODE == XF) {
+    if (I == 0 && lane < NR) {
+      const int r = lane, L2 = P.L + 2, j = P.j;
+      double *tr = P.trace + (size_t)r * 4 * L2;
+      if constexpr (MODE == XB) {
+        if (s_live[r]) {
+          tr[0 * L2 + j] = (double)s_scal[r][0];
+          if (j > 0) tr[3 * L2 + j - 1] = (double)s_scal[r][1];
+        }
+      } else {
+        const C delta = s_scal[r][1];
+        const int was = (j > 0) ? P.done[(j - 1) * NR + r] : 0;
+        int now = was;
+        if (!was) {
+          tr[1 * L2 + j] = (double)delta;
+          if (delta != (C)0) tr[2 * L2 + j] = (double)s_scal[r][2];
+          if (delta == (C)0) now = 1;
+          if (delta < (C)0) {
+            P.neg[j * NR + r] = 1;
+            if (P.strict) {
+              now = 1;
+              atomicExch(P.status, (int)TLS_ERR_INDEFINITE);
+            }
+          }
+        }
+        P.done[j * NR + r] = now;
+      }
+    }
+  }
+}
+
+template <typename SX, typename C, int NR, int MODE, int TRANS>
+static hipError_t xlaunch(const XParams<SX, C> &P, int CH, hipStream_t st) {
+  TLS_LAUNCH(MODE == XA ? PC_TRSV_APPLY : PC_PCG, (k_xapply<SX, C, NR, MODE, TRANS>),
+             dim3(P.N, CH), dim3(256), 0, st, P);
+  return hipGetLastError();
+}
+
+template <typename SX, typename C, int MODE, int TRANS>
+static hipError_t x_nr(int nrhs, const XParams<SX, C> &P, int CH, hipStream_t st) {
+  return nrhs == 1 ? xlaunch<SX, C, 1, MODE, TRANS>(P, CH, st) : xlaunch<SX, C, 2, MODE, TRANS>(P, CH, st);
+}
+
+template <typename SX, typename C>
+static hipError_t x_mode(int mode, int trans, int nrhs, const XParams<SX, C> &P, int CH, hipStream_t st) {
+  switch (mode) {
+    case XA: return trans ? x_nr<SX, C, XA, 1>(nrhs, P, CH, st) : x_nr<SX, C, XA, 0>(nrhs, P, CH, st);
+    case XF0: return x_nr<SX, C, XF0, 1>(nrhs, P, CH, st);
+    case XB: return x_nr<SX, C, XB, 0>(nrhs, P, CH, st);
+    default: return x_nr<SX, C, XF, 1>(nrhs, P, CH, st);
+  }
+}
+
+// tiles per workgroup: one tile per wave, so that a block row of N tiles is
+// spread over N/4 workgroups (the chip has 256 CUs; a single CU streams far
+// below its share of the memory bandwidth)
+static int chunk_of(int N) { return N <= 4 ? N : 4; }
+
+template <typename C>
+static hipError_t x_dispatch(const FactorView &F, int mode, int trans, int nrhs, const SolveBufs &B,
+                             hipStream_t st) {
+  auto go = [&](auto *X) {
+    using SX = std::remove_const_t<std::remove_pointer_t<decltype(X)>>;
+    XParams<SX, C> P{};
+    P.X = X;
+    P.dscale = (const C *)(std::is_same<C, double>::value ? (const void *)F.dscale64 : (const void *)F.dscale32);
+    P.N = F.N;
+    P.Np = F.Np;
+    P.n = F.n;
+    P.chunk = chunk_of(F.N);
+    P.in = B.in;
+    P.out = B.out;
+    P.ldi = B.ldi ? B.ldi : F.n;
+    P.ldo = B.ldo ? B.ldo : F.n;
+    P.s = (C *)B.s;
+    P.pb0 = (C *)B.p;
+    P.pb1 = (C *)B.chain;    // the substitution chain buffer doubles as the second p buffer
+    P.q = (C *)B.q;
+    P.w = (C *)B.w;
+    P.part = (C *)B.part;
+    P.done = B.done;
+    P.neg = B.neg;
+    P.trace = B.trace;
+    P.sigma2 = B.sigma2;
+    P.j = B.j;
+    P.L = B.L;
+    P.strict = B.strict;
+    P.cpart = (C *)B.cpart;
+    P.cnt = B.cnt;
+    P.status = B.sync + F.N + 3;
+    const int CH = (F.N + P.chunk - 1) / P.chunk;
+    return x_mode<SX, C>(mode, trans, nrhs, P, CH, st);
+  };
+  const void *X = trans ? F.xc : F.xr;
+  switch (F.xstorage) {
+    case TLS_FP64: return go((const double *)X);
+    case TLS_FP32: return go((const float *)X);
+    case TLS_FP16: return go((const half_t *)X);
+    default: return go((const bf16_t *)X);
+  }
+}
+
+// mode: 0 apply R^{-1} (X, D^{-1} after), 1 apply R^{-T} (D^{-1} before, X^T),
+// 2 PCG init, 3 PCG backward, 4 PCG forward (same numbering as launch_trsv)
+hipError_t launch_xapply(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
+                         hipStream_t st) {
+  int m = XA, trans = 0;
+  switch (mode) {
+    case 0: m = XA; trans = 0; break;
+    case 1: m = XA; trans = 1; break;
+    case 2: m = XF0; trans = 1; break;
+    case 3: m = XB; trans = 0; break;
+    default: m = XF; trans = 1; break;
+  }
+  if (compute == TLS_FP64) return x_dispatch<double>(F, m, trans, nrhs, B, st);
+  return x_dispatch<float>(F, m, trans, nrhs, B, st);
+}
+
+size_t xapply_chunk_count(int N) { return (N + chunk_of(N) - 1) / chunk_of(N); }
+
+}  // namespace tls

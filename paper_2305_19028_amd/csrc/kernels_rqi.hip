@@ -76,9 +76,9 @@ hipError_t launch_residual(const MatView &A, const double *b, const double *x, d
                            double *part, hipStream_t st) {
   const dim3 g(matvec_blocks(A));
   if (A.format == TLS_DENSE_COLMAJOR)
-    hipLaunchKernelGGL(k_residual_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, b, x, r, part);
+    TLS_LAUNCH(PC_RESIDUAL, k_residual_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, b, x, r, part);
   else
-    hipLaunchKernelGGL(k_residual_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
+    TLS_LAUNCH(PC_RESIDUAL, k_residual_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
                        r, part);
   return hipGetLastError();
 }
@@ -122,17 +122,17 @@ __global__ void k_rmatvec_csc(int n, const int32_t *col_ptr, const int32_t *row_
 hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream_t st) {
   const dim3 g((A.m + 255) / 256);
   if (A.format == TLS_DENSE_COLMAJOR)
-    hipLaunchKernelGGL(k_matvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
+    TLS_LAUNCH(PC_RESIDUAL, k_matvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
   else
-    hipLaunchKernelGGL(k_matvec_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, x, y);
+    TLS_LAUNCH(PC_RESIDUAL, k_matvec_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, x, y);
   return hipGetLastError();
 }
 hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st) {
   const dim3 g((A.n + 3) / 4);
   if (A.format == TLS_DENSE_COLMAJOR)
-    hipLaunchKernelGGL(k_rmatvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
+    TLS_LAUNCH(PC_GRADIENT, k_rmatvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
   else
-    hipLaunchKernelGGL(k_rmatvec_csc, g, dim3(256), 0, st, A.n, A.col_ptr, A.row_idx, A.cval, x, y);
+    TLS_LAUNCH(PC_GRADIENT, k_rmatvec_csc, g, dim3(256), 0, st, A.n, A.col_ptr, A.row_idx, A.cval, x, y);
   return hipGetLastError();
 }
 
@@ -178,10 +178,10 @@ hipError_t launch_gradient(const MatView &A, const double *r, const double *x, c
                            double *f, double *part, hipStream_t st) {
   const dim3 g(rmatvec_blocks(A));
   if (A.format == TLS_DENSE_COLMAJOR)
-    hipLaunchKernelGGL(k_gradient<false>, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, nullptr,
+    TLS_LAUNCH(PC_GRADIENT, k_gradient<false>, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, nullptr,
                        nullptr, nullptr, r, x, scal, f, part);
   else
-    hipLaunchKernelGGL(k_gradient<true>, g, dim3(256), 0, st, A.m, A.n, (int64_t)0, nullptr,
+    TLS_LAUNCH(PC_GRADIENT, k_gradient<true>, g, dim3(256), 0, st, A.m, A.n, (int64_t)0, nullptr,
                        A.col_ptr, A.row_idx, A.cval, r, x, scal, f, part);
   return hipGetLastError();
 }
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_outer_rq(int n, const double *x, const 
 hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
                            double clamp_max, hipStream_t st) {
   (void)clamp_max;
-  hipLaunchKernelGGL(k_outer_rq, dim3(1), dim3(256), 0, st, n, x, part_r, nb_r, scal);
+  TLS_LAUNCH(PC_SCALARS, k_outer_rq, dim3(1), dim3(256), 0, st, n, x, part_r, nb_r, scal);
   return hipGetLastError();
 }
 
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, 
 hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
                             double *scal, int k, double *rec, hipStream_t st) {
   (void)x; (void)f; (void)n;
-  hipLaunchKernelGGL(k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec);
+  TLS_LAUNCH(PC_SCALARS, k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec);
   return hipGetLastError();
 }
 
@@ -264,7 +264,7 @@ __global__ void k_make_rhs(int n, const double *f, const double *x, double *rhs)
   rhs[n + i] = x[i];
 }
 hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_rhs, dim3((n + 255) / 256), dim3(256), 0, st, n, f, x, rhs);
+  TLS_LAUNCH(PC_SCALARS, k_make_rhs, dim3((n + 255) / 256), dim3(256), 0, st, n, f, x, rhs);
   return hipGetLastError();
 }
 
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const dou
 }
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
                              const double *scal, double *xbest, double *xsnap, hipStream_t st) {
-  hipLaunchKernelGGL(k_rqi_update, dim3(1), dim3(1024), 0, st, n, x, omega_u, f, (double *)scal,
+  TLS_LAUNCH(PC_SCALARS, k_rqi_update, dim3(1), dim3(1024), 0, st, n, x, omega_u, f, (double *)scal,
                      xbest, xsnap);
   return hipGetLastError();
 }
@@ -315,7 +315,7 @@ __global__ void k_axpy_scal(int n, double *x, const double *u, const double *sca
 }
 hipError_t launch_axpy_init(int n, double *x, const double *u, const double *scal, int which,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_scal, dim3((n + 255) / 256), dim3(256), 0, st, n, x, u, scal, which);
+  TLS_LAUNCH(PC_SCALARS, k_axpy_scal, dim3((n + 255) / 256), dim3(256), 0, st, n, x, u, scal, which);
   return hipGetLastError();
 }
 
@@ -327,7 +327,7 @@ hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStre
   if (!count) return hipSuccess;
   size_t g = (count + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)g), dim3(256), 0, st, dst, src, count);
+  TLS_LAUNCH(PC_SCALARS, k_copy, dim3((unsigned)g), dim3(256), 0, st, dst, src, count);
   return hipGetLastError();
 }
 __global__ void k_add(double *x, const double *dx, size_t count) {
@@ -338,7 +338,7 @@ hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t
   if (!count) return hipSuccess;
   size_t g = (count + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_add, dim3((unsigned)g), dim3(256), 0, st, x, dx, count);
+  TLS_LAUNCH(PC_SCALARS, k_add, dim3((unsigned)g), dim3(256), 0, st, x, dx, count);
   return hipGetLastError();
 }
 
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_residual_dd(int format, int m, int n, i
 }
 hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x, double *part,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_residual_dd, dim3(matvec_blocks(A)), dim3(256), 0, st, A.format, A.m, A.n,
+  TLS_LAUNCH(PC_RESID_DD, k_residual_dd, dim3(matvec_blocks(A)), dim3(256), 0, st, A.format, A.m, A.n,
                      A.ld, A.val, A.row_ptr, A.col_idx, b, x, part);
   return hipGetLastError();
 }
@@ -458,26 +458,36 @@ __global__ __launch_bounds__(256) void k_sigma_dd(int n, const double *x, const 
 }
 hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_sigma_dd, dim3(1), dim3(256), 0, st, n, x, part, nb, scal);
+  TLS_LAUNCH(PC_RESID_DD, k_sigma_dd, dim3(1), dim3(256), 0, st, n, x, part, nb, scal);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos step bookkeeping (gate estimates): w = V[k+1] holds M v_k; full
-// reorthogonalisation against v_0..v_k by classical Gram-Schmidt applied
-// twice, alpha_k from the first pass, beta_k = ||w||, v_{k+1} = w / beta_k.
-// One workgroup; ab[0..K) alpha, ab[K..2K) beta, ab[2K] active flag (1/0),
-// ab[2K+1] number of completed steps.
+// Lanczos step bookkeeping (gate estimates), two recurrences at once (one
+// workgroup each): run 0 on M_s = R_hat^{-1} R_hat^{-T}, run 1 on
+// M = D^{-1} M_s D^{-1} = (R^T R)^{-1}. The device applies M_s to the pair
+// [v0_k, D^{-1} v1_k]; here w1 = D^{-1} (M_s D^{-1} v1_k). Each run is
+// reorthogonalised against its basis by classical Gram-Schmidt applied
+// twice; alpha_k from the first pass, beta_k = ||w||, v_{k+1} = w / beta_k,
+// and the next operator input (D^{-1} v1_{k+1} for run 1) is written to
+// `nxt`. Layout: V[run][K+1][Np]; ab[run][2K+2]: alpha, beta, active, steps.
 // ---------------------------------------------------------------------------
 constexpr int LZ_MAX = 32;
 __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int K, double *V,
-                                                       double *ab) {
+                                                       const double *Wout, double *nxt,
+                                                       const double *dsc, double *ab) {
   __shared__ double red[16][LZ_MAX + 1];
   __shared__ double h[LZ_MAX + 1];
-  if (ab[2 * K] == 0.0) return;        // stopped earlier (uniform across the block)
-  double *w = V + (size_t)(k + 1) * Np;
+  const int run = blockIdx.x;
+  double *Vr = V + (size_t)run * (K + 1) * Np;
+  double *abr = ab + (size_t)run * (2 * K + 2);
+  if (abr[2 * K] == 0.0) return;        // this run stopped earlier (uniform per block)
+  double *w = Vr + (size_t)(k + 1) * Np;
+  const double *src = Wout + (size_t)run * Np;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = blockDim.x >> 6;
+  for (int j = tid; j < n; j += blockDim.x) w[j] = run ? dsc[j] * src[j] : src[j];
+  __syncthreads();
   double alpha = 0;
   for (int pass = 0; pass < 2; ++pass) {
     double acc[LZ_MAX + 1];
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int
       const double wj = w[j];
 #pragma unroll
       for (int i = 0; i <= LZ_MAX; ++i)
-        if (i <= k) acc[i] += V[(size_t)i * Np + j] * wj;
+        if (i <= k) acc[i] += Vr[(size_t)i * Np + j] * wj;
     }
 #pragma unroll
     for (int i = 0; i <= LZ_MAX; ++i) {
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int
     if (pass == 0) alpha = h[k];
     for (int j = tid; j < n; j += blockDim.x) {
       double wj = w[j];
-      for (int i = 0; i <= k; ++i) wj -= h[i] * V[(size_t)i * Np + j];
+      for (int i = 0; i <= k; ++i) wj -= h[i] * Vr[(size_t)i * Np + j];
       w[j] = wj;
     }
     __syncthreads();
@@ -519,20 +529,26 @@ __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int
   double tot = 0;
   for (int q = 0; q < nw; ++q) tot += red[q][0];
   const double beta = sqrt(tot);
-  // stop on an invariant subspace (relative to the operator scale alpha)
   const bool stop = !(beta > 1e-13 * fabs(alpha)) || (k + 1 >= K);
-  if (!stop)
-    for (int j = tid; j < n; j += blockDim.x) w[j] /= beta;
+  if (!stop) {
+    const double ib = 1.0 / beta;
+    for (int j = tid; j < n; j += blockDim.x) {
+      const double v = w[j] * ib;
+      w[j] = v;
+      nxt[(size_t)run * Np + j] = run ? dsc[j] * v : v;
+    }
+  }
   __syncthreads();
   if (tid == 0) {
-    ab[k] = alpha;
-    ab[K + k] = beta;
-    ab[2 * K + 1] = (double)(k + 1);
-    if (stop) ab[2 * K] = 0.0;
+    abr[k] = alpha;
+    abr[K + k] = beta;
+    abr[2 * K + 1] = (double)(k + 1);
+    if (stop) abr[2 * K] = 0.0;
   }
 }
-hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, double *ab, hipStream_t st) {
-  hipLaunchKernelGGL(k_lanczos_orth, dim3(1), dim3(1024), 0, st, n, Np, k, K, V, ab);
+hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const double *Wout,
+                               double *nxt, const double *dsc, double *ab, hipStream_t st) {
+  TLS_LAUNCH(PC_LANCZOS, k_lanczos_orth, dim3(2), dim3(1024), 0, st, n, Np, k, K, V, Wout, nxt, dsc, ab);
   return hipGetLastError();
 }
 

@@ -50,8 +50,9 @@ struct TrsvParams {
   int *sync;
   C *chain;            // [NR][Np] published block solutions
   // apply modes
-  const double *in;    // [NR][n]
-  double *out;         // [NR][n]
+  const double *in;    // [NR][ldi]
+  double *out;         // [NR][ldo]
+  int ldi, ldo;
   // PCG modes
   C *s, *p, *q, *w;    // [NR][Np]
   C *part;             // [(L+2)][3][NR][N]: ss, pp, qq
@@ -199,9 +200,9 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
           C y = 0;
           const size_t vi = (size_t)r * Np + row;
           if constexpr (MODE == APPLY_B) {
-            y = (row < P.n) ? (C)P.in[(size_t)r * P.n + row] : (C)0;
+            y = (row < P.n) ? (C)P.in[(size_t)r * P.ldi + row] : (C)0;
           } else if constexpr (MODE == APPLY_F || MODE == PCG_F0) {
-            y = (row < P.n) ? P.dscale[row] * (C)P.in[(size_t)r * P.n + row] : (C)0;
+            y = (row < P.n) ? P.dscale[row] * (C)P.in[(size_t)r * P.ldi + row] : (C)0;
           } else if constexpr (MODE == PCG_B) {
             C pv = P.p[vi];
             if (P.j > 0 && s_live[r]) {
@@ -246,9 +247,9 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
           const size_t vi = (size_t)r * Np + row;
           P.chain[vi] = x;
           if constexpr (MODE == APPLY_B) {
-            if (row < P.n) P.out[(size_t)r * P.n + row] = (double)(P.dscale[row] * x);
+            if (row < P.n) P.out[(size_t)r * P.ldo + row] = (double)(P.dscale[row] * x);
           } else if constexpr (MODE == APPLY_F) {
-            if (row < P.n) P.out[(size_t)r * P.n + row] = (double)x;
+            if (row < P.n) P.out[(size_t)r * P.ldo + row] = (double)x;
           } else if constexpr (MODE == PCG_F0) {
             P.s[vi] = x;
             P.p[vi] = x;
@@ -340,7 +341,9 @@ __global__ void k_pcg_finish(const C *w, double *out, int n, int Np, int NR) {
 // ---------------------------------------------------------------------------
 template <typename S, typename C, int NR, int MODE>
 static hipError_t launch_one(const TrsvParams<S, C> &P, hipStream_t st) {
+  prof_begin(MODE <= APPLY_F ? PC_TRSV_APPLY : PC_PCG, st);
   hipLaunchKernelGGL((k_trsv<S, C, NR, MODE>), dim3(P.N), dim3(WG), 0, st, P);
+  prof_end(st);
   return hipGetLastError();
 }
 
@@ -376,6 +379,8 @@ static hipError_t dispatch_storage(const FactorView &F, int mode, int nrhs, cons
     P.chain = (C *)B.chain;
     P.in = B.in;
     P.out = B.out;
+    P.ldi = B.ldi ? B.ldi : F.n;
+    P.ldo = B.ldo ? B.ldo : F.n;
     P.s = (C *)B.s; P.p = (C *)B.p; P.q = (C *)B.q; P.w = (C *)B.w;
     P.part = (C *)B.part;
     P.done = B.done;
@@ -404,10 +409,12 @@ hipError_t launch_trsv(const FactorView &F, int compute, int mode, int nrhs, con
 hipError_t launch_pcg_finish(int compute, const void *w, double *out, int n, int Np, int nrhs,
                              hipStream_t st) {
   const int g = (n + 255) / 256;
+  prof_begin(PC_SCALARS, st);
   if (compute == TLS_FP64)
     hipLaunchKernelGGL(k_pcg_finish<double>, dim3(g), dim3(256), 0, st, (const double *)w, out, n, Np, nrhs);
   else
     hipLaunchKernelGGL(k_pcg_finish<float>, dim3(g), dim3(256), 0, st, (const float *)w, out, n, Np, nrhs);
+  prof_end(st);
   return hipGetLastError();
 }
 

@@ -98,9 +98,13 @@ struct tls_precond_s {
   int32_t *col_ptr = nullptr, *row_idx = nullptr;
   double *cval = nullptr;
   tls_gate_report rep{};
+  void *xr = nullptr, *xc = nullptr;   // explicit inverse tiles
+  int xstorage = TLS_FP64;
+  int apply_mode = 0;             // 0 explicit inverse, 1 substitution
   void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
   int64_t fws_m = 0;
   int have_sigma_n = 0, have_kappa = 0;
+  double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
   FactorView view() const {
     FactorView F;
     F.n = (int)n;
@@ -112,6 +116,9 @@ struct tls_precond_s {
     F.dinv32 = dinv32;
     F.dscale64 = dsc64;
     F.dscale32 = dsc32;
+    F.xr = xr;
+    F.xc = xc;
+    F.xstorage = xstorage;
     return F;
   }
 };
@@ -175,8 +182,11 @@ struct FactorWs {
   double *lz;      // Lanczos vectors
   double *lzs;     // Lanczos scalars
   int *flag;
+  void *xr, *xc;   // explicit inverse tiles (FP64-sized)
+  double *yinv;    // inversion scratch
+  int *cnt;        // per-block arrival counters of internal applies
 };
-constexpr int LANCZOS_STEPS = 24;
+constexpr int LANCZOS_STEPS = 12;
 
 FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format) {
   const int Np = ceil_div(n, NB) * NB, N = Np / NB;
@@ -200,9 +210,14 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format) 
   }
   W.info = c.take<int>(4);
   W.sync = c.take<int>(N + 8);
-  W.lz = c.take<double>((size_t)(LANCZOS_STEPS + 5) * Np);
-  W.lzs = c.take<double>(2 * LANCZOS_STEPS + 8);
+  W.lz = c.take<double>((size_t)(2 * (LANCZOS_STEPS + 1) + 9) * Np);
+  W.lzs = c.take<double>(4 * LANCZOS_STEPS + 8);
   W.flag = c.take<int>(4);
+  W.xr = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
+  W.xc = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
+  W.yinv = c.take<double>(std::max(invert_scratch_doubles(N),
+                                    (size_t)N * xapply_chunk_count(N) * 2 * NB));
+  W.cnt = c.take<int>(N);
   (void)m;
   return W;
 }
@@ -215,6 +230,8 @@ struct PcgWs {
   int *done, *neg;
   double *trace;
   double *sigma2;
+  void *cpart;
+  int *cnt;
   int L;
 };
 
@@ -232,6 +249,8 @@ PcgWs carve_pcg(Carver &c, int Np, int N, int nrhs, int L) {
   W.neg = c.take<int>((size_t)(L + 2) * nrhs);
   W.trace = c.take<double>((size_t)nrhs * 4 * (L + 2));
   W.sigma2 = c.take<double>(2);
+  W.cpart = c.take<double>((size_t)N * xapply_chunk_count(N) * nrhs * NB);
+  W.cnt = c.take<int>(N);
   return W;
 }
 
@@ -249,6 +268,8 @@ SolveBufs bufs_of(const PcgWs &W) {
   B.trace = W.trace;
   B.sigma2 = W.sigma2;
   B.L = W.L;
+  B.cpart = W.cpart;
+  B.cnt = W.cnt;
   return B;
 }
 
@@ -263,13 +284,27 @@ tls_status sync_status(const int *sync, int N, hipStream_t st) {
   return TLS_OK;
 }
 
+hipError_t launch_precond(const tls_precond_s *P, int compute, int mode, int nrhs,
+                          const SolveBufs &B, hipStream_t st) {
+  if (P->apply_mode == 0 && P->xr) return launch_xapply(P->view(), compute, mode, nrhs, B, st);
+  return launch_trsv(P->view(), compute, mode, nrhs, B, st);
+}
+
+// zero the synchronisation state of a solve workspace
+tls_status reset_solve_ws(const tls_precond_s *P, PcgWs &W, hipStream_t st) {
+  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
+  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
+  return TLS_OK;
+}
+
 // R^{-1} (trans = 0) or R^{-T} (trans = 1) on nrhs FP64 vectors
 tls_status apply_R(const tls_precond_s *P, int trans, int nrhs, const double *in, double *out,
-                   int compute, PcgWs &W, hipStream_t st) {
+                   int compute, PcgWs &W, hipStream_t st, int ld = 0) {
   SolveBufs B = bufs_of(W);
   B.in = in;
   B.out = out;
-  HIPCHK(launch_trsv(P->view(), compute, trans ? 1 /*APPLY_F*/ : 0 /*APPLY_B*/, nrhs, B, st));
+  B.ldi = B.ldo = ld;
+  HIPCHK(launch_precond(P, compute, trans ? 1 : 0, nrhs, B, st));
   return TLS_OK;
 }
 
@@ -286,12 +321,11 @@ tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, con
   B.strict = strict;
   B.in = rhs;
   B.j = 0;
-  const FactorView F = P->view();
-  HIPCHK(launch_trsv(F, compute, 2 /*PCG_F0*/, nrhs, B, st));
+  HIPCHK(launch_precond(P, compute, 2 /* init: s_0 = R^{-T} f */, nrhs, B, st));
   for (int j = 0; j <= l; ++j) {
     B.j = j;
-    HIPCHK(launch_trsv(F, compute, 3 /*PCG_B*/, nrhs, B, st));
-    HIPCHK(launch_trsv(F, compute, 4 /*PCG_F*/, nrhs, B, st));
+    HIPCHK(launch_precond(P, compute, 3 /* q = R^{-1} p */, nrhs, B, st));
+    HIPCHK(launch_precond(P, compute, 4 /* R^{-T} q, s update */, nrhs, B, st));
   }
   HIPCHK(launch_pcg_finish(compute, W.w, omega, (int)P->n, P->Np, nrhs, st));
   (void)N;
@@ -337,12 +371,80 @@ void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// kernel-class profiling (HIP events on the launch stream)
+// ---------------------------------------------------------------------------
+namespace tls {
+namespace {
+struct ProfRec { int cls; hipEvent_t a, b; };
+struct ProfState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<ProfRec> recs;
+  int open_cls = -1;
+  hipEvent_t open_ev = nullptr;
+};
+ProfState g_prof;
+hipEvent_t prof_event() {
+  if (g_prof.next == g_prof.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+  }
+  return g_prof.pool[g_prof.next++];
+}
+}  // namespace
+void prof_begin(int cls, hipStream_t st) {
+  if (!g_prof.on) return;
+  hipEvent_t e = prof_event();
+  if (!e) return;
+  hipEventRecord(e, st);
+  g_prof.open_cls = cls;
+  g_prof.open_ev = e;
+}
+void prof_end(hipStream_t st) {
+  if (!g_prof.on || g_prof.open_cls < 0) return;
+  hipEvent_t e = prof_event();
+  if (!e) return;
+  hipEventRecord(e, st);
+  g_prof.recs.push_back({g_prof.open_cls, g_prof.open_ev, e});
+  g_prof.open_cls = -1;
+}
+}  // namespace tls
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
 
 const char *tls_last_error(void) { return g_err.c_str(); }
+
+tls_status tls_profile_start(void) {
+  g_prof.on = true;
+  g_prof.next = 0;
+  g_prof.recs.clear();
+  g_prof.open_cls = -1;
+  return TLS_OK;
+}
+
+tls_status tls_profile_stop(tls_kernel_times *out) {
+  g_prof.on = false;
+  tls_kernel_times t{};
+  for (const ProfRec &r : g_prof.recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.cls >= 0 && r.cls < TLS_PROF_CLASSES) {
+      t.launches[r.cls]++;
+      t.total_ms[r.cls] += ms;
+    }
+  }
+  g_prof.recs.clear();
+  g_prof.next = 0;
+  if (out) *out = t;
+  return TLS_OK;
+}
 const char *tls_version(void) { return "libtls 0.1 (gfx950)"; }
 
 void tls_default_opts(tls_rqi_opts *o) {
@@ -381,6 +483,13 @@ size_t tls_precond_import_workspace_size(int64_t n) {
 
 void tls_precond_destroy(tls_precond P) { delete P; }
 
+tls_status tls_precond_set_apply(tls_precond P, int32_t mode) {
+  if (!P) return fail(TLS_ERR_ARG, "P is NULL");
+  if (mode != 0 && mode != 1) return fail(TLS_ERR_ARG, "apply mode must be 0 or 1");
+  P->apply_mode = mode;
+  return TLS_OK;
+}
+
 tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage, tls_gate_report *rep) {
   if (!P) return fail(TLS_ERR_ARG, "P is NULL");
   if (n) *n = P->n;
@@ -409,67 +518,94 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
   return TLS_OK;
 }
 
-// Lanczos on M = R^{-1} R^{-T} = (R^T R)^{-1} (eigenvalues 1/sigma_i^2 of the
-// factored matrix): with use_scaling the operator uses R_hat alone (the
-// scaled A D^{-1}), otherwise R = R_hat D (A itself). Runs on the device
-// with full reorthogonalisation; the tridiagonal is read back once.
-tls_status lanczos_extremes(tls_precond_s *P, FactorWs &W, int use_scaling, double *lam_lo,
-                            double *lam_hi, int *steps, hipStream_t st) {
+// Lanczos for the gate estimates (eigenvalues 1/sigma_i^2): run 0 on
+// R_hat^{-1} R_hat^{-T} (the scaled A D^{-1}), run 1 on R^{-1} R^{-T} with
+// R = R_hat D (A itself). Both recurrences share each 2-RHS application of
+// the preconditioner; all of it stays on the device and the two
+// tridiagonal matrices are read back once. Extremal eigenvalues of each
+// tridiagonal matrix come from bisection on the host.
+tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *steps,
+                        hipStream_t st) {
   const int n = (int)P->n, Np = P->Np;
   const int K = std::min(LANCZOS_STEPS, n);
-  double *V = W.lz;                                   // K+1 basis vectors, stride Np
+  double *V = W.lz;                                   // [2][K+1][Np]
+  double *inb = W.lz + (size_t)2 * (LANCZOS_STEPS + 1) * Np;     // [2][Np] operator input
+  double *tmp = inb + (size_t)2 * Np;                            // [2][Np]
+  double *outb = tmp + (size_t)2 * Np;                           // [2][Np]
+  double *ones = outb + (size_t)2 * Np;                          // [Np]
   PcgWs S{};
   S.sync = W.sync;
-  S.chain = W.lz + (size_t)(LANCZOS_STEPS + 2) * Np;
+  S.chain = ones + Np;                                           // [2][Np]
   S.L = 0;
-  double *tmp = W.lz + (size_t)(LANCZOS_STEPS + 3) * Np;
-  double *ones = W.lz + (size_t)(LANCZOS_STEPS + 4) * Np;
-  double *ab = W.lzs;                                 // 2K + 2 scalars
+  S.cpart = W.yinv;     // free after the inversion
+  S.cnt = W.cnt;
+  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
+  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
+  double *ab = W.lzs;                                 // [2][2K+2]
   tls_precond_s Q = *P;
-  if (use_scaling) {
-    HIPCHK(launch_fill_f64(ones, 1.0, (size_t)Np, st));
-    Q.dsc64 = ones;
+  HIPCHK(launch_fill_f64(ones, 1.0, (size_t)Np, st));
+  Q.dsc64 = ones;                                     // apply R_hat alone
+  // v_0 = ones/sqrt(n) for both runs; operator input [v0, D^{-1} v0]
+  const double v0 = 1.0 / std::sqrt((double)n);
+  HIPCHK(launch_fill_f64(V, v0, (size_t)n, st));
+  HIPCHK(launch_fill_f64(V + (size_t)(K + 1) * Np, v0, (size_t)n, st));
+  HIPCHK(launch_fill_f64(inb, v0, (size_t)n, st));
+  HIPCHK(launch_fill_f64(inb + Np, 0.0, (size_t)n, st));
+  HIPCHK(launch_axpy_init(n, inb + Np, P->dsc64, nullptr, -1, st));   // D^{-1} * 1
+  {
+    // scale by v0: inb[1] = v0 * dsc (axpy wrote dsc); reuse copy + axpy with a device scalar
+    HIPCHK(launch_fill_f64(ab, v0, 1, st));
+    HIPCHK(launch_fill_f64(tmp, 0.0, (size_t)n, st));
+    HIPCHK(launch_axpy_init(n, tmp, inb + Np, ab, 0, st));
+    HIPCHK(launch_copy_f64(inb + Np, tmp, (size_t)n, st));
   }
-  HIPCHK(launch_fill_f64(V, 1.0 / std::sqrt((double)n), (size_t)n, st));   // v_0
-  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (size_t)K + 2, st));
+  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (2 * (size_t)K + 2), st));
   HIPCHK(launch_fill_f64(ab + 2 * K, 1.0, 1, st));
+  HIPCHK(launch_fill_f64(ab + (2 * K + 2) + 2 * K, 1.0, 1, st));
+  // the apply kernels read [nrhs][n]-packed inputs: pack with stride n
   for (int k = 0; k < K; ++k) {
-    TRY(apply_R(&Q, 1, 1, V + (size_t)k * Np, tmp, TLS_FP64, S, st));
-    TRY(apply_R(&Q, 0, 1, tmp, V + (size_t)(k + 1) * Np, TLS_FP64, S, st));
-    HIPCHK(launch_lanczos_orth(n, Np, k, K, V, ab, st));
+    TRY(apply_R(&Q, 1, 2, inb, tmp, TLS_FP64, S, st, Np));
+    TRY(apply_R(&Q, 0, 2, tmp, outb, TLS_FP64, S, st, Np));
+    HIPCHK(launch_lanczos_orth(n, Np, k, K, V, outb, inb, P->dsc64, ab, st));
   }
-  std::vector<double> h(2 * K + 2);
+  std::vector<double> h(2 * (2 * K + 2));
   HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  const int done = (int)h[2 * K + 1];
-  std::vector<double> a(h.begin(), h.begin() + done), b(h.begin() + K, h.begin() + K + std::max(done - 1, 0));
-  *steps = done;
-  tridiag_extremes(a, b, lam_lo, lam_hi);
+  for (int run = 0; run < 2; ++run) {
+    const double *hr = h.data() + run * (2 * K + 2);
+    const int done = (int)hr[2 * K + 1];
+    std::vector<double> a(hr, hr + done), b(hr + K, hr + K + std::max(done - 1, 0));
+    tridiag_extremes(a, b, &lam[run][0], &lam[run][1]);
+    steps[run] = done;
+  }
   return TLS_OK;
 }
 
-// sigma'_n(A) and sigma'_1(A) estimates (unscaled operator)
-tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
-  double lo = 0, hi = 0;
-  int steps = 0;
-  TRY(lanczos_extremes(P, W, 0, &lo, &hi, &steps, st));
-  P->rep.sigma_n_est = 1.0 / std::sqrt(hi);
-  P->rep.sigma_1_est = 1.0 / std::sqrt(std::max(lo, 1e-300));
-  P->rep.lanczos_steps = steps;
+// Lanczos estimates: kappa(A D^{-1}) and sigma'_n(A), sigma'_1(A)
+tls_status run_estimates(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  double lam[2][2];
+  int steps[2];
+  TRY(lanczos_pair(P, W, lam, steps, st));
+  tls_gate_report &R = P->rep;
+  P->smin_s = 1.0 / std::sqrt(lam[0][1]);
+  P->smax_s = 1.0 / std::sqrt(std::max(lam[0][0], 1e-300));
+  R.sigma_n_est = 1.0 / std::sqrt(lam[1][1]);
+  R.sigma_1_est = 1.0 / std::sqrt(std::max(lam[1][0], 1e-300));
+  R.lanczos_steps = steps[1];
   P->have_sigma_n = 1;
   return TLS_OK;
+}
+
+tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  return run_estimates(P, W, st);
 }
 
 // the A-only constraints of Section 3.1 from Lanczos estimates
 tls_status run_gate(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   tls_gate_report &R = P->rep;
   const double n = (double)P->n;
-  double lo = 0, hi = 0;
-  int steps = 0;
-  // scaled operator: eigenvalues of R_hat^{-1} R_hat^{-T} are 1/sigma_i(A D^{-1})^2
-  TRY(lanczos_extremes(P, W, 1, &lo, &hi, &steps, st));
-  const double smin_s = 1.0 / std::sqrt(hi), smax_s = 1.0 / std::sqrt(std::max(lo, 1e-300));
-  TRY(estimate_sigma_n(P, W, st));
+  TRY(run_estimates(P, W, st));
+  const double smin_s = P->smin_s, smax_s = P->smax_s;
   const double kap = P->scaled ? smax_s / smin_s : R.sigma_1_est / R.sigma_n_est;
   R.kappa_est = kap;
   // ||A D^{-1}||_F = sqrt(n) exactly when scaled
@@ -517,6 +653,11 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
       HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, uq, W.tiles, st));
       HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
       P->storage = uq;
+      P->xstorage = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+      HIPCHK(launch_invert(P->N, uq, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr,
+                           W.xc, st));
+      P->xr = W.xr;
+      P->xc = W.xc;
       return TLS_OK;
     }
     *breakdown = info;
@@ -649,6 +790,11 @@ tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_h
     HIPCHK(launch_scale_vectors((int)n, P->Np, W.d, 1, W.dsc64, W.dsc32, stream));
     HIPCHK(launch_import_tiles((int)n, P->N, P->Np, (const double *)W.G, storage, W.tiles, stream));
     HIPCHK(launch_diag_inverse(P->N, storage, W.tiles, W.dinv64, W.dinv32, stream));
+    P->xstorage = (storage == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+    HIPCHK(launch_invert(P->N, storage, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr,
+                         W.xc, stream));
+    P->xr = W.xr;
+    P->xc = W.xc;
     HIPCHK(hipStreamSynchronize(stream));
     P->rep.requested = P->rep.used = storage;
     P->rep.u_q = unit_roundoff(storage);
@@ -706,7 +852,7 @@ tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs, const 
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "PCG workspace %zu < %zu bytes", ws_bytes, need);
     Carver c(ws);
     PcgWs W = carve_pcg(c, P->Np, P->N, nrhs, l);
-    HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
+    TRY(reset_solve_ws(P, W, stream));
     HIPCHK(launch_fill_f64(W.sigma2, sigma2, 1, stream));
     TRY(pcg_run(P, W.sigma2, nrhs, rhs, omega, l, u_p, strict_pd, W, stream));
     if (trace || strict_pd) {
@@ -732,7 +878,7 @@ tls_status tls_apply_precond(const tls_precond P, int32_t trans, int32_t nrhs, c
   if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "apply workspace too small (%zu < %zu)", ws_bytes, need);
   Carver c(ws);
   PcgWs W = carve_pcg(c, P->Np, P->N, nrhs, 0);
-  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
+  TRY(reset_solve_ws(P, W, stream));
   TRY(apply_R(P, trans, nrhs, in, out, u_p, W, stream));
   return TLS_OK;
 }
@@ -838,7 +984,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     tls_rqi_stats &S = stats ? *stats : local;
     std::memset(&S, 0, sizeof S);
 
-    HIPCHK(launch_fill_i32(W.pcg.sync, 0, P->N + 8, st));
+    TRY(reset_solve_ws(P, W.pcg, st));
     HIPCHK(launch_fill_f64(W.scal, 0.0, 32, st));
     // finite b
     HIPCHK(launch_fill_i32(W.pcg.done, 0, 1, st));

@@ -94,6 +94,15 @@ class c_rqi_stats(C.Structure):
         }
 
 
+PROF_CLASSES = ["precond_apply", "pcg_step", "gram", "chol_panel", "chol_update", "residual",
+                "gradient", "outer_scalars", "setup", "lanczos", "pack", "residual_dd", "invert"]
+
+
+class c_kernel_times(C.Structure):
+    _fields_ = [("launches", C.c_int32 * len(PROF_CLASSES)),
+                ("total_ms", C.c_double * len(PROF_CLASSES))]
+
+
 # ----------------------------------------------------------------------------
 # library loading
 # ----------------------------------------------------------------------------
@@ -128,6 +137,9 @@ _SIGS = {
                                 C.POINTER(c_rqi_opts), C.c_void_p, C.POINTER(C.c_double),
                                 C.POINTER(c_rqi_stats), C.c_void_p, C.c_size_t, C.c_void_p]),
     "tls_round": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
+    "tls_profile_start": (C.c_int, []),
+    "tls_precond_set_apply": (C.c_int, [C.c_void_p, C.c_int32]),
+    "tls_profile_stop": (C.c_int, [C.POINTER(c_kernel_times)]),
 }
 
 
@@ -247,6 +259,11 @@ class Precond:
         st = C.c_int32()
         _check(lib().tls_precond_info(self.handle, C.byref(n), C.byref(st), None))
         return n.value
+
+    def set_apply(self, mode):
+        """0: explicit-inverse GEMV (default), 1: blocked substitution."""
+        m = {"inverse": 0, "substitution": 1}.get(mode, mode)
+        _check(lib().tls_precond_set_apply(self.handle, int(m)))
 
     def info(self):
         n = C.c_int64()
@@ -403,3 +420,14 @@ def tls_rqi_solve(A: Matrix, b, P: Precond, opts: c_rqi_opts | None = None, x_ou
     d = st.to_dict()
     d["status"] = STATUS.get(status, status)
     return x, sig.value, d
+
+
+def tls_profile_start():
+    _check(lib().tls_profile_start())
+
+
+def tls_profile_stop():
+    """Per kernel class: {name: (launches, total_ms)} since tls_profile_start."""
+    t = c_kernel_times()
+    _check(lib().tls_profile_stop(C.byref(t)))
+    return {name: (t.launches[i], t.total_ms[i]) for i, name in enumerate(PROF_CLASSES)}

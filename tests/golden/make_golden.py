@@ -1,0 +1,62 @@
+"""Write the stored reference answers used by the benchmark and the
+full-size GPU tests. Calls only the oracle and the seeded generators.
+
+    python tests/golden/make_golden.py
+
+For each workload: the plain float64 RQI-PCGTLS of the oracle (Algorithms
+2 and 3), its Rayleigh quotient re-evaluated in long double, Newton
+polishing with long-double residuals, and the certificates of
+oracle.certify (normal-equation residual, smallest root). The file records
+the certificate values next to the answer.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import tlsgen  # noqa: E402
+from oracle import certify, polish, rqi  # noqa: E402
+
+WORKLOADS = {
+    # name: (generator call, description)
+    "sparse_c2": (lambda: tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)[:2],
+                  "CSR 20000x2000, 0.5% nnz, column scales logU[1,1e4], b noise 1e-4, seed 2000"),
+    "dense_c1": (lambda: tlsgen.dense_gaussian(200, 20, seed=1000)[:2],
+                 "dense 200x20 N(0,1) + 1e-3 perturbation, b noise 1e-3, seed 1000"),
+}
+
+
+def reference(name):
+    A, b = WORKLOADS[name][0]()
+    t0 = time.time()
+    res = rqi.rqi_pcgtls(A, b, patience=2)
+    x, sig = polish.polish(A, b, res.x, steps=2)
+    c = certify.certify(A, b, x, sig)
+    return {
+        "workload": name,
+        "description": WORKLOADS[name][1],
+        "sigma": sig,
+        "x": [float(v) for v in x],
+        "certificate": {"normal_eq": c.normal_eq, "g_rel": c.g_rel, "rq_rel": c.rq_rel,
+                        "smallest_root": bool(c.smallest_root)},
+        "oracle_iters": res.iters,
+        "oracle_seconds": time.time() - t0,
+    }
+
+
+def main():
+    for name in WORKLOADS:
+        ref = reference(name)
+        path = os.path.join(HERE, f"{name}_ref.json")
+        with open(path, "w") as f:
+            json.dump(ref, f, indent=0)
+        print(name, "sigma", ref["sigma"], ref["certificate"], f"{ref['oracle_seconds']:.2f}s")
+
+
+if __name__ == "__main__":
+    main()

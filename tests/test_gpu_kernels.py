@@ -65,14 +65,16 @@ def _tri(n, seed, cond=10.0):
     return R
 
 
-@pytest.mark.parametrize("n", [5, 64, 100, 257, 1000])
+@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("n", [5, 64, 100, 257, 1000, 3100])
 @pytest.mark.parametrize("nrhs", [1, 2])
-def test_triangular_solves_fp64(n, nrhs):
+def test_triangular_solves_fp64(n, nrhs, mode):
     tls = _tls()
-    print(f"trsv n={n} nrhs={nrhs}", flush=True)
+    print(f"trsv n={n} nrhs={nrhs} {mode}", flush=True)
     R = _tri(n, n)
     d = np.exp(np.random.default_rng(2).uniform(-2, 2, n))
     P = tls.tls_precond_import(R, d, "fp64")
+    P.set_apply(mode)
     V = np.random.default_rng(3).standard_normal((nrhs, n))
     Rfull = R * d[None, :]          # R = R_hat diag(d)
     for trans in (0, 1):
@@ -82,17 +84,20 @@ def test_triangular_solves_fp64(n, nrhs):
             assert np.linalg.norm(out[r] - ref) <= 1e-12 * np.linalg.norm(ref), (trans, r)
 
 
+@pytest.mark.parametrize("mode", ["inverse", "substitution"])
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("u_p", ["fp64", "fp32"])
-def test_triangular_solves_low_storage(storage, u_p):
+def test_triangular_solves_low_storage(storage, u_p, mode):
     tls = _tls()
     n = 300
     R = _tri(n, 7)
     R = R / np.abs(R).max()
     P = tls.tls_precond_import(R, None, storage)
+    P.set_apply(mode)
     Rq = np.triu(lowprec.round_to(R, storage))      # what the library stores
     V = np.random.default_rng(4).standard_normal((2, n))
-    tol = 1e-12 if u_p == "fp64" else 1e-4
+    # the explicit inverse of a low-precision factor is held in FP32
+    tol = 1e-12 if (u_p == "fp64" and mode == "substitution") else (1e-6 if u_p == "fp64" else 1e-4)
     for trans in (0, 1):
         out = tls.tls_apply_precond(P, trans, V, u_p).cpu().numpy()
         for r in range(2):
@@ -100,13 +105,15 @@ def test_triangular_solves_low_storage(storage, u_p):
             assert np.linalg.norm(out[r] - ref) <= tol * np.linalg.norm(ref) * 10, (trans, r)
 
 
-@pytest.mark.parametrize("n,l", [(20, 0), (20, 3), (130, 5), (700, 8)])
-def test_pcg_step_matches_algorithm3(n, l):
+@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("n,l", [(20, 0), (20, 3), (130, 5), (700, 8), (3100, 3)])
+def test_pcg_step_matches_algorithm3(n, l, mode):
     tls = _tls()
-    print(f"pcg n={n} l={l}", flush=True)
+    print(f"pcg n={n} l={l} {mode}", flush=True)
     A, b, _ = tlsgen.dense_gaussian(3 * n, n, seed=n)
     R = rqi.cholesky_R(A)
     P = tls.tls_precond_import(R, None, "fp64")
+    P.set_apply(mode)
     sR, sRT = rqi._tri_solvers(R)
     s_n = np.linalg.svd(A, compute_uv=False)[-1]
     sig2 = (0.7 * s_n) ** 2
@@ -127,11 +134,13 @@ def test_pcg_step_matches_algorithm3(n, l):
         assert np.linalg.norm(out32[r] - w) <= 1e-4 * np.linalg.norm(w)
 
 
-def test_pcg_sigma_zero_and_single_rhs():
+@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+def test_pcg_sigma_zero_and_single_rhs(mode):
     tls = _tls()
     A, b, _ = tlsgen.dense_gaussian(90, 30, seed=3)
     R = rqi.cholesky_R(A)
     P = tls.tls_precond_import(R, None, "fp64")
+    P.set_apply(mode)
     f = np.random.default_rng(9).standard_normal(30)
     out, tr = tls.tls_pcg_step(P, 0.0, f, 4, trace=True)
     ref = sla.solve_triangular(R, sla.solve_triangular(R, f, trans="T"))
