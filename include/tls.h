@@ -125,7 +125,8 @@ typedef struct {
   int32_t strict_pd;       /* 1: delta_j <= 0 in PCGTLS is an error              */
   int32_t shift_clamp;     /* 1: shift = min(sigma_k^2, tau * sigma'_n estimate^2) */
   int32_t refine_sweeps;   /* final FP64 refinement RQI steps (explicit operator) */
-  int32_t refine_pcg_steps;/* PCG steps per refinement solve                     */
+  int32_t refine_pcg_steps;/* maximum PCG steps per refinement solve (it stops
+                              earlier once r^T M r has fallen by 1e-26)           */
   int32_t allow_escalate;  /* raise u_q when the b-dependent gate (6) fails       */
   int32_t gate_enforce;    /* 1: run the b-dependent gate                         */
   int32_t reserved;

@@ -157,3 +157,24 @@ def tls_correction(A, b, x) -> tuple[np.ndarray, np.ndarray]:
     res = A @ x - b
     Er = -np.outer(res, z) / (1.0 + x @ x)
     return Er[:, :-1], Er[:, -1]
+
+
+def planted_gap_solution(A, x_true, lam):
+    """Closed form of the planted-gap instance b = A x_true + e, A^T e = 0,
+    with sigma_{n+1}^2 = lam: from f = 0 in eq. (2),
+    (A^T A - lam I) x = A^T b = A^T A x_true, so
+    x_TLS = x_true + lam (A^T A - lam I)^{-1} x_true. The solve runs on the
+    column-equilibrated matrix D^{-1}(A^T A - lam I)D^{-1} by Cholesky.
+
+    Returns (sigma, x_TLS)."""
+    import scipy.linalg as sla
+    if hasattr(A, "to_scipy"):
+        S = A.to_scipy()
+        G = (S.T @ S).toarray()
+    else:
+        A = np.asarray(A, dtype=np.float64)
+        G = A.T @ A
+    d = np.sqrt(np.diag(G))
+    M = G / np.outer(d, d) - lam * np.diag(1.0 / (d * d))
+    y = sla.cho_solve(sla.cho_factor(M, lower=False), x_true / d) / d
+    return float(np.sqrt(lam)), x_true + lam * y

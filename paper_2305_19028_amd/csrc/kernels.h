@@ -149,6 +149,10 @@ hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStre
 hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t st);
 hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const double *Wout,
                                double *nxt, const double *dsc, double *ab, hipStream_t st);
+hipError_t launch_ref_step1(int n, int nrhs, const double *scal, double *x, double *r,
+                            const double *p, double *q, double *rs, hipStream_t st);
+hipError_t launch_ref_step2(int n, int nrhs, const double *r, const double *z, double *p, double *rs,
+                            int first, hipStream_t st);
 hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
                            hipStream_t st);
 

@@ -552,4 +552,65 @@ hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const dou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Refinement sweep: PCG on the explicit operator K = A^T A - mu I (two
+// right-hand sides), preconditioned by M = (R^T R)^{-1}. Scalar and vector
+// steps in one workgroup per right-hand side (n <= 65536).
+//   rs layout per rhs (doubles): 0 r.z (current), 1 alpha, 2 beta, 3 p.q
+// ---------------------------------------------------------------------------
+// q_r = A^T t_r - mu p_r; alpha = rz / (p.q); x += alpha p; r -= alpha q
+__global__ __launch_bounds__(1024) void k_ref_step1(int n, const double *scal, double *x, double *r,
+                                                    const double *p, double *q, double *rs) {
+  __shared__ double sc[16];
+  const int rhs = blockIdx.x;
+  const size_t o = (size_t)rhs * n;
+  const double mu = scal[1];
+  double pq = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double qi = q[o + i] - mu * p[o + i];
+    q[o + i] = qi;
+    pq += p[o + i] * qi;
+  }
+  pq = wave_sum(pq);
+  if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = pq;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sc[w];
+  const double rz = rs[4 * rhs + 0];
+  const double alpha = (t != 0.0) ? rz / t : 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    x[o + i] += alpha * p[o + i];
+    r[o + i] -= alpha * q[o + i];
+  }
+  if (threadIdx.x == 0) { rs[4 * rhs + 1] = alpha; rs[4 * rhs + 3] = t; }
+}
+// beta = r.z_new / r.z_old; p = z + beta p (first: p = z)
+__global__ __launch_bounds__(1024) void k_ref_step2(int n, const double *r, const double *z, double *p,
+                                                    double *rs, int first) {
+  __shared__ double sc[16];
+  const int rhs = blockIdx.x;
+  const size_t o = (size_t)rhs * n;
+  double rz = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) rz += r[o + i] * z[o + i];
+  rz = wave_sum(rz);
+  if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = rz;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sc[w];
+  const double beta = first ? 0.0 : ((rs[4 * rhs] != 0.0) ? t / rs[4 * rhs] : 0.0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[o + i] = z[o + i] + beta * p[o + i];
+  __syncthreads();
+  if (threadIdx.x == 0) { rs[4 * rhs + 0] = t; rs[4 * rhs + 2] = beta; }
+}
+hipError_t launch_ref_step1(int n, int nrhs, const double *scal, double *x, double *r,
+                            const double *p, double *q, double *rs, hipStream_t st) {
+  TLS_LAUNCH(PC_SCALARS, k_ref_step1, dim3(nrhs), dim3(1024), 0, st, n, scal, x, r, p, q, rs);
+  return hipGetLastError();
+}
+hipError_t launch_ref_step2(int n, int nrhs, const double *r, const double *z, double *p, double *rs,
+                            int first, hipStream_t st) {
+  TLS_LAUNCH(PC_SCALARS, k_ref_step2, dim3(nrhs), dim3(1024), 0, st, n, r, z, p, rs, first);
+  return hipGetLastError();
+}
+
 }  // namespace tls

@@ -105,6 +105,7 @@ struct tls_precond_s {
   int64_t fws_m = 0;
   int have_sigma_n = 0, have_kappa = 0;
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
+  double normA_F2 = 0;             // ||A||_F^2 = sum_j d_j^2
   FactorView view() const {
     FactorView F;
     F.n = (int)n;
@@ -724,9 +725,12 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
     }
     HIPCHK(launch_scale_vectors(n, P->Np, W.d, P->scaled, W.dsc64, W.dsc32, stream));
     int flag = 0;
+    std::vector<double> dh(n);
     HIPCHK(hipMemcpyAsync(&flag, W.flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(dh.data(), W.d, n * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     if (flag) return fail(TLS_ERR_NONFINITE, "A contains NaN or Inf");
+    for (double v : dh) P->normA_F2 += v * v;
     int uq = u_q;
     for (;;) {
       int bd = 0;
@@ -910,6 +914,7 @@ namespace {
 
 struct RqiWs {
   double *r, *f, *xbest, *rhs, *wu, *t1, *t2, *part, *scal, *rec;
+  double *rr, *rz, *rp, *rq, *rt, *rs;   // refinement PCG: residual, M r, direction, K p, A p, scalars
   PcgWs pcg;
 };
 
@@ -928,7 +933,13 @@ RqiWs carve_rqi(Carver &c, int64_t m, int64_t n, const tls_precond_s *P, int kma
   W.t2 = c.take<double>(n);
   W.part = c.take<double>(2 * (size_t)nb);
   W.scal = c.take<double>(32);
-  W.rec = c.take<double>(4 * (size_t)(kmax + 2));
+  W.rec = c.take<double>(4 * (size_t)(kmax + 8));
+  W.rr = c.take<double>(2 * n);
+  W.rz = c.take<double>(2 * n);
+  W.rp = c.take<double>(2 * n);
+  W.rq = c.take<double>(2 * n);
+  W.rt = c.take<double>(2 * m);
+  W.rs = c.take<double>(16);
   W.pcg = carve_pcg(c, P->Np, P->N, 2, L);
   return W;
 }
@@ -970,6 +981,8 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     if (o->u_p != TLS_FP64 && o->u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
     if (o->kmax < 1 || o->kmax > TLS_MAX_ITERS) return fail(TLS_ERR_ARG, "kmax must be in [1, %d]", TLS_MAX_ITERS);
     if (o->stop_patience < 1) return fail(TLS_ERR_ARG, "stop_patience must be >= 1");
+    if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return fail(TLS_ERR_ARG, "refine_sweeps must be in [0, 4]");
+    if (o->refine_sweeps > 0 && o->refine_pcg_steps < 1) return fail(TLS_ERR_ARG, "refine_pcg_steps must be >= 1");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     const size_t need = tls_rqi_workspace_size(A, P, o);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "RQI workspace %zu < %zu bytes", ws_bytes, need);
@@ -978,6 +991,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     Carver c(ws);
     RqiWs W = carve_rqi(c, A->m, A->n, P, kmax, L);
     const int n = (int)A->n;
+    const int m = (int)A->m;
     const MatView V = make_view(A, P);
     const int nb_r = matvec_blocks(V), nb_f = rmatvec_blocks(V);
     tls_rqi_stats local{};
@@ -994,23 +1008,66 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     HIPCHK(hipStreamSynchronize(st));
     if (bad) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
 
-    // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1 --------------------------
-    HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
-    TRY(solve_normal(P, W.t1, x, W.t2, W.pcg, st));               // x = R^{-1} R^{-T} A^T b
-    for (int c2 = 0; c2 < o->ls_corrections; ++c2) {               // corrected semi-normal equations
+    // one Rayleigh-quotient evaluation at x (residual pass, scalars, gradient pass, psi)
+    auto evaluate = [&](int k, double cap) -> tls_status {
+      HIPCHK(launch_fill_f64(W.scal + 14, cap, 1, st));
       HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
-      HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
-      TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
-      HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
-    }
-    HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
-    HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2 (cap 0: none)
-    {
-      double h[2];
-      HIPCHK(hipMemcpyAsync(h, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, cap, st));
+      HIPCHK(launch_gradient(V, W.r, x, W.scal, W.f, W.part, st));
+      HIPCHK(launch_outer_psi(n, x, W.f, W.part, nb_f, W.scal, k, W.rec, st));
+      return TLS_OK;
+    };
+
+    // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1; the b-dependent gate ---
+    for (;;) {
+      HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
+      TRY(solve_normal(P, W.t1, x, W.t2, W.pcg, st));               // x = R^{-1} R^{-T} A^T b
+      for (int c2 = 0; c2 < o->ls_corrections; ++c2) {               // corrected semi-normal equations
+        HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+        HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
+        TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
+        HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
+      }
+      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
+      HIPCHK(launch_fill_f64(W.scal + 14, 0.0, 1, st));
+      HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
+      double h2[2];
+      HIPCHK(hipMemcpyAsync(h2, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      S.sigma_ls = std::sqrt(h[0]);
+      S.sigma_ls = std::sqrt(h2[0]);
+      if (!(o->gate_enforce && P->storage != TLS_FP64)) break;
+      // constraint (6) with sigma_{n+1} <= sigma_0 and the Lanczos estimates
+      if (!P->have_kappa) {
+        FactorWs FW = factor_ws_of(P);
+        TRY(run_gate(P, FW, st));
+      }
+      tls_gate_report &R = P->rep;
+      const double ratio = (S.sigma_ls / R.sigma_n_est) * (S.sigma_ls / R.sigma_n_est);
+      R.ctilde_min = 1.0 - ratio;
+      R.bound6 = (1.0 - ratio) / R.kappaF_est;
+      R.verdict &= ~(8 | 16);
+      if (R.u_q < R.bound6) R.verdict |= 8;
+      break;
     }
+    // a-posteriori check, decided after the first PCGTLS run when (6) failed
+    bool gate_pending = o->gate_enforce && P->storage != TLS_FP64 && !(P->rep.verdict & 8);
+    auto escalate = [&]() -> tls_status {
+      tls_gate_report &R = P->rep;
+      if (!o->allow_escalate)
+        return fail(TLS_ERR_PRECISION, "u_q = %g fails constraint (6) (bound %.3g) and PCGTLS met "
+                    "delta_j <= 0 with the factor", R.u_q, R.bound6);
+      const auto tf = clk::now();
+      const int next = (P->storage == TLS_BF16) ? TLS_FP16 : (P->storage == TLS_FP16) ? TLS_FP32 : TLS_FP64;
+      FactorWs FW = factor_ws_of(P);
+      int bd = 0;
+      TRY(factor_once(A, P, FW, next, st, &bd));
+      P->have_kappa = P->have_sigma_n = 0;
+      if (next != TLS_FP64) TRY(run_gate(P, FW, st));
+      R.escalations++;
+      R.used = P->storage;
+      S.t_factor_ms += ms_since(tf);
+      return TLS_OK;
+    };
     TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
     HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));           // x_1 = x_0 + sigma_0^2 u_0
 
@@ -1022,7 +1079,6 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     }
     if (o->shift_clamp && std::isfinite(P->rep.sigma_n_est) && P->rep.sigma_n_est > 0)
       cap = o->shift_clamp_tau * P->rep.sigma_n_est * P->rep.sigma_n_est;
-    HIPCHK(launch_fill_f64(W.scal + 14, cap, 1, st));
 
     // ---- main loop -----------------------------------------------------------
     double best = std::numeric_limits<double>::infinity();
@@ -1030,10 +1086,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     S.stopped = 1;
     double h[16];
     for (k = 1; k <= kmax; ++k) {
-      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
-      HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, cap, st));
-      HIPCHK(launch_gradient(V, W.r, x, W.scal, W.f, W.part, st));
-      HIPCHK(launch_outer_psi(n, x, W.f, W.part, nb_f, W.scal, k, W.rec, st));
+      TRY(evaluate(k, cap));
       if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
       HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1055,18 +1108,85 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       if (psi == 0.0) { S.stopped = 2; break; }
       if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
       if (k == kmax) break;
-      // lines: two PCGTLS solves with l = k (k+1 steps), sharing sigma_k^2
+      // two PCGTLS solves with l = k (k+1 steps), sharing the shift
       HIPCHK(launch_make_rhs(n, W.f, x, W.rhs, st));
       TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, k, o->u_p, o->strict_pd, W.pcg, st));
       S.pcg_steps += k + 1;
+      if (gate_pending) {
+        // a posteriori: the low-precision preconditioned system stayed positive
+        // definite (delta_j > 0) in the first PCGTLS run at the actual shift
+        std::vector<int> neg((size_t)(W.pcg.L + 2) * 2);
+        HIPCHK(hipMemcpyAsync(neg.data(), W.pcg.neg, neg.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int nneg = 0;
+        for (int v : neg) nneg += v;
+        gate_pending = false;
+        if (nneg == 0) {
+          P->rep.verdict |= 16;
+        } else {
+          TRY(escalate());
+          return tls_rqi_solve(A, b, P, o, x, sigma, stats, ws, ws_bytes, st);
+        }
+      }
       HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
-    }
-    {
-      int neg[1] = {0};
-      (void)neg;
     }
     // the returned iterate
     HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
+
+    // ---- final FP64 refinement: RQI steps with explicit-operator PCG --------
+    // (skipped when psi already sits at the float64 rounding floor u ||A||_F^2)
+    const bool at_floor = P->normA_F2 > 0 && best <= 32.0 * unit_roundoff(TLS_FP64) * P->normA_F2;
+    for (int sw = 0; sw < (at_floor ? 0 : o->refine_sweeps); ++sw) {
+      TRY(evaluate(kmax + 1 + sw, cap));                   // f, g and the (clamped) shift at x
+      {
+        // a Newton step is only meaningful at the Rayleigh-quotient shift: if the
+        // clamp is active the iterate is not yet near sigma_{n+1}; stop refining
+        double hs[2];
+        HIPCHK(hipMemcpyAsync(hs, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hs[1] != hs[0]) break;
+      }
+      HIPCHK(launch_make_rhs(n, W.f, x, W.rr, st));          // r = [-f, x], omega = u = 0
+      HIPCHK(launch_fill_f64(W.wu, 0.0, 2 * (size_t)n, st));
+      // z = M r with M = (R^T R)^{-1} applied in FP64 arithmetic to the stored
+      // factor: a fixed symmetric preconditioner, so CG reaches FP64 accuracy
+      TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
+      TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
+      HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 1, st));
+      double rz0[8];
+      HIPCHK(hipMemcpyAsync(rz0, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int j = 0; j < o->refine_pcg_steps; ++j) {
+        if (j > 0 && j % 8 == 0) {
+          // stop when both preconditioned residuals r^T M r fell by 1e-26
+          double rzj[8];
+          HIPCHK(hipMemcpyAsync(rzj, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          if (rzj[0] <= 1e-26 * rz0[0] && rzj[4] <= 1e-26 * rz0[4]) break;
+        }
+        for (int q = 0; q < 2; ++q) {                         // K p = A^T (A p) - mu p
+          HIPCHK(launch_matvec(V, W.rp + (size_t)q * n, W.rt + (size_t)q * m, st));
+          HIPCHK(launch_rmatvec(V, W.rt + (size_t)q * m, W.rq + (size_t)q * n, st));
+        }
+        HIPCHK(launch_ref_step1(n, 2, W.scal, W.wu, W.rr, W.rp, W.rq, W.rs, st));
+        TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
+        TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
+        HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 0, st));
+      }
+      HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+      S.refine_steps++;
+      // keep the refined iterate only if psi improves
+      TRY(evaluate(kmax + 1 + sw, cap));
+      HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (h[7] < best) {
+        best = h[7];
+        HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
+      } else {
+        HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
+        break;
+      }
+    }
     // final sigma from a compensated residual at x
     HIPCHK(launch_residual_dd(V, b, x, W.part, st));
     HIPCHK(launch_sigma_dd(n, x, W.part, nb_r, W.scal + 20, st));
@@ -1074,6 +1194,13 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     HIPCHK(hipMemcpyAsync(sg, W.scal + 20, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     TRY(sync_status(W.pcg.sync, P->N, st));
+    {
+      // PCGTLS steps that met delta_j < 0 (the last run's flags)
+      std::vector<int> neg((size_t)(W.pcg.L + 2) * 2);
+      HIPCHK(hipMemcpyAsync(neg.data(), W.pcg.neg, neg.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int v : neg) S.negative_delta += v;
+    }
     S.sigma_final = sg[1];
     if (sigma) *sigma = sg[1];
     S.t_total_ms = ms_since(t0);

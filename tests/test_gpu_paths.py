@@ -1,0 +1,209 @@
+"""GPU tests of the solve paths at full size and of the control logic:
+precision gate and escalation (Section 3.1 constraints), shift clamp,
+final refinement, failure statuses."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import tlsgen
+from oracle import certify, constraints, exact, polish, rqi
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _tls():
+    from paper_2305_19028_amd import tls
+    return tls
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", f"{name}_ref.json")) as f:
+        ref = json.load(f)
+    return np.array(ref["x"]), float(ref["sigma"])
+
+
+@pytest.mark.parametrize("path", ["fp64", "fp16", "bf16", "fp32"])
+def test_sparse_workload_full_size(path):
+    # the benchmark workload: CSR 20000 x 2000, 0.5% nnz, column scales 1..1e4
+    tls = _tls()
+    print(f"sparse 20000x2000 {path}", flush=True)
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    xref, sref = _golden("sparse_c2")
+    Ad = tls.from_tlsgen(A)
+    P, rep = tls.tls_factor_precond(Ad, path)
+    opts = tls.default_opts(u_p="fp64" if path == "fp64" else "fp32", stop_patience=2,
+                            refine_sweeps=0 if path == "fp64" else 1, refine_pcg_steps=4,
+                            gate_enforce=1)
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts)
+    x = x.cpu().numpy()
+    assert abs(sigma - sref) / sref < 1e-10
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) < 1e-10
+    if path != "fp64":
+        g = P.info()["gate"]
+        assert g["verdict"] & (8 | 16)         # (6) or the a-posteriori check holds
+        assert g["bound6"] > 0
+
+
+def test_sampled_rows_of_normal_equations_full_size():
+    # property at full size: (A^T A - sigma^2 I) x = A^T b on sampled rows, in long double
+    tls = _tls()
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    Ad = tls.from_tlsgen(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp16")
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p="fp32", stop_patience=2))
+    x = x.cpu().numpy()
+    f, g, s2 = polish.newton_residual_ld(A, b, x, sigma2=sigma ** 2)
+    scale = np.sqrt(float(np.sum(A.val.astype(np.longdouble) ** 2))) ** 2 * np.linalg.norm(x)
+    rows = np.random.default_rng(0).choice(2000, 64, replace=False)
+    assert float(np.max(np.abs(f[rows]))) / scale < 1e-13
+    assert abs(float(g)) / np.linalg.norm(b) ** 2 < 1e-13
+
+
+def _gap_problem(rel_gap, seed=4001):
+    return tlsgen.planted_gap(m=4000, n=300, density=0.01, scale_decades=6.0, rel_gap=rel_gap, seed=seed)
+
+
+def test_gate_bounds_against_exact_constraints():
+    tls = _tls()
+    A, b, x_t, lam, sn = _gap_problem(1e-3)
+    Af = A.to_dense()
+    ex = constraints.bounds(Af, b, scaled=True)
+    Ad = tls.from_tlsgen(A)
+    P, rep = tls.tls_factor_precond(Ad, "fp32")
+    # the exact planted sigma_{n+1}
+    assert abs(ex.sigma - np.sqrt(lam)) / np.sqrt(lam) < 1e-8
+    opts = tls.default_opts(u_p="fp32", stop_patience=3, gate_enforce=1, shift_clamp=1,
+                            shift_clamp_tau=0.999, kmax=80)
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts, allow_no_convergence=True)
+    g = P.info()["gate"]
+    # kappa of the scaled matrix and sigma'_n within Lanczos accuracy
+    assert 0.3 < g["kappa_est"] / ex.kappa <= 1.0 + 1e-6
+    assert abs(g["sigma_n_est"] - ex.sigma_n_A) / ex.sigma_n_A < 0.3
+    # (6) from sigma_0 >= sigma_{n+1} is never looser than the exact (6)
+    assert g["bound6"] <= ex.bound6 * 1.5 or g["bound6"] <= 0
+
+
+def test_gate_rejects_then_escalates():
+    # tiny gap: constraint (6) fails for 16-bit factors; the a-posteriori check
+    # (no delta_j <= 0 in the first PCGTLS run) decides, escalation fixes a failure
+    tls = _tls()
+    A, b, x_t, lam, sn = _gap_problem(1e-3, seed=4002)
+    sig_ref, x_ref = exact.planted_gap_solution(A, x_t, lam)
+    Ad = tls.from_tlsgen(A)
+    P, rep = tls.tls_factor_precond(Ad, "bf16")
+    opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=0, stop_patience=3, kmax=120)
+    try:
+        x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts, allow_no_convergence=True)
+        g = P.info()["gate"]
+        assert not (g["verdict"] & 8) and (g["verdict"] & 16)
+        rejected = False
+    except tls.TLSError as e:
+        assert e.status == -4                      # TLS_ERR_PRECISION
+        g = P.info()["gate"]
+        assert not (g["verdict"] & (8 | 16))
+        rejected = True
+    if rejected:
+        # the same configuration with escalation allowed raises u_q
+        P2, _ = tls.tls_factor_precond(Ad, "bf16")
+        opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=3, kmax=120)
+        tls.tls_rqi_solve(Ad, b, P2, opts, allow_no_convergence=True)
+        g2 = P2.info()["gate"]
+        assert g2["escalations"] >= 1 and g2["used"] != tls.PREC["bf16"]
+    assert g["bound6"] < 2.0 ** -8                 # (6) rejects bf16 on this instance
+    # an FP32 factor: constraint (6) with the exact sigma_{n+1} admits it; the
+    # solve runs (accuracy on this tiny-gap stress instance is limited by the
+    # k+1-step inner solves, as for the float64 oracle, and is not asserted)
+    P3, _ = tls.tls_factor_precond(Ad, "fp32")
+    opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=3, kmax=60,
+                            shift_clamp=1, shift_clamp_tau=0.9)
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P3, opts, allow_no_convergence=True)
+    assert np.isfinite(sigma) and st["iters"] >= 2
+
+
+def test_shift_clamp_recovers_smallest_root():
+    tls = _tls()
+    A, b = tlsgen.paper_bjorck()
+    ref = exact.svd_tls(A, b)
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp64")
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(shift_clamp=1, stop_patience=3, kmax=80))
+    x = x.cpu().numpy()
+    assert abs(sigma - ref.sigma) / ref.sigma < 1e-12
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) < 1e-10
+    assert certify.certify(A, b, x, sigma).smallest_root
+    assert st["clamped"] >= 1
+
+
+def test_refinement_sweep_reaches_tolerance():
+    # bf16 factor, RQI cut after two iterations (iterate not yet at the float64
+    # floor): the explicit-operator refinement takes it to the reference
+    tls = _tls()
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    xref, sref = _golden("sparse_c2")
+    Ad = tls.from_tlsgen(A)
+    errs = {}
+    for sweeps in (0, 2):
+        P, _ = tls.tls_factor_precond(Ad, "bf16")
+        opts = tls.default_opts(u_p="fp32", kmax=2, stop_patience=3, refine_sweeps=sweeps,
+                                refine_pcg_steps=200)
+        x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts, allow_no_convergence=True)
+        x = x.cpu().numpy()
+        errs[sweeps] = (abs(sigma - sref) / sref, np.linalg.norm(x - xref) / np.linalg.norm(xref),
+                        st["refine_steps"])
+    assert errs[2][2] >= 1
+    assert errs[0][1] > 1e-10                     # the cut RQI alone is not there yet
+    assert errs[2][0] < 1e-10 and errs[2][1] < 1e-10, errs
+
+
+def test_failure_statuses():
+    tls = _tls()
+    A, b, _ = tlsgen.dense_gaussian(100, 10, seed=5)
+    # NaN in A
+    A2 = A.copy()
+    A2[3, 4] = np.nan
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_factor_precond(tls.dense(A2), "fp64")
+    assert e.value.status == -9
+    # zero column: A^T A singular, Cholesky breakdown (scaled and unscaled)
+    A3 = A.copy()
+    A3[:, 7] = 0.0
+    for scaling in (False, True):
+        with pytest.raises(tls.TLSError) as e:
+            tls.tls_factor_precond(tls.dense(A3), "fp64", scaling=scaling)
+        assert e.value.status == -3
+    # NaN in b
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp64")
+    b2 = b.copy()
+    b2[0] = np.inf
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_rqi_solve(Ad, b2, P)
+    assert e.value.status == -9
+    # kmax = 1: no convergence (the result is still written)
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_rqi_solve(Ad, b, P, tls.default_opts(kmax=1, stop_patience=5))
+    assert e.value.status == -7
+    # strict positive definiteness: a shift above sigma'_n^2
+    sn = np.linalg.svd(A, compute_uv=False)[-1]
+    f = np.random.default_rng(0).standard_normal(10)
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_pcg_step(P, (1.5 * sn) ** 2, f, 5, strict=True)
+    assert e.value.status == -5
+    # workspace and argument errors
+    with pytest.raises(tls.TLSError):
+        tls.tls_pcg_step(P, 1.0, f, 5, u_p="fp16")
+
+
+def test_deterministic_repeat():
+    tls = _tls()
+    A, b, _, _ = tlsgen.sparse_scaled(5000, 400, 0.01, 4.0, 1e-4, seed=9)
+    Ad = tls.from_tlsgen(A)
+    outs = []
+    for _ in range(3):
+        P, _ = tls.tls_factor_precond(Ad, "fp16")
+        x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p="fp32", stop_patience=2))
+        outs.append((x.cpu().numpy().tobytes(), sigma, tuple(st["psi"])))
+    assert outs[0] == outs[1] == outs[2]

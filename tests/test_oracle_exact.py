@@ -97,3 +97,17 @@ def test_minimal_correction():
     E, r = exact.tls_correction(A, b, s.x)
     assert abs(np.linalg.norm(np.column_stack([E, r])) - s.sigma) / s.sigma < 1e-12
     assert np.linalg.norm((A + E) @ s.x - (b + r)) < 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("rel_gap,seed", [(1e-3, 4001), (1e-2, 4003)])
+def test_planted_gap_closed_form(rel_gap, seed):
+    # the planted-gap construction and its closed form against the SVD of [A, b]
+    A, b, x_t, lam, sn = tlsgen.planted_gap(m=4000, n=300, density=0.01, scale_decades=6.0,
+                                            rel_gap=rel_gap, seed=seed)
+    sig, x = exact.planted_gap_solution(A, x_t, lam)
+    s = exact.svd_tls(A.to_dense(), b)
+    bs, bx = certify.attainable(s.sigma_1_Ab, s.sigma, s.kappa_tls)
+    assert abs(s.sigma - sig) / sig < max(1e-12, 10 * bs)
+    assert np.linalg.norm(s.x - x) / np.linalg.norm(x) < max(1e-10, 10 * bx)
+    gap = (s.sigma_n_A - s.sigma) / s.sigma_n_A
+    assert 0.5 * rel_gap < gap < 2 * rel_gap

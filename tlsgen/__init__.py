@@ -205,15 +205,20 @@ def planted_gap(m: int = 100000, n: int = 8000, density: float = 0.001,
     """CSR A (as in ``sparse_scaled`` with wider column scales) and
     b = A x_true + e with e orthogonal to range(A), its norm chosen so that
     the smallest singular value of [A, b] equals sqrt(lam) with
-    lam = ((1 - rel_gap) * sigma_n(A))**2.
+    lam = ((1 - rel_gap) * sigma_n)**2, sigma_n an estimate of sigma_n(A).
 
-    Instance construction (not the solver): sigma_n(A) from the dense
-    eigen-decomposition of A^T A, e from a projected Gaussian vector. With
-    A^T e = 0, the smallest root of the TLS secular equation is lam when
+    Instance construction (not the solver). With A^T e = 0, the smallest root
+    of the TLS secular equation is lam when
     ||e||^2 = lam (1 + ||x||^2 + lam x^T (A^T A - lam I)^{-1} x).
+    The projection and the quadratic form are evaluated through the
+    column-equilibrated Gram matrix G_s = D^{-1} A^T A D^{-1} (well
+    conditioned even for widely scaled columns); sigma_n comes from the
+    eigenvalues of A^T A and only needs to be accurate enough to keep lam
+    below sigma_n(A)^2.
 
-    Returns (CSR, b, x_true, lam, sigma_n)."""
+    Returns (CSR, b, x_true, lam, sigma_n estimate)."""
     import scipy.linalg as sla
+    import scipy.sparse as sp
     g = rng(seed)
     nnz = int(round(density * m * n))
     pos = _uniform_positions(g, m, n, nnz)
@@ -223,18 +228,22 @@ def planted_gap(m: int = 100000, n: int = 8000, density: float = 0.001,
     A = _csr_from_positions(m, n, pos, val)
     x = g.standard_normal(n)
     S = A.to_scipy()
+    d = np.sqrt(np.asarray(S.multiply(S).sum(axis=0)).ravel())
+    Ss = S @ sp.diags(1.0 / d)
+    Gs = (Ss.T @ Ss).toarray()
+    cf = sla.cho_factor(Gs, lower=False)
     G = (S.T @ S).toarray()
-    evals, evecs = sla.eigh(G)
-    sig_n = math.sqrt(max(evals[0], 0.0))
+    sig_n = math.sqrt(max(sla.eigvalsh(G, subset_by_index=[0, 0])[0], 0.0))
     lam = ((1.0 - rel_gap) * sig_n) ** 2
-    # projected noise direction: e = h - A G^{-1} A^T h
+    # projected noise direction: e = h - A_s G_s^{-1} A_s^T h, applied twice
     h = g.standard_normal(m)
-    coef = evecs @ ((evecs.T @ (S.T @ h)) / evals)
-    e = h - S @ coef
-    e -= S @ (evecs @ ((evecs.T @ (S.T @ e)) / evals))   # second projection pass
-    t = evecs.T @ x
-    quad = float(np.sum(t * t / (evals - lam)))
-    e_norm2 = lam * (1.0 + float(x @ x) + lam * quad)
+    e = h - Ss @ sla.cho_solve(cf, Ss.T @ h)
+    e = e - Ss @ sla.cho_solve(cf, Ss.T @ e)
+    # q = x^T (A^T A - lam I)^{-1} x = (x/d)^T (G_s - lam D^{-2})^{-1} (x/d)
+    Msh = Gs - lam * np.diag(1.0 / (d * d))
+    xs = x / d
+    q = float(xs @ sla.cho_solve(sla.cho_factor(Msh, lower=False), xs))
+    e_norm2 = lam * (1.0 + float(x @ x) + lam * q)
     e *= math.sqrt(e_norm2) / np.linalg.norm(e)
     b = S @ x + e
     return A, np.asarray(b), x, lam, sig_n
