@@ -128,11 +128,64 @@ def kernel_profile(tls, torch, Ad, bd, path, reps=3):
                 "avg_us": (v[1] / v[0] * 1e3) if v[0] else 0.0} for k, v in prof.items() if v[0]}
 
 
-def trsv_bytes(n, storage_bytes, nrhs=2, compute_bytes=4):
-    """Algorithmic bytes of one triangular solve with R (Table 1: n^2 flops
-    per substitution): the n(n+1)/2 stored entries of the triangle, plus the
-    right-hand sides read and solutions written."""
-    return n * (n + 1) // 2 * storage_bytes + 2 * nrhs * n * compute_bytes
+NB = 64
+PEAKS = {  # MI355X published peaks
+    "hbm": (8000.0, "GB/s"),
+    "alu_f64": (78.6, "TFLOP/s"),    # FP64 vector
+    "alu_f32": (157.3, "TFLOP/s"),   # FP32 vector
+}
+SIZE = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def class_work(cls, path, m, n, nnz, launches):
+    """Algorithmic work of one kernel class over one solve: (bound, amount in
+    bytes or flops, description). `launches` is the class's launch count per
+    solve (from the HIP-event profile). None for latency-only classes."""
+    cfg = PATHS[path]
+    Np = -(-n // NB) * NB
+    N = Np // NB
+    tri = n * (n + 1) // 2
+    bx = 8 if cfg["u_q"] == "fp64" else 4          # explicit inverse X storage
+    bp = SIZE[cfg["u_p"]]
+    alu = "alu_f64" if cfg["u_q"] == "fp64" else "alu_f32"
+    if cls == "pcg_step":
+        # one application of X or X^T to the two PCG right-hand sides: the
+        # triangle once, 2 vectors in and out, the fused scalar partials
+        per = tri * bx + 2 * 2 * n * bp
+        return "hbm", per * launches, f"X triangle {tri}x{bx} B + 2-RHS vectors per launch"
+    if cls == "precond_apply":
+        per = tri * bx + 2 * n * 8
+        return "hbm", per * launches, f"X triangle {tri}x{bx} B + FP64 vector in/out per launch"
+    if cls == "chol_panel":
+        fl = sum(NB ** 3 / 3 + (N - k - 1) * NB ** 3 for k in range(N))
+        return alu, fl * launches / N, "diagonal tile n_b^3/3 + (N-k-1) n_b^3 per panel"
+    if cls == "chol_update":
+        fl = sum((N - k - 1) * (N - k) / 2 * 2 * NB ** 3 for k in range(N))
+        return alu, fl * launches / max(N - 1, 1), "2 n_b^3 per trailing tile pair"
+    if cls == "invert":
+        return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches"
+    if cls in ("residual", "gradient"):
+        per = 12 * nnz + 4 * (m + 1) + 8 * (m + n)
+        return "hbm", per * launches, "CSR/CSC pass 12 nnz + 4(m+1) + 8(m+n) B"
+    if cls == "gram":
+        per = 12 * nnz + tri * (8 if cfg["u_q"] == "fp64" else 4)
+        return "hbm", per, "CSC read + Gram triangle write"
+    return None
+
+
+def roofline_of(cls, path, m, n, nnz, entry):
+    w = class_work(cls, path, m, n, nnz, entry["launches"])
+    if w is None:
+        return {"bound": "latency", "kernel": cls, "achieved": None, "peak": None, "unit": None,
+                "frac": None, "traffic": None, "avg_us": entry["avg_us"]}
+    bound, amount, what = w
+    peak, unit = PEAKS[bound]
+    secs = entry["ms_per_solve"] * 1e-3
+    achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
+    return {"bound": "hbm" if bound == "hbm" else "alu", "kernel": cls, "achieved": achieved,
+            "peak": peak, "unit": unit, "frac": achieved / peak, "traffic": None,
+            "avg_us": entry["avg_us"], "launches_per_solve": entry["launches"],
+            "work_per_launch": amount / max(entry["launches"], 1), "work": what}
 
 
 def cpu_baseline(A, b, seconds):
@@ -186,21 +239,16 @@ def main():
     prof = {p: kernel_profile(tls, torch, Ad, bd, p) for p in ("fp64", "mixed")}
     print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)
 
-    # dominant kernel class of the mixed path
+    # dominant kernel class of the mixed path, and every class's fraction
+    m, n, nnz = A.m, A.n, len(A.val)
     pm = prof["mixed"]
     dom = max(pm, key=lambda k: pm[k]["ms_per_solve"])
-    n = A.n
-    roof = None
-    if dom == "pcg_trsv":
-        per_launch = trsv_bytes(n, 2, nrhs=2, compute_bytes=4)
-        achieved = per_launch / (pm[dom]["avg_us"] * 1e-6) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_trsv (PCGTLS step, FP16 factor, FP32, 2 RHS)",
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": per_launch, "avg_us": pm[dom]["avg_us"]}
-    else:
-        roof = {"bound": "latency", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None, "avg_us": pm[dom]["avg_us"]}
+    roof = roofline_of(dom, "mixed", m, n, nnz, pm[dom])
+    for path in prof:
+        for cls, e in prof[path].items():
+            r = roofline_of(cls, path, m, n, nnz, e)
+            e["frac"] = r["frac"]
+            e["bound"] = r["bound"]
 
     cpu = None
     if not args.no_cpu:

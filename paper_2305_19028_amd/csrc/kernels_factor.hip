@@ -408,132 +408,167 @@ hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, 
 // blocked right-looking Cholesky, upper: G = R^T R, 64x64 tiles
 // --------------------------------------------------------------------------
 
-// Panel k of the blocked Cholesky. Every workgroup factors the diagonal tile
-// G(k, k) = R_kk^T R_kk itself (so no workgroup waits for another):
-// 256 threads hold 4x4 register blocks of the tile; step c publishes the
-// current row c through a double-buffered LDS row and eliminates with
-// G(r, c') -= G(c, r) G(c, c') / G(c, c) (rows kept unscaled, one barrier per
-// step); rows are scaled by 1/sqrt(pivot) at the end. Workgroup 0 writes
-// R_kk; workgroup j > 0 then solves R_kk^T Y = G(k, k+j) by forward
-// substitution in the same layout and writes Y = R(k, k+j).
-// (Measured alternatives: one wave with the tile in registers and fully
-// unrolled updates is instruction-fetch bound; one wave with the tile in
-// LDS is bound by the latency of its read-modify-write chain. The barrier
-// per step of this version costs about 160 ns.)
+// Panel k of the blocked Cholesky, one launch of N - k workgroups.
+// Workgroup j eliminates the augmented block [G(k,k) | G(k,k+j)] (j = 0: the
+// diagonal tile alone): the same elimination that turns G(k,k) into R(k,k)
+// turns the appended columns into R(k,k+j) = R(k,k)^{-T} G(k,k+j).
+// Thread (tr, tc) holds the 4x4 register blocks of rows 4tr.. and columns
+// 4tc.. of both tiles; the 16 threads of one row group are a quarter wave.
+// The 64 columns are taken four at a time. For group g the owning quarter
+// wave gathers the 4x4 diagonal block by cross-lane shuffles, factors it
+// (redundantly in each lane, so all lanes agree bit for bit), turns its
+// four rows into rows of R and publishes them in a double-buffered LDS slab;
+// after one barrier the rows below take the rank-4 update. One barrier per
+// four columns; the finished rows are staged in LDS and written coalesced.
 template <typename C>
 __global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *info) {
-  __shared__ C T[NB][NB + 1];
-  __shared__ C rowbuf[2][NB];
-  __shared__ C piv[NB];
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  __shared__ C stage[NB][NB + 1];
+  __shared__ C slab[2][4][2 * NB];
+  __shared__ int bad_s[2];   // per slab buffer, so a flag is never rewritten while still being read
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const int lane = tid & 63;
   const size_t base = (size_t)k * NB;
-  C v[4][4];
+  const bool has_b = blockIdx.x > 0;
+  const size_t cb = (size_t)(k + blockIdx.x) * NB;
+  if (tid < 2) bad_s[tid] = 0;
+  C tmp[16];   // all 16 loads of a thread in flight before the first wait
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int t = tid + 256 * i;
+    tmp[i] = G[(base + t / NB) * Np + base + t % NB];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int t = tid + 256 * i, r = t % NB, c = t / NB;
+    stage[r][c] = (r <= c) ? tmp[i] : (C)0;
+  }
+  if (has_b) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int t = tid + 256 * i;
+      tmp[i] = G[(cb + t / NB) * Np + base + t % NB];
+    }
+  }
+  __syncthreads();
+  C v[4][4], w[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int r = 4 * tr + x, c = 4 * tc + y;
-      v[x][y] = (r <= c) ? G[(base + c) * Np + base + r] : (C)0;
-    }
-  int bad = 0;
-  for (int c = 0; c < NB; ++c) {
-    const int buf = c & 1;
-    if (tr == (c >> 2)) {
-      const int x = c & 3;
+    for (int y = 0; y < 4; ++y) { v[x][y] = stage[4 * tr + x][4 * tc + y]; w[x][y] = (C)0; }
+  if (has_b) {
+    __syncthreads();
 #pragma unroll
-      for (int xx = 0; xx < 4; ++xx)
-        if (xx == x) {
-#pragma unroll
-          for (int y = 0; y < 4; ++y) rowbuf[buf][4 * tc + y] = v[xx][y];
-        }
+    for (int i = 0; i < 16; ++i) {
+      const int t = tid + 256 * i;
+      stage[t % NB][t / NB] = tmp[i];
     }
     __syncthreads();
-    const C p = rowbuf[buf][c];
-    if (!(p > (C)0)) { bad = c + 1; break; }
-    if (tid == 0) piv[c] = p;
-    const C ip = (C)1 / p;
-    C rr[4], rc[4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) { rr[x] = rowbuf[buf][4 * tr + x]; rc[x] = rowbuf[buf][4 * tc + x]; }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int r = 4 * tr + x, cc = 4 * tc + y;
-        if (r > c && cc >= r) v[x][y] -= rr[x] * rc[y] * ip;
+      for (int y = 0; y < 4; ++y) w[x][y] = stage[4 * tr + x][4 * tc + y];
+  }
+  __syncthreads();   // from here on `stage` collects the output tile
+  int bad = 0;
+  for (int g = 0; g < NB / 4; ++g) {
+    const int buf = g & 1;
+    if (tr == g) {
+      const int src = (lane & ~15) + g;      // lane holding the diagonal block
+      C d[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) d[x][y] = __shfl(v[x][y], src);
+      C rd[4][4], inv[4];
+      int badrow = 0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const C p = d[s][s];
+        if (!(p > (C)0) && !badrow) badrow = s + 1;
+        const C rs = sqrt(p);
+        inv[s] = (C)1 / rs;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) rd[s][t] = (t == s) ? rs : (t > s ? d[s][t] * inv[s] : (C)0);
+#pragma unroll
+        for (int s2 = s + 1; s2 < 4; ++s2)
+#pragma unroll
+          for (int t = s2; t < 4; ++t) d[s2][t] -= rd[s][s2] * rd[s][t];
       }
+      if (tc == g) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) v[x][y] = rd[x][y];
+      } else if (tc > g) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) v[s][y] *= inv[s];
+#pragma unroll
+          for (int s2 = s + 1; s2 < 4; ++s2)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) v[s2][y] -= rd[s][s2] * v[s][y];
+        }
+      } else {
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) v[x][y] = (C)0;
+      }
+      if (has_b) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) w[s][y] *= inv[s];
+#pragma unroll
+          for (int s2 = s + 1; s2 < 4; ++s2)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) w[s2][y] -= rd[s][s2] * w[s][y];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          slab[buf][s][4 * tc + y] = v[s][y];
+          slab[buf][s][NB + 4 * tc + y] = w[s][y];
+          stage[4 * g + s][4 * tc + y] = has_b ? w[s][y] : v[s][y];
+        }
+      if (badrow && tc == 0) bad_s[buf] = 4 * g + badrow;
+    }
+    __syncthreads();
+    bad = bad_s[buf];   // uniform: every thread reads the same LDS word after the barrier
+    if (bad) break;
+    if (tr > g) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        C rr[4], rc[4], rb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          rr[x] = slab[buf][s][4 * tr + x];
+          rc[x] = slab[buf][s][4 * tc + x];
+          rb[x] = slab[buf][s][NB + 4 * tc + x];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            v[x][y] -= rr[x] * rc[y];
+            w[x][y] -= rr[x] * rb[y];
+          }
+      }
+    }
   }
   if (bad) {
     if (tid == 0 && blockIdx.x == 0) atomicMin(info, k * NB + bad);
-    return;   // uniform: every thread read the same pivot
-  }
-  __syncthreads();
-  // R(r, c') = G(r, c') / sqrt(piv_r), R(r, r) = sqrt(piv_r)
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int r = 4 * tr + x;
-    const C sr = sqrt(piv[r]);
-    const C isr = (C)1 / sr;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int c = 4 * tc + y;
-      const C val = (c > r) ? v[x][y] * isr : (c == r ? sr : (C)0);
-      v[x][y] = val;
-      T[r][c] = val;
-    }
-  }
-  if (blockIdx.x == 0) {
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int r = 4 * tr + x, c = 4 * tc + y;
-        if (r <= c) G[(base + c) * Np + base + r] = v[x][y];
-      }
     return;
   }
   __syncthreads();
-  // forward substitution R_kk^T Y = B, B = G(k, jb) (rows of block k, columns of block jb)
-  const size_t cb = (size_t)(k + blockIdx.x) * NB;
-  C b[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) b[x][y] = G[(cb + 4 * tc + y) * Np + base + 4 * tr + x];
-  for (int i = 0; i < NB; ++i) {
-    const int buf = i & 1;
-    if (tr == (i >> 2)) {
-      const int x = i & 3;
-      const C id = (C)1 / T[i][i];
-#pragma unroll
-      for (int xx = 0; xx < 4; ++xx)
-        if (xx == x) {
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            b[xx][y] *= id;                      // Y(i, c') final
-            rowbuf[buf][4 * tc + y] = b[xx][y];
-          }
-        }
-    }
-    __syncthreads();
-    C yr[4], rt[4];
-#pragma unroll
-    for (int y = 0; y < 4; ++y) yr[y] = rowbuf[buf][4 * tc + y];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) rt[x] = T[i][4 * tr + x];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int r = 4 * tr + x;
-      if (r > i) {
-#pragma unroll
-        for (int y = 0; y < 4; ++y) b[x][y] -= rt[x] * yr[y];
-      }
-    }
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int r = t % NB, c = t / NB;
+    if (has_b) G[(cb + c) * Np + base + r] = stage[r][c];
+    else if (r <= c) G[(base + c) * Np + base + r] = stage[r][c];
   }
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) G[(cb + 4 * tc + y) * Np + base + 4 * tr + x] = b[x][y];
 }
 
 // trailing update G(i, j) -= R(k, i)^T R(k, j) for k < i <= j
@@ -549,10 +584,20 @@ __global__ __launch_bounds__(256) void k_chol_update(int k, int N, int Np, C *G)
   const int i = k + 1 + a, j = k + 1 + b;
   const int tid = threadIdx.x;
   const size_t base = (size_t)k * NB;
-  for (int t = tid; t < NB * NB; t += blockDim.x) {
-    const int r = t % NB, c = t / NB;
-    Ri[r][c] = G[((size_t)i * NB + c) * Np + base + r];
-    Rj[r][c] = G[((size_t)j * NB + c) * Np + base + r];
+  {
+    C ti[16], tj[16];   // all 32 loads in flight before the first wait
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, r = t % NB, c = t / NB;
+      ti[q] = G[((size_t)i * NB + c) * Np + base + r];
+      tj[q] = G[((size_t)j * NB + c) * Np + base + r];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, r = t % NB, c = t / NB;
+      Ri[r][c] = ti[q];
+      Rj[r][c] = tj[q];
+    }
   }
   __syncthreads();
   const int tr = tid & 15, tc = tid >> 4;

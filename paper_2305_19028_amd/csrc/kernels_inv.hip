@@ -61,18 +61,35 @@ __global__ __launch_bounds__(256) void k_inv_init(int N, const S *Rt, const doub
   }
 }
 
-// 64x64x64 FP64 tile product accumulated by 256 threads (4x4 outputs each):
-// acc += A_tile * B_tile, both column-major in global memory
-__device__ inline void tile_mac(const double *A, const double *B, double (*As)[NB + 1],
-                                double (*Bs)[NB + 1], double acc[4][4]) {
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += 256) {
-    const int r = t % NB, c = t / NB;
-    As[r][c] = A[t];
-    Bs[r][c] = B[t];
+// 64x64x64 FP64 tile products accumulated by 256 threads (4x4 outputs
+// each). The operand tiles (column-major in global memory) travel through
+// registers: the loads of product k+1 are in flight while product k runs
+// from LDS, so each product costs one memory latency at most once.
+struct TileRegs {
+  double a[16], b[16];
+};
+__device__ inline void tile_fetch(const double *A, const double *B, TileRegs &R) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    R.a[i] = A[tid + 256 * i];
+    R.b[i] = B[tid + 256 * i];
+  }
+}
+__device__ inline void tile_stage(const TileRegs &R, double (*As)[NB + 1], double (*Bs)[NB + 1]) {
+  const int tid = threadIdx.x;
+  __syncthreads();   // the previous product has finished reading LDS
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int t = tid + 256 * i, r = t % NB, c = t / NB;
+    As[r][c] = R.a[i];
+    Bs[r][c] = R.b[i];
   }
   __syncthreads();
+}
+__device__ inline void tile_fma(const double (*As)[NB + 1], const double (*Bs)[NB + 1],
+                                double acc[4][4]) {
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
 #pragma unroll 4
   for (int k = 0; k < NB; ++k) {
     double a[4], b[4];
@@ -95,10 +112,14 @@ __global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, do
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;      // partial pair at the end (uniform)
   double acc[4][4] = {};
-  for (int k = 0; k <= b; ++k) {
-    if (J0 + k >= N) break;
-    tile_mac(W + up_tile(I0 + a, J0 + k) * NB * NB, W + up_tile(J0 + k, J0 + b) * NB * NB, As,
-             Bs, acc);
+  const int kend = b;                           // J0 + b < N, so every k <= b is in range
+  TileRegs R;
+  tile_fetch(W + up_tile(I0 + a, J0) * NB * NB, W + up_tile(J0, J0 + b) * NB * NB, R);
+  for (int k = 0; k <= kend; ++k) {
+    tile_stage(R, As, Bs);
+    if (k < kend)
+      tile_fetch(W + up_tile(I0 + a, J0 + k + 1) * NB * NB, W + up_tile(J0 + k + 1, J0 + b) * NB * NB, R);
+    tile_fma(As, Bs, acc);
   }
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
   double *dst = Y + ((size_t)pair * per + rem) * NB * NB;
@@ -117,10 +138,14 @@ __global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, co
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;
   double acc[4][4] = {};
-  for (int k = a; k < hb; ++k) {
-    if (I0 + k >= N) break;
-    tile_mac(W + up_tile(I0 + a, I0 + k) * NB * NB, Y + ((size_t)pair * per + b * hb + k) * NB * NB,
-             As, Bs, acc);
+  const int kend = hb - 1;                      // I0 + k < J0 < N for every k < hb
+  TileRegs R;
+  auto yt = [&](int k) { return Y + ((size_t)pair * per + b * hb + k) * NB * NB; };
+  tile_fetch(W + up_tile(I0 + a, I0 + a) * NB * NB, yt(a), R);
+  for (int k = a; k <= kend; ++k) {
+    tile_stage(R, As, Bs);
+    if (k < kend) tile_fetch(W + up_tile(I0 + a, I0 + k + 1) * NB * NB, yt(k + 1), R);
+    tile_fma(As, Bs, acc);
   }
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
   double *dst = W + up_tile(I0 + a, J0 + b) * NB * NB;
@@ -241,6 +266,58 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
   C *p_cur = (P.j & 1) ? P.pb1 : P.pb0;
   C *p_old = (P.j & 1) ? P.pb0 : P.pb1;
 
+  // ---- every global read that does not depend on another is issued first,
+  // so that the whole prologue costs one memory round trip ------------------
+  // (a) this wave's tile: one tile per wave (chunk <= 4); lane = tile row
+  const int K_lo = TRANS ? 0 : I;               // input blocks feeding output block I
+  const int K_hi = TRANS ? I + 1 : N;
+  const int K = K_lo + sidx * P.chunk + w;
+  const bool has_tile = (w < P.chunk) && (K < K_hi);
+  SX t[NB];
+  if (has_tile) {
+    const SX *T = P.X + (TRANS ? xc_tile(I, K) : xr_tile(I, K, N)) * NB * NB + (size_t)lane * NB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) t[c] = T[c];
+  }
+  // (b) the inputs of block K (combined with the step scalars below)
+  const int row = K * NB + lane;
+  C in_a[NR], in_b[NR], in_ds = (C)0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { in_a[r] = (C)0; in_b[r] = (C)0; }
+  if (has_tile) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const size_t vi = (size_t)r * Np + row;
+      if constexpr (MODE == XA || MODE == XF0) {
+        in_a[r] = (row < P.n) ? (C)P.in[(size_t)r * P.ldi + row] : (C)0;
+      } else if constexpr (MODE == XB) {
+        if (P.j > 0) { in_a[r] = P.s[vi]; in_b[r] = p_old[vi]; }
+        else in_a[r] = p_cur[vi];
+      } else {
+        in_a[r] = P.q[vi];
+      }
+    }
+    if constexpr (TRANS) in_ds = P.dscale[row];
+  }
+  // (c) the rows of output block I that the epilogue needs (wave 0)
+  const int orow = I * NB + lane;
+  C e_s[NR], e_p[NR], e_po[NR], e_q[NR], e_w[NR], e_ds = (C)0;
+  if (w == 0) {
+    if constexpr (!TRANS) e_ds = P.dscale[orow];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const size_t vi = (size_t)r * Np + orow;
+      e_s[r] = e_p[r] = e_po[r] = e_q[r] = e_w[r] = (C)0;
+      if constexpr (MODE == XB) {
+        e_p[r] = p_cur[vi];
+        if (P.j > 0) { e_s[r] = P.s[vi]; e_po[r] = p_old[vi]; }
+      } else if constexpr (MODE == XF) {
+        e_s[r] = P.s[vi]; e_p[r] = p_cur[vi]; e_q[r] = P.q[vi]; e_w[r] = P.w[vi];
+      }
+    }
+  }
+  // (d) convergence flags of the previous step and the step scalars
+  //     (recomputed identically by every workgroup)
   if (tid == 0) {
     int all_done = 1;
     for (int r = 0; r < NR; ++r) {
@@ -255,12 +332,8 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
         for (int r = 0; r < NR; ++r) P.done[P.j * NR + r] = 1;
     }
   }
-  __syncthreads();
-  if (s_skip) return;   // uniform for the whole grid
-
-  // ---- step scalars (recomputed identically by every workgroup) -----------
   if constexpr (MODE == XB || MODE == XF) {
-    if (w == 0) {
+    if (w == 1) {
       for (int r = 0; r < NR; ++r) {
         const C eta = xsum_parts(xpart_ptr(P.part, P.j, 0, r, NR, N), N);
         if constexpr (MODE == XB) {
@@ -278,49 +351,33 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (s_skip) return;   // uniform for the whole grid
 
-  // ---- tiles of this chunk: wave w takes tiles w, w+4, ... ---------------
-  const int K_lo = TRANS ? 0 : I;               // input blocks feeding output block I
-  const int K_hi = TRANS ? I + 1 : N;
-  const int k0 = K_lo + sidx * P.chunk;
-  const int k1 = min(K_hi, k0 + P.chunk);
+  // ---- the tile product ----------------------------------------------------
   C acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0;
-  for (int K = k0 + w; K < k1; K += 4) {
-    // input block K (prologue transform), staged in this wave's LDS slot
-    const int row = K * NB + lane;
+  if (has_tile) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       C v;
-      const size_t vi = (size_t)r * Np + row;
-      if constexpr (MODE == XA) {
-        const C iv = (row < P.n) ? (C)P.in[(size_t)r * P.ldi + row] : (C)0;
-        v = TRANS ? P.dscale[row] * iv : iv;
-      } else if constexpr (MODE == XF0) {
-        v = (row < P.n) ? P.dscale[row] * (C)P.in[(size_t)r * P.ldi + row] : (C)0;
-      } else if constexpr (MODE == XB) {
-        v = (P.j > 0) ? P.s[vi] + s_scal[r][1] * p_old[vi] : p_cur[vi];
-      } else {
-        v = P.dscale[row] * P.q[vi];
-      }
+      if constexpr (MODE == XA) v = TRANS ? in_ds * in_a[r] : in_a[r];
+      else if constexpr (MODE == XF0) v = in_ds * in_a[r];
+      else if constexpr (MODE == XB) v = (P.j > 0) ? in_a[r] + s_scal[r][1] * in_b[r] : in_a[r];
+      else v = in_ds * in_a[r];
       s_v[w][r][lane] = v;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const SX *T = P.X + (TRANS ? xc_tile(I, K) : xr_tile(I, K, N)) * NB * NB + (size_t)lane * NB;
-#pragma unroll 8
-    for (int c = 0; c < NB; ++c) {
-      const C t = cvt<C>(T[c]);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] += t * s_v[w][r][c];
+    for (int c = 0; c < NB; ++c) {
+      const C tc = cvt<C>(t[c]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += tc * s_v[w][r][c];
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) s_acc[w][r][lane] = acc[r];
@@ -362,13 +419,12 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
   if (w != 0) return;
 
   // ---- epilogue (wave 0, lane = row of block I) --------------------------
-  const int row = I * NB + lane;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const C x = res[r];
-    const size_t vi = (size_t)r * Np + row;
+    const size_t vi = (size_t)r * Np + orow;
     if constexpr (MODE == XA) {
-      if (row < P.n) P.out[(size_t)r * P.ldo + row] = (double)(TRANS ? x : P.dscale[row] * x);
+      if (orow < P.n) P.out[(size_t)r * P.ldo + orow] = (double)(TRANS ? x : e_ds * x);
     } else if constexpr (MODE == XF0) {
       P.s[vi] = x;
       P.pb0[vi] = x;
@@ -376,9 +432,9 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
       const C ss = wave_sum(x * x);
       if (lane == 0) xpart_ptr(P.part, 0, 0, r, NR, N)[I] = ss;
     } else if constexpr (MODE == XB) {
-      const C qv = P.dscale[row] * x;                 // q = D^{-1} X p
-      C pv = p_cur[vi];
-      if (P.j > 0) pv = P.s[vi] + s_scal[r][1] * p_old[vi];
+      const C qv = e_ds * x;                          // q = D^{-1} X p
+      C pv = e_p[r];
+      if (P.j > 0) pv = e_s[r] + s_scal[r][1] * e_po[r];
       if (s_live[r]) {
         P.q[vi] = qv;
         if (P.j > 0) p_cur[vi] = pv;
@@ -390,10 +446,10 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
       }
     } else {   // XF: x = t = X^T D^{-1} q
       const C delta = s_scal[r][1];
-      C sv = P.s[vi];
+      C sv = e_s[r];
       if (s_live[r] && delta != (C)0) {
-        P.w[vi] += s_scal[r][2] * P.q[vi];                        // omega_{j+1}
-        sv = sv - s_scal[r][2] * (p_cur[vi] - s_scal[r][3] * x);  // s_{j+1}
+        P.w[vi] = e_w[r] + s_scal[r][2] * e_q[r];                 // omega_{j+1}
+        sv = sv - s_scal[r][2] * (e_p[r] - s_scal[r][3] * x);     // s_{j+1}
         P.s[vi] = sv;
       }
       const C ss = wave_sum(sv * sv);
