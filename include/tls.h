@@ -113,6 +113,11 @@ typedef struct {
 
 #define TLS_MAX_ITERS 256
 
+/* Warm-start network (a project addition; see tls_mlp_forward). */
+#define TLS_MLP_IN 32
+#define TLS_MLP_WIDTH 256
+#define TLS_MLP_PARAMS 140289   /* 32*256+256 + 2*(256*256+256) + 256+1 */
+
 /* Options of tls_rqi_solve. tls_default_opts() fills the plain FP64 path. */
 typedef struct {
   int32_t u_p;             /* tls_prec of PCGTLS: TLS_FP64 or TLS_FP32            */
@@ -129,10 +134,15 @@ typedef struct {
                               earlier once r^T M r has fallen by 1e-26)           */
   int32_t allow_escalate;  /* raise u_q when the b-dependent gate (6) fails       */
   int32_t gate_enforce;    /* 1: run the b-dependent gate                         */
-  int32_t reserved;
+  int32_t features;        /* 1: compute the warm-start features (stats.features)
+                              even when no warm start is requested                */
   double shift_clamp_tau;  /* tau of the clamp (0 < tau < 1)                       */
-  double sigma0_hint;      /* warm start: initial shift sigma (<= 0: none)         */
+  double sigma0_hint;      /* warm start from a given shift estimate sigma_hat
+                              (<= 0: none; ignored when mlp_theta is set)         */
   double *x_snapshots;     /* device, optional (kmax * n): x_k at each psi_k       */
+  const float *mlp_theta;  /* device, optional: warm-start network parameters
+                              (TLS_MLP_PARAMS floats); NULL = plain LS start      */
+  const float *mlp_norm;   /* device: input standardisation [mean(32), scale(32)] */
 } tls_rqi_opts;
 
 /* Per-call record of the iteration (host). */
@@ -152,6 +162,9 @@ typedef struct {
   double t_factor_ms;      /* time in escalation refactoring, if any               */
   double t_total_ms;
   double sigma_final;      /* sigma after the compensated residual                 */
+  double sigma_hat;        /* warm-start shift estimate (0 when none)              */
+  double psi_warm, psi_plain; /* psi at the warm and at the plain x_1 (warm start)  */
+  float features[TLS_MLP_IN]; /* warm-start features (when computed)              */
 } tls_rqi_stats;
 
 /* ---------------------------------------------------------------------------
@@ -249,7 +262,43 @@ TLS_API size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P,
 /* Solve the TLS problem for (A, b) with the preconditioner P built from the
  * same A. x (device, n, out) receives the iterate with the smallest psi (or
  * the refined one), *sigma (host) sigma_{n+1} from a compensated residual.
- * opts and stats are host structures (stats may be NULL). */
+ * opts and stats are host structures (stats may be NULL).
+ *
+ * Warm start (project addition; opts.mlp_theta or opts.sigma0_hint). After
+ * x_0 = x_LS, u_0 = (R^T R)^{-1} x_0 and sigma_0 (the quantities of the
+ * initial step of Algorithm 2), u_1 = (R^T R)^{-1} u_0 is formed and the
+ * shift estimate lam = sigma_hat^2 of sigma_{n+1}^2 gives the candidate
+ *   x_1w = x_0 + lam u_0 + lam^2 u_1
+ * (the second-order truncation of x_TLS = (I - lam (A^T A)^{-1})^{-1} x_LS).
+ * psi (eq. 4) is evaluated at x_1w and at the plain x_1 = x_0 + sigma_0^2 u_0;
+ * the iteration starts from the one with the smaller psi (stats.warm_used).
+ * The estimate of y = ln(1 - sigma_{n+1}^2 / sigma_0^2), the log of the
+ * relative gap between the least-squares estimate and the answer, is
+ * y_hat = feature 31 + net(features): a quadrature estimate of the gap
+ * corrected by the network's output. Then sigma_hat^2 = sigma_0^2 (1 - exp(min(y_hat, 0))),
+ * further clamped, with the shift clamp on, to tau times the sigma'_n
+ * estimate squared.
+ *
+ * Features (stats.features, FP32, natural logarithms), from xx = x_0^T x_0,
+ * xu = x_0^T u_0, uu = u_0^T u_0, uv = u_0^T u_1, vv = u_1^T u_1,
+ * rr = ||b - A x_0||^2, t = sigma_0^2 xu / (1 + xx), the Ritz values
+ * th_max >= th_min of (R^T R)^{-1} on span{x_0, u_0}, and d_j = ||A e_j||:
+ *   0 ln m          1 ln n           2 ln ||A||_F     3 ln ||b||
+ *   4 ln ||A^T b||  5 ln sigma_0     6 ln ||x_0||     7 ln ||r_0||
+ *   8 ln(||r_0||/||b||)              9 ln t           10 ln(sqrt(uu/xx))
+ *   11 -ln(th_max)/2  12 -ln(th_min)/2  13 ln sigma_0 + ln(th_max)/2
+ *   14 sigma_0^2 th_max               15 t / (1 + t)
+ *   16..19 min, max, mean, standard deviation of ln d_j
+ *   20 ln(||A^T b|| / (||A||_F ||b||))  21 ln(1 + xx)  22 ln(uv xx / (xu uu))
+ *   23 ln(uu xx / xu^2)  24 ln(||A||_F / sqrt(n)) - ln sigma_0
+ *   25 ln(||b|| / sqrt(m))  26 ln(th_max / th_min) / 2
+ *   27 ln(sigma_0^2 uv / uu)  28 ln(sigma_0^2 sqrt(vv / uu))
+ *   29 ln(sigma_0^4 vv / xx) / 2  30 1
+ *   31 ln(gap_G), gap_G = max(1 - lam_G / sigma_0^2, 1e-13), where lam_G solves
+ *      lam (1 + q(lam)) = ||r_0||^2 (the secular form of eq. 2) with the
+ *      quadratic form q(lam) = x_0^T (I - lam (A^T A)^{-1})^{-1} x_0 replaced
+ *      by its two-point Gauss rule from two Lanczos steps on (R^T R)^{-1}
+ *      started at x_0 (it uses the moments xx, xu, uu, uv) */
 TLS_API tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P,
                          const tls_rqi_opts *opts, double *x, double *sigma,
                          tls_rqi_stats *stats, void *ws, size_t ws_bytes,
@@ -261,14 +310,42 @@ TLS_API tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_preco
 TLS_API tls_status tls_round(const double *in, int64_t count, int32_t prec, double *out,
                              hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Warm-start network (project addition, not in the paper): 32 -> 256 -> 256
+ * -> 256 -> 1, exact GELU after each hidden layer, FP32, on the device.
+ * theta: TLS_MLP_PARAMS floats, per layer W (out x in, row-major) then the
+ * bias; norm: 64 floats [mean(32), scale(32)], inputs are (x - mean) * scale.
+ * X: batch x 32 row-major. All arrays are device arrays owned by the caller;
+ * the workspace (256-byte aligned) holds the batch activations. Results are
+ * bitwise reproducible (fixed-order reductions).
+ * ------------------------------------------------------------------------- */
+TLS_API size_t tls_mlp_workspace_size(int64_t batch);
+
+/* y (batch) = network(X). */
+TLS_API tls_status tls_mlp_forward(const float *theta, const float *norm, const float *X,
+                                   int64_t batch, float *y, void *ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* Mean squared error L = mean_b (y_b - t_b)^2 and its gradient: *loss
+ * (device, 1 float), grad (device, TLS_MLP_PARAMS floats, overwritten). */
+TLS_API tls_status tls_mlp_loss_grad(const float *theta, const float *norm, const float *X,
+                                     const float *t, int64_t batch, float *grad, float *loss,
+                                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam update (Kingma & Ba, Algorithm 1) of count parameters at step
+ * number step >= 1: m, v (device) are the moment estimates, updated in place. */
+TLS_API tls_status tls_mlp_adam(float *theta, float *m, float *v, const float *grad,
+                                int64_t count, int64_t step, float lr, float beta1, float beta2,
+                                float eps, hipStream_t stream);
+
 /* Kernel-class timing. While profiling is on, the library records a pair of
  * HIP events on the caller's stream around every kernel it launches and
  * accumulates the elapsed time per kernel class. Process-wide state, not
  * thread-safe; meant for benchmarks. Classes (index: name):
  *   0 precond_apply  1 pcg_step  2 gram  3 chol_panel  4 chol_update
  *   5 residual  6 gradient  7 outer_scalars  8 setup  9 lanczos
- *   10 pack  11 residual_dd  12 invert */
-#define TLS_PROF_CLASSES 13
+ *   10 pack  11 residual_dd  12 invert  13 mlp */
+#define TLS_PROF_CLASSES 14
 typedef struct {
   int32_t launches[TLS_PROF_CLASSES];
   double total_ms[TLS_PROF_CLASSES];

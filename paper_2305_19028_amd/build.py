@@ -21,7 +21,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtls.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["tls_api.hip", "kernels_trsv.hip", "kernels_factor.hip", "kernels_rqi.hip",
+SOURCES = ["tls_api.hip", "kernels_trsv.hip", "kernels_factor.hip", "kernels_rqi.hip", "kernels_mlp.hip",
            "kernels_inv.hip"]
 
 FLAGS = [

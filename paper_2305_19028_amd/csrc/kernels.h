@@ -12,7 +12,8 @@ namespace tls {
 
 // kernel classes of the profiling hooks (order as in tls.h)
 enum ProfClass { PC_TRSV_APPLY = 0, PC_PCG, PC_GRAM, PC_CHOL_PANEL, PC_CHOL_UPDATE, PC_RESIDUAL,
-                 PC_GRADIENT, PC_SCALARS, PC_SETUP, PC_LANCZOS, PC_PACK, PC_RESID_DD, PC_INVERT };
+                 PC_GRADIENT, PC_SCALARS, PC_SETUP, PC_LANCZOS, PC_PACK, PC_RESID_DD, PC_INVERT,
+                 PC_MLP };
 // no-ops unless profiling is on (see tls_profile_start)
 void prof_begin(int cls, hipStream_t st);
 void prof_end(hipStream_t st);
@@ -155,5 +156,31 @@ hipError_t launch_ref_step2(int n, int nrhs, const double *r, const double *z, d
                             int first, hipStream_t st);
 hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, double *scal,
                            hipStream_t st);
+
+// ---- warm start (kernels_rqi.hip) ---------------------------------------------
+struct DotPairs {
+  static constexpr int MAX = 8;
+  const double *a[MAX], *b[MAX];
+  int64_t len[MAX];
+};
+hipError_t launch_dots(const DotPairs &D, int count, double *out, hipStream_t st);
+hipError_t launch_axpy2(int n, const double *x0, const double *u0, const double *u1, double c1,
+                        double c2, double *out, hipStream_t st);
+// ---- kernels_mlp.hip --------------------------------------------------------
+// activations of a training batch of B samples (row-major, B x width)
+struct MlpBufs {
+  float *h0;              // standardised inputs, B x 32
+  float *z[3], *h[3];     // hidden pre-activations and GELU outputs, B x 256
+  float *dz[2];           // gradients w.r.t. pre-activations (ping-pong), B x 256
+  float *dy;              // dL/dy, B
+};
+hipError_t launch_mlp_forward(const float *theta, const float *norm, const float *X, int64_t B,
+                              float *y, const MlpBufs &M, hipStream_t st);
+hipError_t launch_mlp_backward(const float *theta, const float *y, const float *t, int64_t B,
+                               float *grad, float *loss, const MlpBufs &M, hipStream_t st);
+hipError_t launch_mlp_adam(int64_t count, float *theta, float *m, float *v, const float *g, float lr,
+                           float b1, float b2, float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_infer1(const float *theta, const float *norm, const float *feat, double *y,
+                             hipStream_t st);
 
 }  // namespace tls

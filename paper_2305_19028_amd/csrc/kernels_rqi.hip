@@ -614,3 +614,38 @@ hipError_t launch_ref_step2(int n, int nrhs, const double *r, const double *z, d
 }
 
 }  // namespace tls
+
+namespace tls {
+
+// ---------------------------------------------------------------------------
+// warm start: dot products (one workgroup per pair, fixed order) and
+// x_w = x_0 + c1 u_0 + c2 u_1
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dots(DotPairs D, double *out) {
+  __shared__ double sc[4];
+  const int p = blockIdx.x;
+  const double *a = D.a[p], *b = D.b[p];
+  const int64_t len = D.len[p];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += 256) s = fma(a[i], b[i], s);
+  s = block_sum(s, sc);
+  if (threadIdx.x == 0) out[p] = s;
+}
+hipError_t launch_dots(const DotPairs &D, int count, double *out, hipStream_t st) {
+  if (count <= 0 || count > DotPairs::MAX) return hipErrorInvalidValue;
+  TLS_LAUNCH(PC_SCALARS, k_dots, dim3(count), dim3(256), 0, st, D, out);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy2(int n, const double *x0, const double *u0, const double *u1, double c1,
+                        double c2, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x0[i] + (c1 * u0[i] + c2 * u1[i]);
+}
+hipError_t launch_axpy2(int n, const double *x0, const double *u0, const double *u1, double c1,
+                        double c2, double *out, hipStream_t st) {
+  TLS_LAUNCH(PC_SCALARS, k_axpy2, dim3((n + 255) / 256), dim3(256), 0, st, n, x0, u0, u1, c1, c2, out);
+  return hipGetLastError();
+}
+
+}  // namespace tls

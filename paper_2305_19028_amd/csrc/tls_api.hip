@@ -106,6 +106,7 @@ struct tls_precond_s {
   int have_sigma_n = 0, have_kappa = 0;
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
   double normA_F2 = 0;             // ||A||_F^2 = sum_j d_j^2
+  double lnd[4] = {0, 0, 0, 0};    // min, max, mean, std of ln d_j (warm-start features)
   FactorView view() const {
     FactorView F;
     F.n = (int)n;
@@ -465,6 +466,9 @@ void tls_default_opts(tls_rqi_opts *o) {
   o->shift_clamp_tau = 0.9;
   o->sigma0_hint = -1.0;
   o->x_snapshots = nullptr;
+  o->features = 0;
+  o->mlp_theta = nullptr;
+  o->mlp_norm = nullptr;
 }
 
 size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q) {
@@ -731,6 +735,16 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
     HIPCHK(hipStreamSynchronize(stream));
     if (flag) return fail(TLS_ERR_NONFINITE, "A contains NaN or Inf");
     for (double v : dh) P->normA_F2 += v * v;
+    {
+      double lo = INFINITY, hi = -INFINITY, sum = 0, sq = 0;
+      for (double v : dh) {
+        const double l = std::log(std::max(v, 1e-300));
+        lo = std::min(lo, l); hi = std::max(hi, l); sum += l; sq += l * l;
+      }
+      const double mean = sum / n;
+      P->lnd[0] = lo; P->lnd[1] = hi; P->lnd[2] = mean;
+      P->lnd[3] = std::sqrt(std::max(0.0, sq / n - mean * mean));
+    }
     int uq = u_q;
     for (;;) {
       int bd = 0;
@@ -932,7 +946,7 @@ RqiWs carve_rqi(Carver &c, int64_t m, int64_t n, const tls_precond_s *P, int kma
   W.t1 = c.take<double>(n);
   W.t2 = c.take<double>(n);
   W.part = c.take<double>(2 * (size_t)nb);
-  W.scal = c.take<double>(32);
+  W.scal = c.take<double>(48);
   W.rec = c.take<double>(4 * (size_t)(kmax + 8));
   W.rr = c.take<double>(2 * n);
   W.rz = c.take<double>(2 * n);
@@ -950,6 +964,102 @@ tls_status solve_normal(const tls_precond_s *P, const double *v, double *x, doub
   TRY(apply_R(P, 1, 1, v, tmp, TLS_FP64, W, st));
   TRY(apply_R(P, 0, 1, tmp, x, TLS_FP64, W, st));
   return TLS_OK;
+}
+
+struct WarmScalars {
+  double m, n, nA2, bb, atb2, s0, xx, rr, xu, uu, uv, vv;
+  double lnd[4];
+};
+
+// Relative gap 1 - lam / sigma_0^2 from the secular equation of f = 0, g = 0
+// (eq. 2) in its form lam (1 + x_0^T (I - lam M)^{-1} x_0) = ||r_0||^2,
+// M = (A^T A)^{-1}, with the quadratic form replaced by its two-point Gauss
+// rule from the Lanczos process on M started at x_0 (moments xx, xu, uu, uv).
+// Floored at 1e-13 (relative gaps below are rounding).
+double gauss_gap(const WarmScalars &w) {
+  const double floor_gap = 1e-13;
+  if (!(w.xx > 0) || !(w.xu > 0) || !(w.rr > 0)) return floor_gap;
+  const double a1 = w.xu / w.xx;
+  const double b2 = w.uu / w.xx - a1 * a1;
+  double th[2] = {a1, a1}, om[2] = {w.xx, 0.0};
+  if (b2 > 1e-12 * a1 * a1) {
+    const double a2 = (w.uv - 2.0 * a1 * w.uu + a1 * a1 * w.xu) / (w.xx * b2);
+    // eigenpairs of [a1 b; b a2], b = sqrt(b2)
+    const double mean = 0.5 * (a1 + a2), half = 0.5 * (a1 - a2);
+    const double rad = std::sqrt(half * half + b2);
+    th[0] = mean + rad;
+    th[1] = mean - rad;
+    for (int j = 0; j < 2; ++j) {
+      // eigenvector (b, th - a1) normalised; weight xx * (first component)^2
+      const double z0 = std::sqrt(b2), z1 = th[j] - a1;
+      om[j] = w.xx * z0 * z0 / (z0 * z0 + z1 * z1);
+    }
+  }
+  const double thmax = std::max(th[0], th[1]);
+  auto h = [&](double lam) {
+    double y = 0.0;
+    for (int j = 0; j < 2; ++j) y += om[j] / (1.0 - lam * th[j]);
+    return lam * (1.0 + y) - w.rr;
+  };
+  double lo = 0.0, hi = std::min(w.rr, thmax > 0 ? 1.0 / thmax : w.rr);
+  for (int it = 0; it < 200 && hi > lo; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (h(mid) > 0) hi = mid; else lo = mid;
+  }
+  const double s02 = w.rr / (1.0 + w.xx);
+  const double gap = 1.0 - 0.5 * (lo + hi) / s02;
+  return std::max(gap, floor_gap);
+}
+
+// the 32 warm-start features (definitions in the tls_rqi_solve comment of tls.h)
+void warm_features(const WarmScalars &w, float *f) {
+  auto L = [](double v) { return std::log(std::max(v, 1e-300)); };
+  const double s02 = w.s0 * w.s0;
+  const double t = s02 * w.xu / (1.0 + w.xx);
+  // Ritz values of (R^T R)^{-1} on span{x_0, u_0}: det(K - th G) = 0 with
+  // G = [xx xu; xu uu], K = [xu uu; uu uv]
+  const double a2 = w.xx * w.uu - w.xu * w.xu;
+  const double a1 = w.xx * w.uv - w.xu * w.uu;
+  const double a0 = w.xu * w.uv - w.uu * w.uu;
+  double thmax = w.xu / std::max(w.xx, 1e-300), thmin = thmax;
+  if (a2 > 1e-12 * w.xx * w.uu) {
+    const double disc = std::sqrt(std::max(0.0, a1 * a1 - 4.0 * a2 * a0));
+    thmax = (a1 + disc) / (2.0 * a2);
+    thmin = (a1 - disc) / (2.0 * a2);
+    if (!(thmin > 0)) thmin = std::min(thmax, w.xu / std::max(w.xx, 1e-300));
+  }
+  double v[TLS_MLP_IN];
+  v[0] = L(w.m);
+  v[1] = L(w.n);
+  v[2] = 0.5 * L(w.nA2);
+  v[3] = 0.5 * L(w.bb);
+  v[4] = 0.5 * L(w.atb2);
+  v[5] = L(w.s0);
+  v[6] = 0.5 * L(w.xx);
+  v[7] = 0.5 * L(w.rr);
+  v[8] = v[7] - v[3];
+  v[9] = L(t);
+  v[10] = 0.5 * L(w.uu / std::max(w.xx, 1e-300));
+  v[11] = -0.5 * L(thmax);
+  v[12] = -0.5 * L(thmin);
+  v[13] = v[5] - v[11];
+  v[14] = s02 * thmax;
+  v[15] = t / (1.0 + t);
+  for (int i = 0; i < 4; ++i) v[16 + i] = w.lnd[i];
+  v[20] = v[4] - v[2] - v[3];
+  v[21] = std::log1p(w.xx);
+  v[22] = L(w.uv * w.xx / std::max(w.xu * w.uu, 1e-300));
+  v[23] = L(w.uu * w.xx / std::max(w.xu * w.xu, 1e-300));
+  v[24] = v[2] - 0.5 * v[1] - v[5];
+  v[25] = v[3] - 0.5 * v[0];
+  v[26] = 0.5 * L(thmax / std::max(thmin, 1e-300));
+  v[27] = L(s02 * w.uv / std::max(w.uu, 1e-300));
+  v[28] = L(s02 * std::sqrt(w.vv / std::max(w.uu, 1e-300)));
+  v[29] = 0.5 * L(s02 * s02 * w.vv / std::max(w.xx, 1e-300));
+  v[30] = 1.0;
+  v[31] = std::log(gauss_gap(w));
+  for (int i = 0; i < TLS_MLP_IN; ++i) f[i] = (float)v[i];
 }
 
 }  // namespace
@@ -983,6 +1093,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     if (o->stop_patience < 1) return fail(TLS_ERR_ARG, "stop_patience must be >= 1");
     if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return fail(TLS_ERR_ARG, "refine_sweeps must be in [0, 4]");
     if (o->refine_sweeps > 0 && o->refine_pcg_steps < 1) return fail(TLS_ERR_ARG, "refine_pcg_steps must be >= 1");
+    if (o->mlp_theta && !o->mlp_norm) return fail(TLS_ERR_ARG, "mlp_theta needs mlp_norm");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     const size_t need = tls_rqi_workspace_size(A, P, o);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "RQI workspace %zu < %zu bytes", ws_bytes, need);
@@ -999,7 +1110,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     std::memset(&S, 0, sizeof S);
 
     TRY(reset_solve_ws(P, W.pcg, st));
-    HIPCHK(launch_fill_f64(W.scal, 0.0, 32, st));
+    HIPCHK(launch_fill_f64(W.scal, 0.0, 48, st));
     // finite b
     HIPCHK(launch_fill_i32(W.pcg.done, 0, 1, st));
     HIPCHK(launch_check_finite(b, (size_t)A->m, W.pcg.done, st));
@@ -1009,18 +1120,26 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     if (bad) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
 
     // one Rayleigh-quotient evaluation at x (residual pass, scalars, gradient pass, psi)
-    auto evaluate = [&](int k, double cap) -> tls_status {
+    auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
       HIPCHK(launch_fill_f64(W.scal + 14, cap, 1, st));
-      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
-      HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, cap, st));
-      HIPCHK(launch_gradient(V, W.r, x, W.scal, W.f, W.part, st));
-      HIPCHK(launch_outer_psi(n, x, W.f, W.part, nb_f, W.scal, k, W.rec, st));
+      HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
+      HIPCHK(launch_outer_rq(n, xv, W.part, nb_r, W.scal, cap, st));
+      HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, W.part, st));
+      HIPCHK(launch_outer_psi(n, xv, W.f, W.part, nb_f, W.scal, k, W.rec, st));
       return TLS_OK;
     };
+    auto evaluate = [&](int k, double cap) -> tls_status { return evaluate_at(x, k, cap); };
 
     // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1; the b-dependent gate ---
+    double rr0 = 0.0;
     for (;;) {
       HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
+      if (o->mlp_theta || o->sigma0_hint > 0 || o->features) {
+        DotPairs D{};
+        D.a[0] = D.b[0] = b; D.len[0] = m;
+        D.a[1] = D.b[1] = W.t1; D.len[1] = n;
+        HIPCHK(launch_dots(D, 2, W.scal + 24, st));                  // ||b||^2, ||A^T b||^2
+      }
       TRY(solve_normal(P, W.t1, x, W.t2, W.pcg, st));               // x = R^{-1} R^{-T} A^T b
       for (int c2 = 0; c2 < o->ls_corrections; ++c2) {               // corrected semi-normal equations
         HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
@@ -1031,10 +1150,11 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
       HIPCHK(launch_fill_f64(W.scal + 14, 0.0, 1, st));
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
-      double h2[2];
-      HIPCHK(hipMemcpyAsync(h2, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      double h2[5];
+      HIPCHK(hipMemcpyAsync(h2, W.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       S.sigma_ls = std::sqrt(h2[0]);
+      rr0 = h2[3];
       if (!(o->gate_enforce && P->storage != TLS_FP64)) break;
       // constraint (6) with sigma_{n+1} <= sigma_0 and the Lanczos estimates
       if (!P->have_kappa) {
@@ -1068,9 +1188,6 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       S.t_factor_ms += ms_since(tf);
       return TLS_OK;
     };
-    TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
-    HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));           // x_1 = x_0 + sigma_0^2 u_0
-
     // shift cap for the clamp (a deviation for starts above sigma'_n)
     double cap = 0.0;
     if (o->shift_clamp && !P->have_sigma_n) {
@@ -1079,6 +1196,64 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     }
     if (o->shift_clamp && std::isfinite(P->rep.sigma_n_est) && P->rep.sigma_n_est > 0)
       cap = o->shift_clamp_tau * P->rep.sigma_n_est * P->rep.sigma_n_est;
+
+    TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
+    const bool warm = o->mlp_theta != nullptr || o->sigma0_hint > 0;
+    bool plain_step = true;
+    if (warm || o->features) {
+      // u_1 = (R^T R)^{-1} u_0 and the dot products of the features
+      double *u1 = W.rp, *xw = W.rq;
+      TRY(solve_normal(P, W.t1, u1, W.t2, W.pcg, st));
+      DotPairs D{};
+      const double *pa[5] = {x, x, W.t1, W.t1, u1}, *pb[5] = {x, W.t1, W.t1, u1, u1};
+      for (int i = 0; i < 5; ++i) { D.a[i] = pa[i]; D.b[i] = pb[i]; D.len[i] = n; }
+      HIPCHK(launch_dots(D, 5, W.scal + 26, st));
+      double hd[7];
+      HIPCHK(hipMemcpyAsync(hd, W.scal + 24, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      WarmScalars ws_{};
+      ws_.m = (double)m; ws_.n = (double)n; ws_.nA2 = P->normA_F2; ws_.bb = hd[0]; ws_.atb2 = hd[1];
+      ws_.s0 = S.sigma_ls; ws_.xx = hd[2]; ws_.xu = hd[3]; ws_.uu = hd[4]; ws_.uv = hd[5];
+      ws_.vv = hd[6]; ws_.rr = rr0;
+      for (int i = 0; i < 4; ++i) ws_.lnd[i] = P->lnd[i];
+      warm_features(ws_, S.features);
+      double sig_hat = -1.0;
+      if (o->mlp_theta) {
+        HIPCHK(hipMemcpyAsync(W.rs, S.features, TLS_MLP_IN * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_mlp_infer1(o->mlp_theta, o->mlp_norm, (const float *)W.rs, W.scal + 22, st));
+        double yh = 0.0;
+        HIPCHK(hipMemcpyAsync(&yh, W.scal + 22, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        // y = ln(1 - sigma^2 / sigma_0^2) = two-point Gauss estimate + learned correction
+        const double y = (double)S.features[31] + yh;
+        if (std::isfinite(y)) sig_hat = S.sigma_ls * std::sqrt(std::max(0.0, -std::expm1(std::min(y, 0.0))));
+      } else if (o->sigma0_hint > 0) {
+        sig_hat = o->sigma0_hint;
+      }
+      if (warm && sig_hat >= 0.0) {
+        sig_hat = std::min(sig_hat, S.sigma_ls);
+        if (cap > 0) sig_hat = std::min(sig_hat, std::sqrt(cap));
+        const double lam = sig_hat * sig_hat;
+        HIPCHK(launch_axpy2(n, x, W.t1, u1, lam, lam * lam, xw, st));      // warm candidate
+        HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));              // plain x_1
+        plain_step = false;
+        double pw = 0.0, pp = 0.0;
+        TRY(evaluate_at(xw, 1, cap));
+        HIPCHK(hipMemcpyAsync(&pw, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        TRY(evaluate_at(x, 1, cap));
+        HIPCHK(hipMemcpyAsync(&pp, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        S.sigma_hat = sig_hat;
+        S.psi_warm = pw;
+        S.psi_plain = pp;
+        if (pw < pp) {
+          HIPCHK(launch_copy_f64(x, xw, (size_t)n, st));
+          S.warm_used = 1;
+        }
+      }
+    }
+    if (plain_step) HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));   // x_1 = x_0 + sigma_0^2 u_0
 
     // ---- main loop -----------------------------------------------------------
     double best = std::numeric_limits<double>::infinity();
@@ -1210,6 +1385,84 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
   }
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// warm-start network
+// ===========================================================================
+namespace {
+
+MlpBufs carve_mlp(Carver &c, int64_t B, float **y) {
+  MlpBufs M{};
+  M.h0 = c.take<float>((size_t)B * TLS_MLP_IN);
+  for (int i = 0; i < 3; ++i) {
+    M.z[i] = c.take<float>((size_t)B * TLS_MLP_WIDTH);
+    M.h[i] = c.take<float>((size_t)B * TLS_MLP_WIDTH);
+  }
+  for (int i = 0; i < 2; ++i) M.dz[i] = c.take<float>((size_t)B * TLS_MLP_WIDTH);
+  M.dy = c.take<float>((size_t)B);
+  *y = c.take<float>((size_t)B);
+  return M;
+}
+
+tls_status check_mlp_ws(int64_t batch, void *ws, size_t ws_bytes) {
+  if (batch < 1 || batch > (int64_t)1 << 24) return fail(TLS_ERR_ARG, "batch must be in [1, 2^24]");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  const size_t need = tls_mlp_workspace_size(batch);
+  if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "MLP workspace %zu < %zu bytes", ws_bytes, need);
+  return TLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tls_mlp_workspace_size(int64_t batch) {
+  if (batch < 1) return 0;
+  Carver c(nullptr);
+  float *y = nullptr;
+  carve_mlp(c, batch, &y);
+  return c.size();
+}
+
+tls_status tls_mlp_forward(const float *theta, const float *norm, const float *X, int64_t batch,
+                           float *y, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!theta || !norm || !X || !y) return fail(TLS_ERR_ARG, "NULL argument to tls_mlp_forward");
+  TRY(check_mlp_ws(batch, ws, ws_bytes));
+  Carver c(ws);
+  float *yw = nullptr;
+  MlpBufs M = carve_mlp(c, batch, &yw);
+  HIPCHK(launch_mlp_forward(theta, norm, X, batch, y, M, stream));
+  return TLS_OK;
+}
+
+tls_status tls_mlp_loss_grad(const float *theta, const float *norm, const float *X, const float *t,
+                             int64_t batch, float *grad, float *loss, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  if (!theta || !norm || !X || !t || !grad || !loss)
+    return fail(TLS_ERR_ARG, "NULL argument to tls_mlp_loss_grad");
+  TRY(check_mlp_ws(batch, ws, ws_bytes));
+  Carver c(ws);
+  float *y = nullptr;
+  MlpBufs M = carve_mlp(c, batch, &y);
+  HIPCHK(launch_mlp_forward(theta, norm, X, batch, y, M, stream));
+  HIPCHK(launch_mlp_backward(theta, y, t, batch, grad, loss, M, stream));
+  return TLS_OK;
+}
+
+tls_status tls_mlp_adam(float *theta, float *m, float *v, const float *grad, int64_t count,
+                        int64_t step, float lr, float beta1, float beta2, float eps,
+                        hipStream_t stream) {
+  if (!theta || !m || !v || !grad || count < 1) return fail(TLS_ERR_ARG, "bad arguments to tls_mlp_adam");
+  if (step < 1) return fail(TLS_ERR_ARG, "Adam step numbers start at 1");
+  if (!(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 && lr > 0))
+    return fail(TLS_ERR_ARG, "Adam needs 0 <= beta < 1, eps > 0, lr > 0");
+  const double c1 = 1.0 / (1.0 - std::pow((double)beta1, (double)step));
+  const double c2 = 1.0 / (1.0 - std::pow((double)beta2, (double)step));
+  HIPCHK(launch_mlp_adam(count, theta, m, v, grad, lr, beta1, beta2, eps, (float)c1, (float)c2, stream));
+  return TLS_OK;
 }
 
 }  // extern "C"

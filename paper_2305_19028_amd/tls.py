@@ -64,13 +64,18 @@ class c_gate_report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+MLP_IN = 32
+MLP_WIDTH = 256
+MLP_PARAMS = 140289
+
+
 class c_rqi_opts(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "u_p", "kmax", "stop_patience", "stop_ge", "ls_corrections", "strict_pd",
         "shift_clamp", "refine_sweeps", "refine_pcg_steps", "allow_escalate",
-        "gate_enforce", "reserved")] + \
+        "gate_enforce", "features")] + \
         [("shift_clamp_tau", C.c_double), ("sigma0_hint", C.c_double),
-         ("x_snapshots", C.c_void_p)]
+         ("x_snapshots", C.c_void_p), ("mlp_theta", C.c_void_p), ("mlp_norm", C.c_void_p)]
 
 
 class c_rqi_stats(C.Structure):
@@ -79,7 +84,9 @@ class c_rqi_stats(C.Structure):
         "refine_steps", "clamped")] + \
         [("sigma_ls", C.c_double), ("psi", C.c_double * MAX_ITERS),
          ("sigma", C.c_double * MAX_ITERS), ("t_ms", C.c_double * MAX_ITERS),
-         ("t_factor_ms", C.c_double), ("t_total_ms", C.c_double), ("sigma_final", C.c_double)]
+         ("t_factor_ms", C.c_double), ("t_total_ms", C.c_double), ("sigma_final", C.c_double),
+         ("sigma_hat", C.c_double), ("psi_warm", C.c_double), ("psi_plain", C.c_double),
+         ("features", C.c_float * MLP_IN)]
 
     def to_dict(self):
         k = self.iters
@@ -90,12 +97,15 @@ class c_rqi_stats(C.Structure):
             "clamped": self.clamped, "sigma_ls": self.sigma_ls,
             "psi": list(self.psi[:k]), "sigma": list(self.sigma[:k]), "t_ms": list(self.t_ms[:k]),
             "t_factor_ms": self.t_factor_ms, "t_total_ms": self.t_total_ms,
-            "sigma_final": self.sigma_final,
+            "sigma_final": self.sigma_final, "sigma_hat": self.sigma_hat,
+            "psi_warm": self.psi_warm, "psi_plain": self.psi_plain,
+            "features": list(self.features),
         }
 
 
 PROF_CLASSES = ["precond_apply", "pcg_step", "gram", "chol_panel", "chol_update", "residual",
-                "gradient", "outer_scalars", "setup", "lanczos", "pack", "residual_dd", "invert"]
+                "gradient", "outer_scalars", "setup", "lanczos", "pack", "residual_dd", "invert",
+                "mlp"]
 
 
 class c_kernel_times(C.Structure):
@@ -137,6 +147,14 @@ _SIGS = {
                                 C.POINTER(c_rqi_opts), C.c_void_p, C.POINTER(C.c_double),
                                 C.POINTER(c_rqi_stats), C.c_void_p, C.c_size_t, C.c_void_p]),
     "tls_round": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
+    "tls_mlp_workspace_size": (C.c_size_t, [C.c_int64]),
+    "tls_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tls_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tls_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                               C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                               C.c_void_p]),
     "tls_profile_start": (C.c_int, []),
     "tls_precond_set_apply": (C.c_int, [C.c_void_p, C.c_int32]),
     "tls_profile_stop": (C.c_int, [C.POINTER(c_kernel_times)]),
@@ -394,6 +412,12 @@ def default_opts(**kw) -> c_rqi_opts:
             v = _prec(v)
         if k == "x_snapshots":
             v = v.data_ptr() if v is not None else None
+        if k == "mlp":
+            # (theta, norm) device float32 tensors; the caller keeps them alive
+            theta, norm = v if v is not None else (None, None)
+            o.mlp_theta = theta.data_ptr() if theta is not None else None
+            o.mlp_norm = norm.data_ptr() if norm is not None else None
+            continue
         setattr(o, k, v)
     return o
 
@@ -431,3 +455,44 @@ def tls_profile_stop():
     t = c_kernel_times()
     _check(lib().tls_profile_stop(C.byref(t)))
     return {name: (t.launches[i], t.total_ms[i]) for i, name in enumerate(PROF_CLASSES)}
+
+
+# ----------------------------------------------------------------------------
+# warm-start network
+# ----------------------------------------------------------------------------
+def _f32(t):
+    torch = _torch()
+    return torch.as_tensor(t).to(device="cuda", dtype=torch.float32).contiguous()
+
+
+def tls_mlp_forward(theta, norm, X):
+    """y (batch,) = network(X) on the device (float32 tensors)."""
+    torch = _torch()
+    th, nm, Xd = _f32(theta), _f32(norm), _f32(X)
+    B = Xd.shape[0]
+    y = torch.empty(B, dtype=torch.float32, device="cuda")
+    ws = Workspace(lib().tls_mlp_workspace_size(B))
+    _check(lib().tls_mlp_forward(_ptr(th), _ptr(nm), _ptr(Xd), B, _ptr(y), ws.ptr, ws.nbytes,
+                                 _stream()))
+    return y
+
+
+def tls_mlp_loss_grad(theta, norm, X, t, grad_out=None, ws=None):
+    """(loss [1] device tensor, grad [MLP_PARAMS] device tensor)."""
+    torch = _torch()
+    th, nm, Xd, td = _f32(theta), _f32(norm), _f32(X), _f32(t)
+    B = Xd.shape[0]
+    g = grad_out if grad_out is not None else torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    need = lib().tls_mlp_workspace_size(B)
+    if ws is None or ws.nbytes < need:
+        ws = Workspace(need)
+    _check(lib().tls_mlp_loss_grad(_ptr(th), _ptr(nm), _ptr(Xd), _ptr(td), B, _ptr(g), _ptr(loss),
+                                   ws.ptr, ws.nbytes, _stream()))
+    return loss, g
+
+
+def tls_mlp_adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of the float32 device tensors theta, m, v."""
+    _check(lib().tls_mlp_adam(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), theta.numel(), step,
+                              lr, beta1, beta2, eps, _stream()))

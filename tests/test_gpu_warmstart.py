@@ -1,0 +1,45 @@
+"""The learned warm start end to end on the device: labels from plain
+solves, training with the library's kernels, and what the trained network
+gains over the plain least-squares start on held-out problems (reduced
+sizes: m in [2000, 8000], n in [40, 250], 256 training problems)."""
+import json
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_trained_network_gain():
+    from paper_2305_19028_amd import warmstart as ws
+    mr, nr = (2000, 8000), (40, 250)
+    print("warm start: dataset", flush=True)
+    F, y = ws.make_dataset(range(256), mr, nr, path="fp64")
+    assert np.all(np.isfinite(F)) and np.all(y <= 0) and np.all(np.isfinite(y))
+    norm = ws.fit_norm(F)
+    print("warm start: training", flush=True)
+    theta, hist = ws.train(F, y, norm, epochs=150, batch=64, lr=1e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    print("warm start: held-out evaluation", flush=True)
+    test_seeds = range(10 ** 6, 10 ** 6 + 32)
+    recs = ws.evaluate(theta, norm, test_seeds, mr, nr, path="fp64")
+    Ft, yt = ws.make_dataset(test_seeds, mr, nr, path="fp64")
+    yp = ws.predict(theta, norm, Ft)
+    # gaps that matter at the 1e-10 tolerance (smaller ones are rounding noise)
+    sel = yt >= np.log(1e-10)
+    assert sel.sum() >= 8
+    mse_net = float(np.mean((yp - yt)[sel] ** 2))
+    mse_const = float(np.mean((yt[sel] - y.mean()) ** 2))      # best constant from training
+    mse_first = float(np.mean((ws.base(Ft) - yt)[sel] ** 2))   # quadrature estimate alone
+    s = ws.summarize(recs)
+    s.update({"resolvable": int(sel.sum()), "mse_net": mse_net, "mse_const": mse_const, "mse_quadrature": mse_first})
+    print("warm start summary:", json.dumps(s), flush=True)
+    # the network explains most of the variance of the relative gap, and its
+    # correction does not make the quadrature estimate worse
+    assert mse_net < 0.5 * mse_const
+    assert mse_net <= 2.0 * mse_first + 0.05
+    # the warm solves return the plain method's answer
+    plain_err = max(r["plain"]["err_sigma"] for r in recs)
+    warm_err = max(r["warm"]["err_sigma"] for r in recs)
+    assert warm_err <= max(1e-10, 10 * plain_err)
+    assert s["warm"]["reached_tol"] >= s["plain"]["reached_tol"]

@@ -397,3 +397,33 @@ def warmstart_problem(seed: int, m_range=(5000, 50000), n_range=(500, 5000),
     else:
         A, b, x, _ = sparse_scaled(m, n, seed=sub, noise_b=noise)
     return {"kind": kind, "m": m, "n": n, "noise": noise, "A": A, "b": b, "x_true": x}
+
+
+# ----------------------------------------------------------------------------
+# warm-start network: initial parameters and synthetic batches
+# ----------------------------------------------------------------------------
+
+MLP_LAYERS = [(32, 256), (256, 256), (256, 256), (256, 1)]   # (in, out)
+
+
+def mlp_init(seed: int = 7) -> np.ndarray:
+    """Initial parameters (float32): for each layer W (out x in, row-major)
+    then its bias, both uniform on [-1/sqrt(in), 1/sqrt(in)]."""
+    g = rng(seed)
+    parts = []
+    for i, o in MLP_LAYERS:
+        a = 1.0 / math.sqrt(i)
+        parts.append(g.uniform(-a, a, size=i * o))
+        parts.append(g.uniform(-a, a, size=o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(batch: int, seed: int = 11):
+    """Synthetic (features, targets, norm) for network tests: features
+    N(1, 2^2), targets a smooth function of them, norm = [mean, 1/std]."""
+    g = rng(seed)
+    X = (1.0 + 2.0 * g.standard_normal((batch, 32))).astype(np.float32)
+    t = (np.tanh(X[:, :8].astype(np.float64) @ g.standard_normal(8) / 8.0)
+         - 0.1 * X[:, 8].astype(np.float64) ** 2 / 4.0).astype(np.float32)
+    norm = np.concatenate([np.full(32, 1.0), np.full(32, 0.5)]).astype(np.float32)
+    return X, t, norm
