@@ -86,8 +86,10 @@ typedef struct tls_precond_s *tls_precond;
 
 /* Outcome of the per-instance check of the factorization precision u_q
  * against the constraints of Section 3.1 (the constants the paper drops
- * are taken as one). Estimates come from Lanczos on the preconditioned
- * operator R^{-T} R^{-1}. */
+ * are taken as one). Estimates come from Lanczos on R^{-T} R^{-1}; they are
+ * only as good as the factor, so with tls_rqi_solve's gate on, the factor is
+ * also certified by Lanczos on R^{-T} A^T A R^{-1} (the operator whose
+ * distance from I the analysis of Section 3.1 bounds). */
 typedef struct {
   double kappa_est;        /* kappa(A D^{-1}) estimate (D = I when unscaled)   */
   double kappaF_est;       /* kappa_F(A D^{-1}) = ||A D^{-1}||_F / sigma_min    */
@@ -102,10 +104,14 @@ typedef struct {
                               filled by tls_rqi_solve, which knows b             */
   double u_q;              /* unit roundoff of the precision finally used        */
   double ctilde_min;       /* lambda_min estimate of C = I - s0^2 R^{-T}R^{-1}   */
+  double quality_lo;       /* extreme Ritz values of R^{-T} A^T A R^{-1} (FP64   */
+  double quality_hi;       /* products with A): the a-posteriori certificate     */
   int32_t requested;       /* tls_prec asked for                                 */
   int32_t used;            /* tls_prec actually used (after escalation)          */
   int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,
-                              3: (6) holds, 4: a-posteriori certificate holds    */
+                              3: (6) holds, 4: a-posteriori certificate holds:
+                              quality_lo >= 1/2 and quality_hi <= 3/2 (the
+                              factor is within 50% of A^T A in every direction) */
   int32_t escalations;     /* times u_q was raised                               */
   int32_t chol_retries;    /* diagonal-shift retries after breakdown             */
   int32_t lanczos_steps;

@@ -94,6 +94,9 @@ hipError_t launch_quantize_csc(int n, const int32_t *col_ptr, const double *cval
 hipError_t launch_gram_sparse(int m, int n, int Np, const int32_t *row_ptr, const int32_t *col_idx,
                               const void *valq, const int32_t *col_ptr, const int32_t *row_idx,
                               const void *cvalq, int compute, void *G, hipStream_t st);
+size_t gram_cast_bytes(int64_t m, int64_t n);
+hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
+                            int scaled, int q, void *cast, void *G, hipStream_t st);
 hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, const double *d,
                              int scaled, int q, int compute, void *G, hipStream_t st);
 hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st);
@@ -149,7 +152,7 @@ hipError_t launch_axpy_init(int n, double *x, const double *u, const double *sca
 hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);
 hipError_t launch_add_f64(double *x, const double *dx, size_t count, hipStream_t st);
 hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const double *Wout,
-                               double *nxt, const double *dsc, double *ab, hipStream_t st);
+                               double *nxt, const double *dsc, double *ab, hipStream_t st, int runs = 2);
 hipError_t launch_ref_step1(int n, int nrhs, const double *scal, double *x, double *r,
                             const double *p, double *q, double *rs, hipStream_t st);
 hipError_t launch_ref_step2(int n, int nrhs, const double *r, const double *z, double *p, double *rs,

@@ -375,6 +375,290 @@ hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, 
   return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// dense Gram on the matrix cores
+//
+// G = Ahat^T Ahat (upper tiles) with 128 x 128 output tiles per workgroup
+// of four waves (64 x 64 each). A K-chunk of 32 rows of the two column
+// panels is staged in LDS (row = one column of Ahat, 32 consecutive
+// entries); the next chunk's global loads are in flight while the current
+// one feeds the MFMAs. Instructions by input type:
+//   bf16 / fp16: v_mfma_f32_32x32x16 (FP32 accumulation), operand = 8
+//                consecutive k of one column
+//   fp32:        v_mfma_f32_32x32x2_f32
+//   fp64:        v_mfma_f64_16x16x4_f64
+// The MFMA's A operand takes the output-column panel and its B operand the
+// output-row panel, so that a lane's results lie along a column of the
+// column-major G and the stores coalesce.
+// Low-precision inputs come from a cast buffer (zero padded to whole
+// chunks and tiles, 16-byte vector loads); FP64 reads A itself with
+// bounds checks.
+// --------------------------------------------------------------------------
+typedef __bf16 g_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 g_f16x8 __attribute__((ext_vector_type(8)));
+typedef float g_f32x16 __attribute__((ext_vector_type(16)));
+typedef double g_f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 128, GKC = 32;
+
+template <typename T> __device__ inline T cast_bits(double v);
+template <> __device__ inline float cast_bits<float>(double v) {
+  return __builtin_bit_cast(float, f64_to_f32_bits(v));
+}
+template <> __device__ inline half_t cast_bits<half_t>(double v) { return half_t{f64_to_f16_bits(v)}; }
+template <> __device__ inline bf16_t cast_bits<bf16_t>(double v) { return bf16_t{f64_to_bf16_bits(v)}; }
+
+// out (mp x n128, column-major) = round(A D^{-1}) (or round(A)), zero padding
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_dense(int m, int n, int64_t ld, const double *A,
+                                                    const double *d, int scaled, int mp, T *out) {
+  const int c = blockIdx.y;
+  const double sc = (c < n && scaled) ? 1.0 / d[c] : 1.0;
+  const double *col = A + (size_t)c * ld;
+  T *o = out + (size_t)c * mp;
+  for (int r = blockIdx.x * 1024 + threadIdx.x; r < min(mp, (int)(blockIdx.x + 1) * 1024); r += 256) {
+    const double v = (r < m && c < n) ? col[r] * sc : 0.0;
+    o[r] = cast_bits<T>(v);
+  }
+}
+
+template <typename T> struct GramIn { using V = uint4; static constexpr int E = 16 / sizeof(T); };
+
+template <typename T, typename C>
+__global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, const T *A, int Np, C *G,
+                                                   const double *d, int scaled) {
+  constexpr bool F64 = std::is_same<T, double>::value;
+  constexpr int PADE = 16 / (int)sizeof(T);
+  constexpr int RL = GKC + PADE;                     // LDS row length (elements)
+  __shared__ __attribute__((aligned(16))) T Ps[GT][RL];   // output-column panel (J)
+  __shared__ __attribute__((aligned(16))) T Qs[GT][RL];   // output-row panel (I)
+  const int l = blockIdx.x;
+  int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  const int I = l - J * (J + 1) / 2;
+  const bool diag = (I == J);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;                 // wave's 64 x 64 block (rows, cols)
+  const int r0 = I * GT, c0 = J * GT;
+
+  // ---- global -> register staging --------------------------------------
+  constexpr int VPC = GKC * (int)sizeof(T) / 16;     // 16-byte vectors per column chunk
+  constexpr int NV = GT * VPC / 256;                 // per thread per panel (cast buffer)
+  uint4 pv[F64 ? 1 : NV], qv[F64 ? 1 : NV];
+  double pe[F64 ? 16 : 1], qe[F64 ? 16 : 1];
+  auto fetch = [&](int k0) {
+    if constexpr (F64) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = tid + 256 * i, c = e / GKC, r = k0 + e % GKC;
+        pe[i] = (r < m && c0 + c < n) ? ((const double *)A)[(size_t)(c0 + c) * ld + r] : 0.0;
+        qe[i] = (!diag && r < m && r0 + c < n) ? ((const double *)A)[(size_t)(r0 + c) * ld + r] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int v = tid + 256 * i, c = v / VPC, o = (v % VPC) * (16 / (int)sizeof(T));
+        pv[i] = *(const uint4 *)(A + (size_t)(c0 + c) * ld + k0 + o);
+        if (!diag) qv[i] = *(const uint4 *)(A + (size_t)(r0 + c) * ld + k0 + o);
+      }
+    }
+  };
+  auto stage = [&]() {
+    if constexpr (F64) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e = tid + 256 * i, c = e / GKC, r = e % GKC;
+        Ps[c][r] = pe[i];
+        if (!diag) Qs[c][r] = qe[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int v = tid + 256 * i, c = v / VPC, o = (v % VPC) * (16 / (int)sizeof(T));
+        *(uint4 *)&Ps[c][o] = pv[i];
+        if (!diag) *(uint4 *)&Qs[c][o] = qv[i];
+      }
+    }
+  };
+  const T (*Qp)[RL] = diag ? Ps : Qs;
+
+  // ---- accumulators ------------------------------------------------------
+  g_f32x16 acc32[2][2];
+  g_f64x4 acc64[4][4];
+  if constexpr (F64) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc64[t][u] = g_f64x4{0, 0, 0, 0};
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc32[t][u][q] = 0.0f;
+  }
+
+  // FP32 accumulators are folded into FP64 sums every FLUSH chunks, so that
+  // the accumulation error over the m rows stays near that of one chunk
+  // (about sqrt(32 FLUSH) u_32 relative) instead of growing like sqrt(m)
+  constexpr int FLUSH = std::is_same<T, float>::value ? 1 : 8;
+  double sum64[F64 ? 1 : 2][F64 ? 1 : 2][F64 ? 1 : 16];
+  if constexpr (!F64) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sum64[t][u][q] = 0.0;
+  }
+  auto flush = [&]() {
+    if constexpr (!F64) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            sum64[t][u][q] += (double)acc32[t][u][q];
+            acc32[t][u][q] = 0.0f;
+          }
+    }
+  };
+  const int kend = F64 ? m : ((m + GKC - 1) / GKC) * GKC;
+  int chunk = 0;
+  fetch(0);
+  for (int k0 = 0; k0 < kend; k0 += GKC) {
+    if (++chunk == FLUSH) { flush(); chunk = 0; }
+    __syncthreads();                 // previous chunk fully consumed
+    stage();
+    __syncthreads();
+    if (k0 + GKC < kend) fetch(k0 + GKC);
+    if constexpr (F64) {
+#pragma unroll
+      for (int s = 0; s < GKC / 4; ++s) {
+        double a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = Ps[wc * 64 + t * 16 + (lane & 15)][s * 4 + (lane >> 4)];
+          b[t] = Qp[wr * 64 + t * 16 + (lane & 15)][s * 4 + (lane >> 4)];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc64[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc64[t][u], 0, 0, 0);
+      }
+    } else if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+      for (int s = 0; s < GKC / 2; ++s) {
+        float a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = Ps[wc * 64 + t * 32 + (lane & 31)][s * 2 + (lane >> 5)];
+          b[t] = Qp[wr * 64 + t * 32 + (lane & 31)][s * 2 + (lane >> 5)];
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[u], acc32[t][u], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < GKC / 16; ++s) {
+        uint4 a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = *(const uint4 *)&Ps[wc * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
+          b[t] = *(const uint4 *)&Qp[wr * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if constexpr (std::is_same<T, bf16_t>::value)
+              acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(g_bf16x8, a[t]), __builtin_bit_cast(g_bf16x8, b[u]), acc32[t][u], 0, 0, 0);
+            else
+              acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(g_f16x8, a[t]), __builtin_bit_cast(g_f16x8, b[u]), acc32[t][u], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+  // ---- epilogue: D(i, j) = G(c0 + .. i, r0 + .. j), stored at G[c * Np + r], r <= c
+  if constexpr (F64) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = c0 + wc * 64 + t * 16 + 4 * q + (lane >> 4);
+          const int r = r0 + wr * 64 + u * 16 + (lane & 15);
+          if (r <= c && c < Np) {
+            // FP64 reads A unscaled: H = D^{-1} (A^T A) D^{-1} on output
+            double v = acc64[t][u][q];
+            if (scaled && c < n) v *= (1.0 / d[r]) * (1.0 / d[c]);
+            G[(size_t)c * Np + r] = (C)v;
+          }
+        }
+  } else {
+    flush();
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = c0 + wc * 64 + t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+          const int r = r0 + wr * 64 + u * 32 + (lane & 31);
+          if (r <= c && c < Np) G[(size_t)c * Np + r] = (C)sum64[t][u][q];
+        }
+  }
+}
+
+size_t gram_cast_bytes(int64_t m, int64_t n) {
+  const int64_t mp = ((m + GKC - 1) / GKC) * GKC;
+  const int64_t n128 = ((n + GT - 1) / GT) * GT;
+  return (size_t)mp * n128 * 4;   // room for the widest low-precision input (FP32)
+}
+
+hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
+                            int scaled, int q, void *cast, void *G, hipStream_t st) {
+  const int NT = (n + GT - 1) / GT;
+  const dim3 g((unsigned)(NT * (NT + 1) / 2));
+  if (q == TLS_FP64) {
+    TLS_LAUNCH(PC_GRAM, (k_gram_mfma<double, double>), g, dim3(256), 0, st, m, n, ld, A, Np, (double *)G,
+               d, scaled);
+    return hipGetLastError();
+  }
+  const int mp = ((m + GKC - 1) / GKC) * GKC;
+  const int n128 = NT * GT;
+  const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
+  switch (q) {
+    case TLS_FP32:
+      TLS_LAUNCH(PC_GRAM, k_cast_dense<float>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (float *)cast);
+      TLS_LAUNCH(PC_GRAM, (k_gram_mfma<float, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
+                 (const float *)cast, Np, (float *)G, d, 0);
+      break;
+    case TLS_FP16:
+      TLS_LAUNCH(PC_GRAM, k_cast_dense<half_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (half_t *)cast);
+      TLS_LAUNCH(PC_GRAM, (k_gram_mfma<half_t, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
+                 (const half_t *)cast, Np, (float *)G, d, 0);
+      break;
+    default:
+      TLS_LAUNCH(PC_GRAM, k_cast_dense<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (bf16_t *)cast);
+      TLS_LAUNCH(PC_GRAM, (k_gram_mfma<bf16_t, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
+                 (const bf16_t *)cast, Np, (float *)G, d, 0);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // identity in the padding columns n..Np-1 (upper triangle)
 template <typename C>
 __global__ void k_gram_pad(int n, int Np, C *G) {

@@ -547,8 +547,8 @@ __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int
   }
 }
 hipError_t launch_lanczos_orth(int n, int Np, int k, int K, double *V, const double *Wout,
-                               double *nxt, const double *dsc, double *ab, hipStream_t st) {
-  TLS_LAUNCH(PC_LANCZOS, k_lanczos_orth, dim3(2), dim3(1024), 0, st, n, Np, k, K, V, Wout, nxt, dsc, ab);
+                               double *nxt, const double *dsc, double *ab, hipStream_t st, int runs) {
+  TLS_LAUNCH(PC_LANCZOS, k_lanczos_orth, dim3(runs), dim3(1024), 0, st, n, Np, k, K, V, Wout, nxt, dsc, ab);
   return hipGetLastError();
 }
 

@@ -103,6 +103,7 @@ struct tls_precond_s {
   int apply_mode = 0;             // 0 explicit inverse, 1 substitution
   void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
   int64_t fws_m = 0;
+  int fws_cast = 0;               // the factor workspace holds a cast buffer
   int have_sigma_n = 0, have_kappa = 0;
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
   double normA_F2 = 0;             // ||A||_F^2 = sum_j d_j^2
@@ -187,10 +188,13 @@ struct FactorWs {
   void *xr, *xc;   // explicit inverse tiles (FP64-sized)
   double *yinv;    // inversion scratch
   int *cnt;        // per-block arrival counters of internal applies
+  double *tm;      // m-vector (products with A in the certificate)
+  void *cast;      // dense A rounded to u_q (matrix-core Gram input), or NULL
 };
 constexpr int LANCZOS_STEPS = 12;
+constexpr int QUALITY_STEPS = 8;
 
-FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format) {
+FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast) {
   const int Np = ceil_div(n, NB) * NB, N = Np / NB;
   FactorWs W{};
   W.tiles = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
@@ -220,7 +224,9 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format) 
   W.yinv = c.take<double>(std::max(invert_scratch_doubles(N),
                                     (size_t)N * xapply_chunk_count(N) * 2 * NB));
   W.cnt = c.take<int>(N);
-  (void)m;
+  W.tm = c.take<double>((size_t)std::max<int64_t>(m, 1));
+  // low-precision copy of a dense A for the matrix-core Gram
+  W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
   return W;
 }
 
@@ -475,14 +481,14 @@ size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q) {
   (void)u_q;
   if (check_matrix(A) != TLS_OK) return 0;
   Carver c(nullptr);
-  carve_factor(c, A->m, A->n, A->nnz, A->format);
+  carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64);
   return c.size();
 }
 
 size_t tls_precond_import_workspace_size(int64_t n) {
   if (n <= 0) return 0;
   Carver c(nullptr);
-  carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR);
+  carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR, 0);
   return c.size();
 }
 
@@ -517,7 +523,9 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
     HIPCHK(launch_gram_sparse((int)A->m, n, Np, A->row_ptr, A->col_idx, W.valq, W.col_ptr,
                               W.row_idx, W.cvalq, compute, W.G, st));
   } else {
-    HIPCHK(launch_gram_dense((int)A->m, n, Np, A->ld, A->val, W.d, P->scaled, uq, compute, W.G, st));
+    if (uq != TLS_FP64 && !W.cast)
+      return fail(TLS_ERR_WORKSPACE, "factor workspace sized for FP64 cannot hold a u_q = %d cast of A", uq);
+    HIPCHK(launch_gram_mfma((int)A->m, n, Np, A->ld, A->val, W.d, P->scaled, uq, W.cast, W.G, st));
   }
   HIPCHK(launch_gram_pad(n, Np, compute, W.G, st));
   return TLS_OK;
@@ -605,6 +613,50 @@ tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   return run_estimates(P, W, st);
 }
 
+// A-posteriori certificate of the factor: extreme Ritz values of
+// M = R^{-T} A^T A R^{-1} after QUALITY_STEPS Lanczos steps (products with A
+// and the applications of R in FP64). M = I for the exact factor.
+tls_status factor_quality(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
+  const int n = (int)P->n, Np = P->Np;
+  const int K = std::min(QUALITY_STEPS, n);
+  double *Vb = W.lz;                                              // [K+1][Np]
+  double *inb = W.lz + (size_t)2 * (LANCZOS_STEPS + 1) * Np;      // operator input
+  double *tmp = inb + (size_t)2 * Np;
+  double *outb = tmp + (size_t)2 * Np;
+  double *tn = outb + (size_t)2 * Np;
+  PcgWs S{};
+  S.sync = W.sync;
+  S.chain = tn + Np;
+  S.L = 0;
+  S.cpart = W.yinv;
+  S.cnt = W.cnt;
+  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
+  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
+  double *ab = W.lzs;
+  const double v0 = 1.0 / std::sqrt((double)n);
+  HIPCHK(launch_fill_f64(Vb, v0, (size_t)n, st));
+  HIPCHK(launch_fill_f64(inb, v0, (size_t)n, st));
+  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (size_t)K + 2, st));
+  HIPCHK(launch_fill_f64(ab + 2 * K, 1.0, 1, st));
+  for (int k = 0; k < K; ++k) {
+    TRY(apply_R(P, 0, 1, inb, tmp, TLS_FP64, S, st));      // R^{-1} v
+    HIPCHK(launch_matvec(V, tmp, W.tm, st));                 // A R^{-1} v
+    HIPCHK(launch_rmatvec(V, W.tm, tn, st));                 // A^T A R^{-1} v
+    TRY(apply_R(P, 1, 1, tn, outb, TLS_FP64, S, st));      // R^{-T} A^T A R^{-1} v
+    HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
+  }
+  std::vector<double> h(2 * K + 2);
+  HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int done = std::max(1, (int)h[2 * K + 1]);
+  std::vector<double> a(h.begin(), h.begin() + done), b(h.begin() + K, h.begin() + K + done - 1);
+  double lo = 0, hi = 0;
+  tridiag_extremes(a, b, &lo, &hi);
+  P->rep.quality_lo = lo;
+  P->rep.quality_hi = hi;
+  return TLS_OK;
+}
+
 // the A-only constraints of Section 3.1 from Lanczos estimates
 tls_status run_gate(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   tls_gate_report &R = P->rep;
@@ -632,7 +684,7 @@ tls_status run_gate(tls_precond_s *P, FactorWs &W, hipStream_t st) {
 
 FactorWs factor_ws_of(const tls_precond_s *P) {
   Carver c(P->fws_base);
-  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format);
+  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format, P->fws_cast);
 }
 
 tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
@@ -687,7 +739,7 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
     const size_t need = tls_factor_workspace_size(A, u_q);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "factor workspace %zu < %zu bytes", ws_bytes, need);
     Carver c(ws);
-    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format);
+    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64);
     auto *P = new (std::nothrow) tls_precond_s();
     if (!P) return fail(TLS_ERR_ARG, "out of host memory");
     std::unique_ptr<tls_precond_s> guard(P);
@@ -708,6 +760,7 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
     P->d = W.d;
     P->fws_base = ws;
     P->fws_m = A->m;
+    P->fws_cast = u_q != TLS_FP64;
     P->rep = tls_gate_report{};
     P->rep.requested = u_q;
     P->rep.sigma_n_est = P->rep.sigma_1_est = std::numeric_limits<double>::quiet_NaN();
@@ -782,7 +835,7 @@ tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_h
     const size_t need = tls_precond_import_workspace_size(n);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "import workspace %zu < %zu bytes", ws_bytes, need);
     Carver c(ws);
-    FactorWs W = carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR);
+    FactorWs W = carve_factor(c, n + 1, n, 0, TLS_DENSE_COLMAJOR, 0);
     auto P = std::make_unique<tls_precond_s>();
     P->n = n;
     P->Np = ceil_div(n, NB) * NB;
@@ -1167,15 +1220,22 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       R.bound6 = (1.0 - ratio) / R.kappaF_est;
       R.verdict &= ~(8 | 16);
       if (R.u_q < R.bound6) R.verdict |= 8;
+      // a-posteriori certificate of the factor itself (the estimates above
+      // come from the factor and cannot reveal that it is poor)
+      {
+        FactorWs FW = factor_ws_of(P);
+        TRY(factor_quality(P, FW, V, st));
+        if (R.quality_lo >= 0.5 && R.quality_hi <= 1.5) R.verdict |= 16;
+      }
       break;
     }
-    // a-posteriori check, decided after the first PCGTLS run when (6) failed
-    bool gate_pending = o->gate_enforce && P->storage != TLS_FP64 && !(P->rep.verdict & 8);
+    const bool gate_failed = o->gate_enforce && P->storage != TLS_FP64 && !(P->rep.verdict & 16);
     auto escalate = [&]() -> tls_status {
       tls_gate_report &R = P->rep;
       if (!o->allow_escalate)
-        return fail(TLS_ERR_PRECISION, "u_q = %g fails constraint (6) (bound %.3g) and PCGTLS met "
-                    "delta_j <= 0 with the factor", R.u_q, R.bound6);
+        return fail(TLS_ERR_PRECISION, "the u_q = %g factor fails the a-posteriori certificate "
+                    "(Ritz values of R^-T A^T A R^-1 in [%.3g, %.3g]; (6) bound %.3g)", R.u_q,
+                    R.quality_lo, R.quality_hi, R.bound6);
       const auto tf = clk::now();
       const int next = (P->storage == TLS_BF16) ? TLS_FP16 : (P->storage == TLS_FP16) ? TLS_FP32 : TLS_FP64;
       FactorWs FW = factor_ws_of(P);
@@ -1188,6 +1248,10 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       S.t_factor_ms += ms_since(tf);
       return TLS_OK;
     };
+    if (gate_failed) {
+      TRY(escalate());
+      return tls_rqi_solve(A, b, P, o, x, sigma, stats, ws, ws_bytes, st);
+    }
     // shift cap for the clamp (a deviation for starts above sigma'_n)
     double cap = 0.0;
     if (o->shift_clamp && !P->have_sigma_n) {
@@ -1287,22 +1351,6 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       HIPCHK(launch_make_rhs(n, W.f, x, W.rhs, st));
       TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, k, o->u_p, o->strict_pd, W.pcg, st));
       S.pcg_steps += k + 1;
-      if (gate_pending) {
-        // a posteriori: the low-precision preconditioned system stayed positive
-        // definite (delta_j > 0) in the first PCGTLS run at the actual shift
-        std::vector<int> neg((size_t)(W.pcg.L + 2) * 2);
-        HIPCHK(hipMemcpyAsync(neg.data(), W.pcg.neg, neg.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        int nneg = 0;
-        for (int v : neg) nneg += v;
-        gate_pending = false;
-        if (nneg == 0) {
-          P->rep.verdict |= 16;
-        } else {
-          TRY(escalate());
-          return tls_rqi_solve(A, b, P, o, x, sigma, stats, ws, ws_bytes, st);
-        }
-      }
       HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
     }
     // the returned iterate

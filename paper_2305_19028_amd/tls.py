@@ -56,7 +56,8 @@ class c_matrix(C.Structure):
 class c_gate_report(C.Structure):
     _fields_ = [(k, C.c_double) for k in (
         "kappa_est", "kappaF_est", "sigma_n_est", "sigma_1_est", "lam_min_H", "bound5",
-        "bound_chol", "bound_wilkinson", "bound_hp", "bound6", "u_q", "ctilde_min")] + \
+        "bound_chol", "bound_wilkinson", "bound_hp", "bound6", "u_q", "ctilde_min",
+        "quality_lo", "quality_hi")] + \
         [(k, C.c_int32) for k in ("requested", "used", "verdict", "escalations",
                                   "chol_retries", "lanczos_steps")]
 

@@ -1,0 +1,113 @@
+"""Dense path on the matrix cores: the MFMA Gram (FP64, FP32, FP16, BF16
+inputs) against the oracle, and full-size dense solves (65536 x 4096) with
+answers fixed by a planted SVD and by the normal-equation identity."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import tlsgen
+from oracle import lowprec
+
+pytestmark = pytest.mark.gpu
+
+
+def _tls():
+    from paper_2305_19028_amd import tls
+    return tls
+
+
+@pytest.mark.parametrize("u_q", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", [(3000, 300), (4097, 129), (300, 64)])
+def test_gram_tiles_against_oracle(u_q, shape):
+    """Several 128 x 128 Gram tiles, ragged m (partial K chunk) and ragged n
+    (partial tile): R^T R of the stored factor against the Gram matrix of the
+    oracle's rounding of A D^{-1}."""
+    tls = _tls()
+    m, n = shape
+    print(f"gram {u_q} {shape}", flush=True)
+    A, b, _ = tlsgen.dense_gaussian(m, n, seed=31 + n)
+    P, rep = tls.tls_factor_precond(tls.dense(A), u_q)
+    Rh, d = tls.tls_precond_export(P)
+    Ah = A / d if u_q == "fp64" else lowprec.round_to(A * (1.0 / d), u_q)
+    H = Ah.T @ Ah
+    if u_q == "fp64":
+        assert np.max(np.abs(Rh - sla.cholesky(H, lower=False))) < 1e-11
+        return
+    u = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[u_q]
+    # FP32 products, FP32 sums over 32-row chunks folded into FP64, Cholesky in
+    # FP32, factor stored in u_q: the storage rounding dominates
+    err = np.linalg.norm(Rh.T @ Rh - H, 2) / np.linalg.norm(H, 2)
+    assert err < 30 * u, err
+    assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
+
+
+def _planted_c3(seed=3100):
+    # the configuration's spectrum: sigma'_i geometric from 1 to 1e-3, and a
+    # planted smallest singular value of [A, b] at 3.9e-5
+    m, n = 65536, 4096
+    s = np.concatenate([1e-3 ** (np.arange(n) / (n - 1)), [3.9e-5]])
+    A, b, sig, w = tlsgen.planted_svd(m, n, s, seed=seed)
+    x = 2 * w[n] * w[:n] / (1 - 2 * w[n] ** 2)    # x_TLS = -v_{1:n}/v_{n+1}, v = (I - 2ww^T) e_{n+1}
+    return A, b, float(s[n]), x
+
+
+@pytest.fixture(scope="module")
+def planted():
+    print("planted 65536 x 4096: generating", flush=True)
+    return _planted_c3()
+
+
+def test_c3_planted_fp64(planted):
+    tls = _tls()
+    A, b, sig, x = planted
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp64")
+    xs, s, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(stop_patience=2))
+    es = abs(s - sig) / sig
+    ex = np.linalg.norm(xs.cpu().numpy() - x) / np.linalg.norm(x)
+    print(f"fp64: sigma {es:.2e} x {ex:.2e} iters {st['iters']}", flush=True)
+    # attainable: u sigma_1 / sigma_{n+1} ~ 3e-12, u kappa_TLS ~ 1e-13
+    assert es < 1e-10 and ex < 1e-10
+
+
+def test_c3_planted_mixed_gate_escalates(planted):
+    """BF16 requested with the gate on: the factor that is used carries the
+    a-posteriori certificate (Ritz values of R^{-T} A^T A R^{-1} within
+    [1/2, 3/2]; escalation if the BF16 one had failed), and the answer meets
+    1e-10."""
+    tls = _tls()
+    A, b, sig, x = planted
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "bf16")
+    opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=2,
+                            refine_sweeps=1)
+    xs, s, st = tls.tls_rqi_solve(Ad, b, P, opts)
+    g = P.info()["gate"]
+    es = abs(s - sig) / sig
+    ex = np.linalg.norm(xs.cpu().numpy() - x) / np.linalg.norm(x)
+    print(f"mixed: used {g['used']} escalations {g['escalations']} quality "
+          f"[{g['quality_lo']:.3g}, {g['quality_hi']:.3g}] sigma {es:.2e} x {ex:.2e}", flush=True)
+    if g["used"] != tls.PREC["fp64"]:
+        assert g["verdict"] & 16 and 0.5 <= g["quality_lo"] and g["quality_hi"] <= 1.5
+    assert g["used"] == tls.PREC["bf16"] or g["escalations"] >= 1
+    assert es < 1e-10 and ex < 1e-10
+
+
+def test_c3_reflector_fp64_normal_equations():
+    """The configuration's own generator (with the 1e-5 perturbation, no
+    closed form): the FP64 answer satisfies (A^T A - sigma^2 I) x = A^T b and
+    sigma^2 = ||b - A x||^2 / (1 + ||x||^2) to rounding."""
+    tls = _tls()
+    print("reflector 65536 x 4096: generating", flush=True)
+    A, b, _, _ = tlsgen.reflector_dense(65536, 4096)
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp64")
+    xs, s, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(stop_patience=2))
+    x = xs.cpu().numpy()
+    r = b - A @ x
+    res = A.T @ (A @ x) - s * s * x - A.T @ b
+    scale = np.linalg.norm(A.T @ (A @ x)) + np.linalg.norm(A.T @ b)
+    assert np.linalg.norm(res) / scale < 1e-11
+    assert abs(s * s - (r @ r) / (1 + x @ x)) / (s * s) < 1e-9

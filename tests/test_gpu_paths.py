@@ -87,8 +87,9 @@ def test_gate_bounds_against_exact_constraints():
 
 
 def test_gate_rejects_then_escalates():
-    # tiny gap: constraint (6) fails for 16-bit factors; the a-posteriori check
-    # (no delta_j <= 0 in the first PCGTLS run) decides, escalation fixes a failure
+    # tiny gap: constraint (6) fails for 16-bit factors; the a-posteriori
+    # certificate of the factor (Ritz values of R^{-T} A^T A R^{-1}) decides,
+    # escalation fixes a failure
     tls = _tls()
     A, b, x_t, lam, sn = _gap_problem(1e-3, seed=4002)
     sig_ref, x_ref = exact.planted_gap_solution(A, x_t, lam)
