@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 WORKLOAD = "sparse_c2"
 TOL = 1e-10
 
@@ -61,8 +62,11 @@ def make_problem():
 
 
 PATHS = {
-    "fp64": dict(u_q="fp64", u_p="fp64"),
-    "mixed": dict(u_q="fp16", u_p="fp32"),
+    "fp64": dict(u_q="fp64", u_p="fp64", opts={}),
+    # the gate (constraint checks and the factor certificate) runs per instance
+    # before the FP16 factor is used; the final FP64 refinement sweep is on
+    "mixed": dict(u_q="fp16", u_p="fp32", opts=dict(gate_enforce=1, allow_escalate=1,
+                                                    refine_sweeps=1)),
 }
 
 
@@ -73,7 +77,8 @@ def one_solve(tls, torch, Ad, bd, path, snaps=None):
     P, rep = tls.tls_factor_precond(Ad, cfg["u_q"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    opts = tls.default_opts(u_p=cfg["u_p"], stop_patience=2, kmax=40, x_snapshots=snaps)
+    opts = tls.default_opts(u_p=cfg["u_p"], stop_patience=2, kmax=40, x_snapshots=snaps,
+                            **cfg["opts"])
     x, sigma, st = tls.tls_rqi_solve(Ad, bd, P, opts)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -173,6 +178,37 @@ def class_work(cls, path, m, n, nnz, launches):
     return None
 
 
+# kernels (name in the profiler's records, source file) behind each class
+CLASS_KERNELS = {
+    "mixed": {"chol_panel": ("void tls::k_chol_panel<float>", "kernels_factor"),
+              "chol_update": ("void tls::k_chol_update<float>", "kernels_factor"),
+              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0>", "kernels_inv"),
+              "invert": ("tls::k_inv_phase2", "kernels_inv")},
+    "fp64": {"chol_panel": ("void tls::k_chol_panel<double>", "kernels_factor"),
+             "chol_update": ("void tls::k_chol_update<double>", "kernels_factor"),
+             "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0>", "kernels_inv"),
+             "invert": ("tls::k_inv_phase2", "kernels_inv")},
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_20000x2000_hbm_traffic.md")
+
+
+def measured_traffic(cls, path):
+    """HBM bytes per launch (read + written) from the committed PMC summary,
+    or None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    ent = CLASS_KERNELS.get(path, {}).get(cls)
+    if ent is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    name, src = ent
+    with open(os.path.join(ROOT, "paper_2305_19028_amd", "csrc", src + ".hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != blob["source"].get(src):
+            return None
+    k = blob["kernels"].get(name)
+    return None if k is None else (k["read_kib"] + k["write_kib"]) * 1024.0
+
+
 def roofline_of(cls, path, m, n, nnz, entry):
     w = class_work(cls, path, m, n, nnz, entry["launches"])
     if w is None:
@@ -183,7 +219,8 @@ def roofline_of(cls, path, m, n, nnz, entry):
     secs = entry["ms_per_solve"] * 1e-3
     achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
     return {"bound": "hbm" if bound == "hbm" else "alu", "kernel": cls, "achieved": achieved,
-            "peak": peak, "unit": unit, "frac": achieved / peak, "traffic": None,
+            "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": measured_traffic(cls, path),
             "avg_us": entry["avg_us"], "launches_per_solve": entry["launches"],
             "work_per_launch": amount / max(entry["launches"], 1), "work": what}
 
@@ -224,6 +261,13 @@ def main():
     bd = tls.device_vector(b)
 
     if args.profile_only:
+        # a plain device copy of known size first: it calibrates the HBM byte
+        # counters of the profiler against the bytes actually moved
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copied {COPY_BYTES} bytes", flush=True)
         for path in ("fp64", "mixed"):
             for _ in range(max(args.steps, 1)):
                 one_solve(tls, torch, Ad, bd, path)
@@ -255,9 +299,12 @@ def main():
         cpu = cpu_baseline(A, b, args.cpu_seconds)
 
     mixed = res["mixed"]
+    ttt = mixed["time_to_tol_ms"]
     line = {
         "metric": "time to sigma_min/x_TLS at 1e-10 rel err, mixed vs FP64 GPU path; % roofline",
-        "value": mixed["ms_median"],
+        # time from the enqueue of the factorization to the first iterate within
+        # 1e-10 of the reference (first crossing); ms_per_step is the whole solve
+        "value": ttt if ttt is not None else mixed["ms_median"],
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
@@ -272,7 +319,9 @@ def main():
                                "b noise 1e-4, seed 2000",
                    "paths": {"mixed": PATHS["mixed"], "fp64": PATHS["fp64"]}},
         "fp64_path_ms": res["fp64"]["ms_median"],
-        "speedup_vs_fp64": res["fp64"]["ms_median"] / mixed["ms_median"],
+        "speedup_vs_fp64": {
+            "time_to_tol": (res["fp64"]["time_to_tol_ms"] / ttt) if ttt and res["fp64"]["time_to_tol_ms"] else None,
+            "whole_solve": res["fp64"]["ms_median"] / mixed["ms_median"]},
         "time_to_tol_ms": {"mixed": mixed["time_to_tol_ms"], "fp64": res["fp64"]["time_to_tol_ms"]},
         "errors": {p: {"sigma": res[p]["err_sigma"], "x": res[p]["err_x"]} for p in res},
         "rqi_iters": {p: res[p]["rqi_iters"] for p in res},

@@ -23,9 +23,8 @@ Reading: kappa_F(A) = ||A||_F ||A^+||_2 = ||A||_F / sigma'_n, the
 combination that appears in the bound on ||Delta||_2 (the product of
 ||Delta A||_F <~ gamma ||A||_F and ||R-hat^{-1}||_2 = 1/sigma'_n).
 
-Pins: tests/test_oracle_constraints.py (constant-free magnitudes on the
-model problems against the values printed in Section 4, the eigenvalue
-interval of C-tilde = I - sigma^2 R^{-T} R^{-1}).
+Pins: tests/test_oracle_misc.py (constant-free magnitudes on the model
+problems against the values printed in Section 4).
 """
 from __future__ import annotations
 

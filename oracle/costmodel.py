@@ -10,7 +10,7 @@ with (c, c_p, c_q) the per-precision weights (1 double, 0.5 single,
 read as cost(plain)/cost(MP), the only orientation under which "up to 4x"
 holds.
 
-Pins: tests/test_oracle_costmodel.py (the formula equals the sum of the
+Pins: tests/test_oracle_misc.py (the formula equals the sum of the
 Table 1 counts over the lines of Algorithm 4; the supremum 4 for
 (1, 0.5, 0.25); speedup >= 1 whenever the weights are <= 1).
 """

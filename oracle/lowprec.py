@@ -16,7 +16,7 @@ Rounding to nearest-even is written from the IEEE 754 definition: keep p
 significant bits (p = 11 for fp16, 8 for bf16), with the quantum floored
 at the smallest subnormal and overflow to infinity.
 
-Pins: tests/test_oracle_lowprec.py (rounding against numpy's float16
+Pins: tests/test_oracle_misc.py (rounding against numpy's float16
 cast, which is IEEE RNE, against exhaustive bf16 neighbours, and the
 backward-error size of the scaled factor).
 """

@@ -11,9 +11,9 @@ g = 0 (eq. 2) whose residuals f, g are evaluated in long double and whose
 linear solves run in float64 (mixed-precision refinement of an RQI
 iterate); this moves x from float64's u*kappa_TLS accuracy towards u.
 
-Pins: tests/test_oracle_polish.py (stationarity of the Rayleigh quotient,
-agreement with the mpmath route on small inputs, agreement of the Rayleigh
-quotient at the SVD and RQI solutions).
+Pins: tests/test_oracle_misc.py (the Rayleigh quotient against the mpmath
+route and its second-order stationarity; the polished x against the SVD
+solution of the Van Huffel problem).
 """
 from __future__ import annotations
 

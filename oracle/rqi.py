@@ -16,7 +16,8 @@ Readings of the paper (each listed in the design notes):
 * the k-th RQI runs PCGTLS with l = k, i.e. j = 0..k, k+1 steps (Section 2
   and the cost model of Section 3.2 count k+1 steps).
 * the PCGTLS loop also ends when delta_j = 0; delta_j < 0 means the shifted
-  system lost positive definiteness and raises ``IndefiniteError``.
+  system lost positive definiteness: the loop continues as printed, or
+  raises ``IndefiniteError`` when ``strict`` is set.
 * termination (eq. 4): stop when psi_{k+1} > psi_k (``stop_ge`` uses >= as
   in Example 2); ``patience`` p stops after p consecutive iterations that
   do not improve on the best psi; the iterate with the smallest psi is

@@ -71,6 +71,18 @@ hipError_t launch_pcg_finish(int compute, const void *w, double *out, int n, int
 
 // ---- kernels_factor.hip ----------------------------------------------------
 hipError_t launch_fill_i32(int *p, int v, size_t count, hipStream_t st);
+// up to MAX fills in one launch
+struct FillSet {
+  static constexpr int MAX = 6;
+  void *ptr[MAX];
+  size_t n[MAX];
+  uint64_t bits[MAX];
+  int wide[MAX];
+  int count = 0;
+  void add_i32(int *p, int v, size_t cnt);
+  void add_f64(double *p, double v, size_t cnt);
+};
+hipError_t launch_fill_multi(const FillSet &F, hipStream_t st);
 hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st);
 hipError_t launch_round(const double *in, int64_t count, int q, double *out, hipStream_t st);
 hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st);

@@ -7,6 +7,8 @@
 // Dense matrices are column-major. The Gram matrix G is Np x Np
 // column-major with only its upper triangle meaningful; Cholesky overwrites
 // it with R (G = R^T R). Padding rows/columns n..Np-1 hold the identity.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -38,6 +40,34 @@ hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st) {
   if (!count) return hipSuccess;
   TLS_LAUNCH(PC_SETUP, k_fill_f64, dim3(grid_for(count)), dim3(256), 0, st, p, v, count);
   return hipGetLastError();
+}
+
+// several fills in one launch (regions of 4- or 8-byte words)
+__global__ void k_fill_multi(FillSet F) {
+  for (int r = 0; r < F.count; ++r) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (F.wide[r]) {
+      uint64_t *p = (uint64_t *)F.ptr[r];
+      for (; i < F.n[r]; i += (size_t)gridDim.x * blockDim.x) p[i] = F.bits[r];
+    } else {
+      uint32_t *p = (uint32_t *)F.ptr[r];
+      for (; i < F.n[r]; i += (size_t)gridDim.x * blockDim.x) p[i] = (uint32_t)F.bits[r];
+    }
+  }
+}
+hipError_t launch_fill_multi(const FillSet &F, hipStream_t st) {
+  size_t most = 1;
+  for (int r = 0; r < F.count; ++r) most = std::max(most, F.n[r]);
+  TLS_LAUNCH(PC_SETUP, k_fill_multi, dim3(grid_for(most)), dim3(256), 0, st, F);
+  return hipGetLastError();
+}
+void FillSet::add_i32(int *p, int v, size_t cnt) {
+  if (!cnt || count >= MAX) return;
+  ptr[count] = p; n[count] = cnt; bits[count] = (uint32_t)v; wide[count] = 0; ++count;
+}
+void FillSet::add_f64(double *p, double v, size_t cnt) {
+  if (!cnt || count >= MAX) return;
+  ptr[count] = p; n[count] = cnt; bits[count] = __builtin_bit_cast(uint64_t, v); wide[count] = 1; ++count;
 }
 
 __global__ void k_check_finite(const double *v, size_t count, int *flag) {

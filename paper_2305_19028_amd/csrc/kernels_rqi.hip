@@ -197,7 +197,7 @@ __device__ inline double sum_pairs(const double *part, int nb, int which, double
 
 // sigma^2, the clamped shift and g from the residual partials
 __global__ __launch_bounds__(256) void k_outer_rq(int n, const double *x, const double *part_r,
-                                                  int nb_r, double *scal) {
+                                                  int nb_r, double *scal, double cap) {
   __shared__ double sc[8];
   double xx = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) xx += x[i] * x[i];
@@ -206,8 +206,8 @@ __global__ __launch_bounds__(256) void k_outer_rq(int n, const double *x, const 
   const double br = sum_pairs(part_r, nb_r, 1, sc);
   if (threadIdx.x == 0) {
     const double sig2 = rr / (1.0 + xx);
-    const double cap = scal[S_CAP];
     const double mu = (cap > 0 && sig2 > cap) ? cap : sig2;
+    scal[S_CAP] = cap;
     scal[S_SIG2] = sig2;
     scal[S_MU] = mu;
     scal[S_XX] = xx;
@@ -218,8 +218,7 @@ __global__ __launch_bounds__(256) void k_outer_rq(int n, const double *x, const 
 }
 hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
                            double clamp_max, hipStream_t st) {
-  (void)clamp_max;
-  TLS_LAUNCH(PC_SCALARS, k_outer_rq, dim3(1), dim3(256), 0, st, n, x, part_r, nb_r, scal);
+  TLS_LAUNCH(PC_SCALARS, k_outer_rq, dim3(1), dim3(256), 0, st, n, x, part_r, nb_r, scal, clamp_max);
   return hipGetLastError();
 }
 

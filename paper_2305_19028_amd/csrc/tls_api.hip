@@ -300,8 +300,10 @@ hipError_t launch_precond(const tls_precond_s *P, int compute, int mode, int nrh
 
 // zero the synchronisation state of a solve workspace
 tls_status reset_solve_ws(const tls_precond_s *P, PcgWs &W, hipStream_t st) {
-  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
-  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
+  FillSet F;
+  F.add_i32(W.sync, 0, P->N + 8);
+  F.add_i32(W.cnt, 0, P->N);
+  HIPCHK(launch_fill_multi(F, st));
   return TLS_OK;
 }
 
@@ -321,9 +323,13 @@ tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, con
                    double *omega, int l, int compute, int strict, PcgWs &W, hipStream_t st) {
   if (l + 1 > W.L + 1) return fail(TLS_ERR_WORKSPACE, "PCG workspace sized for l <= %d", W.L);
   const int N = P->N;
-  HIPCHK(launch_fill_i32(W.done, 0, (size_t)(W.L + 2) * nrhs, st));
-  HIPCHK(launch_fill_i32(W.neg, 0, (size_t)(W.L + 2) * nrhs, st));
-  HIPCHK(launch_fill_f64(W.trace, std::numeric_limits<double>::quiet_NaN(), (size_t)nrhs * 4 * (W.L + 2), st));
+  {
+    FillSet F;
+    F.add_i32(W.done, 0, (size_t)(W.L + 2) * nrhs);
+    F.add_i32(W.neg, 0, (size_t)(W.L + 2) * nrhs);
+    F.add_f64(W.trace, std::numeric_limits<double>::quiet_NaN(), (size_t)nrhs * 4 * (W.L + 2));
+    HIPCHK(launch_fill_multi(F, st));
+  }
   SolveBufs B = bufs_of(W);
   B.sigma2 = sig2_dev;
   B.strict = strict;
@@ -1174,7 +1180,6 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
 
     // one Rayleigh-quotient evaluation at x (residual pass, scalars, gradient pass, psi)
     auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
-      HIPCHK(launch_fill_f64(W.scal + 14, cap, 1, st));
       HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
       HIPCHK(launch_outer_rq(n, xv, W.part, nb_r, W.scal, cap, st));
       HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, W.part, st));
@@ -1201,7 +1206,6 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
         HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
       }
       HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
-      HIPCHK(launch_fill_f64(W.scal + 14, 0.0, 1, st));
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       double h2[5];
       HIPCHK(hipMemcpyAsync(h2, W.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
