@@ -115,6 +115,17 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// 1/sqrt(p) from the hardware estimate refined by one Newton step
+// y <- y (3 - p y^2) / 2 (relative error about the square of the estimate's)
+__device__ inline float rsqrt_nr(float p) {
+  const float y = __builtin_amdgcn_rsqf(p);
+  return y * (1.5f - 0.5f * p * y * y);
+}
+__device__ inline double rsqrt_nr(double p) {
+  const double y = __builtin_amdgcn_rsq(p);
+  return y * (1.5 - 0.5 * p * y * y);
+}
+
 // sum over a 256-thread block; result valid in every thread
 template <typename T>
 __device__ inline T block_sum(T v, T *scratch /* >= 4 */) {

@@ -37,6 +37,7 @@ struct FactorView {
   // explicit inverse X = R_hat^{-1} (row-packed tiles of X and of X^T)
   const void *xr, *xc;
   int xstorage;
+  int xrow;                 // 1: one workgroup per block row; 0: split over the chip
 };
 
 // buffers of one triangular-solve / PCGTLS launch
@@ -144,8 +145,9 @@ hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream
 hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st);
 // f = -A^T r - shift x with shift read from scal; partial f.f per block
 int rmatvec_blocks(const MatView &A);
-hipError_t launch_gradient(const MatView &A, const double *r, const double *x,
-                           const double *shift, double *f, double *part, hipStream_t st);
+hipError_t launch_gradient(const MatView &A, const double *r, const double *x, double *scal,
+                           double *f, double *part, const double *part_r, int nb_r, double cap,
+                           hipStream_t st);
 // compensated residual r = b - A x in double-double, partial sums (hi/lo) of r.r
 hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x, double *part,
                               hipStream_t st);
@@ -154,8 +156,9 @@ hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x
 struct OuterScalars;   // device struct, see kernels_rqi.hip
 hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
                            double clamp_max, hipStream_t st);
-hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f,
-                            int nb_f, double *scal, int k, double *rec, hipStream_t st);
+hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
+                            double *scal, int k, double *rec, double *rhs, double *xbest,
+                            hipStream_t st);
 hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st);
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
                              const double *scal, double *xbest, double *xsnap, hipStream_t st);

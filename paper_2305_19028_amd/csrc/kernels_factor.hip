@@ -799,8 +799,8 @@ __global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *in
       for (int s = 0; s < 4; ++s) {
         const C p = d[s][s];
         if (!(p > (C)0) && !badrow) badrow = s + 1;
-        const C rs = sqrt(p);
-        inv[s] = (C)1 / rs;
+        inv[s] = rsqrt_nr(p);          // one instruction plus a Newton step on the chain
+        const C rs = p * inv[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) rd[s][t] = (t == s) ? rs : (t > s ? d[s][t] * inv[s] : (C)0);
 #pragma unroll

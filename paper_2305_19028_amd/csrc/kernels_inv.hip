@@ -253,15 +253,23 @@ __device__ inline C xsum_parts(const C *p, int N) {
 
 enum XMode { XA = 0, XF0 = 2, XB = 3, XF = 4 };   // XA: plain apply
 
-template <typename SX, typename C, int NR, int MODE, int TRANS>
-__global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
-  __shared__ C s_v[4][NR][NB];       // per-wave input block
-  __shared__ C s_acc[4][NR][NB];
+// ROW = 0: grid (N, CH), four waves, one tile per wave, chunk partials
+//          reduced by the last workgroup of each block (split over the chip;
+//          measured faster for n up to about 2000);
+// ROW = 1: grid (N), XW waves per workgroup, each wave streams every XW-th
+//          tile of the block row; no cross-workgroup reduction (measured
+//          faster in the PCG modes at n = 4096).
+constexpr int XW = 4;
+template <typename SX, typename C, int NR, int MODE, int TRANS, int ROW>
+__global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P) {
+  constexpr int NW = ROW ? XW : 4;
+  __shared__ C s_v[NW][NR][NB];      // per-wave input block
+  __shared__ C s_acc[NW][NR][NB];
   __shared__ C s_scal[NR][4];
   __shared__ int s_live[NR], s_last, s_skip;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
-  const int I = blockIdx.x, sidx = blockIdx.y, CH = gridDim.y;
+  const int I = blockIdx.x, sidx = ROW ? 0 : blockIdx.y, CH = ROW ? 1 : gridDim.y;
   // pbuf of the current p (step j) and of the previous one
   C *p_cur = (P.j & 1) ? P.pb1 : P.pb0;
   C *p_old = (P.j & 1) ? P.pb0 : P.pb1;
@@ -271,23 +279,23 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
   // (a) this wave's tile: one tile per wave (chunk <= 4); lane = tile row
   const int K_lo = TRANS ? 0 : I;               // input blocks feeding output block I
   const int K_hi = TRANS ? I + 1 : N;
-  const int K = K_lo + sidx * P.chunk + w;
-  const bool has_tile = (w < P.chunk) && (K < K_hi);
+  const int k_end = ROW ? K_hi : min(K_hi, K_lo + sidx * P.chunk + P.chunk);
+  int K = K_lo + sidx * (ROW ? 0 : P.chunk) + w;
+  bool has_tile = K < k_end;
   SX t[NB];
-  if (has_tile) {
-    const SX *T = P.X + (TRANS ? xc_tile(I, K) : xr_tile(I, K, N)) * NB * NB + (size_t)lane * NB;
+  C in_a[NR], in_b[NR], in_ds = (C)0;
+  // tile K's row for this lane and the inputs of block K (combined with the
+  // step scalars later)
+  auto load_tile = [&](int Kt) {
+    const SX *T = P.X + (TRANS ? xc_tile(I, Kt) : xr_tile(I, Kt, N)) * NB * NB + (size_t)lane * NB;
 #pragma unroll
     for (int c = 0; c < NB; ++c) t[c] = T[c];
-  }
-  // (b) the inputs of block K (combined with the step scalars below)
-  const int row = K * NB + lane;
-  C in_a[NR], in_b[NR], in_ds = (C)0;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) { in_a[r] = (C)0; in_b[r] = (C)0; }
-  if (has_tile) {
+    const int row = Kt * NB + lane;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const size_t vi = (size_t)r * Np + row;
+      in_a[r] = (C)0;
+      in_b[r] = (C)0;
       if constexpr (MODE == XA || MODE == XF0) {
         in_a[r] = (row < P.n) ? (C)P.in[(size_t)r * P.ldi + row] : (C)0;
       } else if constexpr (MODE == XB) {
@@ -298,7 +306,10 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
       }
     }
     if constexpr (TRANS) in_ds = P.dscale[row];
-  }
+  };
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { in_a[r] = (C)0; in_b[r] = (C)0; }
+  if (has_tile) load_tile(K);
   // (c) the rows of output block I that the epilogue needs (wave 0)
   const int orow = I * NB + lane;
   C e_s[NR], e_p[NR], e_po[NR], e_q[NR], e_w[NR], e_ds = (C)0;
@@ -359,7 +370,10 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
   C acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0;
-  if (has_tile) {
+  bool first = true;
+  while (has_tile) {
+    if (!first) load_tile(K);   // later tiles of the row variant
+    first = false;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       C v;
@@ -378,18 +392,27 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] += tc * s_v[w][r][c];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    K += NW;
+    has_tile = ROW && K < k_end;
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) s_acc[w][r][lane] = acc[r];
   __syncthreads();
 
-  // ---- chunk reduction ----------------------------------------------------
+  // ---- reduction over the waves (and, split, over the chunk workgroups) ----
   C res[NR];
   if (CH == 1) {
     if (w == 0) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        res[r] = (s_acc[0][r][lane] + s_acc[1][r][lane]) + (s_acc[2][r][lane] + s_acc[3][r][lane]);
+      for (int r = 0; r < NR; ++r) {
+        C v = s_acc[0][r][lane];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) v += s_acc[q][r][lane];
+        res[r] = v;
+      }
     }
   } else {
     C *mine = P.cpart + (((size_t)I * CH + sidx) * NR) * NB;
@@ -490,8 +513,12 @@ __global__ __launch_bounds__(256) void k_xapply(XParams<SX, C> P) {
 
 template <typename SX, typename C, int NR, int MODE, int TRANS>
 static hipError_t xlaunch(const XParams<SX, C> &P, int CH, hipStream_t st) {
-  TLS_LAUNCH(MODE == XA ? PC_TRSV_APPLY : PC_PCG, (k_xapply<SX, C, NR, MODE, TRANS>),
-             dim3(P.N, CH), dim3(256), 0, st, P);
+  if (CH == 0)   // one workgroup per block row
+    TLS_LAUNCH(MODE == XA ? PC_TRSV_APPLY : PC_PCG, (k_xapply<SX, C, NR, MODE, TRANS, 1>),
+               dim3(P.N), dim3(64 * XW), 0, st, P);
+  else
+    TLS_LAUNCH(MODE == XA ? PC_TRSV_APPLY : PC_PCG, (k_xapply<SX, C, NR, MODE, TRANS, 0>),
+               dim3(P.N, CH), dim3(256), 0, st, P);
   return hipGetLastError();
 }
 
@@ -547,7 +574,7 @@ static hipError_t x_dispatch(const FactorView &F, int mode, int trans, int nrhs,
     P.cpart = (C *)B.cpart;
     P.cnt = B.cnt;
     P.status = B.sync + F.N + 3;
-    const int CH = (F.N + P.chunk - 1) / P.chunk;
+    const int CH = F.xrow ? 0 : (F.N + P.chunk - 1) / P.chunk;
     return x_mode<SX, C>(mode, trans, nrhs, P, CH, st);
   };
   const void *X = trans ? F.xc : F.xr;

@@ -139,13 +139,42 @@ hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStrea
 // ---------------------------------------------------------------------------
 // f = -A^T r - mu x with partials of f.f and f.x (one wave per column)
 // ---------------------------------------------------------------------------
+__device__ inline double sum_pairs(const double *part, int nb, int which, double *sc);
+
+// sigma^2 = rr / (1 + x^T x), the clamped shift mu and g = -b^T r + mu from the
+// residual partials (every workgroup of the gradient computes the same values
+// in the same order; workgroup 0 records them)
+__device__ inline double rq_scalars(int n, const double *x, const double *part_r, int nb_r,
+                                    double *scal, double cap, double *sc) {
+  double xx = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) xx += x[i] * x[i];
+  xx = block_sum(xx, sc);
+  const double rr = sum_pairs(part_r, nb_r, 0, sc + 4);
+  const double br = sum_pairs(part_r, nb_r, 1, sc);
+  const double sig2 = rr / (1.0 + xx);
+  const double mu = (cap > 0 && sig2 > cap) ? cap : sig2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_SIG2] = sig2;
+    scal[S_MU] = mu;
+    scal[S_XX] = xx;
+    scal[S_RR] = rr;
+    scal[S_BR] = br;
+    scal[S_G] = -br + mu;
+    scal[S_CAP] = cap;
+  }
+  return mu;
+}
+
 template <bool CSC>
 __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, const double *A,
                                                   const int32_t *col_ptr, const int32_t *row_idx,
                                                   const double *cval, const double *r,
-                                                  const double *x, const double *scal, double *f,
-                                                  double *part) {
+                                                  const double *x, double *scal, double *f,
+                                                  double *part, const double *part_r, int nb_r,
+                                                  double cap) {
   __shared__ double sff[4], sfx[4];
+  __shared__ double sc[8];
+  const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + w;
   double fv = 0, xv = 0;
@@ -163,7 +192,7 @@ __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, cons
     }
     acc = wave_sum(acc);
     xv = x[j];
-    fv = -acc - scal[S_MU] * xv;
+    fv = -acc - mu * xv;
     if (lane == 0) f[j] = fv;
   }
   if (lane == 0) { sff[w] = fv * fv; sfx[w] = fv * xv; }
@@ -174,15 +203,16 @@ __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, cons
   }
 }
 
-hipError_t launch_gradient(const MatView &A, const double *r, const double *x, const double *scal,
-                           double *f, double *part, hipStream_t st) {
+hipError_t launch_gradient(const MatView &A, const double *r, const double *x, double *scal,
+                           double *f, double *part, const double *part_r, int nb_r, double cap,
+                           hipStream_t st) {
   const dim3 g(rmatvec_blocks(A));
   if (A.format == TLS_DENSE_COLMAJOR)
     TLS_LAUNCH(PC_GRADIENT, k_gradient<false>, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, nullptr,
-                       nullptr, nullptr, r, x, scal, f, part);
+                       nullptr, nullptr, r, x, scal, f, part, part_r, nb_r, cap);
   else
     TLS_LAUNCH(PC_GRADIENT, k_gradient<true>, g, dim3(256), 0, st, A.m, A.n, (int64_t)0, nullptr,
-                       A.col_ptr, A.row_idx, A.cval, r, x, scal, f, part);
+                       A.col_ptr, A.row_idx, A.cval, r, x, scal, f, part, part_r, nb_r, cap);
   return hipGetLastError();
 }
 
@@ -224,8 +254,11 @@ hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_
 
 // psi_k from the gradient partials; best-psi bookkeeping; record (sigma, psi, mu)
 __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, int nb_f,
-                                                   double *scal, int k, double *rec) {
+                                                   double *scal, int k, double *rec,
+                                                   const double *x, const double *f, double *rhs,
+                                                   double *xbest) {
   __shared__ double sc[8];
+  __shared__ int s_best;
   const double ff = sum_pairs(part_f, nb_f, 0, sc);
   const double fx = sum_pairs(part_f, nb_f, 1, sc + 4);
   if (threadIdx.x == 0) {
@@ -246,12 +279,22 @@ __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, 
     rec[4 * (k - 1) + 1] = psi;
     rec[4 * (k - 1) + 2] = mu;
     rec[4 * (k - 1) + 3] = isbest;
+    s_best = isbest;
+  }
+  __syncthreads();
+  // the next PCGTLS right-hand sides [-f, x], and the best iterate so far
+  const bool keep = s_best && xbest;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double xi = x[i];
+    if (rhs) { rhs[i] = -f[i]; rhs[n + i] = xi; }
+    if (keep) xbest[i] = xi;
   }
 }
 hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
-                            double *scal, int k, double *rec, hipStream_t st) {
-  (void)x; (void)f; (void)n;
-  TLS_LAUNCH(PC_SCALARS, k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec);
+                            double *scal, int k, double *rec, double *rhs, double *xbest,
+                            hipStream_t st) {
+  TLS_LAUNCH(PC_SCALARS, k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec, x, f,
+             rhs, xbest);
   return hipGetLastError();
 }
 
@@ -462,26 +505,29 @@ hipError_t launch_sigma_dd(int n, const double *x, const double *part, int nb, d
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos step bookkeeping (gate estimates), two recurrences at once (one
-// workgroup each): run 0 on M_s = R_hat^{-1} R_hat^{-T}, run 1 on
+// Lanczos step bookkeeping (gate estimates), up to two recurrences at once
+// (one workgroup each): run 0 on M_s = R_hat^{-1} R_hat^{-T}, run 1 on
 // M = D^{-1} M_s D^{-1} = (R^T R)^{-1}. The device applies M_s to the pair
-// [v0_k, D^{-1} v1_k]; here w1 = D^{-1} (M_s D^{-1} v1_k). Each run is
-// reorthogonalised against its basis by classical Gram-Schmidt applied
-// twice; alpha_k from the first pass, beta_k = ||w||, v_{k+1} = w / beta_k,
-// and the next operator input (D^{-1} v1_{k+1} for run 1) is written to
-// `nxt`. Layout: V[run][K+1][Np]; ab[run][2K+2]: alpha, beta, active, steps.
+// [v0_k, D^{-1} v1_k]; here w1 = D^{-1} (M_s D^{-1} v1_k). The three-term
+// recurrence orthogonalises w against v_k and v_{k-1} by classical
+// Gram-Schmidt applied twice (enough for the extreme Ritz values after the
+// dozen steps the gate takes); alpha_k from the first pass,
+// beta_k = ||w||, v_{k+1} = w / beta_k, and the next operator input
+// (D^{-1} v1_{k+1} for run 1) is written to `nxt`.
+// Layout: V[run][K+1][Np]; ab[run][2K+2]: alpha, beta, active, steps.
 // ---------------------------------------------------------------------------
-constexpr int LZ_MAX = 32;
 __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int K, double *V,
                                                        const double *Wout, double *nxt,
                                                        const double *dsc, double *ab) {
-  __shared__ double red[16][LZ_MAX + 1];
-  __shared__ double h[LZ_MAX + 1];
+  __shared__ double red[16][2];
+  __shared__ double h[2];
   const int run = blockIdx.x;
   double *Vr = V + (size_t)run * (K + 1) * Np;
   double *abr = ab + (size_t)run * (2 * K + 2);
   if (abr[2 * K] == 0.0) return;        // this run stopped earlier (uniform per block)
   double *w = Vr + (size_t)(k + 1) * Np;
+  const double *vk = Vr + (size_t)k * Np;
+  const double *vp = (k > 0) ? Vr + (size_t)(k - 1) * Np : nullptr;
   const double *src = Wout + (size_t)run * Np;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = blockDim.x >> 6;
@@ -489,36 +535,26 @@ __global__ __launch_bounds__(1024) void k_lanczos_orth(int n, int Np, int k, int
   __syncthreads();
   double alpha = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    double acc[LZ_MAX + 1];
-#pragma unroll
-    for (int i = 0; i <= LZ_MAX; ++i) acc[i] = 0;
+    double a0 = 0, a1 = 0;
     for (int j = tid; j < n; j += blockDim.x) {
       const double wj = w[j];
-#pragma unroll
-      for (int i = 0; i <= LZ_MAX; ++i)
-        if (i <= k) acc[i] += Vr[(size_t)i * Np + j] * wj;
+      a0 += vk[j] * wj;
+      if (vp) a1 += vp[j] * wj;
     }
-#pragma unroll
-    for (int i = 0; i <= LZ_MAX; ++i) {
-      if (i <= k) {
-        const double v = wave_sum(acc[i]);
-        if (lane == 0) red[wv][i] = v;
-      }
-    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) { red[wv][0] = a0; red[wv][1] = a1; }
     __syncthreads();
-    if (tid <= k) {
+    if (tid < 2) {
       double t = 0;
       for (int q = 0; q < nw; ++q) t += red[q][tid];
       h[tid] = t;
     }
     __syncthreads();
-    if (pass == 0) alpha = h[k];
-    for (int j = tid; j < n; j += blockDim.x) {
-      double wj = w[j];
-      for (int i = 0; i <= k; ++i) wj -= h[i] * Vr[(size_t)i * Np + j];
-      w[j] = wj;
-    }
-    __syncthreads();
+    const double hk = h[0], hp = h[1];
+    if (pass == 0) alpha = hk;
+    for (int j = tid; j < n; j += blockDim.x) w[j] -= hk * vk[j] + (vp ? hp * vp[j] : 0.0);
+    __syncthreads();   // w complete; red and h are rewritten next
   }
   double nn = 0;
   for (int j = tid; j < n; j += blockDim.x) nn += w[j] * w[j];

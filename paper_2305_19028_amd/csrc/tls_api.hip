@@ -100,7 +100,7 @@ struct tls_precond_s {
   tls_gate_report rep{};
   void *xr = nullptr, *xc = nullptr;   // explicit inverse tiles
   int xstorage = TLS_FP64;
-  int apply_mode = 0;             // 0 explicit inverse, 1 substitution
+  int apply_mode = 0;             // 0 explicit inverse (split GEMV), 1 substitution, 2 row GEMV
   void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
   int64_t fws_m = 0;
   int fws_cast = 0;               // the factor workspace holds a cast buffer
@@ -122,6 +122,7 @@ struct tls_precond_s {
     F.xr = xr;
     F.xc = xc;
     F.xstorage = xstorage;
+    F.xrow = (apply_mode == 2);
     return F;
   }
 };
@@ -294,7 +295,7 @@ tls_status sync_status(const int *sync, int N, hipStream_t st) {
 
 hipError_t launch_precond(const tls_precond_s *P, int compute, int mode, int nrhs,
                           const SolveBufs &B, hipStream_t st) {
-  if (P->apply_mode == 0 && P->xr) return launch_xapply(P->view(), compute, mode, nrhs, B, st);
+  if (P->apply_mode != 1 && P->xr) return launch_xapply(P->view(), compute, mode, nrhs, B, st);
   return launch_trsv(P->view(), compute, mode, nrhs, B, st);
 }
 
@@ -502,7 +503,7 @@ void tls_precond_destroy(tls_precond P) { delete P; }
 
 tls_status tls_precond_set_apply(tls_precond P, int32_t mode) {
   if (!P) return fail(TLS_ERR_ARG, "P is NULL");
-  if (mode != 0 && mode != 1) return fail(TLS_ERR_ARG, "apply mode must be 0 or 1");
+  if (mode < 0 || mode > 2) return fail(TLS_ERR_ARG, "apply mode must be 0, 1 or 2");
   P->apply_mode = mode;
   return TLS_OK;
 }
@@ -1004,7 +1005,7 @@ RqiWs carve_rqi(Carver &c, int64_t m, int64_t n, const tls_precond_s *P, int kma
   W.wu = c.take<double>(2 * n);
   W.t1 = c.take<double>(n);
   W.t2 = c.take<double>(n);
-  W.part = c.take<double>(2 * (size_t)nb);
+  W.part = c.take<double>(4 * (size_t)nb);   // residual and gradient partials
   W.scal = c.take<double>(48);
   W.rec = c.take<double>(4 * (size_t)(kmax + 8));
   W.rr = c.take<double>(2 * n);
@@ -1179,11 +1180,14 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     if (bad) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
 
     // one Rayleigh-quotient evaluation at x (residual pass, scalars, gradient pass, psi)
+    // residual partials -> (gradient with the Rayleigh-quotient scalars) ->
+    // (psi, the next right-hand sides [-f, x], and x into xbest when psi is
+    // the smallest so far): three launches
+    double *part_f = W.part + 2 * (size_t)nb_r;
     auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
       HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
-      HIPCHK(launch_outer_rq(n, xv, W.part, nb_r, W.scal, cap, st));
-      HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, W.part, st));
-      HIPCHK(launch_outer_psi(n, xv, W.f, W.part, nb_f, W.scal, k, W.rec, st));
+      HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
+      HIPCHK(launch_outer_psi(n, xv, W.f, part_f, nb_f, W.scal, k, W.rec, W.rhs, W.xbest, st));
       return TLS_OK;
     };
     auto evaluate = [&](int k, double cap) -> tls_status { return evaluate_at(x, k, cap); };
@@ -1340,19 +1344,18 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       S.t_ms[k - 1] = ms_since(t0);
       if (h[1] != h[0]) S.clamped++;
       if (!std::isfinite(psi)) return fail(TLS_ERR_NO_CONVERGENCE, "psi became non-finite at k = %d", k);
-      if (psi < best) {
+      if (psi < best) {          // the psi kernel has copied x to xbest
         best = psi;
         S.k_best = k;
         no_improve = 0;
-        HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
       } else if (o->stop_ge ? (psi >= best) : (psi > best)) {
         ++no_improve;
       }
       if (psi == 0.0) { S.stopped = 2; break; }
       if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
       if (k == kmax) break;
-      // two PCGTLS solves with l = k (k+1 steps), sharing the shift
-      HIPCHK(launch_make_rhs(n, W.f, x, W.rhs, st));
+      // two PCGTLS solves with l = k (k+1 steps), sharing the shift; the
+      // right-hand sides [-f, x] were written by the psi kernel
       TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, k, o->u_p, o->strict_pd, W.pcg, st));
       S.pcg_steps += k + 1;
       HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));

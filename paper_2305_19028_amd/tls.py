@@ -280,8 +280,9 @@ class Precond:
         return n.value
 
     def set_apply(self, mode):
-        """0: explicit-inverse GEMV (default), 1: blocked substitution."""
-        m = {"inverse": 0, "substitution": 1}.get(mode, mode)
+        """0: explicit-inverse GEMV split over the chip (default);
+        1: blocked substitution; 2: explicit-inverse GEMV, one workgroup per block row."""
+        m = {"inverse": 0, "substitution": 1, "inverse_rows": 2}.get(mode, mode)
         _check(lib().tls_precond_set_apply(self.handle, int(m)))
 
     def info(self):

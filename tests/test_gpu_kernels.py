@@ -65,7 +65,7 @@ def _tri(n, seed, cond=10.0):
     return R
 
 
-@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("mode", ["inverse", "inverse_rows", "substitution"])
 @pytest.mark.parametrize("n", [5, 64, 100, 257, 1000, 3100])
 @pytest.mark.parametrize("nrhs", [1, 2])
 def test_triangular_solves_fp64(n, nrhs, mode):
@@ -84,7 +84,7 @@ def test_triangular_solves_fp64(n, nrhs, mode):
             assert np.linalg.norm(out[r] - ref) <= 1e-12 * np.linalg.norm(ref), (trans, r)
 
 
-@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("mode", ["inverse", "inverse_rows", "substitution"])
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("u_p", ["fp64", "fp32"])
 def test_triangular_solves_low_storage(storage, u_p, mode):
@@ -105,7 +105,7 @@ def test_triangular_solves_low_storage(storage, u_p, mode):
             assert np.linalg.norm(out[r] - ref) <= tol * np.linalg.norm(ref) * 10, (trans, r)
 
 
-@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("mode", ["inverse", "inverse_rows", "substitution"])
 @pytest.mark.parametrize("n,l", [(20, 0), (20, 3), (130, 5), (700, 8), (3100, 3)])
 def test_pcg_step_matches_algorithm3(n, l, mode):
     tls = _tls()
@@ -134,7 +134,7 @@ def test_pcg_step_matches_algorithm3(n, l, mode):
         assert np.linalg.norm(out32[r] - w) <= 1e-4 * np.linalg.norm(w)
 
 
-@pytest.mark.parametrize("mode", ["inverse", "substitution"])
+@pytest.mark.parametrize("mode", ["inverse", "inverse_rows", "substitution"])
 def test_pcg_sigma_zero_and_single_rhs(mode):
     tls = _tls()
     A, b, _ = tlsgen.dense_gaussian(90, 30, seed=3)
