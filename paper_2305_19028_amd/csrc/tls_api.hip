@@ -192,8 +192,8 @@ struct FactorWs {
   double *tm;      // m-vector (products with A in the certificate)
   void *cast;      // dense A rounded to u_q (matrix-core Gram input), or NULL
 };
-constexpr int LANCZOS_STEPS = 12;
-constexpr int QUALITY_STEPS = 8;
+constexpr int LANCZOS_STEPS = 8;
+constexpr int QUALITY_STEPS = 6;
 
 FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast) {
   const int Np = ceil_div(n, NB) * NB, N = Np / NB;
