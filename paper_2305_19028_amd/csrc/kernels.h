@@ -74,7 +74,7 @@ hipError_t launch_pcg_finish(int compute, const void *w, double *out, int n, int
 hipError_t launch_fill_i32(int *p, int v, size_t count, hipStream_t st);
 // up to MAX fills in one launch
 struct FillSet {
-  static constexpr int MAX = 6;
+  static constexpr int MAX = 8;
   void *ptr[MAX];
   size_t n[MAX];
   uint64_t bits[MAX];
@@ -184,6 +184,7 @@ struct DotPairs {
 hipError_t launch_dots(const DotPairs &D, int count, double *out, hipStream_t st);
 hipError_t launch_axpy2(int n, const double *x0, const double *u0, const double *u1, double c1,
                         double c2, double *out, hipStream_t st);
+hipError_t launch_scale_copy(int n, const double *src, double alpha, double *dst, hipStream_t st);
 // ---- kernels_mlp.hip --------------------------------------------------------
 // activations of a training batch of B samples (row-major, B x width)
 struct MlpBufs {

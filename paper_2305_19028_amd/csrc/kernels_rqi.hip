@@ -677,6 +677,14 @@ __global__ void k_axpy2(int n, const double *x0, const double *u0, const double 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = x0[i] + (c1 * u0[i] + c2 * u1[i]);
 }
+__global__ void k_scale_copy(int n, const double *src, double alpha, double *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = alpha * src[i];
+}
+hipError_t launch_scale_copy(int n, const double *src, double alpha, double *dst, hipStream_t st) {
+  TLS_LAUNCH(PC_SETUP, k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, st, n, src, alpha, dst);
+  return hipGetLastError();
+}
 hipError_t launch_axpy2(int n, const double *x0, const double *u0, const double *u1, double c1,
                         double c2, double *out, hipStream_t st) {
   TLS_LAUNCH(PC_SCALARS, k_axpy2, dim3((n + 255) / 256), dim3(256), 0, st, n, x0, u0, u1, c1, c2, out);

@@ -559,29 +559,34 @@ tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *st
   S.L = 0;
   S.cpart = W.yinv;     // free after the inversion
   S.cnt = W.cnt;
-  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
-  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
   double *ab = W.lzs;                                 // [2][2K+2]
   tls_precond_s Q = *P;
-  HIPCHK(launch_fill_f64(ones, 1.0, (size_t)Np, st));
   Q.dsc64 = ones;                                     // apply R_hat alone
   // v_0 = ones/sqrt(n) for both runs; operator input [v0, D^{-1} v0]
   const double v0 = 1.0 / std::sqrt((double)n);
-  HIPCHK(launch_fill_f64(V, v0, (size_t)n, st));
-  HIPCHK(launch_fill_f64(V + (size_t)(K + 1) * Np, v0, (size_t)n, st));
-  HIPCHK(launch_fill_f64(inb, v0, (size_t)n, st));
-  HIPCHK(launch_fill_f64(inb + Np, 0.0, (size_t)n, st));
-  HIPCHK(launch_axpy_init(n, inb + Np, P->dsc64, nullptr, -1, st));   // D^{-1} * 1
   {
-    // scale by v0: inb[1] = v0 * dsc (axpy wrote dsc); reuse copy + axpy with a device scalar
-    HIPCHK(launch_fill_f64(ab, v0, 1, st));
-    HIPCHK(launch_fill_f64(tmp, 0.0, (size_t)n, st));
-    HIPCHK(launch_axpy_init(n, tmp, inb + Np, ab, 0, st));
-    HIPCHK(launch_copy_f64(inb + Np, tmp, (size_t)n, st));
+    FillSet F;
+    F.add_i32(W.sync, 0, P->N + 8);
+    F.add_i32(W.cnt, 0, P->N);
+    F.add_f64(ones, 1.0, (size_t)Np);
+    F.add_f64(V, v0, (size_t)n);
+    F.add_f64(V + (size_t)(K + 1) * Np, v0, (size_t)n);
+    F.add_f64(inb, v0, (size_t)n);
+    HIPCHK(launch_fill_multi(F, st));
   }
-  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (2 * (size_t)K + 2), st));
-  HIPCHK(launch_fill_f64(ab + 2 * K, 1.0, 1, st));
-  HIPCHK(launch_fill_f64(ab + (2 * K + 2) + 2 * K, 1.0, 1, st));
+  HIPCHK(launch_scale_copy(n, P->dsc64, v0, inb + Np, st));           // v0 D^{-1} 1
+  {
+    // per run: alpha, beta = 0, active = 1, steps = 0 (disjoint regions)
+    FillSet F;
+    for (int run = 0; run < 2; ++run) {
+      double *abr = ab + (size_t)run * (2 * K + 2);
+      F.add_f64(abr, 0.0, 2 * (size_t)K);
+      F.add_f64(abr + 2 * K, 1.0, 1);
+      F.add_f64(abr + 2 * K + 1, 0.0, 1);
+    }
+    HIPCHK(launch_fill_multi(F, st));
+  }
+  (void)tmp;
   // the apply kernels read [nrhs][n]-packed inputs: pack with stride n
   for (int k = 0; k < K; ++k) {
     TRY(apply_R(&Q, 1, 2, inb, tmp, TLS_FP64, S, st, Np));
@@ -637,14 +642,19 @@ tls_status factor_quality(tls_precond_s *P, FactorWs &W, const MatView &V, hipSt
   S.L = 0;
   S.cpart = W.yinv;
   S.cnt = W.cnt;
-  HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, st));
-  HIPCHK(launch_fill_i32(W.cnt, 0, P->N, st));
   double *ab = W.lzs;
   const double v0 = 1.0 / std::sqrt((double)n);
-  HIPCHK(launch_fill_f64(Vb, v0, (size_t)n, st));
-  HIPCHK(launch_fill_f64(inb, v0, (size_t)n, st));
-  HIPCHK(launch_fill_f64(ab, 0.0, 2 * (size_t)K + 2, st));
-  HIPCHK(launch_fill_f64(ab + 2 * K, 1.0, 1, st));
+  {
+    FillSet F;
+    F.add_i32(W.sync, 0, P->N + 8);
+    F.add_i32(W.cnt, 0, P->N);
+    F.add_f64(Vb, v0, (size_t)n);
+    F.add_f64(inb, v0, (size_t)n);
+    F.add_f64(ab, 0.0, 2 * (size_t)K);
+    F.add_f64(ab + 2 * K, 1.0, 1);
+    F.add_f64(ab + 2 * K + 1, 0.0, 1);
+    HIPCHK(launch_fill_multi(F, st));
+  }
   for (int k = 0; k < K; ++k) {
     TRY(apply_R(P, 0, 1, inb, tmp, TLS_FP64, S, st));      // R^{-1} v
     HIPCHK(launch_matvec(V, tmp, W.tm, st));                 // A R^{-1} v
@@ -1169,15 +1179,18 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     tls_rqi_stats &S = stats ? *stats : local;
     std::memset(&S, 0, sizeof S);
 
-    TRY(reset_solve_ws(P, W.pcg, st));
-    HIPCHK(launch_fill_f64(W.scal, 0.0, 48, st));
-    // finite b
-    HIPCHK(launch_fill_i32(W.pcg.done, 0, 1, st));
+    {
+      FillSet F;
+      F.add_i32(W.pcg.sync, 0, P->N + 8);
+      F.add_i32(W.pcg.cnt, 0, P->N);
+      F.add_f64(W.scal, 0.0, 48);
+      F.add_i32(W.pcg.done, 0, 1);
+      HIPCHK(launch_fill_multi(F, st));
+    }
+    // finite b: the flag is read back with sigma_0 below (NaN or Inf on the
+    // way produce no fault, only values that are then discarded)
     HIPCHK(launch_check_finite(b, (size_t)A->m, W.pcg.done, st));
-    int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (bad) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
+    int bad_b = 0;
 
     // one Rayleigh-quotient evaluation at x (residual pass, scalars, gradient pass, psi)
     // residual partials -> (gradient with the Rayleigh-quotient scalars) ->
@@ -1213,7 +1226,9 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       double h2[5];
       HIPCHK(hipMemcpyAsync(h2, W.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(&bad_b, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      if (bad_b) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
       S.sigma_ls = std::sqrt(h2[0]);
       rr0 = h2[3];
       if (!(o->gate_enforce && P->storage != TLS_FP64)) break;
