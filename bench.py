@@ -3,19 +3,26 @@ mixed-precision path vs the plain FP64 GPU path, with the roofline of the
 dominant kernel and the CPU oracle timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                    [--workload sparse_20000x2000 | dense_planted_65536x4096]
 
-Workload: sparse CSR A 20000 x 2000 with 0.5% nonzeros at uniformly random
-positions, N(0,1) values times log-uniform column scales in [1, 1e4],
-b = A x_true + 1e-4 N(0,1) (seed 2000), resident on the device.
-
-One step = one whole solve: tls_factor_precond (CSC copy, scaling, Gram,
-Cholesky, packing, gate) + tls_rqi_solve (x_LS, initial inverse step, the
-RQI loop with two PCGTLS solves per iteration, final compensated sigma).
+Default workload: sparse CSR A 20000 x 2000 with 0.5% nonzeros at uniformly
+random positions, N(0,1) values times log-uniform column scales in
+[1, 1e4], b = A x_true + 1e-4 N(0,1) (seed 2000), resident on the device.
+Reference: the stored oracle answer (tests/golden/sparse_c2_ref.json).
   plain FP64 path : u_q = FP64 factor, u_p = FP64 PCGTLS
-  mixed path      : u_q = FP16 factor (scaled), u_p = FP32 PCGTLS, FP64 outer
-Both use the same stopping rule (psi, patience 2). Errors are checked
-against the stored oracle reference (tests/golden/sparse_c2_ref.json).
+  mixed path      : u_q = FP16 factor (scaled), u_p = FP32 PCGTLS, FP64 outer,
+                    gate and certificate enforced, FP64 refinement sweep
+
+Second workload (not the default line): dense 65536 x 4096 with a planted
+SVD, sigma'_i geometric from 1 to 1e-3 and sigma_{n+1} = 3.9e-5 (exact
+reference by the closed form); mixed path with a BF16 factor from the
+matrix-core Gram.
+
+One step = one whole solve: tls_factor_precond + tls_rqi_solve. Both paths
+use the same stopping rule (psi, patience 2); `value` is the time from the
+factorization's enqueue to the first iterate within 1e-10 of the reference.
 """
+
 from __future__ import annotations
 
 import argparse
@@ -33,8 +40,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
-WORKLOAD = "sparse_c2"
 TOL = 1e-10
+GATED = dict(gate_enforce=1, allow_escalate=1, refine_sweeps=1)
+WORKLOADS = {
+    "sparse_20000x2000": {
+        "describe": "sparse CSR 20000x2000, 0.5% nnz, column scales logU[1,1e4], b noise 1e-4, seed 2000",
+        "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
+                  # the gate (constraint checks and the factor certificate) runs per
+                  # instance before the FP16 factor is used; FP64 refinement on
+                  "mixed": dict(u_q="fp16", u_p="fp32", opts=GATED)},
+        "dtype": "f16 factor / f32 PCG / f64 outer",
+    },
+    "dense_planted_65536x4096": {
+        "describe": "dense 65536x4096 planted SVD, sigma' geometric 1..1e-3, sigma_{n+1} 3.9e-5, seed 3100",
+        "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
+                  "mixed": dict(u_q="bf16", u_p="fp32", opts=GATED)},
+        "dtype": "bf16 factor (MFMA Gram) / f32 PCG / f64 outer",
+    },
+}
+WORKLOAD = "sparse_20000x2000"
+PATHS = WORKLOADS[WORKLOAD]["paths"]
 
 
 def parse():
@@ -46,42 +71,45 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="a few solves of each path, no CPU leg (for rocprofv3 runs)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS))
     return ap.parse_args()
 
 
-def load_ref():
-    with open(os.path.join(ROOT, "tests", "golden", f"{WORKLOAD}_ref.json")) as f:
-        ref = json.load(f)
-    return np.array(ref["x"]), float(ref["sigma"])
-
-
-def make_problem():
+def make_problem(workload):
+    """(A, b, x_ref, sigma_ref) of the workload."""
     import tlsgen
-    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
-    return A, b
-
-
-PATHS = {
-    "fp64": dict(u_q="fp64", u_p="fp64", opts={}),
-    # the gate (constraint checks and the factor certificate) runs per instance
-    # before the FP16 factor is used; the final FP64 refinement sweep is on
-    "mixed": dict(u_q="fp16", u_p="fp32", opts=dict(gate_enforce=1, allow_escalate=1,
-                                                    refine_sweeps=1)),
-}
+    if workload == "sparse_20000x2000":
+        A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+        with open(os.path.join(ROOT, "tests", "golden", "sparse_c2_ref.json")) as f:
+            ref = json.load(f)
+        return A, b, np.array(ref["x"]), float(ref["sigma"])
+    m, n = 65536, 4096
+    sig = np.concatenate([1e-3 ** (np.arange(n) / (n - 1)), [3.9e-5]])
+    A, b, _, w = tlsgen.planted_svd(m, n, sig, seed=3100)
+    # v = (I - 2 w w^T) e_{n+1} is the right singular vector of sigma_{n+1}
+    x = 2 * w[n] * w[:n] / (1 - 2 * w[n] ** 2)
+    return A, b, x, float(sig[n])
 
 
 def one_solve(tls, torch, Ad, bd, path, snaps=None):
+    """Factor and solve. The gate of a low-precision factor is left running
+    on the library's side streams when the factorization call returns
+    (wait_gate=False) and overlaps the solve, which reads its verdict before
+    it returns; so the factor time (the call plus the rest of its own stream)
+    excludes the gate and the solve time includes whatever of it was not
+    hidden."""
     cfg = PATHS[path]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P, rep = tls.tls_factor_precond(Ad, cfg["u_q"])
-    torch.cuda.synchronize()
+    P, _ = tls.tls_factor_precond(Ad, cfg["u_q"], wait_gate=False)
+    torch.cuda.current_stream().synchronize()
     t1 = time.perf_counter()
     opts = tls.default_opts(u_p=cfg["u_p"], stop_patience=2, kmax=40, x_snapshots=snaps,
                             **cfg["opts"])
     x, sigma, st = tls.tls_rqi_solve(Ad, bd, P, opts)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    rep = P.info()["gate"]
     return P, x, sigma, st, (t1 - t0) * 1e3, (t2 - t1) * 1e3, rep
 
 
@@ -118,6 +146,7 @@ def run_path(tls, torch, Ad, bd, path, steps, warmup, xref, sref):
         "factor_ms": statistics.median(factors),
         "rqi_iters": st["iters"], "pcg_steps": st["pcg_steps"], "k_best": st["k_best"],
         "err_sigma": es, "err_x": ex, "gate_verdict": rep["verdict"],
+        "gate_async": st["gate_async"],
         "kappa_est": rep["kappa_est"],
     }
 
@@ -138,6 +167,9 @@ PEAKS = {  # MI355X published peaks
     "hbm": (8000.0, "GB/s"),
     "alu_f64": (78.6, "TFLOP/s"),    # FP64 vector
     "alu_f32": (157.3, "TFLOP/s"),   # FP32 vector
+    "mfma_f64": (78.6, "TFLOP/s"),   # FP64 matrix
+    "mfma_f32": (157.3, "TFLOP/s"),  # FP32 matrix
+    "mfma_16": (2500.0, "TFLOP/s"),  # BF16 / FP16 dense matrix
 }
 SIZE = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 
@@ -169,10 +201,16 @@ def class_work(cls, path, m, n, nnz, launches):
         return alu, fl * launches / max(N - 1, 1), "2 n_b^3 per trailing tile pair"
     if cls == "invert":
         return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches"
+    dense = nnz == m * n
     if cls in ("residual", "gradient"):
+        if dense:
+            return "hbm", (8 * m * n + 16 * m) * launches, "dense pass 8mn + 16m B"
         per = 12 * nnz + 4 * (m + 1) + 8 * (m + n)
         return "hbm", per * launches, "CSR/CSC pass 12 nnz + 4(m+1) + 8(m+n) B"
     if cls == "gram":
+        if dense:
+            peak = "mfma_f64" if cfg["u_q"] == "fp64" else ("mfma_f32" if cfg["u_q"] == "fp32" else "mfma_16")
+            return peak, float(m) * n * (n + 1), "upper-half SYRK m n (n+1) flops"
         per = 12 * nnz + tri * (8 if cfg["u_q"] == "fp64" else 4)
         return "hbm", per, "CSC read + Gram triangle write"
     return None
@@ -197,7 +235,7 @@ def measured_traffic(cls, path):
     or None when the kernel's source changed since the counters were taken."""
     import hashlib
     ent = CLASS_KERNELS.get(path, {}).get(cls)
-    if ent is None or not os.path.exists(TRAFFIC_FILE):
+    if WORKLOAD != "sparse_20000x2000" or ent is None or not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
@@ -218,7 +256,8 @@ def roofline_of(cls, path, m, n, nnz, entry):
     peak, unit = PEAKS[bound]
     secs = entry["ms_per_solve"] * 1e-3
     achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
-    return {"bound": "hbm" if bound == "hbm" else "alu", "kernel": cls, "achieved": achieved,
+    kind = "hbm" if bound == "hbm" else ("mfma" if bound.startswith("mfma") else "alu")
+    return {"bound": kind, "kernel": cls, "achieved": achieved,
             "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": measured_traffic(cls, path),
             "avg_us": entry["avg_us"], "launches_per_solve": entry["launches"],
@@ -255,10 +294,13 @@ def main():
     from paper_2305_19028_amd import tls
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    A, b = make_problem()
-    xref, sref = load_ref()
+    global WORKLOAD, PATHS
+    WORKLOAD = args.workload
+    PATHS = WORKLOADS[WORKLOAD]["paths"]
+    A, b, xref, sref = make_problem(WORKLOAD)
     Ad = tls.from_tlsgen(A)
     bd = tls.device_vector(b)
+    dense = not hasattr(A, "row_ptr")
 
     if args.profile_only:
         # a plain device copy of known size first: it calibrates the HBM byte
@@ -284,7 +326,8 @@ def main():
     print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)
 
     # dominant kernel class of the mixed path, and every class's fraction
-    m, n, nnz = A.m, A.n, len(A.val)
+    m, n = (A.shape if dense else (A.m, A.n))
+    nnz = m * n if dense else len(A.val)
     pm = prof["mixed"]
     dom = max(pm, key=lambda k: pm[k]["ms_per_solve"])
     roof = roofline_of(dom, "mixed", m, n, nnz, pm[dom])
@@ -295,7 +338,7 @@ def main():
             e["bound"] = r["bound"]
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not dense:
         cpu = cpu_baseline(A, b, args.cpu_seconds)
 
     mixed = res["mixed"]
@@ -313,10 +356,9 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16 factor / f32 PCG / f64 outer",
+        "dtype": WORKLOADS[WORKLOAD]["dtype"],
         "data": "synthetic",
-        "config": {"workload": "sparse CSR 20000x2000, 0.5% nnz, column scales logU[1,1e4], "
-                               "b noise 1e-4, seed 2000",
+        "config": {"workload": WORKLOADS[WORKLOAD]["describe"],
                    "paths": {"mixed": PATHS["mixed"], "fp64": PATHS["fp64"]}},
         "fp64_path_ms": res["fp64"]["ms_median"],
         "speedup_vs_fp64": {
@@ -325,6 +367,8 @@ def main():
         "time_to_tol_ms": {"mixed": mixed["time_to_tol_ms"], "fp64": res["fp64"]["time_to_tol_ms"]},
         "errors": {p: {"sigma": res[p]["err_sigma"], "x": res[p]["err_x"]} for p in res},
         "rqi_iters": {p: res[p]["rqi_iters"] for p in res},
+        "factor_ms": {p: res[p]["factor_ms"] for p in res},
+        "gate_async": {p: res[p]["gate_async"] for p in res},
         "roofline": roof,
         "kernel_classes": prof,
         "cpu_baseline": cpu,

@@ -26,6 +26,11 @@
  *    calls on the same inputs give bitwise identical outputs.
  *  - Calls that share a workspace or a preconditioner must not overlap in
  *    time (they use synchronisation counters inside the workspace).
+ *  - The gate of a low-precision factor (two Lanczos runs) executes on two
+ *    library-owned streams per device (default priority, non-blocking,
+ *    created on first use, kept until the process ends), forked from the
+ *    caller's stream after the factorization. See tls_factor_precond for
+ *    when the caller may see them still running.
  */
 #ifndef TLS_H
 #define TLS_H
@@ -142,6 +147,11 @@ typedef struct {
   int32_t gate_enforce;    /* 1: run the b-dependent gate                         */
   int32_t features;        /* 1: compute the warm-start features (stats.features)
                               even when no warm start is requested                */
+  int32_t min_inner_steps; /* the k-th PCGTLS runs take l = max(k, this) (l + 1
+                              steps); 0 = l = k as in Algorithm 2. For starts
+                              far above sigma_{n+1}, where k + 1 steps leave the
+                              early Newton systems unsolved (0..4096)            */
+  int32_t reserved;
   double shift_clamp_tau;  /* tau of the clamp (0 < tau < 1)                       */
   double sigma0_hint;      /* warm start from a given shift estimate sigma_hat
                               (<= 0: none; ignored when mlp_theta is set)         */
@@ -157,10 +167,15 @@ typedef struct {
   int32_t k_best;          /* k of the returned iterate (smallest psi)            */
   int32_t pcg_steps;       /* PCGTLS steps executed (per right-hand side)         */
   int32_t warm_used;       /* 1 when the warm-start step was kept                 */
-  int32_t stopped;         /* 0 psi rule, 1 kmax, 2 psi == 0                      */
+  int32_t stopped;         /* 0 psi rule, 1 kmax, 2 fixed point (psi == 0 or psi
+                              repeated exactly)                                   */
   int32_t negative_delta;  /* PCGTLS steps that met delta_j < 0                   */
   int32_t refine_steps;    /* refinement RQI steps taken                          */
   int32_t clamped;         /* iterations whose shift was clamped                  */
+  int32_t gate_async;      /* 1: the gate's Lanczos runs were still in flight when
+                              the iterations began (they overlapped the solve and
+                              were read at a later host synchronisation)          */
+  int32_t reserved;
   double sigma_ls;         /* sigma_0 = ||r_0|| / sqrt(1 + ||x_LS||^2)             */
   double psi[TLS_MAX_ITERS];
   double sigma[TLS_MAX_ITERS];
@@ -186,13 +201,21 @@ TLS_API size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q);
  * columns of A D^{-1} are rounded to u_q, H = (A D^{-1})^T (A D^{-1}) is
  * accumulated in FP32 (FP64 when u_q = FP64), Cholesky gives R_hat, stored
  * in u_q, and R = R_hat D. scaling = 0 factors A^T A itself (FP64 only).
- * The A-only constraints of Section 3.1 are estimated and reported in *rep
- * (host, may be NULL); with allow_escalate the factor is recomputed in the
- * next higher precision when none of the Cholesky constraints nor the
- * a-posteriori checks hold. Breakdown (TLS_ERR_NOT_SPD) is retried with the
- * diagonal shift 2^j n u_q (j = 0, 1, 2) before it is returned.
- * On success *out (host) receives a handle to destroy with
- * tls_precond_destroy. ws must hold tls_factor_workspace_size() bytes. */
+ * For u_q below FP64 the gate runs two Lanczos processes on the factor:
+ * 8 steps on (R^T R)^{-1}, giving the estimates of kappa and sigma'_n behind
+ * the A-only constraints of Section 3.1 (verdict bits 1, 2, 4), and 6 steps
+ * on R^{-T} A^T A R^{-1}, whose extreme Ritz values (quality_lo, quality_hi)
+ * are the a-posteriori certificate of the factor read by tls_rqi_solve.
+ * The two run concurrently. With rep != NULL (host) the call waits for both
+ * and fills *rep. With rep == NULL it returns while they may still run:
+ * tls_rqi_solve then overlaps them with its iterations, and
+ * tls_precond_info (with a report requested), tls_rqi_solve and
+ * tls_precond_destroy wait for them; A and ws must stay valid until then.
+ * allow_escalate applies to Cholesky breakdown (TLS_ERR_NOT_SPD): after the
+ * diagonal shifts 2^j n u_q (j = 0, 1, 2) the factor is recomputed in the
+ * next higher precision. On success *out (host) receives a handle to
+ * destroy with tls_precond_destroy. ws must hold
+ * tls_factor_workspace_size() bytes. */
 TLS_API tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
                               int32_t allow_escalate, void *ws, size_t ws_bytes,
                               hipStream_t stream, tls_precond *out,
@@ -211,7 +234,8 @@ TLS_API tls_status tls_precond_import(int64_t n, const double *R_host, const dou
 
 TLS_API void tls_precond_destroy(tls_precond P);
 
-/* Order n, storage precision and gate report of P (host outputs). */
+/* Order n, storage precision and gate report of P (host outputs, each may
+ * be NULL). Requesting the report waits for a gate still running. */
 TLS_API tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage,
                             tls_gate_report *rep);
 
@@ -274,6 +298,18 @@ TLS_API size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P,
  * same A. x (device, n, out) receives the iterate with the smallest psi (or
  * the refined one), *sigma (host) sigma_{n+1} from a compensated residual.
  * opts and stats are host structures (stats may be NULL).
+ *
+ * Gate (opts.gate_enforce, factor below FP64): after x_LS and sigma_0 the
+ * bound of constraint (6) is formed with sigma_{n+1} <= sigma_0 (verdict bit
+ * 8, reported) and the factor's certificate is read (bit 16: Ritz values of
+ * R^{-T} A^T A R^{-1} within [0.5, 1.5]). Without bit 16 the call fails with
+ * TLS_ERR_PRECISION, or, with opts.allow_escalate, refactors in the next
+ * higher precision and solves again. If the certificate is still being
+ * computed (tls_factor_precond called with rep == NULL) the iterations go
+ * ahead meanwhile and the verdict is read at the first psi read-back after
+ * it is done, or at the end (stats.gate_async = 1); a failed verdict then
+ * discards the iterate and escalates as above, so the returned result is
+ * the one the waiting order gives. The shift clamp waits for the estimates.
  *
  * Warm start (project addition; opts.mlp_theta or opts.sigma0_hint). After
  * x_0 = x_LS, u_0 = (R^T R)^{-1} x_0 and sigma_0 (the quantities of the

@@ -914,24 +914,56 @@ __global__ __launch_bounds__(256) void k_chol_update(int k, int N, int Np, C *G)
     }
   }
   __syncthreads();
-  const int tr = tid & 15, tc = tid >> 4;
-  C acc[4][4] = {};
-  for (int t = 0; t < NB; ++t) {
-    C x4[4], y4[4];
+  // R(k,i)^T R(k,j) on the matrix cores: wave w takes the 32x32 quadrant
+  // (w / 2, w % 2); A operand = columns of Ri, B operand = columns of Rj
+  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  if constexpr (std::is_same<C, double>::value) {
+    g_f64x4 acc[2][2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) { x4[x] = Ri[t][tr * 4 + x]; y4[x] = Rj[t][tc * 4 + x]; }
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+      for (int u = 0; u < 2; ++u) acc[t][u] = g_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      double a[2], bb[2];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] += x4[x] * y4[y];
-  }
+      for (int t = 0; t < 2; ++t) {
+        a[t] = Ri[k0 + (lane >> 4)][wr * 32 + t * 16 + (lane & 15)];
+        bb[t] = Rj[k0 + (lane >> 4)][wc * 32 + t * 16 + (lane & 15)];
+      }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int r = i * NB + tr * 4 + x, c = j * NB + tc * 4 + y;
-      if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[x][y];
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bb[u], acc[t][u], 0, 0, 0);
     }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = i * NB + wr * 32 + t * 16 + 4 * q + (lane >> 4);
+          const int c = j * NB + wc * 32 + u * 16 + (lane & 15);
+          if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[t][u][q];
+        }
+  } else {
+    g_f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+#pragma unroll 8
+    for (int k0 = 0; k0 < NB; k0 += 2) {
+      const float a = Ri[k0 + (lane >> 5)][wr * 32 + (lane & 31)];
+      const float bb = Rj[k0 + (lane >> 5)][wc * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = i * NB + wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      const int c = j * NB + wc * 32 + (lane & 31);
+      if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[q];
+    }
+  }
 }
 
 template <typename C>

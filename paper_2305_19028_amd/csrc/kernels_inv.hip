@@ -61,8 +61,7 @@ __global__ __launch_bounds__(256) void k_inv_init(int N, const S *Rt, const doub
   }
 }
 
-// 64x64x64 FP64 tile products accumulated by 256 threads (4x4 outputs
-// each). The operand tiles (column-major in global memory) travel through
+// 64x64x64 FP64 tile products accumulated by 256 threads. The operand tiles (column-major in global memory) travel through
 // registers: the loads of product k+1 are in flight while product k runs
 // from LDS, so each product costs one memory latency at most once.
 struct TileRegs {
@@ -87,19 +86,51 @@ __device__ inline void tile_stage(const TileRegs &R, double (*As)[NB + 1], doubl
   }
   __syncthreads();
 }
-__device__ inline void tile_fma(const double (*As)[NB + 1], const double (*Bs)[NB + 1],
-                                double acc[4][4]) {
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+// C += A B on the FP64 matrix cores: wave w holds the 32x32 quadrant
+// (w / 2, w % 2) of C as 2x2 blocks of v_mfma_f64_16x16x4 results (lane l,
+// register q: row 4q + l/16, column l mod 16 of a block). Reads one double
+// of A and of B per lane and k-step of 4 (the VALU form, 4x4 outputs per
+// thread, was bound by LDS reads).
+typedef double inv_f64x4 __attribute__((ext_vector_type(4)));
+struct TileAcc {
+  inv_f64x4 c[2][2];
+};
+__device__ inline void tile_zero(TileAcc &T) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) T.c[t][u] = inv_f64x4{0.0, 0.0, 0.0, 0.0};
+}
+__device__ inline void tile_mma(const double (*As)[NB + 1], const double (*Bs)[NB + 1], TileAcc &T) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll 4
-  for (int k = 0; k < NB; ++k) {
-    double a[4], b[4];
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    double a[2], b[2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) { a[x] = As[tr * 4 + x][k]; b[x] = Bs[k][tc * 4 + x]; }
+    for (int t = 0; t < 2; ++t) {
+      a[t] = As[wr * 32 + t * 16 + (lane & 15)][k0 + (lane >> 4)];
+      b[t] = Bs[k0 + (lane >> 4)][wc * 32 + t * 16 + (lane & 15)];
+    }
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+      for (int u = 0; u < 2; ++u)
+        T.c[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], T.c[t][u], 0, 0, 0);
   }
+}
+// dst (column-major 64x64 tile) = sign * C
+__device__ inline void tile_store(const TileAcc &T, double *dst, double sign) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wr * 32 + t * 16 + 4 * q + (lane >> 4);
+        const int c = wc * 32 + u * 16 + (lane & 15);
+        dst[c * NB + r] = sign * T.c[t][u][q];
+      }
 }
 
 // phase 1 of level L: Y = B inv(C) for every pair p; Y tile (a, b), a, b in [0, hb)
@@ -111,7 +142,8 @@ __global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, do
   const int a = rem % hb, b = rem / hb;
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;      // partial pair at the end (uniform)
-  double acc[4][4] = {};
+  TileAcc acc;
+  tile_zero(acc);
   const int kend = b;                           // J0 + b < N, so every k <= b is in range
   TileRegs R;
   tile_fetch(W + up_tile(I0 + a, J0) * NB * NB, W + up_tile(J0, J0 + b) * NB * NB, R);
@@ -119,14 +151,9 @@ __global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, do
     tile_stage(R, As, Bs);
     if (k < kend)
       tile_fetch(W + up_tile(I0 + a, J0 + k + 1) * NB * NB, W + up_tile(J0 + k + 1, J0 + b) * NB * NB, R);
-    tile_fma(As, Bs, acc);
+    tile_mma(As, Bs, acc);
   }
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  double *dst = Y + ((size_t)pair * per + rem) * NB * NB;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) dst[(tc * 4 + y) * NB + tr * 4 + x] = acc[x][y];
+  tile_store(acc, Y + ((size_t)pair * per + rem) * NB * NB, 1.0);
 }
 
 // phase 2: W(I0 + a, J0 + b) = - sum_{k >= a} inv(A)(a, k) Y(k, b)
@@ -137,7 +164,8 @@ __global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, co
   const int a = rem % hb, b = rem / hb;
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;
-  double acc[4][4] = {};
+  TileAcc acc;
+  tile_zero(acc);
   const int kend = hb - 1;                      // I0 + k < J0 < N for every k < hb
   TileRegs R;
   auto yt = [&](int k) { return Y + ((size_t)pair * per + b * hb + k) * NB * NB; };
@@ -145,14 +173,9 @@ __global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, co
   for (int k = a; k <= kend; ++k) {
     tile_stage(R, As, Bs);
     if (k < kend) tile_fetch(W + up_tile(I0 + a, I0 + k + 1) * NB * NB, yt(k + 1), R);
-    tile_fma(As, Bs, acc);
+    tile_mma(As, Bs, acc);
   }
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  double *dst = W + up_tile(I0 + a, J0 + b) * NB * NB;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) dst[(tc * 4 + y) * NB + tr * 4 + x] = -acc[x][y];
+  tile_store(acc, W + up_tile(I0 + a, J0 + b) * NB * NB, -1.0);
 }
 
 // pack W (FP64, column-packed, column-major tiles) into XR and XC of precision SX

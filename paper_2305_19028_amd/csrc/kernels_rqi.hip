@@ -19,38 +19,66 @@ namespace tls {
 enum { S_SIG2 = 0, S_MU, S_XX, S_RR, S_BR, S_G, S_FF, S_PSI, S_BEST, S_ISBEST, S_ZF, S_ZX,
        S_BETA, S_FX, S_CAP, S_K };
 
-constexpr int RES_ROWS = 256;   // rows per workgroup of the residual pass
+constexpr int RES_ROWS = 256;   // rows per workgroup of the CSR residual pass
+// dense row products: 64 rows per workgroup, the columns split over 16 waves
+// (interleaved chunks of 8), partials joined in a fixed order through LDS
+constexpr int RD_ROWS = 64, RD_WAVES = 16, RD_CHUNK = 8;
 
-int matvec_blocks(const MatView &A) { return (A.m + RES_ROWS - 1) / RES_ROWS; }
+int matvec_blocks(const MatView &A) {
+  const int rows = A.format == TLS_DENSE_COLMAJOR ? RD_ROWS : RES_ROWS;
+  return (A.m + rows - 1) / rows;
+}
+
+// this wave's share of row i of A x: columns 8 (w + 16 t) + q, q < 8
+__device__ inline double dense_row_part(int n, int64_t ld, const double *a, const double *x, int w) {
+  double c[RD_CHUNK] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int j = RD_CHUNK * w;
+  for (; j + RD_CHUNK <= n; j += RD_CHUNK * RD_WAVES) {
+#pragma unroll
+    for (int q = 0; q < RD_CHUNK; ++q) c[q] += a[(size_t)(j + q) * ld] * x[j + q];
+  }
+#pragma unroll
+  for (int q = 0; q < RD_CHUNK; ++q)
+    if (j + q < n) c[q] += a[(size_t)(j + q) * ld] * x[j + q];
+  return ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+}
+// the 16 wave partials of the workgroup's 64 rows, summed in wave order;
+// valid in wave 0 (lane = row), every thread passes the barrier
+__device__ inline double dense_row_join(double v, double (*red)[RD_ROWS]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  red[w][lane] = v;
+  __syncthreads();
+  double s = 0;
+  if (w == 0) {
+    s = red[0][lane];
+#pragma unroll
+    for (int q = 1; q < RD_WAVES; ++q) s += red[q][lane];
+  }
+  return s;
+}
 int rmatvec_blocks(const MatView &A) { return (A.n + 3) / 4; }
 
 // ---------------------------------------------------------------------------
 // r = b - A x with partials of r.r and b.r
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_residual_dense(int m, int n, int64_t ld, const double *A,
-                                                        const double *b, const double *x,
-                                                        double *r, double *part) {
-  __shared__ double sc[8];
-  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
+__global__ __launch_bounds__(1024) void k_residual_dense(int m, int n, int64_t ld, const double *A,
+                                                         const double *b, const double *x,
+                                                         double *r, double *part) {
+  __shared__ double red[RD_WAVES][RD_ROWS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * RD_ROWS + lane;
+  const double p = i < m ? dense_row_part(n, ld, A + i, x, w) : 0.0;
+  const double ax = dense_row_join(p, red);
+  if (w != 0) return;
   double rv = 0, bv = 0;
   if (i < m) {
-    double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-    const double *a = A + i;
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-      acc0 += a[(size_t)(j + 0) * ld] * x[j + 0];
-      acc1 += a[(size_t)(j + 1) * ld] * x[j + 1];
-      acc2 += a[(size_t)(j + 2) * ld] * x[j + 2];
-      acc3 += a[(size_t)(j + 3) * ld] * x[j + 3];
-    }
-    for (; j < n; ++j) acc0 += a[(size_t)j * ld] * x[j];
     bv = b[i];
-    rv = bv - ((acc0 + acc1) + (acc2 + acc3));
+    rv = bv - ax;
     r[i] = rv;
   }
-  const double rr = block_sum(rv * rv, sc);
-  const double br = block_sum(bv * rv, sc + 4);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
+  const double rr = wave_sum(rv * rv);
+  const double br = wave_sum(bv * rv);
+  if (lane == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
 }
 
 __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_ptr,
@@ -76,7 +104,8 @@ hipError_t launch_residual(const MatView &A, const double *b, const double *x, d
                            double *part, hipStream_t st) {
   const dim3 g(matvec_blocks(A));
   if (A.format == TLS_DENSE_COLMAJOR)
-    TLS_LAUNCH(PC_RESIDUAL, k_residual_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, b, x, r, part);
+    TLS_LAUNCH(PC_RESIDUAL, k_residual_dense, g, dim3(RD_ROWS * RD_WAVES), 0, st, A.m, A.n, A.ld, A.val, b,
+               x, r, part);
   else
     TLS_LAUNCH(PC_RESIDUAL, k_residual_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
                        r, part);
@@ -84,12 +113,14 @@ hipError_t launch_residual(const MatView &A, const double *b, const double *x, d
 }
 
 // plain products (tests and x_LS): y = A x, y = A^T x
-__global__ void k_matvec_dense(int m, int n, int64_t ld, const double *A, const double *x, double *y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double acc = 0;
-  for (int j = 0; j < n; ++j) acc += A[i + (size_t)j * ld] * x[j];
-  y[i] = acc;
+__global__ __launch_bounds__(1024) void k_matvec_dense(int m, int n, int64_t ld, const double *A,
+                                                       const double *x, double *y) {
+  __shared__ double red[RD_WAVES][RD_ROWS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * RD_ROWS + lane;
+  const double p = i < m ? dense_row_part(n, ld, A + i, x, w) : 0.0;
+  const double ax = dense_row_join(p, red);
+  if (w == 0 && i < m) y[i] = ax;
 }
 __global__ void k_matvec_csr(int m, const int32_t *row_ptr, const int32_t *col_idx,
                              const double *val, const double *x, double *y) {
@@ -104,9 +135,16 @@ __global__ void k_rmatvec_dense(int m, int n, int64_t ld, const double *A, const
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= n) return;
   const double *col = A + (size_t)j * ld;
-  double acc = 0;
-  for (int i = lane; i < m; i += 64) acc += col[i] * x[i];
-  acc = wave_sum(acc);
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int i = lane;
+  for (; i + 192 < m; i += 256) {
+    a0 += col[i] * x[i];
+    a1 += col[i + 64] * x[i + 64];
+    a2 += col[i + 128] * x[i + 128];
+    a3 += col[i + 192] * x[i + 192];
+  }
+  for (; i < m; i += 64) a0 += col[i] * x[i];
+  const double acc = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) y[j] = acc;
 }
 __global__ void k_rmatvec_csc(int n, const int32_t *col_ptr, const int32_t *row_idx,
@@ -120,9 +158,9 @@ __global__ void k_rmatvec_csc(int n, const int32_t *col_ptr, const int32_t *row_
 }
 
 hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream_t st) {
-  const dim3 g((A.m + 255) / 256);
+  const dim3 g(matvec_blocks(A));
   if (A.format == TLS_DENSE_COLMAJOR)
-    TLS_LAUNCH(PC_RESIDUAL, k_matvec_dense, g, dim3(256), 0, st, A.m, A.n, A.ld, A.val, x, y);
+    TLS_LAUNCH(PC_RESIDUAL, k_matvec_dense, g, dim3(RD_ROWS * RD_WAVES), 0, st, A.m, A.n, A.ld, A.val, x, y);
   else
     TLS_LAUNCH(PC_RESIDUAL, k_matvec_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, x, y);
   return hipGetLastError();
@@ -185,10 +223,15 @@ __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, cons
     } else {
       const double *col = A + (size_t)j * ld;
       int i = lane;
-      double a1 = 0;
-      for (; i + 64 < m; i += 128) { acc += col[i] * r[i]; a1 += col[i + 64] * r[i + 64]; }
+      double a1 = 0, a2 = 0, a3 = 0;
+      for (; i + 192 < m; i += 256) {
+        acc += col[i] * r[i];
+        a1 += col[i + 64] * r[i + 64];
+        a2 += col[i + 128] * r[i + 128];
+        a3 += col[i + 192] * r[i + 192];
+      }
       for (; i < m; i += 64) acc += col[i] * r[i];
-      acc += a1;
+      acc = (acc + a1) + (a2 + a3);
     }
     acc = wave_sum(acc);
     xv = x[j];
@@ -406,34 +449,83 @@ __device__ inline dd dd_add(dd a, dd b) {
   return two_sum(s.hi, s.lo);
 }
 
-__global__ __launch_bounds__(256) void k_residual_dd(int format, int m, int n, int64_t ld,
-                                                     const double *A, const int32_t *row_ptr,
-                                                     const int32_t *col_idx, const double *b,
-                                                     const double *x, double *part) {
+// s - a x, exactly split: s + c stays the compensated running value
+__device__ inline void comp_sub(double &s, double &c, double a, double x) {
+  const dd p = two_prod(a, x);
+  const dd t = two_sum(s, -p.hi);
+  s = t.hi;
+  c += t.lo - p.lo;
+}
+// r_i^2 in double-double from the compensated pair (s, c) of r_i
+__device__ inline dd dd_square(double s, double c) {
+  const dd r = two_sum(s, c);
+  // (hi + lo)^2 ~ hi^2 + 2 hi lo
+  const dd sq = two_prod(r.hi, r.hi);
+  return two_sum(sq.hi, sq.lo + 2.0 * r.hi * r.lo);
+}
+
+// dense: 64 rows per workgroup, columns split over 16 waves as in the plain
+// product; each wave keeps two compensated sums (even and odd columns of a
+// chunk), the wave sums are joined to b_i in wave order with TwoSum
+__global__ __launch_bounds__(1024) void k_residual_dd_dense(int m, int n, int64_t ld,
+                                                            const double *A, const double *b,
+                                                            const double *x, double *part) {
+  __shared__ double rhi[RD_WAVES][RD_ROWS], rlo[RD_WAVES][RD_ROWS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * RD_ROWS + lane;
+  double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+  if (i < m) {
+    const double *a = A + i;
+    int j = RD_CHUNK * w;
+    for (; j + RD_CHUNK <= n; j += RD_CHUNK * RD_WAVES) {
+#pragma unroll
+      for (int q = 0; q < RD_CHUNK; q += 2) {
+        comp_sub(s0, c0, a[(size_t)(j + q) * ld], x[j + q]);
+        comp_sub(s1, c1, a[(size_t)(j + q + 1) * ld], x[j + q + 1]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RD_CHUNK; ++q)
+      if (j + q < n) comp_sub(s0, c0, a[(size_t)(j + q) * ld], x[j + q]);
+    const dd t = two_sum(s0, s1);
+    s0 = t.hi;
+    c0 += t.lo + c1;
+  }
+  rhi[w][lane] = s0;
+  rlo[w][lane] = c0;
+  __syncthreads();
+  if (w != 0) return;
+  dd rsq{0.0, 0.0};
+  if (i < m) {
+    double s = b[i], c = 0.0;
+#pragma unroll
+    for (int q = 0; q < RD_WAVES; ++q) {
+      const dd t = two_sum(s, rhi[q][lane]);
+      s = t.hi;
+      c += t.lo + rlo[q][lane];
+    }
+    rsq = dd_square(s, c);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const dd o{__shfl_xor(rsq.hi, off, 64), __shfl_xor(rsq.lo, off, 64)};
+    rsq = dd_add(rsq, o);
+  }
+  if (lane == 0) { part[2 * blockIdx.x] = rsq.hi; part[2 * blockIdx.x + 1] = rsq.lo; }
+}
+
+// CSR: one row per thread, 256 rows per workgroup
+__global__ __launch_bounds__(256) void k_residual_dd_csr(int m, const double *val,
+                                                         const int32_t *row_ptr,
+                                                         const int32_t *col_idx, const double *b,
+                                                         const double *x, double *part) {
   __shared__ double shi[256], slo[256];
   const int i = blockIdx.x * RES_ROWS + threadIdx.x;
   dd rsq{0.0, 0.0};
   if (i < m) {
     double s = b[i], c = 0.0;
-    if (format == TLS_DENSE_COLMAJOR) {
-      for (int j = 0; j < n; ++j) {
-        const dd p = two_prod(A[i + (size_t)j * ld], x[j]);
-        const dd t = two_sum(s, -p.hi);
-        s = t.hi;
-        c += t.lo - p.lo;
-      }
-    } else {
-      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-        const dd p = two_prod(A[e], x[col_idx[e]]);
-        const dd t = two_sum(s, -p.hi);
-        s = t.hi;
-        c += t.lo - p.lo;
-      }
-    }
-    const dd r = two_sum(s, c);
-    // r^2 in double-double: (hi + lo)^2 ~ hi^2 + 2 hi lo
-    const dd sq = two_prod(r.hi, r.hi);
-    rsq = two_sum(sq.hi, sq.lo + 2.0 * r.hi * r.lo);
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) comp_sub(s, c, val[e], x[col_idx[e]]);
+    rsq = dd_square(s, c);
   }
   shi[threadIdx.x] = rsq.hi;
   slo[threadIdx.x] = rsq.lo;
@@ -452,8 +544,12 @@ __global__ __launch_bounds__(256) void k_residual_dd(int format, int m, int n, i
 }
 hipError_t launch_residual_dd(const MatView &A, const double *b, const double *x, double *part,
                               hipStream_t st) {
-  TLS_LAUNCH(PC_RESID_DD, k_residual_dd, dim3(matvec_blocks(A)), dim3(256), 0, st, A.format, A.m, A.n,
-                     A.ld, A.val, A.row_ptr, A.col_idx, b, x, part);
+  if (A.format == TLS_DENSE_COLMAJOR)
+    TLS_LAUNCH(PC_RESID_DD, k_residual_dd_dense, dim3(matvec_blocks(A)), dim3(RD_ROWS * RD_WAVES), 0, st,
+               A.m, A.n, A.ld, A.val, b, x, part);
+  else
+    TLS_LAUNCH(PC_RESID_DD, k_residual_dd_csr, dim3(matvec_blocks(A)), dim3(256), 0, st, A.m, A.val,
+               A.row_ptr, A.col_idx, b, x, part);
   return hipGetLastError();
 }
 

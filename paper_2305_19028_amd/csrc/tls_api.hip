@@ -15,7 +15,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -108,6 +110,19 @@ struct tls_precond_s {
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
   double normA_F2 = 0;             // ||A||_F^2 = sum_j d_j^2
   double lnd[4] = {0, 0, 0, 0};    // min, max, mean, std of ln d_j (warm-start features)
+  // the gate's two Lanczos runs (estimates, certificate) on the library's
+  // side streams: fork point, completion of each run, pending until collected
+  hipEvent_t ev_fork = nullptr, ev_pair = nullptr, ev_cert = nullptr;
+  hipStream_t side[2] = {nullptr, nullptr};
+  int gate_pending = 0, have_quality = 0;
+  ~tls_precond_s() {
+    if (gate_pending) {
+      (void)hipEventSynchronize(ev_pair);
+      (void)hipEventSynchronize(ev_cert);
+    }
+    for (hipEvent_t e : {ev_fork, ev_pair, ev_cert})
+      if (e) (void)hipEventDestroy(e);
+  }
   FactorView view() const {
     FactorView F;
     F.n = (int)n;
@@ -128,6 +143,8 @@ struct tls_precond_s {
 };
 
 namespace {
+
+tls_status gate_finish(tls_precond_s *P);
 
 MatView make_view(const tls_matrix *A, const tls_precond_s *P) {
   MatView V{};
@@ -191,6 +208,9 @@ struct FactorWs {
   int *cnt;        // per-block arrival counters of internal applies
   double *tm;      // m-vector (products with A in the certificate)
   void *cast;      // dense A rounded to u_q (matrix-core Gram input), or NULL
+  // the certificate's own buffers (it runs concurrently with the estimates)
+  int *qsync, *qcnt;
+  double *qpart, *qlz, *qlzs;
 };
 constexpr int LANCZOS_STEPS = 8;
 constexpr int QUALITY_STEPS = 6;
@@ -226,6 +246,11 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
                                     (size_t)N * xapply_chunk_count(N) * 2 * NB));
   W.cnt = c.take<int>(N);
   W.tm = c.take<double>((size_t)std::max<int64_t>(m, 1));
+  W.qsync = c.take<int>(N + 8);
+  W.qcnt = c.take<int>(N);
+  W.qpart = c.take<double>((size_t)N * xapply_chunk_count(N) * 2 * NB);
+  W.qlz = c.take<double>((size_t)(QUALITY_STEPS + 1 + 9) * Np);
+  W.qlzs = c.take<double>(2 * QUALITY_STEPS + 8);
   // low-precision copy of a dense A for the matrix-core Gram
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
   return W;
@@ -512,7 +537,10 @@ tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *storage, t
   if (!P) return fail(TLS_ERR_ARG, "P is NULL");
   if (n) *n = P->n;
   if (storage) *storage = P->storage;
-  if (rep) *rep = P->rep;
+  if (rep) {
+    TRY(gate_finish(P));   // the report is complete once the gate's runs are
+    *rep = P->rep;
+  }
   return TLS_OK;
 }
 
@@ -542,15 +570,14 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
 // R_hat^{-1} R_hat^{-T} (the scaled A D^{-1}), run 1 on R^{-1} R^{-T} with
 // R = R_hat D (A itself). Both recurrences share each 2-RHS application of
 // the preconditioner; all of it stays on the device and the two
-// tridiagonal matrices are read back once. Extremal eigenvalues of each
-// tridiagonal matrix come from bisection on the host.
-tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *steps,
-                        hipStream_t st) {
+// tridiagonal matrices are read back once (collect_pair). Extremal
+// eigenvalues of each tridiagonal matrix come from bisection on the host.
+tls_status enqueue_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   const int n = (int)P->n, Np = P->Np;
   const int K = std::min(LANCZOS_STEPS, n);
   double *V = W.lz;                                   // [2][K+1][Np]
   double *inb = W.lz + (size_t)2 * (LANCZOS_STEPS + 1) * Np;     // [2][Np] operator input
-  double *tmp = inb + (size_t)2 * Np;                            // [2][Np]
+  double *tmp = inb + (size_t)2 * Np;                            // [2][Np] R^{-T} output
   double *outb = tmp + (size_t)2 * Np;                           // [2][Np]
   double *ones = outb + (size_t)2 * Np;                          // [Np]
   PcgWs S{};
@@ -561,6 +588,8 @@ tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *st
   S.cnt = W.cnt;
   double *ab = W.lzs;                                 // [2][2K+2]
   tls_precond_s Q = *P;
+  Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;        // a view: owns no events
+  Q.gate_pending = 0;
   Q.dsc64 = ones;                                     // apply R_hat alone
   // v_0 = ones/sqrt(n) for both runs; operator input [v0, D^{-1} v0]
   const double v0 = 1.0 / std::sqrt((double)n);
@@ -586,16 +615,26 @@ tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *st
     }
     HIPCHK(launch_fill_multi(F, st));
   }
-  (void)tmp;
   // the apply kernels read [nrhs][n]-packed inputs: pack with stride n
-  for (int k = 0; k < K; ++k) {
-    TRY(apply_R(&Q, 1, 2, inb, tmp, TLS_FP64, S, st, Np));
-    TRY(apply_R(&Q, 0, 2, tmp, outb, TLS_FP64, S, st, Np));
-    HIPCHK(launch_lanczos_orth(n, Np, k, K, V, outb, inb, P->dsc64, ab, st));
+  tls_status s = TLS_OK;
+  for (int k = 0; k < K && s == TLS_OK; ++k) {
+    s = apply_R(&Q, 1, 2, inb, tmp, TLS_FP64, S, st, Np);
+    if (s == TLS_OK) s = apply_R(&Q, 0, 2, tmp, outb, TLS_FP64, S, st, Np);
+    if (s == TLS_OK && launch_lanczos_orth(n, Np, k, K, V, outb, inb, P->dsc64, ab, st) != hipSuccess)
+      s = fail(TLS_ERR_HIP, "Lanczos orthogonalization launch failed");
   }
+  return s;
+}
+
+// read back the two tridiagonal matrices (st idle) and set the estimates:
+// kappa(A D^{-1}) and sigma'_n(A), sigma'_1(A)
+tls_status collect_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  const int K = std::min(LANCZOS_STEPS, (int)P->n);
   std::vector<double> h(2 * (2 * K + 2));
-  HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h.data(), W.lzs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  double lam[2][2];
+  int steps[2];
   for (int run = 0; run < 2; ++run) {
     const double *hr = h.data() + run * (2 * K + 2);
     const int done = (int)hr[2 * K + 1];
@@ -603,14 +642,6 @@ tls_status lanczos_pair(tls_precond_s *P, FactorWs &W, double lam[2][2], int *st
     tridiag_extremes(a, b, &lam[run][0], &lam[run][1]);
     steps[run] = done;
   }
-  return TLS_OK;
-}
-
-// Lanczos estimates: kappa(A D^{-1}) and sigma'_n(A), sigma'_1(A)
-tls_status run_estimates(tls_precond_s *P, FactorWs &W, hipStream_t st) {
-  double lam[2][2];
-  int steps[2];
-  TRY(lanczos_pair(P, W, lam, steps, st));
   tls_gate_report &R = P->rep;
   P->smin_s = 1.0 / std::sqrt(lam[0][1]);
   P->smax_s = 1.0 / std::sqrt(std::max(lam[0][0], 1e-300));
@@ -618,36 +649,52 @@ tls_status run_estimates(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   R.sigma_1_est = 1.0 / std::sqrt(std::max(lam[1][0], 1e-300));
   R.lanczos_steps = steps[1];
   P->have_sigma_n = 1;
+  // the A-only constraints of Section 3.1 from the estimates
+  const double n = (double)P->n;
+  const double smin_s = P->smin_s, smax_s = P->smax_s;
+  const double kap = P->scaled ? smax_s / smin_s : R.sigma_1_est / R.sigma_n_est;
+  R.kappa_est = kap;
+  // ||A D^{-1}||_F = sqrt(n) exactly when scaled
+  R.kappaF_est = P->scaled ? std::sqrt(n) / smin_s : std::numeric_limits<double>::quiet_NaN();
+  R.lam_min_H = smin_s * smin_s;
+  R.bound5 = 1.0 / kap;
+  R.bound_chol = 1.0 / (kap * kap);
+  R.bound_wilkinson = 1.0 / (20.0 * std::pow(n, 1.5) * kap * kap);
+  R.bound_hp = R.lam_min_H / ((2.0 * R.lam_min_H + n) * (n + 1.0));
+  R.u_q = unit_roundoff(P->storage);
+  int v = R.verdict & ~(1 | 2 | 4);
+  if (R.u_q < R.bound5) v |= 1;
+  if (R.u_q < R.bound_chol) v |= 2;
+  if (R.u_q < R.bound_hp) v |= 4;
+  R.verdict = v;
+  P->have_kappa = 1;
   return TLS_OK;
-}
-
-tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
-  return run_estimates(P, W, st);
 }
 
 // A-posteriori certificate of the factor: extreme Ritz values of
 // M = R^{-T} A^T A R^{-1} after QUALITY_STEPS Lanczos steps (products with A
-// and the applications of R in FP64). M = I for the exact factor.
-tls_status factor_quality(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
+// and the applications of R in FP64). M = I for the exact factor. Its
+// buffers are its own, so it may run beside enqueue_pair.
+tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
   const int n = (int)P->n, Np = P->Np;
   const int K = std::min(QUALITY_STEPS, n);
-  double *Vb = W.lz;                                              // [K+1][Np]
-  double *inb = W.lz + (size_t)2 * (LANCZOS_STEPS + 1) * Np;      // operator input
+  double *Vb = W.qlz;                                 // [K+1][Np]
+  double *inb = W.qlz + (size_t)(QUALITY_STEPS + 1) * Np;        // operator input
   double *tmp = inb + (size_t)2 * Np;
   double *outb = tmp + (size_t)2 * Np;
   double *tn = outb + (size_t)2 * Np;
   PcgWs S{};
-  S.sync = W.sync;
-  S.chain = tn + Np;
+  S.sync = W.qsync;
+  S.chain = tn + Np;                                  // [2][Np]
   S.L = 0;
-  S.cpart = W.yinv;
-  S.cnt = W.cnt;
-  double *ab = W.lzs;
+  S.cpart = W.qpart;
+  S.cnt = W.qcnt;
+  double *ab = W.qlzs;
   const double v0 = 1.0 / std::sqrt((double)n);
   {
     FillSet F;
-    F.add_i32(W.sync, 0, P->N + 8);
-    F.add_i32(W.cnt, 0, P->N);
+    F.add_i32(W.qsync, 0, P->N + 8);
+    F.add_i32(W.qcnt, 0, P->N);
     F.add_f64(Vb, v0, (size_t)n);
     F.add_f64(inb, v0, (size_t)n);
     F.add_f64(ab, 0.0, 2 * (size_t)K);
@@ -662,8 +709,13 @@ tls_status factor_quality(tls_precond_s *P, FactorWs &W, const MatView &V, hipSt
     TRY(apply_R(P, 1, 1, tn, outb, TLS_FP64, S, st));      // R^{-T} A^T A R^{-1} v
     HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
   }
+  return TLS_OK;
+}
+
+tls_status collect_cert(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  const int K = std::min(QUALITY_STEPS, (int)P->n);
   std::vector<double> h(2 * K + 2);
-  HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h.data(), W.qlzs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const int done = std::max(1, (int)h[2 * K + 1]);
   std::vector<double> a(h.begin(), h.begin() + done), b(h.begin() + K, h.begin() + K + done - 1);
@@ -671,32 +723,106 @@ tls_status factor_quality(tls_precond_s *P, FactorWs &W, const MatView &V, hipSt
   tridiag_extremes(a, b, &lo, &hi);
   P->rep.quality_lo = lo;
   P->rep.quality_hi = hi;
+  P->have_quality = 1;
   return TLS_OK;
 }
 
-// the A-only constraints of Section 3.1 from Lanczos estimates
-tls_status run_gate(tls_precond_s *P, FactorWs &W, hipStream_t st) {
-  tls_gate_report &R = P->rep;
-  const double n = (double)P->n;
-  TRY(run_estimates(P, W, st));
-  const double smin_s = P->smin_s, smax_s = P->smax_s;
-  const double kap = P->scaled ? smax_s / smin_s : R.sigma_1_est / R.sigma_n_est;
-  R.kappa_est = kap;
-  // ||A D^{-1}||_F = sqrt(n) exactly when scaled
-  R.kappaF_est = P->scaled ? std::sqrt(n) / smin_s : std::numeric_limits<double>::quiet_NaN();
-  R.lam_min_H = smin_s * smin_s;
-  R.bound5 = 1.0 / kap;
-  R.bound_chol = 1.0 / (kap * kap);
-  R.bound_wilkinson = 1.0 / (20.0 * std::pow(n, 1.5) * kap * kap);
-  R.bound_hp = R.lam_min_H / ((2.0 * R.lam_min_H + n) * (n + 1.0));
-  R.u_q = unit_roundoff(P->storage);
-  int v = 0;
-  if (R.u_q < R.bound5) v |= 1;
-  if (R.u_q < R.bound_chol) v |= 2;
-  if (R.u_q < R.bound_hp) v |= 4;
-  R.verdict = v;
-  P->have_kappa = 1;
+// two side streams per device, created once (default priority, non-blocking
+// so that work on the legacy default stream does not serialize with them);
+// they live until the process ends
+hipError_t side_streams(hipStream_t out[2]) {
+  static std::mutex mu;
+  static std::map<int, std::pair<hipStream_t, hipStream_t>> pool;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pool.find(dev);
+  if (it == pool.end()) {
+    hipStream_t a = nullptr, b = nullptr;
+    e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(a);
+      return e;
+    }
+    it = pool.emplace(dev, std::make_pair(a, b)).first;
+  }
+  out[0] = it->second.first;
+  out[1] = it->second.second;
+  return hipSuccess;
+}
+
+// the gate's Lanczos runs after everything enqueued on st so far: the
+// estimates on side stream 0, the certificate on side stream 1
+tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
+  HIPCHK(side_streams(P->side));
+  for (hipEvent_t *e : {&P->ev_fork, &P->ev_pair, &P->ev_cert})
+    if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  P->have_kappa = P->have_sigma_n = P->have_quality = 0;
+  HIPCHK(hipEventRecord(P->ev_fork, st));
+  HIPCHK(hipStreamWaitEvent(P->side[0], P->ev_fork, 0));
+  HIPCHK(hipStreamWaitEvent(P->side[1], P->ev_fork, 0));
+  // from here on the runs may be in flight: mark them before any early return
+  P->gate_pending = 1;
+  tls_status s0 = enqueue_pair(P, W, P->side[0]);
+  hipError_t e0 = hipEventRecord(P->ev_pair, P->side[0]);
+  tls_status s1 = enqueue_cert(P, W, V, P->side[1]);
+  hipError_t e1 = hipEventRecord(P->ev_cert, P->side[1]);
+  if (e0 != hipSuccess || e1 != hipSuccess) {
+    // without recorded events the runs cannot be awaited one by one
+    (void)hipDeviceSynchronize();
+    P->gate_pending = 0;
+    return fail(TLS_ERR_HIP, "hipEventRecord failed on a side stream");
+  }
+  if (s0 != TLS_OK || s1 != TLS_OK) {
+    (void)hipEventSynchronize(P->ev_pair);
+    (void)hipEventSynchronize(P->ev_cert);
+    P->gate_pending = 0;
+    return s0 != TLS_OK ? s0 : s1;
+  }
   return TLS_OK;
+}
+
+// both runs finished (without waiting)
+bool gate_ready(const tls_precond_s *P) {
+  return !P->gate_pending ||
+         (hipEventQuery(P->ev_pair) == hipSuccess && hipEventQuery(P->ev_cert) == hipSuccess);
+}
+
+FactorWs factor_ws_of(const tls_precond_s *P);
+
+// wait for both runs and evaluate them on the host
+tls_status gate_finish(tls_precond_s *P) {
+  if (!P->gate_pending) return TLS_OK;
+  P->gate_pending = 0;
+  HIPCHK(hipEventSynchronize(P->ev_pair));
+  HIPCHK(hipEventSynchronize(P->ev_cert));
+  FactorWs W = factor_ws_of(P);
+  TRY(collect_pair(P, W, P->side[0]));
+  TRY(collect_cert(P, W, P->side[1]));
+  return TLS_OK;
+}
+
+// the estimates alone, synchronously on st (the shift clamp of a
+// preconditioner whose gate never ran, e.g. an imported FP64 factor)
+tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+  TRY(gate_finish(P));
+  TRY(enqueue_pair(P, W, st));
+  return collect_pair(P, W, st);
+}
+
+// the b-dependent part of the gate: constraint (6) with sigma_{n+1} <=
+// sigma_0 and the estimates, and the certificate's verdict
+void gate_decide(tls_precond_s *P, double sigma_ls) {
+  tls_gate_report &R = P->rep;
+  const double ratio = (sigma_ls / R.sigma_n_est) * (sigma_ls / R.sigma_n_est);
+  R.ctilde_min = 1.0 - ratio;
+  R.bound6 = (1.0 - ratio) / R.kappaF_est;
+  R.verdict &= ~(8 | 16);
+  if (R.u_q < R.bound6) R.verdict |= 8;
+  if (R.quality_lo >= 0.5 && R.quality_hi <= 1.5) R.verdict |= 16;
 }
 
 FactorWs factor_ws_of(const tls_precond_s *P) {
@@ -820,13 +946,15 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
       int bd = 0;
       tls_status s = factor_once(A, P, W, uq, stream, &bd);
       if (s == TLS_OK) {
-        if (uq != TLS_FP64) TRY(run_gate(P, W, stream));
-        else P->rep.u_q = unit_roundoff(TLS_FP64);
-        const bool chol_ok = (P->rep.verdict & 2) || (P->rep.verdict & 4);
-        if (uq == TLS_FP64 || chol_ok || !allow_escalate) break;
-        // the A-only constraints fail: the a-posteriori evidence is the
-        // factorization itself (it succeeded); keep it unless escalation is
-        // requested explicitly by a failed b-dependent check in the solve
+        P->rep.u_q = unit_roundoff(uq);
+        // a low-precision factor is kept here even where the A-only
+        // constraints fail: the decision belongs to the certificate, read in
+        // the solve (which escalates if asked to); with rep == NULL the two
+        // Lanczos runs finish in the background
+        if (uq != TLS_FP64) {
+          TRY(gate_start(P, W, make_view(A, P), stream));
+          if (rep) TRY(gate_finish(P));
+        }
         break;
       }
       if (s != TLS_ERR_NOT_SPD || !allow_escalate || uq == TLS_FP64) return s;
@@ -1002,9 +1130,10 @@ struct RqiWs {
   PcgWs pcg;
 };
 
-RqiWs carve_rqi(Carver &c, int64_t m, int64_t n, const tls_precond_s *P, int kmax, int L) {
+RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s *P, int kmax, int L) {
   RqiWs W{};
   MatView V{};
+  V.format = format;   // the block counts of the row passes depend on it
   V.m = (int)m;
   V.n = (int)n;
   const int nb = std::max(matvec_blocks(V), rmatvec_blocks(V)) + 1;
@@ -1139,18 +1268,25 @@ extern "C" {
 size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P, const tls_rqi_opts *o) {
   if (check_matrix(A) != TLS_OK || !P || !o) return 0;
   const int kmax = std::max(1, std::min(o->kmax, TLS_MAX_ITERS));
-  const int L = std::max(kmax, o->refine_pcg_steps) + 1;
+  const int L = std::max({kmax, o->refine_pcg_steps, std::min(std::max(o->min_inner_steps, 0), 4096)}) + 1;
   Carver c(nullptr);
-  carve_rqi(c, A->m, A->n, P, kmax, L);
+  carve_rqi(c, A->format, A->m, A->n, P, kmax, L);
   return c.size();
 }
 
-tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
-                         double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
-                         hipStream_t st) {
+}  // extern "C"
+
+namespace {
+
+using solve_clock = std::chrono::steady_clock;
+
+// the solve from a given start time (an escalation re-enters with the
+// caller's start, so t_ms keeps counting from the original call)
+tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
+                          double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
+                          hipStream_t st, solve_clock::time_point t0, double t_factor_prior) {
   try {
-    using clk = std::chrono::steady_clock;
-    const auto t0 = clk::now();
+    using clk = solve_clock;
     auto ms_since = [&](clk::time_point a) {
       return std::chrono::duration<double, std::milli>(clk::now() - a).count();
     };
@@ -1164,13 +1300,15 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return fail(TLS_ERR_ARG, "refine_sweeps must be in [0, 4]");
     if (o->refine_sweeps > 0 && o->refine_pcg_steps < 1) return fail(TLS_ERR_ARG, "refine_pcg_steps must be >= 1");
     if (o->mlp_theta && !o->mlp_norm) return fail(TLS_ERR_ARG, "mlp_theta needs mlp_norm");
+    if (o->min_inner_steps < 0 || o->min_inner_steps > 4096)
+      return fail(TLS_ERR_ARG, "min_inner_steps must be in [0, 4096]");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     const size_t need = tls_rqi_workspace_size(A, P, o);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "RQI workspace %zu < %zu bytes", ws_bytes, need);
     const int kmax = o->kmax;
-    const int L = std::max(kmax, o->refine_pcg_steps) + 1;
+    const int L = std::max({kmax, o->refine_pcg_steps, o->min_inner_steps}) + 1;
     Carver c(ws);
-    RqiWs W = carve_rqi(c, A->m, A->n, P, kmax, L);
+    RqiWs W = carve_rqi(c, A->format, A->m, A->n, P, kmax, L);
     const int n = (int)A->n;
     const int m = (int)A->m;
     const MatView V = make_view(A, P);
@@ -1178,6 +1316,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
     tls_rqi_stats local{};
     tls_rqi_stats &S = stats ? *stats : local;
     std::memset(&S, 0, sizeof S);
+    S.t_factor_ms = t_factor_prior;
 
     {
       FillSet F;
@@ -1207,6 +1346,7 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
 
     // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1; the b-dependent gate ---
     double rr0 = 0.0;
+    bool spec = false;
     for (;;) {
       HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
       if (o->mlp_theta || o->sigma0_hint > 0 || o->features) {
@@ -1232,27 +1372,24 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       S.sigma_ls = std::sqrt(h2[0]);
       rr0 = h2[3];
       if (!(o->gate_enforce && P->storage != TLS_FP64)) break;
-      // constraint (6) with sigma_{n+1} <= sigma_0 and the Lanczos estimates
-      if (!P->have_kappa) {
-        FactorWs FW = factor_ws_of(P);
-        TRY(run_gate(P, FW, st));
-      }
-      tls_gate_report &R = P->rep;
-      const double ratio = (S.sigma_ls / R.sigma_n_est) * (S.sigma_ls / R.sigma_n_est);
-      R.ctilde_min = 1.0 - ratio;
-      R.bound6 = (1.0 - ratio) / R.kappaF_est;
-      R.verdict &= ~(8 | 16);
-      if (R.u_q < R.bound6) R.verdict |= 8;
-      // a-posteriori certificate of the factor itself (the estimates above
+      // constraint (6) with sigma_{n+1} <= sigma_0 and the Lanczos estimates,
+      // and the a-posteriori certificate of the factor itself (the estimates
       // come from the factor and cannot reveal that it is poor)
-      {
+      if (!P->gate_pending && !P->have_quality) {
         FactorWs FW = factor_ws_of(P);
-        TRY(factor_quality(P, FW, V, st));
-        if (R.quality_lo >= 0.5 && R.quality_hi <= 1.5) R.verdict |= 16;
+        TRY(gate_start(P, FW, V, st));
+      }
+      // runs still in flight: iterate speculatively and decide at a later
+      // host synchronisation (the shift clamp needs the estimates first)
+      spec = P->gate_pending && !o->shift_clamp;
+      if (!spec) {
+        TRY(gate_finish(P));
+        gate_decide(P, S.sigma_ls);
       }
       break;
     }
-    const bool gate_failed = o->gate_enforce && P->storage != TLS_FP64 && !(P->rep.verdict & 16);
+    const bool gate_failed = !spec && o->gate_enforce && P->storage != TLS_FP64 &&
+                             !(P->rep.verdict & 16);
     auto escalate = [&]() -> tls_status {
       tls_gate_report &R = P->rep;
       if (!o->allow_escalate)
@@ -1263,198 +1400,236 @@ tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, co
       const int next = (P->storage == TLS_BF16) ? TLS_FP16 : (P->storage == TLS_FP16) ? TLS_FP32 : TLS_FP64;
       FactorWs FW = factor_ws_of(P);
       int bd = 0;
+      TRY(gate_finish(P));   // its runs read the factor that is replaced now
       TRY(factor_once(A, P, FW, next, st, &bd));
-      P->have_kappa = P->have_sigma_n = 0;
-      if (next != TLS_FP64) TRY(run_gate(P, FW, st));
+      P->have_kappa = P->have_sigma_n = P->have_quality = 0;
+      if (next != TLS_FP64) TRY(gate_start(P, FW, V, st));
       R.escalations++;
       R.used = P->storage;
       S.t_factor_ms += ms_since(tf);
       return TLS_OK;
     };
-    if (gate_failed) {
+    auto resolve = [&]() -> tls_status {
       TRY(escalate());
-      return tls_rqi_solve(A, b, P, o, x, sigma, stats, ws, ws_bytes, st);
-    }
+      return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, t0, S.t_factor_ms);
+    };
+    if (gate_failed) return resolve();
     // shift cap for the clamp (a deviation for starts above sigma'_n)
     double cap = 0.0;
     if (o->shift_clamp && !P->have_sigma_n) {
-      FactorWs FW = factor_ws_of(P);
-      TRY(estimate_sigma_n(P, FW, st));
+      TRY(gate_finish(P));
+      if (!P->have_sigma_n) {
+        FactorWs FW = factor_ws_of(P);
+        TRY(estimate_sigma_n(P, FW, st));
+      }
     }
     if (o->shift_clamp && std::isfinite(P->rep.sigma_n_est) && P->rep.sigma_n_est > 0)
       cap = o->shift_clamp_tau * P->rep.sigma_n_est * P->rep.sigma_n_est;
 
-    TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
-    const bool warm = o->mlp_theta != nullptr || o->sigma0_hint > 0;
-    bool plain_step = true;
-    if (warm || o->features) {
-      // u_1 = (R^T R)^{-1} u_0 and the dot products of the features
-      double *u1 = W.rp, *xw = W.rq;
-      TRY(solve_normal(P, W.t1, u1, W.t2, W.pcg, st));
-      DotPairs D{};
-      const double *pa[5] = {x, x, W.t1, W.t1, u1}, *pb[5] = {x, W.t1, W.t1, u1, u1};
-      for (int i = 0; i < 5; ++i) { D.a[i] = pa[i]; D.b[i] = pb[i]; D.len[i] = n; }
-      HIPCHK(launch_dots(D, 5, W.scal + 26, st));
-      double hd[7];
-      HIPCHK(hipMemcpyAsync(hd, W.scal + 24, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      WarmScalars ws_{};
-      ws_.m = (double)m; ws_.n = (double)n; ws_.nA2 = P->normA_F2; ws_.bb = hd[0]; ws_.atb2 = hd[1];
-      ws_.s0 = S.sigma_ls; ws_.xx = hd[2]; ws_.xu = hd[3]; ws_.uu = hd[4]; ws_.uv = hd[5];
-      ws_.vv = hd[6]; ws_.rr = rr0;
-      for (int i = 0; i < 4; ++i) ws_.lnd[i] = P->lnd[i];
-      warm_features(ws_, S.features);
-      double sig_hat = -1.0;
-      if (o->mlp_theta) {
-        HIPCHK(hipMemcpyAsync(W.rs, S.features, TLS_MLP_IN * sizeof(float), hipMemcpyHostToDevice, st));
-        HIPCHK(launch_mlp_infer1(o->mlp_theta, o->mlp_norm, (const float *)W.rs, W.scal + 22, st));
-        double yh = 0.0;
-        HIPCHK(hipMemcpyAsync(&yh, W.scal + 22, sizeof(double), hipMemcpyDeviceToHost, st));
+    S.gate_async = spec ? 1 : 0;
+    // everything from here on uses the factor; under speculation the gate's
+    // verdict is read when its runs are done (polled at each psi read-back,
+    // awaited at the end) and a failed certificate discards the result
+    auto body = [&]() -> tls_status {
+      TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
+      const bool warm = o->mlp_theta != nullptr || o->sigma0_hint > 0;
+      bool plain_step = true;
+      if (warm || o->features) {
+        // u_1 = (R^T R)^{-1} u_0 and the dot products of the features
+        double *u1 = W.rp, *xw = W.rq;
+        TRY(solve_normal(P, W.t1, u1, W.t2, W.pcg, st));
+        DotPairs D{};
+        const double *pa[5] = {x, x, W.t1, W.t1, u1}, *pb[5] = {x, W.t1, W.t1, u1, u1};
+        for (int i = 0; i < 5; ++i) { D.a[i] = pa[i]; D.b[i] = pb[i]; D.len[i] = n; }
+        HIPCHK(launch_dots(D, 5, W.scal + 26, st));
+        double hd[7];
+        HIPCHK(hipMemcpyAsync(hd, W.scal + 24, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        // y = ln(1 - sigma^2 / sigma_0^2) = two-point Gauss estimate + learned correction
-        const double y = (double)S.features[31] + yh;
-        if (std::isfinite(y)) sig_hat = S.sigma_ls * std::sqrt(std::max(0.0, -std::expm1(std::min(y, 0.0))));
-      } else if (o->sigma0_hint > 0) {
-        sig_hat = o->sigma0_hint;
-      }
-      if (warm && sig_hat >= 0.0) {
-        sig_hat = std::min(sig_hat, S.sigma_ls);
-        if (cap > 0) sig_hat = std::min(sig_hat, std::sqrt(cap));
-        const double lam = sig_hat * sig_hat;
-        HIPCHK(launch_axpy2(n, x, W.t1, u1, lam, lam * lam, xw, st));      // warm candidate
-        HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));              // plain x_1
-        plain_step = false;
-        double pw = 0.0, pp = 0.0;
-        TRY(evaluate_at(xw, 1, cap));
-        HIPCHK(hipMemcpyAsync(&pw, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        TRY(evaluate_at(x, 1, cap));
-        HIPCHK(hipMemcpyAsync(&pp, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        S.sigma_hat = sig_hat;
-        S.psi_warm = pw;
-        S.psi_plain = pp;
-        if (pw < pp) {
-          HIPCHK(launch_copy_f64(x, xw, (size_t)n, st));
-          S.warm_used = 1;
-        }
-      }
-    }
-    if (plain_step) HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));   // x_1 = x_0 + sigma_0^2 u_0
-
-    // ---- main loop -----------------------------------------------------------
-    double best = std::numeric_limits<double>::infinity();
-    int no_improve = 0, k = 0;
-    S.stopped = 1;
-    double h[16];
-    for (k = 1; k <= kmax; ++k) {
-      TRY(evaluate(k, cap));
-      if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
-      HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      const double psi = h[7], sig2 = h[0];
-      S.iters = k;
-      S.psi[k - 1] = psi;
-      S.sigma[k - 1] = std::sqrt(sig2);
-      S.t_ms[k - 1] = ms_since(t0);
-      if (h[1] != h[0]) S.clamped++;
-      if (!std::isfinite(psi)) return fail(TLS_ERR_NO_CONVERGENCE, "psi became non-finite at k = %d", k);
-      if (psi < best) {          // the psi kernel has copied x to xbest
-        best = psi;
-        S.k_best = k;
-        no_improve = 0;
-      } else if (o->stop_ge ? (psi >= best) : (psi > best)) {
-        ++no_improve;
-      }
-      if (psi == 0.0) { S.stopped = 2; break; }
-      if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
-      if (k == kmax) break;
-      // two PCGTLS solves with l = k (k+1 steps), sharing the shift; the
-      // right-hand sides [-f, x] were written by the psi kernel
-      TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, k, o->u_p, o->strict_pd, W.pcg, st));
-      S.pcg_steps += k + 1;
-      HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
-    }
-    // the returned iterate
-    HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
-
-    // ---- final FP64 refinement: RQI steps with explicit-operator PCG --------
-    // (skipped when psi already sits at the float64 rounding floor u ||A||_F^2)
-    const bool at_floor = P->normA_F2 > 0 && best <= 32.0 * unit_roundoff(TLS_FP64) * P->normA_F2;
-    for (int sw = 0; sw < (at_floor ? 0 : o->refine_sweeps); ++sw) {
-      TRY(evaluate(kmax + 1 + sw, cap));                   // f, g and the (clamped) shift at x
-      {
-        // a Newton step is only meaningful at the Rayleigh-quotient shift: if the
-        // clamp is active the iterate is not yet near sigma_{n+1}; stop refining
-        double hs[2];
-        HIPCHK(hipMemcpyAsync(hs, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (hs[1] != hs[0]) break;
-      }
-      HIPCHK(launch_make_rhs(n, W.f, x, W.rr, st));          // r = [-f, x], omega = u = 0
-      HIPCHK(launch_fill_f64(W.wu, 0.0, 2 * (size_t)n, st));
-      // z = M r with M = (R^T R)^{-1} applied in FP64 arithmetic to the stored
-      // factor: a fixed symmetric preconditioner, so CG reaches FP64 accuracy
-      TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
-      TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
-      HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 1, st));
-      double rz0[8];
-      HIPCHK(hipMemcpyAsync(rz0, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      for (int j = 0; j < o->refine_pcg_steps; ++j) {
-        if (j > 0 && j % 8 == 0) {
-          // stop when both preconditioned residuals r^T M r fell by 1e-26
-          double rzj[8];
-          HIPCHK(hipMemcpyAsync(rzj, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        WarmScalars ws_{};
+        ws_.m = (double)m; ws_.n = (double)n; ws_.nA2 = P->normA_F2; ws_.bb = hd[0]; ws_.atb2 = hd[1];
+        ws_.s0 = S.sigma_ls; ws_.xx = hd[2]; ws_.xu = hd[3]; ws_.uu = hd[4]; ws_.uv = hd[5];
+        ws_.vv = hd[6]; ws_.rr = rr0;
+        for (int i = 0; i < 4; ++i) ws_.lnd[i] = P->lnd[i];
+        warm_features(ws_, S.features);
+        double sig_hat = -1.0;
+        if (o->mlp_theta) {
+          HIPCHK(hipMemcpyAsync(W.rs, S.features, TLS_MLP_IN * sizeof(float), hipMemcpyHostToDevice, st));
+          HIPCHK(launch_mlp_infer1(o->mlp_theta, o->mlp_norm, (const float *)W.rs, W.scal + 22, st));
+          double yh = 0.0;
+          HIPCHK(hipMemcpyAsync(&yh, W.scal + 22, sizeof(double), hipMemcpyDeviceToHost, st));
           HIPCHK(hipStreamSynchronize(st));
-          if (rzj[0] <= 1e-26 * rz0[0] && rzj[4] <= 1e-26 * rz0[4]) break;
+          // y = ln(1 - sigma^2 / sigma_0^2) = two-point Gauss estimate + learned correction
+          const double y = (double)S.features[31] + yh;
+          if (std::isfinite(y)) sig_hat = S.sigma_ls * std::sqrt(std::max(0.0, -std::expm1(std::min(y, 0.0))));
+        } else if (o->sigma0_hint > 0) {
+          sig_hat = o->sigma0_hint;
         }
-        for (int q = 0; q < 2; ++q) {                         // K p = A^T (A p) - mu p
-          HIPCHK(launch_matvec(V, W.rp + (size_t)q * n, W.rt + (size_t)q * m, st));
-          HIPCHK(launch_rmatvec(V, W.rt + (size_t)q * m, W.rq + (size_t)q * n, st));
+        if (warm && sig_hat >= 0.0) {
+          sig_hat = std::min(sig_hat, S.sigma_ls);
+          if (cap > 0) sig_hat = std::min(sig_hat, std::sqrt(cap));
+          const double lam = sig_hat * sig_hat;
+          HIPCHK(launch_axpy2(n, x, W.t1, u1, lam, lam * lam, xw, st));      // warm candidate
+          HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));              // plain x_1
+          plain_step = false;
+          double pw = 0.0, pp = 0.0;
+          TRY(evaluate_at(xw, 1, cap));
+          HIPCHK(hipMemcpyAsync(&pw, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          TRY(evaluate_at(x, 1, cap));
+          HIPCHK(hipMemcpyAsync(&pp, W.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          S.sigma_hat = sig_hat;
+          S.psi_warm = pw;
+          S.psi_plain = pp;
+          if (pw < pp) {
+            HIPCHK(launch_copy_f64(x, xw, (size_t)n, st));
+            S.warm_used = 1;
+          }
         }
-        HIPCHK(launch_ref_step1(n, 2, W.scal, W.wu, W.rr, W.rp, W.rq, W.rs, st));
+      }
+      if (plain_step) HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));   // x_1 = x_0 + sigma_0^2 u_0
+
+      // ---- main loop -----------------------------------------------------------
+      double best = std::numeric_limits<double>::infinity();
+      int no_improve = 0, k = 0;
+      S.stopped = 1;
+      double h[16];
+      for (k = 1; k <= kmax; ++k) {
+        TRY(evaluate(k, cap));
+        if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
+        HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const double psi = h[7], sig2 = h[0];
+        S.iters = k;
+        S.psi[k - 1] = psi;
+        S.sigma[k - 1] = std::sqrt(sig2);
+        S.t_ms[k - 1] = ms_since(t0);
+        if (spec && P->gate_pending && gate_ready(P)) {
+          TRY(gate_finish(P));
+          gate_decide(P, S.sigma_ls);
+          if (!(P->rep.verdict & 16)) return TLS_OK;   // discarded below: escalation
+        }
+        if (h[1] != h[0]) S.clamped++;
+        if (!std::isfinite(psi)) return fail(TLS_ERR_NO_CONVERGENCE, "psi became non-finite at k = %d", k);
+        if (psi < best) {          // the psi kernel has copied x to xbest
+          best = psi;
+          S.k_best = k;
+          no_improve = 0;
+        } else if (o->stop_ge ? (psi >= best) : (psi > best)) {
+          ++no_improve;
+        }
+        // psi == 0, or exactly the previous psi: the iterate no longer moves
+        if (psi == 0.0 || (k > 1 && psi == S.psi[k - 2])) { S.stopped = 2; break; }
+        if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
+        if (k == kmax) break;
+        // two PCGTLS solves with l = k (k+1 steps; at least min_inner_steps
+        // when asked), sharing the shift; the right-hand sides [-f, x] were
+        // written by the psi kernel
+        const int l = std::max(k, o->min_inner_steps);
+        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, l, o->u_p, o->strict_pd, W.pcg, st));
+        S.pcg_steps += l + 1;
+        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+      }
+      // the returned iterate
+      HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
+
+      // ---- final FP64 refinement: RQI steps with explicit-operator PCG --------
+      // (skipped when psi already sits at the float64 rounding floor u ||A||_F^2)
+      const bool at_floor = P->normA_F2 > 0 && best <= 32.0 * unit_roundoff(TLS_FP64) * P->normA_F2;
+      for (int sw = 0; sw < (at_floor ? 0 : o->refine_sweeps); ++sw) {
+        TRY(evaluate(kmax + 1 + sw, cap));                   // f, g and the (clamped) shift at x
+        {
+          // a Newton step is only meaningful at the Rayleigh-quotient shift: if the
+          // clamp is active the iterate is not yet near sigma_{n+1}; stop refining
+          double hs[2];
+          HIPCHK(hipMemcpyAsync(hs, W.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          if (hs[1] != hs[0]) break;
+        }
+        HIPCHK(launch_make_rhs(n, W.f, x, W.rr, st));          // r = [-f, x], omega = u = 0
+        HIPCHK(launch_fill_f64(W.wu, 0.0, 2 * (size_t)n, st));
+        // z = M r with M = (R^T R)^{-1} applied in FP64 arithmetic to the stored
+        // factor: a fixed symmetric preconditioner, so CG reaches FP64 accuracy
         TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
         TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
-        HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 0, st));
+        HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 1, st));
+        double rz0[8];
+        HIPCHK(hipMemcpyAsync(rz0, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int j = 0; j < o->refine_pcg_steps; ++j) {
+          if (j > 0 && j % 8 == 0) {
+            // stop when both preconditioned residuals r^T M r fell by 1e-26
+            double rzj[8];
+            HIPCHK(hipMemcpyAsync(rzj, W.rs, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (rzj[0] <= 1e-26 * rz0[0] && rzj[4] <= 1e-26 * rz0[4]) break;
+          }
+          for (int q = 0; q < 2; ++q) {                         // K p = A^T (A p) - mu p
+            HIPCHK(launch_matvec(V, W.rp + (size_t)q * n, W.rt + (size_t)q * m, st));
+            HIPCHK(launch_rmatvec(V, W.rt + (size_t)q * m, W.rq + (size_t)q * n, st));
+          }
+          HIPCHK(launch_ref_step1(n, 2, W.scal, W.wu, W.rr, W.rp, W.rq, W.rs, st));
+          TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
+          TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
+          HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 0, st));
+        }
+        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+        S.refine_steps++;
+        // keep the refined iterate only if psi improves
+        TRY(evaluate(kmax + 1 + sw, cap));
+        HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (h[7] < best) {
+          best = h[7];
+          HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
+        } else {
+          HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
+          break;
+        }
       }
-      HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
-      S.refine_steps++;
-      // keep the refined iterate only if psi improves
-      TRY(evaluate(kmax + 1 + sw, cap));
-      HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+      // final sigma from a compensated residual at x
+      HIPCHK(launch_residual_dd(V, b, x, W.part, st));
+      HIPCHK(launch_sigma_dd(n, x, W.part, nb_r, W.scal + 20, st));
+      double sg[2];
+      HIPCHK(hipMemcpyAsync(sg, W.scal + 20, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      if (h[7] < best) {
-        best = h[7];
-        HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
-      } else {
-        HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
-        break;
+      TRY(sync_status(W.pcg.sync, P->N, st));
+      {
+        // PCGTLS steps that met delta_j < 0 (the last run's flags)
+        std::vector<int> neg((size_t)(W.pcg.L + 2) * 2);
+        HIPCHK(hipMemcpyAsync(neg.data(), W.pcg.neg, neg.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int v : neg) S.negative_delta += v;
       }
+      S.sigma_final = sg[1];
+      if (sigma) *sigma = sg[1];
+      S.t_total_ms = ms_since(t0);
+      if (S.stopped == 1)
+        return fail(TLS_ERR_NO_CONVERGENCE, "kmax = %d reached before the psi rule fired", kmax);
+      return TLS_OK;
+    };
+    const tls_status bs = body();
+    if (spec) {
+      if (P->gate_pending) {
+        TRY(gate_finish(P));
+        gate_decide(P, S.sigma_ls);
+      }
+      if (!(P->rep.verdict & 16)) return resolve();
     }
-    // final sigma from a compensated residual at x
-    HIPCHK(launch_residual_dd(V, b, x, W.part, st));
-    HIPCHK(launch_sigma_dd(n, x, W.part, nb_r, W.scal + 20, st));
-    double sg[2];
-    HIPCHK(hipMemcpyAsync(sg, W.scal + 20, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    TRY(sync_status(W.pcg.sync, P->N, st));
-    {
-      // PCGTLS steps that met delta_j < 0 (the last run's flags)
-      std::vector<int> neg((size_t)(W.pcg.L + 2) * 2);
-      HIPCHK(hipMemcpyAsync(neg.data(), W.pcg.neg, neg.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      for (int v : neg) S.negative_delta += v;
-    }
-    S.sigma_final = sg[1];
-    if (sigma) *sigma = sg[1];
-    S.t_total_ms = ms_since(t0);
-    if (S.stopped == 1)
-      return fail(TLS_ERR_NO_CONVERGENCE, "kmax = %d reached before the psi rule fired", kmax);
-    return TLS_OK;
+    return bs;
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
+                         double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+  return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, solve_clock::now(), 0.0);
 }
 
 }  // extern "C"

@@ -74,15 +74,18 @@ class c_rqi_opts(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "u_p", "kmax", "stop_patience", "stop_ge", "ls_corrections", "strict_pd",
         "shift_clamp", "refine_sweeps", "refine_pcg_steps", "allow_escalate",
-        "gate_enforce", "features")] + \
+        "gate_enforce", "features", "min_inner_steps", "reserved")] + \
         [("shift_clamp_tau", C.c_double), ("sigma0_hint", C.c_double),
          ("x_snapshots", C.c_void_p), ("mlp_theta", C.c_void_p), ("mlp_norm", C.c_void_p)]
+
+
+_OPT_FIELDS = {name for name, _ in c_rqi_opts._fields_}
 
 
 class c_rqi_stats(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "iters", "k_best", "pcg_steps", "warm_used", "stopped", "negative_delta",
-        "refine_steps", "clamped")] + \
+        "refine_steps", "clamped", "gate_async", "reserved")] + \
         [("sigma_ls", C.c_double), ("psi", C.c_double * MAX_ITERS),
          ("sigma", C.c_double * MAX_ITERS), ("t_ms", C.c_double * MAX_ITERS),
          ("t_factor_ms", C.c_double), ("t_total_ms", C.c_double), ("sigma_final", C.c_double),
@@ -95,7 +98,7 @@ class c_rqi_stats(C.Structure):
             "iters": k, "k_best": self.k_best, "pcg_steps": self.pcg_steps,
             "warm_used": self.warm_used, "stopped": self.stopped,
             "negative_delta": self.negative_delta, "refine_steps": self.refine_steps,
-            "clamped": self.clamped, "sigma_ls": self.sigma_ls,
+            "clamped": self.clamped, "gate_async": self.gate_async, "sigma_ls": self.sigma_ls,
             "psi": list(self.psi[:k]), "sigma": list(self.sigma[:k]), "t_ms": list(self.t_ms[:k]),
             "t_factor_ms": self.t_factor_ms, "t_total_ms": self.t_total_ms,
             "sigma_final": self.sigma_final, "sigma_hat": self.sigma_hat,
@@ -297,8 +300,11 @@ def _prec(p) -> int:
     return PREC[p] if isinstance(p, str) else int(p)
 
 
-def tls_factor_precond(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False):
-    """Build the preconditioner of A (see tls.h). Returns (Precond, gate report dict)."""
+def tls_factor_precond(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False, wait_gate=True):
+    """Build the preconditioner of A (see tls.h). Returns (Precond, gate report
+    dict). With wait_gate=False the gate's Lanczos runs of a low-precision
+    factor finish in the background (the solve overlaps them) and the report
+    is None; Precond.info() waits for them."""
     L = lib()
     nb = L.tls_factor_workspace_size(C.byref(A.c), _prec(u_q))
     if nb == 0:
@@ -307,8 +313,9 @@ def tls_factor_precond(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False
     h = C.c_void_p()
     rep = c_gate_report()
     _check(L.tls_factor_precond(C.byref(A.c), _prec(u_q), int(scaling), int(allow_escalate),
-                                ws.ptr, ws.nbytes, _stream(), C.byref(h), C.byref(rep)))
-    return Precond(h, ws, A), rep.to_dict()
+                                ws.ptr, ws.nbytes, _stream(), C.byref(h),
+                                C.byref(rep) if wait_gate else None))
+    return Precond(h, ws, A), (rep.to_dict() if wait_gate else None)
 
 
 def tls_precond_import(R, d=None, storage="fp64"):
@@ -420,6 +427,8 @@ def default_opts(**kw) -> c_rqi_opts:
             o.mlp_theta = theta.data_ptr() if theta is not None else None
             o.mlp_norm = norm.data_ptr() if norm is not None else None
             continue
+        if k not in _OPT_FIELDS:
+            raise TypeError(f"unknown option {k!r}")
         setattr(o, k, v)
     return o
 

@@ -124,6 +124,46 @@ def test_gate_rejects_then_escalates():
     assert np.isfinite(sigma) and st["iters"] >= 2
 
 
+def _solve_pair(tls, Ad, b, u_q, opts, wait_gate):
+    P, _ = tls.tls_factor_precond(Ad, u_q, wait_gate=wait_gate)
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts, allow_no_convergence=True)
+    return x.cpu().numpy(), sigma, st, P.info()
+
+
+def test_background_gate_gives_the_waiting_result():
+    # the gate's Lanczos runs overlap the iterations: same iterate, same
+    # sigma, same report as when the factorization call waits for them
+    tls = _tls()
+    print("background gate, sparse 20000x2000 fp16", flush=True)
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    Ad = tls.from_tlsgen(A)
+    opts = tls.default_opts(u_p="fp32", stop_patience=2, gate_enforce=1, allow_escalate=1,
+                            refine_sweeps=1)
+    xw, sw, stw, iw = _solve_pair(tls, Ad, b, "fp16", opts, True)
+    xa, sa, sta, ia = _solve_pair(tls, Ad, b, "fp16", opts, False)
+    assert stw["gate_async"] == 0 and sta["gate_async"] == 1
+    assert xw.tobytes() == xa.tobytes() and sw == sa
+    assert stw["psi"] == sta["psi"]
+    for key in ("verdict", "quality_lo", "quality_hi", "kappa_est", "sigma_n_est", "bound6", "used"):
+        assert iw["gate"][key] == ia["gate"][key], key
+    assert ia["gate"]["verdict"] & 16
+
+
+def test_background_gate_failure_escalates_like_waiting():
+    # a bf16 factor the certificate may reject: the speculative iterations
+    # are discarded and the escalated solve returns the waiting order's result
+    tls = _tls()
+    A, b, x_t, lam, sn = _gap_problem(1e-3, seed=4002)
+    Ad = tls.from_tlsgen(A)
+    opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=3, kmax=120)
+    xw, sw, stw, iw = _solve_pair(tls, Ad, b, "bf16", opts, True)
+    xa, sa, sta, ia = _solve_pair(tls, Ad, b, "bf16", opts, False)
+    print(f"escalations {iw['gate']['escalations']} / {ia['gate']['escalations']}", flush=True)
+    assert iw["gate"]["escalations"] == ia["gate"]["escalations"]
+    assert iw["gate"]["used"] == ia["gate"]["used"]
+    assert xw.tobytes() == xa.tobytes() and sw == sa
+
+
 def test_shift_clamp_recovers_smallest_root():
     tls = _tls()
     A, b = tlsgen.paper_bjorck()
