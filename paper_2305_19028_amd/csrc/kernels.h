@@ -114,7 +114,9 @@ hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, 
                              int scaled, int q, int compute, void *G, hipStream_t st);
 hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st);
 hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st);
-hipError_t launch_cholesky(int N, int Np, int compute, void *G, int *info, hipStream_t st);
+// blocked Cholesky of G in place (upper); rdiag: N 64x64 tiles of scratch
+// in the compute precision (the diagonal tiles while the steps run)
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st);
 hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
                              hipStream_t st);
 hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64,

@@ -722,67 +722,202 @@ hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, 
 // blocked right-looking Cholesky, upper: G = R^T R, 64x64 tiles
 // --------------------------------------------------------------------------
 
-// Panel k of the blocked Cholesky, one launch of N - k workgroups.
-// Workgroup j eliminates the augmented block [G(k,k) | G(k,k+j)] (j = 0: the
-// diagonal tile alone): the same elimination that turns G(k,k) into R(k,k)
-// turns the appended columns into R(k,k+j) = R(k,k)^{-T} G(k,k+j).
-// Thread (tr, tc) holds the 4x4 register blocks of rows 4tr.. and columns
-// 4tc.. of both tiles; the 16 threads of one row group are a quarter wave.
-// The 64 columns are taken four at a time. For group g the owning quarter
-// wave gathers the 4x4 diagonal block by cross-lane shuffles, factors it
-// (redundantly in each lane, so all lanes agree bit for bit), turns its
-// four rows into rows of R and publishes them in a double-buffered LDS slab;
-// after one barrier the rows below take the rank-4 update. One barrier per
-// four columns; the finished rows are staged in LDS and written coalesced.
+// U = Ri^T Rj for two 64x64 tiles in LDS (Ri[t][r] = entry (t, r) of the
+// tile of R whose columns index U's rows) on the matrix cores. Wave w takes
+// the 32x32 quadrant (rows 32 (w % 2).., columns 32 (w / 2)..). The operands
+// are passed transposed (A from Rj, B from Ri) so that consecutive lanes
+// hold consecutive rows r of U: the callback emit(r, c, value) then touches
+// contiguous column-major addresses.
+template <typename C, typename Emit>
+__device__ inline void tile_product_t(const C (*Ri)[NB + 1], const C (*Rj)[NB + 1], Emit emit) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  if constexpr (std::is_same<C, double>::value) {
+    g_f64x4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) acc[t][u] = g_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      double a[2], bb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = Rj[k0 + (lane >> 4)][wr * 32 + t * 16 + (lane & 15)];
+        bb[t] = Ri[k0 + (lane >> 4)][wc * 32 + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bb[u], acc[t][u], 0, 0, 0);
+    }
+    // D(row, col) = sum Rj(t, c) Ri(t, r): col -> r, row -> c
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          emit(wc * 32 + u * 16 + (lane & 15), wr * 32 + t * 16 + 4 * q + (lane >> 4), acc[t][u][q]);
+  } else {
+    g_f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+#pragma unroll 8
+    for (int k0 = 0; k0 < NB; k0 += 2) {
+      const float a = Rj[k0 + (lane >> 5)][wr * 32 + (lane & 31)];
+      const float bb = Ri[k0 + (lane >> 5)][wc * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      emit(wc * 32 + (lane & 31), wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3), acc[q]);
+  }
+}
+
+// the (r, c) positions tile_product_t gives this lane, in the same order
+template <typename C, typename At>
+__device__ inline void tile_product_t_index(At at) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  if constexpr (std::is_same<C, double>::value) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) at(wc * 32 + u * 16 + (lane & 15), wr * 32 + t * 16 + 4 * q + (lane >> 4));
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) at(wc * 32 + (lane & 31), wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3));
+  }
+}
+
+// a 64x64 tile at (row block I, column block J) of G into registers (16
+// values per thread, all loads in flight before the first wait), then LDS
 template <typename C>
-__global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *info) {
-  __shared__ C stage[NB][NB + 1];
+__device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB + 1]) {
+  C tmp[16];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q;
+    tmp[q] = G[((size_t)J * NB + t / NB) * Np + (size_t)I * NB + t % NB];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int t = tid + 256 * q;
+    dst[t % NB][t / NB] = tmp[q];
+  }
+}
+
+// One step of the blocked right-looking Cholesky (upper, G = R^T R, 64x64
+// tiles), for block row p. Launch k (FUSED) carries two kinds of workgroups
+// that touch disjoint tiles:
+//  - panel workgroups 0 .. N-p-1 factor block row p = k + 1. Workgroup j
+//    takes step k's update of its two tiles itself,
+//      G(p,p) - R(k,p)^T R(k,p),  G(p,p+j) - R(k,p)^T R(k,p+j)
+//    (two MFMA products from the R tiles of row k), then eliminates the
+//    augmented block [G(p,p) | G(p,p+j)] (j = 0: the diagonal tile alone):
+//    the elimination that turns G(p,p) into R(p,p) turns the appended
+//    columns into R(p,p+j) = R(p,p)^{-T} G(p,p+j);
+//  - update workgroups take step k's update G(i,j) -= R(k,i)^T R(k,j) of the
+//    tiles in block rows i >= k + 2 (k + 2 <= i <= j < N), one pair each.
+// So the trailing update of step k runs beside the panel of step k + 1,
+// and the chain of dependent launches is one per block row. The first
+// launch (not FUSED) is the panel of block row 0 alone.
+// Panel elimination: thread (tr, tc) holds the 4x4 register blocks of rows
+// 4tr.. and columns 4tc.. of both tiles; the 16 threads of one row group are
+// a quarter wave. The 64 columns are taken four at a time. For group g the
+// owning quarter wave gathers the 4x4 diagonal block by cross-lane
+// shuffles, factors it (redundantly in each lane, so all lanes agree bit
+// for bit), turns its four rows into rows of R and publishes them in a
+// double-buffered LDS slab; after one barrier the rows below take the
+// rank-4 update. One barrier per four columns; the finished rows are staged
+// in LDS and written coalesced.
+// R(p,p) goes to rdiag (tile p, column-major), not to G: the other panel
+// workgroups of the launch still read G(p,p). k_chol_restore copies the
+// diagonal tiles back at the end.
+template <typename C, bool FUSED>
+__global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C *rdiag, int *info) {
+  __shared__ C ta[NB][NB + 1];     // R(k, .) operand / staged G(p,p) / output tile
+  __shared__ C tb[NB][NB + 1];     // R(k, .) operand / staged G(p,p+j)
   __shared__ C slab[2][4][2 * NB];
   __shared__ int bad_s[2];   // per slab buffer, so a flag is never rewritten while still being read
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const int tid = threadIdx.x;
+  const int p = FUSED ? k + 1 : k;
+  if (FUSED && (int)blockIdx.x >= N - p) {
+    // ---- update role: pair (i, j), k + 2 <= i <= j < N -------------------
+    const int l = blockIdx.x - (N - p);
+    int bq = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+    while ((bq + 1) * (bq + 2) / 2 <= l) ++bq;
+    while (bq * (bq + 1) / 2 > l) --bq;
+    const int i = k + 2 + (l - bq * (bq + 1) / 2), j = k + 2 + bq;
+    tile_to_lds(G, Np, k, i, ta);
+    tile_to_lds(G, Np, k, j, tb);
+    __syncthreads();
+    C *Gij = G + (size_t)j * NB * Np + (size_t)i * NB;
+    tile_product_t<C>(ta, tb, [&](int r, int c, C v) {
+      if (i < j || r <= c) Gij[(size_t)c * Np + r] -= v;
+    });
+    return;
+  }
+  // ---- panel role: workgroup jb of block row p ---------------------------
+  const int jb = blockIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
   const int lane = tid & 63;
-  const size_t base = (size_t)k * NB;
-  const bool has_b = blockIdx.x > 0;
-  const size_t cb = (size_t)(k + blockIdx.x) * NB;
+  const size_t base = (size_t)p * NB;
+  const bool has_b = jb > 0;
+  const size_t cb = (size_t)(p + jb) * NB;
   if (tid < 2) bad_s[tid] = 0;
-  C tmp[16];   // all 16 loads of a thread in flight before the first wait
+  if (FUSED) {
+    // step k's update of the two tiles: ta <- R(k,p), tb <- R(k,p+jb)
+    tile_to_lds(G, Np, k, p, ta);
+    if (has_b) tile_to_lds(G, Np, k, p + jb, tb);
+    __syncthreads();
+    // the products in registers, then the updated tiles staged in ta / tb
+    C u1[16], u2[16];
+    int n1 = 0, n2 = 0;
+    tile_product_t<C>(ta, ta, [&](int, int, C v) { u1[n1++] = v; });
+    if (has_b) tile_product_t<C>(ta, tb, [&](int, int, C v) { u2[n2++] = v; });
+    C g1[16], g2[16];
+    n1 = n2 = 0;
+    tile_product_t_index<C>([&](int r, int c) { g1[n1++] = G[(base + c) * Np + base + r]; });
+    if (has_b) tile_product_t_index<C>([&](int r, int c) { g2[n2++] = G[(cb + c) * Np + base + r]; });
+    __syncthreads();   // every wave is done reading the R tiles
+    n1 = n2 = 0;
+    tile_product_t_index<C>([&](int r, int c) {
+      ta[r][c] = (r <= c) ? g1[n1] - u1[n1] : (C)0;
+      ++n1;
+    });
+    if (has_b) tile_product_t_index<C>([&](int r, int c) {
+      tb[r][c] = g2[n2] - u2[n2];
+      ++n2;
+    });
+  } else {
+    C tmp[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int t = tid + 256 * i;
-    tmp[i] = G[(base + t / NB) * Np + base + t % NB];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int t = tid + 256 * i, r = t % NB, c = t / NB;
-    stage[r][c] = (r <= c) ? tmp[i] : (C)0;
-  }
-  if (has_b) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int t = tid + 256 * i;
-      tmp[i] = G[(cb + t / NB) * Np + base + t % NB];
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q;
+      tmp[q] = G[(base + t / NB) * Np + base + t % NB];
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, r = t % NB, c = t / NB;
+      ta[r][c] = (r <= c) ? tmp[q] : (C)0;
+    }
+    if (has_b) tile_to_lds(G, Np, p, p + jb, tb);
   }
   __syncthreads();
   C v[4][4], w[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) { v[x][y] = stage[4 * tr + x][4 * tc + y]; w[x][y] = (C)0; }
-  if (has_b) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int t = tid + 256 * i;
-      stage[t % NB][t / NB] = tmp[i];
+    for (int y = 0; y < 4; ++y) {
+      v[x][y] = ta[4 * tr + x][4 * tc + y];
+      w[x][y] = has_b ? tb[4 * tr + x][4 * tc + y] : (C)0;
     }
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) w[x][y] = stage[4 * tr + x][4 * tc + y];
-  }
-  __syncthreads();   // from here on `stage` collects the output tile
+  __syncthreads();   // from here on `ta` collects the output tile
+  C (*stage)[NB + 1] = ta;
   int bad = 0;
   for (int g = 0; g < NB / 4; ++g) {
     const int buf = g & 1;
@@ -874,111 +1009,43 @@ __global__ __launch_bounds__(256) void k_chol_panel(int k, int Np, C *G, int *in
     }
   }
   if (bad) {
-    if (tid == 0 && blockIdx.x == 0) atomicMin(info, k * NB + bad);
+    if (tid == 0 && blockIdx.x == 0) atomicMin(info, p * NB + bad);
     return;
   }
   __syncthreads();
   for (int t = tid; t < NB * NB; t += 256) {
     const int r = t % NB, c = t / NB;
     if (has_b) G[(cb + c) * Np + base + r] = stage[r][c];
-    else if (r <= c) G[(base + c) * Np + base + r] = stage[r][c];
+    else if (r <= c) rdiag[(size_t)p * NB * NB + (size_t)c * NB + r] = stage[r][c];
   }
 }
 
-// trailing update G(i, j) -= R(k, i)^T R(k, j) for k < i <= j
+// the diagonal tiles R(p,p) back into G (upper parts), one workgroup per tile
 template <typename C>
-__global__ __launch_bounds__(256) void k_chol_update(int k, int N, int Np, C *G) {
-  __shared__ C Ri[NB][NB + 1];
-  __shared__ C Rj[NB][NB + 1];
-  const int l = blockIdx.x;
-  int b = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
-  while ((b + 1) * (b + 2) / 2 <= l) ++b;
-  while (b * (b + 1) / 2 > l) --b;
-  const int a = l - b * (b + 1) / 2;
-  const int i = k + 1 + a, j = k + 1 + b;
-  const int tid = threadIdx.x;
-  const size_t base = (size_t)k * NB;
-  {
-    C ti[16], tj[16];   // all 32 loads in flight before the first wait
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, r = t % NB, c = t / NB;
-      ti[q] = G[((size_t)i * NB + c) * Np + base + r];
-      tj[q] = G[((size_t)j * NB + c) * Np + base + r];
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, r = t % NB, c = t / NB;
-      Ri[r][c] = ti[q];
-      Rj[r][c] = tj[q];
-    }
-  }
-  __syncthreads();
-  // R(k,i)^T R(k,j) on the matrix cores: wave w takes the 32x32 quadrant
-  // (w / 2, w % 2); A operand = columns of Ri, B operand = columns of Rj
-  const int lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-  if constexpr (std::is_same<C, double>::value) {
-    g_f64x4 acc[2][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) acc[t][u] = g_f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < NB; k0 += 4) {
-      double a[2], bb[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = Ri[k0 + (lane >> 4)][wr * 32 + t * 16 + (lane & 15)];
-        bb[t] = Rj[k0 + (lane >> 4)][wc * 32 + t * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bb[u], acc[t][u], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = i * NB + wr * 32 + t * 16 + 4 * q + (lane >> 4);
-          const int c = j * NB + wc * 32 + u * 16 + (lane & 15);
-          if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[t][u][q];
-        }
-  } else {
-    g_f32x16 acc;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-#pragma unroll 8
-    for (int k0 = 0; k0 < NB; k0 += 2) {
-      const float a = Ri[k0 + (lane >> 5)][wr * 32 + (lane & 31)];
-      const float bb = Rj[k0 + (lane >> 5)][wc * 32 + (lane & 31)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = i * NB + wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-      const int c = j * NB + wc * 32 + (lane & 31);
-      if (i < j || r <= c) G[(size_t)c * Np + r] -= acc[q];
-    }
+__global__ __launch_bounds__(256) void k_chol_restore(int Np, C *G, const C *rdiag) {
+  const int p = blockIdx.x;
+  const size_t base = (size_t)p * NB;
+  for (int t = threadIdx.x; t < NB * NB; t += 256) {
+    const int r = t % NB, c = t / NB;
+    if (r <= c) G[(base + c) * Np + base + r] = rdiag[(size_t)p * NB * NB + t];
   }
 }
 
 template <typename C>
-static hipError_t cholesky_t(int N, int Np, C *G, int *info, hipStream_t st) {
-  for (int k = 0; k < N; ++k) {
-    TLS_LAUNCH(PC_CHOL_PANEL, k_chol_panel<C>, dim3(N - k), dim3(256), 0, st, k, Np, G, info);
-    const int M = N - k - 1;
-    if (M > 0)
-      TLS_LAUNCH(PC_CHOL_UPDATE, k_chol_update<C>, dim3(M * (M + 1) / 2), dim3(256), 0, st, k, N, Np, G);
+static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream_t st) {
+  TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, false>), dim3(N), dim3(256), 0, st, 0, N, Np, G, rdiag, info);
+  for (int k = 0; k + 1 < N; ++k) {
+    const int M = N - k - 2;   // trailing block rows of the update role
+    const int grid = (N - k - 1) + M * (M + 1) / 2;
+    TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, true>), dim3(grid), dim3(256), 0, st, k, N, Np, G, rdiag,
+               info);
   }
+  TLS_LAUNCH(PC_PACK, k_chol_restore<C>, dim3(N), dim3(256), 0, st, Np, G, rdiag);
   return hipGetLastError();
 }
-hipError_t launch_cholesky(int N, int Np, int compute, void *G, int *info, hipStream_t st) {
-  if (compute == TLS_FP64) return cholesky_t<double>(N, Np, (double *)G, info, st);
-  return cholesky_t<float>(N, Np, (float *)G, info, st);
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st) {
+  if (compute == TLS_FP64) return cholesky_t<double>(N, Np, (double *)G, (double *)rdiag, info, st);
+  return cholesky_t<float>(N, Np, (float *)G, (float *)rdiag, info, st);
 }
 
 // --------------------------------------------------------------------------

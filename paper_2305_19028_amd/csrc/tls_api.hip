@@ -200,6 +200,7 @@ struct FactorWs {
   void *valq, *cvalq;
   int *info;
   int *sync;
+  void *rdiag;     // diagonal tiles of R during the Cholesky steps
   double *lz;      // Lanczos vectors
   double *lzs;     // Lanczos scalars
   int *flag;
@@ -237,6 +238,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   }
   W.info = c.take<int>(4);
   W.sync = c.take<int>(N + 8);
+  W.rdiag = c.take<double>((size_t)N * NB * NB);
   W.lz = c.take<double>((size_t)(2 * (LANCZOS_STEPS + 1) + 9) * Np);
   W.lzs = c.take<double>(4 * LANCZOS_STEPS + 8);
   W.flag = c.take<int>(4);
@@ -566,6 +568,18 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
   return TLS_OK;
 }
 
+// the factor as the gate's runs apply it: a view that owns no events, with
+// the row GEMV of the explicit inverse (one workgroup per 64-row block) so
+// that the runs, when they overlap a solve, hold about N CUs instead of the
+// whole chip
+tls_precond_s gate_view(const tls_precond_s *P) {
+  tls_precond_s Q = *P;
+  Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;
+  Q.gate_pending = 0;
+  if (Q.xr && Q.xc) Q.apply_mode = 2;
+  return Q;
+}
+
 // Lanczos for the gate estimates (eigenvalues 1/sigma_i^2): run 0 on
 // R_hat^{-1} R_hat^{-T} (the scaled A D^{-1}), run 1 on R^{-1} R^{-T} with
 // R = R_hat D (A itself). Both recurrences share each 2-RHS application of
@@ -587,9 +601,7 @@ tls_status enqueue_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   S.cpart = W.yinv;     // free after the inversion
   S.cnt = W.cnt;
   double *ab = W.lzs;                                 // [2][2K+2]
-  tls_precond_s Q = *P;
-  Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;        // a view: owns no events
-  Q.gate_pending = 0;
+  tls_precond_s Q = gate_view(P);
   Q.dsc64 = ones;                                     // apply R_hat alone
   // v_0 = ones/sqrt(n) for both runs; operator input [v0, D^{-1} v0]
   const double v0 = 1.0 / std::sqrt((double)n);
@@ -690,6 +702,7 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
   S.cpart = W.qpart;
   S.cnt = W.qcnt;
   double *ab = W.qlzs;
+  const tls_precond_s Q = gate_view(P);
   const double v0 = 1.0 / std::sqrt((double)n);
   {
     FillSet F;
@@ -703,10 +716,10 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
     HIPCHK(launch_fill_multi(F, st));
   }
   for (int k = 0; k < K; ++k) {
-    TRY(apply_R(P, 0, 1, inb, tmp, TLS_FP64, S, st));      // R^{-1} v
+    TRY(apply_R(&Q, 0, 1, inb, tmp, TLS_FP64, S, st));     // R^{-1} v
     HIPCHK(launch_matvec(V, tmp, W.tm, st));                 // A R^{-1} v
     HIPCHK(launch_rmatvec(V, W.tm, tn, st));                 // A^T A R^{-1} v
-    TRY(apply_R(P, 1, 1, tn, outb, TLS_FP64, S, st));      // R^{-T} A^T A R^{-1} v
+    TRY(apply_R(&Q, 1, 1, tn, outb, TLS_FP64, S, st));     // R^{-T} A^T A R^{-1} v
     HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
   }
   return TLS_OK;
@@ -845,7 +858,7 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
       P->rep.chol_retries = attempt;
     }
     HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
-    HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.info, st));
+    HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.rdiag, W.info, st));
     int info = 0;
     HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
