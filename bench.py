@@ -50,6 +50,9 @@ WORKLOADS = {
                   # instance before the FP16 factor is used; FP64 refinement on
                   "mixed": dict(u_q="fp16", u_p="fp32", opts=GATED)},
         "dtype": "f16 factor / f32 PCG / f64 outer",
+        # reported beside the line, not the headline: the FP32 factor (same
+        # FP32 Cholesky arithmetic, FP32 storage) needs fewer RQI iterations
+        "variants": {"fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED)},
     },
     "dense_planted_65536x4096": {
         "describe": "dense 65536x4096 planted SVD, sigma' geometric 1..1e-3, sigma_{n+1} 3.9e-5, seed 3100",
@@ -194,8 +197,10 @@ def class_work(cls, path, m, n, nnz, launches):
         per = tri * bx + 2 * n * 8
         return "hbm", per * launches, f"X triangle {tri}x{bx} B + FP64 vector in/out per launch"
     if cls == "chol_panel":
-        fl = sum(NB ** 3 / 3 + (N - k - 1) * NB ** 3 for k in range(N))
-        return alu, fl * launches / N, "diagonal tile n_b^3/3 + (N-k-1) n_b^3 per panel"
+        # the fused step launches (panel of block row k+1 beside the trailing
+        # update of step k): the factorization's n_p^3/3 flops over its N launches
+        Npad = N * NB
+        return alu, Npad ** 3 / 3 * launches / N, "Cholesky n_p^3/3 flops over its N step launches"
     if cls == "chol_update":
         fl = sum((N - k - 1) * (N - k) / 2 * 2 * NB ** 3 for k in range(N))
         return alu, fl * launches / max(N - 1, 1), "2 n_b^3 per trailing tile pair"
@@ -218,13 +223,11 @@ def class_work(cls, path, m, n, nnz, launches):
 
 # kernels (name in the profiler's records, source file) behind each class
 CLASS_KERNELS = {
-    "mixed": {"chol_panel": ("void tls::k_chol_panel<float>", "kernels_factor"),
-              "chol_update": ("void tls::k_chol_update<float>", "kernels_factor"),
-              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0>", "kernels_inv"),
+    "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
+              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
               "invert": ("tls::k_inv_phase2", "kernels_inv")},
-    "fp64": {"chol_panel": ("void tls::k_chol_panel<double>", "kernels_factor"),
-             "chol_update": ("void tls::k_chol_update<double>", "kernels_factor"),
-             "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0>", "kernels_inv"),
+    "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
+             "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
              "invert": ("tls::k_inv_phase2", "kernels_inv")},
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_20000x2000_hbm_traffic.md")
@@ -322,6 +325,18 @@ def main():
     for path in ("fp64", "mixed"):
         res[path] = run_path(tls, torch, Ad, bd, path, args.steps, args.warmup, xref, sref)
         print(f"# {path}: {res[path]}", file=sys.stderr, flush=True)
+    variants = {}
+    for vname, vcfg in WORKLOADS[WORKLOAD].get("variants", {}).items():
+        PATHS[vname] = vcfg
+        r = run_path(tls, torch, Ad, bd, vname, args.steps, args.warmup, xref, sref)
+        variants[vname] = {"config": vcfg, "time_to_tol_ms": r["time_to_tol_ms"],
+                           "factor_ms": r["factor_ms"], "ms_median": r["ms_median"],
+                           "rqi_iters": r["rqi_iters"], "gate_verdict": r["gate_verdict"],
+                           "errors": {"sigma": r["err_sigma"], "x": r["err_x"]},
+                           "speedup_vs_fp64_time_to_tol":
+                               (res["fp64"]["time_to_tol_ms"] / r["time_to_tol_ms"])
+                               if r["time_to_tol_ms"] and res["fp64"]["time_to_tol_ms"] else None}
+        print(f"# variant {vname}: {variants[vname]}", file=sys.stderr, flush=True)
     prof = {p: kernel_profile(tls, torch, Ad, bd, p) for p in ("fp64", "mixed")}
     print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)
 
@@ -369,6 +384,7 @@ def main():
         "rqi_iters": {p: res[p]["rqi_iters"] for p in res},
         "factor_ms": {p: res[p]["factor_ms"] for p in res},
         "gate_async": {p: res[p]["gate_async"] for p in res},
+        "variants": variants,
         "roofline": roof,
         "kernel_classes": prof,
         "cpu_baseline": cpu,

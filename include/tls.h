@@ -247,9 +247,10 @@ TLS_API tls_status tls_precond_info(const tls_precond P, int64_t *n, int32_t *st
  *     (Table 1), one workgroup per 64-row block, inter-workgroup flags;
  *   2 the GEMV of mode 0 with one workgroup per 64-row block of the result
  *     (four waves stream the block row's tiles; no reduction across
- *     workgroups) instead of mode 0's split over about N^2/4 workgroups
- *     (one 64x64 tile per wave, fixed-order reduction by the last
- *     workgroup of each block). Faster from n of about 4096 up. */
+ *     workgroups) instead of mode 0's split over N x ceil(N / c) workgroups
+ *     (c = 4 tiles per workgroup up to N = 40, growing to 32 for large N;
+ *     fixed-order reduction by the last workgroup of each block). It holds
+ *     only N CUs, which suits work that runs beside a solve. */
 TLS_API tls_status tls_precond_set_apply(tls_precond P, int32_t mode);
 
 /* Copy R_hat (upper, column-major n x n, FP64) and d to host buffers. */

@@ -16,10 +16,11 @@
 // phases (Y = B inv(C), then X12 = -inv(A) Y), all pairs and output tiles
 // of a level in one launch. Arithmetic in FP64 on the stored R_hat values.
 //
-// Storage of X (precision SX): two packed copies of 64x64 row-major tiles,
+// Storage of X (precision SX): two packed copies of 64x64 column-major tiles,
 //   XR: tiles (I, K), K >= I, packed by block row   (for X v)
 //   XC: tiles (J, I) of X^T, I <= J, packed by block row of X^T (for X^T v)
-// so that in both products a lane reads one contiguous 64-element row.
+// In both products lane l owns row l of a tile and the wave reads the tile
+// column by column, each load 64 consecutive elements.
 #include <algorithm>
 
 #include "common.h"
@@ -31,10 +32,10 @@ namespace tls {
 __host__ __device__ inline size_t up_tile(int I, int J) {   // R tiles: column-packed upper
   return (size_t)J * (J + 1) / 2 + I;
 }
-__host__ __device__ inline size_t xr_tile(int I, int K, int N) {   // X row-packed upper
+__host__ __device__ inline size_t xr_tile(int I, int K, int N) {   // X tiles, packed by block row (upper)
   return (size_t)I * N - (size_t)I * (I - 1) / 2 + (K - I);
 }
-__host__ __device__ inline size_t xc_tile(int J, int I) {    // X^T row-packed lower
+__host__ __device__ inline size_t xc_tile(int J, int I) {    // X^T tiles, packed by block row (lower)
   return (size_t)J * (J + 1) / 2 + I;
 }
 
@@ -189,13 +190,16 @@ __global__ __launch_bounds__(256) void k_inv_pack(int N, const double *W, SX *XR
   const double *src = W + (size_t)l * NB * NB;
   SX *xr = XR + xr_tile(I, J, N) * NB * NB;
   SX *xc = XC + xc_tile(J, I) * NB * NB;
+  // both targets column-major within the tile (element (row, col) at
+  // col * 64 + row), so that the apply kernels load one column of a tile,
+  // one row per lane, as 64 consecutive elements
   for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
-    const int r = t / NB, c = t % NB;     // row-major target index t = r*64 + c
+    const int r = t % NB, c = t / NB;
     double v = src[c * NB + r];           // X(I*64 + r, J*64 + c)
     if (I == J && r > c) v = 0.0;
-    xr[t] = st_from<SX>(v);
-    // X^T tile (J, I): element (c', r') = X(r', c'); row-major index c*64 + r below
-    xc[c * NB + r] = st_from<SX>(v);
+    xr[c * NB + r] = st_from<SX>(v);
+    // X^T tile (J, I): element (row c, column r) = X(r, c)
+    xc[r * NB + c] = st_from<SX>(v);
   }
 }
 
@@ -276,12 +280,13 @@ __device__ inline C xsum_parts(const C *p, int N) {
 
 enum XMode { XA = 0, XF0 = 2, XB = 3, XF = 4 };   // XA: plain apply
 
-// ROW = 0: grid (N, CH), four waves, one tile per wave, chunk partials
-//          reduced by the last workgroup of each block (split over the chip;
-//          measured faster for n up to about 2000);
+// ROW = 0: grid (N, CH), four waves; workgroup (I, s) takes chunk s of the
+//          tiles of block row I (chunk_of tiles, every fourth one per wave);
+//          the chunk partials are reduced by the last workgroup of each block
+//          (split over the chip; the default);
 // ROW = 1: grid (N), XW waves per workgroup, each wave streams every XW-th
-//          tile of the block row; no cross-workgroup reduction (measured
-//          faster in the PCG modes at n = 4096).
+//          tile of the block row; no cross-workgroup reduction (holds about
+//          N CUs: the gate's runs use it beside a solve).
 constexpr int XW = 4;
 template <typename SX, typename C, int NR, int MODE, int TRANS, int ROW>
 __global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P) {
@@ -310,9 +315,10 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P
   // tile K's row for this lane and the inputs of block K (combined with the
   // step scalars later)
   auto load_tile = [&](int Kt) {
-    const SX *T = P.X + (TRANS ? xc_tile(I, Kt) : xr_tile(I, Kt, N)) * NB * NB + (size_t)lane * NB;
+    // column c of the tile is 64 consecutive elements: lane = row
+    const SX *T = P.X + (TRANS ? xc_tile(I, Kt) : xr_tile(I, Kt, N)) * NB * NB + lane;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) t[c] = T[c];
+    for (int c = 0; c < NB; ++c) t[c] = T[(size_t)c * NB];
     const int row = Kt * NB + lane;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -409,17 +415,24 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // a fresh accumulator per tile: the FP32 chains stay 64 terms long
+    // however many tiles a wave streams
+    C tacc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tacc[r] = 0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       const C tc = cvt<C>(t[c]);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] += tc * s_v[w][r][c];
+      for (int r = 0; r < NR; ++r) tacc[r] += tc * s_v[w][r][c];
     }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] += tacc[r];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     K += NW;
-    has_tile = ROW && K < k_end;
+    has_tile = K < k_end;
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) s_acc[w][r][lane] = acc[r];
@@ -563,7 +576,17 @@ static hipError_t x_mode(int mode, int trans, int nrhs, const XParams<SX, C> &P,
 // tiles per workgroup: one tile per wave, so that a block row of N tiles is
 // spread over N/4 workgroups (the chip has 256 CUs; a single CU streams far
 // below its share of the memory bandwidth)
-static int chunk_of(int N) { return N <= 4 ? N : 4; }
+// tiles per workgroup of the split apply (one wave takes every fourth tile
+// of the chunk): the grid stays near 256 workgroups, so that the fixed cost
+// of a workgroup (scalars, chunk partial, arrival count) is spread over more
+// tiles as N grows (measured: N = 32 best at 4, N = 64 at 16)
+static int chunk_of(int N) {
+  if (N <= 4) return N;
+  if (N <= 40) return 4;
+  if (N <= 56) return 8;
+  if (N <= 96) return 16;
+  return 32;
+}
 
 template <typename C>
 static hipError_t x_dispatch(const FactorView &F, int mode, int trans, int nrhs, const SolveBufs &B,
