@@ -392,8 +392,12 @@ TLS_API tls_status tls_mlp_adam(float *theta, float *m, float *v, const float *g
  * thread-safe; meant for benchmarks. Classes (index: name):
  *   0 precond_apply  1 pcg_step  2 gram  3 chol_panel  4 chol_update
  *   5 residual  6 gradient  7 outer_scalars  8 setup  9 lanczos
- *   10 pack  11 residual_dd  12 invert  13 mlp */
-#define TLS_PROF_CLASSES 14
+ *   10 pack  11 residual_dd  12 invert  13 mlp
+ *   14 gate: every launch on the library's side streams (the gate's Lanczos
+ *      runs, which overlap the caller's stream), whatever its kernel.
+ * chol_panel counts the Cholesky step launches (each also carries the
+ * previous step's trailing update); chol_update is no longer used. */
+#define TLS_PROF_CLASSES 15
 typedef struct {
   int32_t launches[TLS_PROF_CLASSES];
   double total_ms[TLS_PROF_CLASSES];

@@ -13,9 +13,11 @@ namespace tls {
 // kernel classes of the profiling hooks (order as in tls.h)
 enum ProfClass { PC_TRSV_APPLY = 0, PC_PCG, PC_GRAM, PC_CHOL_PANEL, PC_CHOL_UPDATE, PC_RESIDUAL,
                  PC_GRADIENT, PC_SCALARS, PC_SETUP, PC_LANCZOS, PC_PACK, PC_RESID_DD, PC_INVERT,
-                 PC_MLP };
+                 PC_MLP, PC_GATE };
 // no-ops unless profiling is on (see tls_profile_start)
 void prof_begin(int cls, hipStream_t st);
+// launches on a stream noted here are counted as PC_GATE whatever their kernel
+void prof_note_side_stream(hipStream_t st);
 void prof_end(hipStream_t st);
 
 // a kernel launch on stream `st`, bracketed by the profiling hooks; one statement

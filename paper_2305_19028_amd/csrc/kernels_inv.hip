@@ -280,17 +280,18 @@ __device__ inline C xsum_parts(const C *p, int N) {
 
 enum XMode { XA = 0, XF0 = 2, XB = 3, XF = 4 };   // XA: plain apply
 
-// ROW = 0: grid (N, CH), four waves; workgroup (I, s) takes chunk s of the
-//          tiles of block row I (chunk_of tiles, every fourth one per wave);
+// ROW = 0: grid (N, CH), XS waves; workgroup (I, s) takes chunk s of the
+//          tiles of block row I (chunk_of tiles, every XS-th one per wave);
 //          the chunk partials are reduced by the last workgroup of each block
 //          (split over the chip; the default);
 // ROW = 1: grid (N), XW waves per workgroup, each wave streams every XW-th
 //          tile of the block row; no cross-workgroup reduction (holds about
 //          N CUs: the gate's runs use it beside a solve).
 constexpr int XW = 4;
+constexpr int XS = 8;   // waves per workgroup of the split variant
 template <typename SX, typename C, int NR, int MODE, int TRANS, int ROW>
-__global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P) {
-  constexpr int NW = ROW ? XW : 4;
+__global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, C> P) {
+  constexpr int NW = ROW ? XW : XS;
   __shared__ C s_v[NW][NR][NB];      // per-wave input block
   __shared__ C s_acc[NW][NR][NB];
   __shared__ C s_scal[NR][4];
@@ -454,9 +455,12 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 256) void k_xapply(XParams<SX, C> P
     C *mine = P.cpart + (((size_t)I * CH + sidx) * NR) * NB;
     if (w == 0) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        mine[r * NB + lane] =
-            (s_acc[0][r][lane] + s_acc[1][r][lane]) + (s_acc[2][r][lane] + s_acc[3][r][lane]);
+      for (int r = 0; r < NR; ++r) {
+        C v = s_acc[0][r][lane];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) v += s_acc[q][r][lane];
+        mine[r * NB + lane] = v;
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();
@@ -554,7 +558,7 @@ static hipError_t xlaunch(const XParams<SX, C> &P, int CH, hipStream_t st) {
                dim3(P.N), dim3(64 * XW), 0, st, P);
   else
     TLS_LAUNCH(MODE == XA ? PC_TRSV_APPLY : PC_PCG, (k_xapply<SX, C, NR, MODE, TRANS, 0>),
-               dim3(P.N, CH), dim3(256), 0, st, P);
+               dim3(P.N, CH), dim3(64 * XS), 0, st, P);
   return hipGetLastError();
 }
 
@@ -576,16 +580,15 @@ static hipError_t x_mode(int mode, int trans, int nrhs, const XParams<SX, C> &P,
 // tiles per workgroup: one tile per wave, so that a block row of N tiles is
 // spread over N/4 workgroups (the chip has 256 CUs; a single CU streams far
 // below its share of the memory bandwidth)
-// tiles per workgroup of the split apply (one wave takes every fourth tile
-// of the chunk): the grid stays near 256 workgroups, so that the fixed cost
-// of a workgroup (scalars, chunk partial, arrival count) is spread over more
-// tiles as N grows (measured: N = 32 best at 4, N = 64 at 16)
+// tiles per workgroup of the split apply (one wave takes every XS-th tile of
+// the chunk): the fixed cost of a workgroup (scalars, chunk partial,
+// arrival count) is spread over more tiles as N grows, while each SIMD
+// keeps two waves to overlap one tile's loads with another's products
 static int chunk_of(int N) {
-  if (N <= 4) return N;
-  if (N <= 40) return 4;
-  if (N <= 56) return 8;
-  if (N <= 96) return 16;
-  return 32;
+  if (N <= XS) return N;
+  if (N <= 40) return XS;
+  if (N <= 96) return 2 * XS;
+  return 4 * XS;
 }
 
 template <typename C>

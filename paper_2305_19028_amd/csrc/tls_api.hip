@@ -426,6 +426,7 @@ struct ProfState {
   std::vector<ProfRec> recs;
   int open_cls = -1;
   hipEvent_t open_ev = nullptr;
+  std::vector<hipStream_t> side;   // launches on these count as PC_GATE
 };
 ProfState g_prof;
 hipEvent_t prof_event() {
@@ -437,8 +438,10 @@ hipEvent_t prof_event() {
   return g_prof.pool[g_prof.next++];
 }
 }  // namespace
+void prof_note_side_stream(hipStream_t st) { g_prof.side.push_back(st); }
 void prof_begin(int cls, hipStream_t st) {
   if (!g_prof.on) return;
+  if (std::find(g_prof.side.begin(), g_prof.side.end(), st) != g_prof.side.end()) cls = PC_GATE;
   hipEvent_t e = prof_event();
   if (!e) return;
   hipEventRecord(e, st);
@@ -761,6 +764,8 @@ hipError_t side_streams(hipStream_t out[2]) {
       return e;
     }
     it = pool.emplace(dev, std::make_pair(a, b)).first;
+    prof_note_side_stream(a);
+    prof_note_side_stream(b);
   }
   out[0] = it->second.first;
   out[1] = it->second.second;

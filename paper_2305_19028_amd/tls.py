@@ -109,7 +109,7 @@ class c_rqi_stats(C.Structure):
 
 PROF_CLASSES = ["precond_apply", "pcg_step", "gram", "chol_panel", "chol_update", "residual",
                 "gradient", "outer_scalars", "setup", "lanczos", "pack", "residual_dd", "invert",
-                "mlp"]
+                "mlp", "gate"]
 
 
 class c_kernel_times(C.Structure):
