@@ -26,11 +26,13 @@
  *    calls on the same inputs give bitwise identical outputs.
  *  - Calls that share a workspace or a preconditioner must not overlap in
  *    time (they use synchronisation counters inside the workspace).
- *  - The gate of a low-precision factor (two Lanczos runs) executes on two
- *    library-owned streams per device (default priority, non-blocking,
+ *  - The gate of a low-precision factor (two Lanczos runs) executes on one
+ *    library-owned stream per device (default priority, non-blocking,
  *    created on first use, kept until the process ends), forked from the
- *    caller's stream after the factorization. See tls_factor_precond for
- *    when the caller may see them still running.
+ *    caller's stream after the factorization. Its scalars come back through
+ *    a small pinned host block per preconditioner (pooled per device, kept
+ *    for reuse). See tls_factor_precond for when the caller may see the runs
+ *    still going.
  */
 #ifndef TLS_H
 #define TLS_H
@@ -206,7 +208,7 @@ TLS_API size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q);
  * the A-only constraints of Section 3.1 (verdict bits 1, 2, 4), and 6 steps
  * on R^{-T} A^T A R^{-1}, whose extreme Ritz values (quality_lo, quality_hi)
  * are the a-posteriori certificate of the factor read by tls_rqi_solve.
- * The two run concurrently. With rep != NULL (host) the call waits for both
+ * They run one after the other. With rep != NULL (host) the call waits for both
  * and fills *rep. With rep == NULL it returns while they may still run:
  * tls_rqi_solve then overlaps them with its iterations, and
  * tls_precond_info (with a report requested), tls_rqi_solve and

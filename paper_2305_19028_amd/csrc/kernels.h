@@ -62,8 +62,8 @@ struct SolveBufs {
 hipError_t launch_trsv(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
                        hipStream_t st);
 // ---- kernels_inv.hip --------------------------------------------------------
-hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, double *W,
-                         double *Y, int xstorage, void *XR, void *XC, hipStream_t st);
+hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, void *W, void *Y,
+                         int xstorage, void *XR, void *XC, hipStream_t st);
 size_t invert_scratch_doubles(int N);
 hipError_t launch_xapply(const FactorView &F, int compute, int mode, int nrhs, const SolveBufs &B,
                          hipStream_t st);

@@ -305,17 +305,40 @@ __global__ __launch_bounds__(256) void k_gram_sparse(int n, int Np, const int32_
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int t = ca; t < cb; ++t) {
-      const int i = row_idx[t];
-      const C aij = cvalq[t];
-      const int ra = row_ptr[i], rb = row_ptr[i + 1];
-      for (int e = ra + lane; e < rb; e += 64) {
-        const int k = col_idx[e];
-        if (k >= k0 && k < k1) a[k - k0] += aij * valq[e];
+    // the nonzeros of column j four at a time, one 16-lane group per row:
+    // the four rows' loads are in flight together, and the groups add into
+    // the accumulator in row order (entries of one row have distinct
+    // columns, so the lanes of a group never collide)
+    const int grp = lane >> 4, gl = lane & 15;
+    for (int t0 = ca; t0 < cb; t0 += 4) {
+      const int t = t0 + grp;
+      const bool live = t < cb;
+      int ra = 0, rb = 0;
+      C aij = 0;
+      if (live) {
+        const int i = row_idx[t];
+        aij = cvalq[t];
+        ra = row_ptr[i];
+        rb = row_ptr[i + 1];
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int eb = 0;; eb += 16) {   // 16 entries of each group's row per pass
+        const int e = ra + eb + gl;
+        const bool have = live && e < rb;
+        int k = -1;
+        C v = 0;
+        if (have) {
+          k = col_idx[e];
+          v = aij * valq[e];
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          if (grp == g && have && k >= k0 && k < k1) a[k - k0] += v;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (__ballot(live && ra + eb + 16 < rb) == 0) break;   // uniform over the wave
+      }
     }
     C *colj = G + (size_t)j * Np;
     for (int k = k0 + lane; k < k1; k += 64) colj[k] = a[k - k0];

@@ -40,35 +40,40 @@ __host__ __device__ inline size_t xc_tile(int J, int I) {    // X^T tiles, packe
 }
 
 // ---------------------------------------------------------------------------
-// inversion, FP64 working copy W: full upper tiles in column-packed order
-// (tile (I, J) at up_tile(I, J)), column-major inside a tile
+// inversion, working copy W in the compute precision C: FP64 for an FP64
+// factor, FP32 otherwise (X is then stored in FP32, and FP32 arithmetic on
+// the rounded R_hat leaves an error far below the rounding of R_hat itself).
+// Full upper tiles in column-packed order (tile (I, J) at up_tile(I, J)),
+// column-major inside a tile.
 // ---------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(256) void k_inv_init(int N, const S *Rt, const double *dinv64,
-                                                  double *W) {
-  // diagonal tiles of W = stored diagonal inverses; off-diagonal tiles = R_hat (FP64)
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_inv_init(int N, const S *Rt, const double *dinv64, C *W) {
+  // diagonal tiles of W = stored diagonal inverses; off-diagonal tiles = R_hat
   const int l = blockIdx.x;
   int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= l) ++J;
   while (J * (J + 1) / 2 > l) --J;
   const int I = l - J * (J + 1) / 2;
-  double *dst = W + (size_t)l * NB * NB;
+  C *dst = W + (size_t)l * NB * NB;
   if (I == J) {
     const double *src = dinv64 + (size_t)I * NB * NB;
-    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = src[t];
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = (C)src[t];
   } else {
     const S *src = Rt + (size_t)l * NB * NB;
-    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = cvt<double>(src[t]);
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) dst[t] = cvt<C>(src[t]);
   }
 }
 
-// 64x64x64 FP64 tile products accumulated by 256 threads. The operand tiles (column-major in global memory) travel through
-// registers: the loads of product k+1 are in flight while product k runs
-// from LDS, so each product costs one memory latency at most once.
+// 64x64x64 tile products accumulated by 256 threads. The operand tiles
+// (column-major in global memory) travel through registers: the loads of
+// product k+1 are in flight while product k runs from LDS, so each product
+// costs one memory latency at most once.
+template <typename C>
 struct TileRegs {
-  double a[16], b[16];
+  C a[16], b[16];
 };
-__device__ inline void tile_fetch(const double *A, const double *B, TileRegs &R) {
+template <typename C>
+__device__ inline void tile_fetch(const C *A, const C *B, TileRegs<C> &R) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -76,7 +81,8 @@ __device__ inline void tile_fetch(const double *A, const double *B, TileRegs &R)
     R.b[i] = B[tid + 256 * i];
   }
 }
-__device__ inline void tile_stage(const TileRegs &R, double (*As)[NB + 1], double (*Bs)[NB + 1]) {
+template <typename C>
+__device__ inline void tile_stage(const TileRegs<C> &R, C (*As)[NB + 1], C (*Bs)[NB + 1]) {
   const int tid = threadIdx.x;
   __syncthreads();   // the previous product has finished reading LDS
 #pragma unroll
@@ -87,22 +93,34 @@ __device__ inline void tile_stage(const TileRegs &R, double (*As)[NB + 1], doubl
   }
   __syncthreads();
 }
-// C += A B on the FP64 matrix cores: wave w holds the 32x32 quadrant
-// (w / 2, w % 2) of C as 2x2 blocks of v_mfma_f64_16x16x4 results (lane l,
-// register q: row 4q + l/16, column l mod 16 of a block). Reads one double
-// of A and of B per lane and k-step of 4 (the VALU form, 4x4 outputs per
-// thread, was bound by LDS reads).
+// C += A B on the matrix cores: wave w holds the 32x32 quadrant (w / 2,
+// w % 2) of C. FP64: 2x2 blocks of v_mfma_f64_16x16x4 results (lane l,
+// register q: row 4q + l/16, column l mod 16 of a block); FP32: one
+// v_mfma_f32_32x32x2 result (register q: row 8(q/4) + 4(l/32) + q mod 4,
+// column l mod 32). Each lane reads one element of A and of B per k-step.
 typedef double inv_f64x4 __attribute__((ext_vector_type(4)));
-struct TileAcc {
+typedef float inv_f32x16 __attribute__((ext_vector_type(16)));
+template <typename C>
+struct TileAcc;
+template <>
+struct TileAcc<double> {
   inv_f64x4 c[2][2];
 };
-__device__ inline void tile_zero(TileAcc &T) {
+template <>
+struct TileAcc<float> {
+  inv_f32x16 c;
+};
+__device__ inline void tile_zero(TileAcc<double> &T) {
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) T.c[t][u] = inv_f64x4{0.0, 0.0, 0.0, 0.0};
 }
-__device__ inline void tile_mma(const double (*As)[NB + 1], const double (*Bs)[NB + 1], TileAcc &T) {
+__device__ inline void tile_zero(TileAcc<float> &T) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) T.c[q] = 0.0f;
+}
+__device__ inline void tile_mma(const double (*As)[NB + 1], const double (*Bs)[NB + 1], TileAcc<double> &T) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll 4
   for (int k0 = 0; k0 < NB; k0 += 4) {
@@ -119,8 +137,17 @@ __device__ inline void tile_mma(const double (*As)[NB + 1], const double (*Bs)[N
         T.c[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], T.c[t][u], 0, 0, 0);
   }
 }
+__device__ inline void tile_mma(const float (*As)[NB + 1], const float (*Bs)[NB + 1], TileAcc<float> &T) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll 8
+  for (int k0 = 0; k0 < NB; k0 += 2) {
+    const float a = As[wr * 32 + (lane & 31)][k0 + (lane >> 5)];
+    const float b = Bs[k0 + (lane >> 5)][wc * 32 + (lane & 31)];
+    T.c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, T.c, 0, 0, 0);
+  }
+}
 // dst (column-major 64x64 tile) = sign * C
-__device__ inline void tile_store(const TileAcc &T, double *dst, double sign) {
+__device__ inline void tile_store(const TileAcc<double> &T, double *dst, double sign) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -133,20 +160,30 @@ __device__ inline void tile_store(const TileAcc &T, double *dst, double sign) {
         dst[c * NB + r] = sign * T.c[t][u][q];
       }
 }
+__device__ inline void tile_store(const TileAcc<float> &T, float *dst, float sign) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    const int c = wc * 32 + (lane & 31);
+    dst[c * NB + r] = sign * T.c[q];
+  }
+}
 
 // phase 1 of level L: Y = B inv(C) for every pair p; Y tile (a, b), a, b in [0, hb)
 // B tile (a, k) = W(I0 + a, J0 + k) (still R_hat), inv(C) tile (k, b) = W(J0 + k, J0 + b), k <= b
-__global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, double *Y) {
-  __shared__ double As[NB][NB + 1], Bs[NB][NB + 1];
+template <typename C>
+__global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, C *W, C *Y) {
+  __shared__ C As[NB][NB + 1], Bs[NB][NB + 1];
   const int per = hb * hb;
   const int pair = blockIdx.x / per, rem = blockIdx.x % per;
   const int a = rem % hb, b = rem / hb;
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;      // partial pair at the end (uniform)
-  TileAcc acc;
+  TileAcc<C> acc;
   tile_zero(acc);
   const int kend = b;                           // J0 + b < N, so every k <= b is in range
-  TileRegs R;
+  TileRegs<C> R;
   tile_fetch(W + up_tile(I0 + a, J0) * NB * NB, W + up_tile(J0, J0 + b) * NB * NB, R);
   for (int k = 0; k <= kend; ++k) {
     tile_stage(R, As, Bs);
@@ -154,21 +191,22 @@ __global__ __launch_bounds__(256) void k_inv_phase1(int N, int hb, double *W, do
       tile_fetch(W + up_tile(I0 + a, J0 + k + 1) * NB * NB, W + up_tile(J0 + k + 1, J0 + b) * NB * NB, R);
     tile_mma(As, Bs, acc);
   }
-  tile_store(acc, Y + ((size_t)pair * per + rem) * NB * NB, 1.0);
+  tile_store(acc, Y + ((size_t)pair * per + rem) * NB * NB, (C)1);
 }
 
 // phase 2: W(I0 + a, J0 + b) = - sum_{k >= a} inv(A)(a, k) Y(k, b)
-__global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, const double *Y) {
-  __shared__ double As[NB][NB + 1], Bs[NB][NB + 1];
+template <typename C>
+__global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, C *W, const C *Y) {
+  __shared__ C As[NB][NB + 1], Bs[NB][NB + 1];
   const int per = hb * hb;
   const int pair = blockIdx.x / per, rem = blockIdx.x % per;
   const int a = rem % hb, b = rem / hb;
   const int I0 = pair * 2 * hb, J0 = I0 + hb;
   if (J0 + b >= N || I0 + a >= N) return;
-  TileAcc acc;
+  TileAcc<C> acc;
   tile_zero(acc);
   const int kend = hb - 1;                      // I0 + k < J0 < N for every k < hb
-  TileRegs R;
+  TileRegs<C> R;
   auto yt = [&](int k) { return Y + ((size_t)pair * per + b * hb + k) * NB * NB; };
   tile_fetch(W + up_tile(I0 + a, I0 + a) * NB * NB, yt(a), R);
   for (int k = a; k <= kend; ++k) {
@@ -176,18 +214,18 @@ __global__ __launch_bounds__(256) void k_inv_phase2(int N, int hb, double *W, co
     if (k < kend) tile_fetch(W + up_tile(I0 + a, I0 + k + 1) * NB * NB, yt(k + 1), R);
     tile_mma(As, Bs, acc);
   }
-  tile_store(acc, W + up_tile(I0 + a, J0 + b) * NB * NB, -1.0);
+  tile_store(acc, W + up_tile(I0 + a, J0 + b) * NB * NB, (C)-1);
 }
 
-// pack W (FP64, column-packed, column-major tiles) into XR and XC of precision SX
-template <typename SX>
-__global__ __launch_bounds__(256) void k_inv_pack(int N, const double *W, SX *XR, SX *XC) {
+// pack W (column-packed, column-major tiles) into XR and XC of precision SX
+template <typename SX, typename C>
+__global__ __launch_bounds__(256) void k_inv_pack(int N, const C *W, SX *XR, SX *XC) {
   const int l = blockIdx.x;
   int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= l) ++J;
   while (J * (J + 1) / 2 > l) --J;
   const int I = l - J * (J + 1) / 2;
-  const double *src = W + (size_t)l * NB * NB;
+  const C *src = W + (size_t)l * NB * NB;
   SX *xr = XR + xr_tile(I, J, N) * NB * NB;
   SX *xc = XC + xc_tile(J, I) * NB * NB;
   // both targets column-major within the tile (element (row, col) at
@@ -195,7 +233,7 @@ __global__ __launch_bounds__(256) void k_inv_pack(int N, const double *W, SX *XR
   // one row per lane, as 64 consecutive elements
   for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
     const int r = t % NB, c = t / NB;
-    double v = src[c * NB + r];           // X(I*64 + r, J*64 + c)
+    double v = (double)src[c * NB + r];   // X(I*64 + r, J*64 + c)
     if (I == J && r > c) v = 0.0;
     xr[c * NB + r] = st_from<SX>(v);
     // X^T tile (J, I): element (row c, column r) = X(r, c)
@@ -203,28 +241,37 @@ __global__ __launch_bounds__(256) void k_inv_pack(int N, const double *W, SX *XR
   }
 }
 
-hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, double *W,
-                         double *Y, int xstorage, void *XR, void *XC, hipStream_t st) {
+template <typename C>
+static hipError_t invert_t(int N, int storage, const void *Rt, const double *dinv64, C *W, C *Y,
+                           int xstorage, void *XR, void *XC, hipStream_t st) {
   const int T = N * (N + 1) / 2;
   switch (storage) {
-    case TLS_FP64: TLS_LAUNCH(PC_PACK, k_inv_init<double>, dim3(T), dim3(256), 0, st, N, (const double *)Rt, dinv64, W); break;
-    case TLS_FP32: TLS_LAUNCH(PC_PACK, k_inv_init<float>, dim3(T), dim3(256), 0, st, N, (const float *)Rt, dinv64, W); break;
-    case TLS_FP16: TLS_LAUNCH(PC_PACK, k_inv_init<half_t>, dim3(T), dim3(256), 0, st, N, (const half_t *)Rt, dinv64, W); break;
-    default: TLS_LAUNCH(PC_PACK, k_inv_init<bf16_t>, dim3(T), dim3(256), 0, st, N, (const bf16_t *)Rt, dinv64, W); break;
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, (k_inv_init<double, C>), dim3(T), dim3(256), 0, st, N, (const double *)Rt, dinv64, W); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, (k_inv_init<float, C>), dim3(T), dim3(256), 0, st, N, (const float *)Rt, dinv64, W); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, (k_inv_init<half_t, C>), dim3(T), dim3(256), 0, st, N, (const half_t *)Rt, dinv64, W); break;
+    default: TLS_LAUNCH(PC_PACK, (k_inv_init<bf16_t, C>), dim3(T), dim3(256), 0, st, N, (const bf16_t *)Rt, dinv64, W); break;
   }
   for (int hb = 1; hb < N; hb *= 2) {
     const int pairs = (N + 2 * hb - 1) / (2 * hb);
     const dim3 g(pairs * hb * hb);
-    TLS_LAUNCH(PC_INVERT, k_inv_phase1, g, dim3(256), 0, st, N, hb, W, Y);
-    TLS_LAUNCH(PC_INVERT, k_inv_phase2, g, dim3(256), 0, st, N, hb, W, (const double *)Y);
+    TLS_LAUNCH(PC_INVERT, k_inv_phase1<C>, g, dim3(256), 0, st, N, hb, W, Y);
+    TLS_LAUNCH(PC_INVERT, k_inv_phase2<C>, g, dim3(256), 0, st, N, hb, W, (const C *)Y);
   }
   switch (xstorage) {
-    case TLS_FP64: TLS_LAUNCH(PC_PACK, k_inv_pack<double>, dim3(T), dim3(256), 0, st, N, W, (double *)XR, (double *)XC); break;
-    case TLS_FP32: TLS_LAUNCH(PC_PACK, k_inv_pack<float>, dim3(T), dim3(256), 0, st, N, W, (float *)XR, (float *)XC); break;
-    case TLS_FP16: TLS_LAUNCH(PC_PACK, k_inv_pack<half_t>, dim3(T), dim3(256), 0, st, N, W, (half_t *)XR, (half_t *)XC); break;
-    default: TLS_LAUNCH(PC_PACK, k_inv_pack<bf16_t>, dim3(T), dim3(256), 0, st, N, W, (bf16_t *)XR, (bf16_t *)XC); break;
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, (k_inv_pack<double, C>), dim3(T), dim3(256), 0, st, N, W, (double *)XR, (double *)XC); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, (k_inv_pack<float, C>), dim3(T), dim3(256), 0, st, N, W, (float *)XR, (float *)XC); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, (k_inv_pack<half_t, C>), dim3(T), dim3(256), 0, st, N, W, (half_t *)XR, (half_t *)XC); break;
+    default: TLS_LAUNCH(PC_PACK, (k_inv_pack<bf16_t, C>), dim3(T), dim3(256), 0, st, N, W, (bf16_t *)XR, (bf16_t *)XC); break;
   }
   return hipGetLastError();
+}
+
+// W and Y in FP64 when X is stored in FP64, in FP32 otherwise
+hipError_t launch_invert(int N, int storage, const void *Rt, const double *dinv64, void *W, void *Y,
+                         int xstorage, void *XR, void *XC, hipStream_t st) {
+  if (xstorage == TLS_FP64)
+    return invert_t<double>(N, storage, Rt, dinv64, (double *)W, (double *)Y, xstorage, XR, XC, st);
+  return invert_t<float>(N, storage, Rt, dinv64, (float *)W, (float *)Y, xstorage, XR, XC, st);
 }
 
 size_t invert_scratch_doubles(int N) {

@@ -113,16 +113,11 @@ struct tls_precond_s {
   // the gate's two Lanczos runs (estimates, certificate) on the library's
   // side streams: fork point, completion of each run, pending until collected
   hipEvent_t ev_fork = nullptr, ev_pair = nullptr, ev_cert = nullptr;
-  hipStream_t side[2] = {nullptr, nullptr};
+  hipStream_t side = nullptr;
+  double *hgate = nullptr;         // pinned host block: the runs' tridiagonal scalars
+  int hgate_dev = -1;
   int gate_pending = 0, have_quality = 0;
-  ~tls_precond_s() {
-    if (gate_pending) {
-      (void)hipEventSynchronize(ev_pair);
-      (void)hipEventSynchronize(ev_cert);
-    }
-    for (hipEvent_t e : {ev_fork, ev_pair, ev_cert})
-      if (e) (void)hipEventDestroy(e);
-  }
+  ~tls_precond_s();
   FactorView view() const {
     FactorView F;
     F.n = (int)n;
@@ -578,6 +573,7 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
 tls_precond_s gate_view(const tls_precond_s *P) {
   tls_precond_s Q = *P;
   Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;
+  Q.hgate = nullptr;
   Q.gate_pending = 0;
   if (Q.xr && Q.xc) Q.apply_mode = 2;
   return Q;
@@ -638,20 +634,20 @@ tls_status enqueue_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
     if (s == TLS_OK && launch_lanczos_orth(n, Np, k, K, V, outb, inb, P->dsc64, ab, st) != hipSuccess)
       s = fail(TLS_ERR_HIP, "Lanczos orthogonalization launch failed");
   }
+  if (s == TLS_OK)   // the two tridiagonal matrices into the pinned block
+    HIPCHK(hipMemcpyAsync(P->hgate, ab, 2 * (2 * K + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
   return s;
 }
 
-// read back the two tridiagonal matrices (st idle) and set the estimates:
-// kappa(A D^{-1}) and sigma'_n(A), sigma'_1(A)
-tls_status collect_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+// the two tridiagonal matrices (in the pinned block once ev_pair has
+// completed) and the estimates: kappa(A D^{-1}) and sigma'_n(A), sigma'_1(A)
+tls_status collect_pair(tls_precond_s *P) {
   const int K = std::min(LANCZOS_STEPS, (int)P->n);
-  std::vector<double> h(2 * (2 * K + 2));
-  HIPCHK(hipMemcpyAsync(h.data(), W.lzs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  const double *h = P->hgate;
   double lam[2][2];
   int steps[2];
   for (int run = 0; run < 2; ++run) {
-    const double *hr = h.data() + run * (2 * K + 2);
+    const double *hr = h + run * (2 * K + 2);
     const int done = (int)hr[2 * K + 1];
     std::vector<double> a(hr, hr + done), b(hr + K, hr + K + std::max(done - 1, 0));
     tridiag_extremes(a, b, &lam[run][0], &lam[run][1]);
@@ -725,16 +721,17 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
     TRY(apply_R(&Q, 1, 1, tn, outb, TLS_FP64, S, st));     // R^{-T} A^T A R^{-1} v
     HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
   }
+  HIPCHK(hipMemcpyAsync(P->hgate + 2 * (2 * LANCZOS_STEPS + 2), ab, (2 * K + 2) * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
   return TLS_OK;
 }
 
-tls_status collect_cert(tls_precond_s *P, FactorWs &W, hipStream_t st) {
+// the certificate's tridiagonal matrix (pinned block, after ev_cert)
+tls_status collect_cert(tls_precond_s *P) {
   const int K = std::min(QUALITY_STEPS, (int)P->n);
-  std::vector<double> h(2 * K + 2);
-  HIPCHK(hipMemcpyAsync(h.data(), W.qlzs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  const double *h = P->hgate + 2 * (2 * LANCZOS_STEPS + 2);
   const int done = std::max(1, (int)h[2 * K + 1]);
-  std::vector<double> a(h.begin(), h.begin() + done), b(h.begin() + K, h.begin() + K + done - 1);
+  std::vector<double> a(h, h + done), b(h + K, h + K + done - 1);
   double lo = 0, hi = 0;
   tridiag_extremes(a, b, &lo, &hi);
   P->rep.quality_lo = lo;
@@ -743,62 +740,86 @@ tls_status collect_cert(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   return TLS_OK;
 }
 
-// two side streams per device, created once (default priority, non-blocking
-// so that work on the legacy default stream does not serialize with them);
-// they live until the process ends
-hipError_t side_streams(hipStream_t out[2]) {
-  static std::mutex mu;
-  static std::map<int, std::pair<hipStream_t, hipStream_t>> pool;
+// one side stream per device, created once (default priority, non-blocking
+// so that work on the legacy default stream does not serialize with it);
+// it lives until the process ends. Pinned host blocks for the gate's
+// read-back come from a per-device free list (allocated once, reused).
+constexpr size_t GATE_HOST_DOUBLES = 2 * (2 * LANCZOS_STEPS + 2) + (2 * QUALITY_STEPS + 2);
+std::mutex g_side_mu;
+std::map<int, hipStream_t> g_side_pool;
+std::map<int, std::vector<double *>> g_pinned_free;
+
+hipError_t side_stream(hipStream_t *out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = pool.find(dev);
-  if (it == pool.end()) {
-    hipStream_t a = nullptr, b = nullptr;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto it = g_side_pool.find(dev);
+  if (it == g_side_pool.end()) {
+    hipStream_t a = nullptr;
     e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
-    e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      (void)hipStreamDestroy(a);
-      return e;
-    }
-    it = pool.emplace(dev, std::make_pair(a, b)).first;
+    it = g_side_pool.emplace(dev, a).first;
     prof_note_side_stream(a);
-    prof_note_side_stream(b);
   }
-  out[0] = it->second.first;
-  out[1] = it->second.second;
+  *out = it->second;
   return hipSuccess;
 }
+hipError_t pinned_take(double **out, int *dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto &fl = g_pinned_free[dev];
+  if (!fl.empty()) {
+    *out = fl.back();
+    fl.pop_back();
+  } else {
+    e = hipHostMalloc((void **)out, GATE_HOST_DOUBLES * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+  }
+  *dev_out = dev;
+  return hipSuccess;
+}
+void pinned_give(double *p, int dev) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  g_pinned_free[dev].push_back(p);
+}
 
-// the gate's Lanczos runs after everything enqueued on st so far: the
-// estimates on side stream 0, the certificate on side stream 1
+}  // namespace
+
+tls_precond_s::~tls_precond_s() {
+  if (gate_pending) (void)hipStreamSynchronize(side);
+  for (hipEvent_t e : {ev_fork, ev_pair, ev_cert})
+    if (e) (void)hipEventDestroy(e);
+  if (hgate) pinned_give(hgate, hgate_dev);
+}
+
+namespace {
+
+// the gate's Lanczos runs after everything enqueued on st so far, one after
+// the other on the side stream: the estimates, then the certificate (run
+// side by side with each other they slowed the solve's iterations more)
 tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
-  HIPCHK(side_streams(P->side));
+  HIPCHK(side_stream(&P->side));
+  if (!P->hgate) HIPCHK(pinned_take(&P->hgate, &P->hgate_dev));
   for (hipEvent_t *e : {&P->ev_fork, &P->ev_pair, &P->ev_cert})
     if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   P->have_kappa = P->have_sigma_n = P->have_quality = 0;
   HIPCHK(hipEventRecord(P->ev_fork, st));
-  HIPCHK(hipStreamWaitEvent(P->side[0], P->ev_fork, 0));
-  HIPCHK(hipStreamWaitEvent(P->side[1], P->ev_fork, 0));
+  HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   // from here on the runs may be in flight: mark them before any early return
   P->gate_pending = 1;
-  tls_status s0 = enqueue_pair(P, W, P->side[0]);
-  hipError_t e0 = hipEventRecord(P->ev_pair, P->side[0]);
-  tls_status s1 = enqueue_cert(P, W, V, P->side[1]);
-  hipError_t e1 = hipEventRecord(P->ev_cert, P->side[1]);
-  if (e0 != hipSuccess || e1 != hipSuccess) {
-    // without recorded events the runs cannot be awaited one by one
-    (void)hipDeviceSynchronize();
+  tls_status s0 = enqueue_pair(P, W, P->side);
+  hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
+  tls_status s1 = enqueue_cert(P, W, V, P->side);
+  hipError_t e1 = hipEventRecord(P->ev_cert, P->side);
+  if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
+    (void)hipStreamSynchronize(P->side);
     P->gate_pending = 0;
-    return fail(TLS_ERR_HIP, "hipEventRecord failed on a side stream");
-  }
-  if (s0 != TLS_OK || s1 != TLS_OK) {
-    (void)hipEventSynchronize(P->ev_pair);
-    (void)hipEventSynchronize(P->ev_cert);
-    P->gate_pending = 0;
-    return s0 != TLS_OK ? s0 : s1;
+    if (s0 != TLS_OK) return s0;
+    if (s1 != TLS_OK) return s1;
+    return fail(TLS_ERR_HIP, "hipEventRecord failed on the side stream");
   }
   return TLS_OK;
 }
@@ -817,9 +838,8 @@ tls_status gate_finish(tls_precond_s *P) {
   P->gate_pending = 0;
   HIPCHK(hipEventSynchronize(P->ev_pair));
   HIPCHK(hipEventSynchronize(P->ev_cert));
-  FactorWs W = factor_ws_of(P);
-  TRY(collect_pair(P, W, P->side[0]));
-  TRY(collect_cert(P, W, P->side[1]));
+  TRY(collect_pair(P));
+  TRY(collect_cert(P));
   return TLS_OK;
 }
 
@@ -827,8 +847,10 @@ tls_status gate_finish(tls_precond_s *P) {
 // preconditioner whose gate never ran, e.g. an imported FP64 factor)
 tls_status estimate_sigma_n(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   TRY(gate_finish(P));
+  if (!P->hgate) HIPCHK(pinned_take(&P->hgate, &P->hgate_dev));
   TRY(enqueue_pair(P, W, st));
-  return collect_pair(P, W, st);
+  HIPCHK(hipStreamSynchronize(st));
+  return collect_pair(P);
 }
 
 // the b-dependent part of the gate: constraint (6) with sigma_{n+1} <=
