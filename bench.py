@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--profile-only", action="store_true",
                     help="a few solves of each path, no CPU leg (for rocprofv3 runs)")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--sweep", action="store_true",
+                    help="measured speedup over a size grid of dense planted-SVD problems "
+                         "(one JSON line per size); the default run is unaffected")
     return ap.parse_args()
 
 
@@ -86,12 +89,56 @@ def make_problem(workload):
         with open(os.path.join(ROOT, "tests", "golden", "sparse_c2_ref.json")) as f:
             ref = json.load(f)
         return A, b, np.array(ref["x"]), float(ref["sigma"])
-    m, n = 65536, 4096
-    sig = np.concatenate([1e-3 ** (np.arange(n) / (n - 1)), [3.9e-5]])
-    A, b, _, w = tlsgen.planted_svd(m, n, sig, seed=3100)
     # v = (I - 2 w w^T) e_{n+1} is the right singular vector of sigma_{n+1}
+    return planted_dense(65536, 4096, seed=3100)
+
+
+def planted_dense(m, n, seed):
+    """Dense A = Y diag(s) Z^T shaped like the 65536x4096 workload at another
+    size: sigma'_i geometric from 1 to 1e-3, sigma_{n+1} = 3.9e-5; x_TLS from
+    the construction."""
+    import tlsgen
+    sig = np.concatenate([1e-3 ** (np.arange(n) / (n - 1)), [3.9e-5]])
+    A, b, _, w = tlsgen.planted_svd(m, n, sig, seed=seed)
     x = 2 * w[n] * w[:n] / (1 - 2 * w[n] ** 2)
     return A, b, x, float(sig[n])
+
+
+SWEEP = [(8192, 512), (16384, 1024), (32768, 2048), (65536, 4096)]
+
+
+def sweep(tls, torch, steps, warmup):
+    """Time to 1e-10 of the FP64 and the mixed (BF16 factor) paths over
+    SWEEP, with the RQI counts r each needed (iterations up to the first
+    iterate within tolerance), so the measured speedup can be set against
+    the operation-count model of Section 3.2 at the same r."""
+    global PATHS
+    PATHS = WORKLOADS["dense_planted_65536x4096"]["paths"]
+    for m, n in SWEEP:
+        A, b, xref, sref = planted_dense(m, n, seed=3100 + n)
+        Ad = tls.dense(A)
+        bd = tls.device_vector(b)
+        snaps = torch.zeros((40, n), dtype=torch.float64, device="cuda")
+        out = {"m": m, "n": n}
+        for path in ("fp64", "mixed"):
+            for _ in range(warmup):
+                one_solve(tls, torch, Ad, bd, path)
+            ttts, rs, fs = [], [], []
+            for _ in range(steps):
+                P, x, sigma, st, tf, ts, rep = one_solve(tls, torch, Ad, bd, path, snaps)
+                xs = snaps[: st["iters"]].cpu().numpy()
+                k = next((k for k in range(st["iters"])
+                          if np.linalg.norm(xs[k] - xref) <= TOL * np.linalg.norm(xref)), None)
+                ttts.append(tf + st["t_ms"][k] if k is not None else float("nan"))
+                rs.append(k + 1 if k is not None else None)
+                fs.append(tf)
+            out[path] = {"time_to_tol_ms": statistics.median(ttts), "factor_ms": statistics.median(fs),
+                         "r": rs[-1], "err_sigma": abs(sigma - sref) / sref}
+        out["speedup_time_to_tol"] = out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"]
+        print(json.dumps({"sweep": "dense planted SVD, mixed = BF16 factor / FP32 PCG / gate", **out}),
+              flush=True)
+        del Ad, bd, snaps
+        torch.cuda.empty_cache()
 
 
 def one_solve(tls, torch, Ad, bd, path, snaps=None):
@@ -300,6 +347,9 @@ def main():
     global WORKLOAD, PATHS
     WORKLOAD = args.workload
     PATHS = WORKLOADS[WORKLOAD]["paths"]
+    if args.sweep:
+        sweep(tls, torch, max(args.steps, 1) if args.steps != 10 else 3, args.warmup)
+        return
     A, b, xref, sref = make_problem(WORKLOAD)
     Ad = tls.from_tlsgen(A)
     bd = tls.device_vector(b)

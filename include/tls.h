@@ -118,7 +118,9 @@ typedef struct {
   int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,
                               3: (6) holds, 4: a-posteriori certificate holds:
                               quality_lo >= 1/2 and quality_hi <= 3/2 (the
-                              factor is within 50% of A^T A in every direction) */
+                              factor is within 50% of A^T A in every direction),
+                              5: the solve's sigma lies below the estimate of
+                              sigma'_n (the smallest-root check)               */
   int32_t escalations;     /* times u_q was raised                               */
   int32_t chol_retries;    /* diagonal-shift retries after breakdown             */
   int32_t lanczos_steps;
@@ -177,7 +179,11 @@ typedef struct {
   int32_t gate_async;      /* 1: the gate's Lanczos runs were still in flight when
                               the iterations began (they overlapped the solve and
                               were read at a later host synchronisation)          */
-  int32_t reserved;
+  int32_t ls_refined;      /* != 0: the start was found outside the SPD region
+                              and a second solve ran from x_LS recomputed to
+                              convergence (|ls_refined| - 1 extra corrections);
+                              > 0 its result is returned, < 0 the first one
+                              (smaller sigma); see tls_rqi_solve                  */
   double sigma_ls;         /* sigma_0 = ||r_0|| / sqrt(1 + ||x_LS||^2)             */
   double psi[TLS_MAX_ITERS];
   double sigma[TLS_MAX_ITERS];
@@ -313,6 +319,17 @@ TLS_API size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P,
  * it is done, or at the end (stats.gate_async = 1); a failed verdict then
  * discards the iterate and escalates as above, so the returned result is
  * the one the waiting order gives. The shift clamp waits for the estimates.
+ * Start check (same condition, factor below FP64): a weak factor leaves the
+ * corrected semi-normal equations short of x_LS, and the error can put
+ * sigma_0 at or above sigma'_n, where A^T A - sigma^2 I is indefinite and RQI
+ * may settle on a larger singular value. When the gate finds sigma_0 at or
+ * above its estimate of sigma'_n (c~ <= 0 in (6)), a second solve runs on the
+ * same factor from x_LS recomputed with corrections until the last is below
+ * 1e-8 ||x|| (at most 64), and of the two converged results the one with
+ * the smaller sigma is returned: every Rayleigh quotient bounds
+ * sigma_{n+1} from above (stats.ls_refined). A problem whose own sigma_LS
+ * exceeds sigma'_n is not helped by the second start (the shift clamp is the
+ * remedy there), and keeps the first result.
  *
  * Warm start (project addition; opts.mlp_theta or opts.sigma0_hint). After
  * x_0 = x_LS, u_0 = (R^T R)^{-1} x_0 and sigma_0 (the quantities of the

@@ -1324,7 +1324,8 @@ using solve_clock = std::chrono::steady_clock;
 // caller's start, so t_ms keeps counting from the original call)
 tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
                           double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
-                          hipStream_t st, solve_clock::time_point t0, double t_factor_prior) {
+                          hipStream_t st, solve_clock::time_point t0, double t_factor_prior,
+                          int accurate_ls) {
   try {
     using clk = solve_clock;
     auto ms_since = [&](clk::time_point a) {
@@ -1402,6 +1403,27 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
         HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
       }
+      if (accurate_ls) {
+        // more corrections until the last one is below 1e-8 ||x|| (the
+        // error contracts by about max |1 - theta| over the factor's
+        // certificate per correction)
+        S.ls_refined = 1;
+        for (int c2 = 0; c2 < 64; ++c2) {
+          HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+          HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
+          TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
+          HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
+          DotPairs D{};
+          D.a[0] = D.b[0] = W.rhs; D.len[0] = n;
+          D.a[1] = D.b[1] = x; D.len[1] = n;
+          HIPCHK(launch_dots(D, 2, W.scal + 40, st));
+          double dd[2];
+          HIPCHK(hipMemcpyAsync(dd, W.scal + 40, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          ++S.ls_refined;
+          if (!(dd[0] > 1e-16 * dd[1])) break;
+        }
+      }
       HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       double h2[5];
@@ -1451,7 +1473,18 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     };
     auto resolve = [&]() -> tls_status {
       TRY(escalate());
-      return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, t0, S.t_factor_ms);
+      return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, t0, S.t_factor_ms, 0);
+    };
+    // the start violates the positive-definiteness assumption (sigma_0 at or
+    // above the estimate of sigma'_n, c~ <= 0 in (6)) with a low-precision
+    // factor: x_LS may be short of convergence (a weak factor); a second
+    // solve recomputes it to convergence on the same factor (once)
+    auto start_suspect = [&]() {
+      return !accurate_ls && P->storage != TLS_FP64 && std::isfinite(P->rep.ctilde_min) &&
+             P->rep.ctilde_min <= 0.0;
+    };
+    auto restart_ls = [&]() -> tls_status {
+      return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, t0, S.t_factor_ms, 1);
     };
     if (gate_failed) return resolve();
     // shift cap for the clamp (a deviation for starts above sigma'_n)
@@ -1656,6 +1689,26 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       }
       if (!(P->rep.verdict & 16)) return resolve();
     }
+    if (o->gate_enforce && start_suspect() && (bs == TLS_OK || bs == TLS_ERR_NO_CONVERGENCE)) {
+      // second solve from the converged x_LS; any Rayleigh quotient bounds
+      // sigma_{n+1} from above, so the smaller converged sigma is kept
+      std::vector<double> x_first((size_t)n);
+      HIPCHK(hipMemcpyAsync(x_first.data(), x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const tls_rqi_stats S_first = S;
+      const tls_status b1 = restart_ls();
+      if (b1 != TLS_OK && b1 != TLS_ERR_NO_CONVERGENCE) return b1;
+      if (!(S.sigma_final < S_first.sigma_final)) {
+        const int refined = S.ls_refined;
+        HIPCHK(hipMemcpyAsync(x, x_first.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        S = S_first;
+        S.ls_refined = -refined;
+        if (sigma) *sigma = S.sigma_final;
+        return bs;
+      }
+      return b1;
+    }
     return bs;
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
@@ -1669,7 +1722,7 @@ extern "C" {
 tls_status tls_rqi_solve(const tls_matrix *A, const double *b, tls_precond P, const tls_rqi_opts *o,
                          double *x, double *sigma, tls_rqi_stats *stats, void *ws, size_t ws_bytes,
                          hipStream_t st) {
-  return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, solve_clock::now(), 0.0);
+  return rqi_solve_from(A, b, P, o, x, sigma, stats, ws, ws_bytes, st, solve_clock::now(), 0.0, 0);
 }
 
 }  // extern "C"

@@ -85,7 +85,7 @@ _OPT_FIELDS = {name for name, _ in c_rqi_opts._fields_}
 class c_rqi_stats(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "iters", "k_best", "pcg_steps", "warm_used", "stopped", "negative_delta",
-        "refine_steps", "clamped", "gate_async", "reserved")] + \
+        "refine_steps", "clamped", "gate_async", "ls_refined")] + \
         [("sigma_ls", C.c_double), ("psi", C.c_double * MAX_ITERS),
          ("sigma", C.c_double * MAX_ITERS), ("t_ms", C.c_double * MAX_ITERS),
          ("t_factor_ms", C.c_double), ("t_total_ms", C.c_double), ("sigma_final", C.c_double),
@@ -98,7 +98,8 @@ class c_rqi_stats(C.Structure):
             "iters": k, "k_best": self.k_best, "pcg_steps": self.pcg_steps,
             "warm_used": self.warm_used, "stopped": self.stopped,
             "negative_delta": self.negative_delta, "refine_steps": self.refine_steps,
-            "clamped": self.clamped, "gate_async": self.gate_async, "sigma_ls": self.sigma_ls,
+            "clamped": self.clamped, "gate_async": self.gate_async, "ls_refined": self.ls_refined,
+            "sigma_ls": self.sigma_ls,
             "psi": list(self.psi[:k]), "sigma": list(self.sigma[:k]), "t_ms": list(self.t_ms[:k]),
             "t_factor_ms": self.t_factor_ms, "t_total_ms": self.t_total_ms,
             "sigma_final": self.sigma_final, "sigma_hat": self.sigma_hat,

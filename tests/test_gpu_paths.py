@@ -164,6 +164,29 @@ def test_background_gate_failure_escalates_like_waiting():
     assert xw.tobytes() == xa.tobytes() and sw == sa
 
 
+def test_weak_factor_start_outside_spd_region():
+    """Dense planted SVD 8192 x 512 (sigma' from 1 to 1e-3, sigma_{n+1} =
+    3.9e-5) with a BF16 factor: one corrected semi-normal step leaves x_0 far
+    enough from x_LS that sigma_0 lands above sigma'_n, and RQI from there
+    settles on the next singular value. The solve sees c~ <= 0 in (6), runs
+    a second time from the converged x_LS and keeps the smaller sigma."""
+    tls = _tls()
+    n, m = 512, 8192
+    sig = np.concatenate([1e-3 ** (np.arange(n) / (n - 1)), [3.9e-5]])
+    A, b, _, w = tlsgen.planted_svd(m, n, sig, seed=3612)
+    x_ref = 2 * w[n] * w[:n] / (1 - 2 * w[n] ** 2)
+    Ad = tls.dense(A)
+    for wait in (True, False):
+        P, _ = tls.tls_factor_precond(Ad, "bf16", wait_gate=wait)
+        opts = tls.default_opts(u_p="fp32", stop_patience=2, kmax=40, gate_enforce=1, allow_escalate=1,
+                                refine_sweeps=1)
+        x, s, st = tls.tls_rqi_solve(Ad, b, P, opts, allow_no_convergence=True)
+        print(f"wait={wait}: sigma {s:.6e} ls_refined {st['ls_refined']} iters {st['iters']}", flush=True)
+        assert st["ls_refined"] > 0
+        assert abs(s - sig[n]) / sig[n] < 1e-10
+        assert np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref) < 1e-10
+
+
 def test_shift_clamp_recovers_smallest_root():
     tls = _tls()
     A, b = tlsgen.paper_bjorck()
