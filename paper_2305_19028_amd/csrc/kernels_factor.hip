@@ -746,14 +746,15 @@ hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, 
 // --------------------------------------------------------------------------
 
 // U = Ri^T Rj for two 64x64 tiles in LDS (Ri[t][r] = entry (t, r) of the
-// tile of R whose columns index U's rows) on the matrix cores. Wave w takes
-// the 32x32 quadrant (rows 32 (w % 2).., columns 32 (w / 2)..). The operands
+// tile of R whose columns index U's rows) on the matrix cores, by a group of
+// four waves: wave w takes the 32x32 quadrant (rows 32 (w % 2).., columns
+// 32 ((w / 2) % 2)..), so waves 4-7 of a larger workgroup form a second group. The operands
 // are passed transposed (A from Rj, B from Ri) so that consecutive lanes
 // hold consecutive rows r of U: the callback emit(r, c, value) then touches
 // contiguous column-major addresses.
 template <typename C, typename Emit>
 __device__ inline void tile_product_t(const C (*Ri)[NB + 1], const C (*Rj)[NB + 1], Emit emit) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & 3, wr = w >> 1, wc = w & 1;
   if constexpr (std::is_same<C, double>::value) {
     g_f64x4 acc[2][2];
 #pragma unroll
@@ -801,7 +802,7 @@ __device__ inline void tile_product_t(const C (*Ri)[NB + 1], const C (*Rj)[NB + 
 // the (r, c) positions tile_product_t gives this lane, in the same order
 template <typename C, typename At>
 __device__ inline void tile_product_t_index(At at) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & 3, wr = w >> 1, wc = w & 1;
   if constexpr (std::is_same<C, double>::value) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -817,18 +818,19 @@ __device__ inline void tile_product_t_index(At at) {
 
 // a 64x64 tile at (row block I, column block J) of G into registers (16
 // values per thread, all loads in flight before the first wait), then LDS
-template <typename C>
+template <int THR, typename C>
 __device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB + 1]) {
-  C tmp[16];
+  constexpr int Q = NB * NB / THR;
+  C tmp[Q];
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q;
+  for (int q = 0; q < Q; ++q) {
+    const int t = tid + THR * q;
     tmp[q] = G[((size_t)J * NB + t / NB) * Np + (size_t)I * NB + t % NB];
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int t = tid + 256 * q;
+  for (int q = 0; q < Q; ++q) {
+    const int t = tid + THR * q;
     dst[t % NB][t / NB] = tmp[q];
   }
 }
@@ -860,8 +862,10 @@ __device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB
 // R(p,p) goes to rdiag (tile p, column-major), not to G: the other panel
 // workgroups of the launch still read G(p,p). k_chol_restore copies the
 // diagonal tiles back at the end.
+constexpr int CHOL_THREADS = 512;
 template <typename C, bool FUSED>
-__global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C *rdiag, int *info) {
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np, C *G, C *rdiag, int *info) {
+  constexpr int THR = CHOL_THREADS;
   __shared__ C ta[NB][NB + 1];     // R(k, .) operand / staged G(p,p) / output tile
   __shared__ C tb[NB][NB + 1];     // R(k, .) operand / staged G(p,p+j)
   __shared__ C slab[2][4][2 * NB];
@@ -875,9 +879,10 @@ __global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C
     while ((bq + 1) * (bq + 2) / 2 <= l) ++bq;
     while (bq * (bq + 1) / 2 > l) --bq;
     const int i = k + 2 + (l - bq * (bq + 1) / 2), j = k + 2 + bq;
-    tile_to_lds(G, Np, k, i, ta);
-    tile_to_lds(G, Np, k, j, tb);
+    tile_to_lds<THR>(G, Np, k, i, ta);
+    tile_to_lds<THR>(G, Np, k, j, tb);
     __syncthreads();
+    if (tid >= 256) return;   // one group of four waves takes the product
     C *Gij = G + (size_t)j * NB * Np + (size_t)i * NB;
     tile_product_t<C>(ta, tb, [&](int r, int c, C v) {
       if (i < j || r <= c) Gij[(size_t)c * Np + r] -= v;
@@ -885,80 +890,88 @@ __global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C
     return;
   }
   // ---- panel role: workgroup jb of block row p ---------------------------
+  // thread (tr, tq): row group tr = rows 4tr..; tq < 16 holds the 4x4 block
+  // of columns 4tq.. of G(p,p) (a v-lane), tq >= 16 the block of columns
+  // 4(tq - 16).. of the appended tile G(p,p+jb) (a w-lane). A row group is
+  // half a wave, so its v-lanes and w-lanes take the solves side by side.
   const int jb = blockIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
+  const int tr = tid >> 5, tq = tid & 31, tc = tq & 15;
+  const bool isw = tq >= 16;
   const int lane = tid & 63;
   const size_t base = (size_t)p * NB;
   const bool has_b = jb > 0;
   const size_t cb = (size_t)(p + jb) * NB;
   if (tid < 2) bad_s[tid] = 0;
   if (FUSED) {
-    // step k's update of the two tiles: ta <- R(k,p), tb <- R(k,p+jb)
-    tile_to_lds(G, Np, k, p, ta);
-    if (has_b) tile_to_lds(G, Np, k, p + jb, tb);
+    // step k's update of the two tiles: ta <- R(k,p), tb <- R(k,p+jb);
+    // waves 0-3 form G(p,p) - R(k,p)^T R(k,p), waves 4-7 G(p,p+jb) - R(k,p)^T R(k,p+jb)
+    tile_to_lds<THR>(G, Np, k, p, ta);
+    if (has_b) tile_to_lds<THR>(G, Np, k, p + jb, tb);
     __syncthreads();
-    // the products in registers, then the updated tiles staged in ta / tb
-    C u1[16], u2[16];
-    int n1 = 0, n2 = 0;
-    tile_product_t<C>(ta, ta, [&](int, int, C v) { u1[n1++] = v; });
-    if (has_b) tile_product_t<C>(ta, tb, [&](int, int, C v) { u2[n2++] = v; });
-    C g1[16], g2[16];
-    n1 = n2 = 0;
-    tile_product_t_index<C>([&](int r, int c) { g1[n1++] = G[(base + c) * Np + base + r]; });
-    if (has_b) tile_product_t_index<C>([&](int r, int c) { g2[n2++] = G[(cb + c) * Np + base + r]; });
+    const bool second = tid >= 256;
+    C u[16], gv[16];
+    int nn = 0;
+    if (!second) tile_product_t<C>(ta, ta, [&](int, int, C v) { u[nn++] = v; });
+    else if (has_b) tile_product_t<C>(ta, tb, [&](int, int, C v) { u[nn++] = v; });
+    nn = 0;
+    if (!second) tile_product_t_index<C>([&](int r, int c) { gv[nn++] = G[(base + c) * Np + base + r]; });
+    else if (has_b) tile_product_t_index<C>([&](int r, int c) { gv[nn++] = G[(cb + c) * Np + base + r]; });
     __syncthreads();   // every wave is done reading the R tiles
-    n1 = n2 = 0;
-    tile_product_t_index<C>([&](int r, int c) {
-      ta[r][c] = (r <= c) ? g1[n1] - u1[n1] : (C)0;
-      ++n1;
-    });
-    if (has_b) tile_product_t_index<C>([&](int r, int c) {
-      tb[r][c] = g2[n2] - u2[n2];
-      ++n2;
-    });
+    nn = 0;
+    if (!second) {
+      tile_product_t_index<C>([&](int r, int c) {
+        ta[r][c] = (r <= c) ? gv[nn] - u[nn] : (C)0;
+        ++nn;
+      });
+    } else if (has_b) {
+      tile_product_t_index<C>([&](int r, int c) {
+        tb[r][c] = gv[nn] - u[nn];
+        ++nn;
+      });
+    }
   } else {
-    C tmp[16];
+    constexpr int Q = NB * NB / THR;
+    C tmp[Q];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q;
+    for (int q = 0; q < Q; ++q) {
+      const int t = tid + THR * q;
       tmp[q] = G[(base + t / NB) * Np + base + t % NB];
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int t = tid + 256 * q, r = t % NB, c = t / NB;
+    for (int q = 0; q < Q; ++q) {
+      const int t = tid + THR * q, r = t % NB, c = t / NB;
       ta[r][c] = (r <= c) ? tmp[q] : (C)0;
     }
-    if (has_b) tile_to_lds(G, Np, p, p + jb, tb);
+    if (has_b) tile_to_lds<THR>(G, Np, p, p + jb, tb);
   }
   __syncthreads();
-  C v[4][4], w[4][4];
+  C blk[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      v[x][y] = ta[4 * tr + x][4 * tc + y];
-      w[x][y] = has_b ? tb[4 * tr + x][4 * tc + y] : (C)0;
-    }
+    for (int y = 0; y < 4; ++y)
+      blk[x][y] = isw ? (has_b ? tb[4 * tr + x][4 * tc + y] : (C)0) : ta[4 * tr + x][4 * tc + y];
   __syncthreads();   // from here on `ta` collects the output tile
   C (*stage)[NB + 1] = ta;
+  const int col0 = (isw ? NB : 0) + 4 * tc;   // this block's columns in the slab
   int bad = 0;
   for (int g = 0; g < NB / 4; ++g) {
     const int buf = g & 1;
     if (tr == g) {
-      const int src = (lane & ~15) + g;      // lane holding the diagonal block
+      const int src = (lane & 32) + g;       // the v-lane holding the diagonal block
       C d[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) d[x][y] = __shfl(v[x][y], src);
+        for (int y = 0; y < 4; ++y) d[x][y] = __shfl(blk[x][y], src);
       C rd[4][4], inv[4];
       int badrow = 0;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const C p = d[s][s];
-        if (!(p > (C)0) && !badrow) badrow = s + 1;
-        inv[s] = rsqrt_nr(p);          // one instruction plus a Newton step on the chain
-        const C rs = p * inv[s];
+        const C pv = d[s][s];
+        if (!(pv > (C)0) && !badrow) badrow = s + 1;
+        inv[s] = rsqrt_nr(pv);         // one instruction plus a Newton step on the chain
+        const C rs = pv * inv[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) rd[s][t] = (t == s) ? rs : (t > s ? d[s][t] * inv[s] : (C)0);
 #pragma unroll
@@ -966,47 +979,36 @@ __global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C
 #pragma unroll
           for (int t = s2; t < 4; ++t) d[s2][t] -= rd[s][s2] * rd[s][t];
       }
-      if (tc == g) {
+      if (!isw && tc == g) {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) v[x][y] = rd[x][y];
-      } else if (tc > g) {
+          for (int y = 0; y < 4; ++y) blk[x][y] = rd[x][y];
+      } else if (isw ? has_b : tc > g) {
+        // rows 4g.. of R in this block's columns: rd^{-T} applied to the block
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
-          for (int y = 0; y < 4; ++y) v[s][y] *= inv[s];
+          for (int y = 0; y < 4; ++y) blk[s][y] *= inv[s];
 #pragma unroll
           for (int s2 = s + 1; s2 < 4; ++s2)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) v[s2][y] -= rd[s][s2] * v[s][y];
+            for (int y = 0; y < 4; ++y) blk[s2][y] -= rd[s][s2] * blk[s][y];
         }
       } else {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) v[x][y] = (C)0;
-      }
-      if (has_b) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-#pragma unroll
-          for (int y = 0; y < 4; ++y) w[s][y] *= inv[s];
-#pragma unroll
-          for (int s2 = s + 1; s2 < 4; ++s2)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) w[s2][y] -= rd[s][s2] * w[s][y];
-        }
+          for (int y = 0; y < 4; ++y) blk[x][y] = (C)0;
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          slab[buf][s][4 * tc + y] = v[s][y];
-          slab[buf][s][NB + 4 * tc + y] = w[s][y];
-          stage[4 * g + s][4 * tc + y] = has_b ? w[s][y] : v[s][y];
+          slab[buf][s][col0 + y] = blk[s][y];
+          if (isw == has_b) stage[4 * g + s][4 * tc + y] = blk[s][y];
         }
-      if (badrow && tc == 0) bad_s[buf] = 4 * g + badrow;
+      if (badrow && tq == 0) bad_s[buf] = 4 * g + badrow;
     }
     __syncthreads();
     bad = bad_s[buf];   // uniform: every thread reads the same LDS word after the barrier
@@ -1014,20 +1016,16 @@ __global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C
     if (tr > g) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        C rr[4], rc[4], rb[4];
+        C rr[4], rc[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           rr[x] = slab[buf][s][4 * tr + x];
-          rc[x] = slab[buf][s][4 * tc + x];
-          rb[x] = slab[buf][s][NB + 4 * tc + x];
+          rc[x] = slab[buf][s][col0 + x];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            v[x][y] -= rr[x] * rc[y];
-            w[x][y] -= rr[x] * rb[y];
-          }
+          for (int y = 0; y < 4; ++y) blk[x][y] -= rr[x] * rc[y];
       }
     }
   }
@@ -1036,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_chol_step(int k, int N, int Np, C *G, C
     return;
   }
   __syncthreads();
-  for (int t = tid; t < NB * NB; t += 256) {
+  for (int t = tid; t < NB * NB; t += THR) {
     const int r = t % NB, c = t / NB;
     if (has_b) G[(cb + c) * Np + base + r] = stage[r][c];
     else if (r <= c) rdiag[(size_t)p * NB * NB + (size_t)c * NB + r] = stage[r][c];
@@ -1056,12 +1054,13 @@ __global__ __launch_bounds__(256) void k_chol_restore(int Np, C *G, const C *rdi
 
 template <typename C>
 static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream_t st) {
-  TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, false>), dim3(N), dim3(256), 0, st, 0, N, Np, G, rdiag, info);
+  TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, false>), dim3(N), dim3(CHOL_THREADS), 0, st, 0, N, Np, G, rdiag,
+             info);
   for (int k = 0; k + 1 < N; ++k) {
     const int M = N - k - 2;   // trailing block rows of the update role
     const int grid = (N - k - 1) + M * (M + 1) / 2;
-    TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, true>), dim3(grid), dim3(256), 0, st, k, N, Np, G, rdiag,
-               info);
+    TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, true>), dim3(grid), dim3(CHOL_THREADS), 0, st, k, N, Np, G,
+               rdiag, info);
   }
   TLS_LAUNCH(PC_PACK, k_chol_restore<C>, dim3(N), dim3(256), 0, st, Np, G, rdiag);
   return hipGetLastError();
