@@ -124,6 +124,8 @@ typedef struct {
   int32_t escalations;     /* times u_q was raised                               */
   int32_t chol_retries;    /* diagonal-shift retries after breakdown             */
   int32_t lanczos_steps;
+  int32_t method;          /* 0: Cholesky of the Gram matrix, 1: Householder QR  */
+  int32_t reserved;
 } tls_gate_report;
 
 #define TLS_MAX_ITERS 256
@@ -228,6 +230,33 @@ TLS_API tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t 
                               int32_t allow_escalate, void *ws, size_t ws_bytes,
                               hipStream_t stream, tls_precond *out,
                               tls_gate_report *rep);
+
+/* Bytes of workspace tls_factor_precond_qr needs for A and u_q (covers every
+ * escalation up to FP64): the factor workspace of tls_factor_precond
+ * without its dense cast buffer, plus the QR working matrix, FP64-sized,
+ * (m + Np - n) x Np with Np = 64 ceil(n / 64), and 8 KiB of reflector
+ * scratch per 256 rows of it. */
+TLS_API size_t tls_factor_qr_workspace_size(const tls_matrix *A, int32_t u_q);
+
+/* Build R with R^T R ~ A^T A from the Householder QR of A (Section 3: the
+ * R-factor of A = Q [R; 0], computed in precision u_q; constraint (5) of
+ * Section 3.1 asks u_q <~ kappa(A)^{-1}, against kappa(A)^{-2} for the
+ * Cholesky factor of fl(A^T A)). With scaling = 1, D = diag(||A e_j||),
+ * A D^{-1} is rounded to u_q (as in tls_factor_precond), its R-factor
+ * R_hat is computed with every stored value rounded to u_q (the products
+ * accumulate in FP32; everything in FP64 when u_q = FP64), its rows are
+ * given a nonnegative diagonal and R = R_hat D. Q is not formed. A CSR A is
+ * expanded into the dense working matrix. The gate, the handle and the
+ * solve are those of tls_factor_precond (verdict bit 0, constraint (5),
+ * is the a-priori condition that applies to this factor; bits 1 and 2
+ * concern the Cholesky route and are reported for comparison). A zero or
+ * non-finite pivot gives TLS_ERR_NOT_SPD, or, with allow_escalate, a
+ * refactorization in the next higher precision. ws must hold
+ * tls_factor_qr_workspace_size() bytes. */
+TLS_API tls_status tls_factor_precond_qr(const tls_matrix *A, int32_t u_q, int32_t scaling,
+                                 int32_t allow_escalate, void *ws, size_t ws_bytes,
+                                 hipStream_t stream, tls_precond *out,
+                                 tls_gate_report *rep);
 
 /* Bytes of workspace tls_precond_import needs for order n. */
 TLS_API size_t tls_precond_import_workspace_size(int64_t n);
@@ -414,9 +443,10 @@ TLS_API tls_status tls_mlp_adam(float *theta, float *m, float *v, const float *g
  *   10 pack  11 residual_dd  12 invert  13 mlp
  *   14 gate: every launch on the library's side streams (the gate's Lanczos
  *      runs, which overlap the caller's stream), whatever its kernel.
+ *   15 qr: the Householder QR factorization (tls_factor_precond_qr).
  * chol_panel counts the Cholesky step launches (each also carries the
  * previous step's trailing update); chol_update is no longer used. */
-#define TLS_PROF_CLASSES 15
+#define TLS_PROF_CLASSES 16
 typedef struct {
   int32_t launches[TLS_PROF_CLASSES];
   double total_ms[TLS_PROF_CLASSES];

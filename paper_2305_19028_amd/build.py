@@ -22,7 +22,7 @@ LIB = os.path.join(LIBDIR, "libtls.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 SOURCES = ["tls_api.hip", "kernels_trsv.hip", "kernels_factor.hip", "kernels_rqi.hip", "kernels_mlp.hip",
-           "kernels_inv.hip"]
+           "kernels_inv.hip", "kernels_qr.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

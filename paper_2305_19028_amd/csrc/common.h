@@ -86,6 +86,16 @@ template <> __device__ inline float st_from<float>(double v) {
 template <> __device__ inline half_t st_from<half_t>(double v) { return half_t{f64_to_f16_bits(v)}; }
 template <> __device__ inline bf16_t st_from<bf16_t>(double v) { return bf16_t{f64_to_bf16_bits(v)}; }
 
+// round one value to u_q, returned as double (exactly representable)
+__device__ inline double quantize(double v, int q) {
+  switch (q) {
+    case TLS_FP64: return v;
+    case TLS_FP32: return (double)__builtin_bit_cast(float, f64_to_f32_bits(v));
+    case TLS_FP16: return (double)f16_bits_to_float(f64_to_f16_bits(v));
+    default: return (double)bf16_bits_to_float(f64_to_bf16_bits(v));
+  }
+}
+
 template <typename S> constexpr int prec_of();
 template <> constexpr int prec_of<double>() { return TLS_FP64; }
 template <> constexpr int prec_of<float>() { return TLS_FP32; }

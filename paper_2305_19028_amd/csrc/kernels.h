@@ -13,7 +13,7 @@ namespace tls {
 // kernel classes of the profiling hooks (order as in tls.h)
 enum ProfClass { PC_TRSV_APPLY = 0, PC_PCG, PC_GRAM, PC_CHOL_PANEL, PC_CHOL_UPDATE, PC_RESIDUAL,
                  PC_GRADIENT, PC_SCALARS, PC_SETUP, PC_LANCZOS, PC_PACK, PC_RESID_DD, PC_INVERT,
-                 PC_MLP, PC_GATE };
+                 PC_MLP, PC_GATE, PC_QR };
 // no-ops unless profiling is on (see tls_profile_start)
 void prof_begin(int cls, hipStream_t st);
 // launches on a stream noted here are counted as PC_GATE whatever their kernel
@@ -119,6 +119,15 @@ hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, 
 // blocked Cholesky of G in place (upper); rdiag: N 64x64 tiles of scratch
 // in the compute precision (the diagonal tiles while the steps run)
 hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st);
+// Householder QR (kernels_qr.hip): bytes of the working matrix (FP64-sized,
+// m_pad x Np, m_pad = m + Np - n) and of all QR scratch; R goes to G
+// (column-major Np x Np, compute precision) with a nonnegative diagonal,
+// info receives the first zero or non-finite pivot (column + 1) by atomicMin
+size_t qr_matrix_bytes(int64_t m, int n);
+size_t qr_work_bytes(int64_t m, int n);
+hipError_t launch_qr_factor(int64_t m, int n, int Np, int format, int64_t ldA, const double *val,
+                            const int32_t *row_ptr, const int32_t *col_idx, const double *d, int scaled, int uq,
+                            int compute, void *work, void *G, int *info, hipStream_t st);
 hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
                              hipStream_t st);
 hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64,

@@ -217,16 +217,6 @@ hipError_t launch_scale_vectors(int n, int Np, const double *d, int scaled, doub
   return hipGetLastError();
 }
 
-// round one scaled value to u_q, returned as double (exactly representable)
-__device__ inline double quantize(double v, int q) {
-  switch (q) {
-    case TLS_FP64: return v;
-    case TLS_FP32: return (double)__builtin_bit_cast(float, f64_to_f32_bits(v));
-    case TLS_FP16: return (double)f16_bits_to_float(f64_to_f16_bits(v));
-    default: return (double)bf16_bits_to_float(f64_to_bf16_bits(v));
-  }
-}
-
 __global__ void k_round(const double *in, int64_t count, int q, double *out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < count) out[i] = quantize(in[i], q);

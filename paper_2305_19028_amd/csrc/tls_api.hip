@@ -106,6 +106,7 @@ struct tls_precond_s {
   void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
   int64_t fws_m = 0;
   int fws_cast = 0;               // the factor workspace holds a cast buffer
+  int method = 0;                 // 0 Cholesky of the Gram matrix, 1 Householder QR of A
   int have_sigma_n = 0, have_kappa = 0;
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
   double normA_F2 = 0;             // ||A||_F^2 = sum_j d_j^2
@@ -204,6 +205,7 @@ struct FactorWs {
   int *cnt;        // per-block arrival counters of internal applies
   double *tm;      // m-vector (products with A in the certificate)
   void *cast;      // dense A rounded to u_q (matrix-core Gram input), or NULL
+  void *qrw;       // Householder QR working matrix and reflector scratch, or NULL
   // the certificate's own buffers (it runs concurrently with the estimates)
   int *qsync, *qcnt;
   double *qpart, *qlz, *qlzs;
@@ -211,7 +213,7 @@ struct FactorWs {
 constexpr int LANCZOS_STEPS = 8;
 constexpr int QUALITY_STEPS = 6;
 
-FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast) {
+FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast, int qr = 0) {
   const int Np = ceil_div(n, NB) * NB, N = Np / NB;
   FactorWs W{};
   W.tiles = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
@@ -250,6 +252,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   W.qlzs = c.take<double>(2 * QUALITY_STEPS + 8);
   // low-precision copy of a dense A for the matrix-core Gram
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
+  W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
   return W;
 }
 
@@ -514,6 +517,14 @@ size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q) {
   if (check_matrix(A) != TLS_OK) return 0;
   Carver c(nullptr);
   carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64);
+  return c.size();
+}
+
+size_t tls_factor_qr_workspace_size(const tls_matrix *A, int32_t u_q) {
+  (void)u_q;
+  if (check_matrix(A) != TLS_OK) return 0;
+  Carver c(nullptr);
+  carve_factor(c, A->m, A->n, A->nnz, A->format, 0, 1);
   return c.size();
 }
 
@@ -867,11 +878,44 @@ void gate_decide(tls_precond_s *P, double sigma_ls) {
 
 FactorWs factor_ws_of(const tls_precond_s *P) {
   Carver c(P->fws_base);
-  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format, P->fws_cast);
+  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format, P->fws_cast, P->method);
+}
+
+// tiles of the storage precision, diagonal-tile inverses and the explicit
+// inverse from the factor R_hat in G
+tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, hipStream_t st) {
+  HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, uq, W.tiles, st));
+  HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
+  P->storage = uq;
+  P->xstorage = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+  HIPCHK(launch_invert(P->N, uq, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr, W.xc, st));
+  P->xr = W.xr;
+  P->xc = W.xc;
+  return TLS_OK;
+}
+
+// R_hat from the Householder QR of the scaled, u_q-rounded A (Section 3)
+tls_status factor_qr_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq, hipStream_t st,
+                          int *breakdown) {
+  const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+  *breakdown = 0;
+  if (!W.qrw) return fail(TLS_ERR_WORKSPACE, "factor workspace was not sized for QR");
+  HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
+  HIPCHK(launch_qr_factor(A->m, (int)A->n, P->Np, A->format, A->ld, A->val, A->row_ptr, A->col_idx, W.d,
+                          P->scaled, uq, compute, W.qrw, W.G, W.info, st));
+  int info = 0;
+  HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info != INT32_MAX) {
+    *breakdown = info;
+    return fail(TLS_ERR_NOT_SPD, "QR: zero or non-finite pivot at column %d", info - 1);
+  }
+  return finish_factor(P, W, uq, compute, st);
 }
 
 tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
                        hipStream_t st, int *breakdown) {
+  if (P->method == 1) return factor_qr_once(A, P, W, uq, st, breakdown);
   const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
   const int n = (int)A->n;
   *breakdown = 0;
@@ -889,17 +933,7 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
     int info = 0;
     HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (info == INT32_MAX) {
-      HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, uq, W.tiles, st));
-      HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
-      P->storage = uq;
-      P->xstorage = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
-      HIPCHK(launch_invert(P->N, uq, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr,
-                           W.xc, st));
-      P->xr = W.xr;
-      P->xc = W.xc;
-      return TLS_OK;
-    }
+    if (info == INT32_MAX) return finish_factor(P, W, uq, compute, st);
     *breakdown = info;
     if (!P->scaled) break;   // the shift ladder is defined for the scaled matrix
   }
@@ -910,19 +944,24 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
 
 extern "C" {
 
-tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
-                              int32_t allow_escalate, void *ws, size_t ws_bytes,
-                              hipStream_t stream, tls_precond *out, tls_gate_report *rep) {
+}  // extern "C"
+
+namespace {
+
+tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int32_t allow_escalate, void *ws,
+                          size_t ws_bytes, hipStream_t stream, tls_precond *out, tls_gate_report *rep,
+                          int method) {
   try {
     TRY(check_matrix(A));
     TRY(check_prec(u_q, "u_q"));
     if (!out) return fail(TLS_ERR_ARG, "out is NULL");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (!scaling && u_q != TLS_FP64) return fail(TLS_ERR_ARG, "unscaled factorization is FP64 only");
-    const size_t need = tls_factor_workspace_size(A, u_q);
+    const size_t need = method ? tls_factor_qr_workspace_size(A, u_q) : tls_factor_workspace_size(A, u_q);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "factor workspace %zu < %zu bytes", ws_bytes, need);
+    const int cast = (u_q != TLS_FP64) && !method;
     Carver c(ws);
-    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64);
+    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, cast, method);
     auto *P = new (std::nothrow) tls_precond_s();
     if (!P) return fail(TLS_ERR_ARG, "out of host memory");
     std::unique_ptr<tls_precond_s> guard(P);
@@ -943,9 +982,11 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
     P->d = W.d;
     P->fws_base = ws;
     P->fws_m = A->m;
-    P->fws_cast = u_q != TLS_FP64;
+    P->fws_cast = cast;
+    P->method = method;
     P->rep = tls_gate_report{};
     P->rep.requested = u_q;
+    P->rep.method = method;
     P->rep.sigma_n_est = P->rep.sigma_1_est = std::numeric_limits<double>::quiet_NaN();
     HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
     // finite input check
@@ -1009,6 +1050,22 @@ tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
+                              int32_t allow_escalate, void *ws, size_t ws_bytes,
+                              hipStream_t stream, tls_precond *out, tls_gate_report *rep) {
+  return factor_precond(A, u_q, scaling, allow_escalate, ws, ws_bytes, stream, out, rep, 0);
+}
+
+tls_status tls_factor_precond_qr(const tls_matrix *A, int32_t u_q, int32_t scaling,
+                                 int32_t allow_escalate, void *ws, size_t ws_bytes,
+                                 hipStream_t stream, tls_precond *out, tls_gate_report *rep) {
+  return factor_precond(A, u_q, scaling, allow_escalate, ws, ws_bytes, stream, out, rep, 1);
 }
 
 tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_host, int32_t storage,

@@ -59,7 +59,7 @@ class c_gate_report(C.Structure):
         "bound_chol", "bound_wilkinson", "bound_hp", "bound6", "u_q", "ctilde_min",
         "quality_lo", "quality_hi")] + \
         [(k, C.c_int32) for k in ("requested", "used", "verdict", "escalations",
-                                  "chol_retries", "lanczos_steps")]
+                                  "chol_retries", "lanczos_steps", "method", "reserved")]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,7 +110,7 @@ class c_rqi_stats(C.Structure):
 
 PROF_CLASSES = ["precond_apply", "pcg_step", "gram", "chol_panel", "chol_update", "residual",
                 "gradient", "outer_scalars", "setup", "lanczos", "pack", "residual_dd", "invert",
-                "mlp", "gate"]
+                "mlp", "gate", "qr"]
 
 
 class c_kernel_times(C.Structure):
@@ -131,6 +131,10 @@ _SIGS = {
     "tls_factor_precond": (C.c_int, [C.POINTER(c_matrix), C.c_int32, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p),
                                      C.POINTER(c_gate_report)]),
+    "tls_factor_qr_workspace_size": (C.c_size_t, [C.POINTER(c_matrix), C.c_int32]),
+    "tls_factor_precond_qr": (C.c_int, [C.POINTER(c_matrix), C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p),
+                                        C.POINTER(c_gate_report)]),
     "tls_precond_import_workspace_size": (C.c_size_t, [C.c_int64]),
     "tls_precond_import": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                      C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -301,22 +305,35 @@ def _prec(p) -> int:
     return PREC[p] if isinstance(p, str) else int(p)
 
 
+def _factor(size_fn, call_fn, A, u_q, scaling, allow_escalate, wait_gate):
+    nb = size_fn(C.byref(A.c), _prec(u_q))
+    if nb == 0:
+        _check(-1)
+    ws = Workspace(nb)
+    h = C.c_void_p()
+    rep = c_gate_report()
+    _check(call_fn(C.byref(A.c), _prec(u_q), int(scaling), int(allow_escalate),
+                   ws.ptr, ws.nbytes, _stream(), C.byref(h),
+                   C.byref(rep) if wait_gate else None))
+    return Precond(h, ws, A), (rep.to_dict() if wait_gate else None)
+
+
 def tls_factor_precond(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False, wait_gate=True):
     """Build the preconditioner of A (see tls.h). Returns (Precond, gate report
     dict). With wait_gate=False the gate's Lanczos runs of a low-precision
     factor finish in the background (the solve overlaps them) and the report
     is None; Precond.info() waits for them."""
     L = lib()
-    nb = L.tls_factor_workspace_size(C.byref(A.c), _prec(u_q))
-    if nb == 0:
-        _check(-1)
-    ws = Workspace(nb)
-    h = C.c_void_p()
-    rep = c_gate_report()
-    _check(L.tls_factor_precond(C.byref(A.c), _prec(u_q), int(scaling), int(allow_escalate),
-                                ws.ptr, ws.nbytes, _stream(), C.byref(h),
-                                C.byref(rep) if wait_gate else None))
-    return Precond(h, ws, A), (rep.to_dict() if wait_gate else None)
+    return _factor(L.tls_factor_workspace_size, L.tls_factor_precond, A, u_q, scaling,
+                   allow_escalate, wait_gate)
+
+
+def tls_factor_precond_qr(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False, wait_gate=True):
+    """The preconditioner from the Householder QR of A (see tls.h); same
+    returns and options as tls_factor_precond."""
+    L = lib()
+    return _factor(L.tls_factor_qr_workspace_size, L.tls_factor_precond_qr, A, u_q, scaling,
+                   allow_escalate, wait_gate)
 
 
 def tls_precond_import(R, d=None, storage="fp64"):
