@@ -51,14 +51,18 @@ WORKLOADS = {
                   "mixed": dict(u_q="fp16", u_p="fp32", opts=GATED)},
         "dtype": "f16 factor / f32 PCG / f64 outer",
         # reported beside the line, not the headline: the FP32 factor (same
-        # FP32 Cholesky arithmetic, FP32 storage) needs fewer RQI iterations
-        "variants": {"fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED)},
+        # FP32 Cholesky arithmetic, FP32 storage) needs fewer RQI iterations;
+        # the Householder QR factor (Section 3's choice) in FP16 and FP32
+        "variants": {"fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED),
+                     "qr_fp16": dict(u_q="fp16", u_p="fp32", opts=GATED, method="qr"),
+                     "qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
     },
     "dense_planted_65536x4096": {
         "describe": "dense 65536x4096 planted SVD, sigma' geometric 1..1e-3, sigma_{n+1} 3.9e-5, seed 3100",
         "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
                   "mixed": dict(u_q="bf16", u_p="fp32", opts=GATED)},
         "dtype": "bf16 factor (MFMA Gram) / f32 PCG / f64 outer",
+        "variants": {"qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
     },
 }
 WORKLOAD = "sparse_20000x2000"
@@ -151,7 +155,8 @@ def one_solve(tls, torch, Ad, bd, path, snaps=None):
     cfg = PATHS[path]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P, _ = tls.tls_factor_precond(Ad, cfg["u_q"], wait_gate=False)
+    factor = tls.tls_factor_precond_qr if cfg.get("method") == "qr" else tls.tls_factor_precond
+    P, _ = factor(Ad, cfg["u_q"], wait_gate=False)
     torch.cuda.current_stream().synchronize()
     t1 = time.perf_counter()
     opts = tls.default_opts(u_p=cfg["u_p"], stop_patience=2, kmax=40, x_snapshots=snaps,
@@ -363,7 +368,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"copied {COPY_BYTES} bytes", flush=True)
-        for path in ("fp64", "mixed"):
+        for vname, vcfg in WORKLOADS[WORKLOAD].get("variants", {}).items():
+            PATHS[vname] = vcfg
+        for path in ("fp64", "mixed", *WORKLOADS[WORKLOAD].get("variants", {})):
             for _ in range(max(args.steps, 1)):
                 one_solve(tls, torch, Ad, bd, path)
             torch.cuda.synchronize()
@@ -386,6 +393,19 @@ def main():
                            "speedup_vs_fp64_time_to_tol":
                                (res["fp64"]["time_to_tol_ms"] / r["time_to_tol_ms"])
                                if r["time_to_tol_ms"] and res["fp64"]["time_to_tol_ms"] else None}
+        if vcfg.get("method") == "qr":
+            # the QR factorization's kernels against the FP32 matrix-core peak
+            # (its products run on MFMA in FP32, or FP64 for an FP64 factor):
+            # Table 1's 2mn^2 - 2n^3/3 flops per factorization
+            qp = kernel_profile(tls, torch, Ad, bd, vname, reps=2).get("qr")
+            mm, nn = (A.shape if dense else (A.m, A.n))
+            if qp:
+                fl = 2.0 * mm * nn * nn - 2.0 * nn ** 3 / 3.0
+                peak = PEAKS["mfma_f64" if vcfg["u_q"] == "fp64" else "mfma_f32"][0]
+                ach = fl / (qp["ms_per_solve"] * 1e-3) / 1e12
+                variants[vname]["qr_kernels"] = {
+                    "launches": qp["launches"], "ms": qp["ms_per_solve"], "flops": fl,
+                    "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
         print(f"# variant {vname}: {variants[vname]}", file=sys.stderr, flush=True)
     prof = {p: kernel_profile(tls, torch, Ad, bd, p) for p in ("fp64", "mixed")}
     print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)

@@ -243,9 +243,10 @@ TLS_API size_t tls_factor_qr_workspace_size(const tls_matrix *A, int32_t u_q);
  * Section 3.1 asks u_q <~ kappa(A)^{-1}, against kappa(A)^{-2} for the
  * Cholesky factor of fl(A^T A)). With scaling = 1, D = diag(||A e_j||),
  * A D^{-1} is rounded to u_q (as in tls_factor_precond), its R-factor
- * R_hat is computed with every stored value rounded to u_q (the products
- * accumulate in FP32; everything in FP64 when u_q = FP64), its rows are
- * given a nonnegative diagonal and R = R_hat D. Q is not formed. A CSR A is
+ * R_hat is computed with every entry of the working matrix rounded to u_q
+ * when stored (products and the block reflectors' intermediates in FP32;
+ * everything in FP64 when u_q = FP64), its rows are given a nonnegative
+ * diagonal and R = R_hat D. Q is not formed. A CSR A is
  * expanded into the dense working matrix. The gate, the handle and the
  * solve are those of tls_factor_precond (verdict bit 0, constraint (5),
  * is the a-priori condition that applies to this factor; bits 1 and 2

@@ -4,8 +4,8 @@
 // Q is never formed.
 //
 // Working matrix W: row-major, m_pad x Np (leading dimension Np), in the
-// compute precision (FP64 for an FP64 factor, FP32 otherwise, every stored
-// value rounded to u_q). m_pad = m + (Np - n): rows m..m_pad-1 hold e_j for
+// compute precision (FP64 for an FP64 factor, FP32 otherwise, every entry
+// rounded to u_q when it is stored; products accumulate in FP32). m_pad = m + (Np - n): rows m..m_pad-1 hold e_j for
 // the padding columns j = n..Np-1, so that R(W) = [R(A D^{-1}) 0; 0 I].
 //
 // Panels of NB = 64 columns are reduced one after another. Panel p works on
@@ -186,17 +186,22 @@ __global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpa
       C w = part[buf][0][q];
 #pragma unroll
       for (int k = 1; k < QR_S / 64; ++k) w += part[buf][k][q];
-      wsum[buf][q] = w;
+      wsum[buf][q] = (q > j) ? w : (C)0;    // zero where no update applies
       if (q < j) Zs[q][j] = w;
     }
     if (q == 0) tau_s[j] = tau;
     __syncthreads();
-    const C tv = tau * v;
+    // all 64 values first (independent LDS reads), then a branch-free update:
+    // a(c) - tau v 0 = a(c) for the columns c <= j
+    C ws[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c > j) a[c] -= tv * wsum[buf][c];
-      if (c == j && q >= j) a[c] = (q == j) ? beta : v;
-    }
+    for (int c = 0; c < NB; ++c) ws[c] = wsum[buf][c];
+    const C tv = tau * v;
+    const C keep = (q >= j) ? ((q == j) ? beta : v) : x;   // new entry of column j
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] -= tv * ws[c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = (c == j) ? keep : a[c];
   }
   // the slab's triangle and reflectors, rounded to u_q
   if (valid) {
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpa
   }
   __syncthreads();
   C *T = Tbuf + (size_t)g * NB * NB;
-  for (int e = q; e < NB * NB; e += QR_S) T[e] = store_q(Ts[e / NB][e % NB], uq);
+  for (int e = q; e < NB * NB; e += QR_S) T[e] = Ts[e / NB][e % NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -236,8 +241,10 @@ __global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpa
 // ---------------------------------------------------------------------------
 // Three 64 x 64 LDS tiles: phase 1 Z = Y^T C over the slab's four 64-row
 // chunks (Y chunk in B0, C chunk in B1); phase 2 Zt = T^T Z (T in B0, Z in
-// B1, result rounded to u_q into B2); phase 3 C -= Y Zt chunk by chunk (Y
-// chunk back in B0). Four waves each own a 32 x 32 quadrant of every
+// B1, result into B2); phase 3 C -= Y Zt chunk by chunk (Y chunk back in
+// B0). Only the updated entries of W are rounded to u_q: T and Zt are
+// block intermediates and stay in the accumulation precision, as the
+// column-by-column algorithm rounds only what it stores. Four waves each own a 32 x 32 quadrant of every
 // 64 x 64 product; the C values stay in registers in the product layout.
 template <typename C>
 struct QrTile;
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(256) void k_qr_apply(C *W, int64_t ld, int64_t mpad
   acc.zero();
   acc.kk(B0, B1, wr, wc, lane);
 #pragma unroll
-  for (int r = 0; r < RC; ++r) B2[Tile::row(r, wr, lane)][Tile::col(r, wc, lane)] = store_q(acc.get(r), uq);
+  for (int r = 0; r < RC; ++r) B2[Tile::row(r, wr, lane)][Tile::col(r, wc, lane)] = acc.get(r);
   // phase 3: C -= Y Zt
 #pragma unroll
   for (int ch = 0; ch < QR_FAN; ++ch) {

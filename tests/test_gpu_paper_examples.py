@@ -2,7 +2,8 @@
 (FP64 factor and PCGTLS) and mixed (FP16 factor, FP32 PCGTLS), against the
 oracle's runs of the same algorithm on the same factor construction
 (tests/test_oracle_paper_examples.py pins the oracle to the paper's
-qualitative claims). Per iterate the relative error of x is taken against
+qualitative claims); then the same with the Householder QR factor
+(Section 3's choice) against the oracle's QR runs. Per iterate the relative error of x is taken against
 the SVD of [A, b]; the first RQI within 1e-10 and the limiting accuracy
 are compared. The mixed run has the gate and the refinement off, as the
 oracle's has."""
@@ -10,7 +11,7 @@ import numpy as np
 import pytest
 
 import tlsgen
-from oracle import exact, lowprec, rqi
+from oracle import exact, lowprec, qr, rqi
 
 pytestmark = pytest.mark.gpu
 
@@ -62,3 +63,41 @@ def test_paper_example_iterates_follow_oracle(gen, tau):
     kp, km = rows["plain"][0], rows["mixed"][0]
     if kp is not None and km is not None:
         assert km >= kp - 1            # mixed precision needs at least about as many RQIs
+
+
+@pytest.mark.parametrize("gen,tau", CASES)
+def test_paper_example_qr_factor_follows_oracle(gen, tau):
+    """FP64 QR: the same iterates as the FP64 Cholesky factor (the two
+    factors agree to rounding, Section 3). FP16 QR with FP32 PCGTLS: the
+    first RQI within 1e-10 and the limiting accuracy of the oracle's run on
+    its simulated FP16 QR factor. The GPU rounds the slab results of each
+    tree level to FP16 where the oracle rounds after every reflector, so
+    the counts may differ by the same margin as the Cholesky runs."""
+    import torch
+    tls = _tls()
+    out = getattr(tlsgen, gen)()
+    A, b = out[0], out[1]
+    ref = exact.svd_tls(A, b)
+    n = A.shape[1]
+    sn = np.linalg.svd(A, compute_uv=False)[-1]
+    clamp = None if tau is None else tau * sn * sn
+    Ad = tls.dense(A)
+    rows = {}
+    for name, uq, up, prec in (("plain", "fp64", "fp64", np.float64), ("mixed", "fp16", "fp32", np.float32)):
+        Rh, d = qr.scaled_qr_factor(A, uq)
+        o = rqi.rqi_pcgtls(A, b, Rh * d[None, :], prec_p=prec, patience=3, kmax=60, shift_clamp=clamp)
+        ko, eo = _first_within(o.x_hist, ref)
+        P, _ = tls.tls_factor_precond_qr(Ad, uq)
+        snaps = torch.zeros((60, n), dtype=torch.float64, device="cuda")
+        kw = dict(u_p=up, stop_patience=3, kmax=60, x_snapshots=snaps)
+        if tau is not None:
+            kw.update(shift_clamp=1, shift_clamp_tau=tau)
+        x, s, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(**kw), allow_no_convergence=True)
+        kg, eg = _first_within(snaps[: st["iters"]].cpu().numpy(), ref)
+        rows[name] = kg
+        print(f"{gen} qr {name}: GPU first<=1e-10 {kg} best {eg:.1e} | oracle {ko} best {eo:.1e}", flush=True)
+        if ko is not None:
+            assert kg is not None and abs(kg - ko) <= 2, (kg, ko)
+        assert eg <= 100 * max(eo, 1e-14), (eg, eo)
+    if rows["plain"] is not None and rows["mixed"] is not None:
+        assert rows["mixed"] >= rows["plain"] - 1

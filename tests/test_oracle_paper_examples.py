@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import tlsgen
-from oracle import exact, lowprec, rqi
+from oracle import exact, lowprec, qr, rqi
 
 CASES = ["paper_random", "paper_delta", "paper_toeplitz", "paper_vanhuffel"]
 
@@ -76,3 +76,26 @@ def test_ge_rule_stops_no_later():
     gt = rqi.rqi_pcgtls(A, b, R, prec_p=np.float32, patience=1, kmax=60)
     ge = rqi.rqi_pcgtls(A, b, R, prec_p=np.float32, patience=1, kmax=60, stop_ge=True)
     assert ge.iters <= gt.iters
+
+
+@pytest.mark.parametrize("gen", CASES)
+def test_qr_factor_plain_equals_cholesky_and_mixed_converges(gen):
+    """Section 3: for full-rank A the R-factor of A equals the Cholesky
+    factor of A^T A, so the plain runs take the same iterations; the mixed
+    run with the FP16 QR factor reaches the plain accuracy with at least as
+    many RQIs. On Van Huffel's problem the Cholesky factor needs no more RQIs
+    than the QR factor (the paper sees Cholesky ahead there)."""
+    A, b, ref = _problem(gen)
+    chol = rqi.rqi_pcgtls(A, b, rqi.cholesky_R(A), patience=3, kmax=60)
+    plain = rqi.rqi_pcgtls(A, b, qr.householder_r(A), patience=3, kmax=60)
+    Rh, d = qr.scaled_qr_factor(A, "fp16")
+    mixed = rqi.rqi_pcgtls(A, b, Rh * d[None, :], prec_p=np.float32, patience=3, kmax=60)
+    kc, _ = _first_within(chol, ref)
+    kp, ep = _first_within(plain, ref)
+    km, em = _first_within(mixed, ref)
+    assert kp == kc
+    assert km is not None and km >= kp and em <= 100 * max(ep, 1e-15)
+    if gen == "paper_vanhuffel":
+        kmc, _ = _first_within(rqi.rqi_pcgtls(A, b, _mp_factor(A), prec_p=np.float32, patience=3,
+                                              kmax=60), ref)
+        assert kmc <= km
