@@ -422,14 +422,13 @@ hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, 
 // dense Gram on the matrix cores
 //
 // G = Ahat^T Ahat (upper tiles) with 128 x 128 output tiles per workgroup
-// of four waves (64 x 64 each). A K-chunk of 32 rows of the two column
-// panels is staged in LDS (row = one column of Ahat, 32 consecutive
-// entries); the next chunk's global loads are in flight while the current
-// one feeds the MFMAs. Instructions by input type:
-//   bf16 / fp16: v_mfma_f32_32x32x16 (FP32 accumulation), operand = 8
-//                consecutive k of one column
-//   fp32:        v_mfma_f32_32x32x2_f32
-//   fp64:        v_mfma_f64_16x16x4_f64
+// of four waves (64 x 64 each). FP64 and FP32 inputs (k_gram_mfma): a
+// K-chunk of 32 rows of the two column panels is staged in LDS (row = one
+// column of Ahat, 32 consecutive entries); the next chunk's global loads
+// are in flight while the current one feeds the MFMAs
+// (v_mfma_f64_16x16x4_f64, v_mfma_f32_32x32x2_f32). FP16 / BF16 inputs
+// (k_gram_mfma16, below): v_mfma_f32_32x32x16 with FP32 accumulation, an
+// operand being 8 consecutive k of one column.
 // The MFMA's A operand takes the output-column panel and its B operand the
 // output-row panel, so that a lane's results lie along a column of the
 // column-major G and the stores coalesce.
@@ -465,7 +464,6 @@ __global__ __launch_bounds__(256) void k_cast_dense(int m, int n, int64_t ld, co
   }
 }
 
-template <typename T> struct GramIn { using V = uint4; static constexpr int E = 16 / sizeof(T); };
 
 template <typename T, typename C>
 __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, const T *A, int Np, C *G,
@@ -543,10 +541,10 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
         for (int q = 0; q < 16; ++q) acc32[t][u][q] = 0.0f;
   }
 
-  // FP32 accumulators are folded into FP64 sums every FLUSH chunks, so that
+  // FP32 accumulators are folded into FP64 sums after every chunk, so that
   // the accumulation error over the m rows stays near that of one chunk
-  // (about sqrt(32 FLUSH) u_32 relative) instead of growing like sqrt(m)
-  constexpr int FLUSH = std::is_same<T, float>::value ? 1 : 8;
+  // (about sqrt(32) u_32 relative) instead of growing like sqrt(m) u_32
+  constexpr int FLUSH = 1;
   double sum64[F64 ? 1 : 2][F64 ? 1 : 2][F64 ? 1 : 16];
   if constexpr (!F64) {
 #pragma unroll
@@ -593,7 +591,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
           for (int u = 0; u < 4; ++u)
             acc64[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc64[t][u], 0, 0, 0);
       }
-    } else if constexpr (std::is_same<T, float>::value) {
+    } else {
 #pragma unroll
       for (int s = 0; s < GKC / 2; ++s) {
         float a[2], b[2];
@@ -607,27 +605,6 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
 #pragma unroll
           for (int u = 0; u < 2; ++u)
             acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[u], acc32[t][u], 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < GKC / 16; ++s) {
-        uint4 a[2], b[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          a[t] = *(const uint4 *)&Ps[wc * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
-          b[t] = *(const uint4 *)&Qp[wr * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            if constexpr (std::is_same<T, bf16_t>::value)
-              acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  __builtin_bit_cast(g_bf16x8, a[t]), __builtin_bit_cast(g_bf16x8, b[u]), acc32[t][u], 0, 0, 0);
-            else
-              acc32[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                  __builtin_bit_cast(g_f16x8, a[t]), __builtin_bit_cast(g_f16x8, b[u]), acc32[t][u], 0, 0, 0);
-          }
       }
     }
   }
@@ -664,10 +641,185 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
   }
 }
 
-size_t gram_cast_bytes(int64_t m, int64_t n) {
-  const int64_t mp = ((m + GKC - 1) / GKC) * GKC;
+// ---- 16-bit inputs: K-split Gram --------------------------------------------
+// FP16 / BF16 inputs go through a separate kernel. The K range is cut into
+// segments of G16SEG rows and each (tile, segment) pair is its own workgroup
+// (8 segments x 528 tiles at 65536 x 4096 instead of 528 workgroups over 256
+// CUs). A segment's partial tile goes to a scratch buffer and a second
+// kernel sums the segments in FP64 in a fixed order. Workgroups run in
+// (tile, segment) order, tiles fastest, so the resident ones share a
+// segment (64 MB at n = 4096, held by the last-level cache). Two XCD-aware
+// orders were measured and dropped: each XCD taking a contiguous eighth of
+// the tiles in 8 x 8-panel blocks (the 32 workgroups of an XCD then share
+// about 15 panels through its L2) ran in the same time, and each XCD taking
+// its own segment was 10% slower; neither locality nor the layout of the
+// cast (column-major or chunk-major) moved the kernel, whose chunk loop waits
+// on the latency of its one chunk of register prefetch. Within a segment, 64-row
+// chunks (one 128-byte line per column) are double buffered in LDS with one
+// barrier per chunk: the global loads of chunk k+2 are issued while chunk k
+// feeds the MFMAs, and chunk k+1 is staged after them. The FP32 MFMA sums
+// are folded into FP64 every G16FOLD chunks (256 rows): on the scaled Gram
+// matrix of the 65536 x 4096 planted problem, whose smallest eigenvalue is
+// near 7e-5, FP32 sums over a whole segment moved the diagonal by about 1% of
+// it and took the BF16 path from 22 to 32 RQIs. The segment's FP64 sum is
+// stored in FP32 (at most 1/8 of a unit diagonal entry: 1e-8 absolute).
+constexpr int G16K = 64, G16SEG = 8192, G16RL = G16K + 8, G16FOLD = 4;
+
+// upper tile (I, J), I <= J, of linear index l = J (J + 1) / 2 + I
+__device__ inline void gram_tile_of(int l, int &I, int &J) {
+  J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= l) ++J;
+  while (J * (J + 1) / 2 > l) --J;
+  I = l - J * (J + 1) / 2;
+}
+
+inline int64_t gram_rows_padded(int64_t m) { return ((m + G16K - 1) / G16K) * G16K; }
+inline int gram_segments(int64_t m) { return (int)((gram_rows_padded(m) + G16SEG - 1) / G16SEG); }
+inline size_t gram_cast_only_bytes(int64_t m, int64_t n) {
   const int64_t n128 = ((n + GT - 1) / GT) * GT;
-  return (size_t)mp * n128 * 4;   // room for the widest low-precision input (FP32)
+  return ((size_t)gram_rows_padded(m) * n128 * 4 + 255) / 256 * 256;   // FP32-sized
+}
+
+// the 16-bit cast in chunk-major order: out[((r / 64) n128 + c) 64 + r % 64]
+// = round(A(r, c) / d_c), zero padding. A 64-row chunk of all columns is
+// contiguous, so a panel's chunk is 16 KB in one piece for the Gram kernel
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_blocked(int m, int n, int64_t ld, const double *A, const double *d,
+                                                     int scaled, int mp, int n128, T *out) {
+  const int c = blockIdx.y;
+  const double sc = (c < n && scaled) ? 1.0 / d[c] : 1.0;
+  const double *col = A + (size_t)c * ld;
+  for (int r = blockIdx.x * 1024 + threadIdx.x; r < min(mp, (int)(blockIdx.x + 1) * 1024); r += 256) {
+    const double v = (r < m && c < n) ? col[r] * sc : 0.0;
+    out[((size_t)(r / G16K) * n128 + c) * G16K + (r % G16K)] = cast_bits<T>(v);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_mfma16(int mp, const T *A, float *part, int NT) {
+  __shared__ __attribute__((aligned(16))) T Ps[2][GT][G16RL];   // output-column panel (J)
+  __shared__ __attribute__((aligned(16))) T Qs[2][GT][G16RL];   // output-row panel (I)
+  const int ntiles = NT * (NT + 1) / 2, l = blockIdx.x, seg = blockIdx.y;
+  int I, J;
+  gram_tile_of(l, I, J);
+  const bool diag = (I == J);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int r0 = I * GT, c0 = J * GT;
+  const int kbeg = seg * G16SEG;
+  const int nch = (min(mp, kbeg + G16SEG) - kbeg) / G16K;
+  uint4 pv[4], qv[4];
+  const size_t cstride = (size_t)NT * GT * G16K;          // elements per 64-row chunk
+  auto fetch = [&](int k0) {
+    const T *chunk = A + (size_t)(k0 / G16K) * cstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = tid + 256 * i, c = v >> 3, o = (v & 7) * 8;
+      pv[i] = *(const uint4 *)(chunk + (size_t)(c0 + c) * G16K + o);
+      if (!diag) qv[i] = *(const uint4 *)(chunk + (size_t)(r0 + c) * G16K + o);
+    }
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = tid + 256 * i, c = v >> 3, o = (v & 7) * 8;
+      *(uint4 *)&Ps[b][c][o] = pv[i];
+      if (!diag) *(uint4 *)&Qs[b][c][o] = qv[i];
+    }
+  };
+  g_f32x16 acc[2][2];
+  double sum[2][2][16];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        acc[t][u][q] = 0.0f;
+        sum[t][u][q] = 0.0;
+      }
+  auto fold = [&]() {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          sum[t][u][q] += (double)acc[t][u][q];
+          acc[t][u][q] = 0.0f;
+        }
+  };
+  if (nch > 0) {
+    fetch(kbeg);
+    stage(0);
+    if (nch > 1) fetch(kbeg + G16K);
+  }
+  __syncthreads();
+  for (int it = 0; it < nch; ++it) {
+    const int cur = it & 1;
+    const T (*P)[G16RL] = Ps[cur];
+    const T (*Q)[G16RL] = diag ? Ps[cur] : Qs[cur];
+#pragma unroll
+    for (int s = 0; s < G16K / 16; ++s) {
+      uint4 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = *(const uint4 *)&P[wc * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
+        b[t] = *(const uint4 *)&Q[wr * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if constexpr (std::is_same<T, bf16_t>::value)
+            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(g_bf16x8, a[t]), __builtin_bit_cast(g_bf16x8, b[u]), acc[t][u], 0, 0, 0);
+          else
+            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(g_f16x8, a[t]), __builtin_bit_cast(g_f16x8, b[u]), acc[t][u], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nch) {
+      stage(cur ^ 1);                       // chunk it+1: its buffer was last read in iteration it-1
+      if (it + 2 < nch) fetch(kbeg + (it + 2) * G16K);
+    }
+    if ((it + 1) % G16FOLD == 0) fold();
+    __syncthreads();
+  }
+  fold();
+  // partial tile, column-major inside the tile: part[seg][pos][c_local][r_local]
+  float *dst = part + ((size_t)seg * ntiles + l) * GT * GT;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int cl = wc * 64 + t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int rl = wr * 64 + u * 32 + (lane & 31);
+        dst[cl * GT + rl] = (float)sum[t][u][q];
+      }
+}
+
+// G (upper, column-major, FP32) = sum over segments of the partial tiles,
+// added in FP64 in segment order
+__global__ __launch_bounds__(256) void k_gram_reduce(const float *part, int nseg, int NT, int Np, float *G) {
+  const int l = blockIdx.x, ntiles = NT * (NT + 1) / 2;
+  int I, J;
+  gram_tile_of(l, I, J);
+  for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    double sum = 0.0;
+    for (int k = 0; k < nseg; ++k) sum += (double)part[((size_t)k * ntiles + l) * GT * GT + e];
+    const int c = J * GT + e / GT, r = I * GT + e % GT;
+    if (r <= c && c < Np) G[(size_t)c * Np + r] = (float)sum;
+  }
+}
+
+size_t gram_cast_bytes(int64_t m, int64_t n) {
+  const int64_t NT = (n + GT - 1) / GT;
+  // the cast (room for the widest low-precision input, FP32) and the
+  // segment partials of the 16-bit kernel
+  return gram_cast_only_bytes(m, n) + (size_t)gram_segments(m) * (NT * (NT + 1) / 2) * GT * GT * 4;
 }
 
 hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
@@ -679,9 +831,12 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                d, scaled);
     return hipGetLastError();
   }
-  const int mp = ((m + GKC - 1) / GKC) * GKC;
+  const int mp = (int)gram_rows_padded(m);
   const int n128 = NT * GT;
+  const int ntiles = NT * (NT + 1) / 2, nseg = gram_segments(m);
+  float *part = (float *)((char *)cast + gram_cast_only_bytes(m, n));
   const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
+  const dim3 g16((unsigned)ntiles, (unsigned)nseg);
   switch (q) {
     case TLS_FP32:
       TLS_LAUNCH(PC_GRAM, k_cast_dense<float>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (float *)cast);
@@ -689,14 +844,18 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                  (const float *)cast, Np, (float *)G, d, 0);
       break;
     case TLS_FP16:
-      TLS_LAUNCH(PC_GRAM, k_cast_dense<half_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (half_t *)cast);
-      TLS_LAUNCH(PC_GRAM, (k_gram_mfma<half_t, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
-                 (const half_t *)cast, Np, (float *)G, d, 0);
+      TLS_LAUNCH(PC_GRAM, k_cast_blocked<half_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+                 (half_t *)cast);
+      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(256), 0, st, mp, (const half_t *)cast, part, NT);
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+                 (float *)G);
       break;
     default:
-      TLS_LAUNCH(PC_GRAM, k_cast_dense<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (bf16_t *)cast);
-      TLS_LAUNCH(PC_GRAM, (k_gram_mfma<bf16_t, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
-                 (const bf16_t *)cast, Np, (float *)G, d, 0);
+      TLS_LAUNCH(PC_GRAM, k_cast_blocked<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+                 (bf16_t *)cast);
+      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(256), 0, st, mp, (const bf16_t *)cast, part, NT);
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+                 (float *)G);
       break;
   }
   return hipGetLastError();

@@ -19,7 +19,7 @@ def _tls():
 
 
 @pytest.mark.parametrize("u_q", ["fp64", "fp32", "fp16", "bf16"])
-@pytest.mark.parametrize("shape", [(3000, 300), (4097, 129), (300, 64)])
+@pytest.mark.parametrize("shape", [(3000, 300), (4097, 129), (300, 64), (20000, 200)])
 def test_gram_tiles_against_oracle(u_q, shape):
     """Several 128 x 128 Gram tiles, ragged m (partial K chunk) and ragged n
     (partial tile): R^T R of the stored factor against the Gram matrix of the
@@ -36,8 +36,10 @@ def test_gram_tiles_against_oracle(u_q, shape):
         assert np.max(np.abs(Rh - sla.cholesky(H, lower=False))) < 1e-11
         return
     u = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[u_q]
-    # FP32 products, FP32 sums over 32-row chunks folded into FP64, Cholesky in
-    # FP32, factor stored in u_q: the storage rounding dominates
+    # FP32 products; FP32 sums over 32-row chunks folded into FP64 (FP32
+    # inputs) or over 8192-row segments added in FP64 (FP16 / BF16 inputs;
+    # 20000 rows: three segments, the last ragged); Cholesky in FP32, factor
+    # stored in u_q: the storage rounding dominates
     err = np.linalg.norm(Rh.T @ Rh - H, 2) / np.linalg.norm(H, 2)
     assert err < 30 * u, err
     assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
