@@ -155,3 +155,43 @@ def test_qr_solve_reaches_reference(u_q, u_p, kind):
     # is larger (the CSR case: u sigma_1([A,b]) / sigma_{n+1} = 1.2e-7)
     bs, bx = certify.attainable(ref.sigma_1_Ab, ref.sigma, ref.kappa_tls)
     assert es < max(1e-10, 100 * bs) and ex < max(1e-10, 100 * bx)
+
+
+def test_qr_full_size_sparse_workload():
+    """The 20000 x 2000 sparse workload in the configuration bench.py times
+    (FP16 QR factor, FP32 PCGTLS, gate, refinement): properties that hold at
+    any size. Sampled columns of R_hat^T R_hat against A-hat^T A-hat (the
+    oracle's rounding of A D^{-1}, one column of the Gram matrix at a time)
+    within the backward error of Section 3.1; the certificate within
+    1 +- u kappa_F; the solve within 1e-10 of the stored oracle reference."""
+    import json
+    import os
+    tls = _tls()
+    print("qr full size 20000x2000 fp16", flush=True)
+    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+    root = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(root, "golden", "sparse_c2_ref.json")) as f:
+        ref = json.load(f)
+    Ad = tls.from_tlsgen(A)
+    P, rep = tls.tls_factor_precond_qr(Ad, "fp16")
+    Rh, d = tls.tls_precond_export(P)
+    u = U["fp16"]
+    Ah = lowprec.round_to(_dense(A) / d, "fp16")
+    normF2 = float(np.sum(Ah * Ah))
+    for j in (0, 1, 63, 64, 777, 1500, 1999):
+        gj = Ah.T @ Ah[:, j]
+        rj = Rh.T @ Rh[:, j]
+        # each entry of R^T R - A^T A is bounded by 2 gamma ||A||_F^2 with
+        # gamma ~ sqrt(mn) u (probabilistic); measured far inside
+        assert np.max(np.abs(rj - gj)) <= np.sqrt(20000 * 2000) * u * normF2 / 2000, j
+    kF = rep["kappaF_est"]          # ||A D^{-1}||_F / sigma_min, from the gate's Lanczos run
+    print(f"  quality [{rep['quality_lo']:.4f}, {rep['quality_hi']:.4f}] kappa_F {kF:.3g}", flush=True)
+    assert 1 - u * kF <= rep["quality_lo"] and rep["quality_hi"] <= 1 + u * kF, kF
+    opts = tls.default_opts(u_p="fp32", stop_patience=2, kmax=40, gate_enforce=1, allow_escalate=1,
+                            refine_sweeps=1)
+    bd = __import__("torch").as_tensor(b).cuda()
+    x, sigma, st = tls.tls_rqi_solve(Ad, bd, P, opts)
+    es = abs(sigma - ref["sigma"]) / ref["sigma"]
+    ex = np.linalg.norm(x.cpu().numpy() - np.array(ref["x"])) / np.linalg.norm(ref["x"])
+    print(f"  iters {st['iters']} sigma {es:.1e} x {ex:.1e}", flush=True)
+    assert es < 1e-10 and ex < 1e-10
