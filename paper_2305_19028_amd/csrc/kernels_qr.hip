@@ -12,7 +12,7 @@
 // rows [c0, m_pad), c0 = 64 p, cut into 64-row blocks, with a reduction tree
 // of fan-in QR_FAN = 4:
 //  - level 1: a slab of 4 consecutive blocks (256 rows) is factored by one
-//    workgroup, one row per thread, reflector by reflector; its 64 x 64
+//    workgroup, four threads per row, reflector by reflector; its 64 x 64
 //    triangle stays in the slab's first 64 rows and the reflectors
 //    (unit lower trapezoidal Y) are stored below it in the panel columns;
 //  - level l > 1: a slab stacks the triangles of 4 slabs of level l - 1
@@ -33,7 +33,7 @@ namespace tls {
 
 namespace {
 
-constexpr int QR_S = 256;             // rows of a slab = threads of the local kernel
+constexpr int QR_S = 256;             // rows of a slab
 constexpr int QR_FAN = QR_S / NB;     // blocks (or child triangles) per slab
 constexpr int LDP = NB + 1;           // padded LDS row
 
@@ -106,55 +106,64 @@ __global__ void k_qr_pad(int64_t m, int n, int Np, C *W, int64_t ld) {
 // ---------------------------------------------------------------------------
 // local Householder QR of one slab (256 x 64 panel part)
 // ---------------------------------------------------------------------------
-// Thread q owns local row q in registers. For reflector j: the norm of
-// column j below the diagonal (block sum), beta_j = -sign(alpha) ||x||,
-// v = x / (alpha - beta) with v(j) = 1, tau_j = (beta - alpha) / beta (no
-// reflection when the column is already zero below the diagonal); then one
-// reduction over the slab of v_q a_q(c) for all 64 columns c gives both
-// w_c = v^T a(:, c) for the trailing columns c > j and (Y^T Y)(c, j) for the
-// reflectors c < j (their entries sit below the diagonal in the same
-// registers). Columns c > j are updated with a(:, c) -= tau_j v w_c. T is
-// formed at the end from tau and Y^T Y by recursive doubling:
-// T = [T1, -T1 (Y1^T Y2) T2; 0, T2].
+// Four threads share a row: lane = 4 r + g of a wave holds row 16 w + r of
+// the slab (w = wave) and its columns 16 g .. 16 g + 15 in registers. For
+// reflector j: the norm of column j below the diagonal (block sum),
+// beta_j = -sign(alpha) ||x||, v = x / (alpha - beta) with v(j) = 1,
+// tau_j = (beta - alpha) / beta (no reflection when the column is already
+// zero below the diagonal); the owner of column j passes v to the other
+// three lanes of its row. One reduction over the slab of v_q a_q(c) for all
+// 64 columns c (a transposing butterfly over the 16 rows of a wave, then the
+// 16 waves through LDS) gives both w_c = v^T a(:, c) for the trailing
+// columns c > j and (Y^T Y)(c, j) for the reflectors c < j (their entries
+// sit below the diagonal in the same registers). Columns c > j are updated
+// with a(:, c) -= tau_j v w_c. T is formed at the end from tau and Y^T Y by
+// recursive doubling: T = [T1, -T1 (Y1^T Y2) T2; 0, T2].
+constexpr int QR_LT = 4 * QR_S;                 // threads of the local kernel
+constexpr int QR_LW = QR_LT / 64;               // its waves
 template <typename C>
-__global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpad, int64_t c0, int64_t lpow,
-                                                   int upper_only, C *Tbuf, int uq) {
-  __shared__ C red[2][QR_S / 64];
+__global__ __launch_bounds__(QR_LT) void k_qr_local(C *W, int64_t ld, int64_t mpad, int64_t c0, int64_t lpow,
+                                                    int upper_only, C *Tbuf, int uq) {
+  constexpr int CG = NB / 4;                    // columns per lane
+  __shared__ C red[2][QR_LW];
   __shared__ C alpha_s[2];
-  __shared__ C part[2][QR_S / 64][NB];
+  __shared__ C part[2][QR_LW][NB];
   __shared__ C wsum[2][NB];
   __shared__ C Zs[NB][LDP];
   __shared__ C Ts[NB][LDP];
   __shared__ C Ms[NB][LDP];
   __shared__ C tau_s[NB];
-  const int q = threadIdx.x, lane = q & 63, wv = q >> 6;
-  const int g = blockIdx.x;
-  const int64_t row = qr_row(c0, lpow, g, q);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = lane & 3, q = wv * 16 + (lane >> 2);      // column group, slab row
+  const int g0 = g * CG;
+  const int64_t row = qr_row(c0, lpow, blockIdx.x, q);
   const bool valid = row < mpad;
   const int t = q & 63;
-  C a[NB];
+  C a[CG];
   {
-    const C *src = W + row * ld + c0;
+    const C *src = W + row * ld + c0 + g0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    for (int c = 0; c < CG; ++c) {
       C v = valid ? src[c] : (C)0;
-      if (upper_only && t > c) v = (C)0;
+      if (upper_only && t > g0 + c) v = (C)0;
       a[c] = v;
     }
   }
 #pragma unroll 1
   for (int j = 0; j < NB; ++j) {
-    const int buf = j & 1;
-    C x = (C)0;
+    const int buf = j & 1, gj = j / CG, cj = j % CG;
+    const bool owner = (g == gj);
+    C xs = (C)0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) x = (c == j) ? a[c] : x;
+    for (int c = 0; c < CG; ++c) xs = (c == cj) ? a[c] : xs;
+    const C x = owner ? xs : (C)0;
     C s = wave_sum((q > j) ? x * x : (C)0);
     if (lane == 0) red[buf][wv] = s;
-    if (q == j) alpha_s[buf] = x;
+    if (owner && q == j) alpha_s[buf] = x;
     __syncthreads();
     s = red[buf][0];
 #pragma unroll
-    for (int w = 1; w < QR_S / 64; ++w) s += red[buf][w];
+    for (int w = 1; w < QR_LW; ++w) s += red[buf][w];
     const C alpha = alpha_s[buf];
     C beta = alpha, tau = (C)0, scl = (C)0;
     if (s > (C)0) {
@@ -163,68 +172,68 @@ __global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpa
       tau = (beta - alpha) / beta;
       scl = (C)1 / (alpha - beta);
     }
-    const C v = (q > j) ? x * scl : ((q == j) ? (C)1 : (C)0);
-    // p[c] = v_q a_q(c), summed over the wave by a transposing butterfly:
-    // after it lane L holds the wave's sum for column L
-    C p[NB];
+    const C vown = (q > j) ? x * scl : ((q == j) ? (C)1 : (C)0);
+    const C v = __shfl(vown, (lane & ~3) | gj, 64);
+    // p[c] = v_q a_q(g0 + c), summed over the wave's 16 rows by a
+    // transposing butterfly: afterwards lane 4 r + g holds the sum for
+    // column g0 + r
+    C p[CG];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) p[c] = v * a[c];
-#define QR_BFLY(H)                                                   \
+    for (int c = 0; c < CG; ++c) p[c] = v * a[c];
+#define QR_BFLY(H, M)                                                \
   {                                                                  \
-    const bool hi = (lane & (H)) != 0;                               \
+    const bool hi = (lane & (M)) != 0;                               \
     _Pragma("unroll") for (int i = 0; i < (H); ++i) {                \
       const C mine = hi ? p[(H) + i] : p[i];                         \
       const C other = hi ? p[i] : p[(H) + i];                        \
-      p[i] = mine + __shfl_xor(other, (H), 64);                      \
+      p[i] = mine + __shfl_xor(other, (M), 64);                      \
     }                                                                \
   }
-    QR_BFLY(32) QR_BFLY(16) QR_BFLY(8) QR_BFLY(4) QR_BFLY(2) QR_BFLY(1)
+    QR_BFLY(8, 32) QR_BFLY(4, 16) QR_BFLY(2, 8) QR_BFLY(1, 4)
 #undef QR_BFLY
-    part[buf][wv][lane] = p[0];
+    part[buf][wv][g0 + (lane >> 2)] = p[0];
     __syncthreads();
-    if (q < NB) {
-      C w = part[buf][0][q];
+    if (tid < NB) {
+      C w = part[buf][0][tid];
 #pragma unroll
-      for (int k = 1; k < QR_S / 64; ++k) w += part[buf][k][q];
-      wsum[buf][q] = (q > j) ? w : (C)0;    // zero where no update applies
-      if (q < j) Zs[q][j] = w;
+      for (int k = 1; k < QR_LW; ++k) w += part[buf][k][tid];
+      wsum[buf][tid] = (tid > j) ? w : (C)0;    // zero where no update applies
+      if (tid < j) Zs[tid][j] = w;
     }
-    if (q == 0) tau_s[j] = tau;
+    if (tid == 0) tau_s[j] = tau;
     __syncthreads();
-    // all 64 values first (independent LDS reads), then a branch-free update:
-    // a(c) - tau v 0 = a(c) for the columns c <= j
-    C ws[NB];
+    C ws[CG];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) ws[c] = wsum[buf][c];
+    for (int c = 0; c < CG; ++c) ws[c] = wsum[buf][g0 + c];
     const C tv = tau * v;
-    const C keep = (q >= j) ? ((q == j) ? beta : v) : x;   // new entry of column j
+    const C keep = (q >= j) ? ((q == j) ? beta : v) : xs;   // new entry of column j (owner lanes)
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] -= tv * ws[c];
+    for (int c = 0; c < CG; ++c) a[c] -= tv * ws[c];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = (c == j) ? keep : a[c];
+    for (int c = 0; c < CG; ++c) a[c] = (owner && c == cj) ? keep : a[c];
   }
   // the slab's triangle and reflectors, rounded to u_q
   if (valid) {
-    C *dst = W + row * ld + c0;
+    C *dst = W + row * ld + c0 + g0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) dst[c] = store_q(a[c], uq);
+    for (int c = 0; c < CG; ++c) dst[c] = store_q(a[c], uq);
   }
   // T by recursive doubling over blocks of b = 1, 2, 4, ..., 32 reflectors
-  for (int e = q; e < NB * NB; e += QR_S) {
+  for (int e = tid; e < NB * NB; e += QR_LT) {
     const int r = e / NB, c = e % NB;
     Ts[r][c] = (r == c) ? tau_s[r] : (C)0;
   }
   for (int b = 1; b < NB; b <<= 1) {
     __syncthreads();
     const int per = b * b, total = (NB / (2 * b)) * per;
-    for (int e = q; e < total; e += QR_S) {          // M = (Y1^T Y2) T2
+    for (int e = tid; e < total; e += QR_LT) {       // M = (Y1^T Y2) T2
       const int pr = e / per, r = (e % per) / b, cc = e % b, o = 2 * b * pr;
       C acc = (C)0;
       for (int k = 0; k <= cc; ++k) acc += Zs[o + r][o + b + k] * Ts[o + b + k][o + b + cc];
       Ms[o + r][o + b + cc] = acc;
     }
     __syncthreads();
-    for (int e = q; e < total; e += QR_S) {          // T12 = -T1 M
+    for (int e = tid; e < total; e += QR_LT) {       // T12 = -T1 M
       const int pr = e / per, r = (e % per) / b, cc = e % b, o = 2 * b * pr;
       C acc = (C)0;
       for (int k = r; k < b; ++k) acc += Ts[o + r][o + k] * Ms[o + k][o + b + cc];
@@ -232,8 +241,8 @@ __global__ __launch_bounds__(QR_S) void k_qr_local(C *W, int64_t ld, int64_t mpa
     }
   }
   __syncthreads();
-  C *T = Tbuf + (size_t)g * NB * NB;
-  for (int e = q; e < NB * NB; e += QR_S) T[e] = Ts[e / NB][e % NB];
+  C *T = Tbuf + (size_t)blockIdx.x * NB * NB;
+  for (int e = tid; e < NB * NB; e += QR_LT) T[e] = Ts[e / NB][e % NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -447,7 +456,7 @@ hipError_t qr_t(int64_t m, int n, int Np, int format, int64_t ldA, const double 
     int64_t units = (mpad - c0 + NB - 1) / NB, lpow = 1;
     for (int level = 1;; ++level) {
       const int64_t slabs = (units + QR_FAN - 1) / QR_FAN;
-      TLS_LAUNCH(PC_QR, k_qr_local<C>, dim3((unsigned)slabs), dim3(QR_S), 0, st, W, ld, mpad, c0, lpow,
+      TLS_LAUNCH(PC_QR, k_qr_local<C>, dim3((unsigned)slabs), dim3(QR_LT), 0, st, W, ld, mpad, c0, lpow,
                  level > 1 ? 1 : 0, T, uq);
       if (p + 1 < N)
         TLS_LAUNCH(PC_QR, k_qr_apply<C>, dim3((unsigned)slabs, N - p - 1), dim3(256), 0, st, W, ld, mpad, c0,
