@@ -35,7 +35,7 @@ __device__ inline double dense_row_part(int n, int64_t ld, const double *a, cons
   int j = RD_CHUNK * w;
   for (; j + RD_CHUNK <= n; j += RD_CHUNK * RD_WAVES) {
 #pragma unroll
-    for (int q = 0; q < RD_CHUNK; ++q) c[q] += a[(size_t)(j + q) * ld] * x[j + q];
+    for (int q = 0; q < RD_CHUNK; ++q) c[q] += __builtin_nontemporal_load(a + (size_t)(j + q) * ld) * x[j + q];
   }
 #pragma unroll
   for (int q = 0; q < RD_CHUNK; ++q)
@@ -134,17 +134,16 @@ __global__ void k_matvec_csr(int m, const int32_t *row_ptr, const int32_t *col_i
 __global__ void k_rmatvec_dense(int m, int n, int64_t ld, const double *A, const double *x, double *y) {
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= n) return;
+  // as in k_gradient: eight 512-byte loads in flight, A streamed once
   const double *col = A + (size_t)j * ld;
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int i = lane;
-  for (; i + 192 < m; i += 256) {
-    a0 += col[i] * x[i];
-    a1 += col[i + 64] * x[i + 64];
-    a2 += col[i + 128] * x[i + 128];
-    a3 += col[i + 192] * x[i + 192];
+  for (; i + 448 < m; i += 512) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += __builtin_nontemporal_load(col + i + 64 * u) * x[i + 64 * u];
   }
-  for (; i < m; i += 64) a0 += col[i] * x[i];
-  const double acc = wave_sum((a0 + a1) + (a2 + a3));
+  for (; i < m; i += 64) s[0] += col[i] * x[i];
+  const double acc = wave_sum(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
   if (lane == 0) y[j] = acc;
 }
 __global__ void k_rmatvec_csc(int n, const int32_t *col_ptr, const int32_t *row_idx,
@@ -221,17 +220,17 @@ __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, cons
     if (CSC) {
       for (int e = col_ptr[j] + lane; e < col_ptr[j + 1]; e += 64) acc += cval[e] * r[row_idx[e]];
     } else {
+      // eight independent 512-byte loads of the column in flight per wave;
+      // A is streamed once (non-temporal), r is reused by every column
       const double *col = A + (size_t)j * ld;
       int i = lane;
-      double a1 = 0, a2 = 0, a3 = 0;
-      for (; i + 192 < m; i += 256) {
-        acc += col[i] * r[i];
-        a1 += col[i + 64] * r[i + 64];
-        a2 += col[i + 128] * r[i + 128];
-        a3 += col[i + 192] * r[i + 192];
+      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (; i + 448 < m; i += 512) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += __builtin_nontemporal_load(col + i + 64 * u) * r[i + 64 * u];
       }
-      for (; i < m; i += 64) acc += col[i] * r[i];
-      acc = (acc + a1) + (a2 + a3);
+      for (; i < m; i += 64) s[0] += col[i] * r[i];
+      acc = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
     acc = wave_sum(acc);
     xv = x[j];
