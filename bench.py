@@ -253,9 +253,6 @@ def class_work(cls, path, m, n, nnz, launches):
         # update of step k): the factorization's n_p^3/3 flops over its N launches
         Npad = N * NB
         return alu, Npad ** 3 / 3 * launches / N, "Cholesky n_p^3/3 flops over its N step launches"
-    if cls == "chol_update":
-        fl = sum((N - k - 1) * (N - k) / 2 * 2 * NB ** 3 for k in range(N))
-        return alu, fl * launches / max(N - 1, 1), "2 n_b^3 per trailing tile pair"
     if cls == "invert":
         return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches"
     dense = nnz == m * n

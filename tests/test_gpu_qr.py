@@ -195,3 +195,26 @@ def test_qr_full_size_sparse_workload():
     ex = np.linalg.norm(x.cpu().numpy() - np.array(ref["x"])) / np.linalg.norm(ref["x"])
     print(f"  iters {st['iters']} sigma {es:.1e} x {ex:.1e}", flush=True)
     assert es < 1e-10 and ex < 1e-10
+
+
+def test_qr_failure_statuses():
+    """A zero column makes R singular: TLS_ERR_NOT_SPD from the pivot check,
+    scaled (0/0 in A D^{-1}) and unscaled (an exactly zero pivot); with
+    escalation the FP16 request climbs to FP64 and still fails. NaN in A is
+    rejected before any factorization (TLS_ERR_NONFINITE)."""
+    tls = _tls()
+    A, _, _ = tlsgen.dense_gaussian(300, 70, seed=17)
+    A3 = A.copy()
+    A3[:, 33] = 0.0
+    for scaling in (False, True):
+        with pytest.raises(tls.TLSError) as e:
+            tls.tls_factor_precond_qr(tls.dense(A3), "fp64", scaling=scaling)
+        assert e.value.status == -3
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_factor_precond_qr(tls.dense(A3), "fp16", allow_escalate=True)
+    assert e.value.status == -3
+    A2 = A.copy()
+    A2[5, 6] = np.nan
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_factor_precond_qr(tls.dense(A2), "fp32")
+    assert e.value.status == -9
