@@ -1,7 +1,8 @@
 """Write the stored reference answers used by the benchmark and the
 full-size GPU tests. Calls only the oracle and the seeded generators.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            # the workloads
+    python tests/golden/make_golden.py examples   # the paper's five problems
 
 For each workload: the plain float64 RQI-PCGTLS of the oracle (Algorithms
 2 and 3), its Rayleigh quotient re-evaluated in long double, Newton
@@ -49,7 +50,30 @@ def reference(name):
     }
 
 
+# the five problems of Section 4, answered in extended precision (50-digit
+# mpmath eigen-decomposition of [A, b]^T [A, b]) for the error curves
+EXAMPLES = ["paper_random", "paper_delta", "paper_toeplitz", "paper_vanhuffel", "paper_bjorck"]
+
+
+def examples():
+    from oracle import exact
+    out = {}
+    for gen in EXAMPLES:
+        A, b = getattr(tlsgen, gen)()[:2]
+        t0 = time.time()
+        r = exact.mp_svd_tls(A, b)
+        out[gen] = {"sigma": float(r.sigma), "x": [float(v) for v in r.x],
+                    "sigma_1_Ab": float(r.sigma_1_Ab), "kappa_tls": float(r.kappa_tls),
+                    "seconds": time.time() - t0}
+        print(gen, "sigma", out[gen]["sigma"], f"{out[gen]['seconds']:.1f}s", flush=True)
+    with open(os.path.join(HERE, "paper_examples_mp.json"), "w") as f:
+        json.dump(out, f, indent=0)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "examples":
+        examples()
+        return
     for name in WORKLOADS:
         ref = reference(name)
         path = os.path.join(HERE, f"{name}_ref.json")
