@@ -98,6 +98,7 @@ hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval
 hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
                                  hipStream_t st);
 // scaling vectors: dinv = 1/d (or ones when unscaled), both precisions, padded to Np
+hipError_t launch_dstats(int n, const double *d, double *out, hipStream_t st);
 hipError_t launch_scale_vectors(int n, int Np, const double *d, int scaled, double *dsc64,
                                 float *dsc32, hipStream_t st);
 // quantised scaled values (CSR and CSC arrays): out = round_q(val / d[col]) as compute type

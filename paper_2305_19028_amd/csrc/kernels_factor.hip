@@ -198,6 +198,48 @@ hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
 }
 
 // --------------------------------------------------------------------------
+// statistics of the column norms for the solve (one workgroup, fixed order):
+// out = {sum d_j^2, min, max, mean, std of ln max(d_j, 1e-300)}
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dstats(int n, const double *d, double *out) {
+  __shared__ double sc[8];
+  __shared__ double ext[2][4];
+  double s2 = 0, sl = 0, sq = 0, lo = INFINITY, hi = -INFINITY;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double v = d[j], l = log(fmax(v, 1e-300));
+    s2 += v * v;
+    sl += l;
+    sq += l * l;
+    lo = fmin(lo, l);
+    hi = fmax(hi, l);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { ext[0][w] = lo; ext[1][w] = hi; }
+  s2 = block_sum(s2, sc);
+  sl = block_sum(sl, sc + 4);
+  sq = block_sum(sq, sc);
+  if (threadIdx.x == 0) {
+    lo = fmin(fmin(ext[0][0], ext[0][1]), fmin(ext[0][2], ext[0][3]));
+    hi = fmax(fmax(ext[1][0], ext[1][1]), fmax(ext[1][2], ext[1][3]));
+    const double mean = sl / n;
+    out[0] = s2;
+    out[1] = lo;
+    out[2] = hi;
+    out[3] = mean;
+    out[4] = sqrt(fmax(0.0, sq / n - mean * mean));
+  }
+}
+hipError_t launch_dstats(int n, const double *d, double *out, hipStream_t st) {
+  TLS_LAUNCH(PC_SETUP, k_dstats, dim3(1), dim3(256), 0, st, n, d, out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // column norms d_j = ||A e_j|| (one wave per column, fixed order)
 // --------------------------------------------------------------------------
 __global__ void k_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d) {

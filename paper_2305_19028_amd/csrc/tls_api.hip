@@ -200,6 +200,7 @@ struct FactorWs {
   double *lz;      // Lanczos vectors
   double *lzs;     // Lanczos scalars
   int *flag;
+  double *dstats;  // column-norm statistics for the solve (k_dstats)
   void *xr, *xc;   // explicit inverse tiles (FP64-sized)
   double *yinv;    // inversion scratch
   int *cnt;        // per-block arrival counters of internal applies
@@ -233,12 +234,18 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     W.valq = c.take<char>(nnz * 8);
     W.cvalq = c.take<char>(nnz * 8);
   }
-  W.info = c.take<int>(4);
+  {
+    // one status block, read back in one copy: breakdown info, the
+    // finite-input flag and the column statistics
+    char *stat = c.take<char>(128);
+    W.info = (int *)stat;
+    W.flag = (int *)(stat + 16);
+    W.dstats = (double *)(stat + 32);
+  }
   W.sync = c.take<int>(N + 8);
   W.rdiag = c.take<double>((size_t)N * NB * NB);
   W.lz = c.take<double>((size_t)(2 * (LANCZOS_STEPS + 1) + 9) * Np);
   W.lzs = c.take<double>(4 * LANCZOS_STEPS + 8);
-  W.flag = c.take<int>(4);
   W.xr = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
   W.xc = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
   W.yinv = c.take<double>(std::max(invert_scratch_doubles(N),
@@ -894,28 +901,61 @@ tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, hip
   return TLS_OK;
 }
 
+// wait for gate runs started on a factor that turned out broken
+void gate_drain(tls_precond_s *P) {
+  if (P->gate_pending) {
+    (void)hipStreamSynchronize(P->side);
+    P->gate_pending = 0;
+  }
+}
+
+// the one read-back of a factorization (synchronizes the stream): breakdown
+// info, then the finite-input flag (NaN or Inf in A takes precedence) and the
+// column statistics
+tls_status read_factor_status(tls_precond_s *P, const FactorWs &W, hipStream_t st, int *info) {
+  alignas(8) char stat[72];
+  HIPCHK(hipMemcpyAsync(stat, W.info, sizeof(stat), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int flag = 0;
+  double ds[5];
+  std::memcpy(info, stat, sizeof(int));
+  std::memcpy(&flag, stat + 16, sizeof(int));
+  std::memcpy(ds, stat + 32, sizeof(ds));
+  if (flag) return fail(TLS_ERR_NONFINITE, "A contains NaN or Inf");
+  P->normA_F2 = ds[0];
+  for (int i = 0; i < 4; ++i) P->lnd[i] = ds[1 + i];
+  return TLS_OK;
+}
+
 // R_hat from the Householder QR of the scaled, u_q-rounded A (Section 3)
 tls_status factor_qr_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq, hipStream_t st,
-                          int *breakdown) {
+                          int *breakdown, const MatView *gate) {
   const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
   *breakdown = 0;
   if (!W.qrw) return fail(TLS_ERR_WORKSPACE, "factor workspace was not sized for QR");
   HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
   HIPCHK(launch_qr_factor(A->m, (int)A->n, P->Np, A->format, A->ld, A->val, A->row_ptr, A->col_idx, W.d,
                           P->scaled, uq, compute, W.qrw, W.G, W.info, st));
+  TRY(finish_factor(P, W, uq, compute, st));      // enqueued before the pivot check
+  if (gate) TRY(gate_start(P, W, *gate, st));
   int info = 0;
-  HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  const tls_status rs = read_factor_status(P, W, st, &info);
+  if (rs != TLS_OK || info != INT32_MAX) gate_drain(P);
+  if (rs != TLS_OK) return rs;
   if (info != INT32_MAX) {
     *breakdown = info;
     return fail(TLS_ERR_NOT_SPD, "QR: zero or non-finite pivot at column %d", info - 1);
   }
-  return finish_factor(P, W, uq, compute, st);
+  return TLS_OK;
 }
 
+// gate != NULL: the gate's runs on the new factor are started before the
+// breakdown flag is read, so that their enqueueing overlaps the factor's last
+// kernels; after a breakdown they are drained and started again with the
+// next attempt
 tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
-                       hipStream_t st, int *breakdown) {
-  if (P->method == 1) return factor_qr_once(A, P, W, uq, st, breakdown);
+                       hipStream_t st, int *breakdown, const MatView *gate) {
+  if (P->method == 1) return factor_qr_once(A, P, W, uq, st, breakdown, gate);
   const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
   const int n = (int)A->n;
   *breakdown = 0;
@@ -930,10 +970,16 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
     }
     HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
     HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.rdiag, W.info, st));
+    // packing, diagonal inverses and the explicit inverse are enqueued before
+    // the breakdown flag is read (one synchronization); after a breakdown the
+    // next attempt redoes them
+    TRY(finish_factor(P, W, uq, compute, st));
+    if (gate) TRY(gate_start(P, W, *gate, st));
     int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (info == INT32_MAX) return finish_factor(P, W, uq, compute, st);
+    const tls_status rs = read_factor_status(P, W, st, &info);
+    if (rs != TLS_OK || info != INT32_MAX) gate_drain(P);
+    if (rs != TLS_OK) return rs;
+    if (info == INT32_MAX) return TLS_OK;
     *breakdown = info;
     if (!P->scaled) break;   // the shift ladder is defined for the scaled matrix
   }
@@ -1005,37 +1051,22 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       HIPCHK(launch_colnorms_dense((int)A->m, n, A->ld, A->val, W.d, stream));
     }
     HIPCHK(launch_scale_vectors(n, P->Np, W.d, P->scaled, W.dsc64, W.dsc32, stream));
-    int flag = 0;
-    std::vector<double> dh(n);
-    HIPCHK(hipMemcpyAsync(&flag, W.flag, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(dh.data(), W.d, n * sizeof(double), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    if (flag) return fail(TLS_ERR_NONFINITE, "A contains NaN or Inf");
-    for (double v : dh) P->normA_F2 += v * v;
-    {
-      double lo = INFINITY, hi = -INFINITY, sum = 0, sq = 0;
-      for (double v : dh) {
-        const double l = std::log(std::max(v, 1e-300));
-        lo = std::min(lo, l); hi = std::max(hi, l); sum += l; sq += l * l;
-      }
-      const double mean = sum / n;
-      P->lnd[0] = lo; P->lnd[1] = hi; P->lnd[2] = mean;
-      P->lnd[3] = std::sqrt(std::max(0.0, sq / n - mean * mean));
-    }
+    // ||A||_F^2 and the statistics of ln d_j for the solve; they and the
+    // finite-input flag come back with the factorization's breakdown flag
+    // (read_factor_status), so no synchronization precedes the factorization
+    HIPCHK(launch_dstats(n, W.d, W.dstats, stream));
     int uq = u_q;
     for (;;) {
       int bd = 0;
-      tls_status s = factor_once(A, P, W, uq, stream, &bd);
+      const MatView gv = make_view(A, P);
+      tls_status s = factor_once(A, P, W, uq, stream, &bd, uq != TLS_FP64 ? &gv : nullptr);
       if (s == TLS_OK) {
         P->rep.u_q = unit_roundoff(uq);
         // a low-precision factor is kept here even where the A-only
         // constraints fail: the decision belongs to the certificate, read in
         // the solve (which escalates if asked to); with rep == NULL the two
         // Lanczos runs finish in the background
-        if (uq != TLS_FP64) {
-          TRY(gate_start(P, W, make_view(A, P), stream));
-          if (rep) TRY(gate_finish(P));
-        }
+        if (uq != TLS_FP64 && rep) TRY(gate_finish(P));   // started by factor_once
         break;
       }
       if (s != TLS_ERR_NOT_SPD || !allow_escalate || uq == TLS_FP64) return s;
@@ -1520,9 +1551,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       FactorWs FW = factor_ws_of(P);
       int bd = 0;
       TRY(gate_finish(P));   // its runs read the factor that is replaced now
-      TRY(factor_once(A, P, FW, next, st, &bd));
-      P->have_kappa = P->have_sigma_n = P->have_quality = 0;
-      if (next != TLS_FP64) TRY(gate_start(P, FW, V, st));
+      TRY(factor_once(A, P, FW, next, st, &bd, next != TLS_FP64 ? &V : nullptr));
+      if (next == TLS_FP64) P->have_kappa = P->have_sigma_n = P->have_quality = 0;
       R.escalations++;
       R.used = P->storage;
       S.t_factor_ms += ms_since(tf);
