@@ -1273,7 +1273,7 @@ RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s
   W.t1 = c.take<double>(n);
   W.t2 = c.take<double>(n);
   W.part = c.take<double>(4 * (size_t)nb);   // residual and gradient partials
-  W.scal = c.take<double>(48);
+  W.scal = c.take<double>(64);
   W.rec = c.take<double>(4 * (size_t)(kmax + 8));
   W.rr = c.take<double>(2 * n);
   W.rz = c.take<double>(2 * n);
@@ -1475,7 +1475,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
 
     // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1; the b-dependent gate ---
     double rr0 = 0.0;
-    bool spec = false;
+    bool spec = false, ls_deferred = false;
     for (;;) {
       HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
       if (o->mlp_theta || o->sigma0_hint > 0 || o->features) {
@@ -1514,6 +1514,19 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       }
       HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
+      // nothing before the first psi read-back needs sigma_0 on the host
+      // unless a warm start, the shift clamp or a waiting gate does: then
+      // sigma_0 and the finite-b flag come back with that read-back (the
+      // scalars saved at scal[48..52]) instead of in a synchronization of
+      // their own
+      const bool gated = o->gate_enforce && P->storage != TLS_FP64;
+      ls_deferred = !o->mlp_theta && !(o->sigma0_hint > 0) && !o->features && !o->shift_clamp &&
+                    !accurate_ls && (!gated || P->gate_pending);
+      if (ls_deferred) {
+        HIPCHK(launch_copy_f64(W.scal + 48, W.scal, 5, st));
+        spec = gated;
+        break;
+      }
       double h2[5];
       HIPCHK(hipMemcpyAsync(h2, W.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(&bad_b, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1521,7 +1534,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       if (bad_b) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
       S.sigma_ls = std::sqrt(h2[0]);
       rr0 = h2[3];
-      if (!(o->gate_enforce && P->storage != TLS_FP64)) break;
+      if (!gated) break;
       // constraint (6) with sigma_{n+1} <= sigma_0 and the Lanczos estimates,
       // and the a-posteriori certificate of the factor itself (the estimates
       // come from the factor and cannot reveal that it is poor)
@@ -1653,12 +1666,19 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       double best = std::numeric_limits<double>::infinity();
       int no_improve = 0, k = 0;
       S.stopped = 1;
-      double h[16];
+      double h[64];
       for (k = 1; k <= kmax; ++k) {
         TRY(evaluate(k, cap));
         if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
-        HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+        const bool first = ls_deferred && k == 1;
+        HIPCHK(hipMemcpyAsync(h, W.scal, (first ? 64 : 16) * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (first) HIPCHK(hipMemcpyAsync(&bad_b, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (first) {
+          if (bad_b) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
+          S.sigma_ls = std::sqrt(h[48]);
+          rr0 = h[51];
+        }
         const double psi = h[7], sig2 = h[0];
         S.iters = k;
         S.psi[k - 1] = psi;
