@@ -16,10 +16,13 @@
  *  - The caller owns all device memory: matrices, vectors and workspaces.
  *    The library never allocates device memory. Workspace sizes come from
  *    the *_workspace_size queries; workspaces must be 256-byte aligned.
- *  - Work is enqueued on the given stream. tls_factor_precond and
- *    tls_rqi_solve synchronize that stream internally (to read the gate
- *    estimates and the per-iteration psi of eq. (4)); tls_pcg_step and
- *    tls_apply_precond are asynchronous unless a host trace is requested.
+ *  - Work is enqueued on the given stream. tls_factor_precond synchronizes
+ *    it once per factorization attempt (breakdown and finite-input flags),
+ *    and waits for the gate's runs only when a report is requested;
+ *    tls_rqi_solve synchronizes it once per outer iteration (psi of eq. (4))
+ *    and at the few decisions that need a value on the host; tls_pcg_step
+ *    and tls_apply_precond are asynchronous unless a host trace is
+ *    requested.
  *  - Every call returns a tls_status; no C++ exception crosses the ABI;
  *    tls_last_error() returns a thread-local message for the last failure.
  *  - Results are deterministic: reductions use a fixed order, so repeated
