@@ -129,8 +129,10 @@ size_t qr_work_bytes(int64_t m, int n);
 hipError_t launch_qr_factor(int64_t m, int n, int Np, int format, int64_t ldA, const double *val,
                             const int32_t *row_ptr, const int32_t *col_idx, const double *d, int scaled, int uq,
                             int compute, void *work, void *G, int *info, hipStream_t st);
-hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
-                             hipStream_t st);
+// upper tiles of R into tiles of the storage precision; the diagonal tiles
+// from rdiag (as the Cholesky steps leave them) or, when rdiag is NULL, from G
+hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, const void *rdiag, int storage,
+                             void *tiles, hipStream_t st);
 hipError_t launch_diag_inverse(int N, int storage, const void *tiles, double *dinv64,
                                float *dinv32, hipStream_t st);
 hipError_t launch_import_tiles(int n, int N, int Np, const double *R, int storage, void *tiles,

@@ -8,6 +8,7 @@
 // column-major with only its upper triangle meaningful; Cholesky overwrites
 // it with R (G = R^T R). Padding rows/columns n..Np-1 hold the identity.
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 #include "kernels.h"
@@ -1035,23 +1036,52 @@ __device__ inline void tile_product_t_index(At at) {
   }
 }
 
-// a 64x64 tile at (row block I, column block J) of G into registers (16
-// values per thread, all loads in flight before the first wait), then LDS
+// a 64x64 tile at (row block I, column block J) of G into registers
+// (NB * NB / THR values per thread), and from there into LDS. The two halves
+// are separate so that a workgroup can put all of its global loads in flight
+// before the first wait.
 template <int THR, typename C>
-__device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB + 1]) {
-  constexpr int Q = NB * NB / THR;
-  C tmp[Q];
+__device__ inline void tile_fetch(const C *G, int Np, int I, int J, C (&tmp)[NB * NB / THR]) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < NB * NB / THR; ++q) {
     const int t = tid + THR * q;
     tmp[q] = G[((size_t)J * NB + t / NB) * Np + (size_t)I * NB + t % NB];
   }
+}
+template <int THR, typename C>
+__device__ inline void tile_put(const C (&tmp)[NB * NB / THR], C (*dst)[NB + 1]) {
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < NB * NB / THR; ++q) {
     const int t = tid + THR * q;
     dst[t % NB][t / NB] = tmp[q];
   }
+}
+template <int THR, typename C>
+__device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB + 1]) {
+  C tmp[NB * NB / THR];
+  tile_fetch<THR>(G, Np, I, J, tmp);
+  tile_put<THR>(tmp, dst);
+}
+
+// four consecutive entries of a column (16-byte aligned for float, 32 for double)
+__device__ inline void store_col4(float *p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, d);
+}
+__device__ inline void store_col4(double *p, double a, double b, double c, double d) {
+  reinterpret_cast<double2 *>(p)[0] = make_double2(a, b);
+  reinterpret_cast<double2 *>(p)[1] = make_double2(c, d);
+}
+
+// the value v holds in lane src of the wave (src the same for all active lanes)
+__device__ inline float read_lane(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double read_lane(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 // One step of the blocked right-looking Cholesky (upper, G = R^T R, 64x64
@@ -1070,25 +1100,28 @@ __device__ inline void tile_to_lds(const C *G, int Np, int I, int J, C (*dst)[NB
 // and the chain of dependent launches is one per block row. The first
 // launch (not FUSED) is the panel of block row 0 alone.
 // Panel elimination: thread (tr, tc) holds the 4x4 register blocks of rows
-// 4tr.. and columns 4tc.. of both tiles; the 16 threads of one row group are
-// a quarter wave. The 64 columns are taken four at a time. For group g the
-// owning quarter wave gathers the 4x4 diagonal block by cross-lane
-// shuffles, factors it (redundantly in each lane, so all lanes agree bit
-// for bit), turns its four rows into rows of R and publishes them in a
-// double-buffered LDS slab; after one barrier the rows below take the
-// rank-4 update. One barrier per four columns; the finished rows are staged
-// in LDS and written coalesced.
+// 4tr.. and columns 4tc.. of both tiles; the 32 threads of one row group (16
+// per tile) are half a wave. The 64 columns are taken four at a time. For
+// group g the owning half wave reads the 4x4 diagonal block from the
+// registers of the lane that holds it, factors it (redundantly in each lane,
+// so all lanes agree bit for bit), turns its four rows into rows of R and
+// publishes them in a double-buffered LDS slab; after one barrier the rows
+// below take the rank-4 update. One barrier per four columns; a failed pivot
+// is checked once, after the last group (the rows already written are then
+// of no use: the factorization is reported as failed). Each owning lane
+// writes its finished rows straight to memory as pieces of four column
+// entries, so no output tile is staged.
 // R(p,p) goes to rdiag (tile p, column-major), not to G: the other panel
-// workgroups of the launch still read G(p,p). k_chol_restore copies the
-// diagonal tiles back at the end.
+// workgroups of the launch still read G(p,p). The packing kernel takes the
+// diagonal tiles from rdiag.
 constexpr int CHOL_THREADS = 512;
 template <typename C, bool FUSED>
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np, C *G, C *rdiag, int *info) {
   constexpr int THR = CHOL_THREADS;
-  __shared__ C ta[NB][NB + 1];     // R(k, .) operand / staged G(p,p) / output tile
+  __shared__ C ta[NB][NB + 1];     // R(k, .) operand / staged G(p,p)
   __shared__ C tb[NB][NB + 1];     // R(k, .) operand / staged G(p,p+j)
   __shared__ C slab[2][4][2 * NB];
-  __shared__ int bad_s[2];   // per slab buffer, so a flag is never rewritten while still being read
+  __shared__ int bad_s;      // first failed pivot of the tile (1-based), INT_MAX while none
   const int tid = threadIdx.x;
   const int p = FUSED ? k + 1 : k;
   if (FUSED && (int)blockIdx.x >= N - p) {
@@ -1098,13 +1131,21 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
     while ((bq + 1) * (bq + 2) / 2 <= l) ++bq;
     while (bq * (bq + 1) / 2 > l) --bq;
     const int i = k + 2 + (l - bq * (bq + 1) / 2), j = k + 2 + bq;
-    tile_to_lds<THR>(G, Np, k, i, ta);
-    tile_to_lds<THR>(G, Np, k, j, tb);
+    // the two R tiles and this thread's entries of G(i,j) in flight together
+    C ri[NB * NB / THR], rj[NB * NB / THR], gv[16];
+    tile_fetch<THR>(G, Np, k, i, ri);
+    tile_fetch<THR>(G, Np, k, j, rj);
+    C *Gij = G + (size_t)j * NB * Np + (size_t)i * NB;
+    int nn = 0;
+    if (tid < 256) tile_product_t_index<C>([&](int r, int c) { gv[nn++] = Gij[(size_t)c * Np + r]; });
+    tile_put<THR>(ri, ta);
+    tile_put<THR>(rj, tb);
     __syncthreads();
     if (tid >= 256) return;   // one group of four waves takes the product
-    C *Gij = G + (size_t)j * NB * Np + (size_t)i * NB;
+    nn = 0;
     tile_product_t<C>(ta, tb, [&](int r, int c, C v) {
-      if (i < j || r <= c) Gij[(size_t)c * Np + r] -= v;
+      if (i < j || r <= c) Gij[(size_t)c * Np + r] = gv[nn] - v;
+      ++nn;
     });
     return;
   }
@@ -1116,25 +1157,27 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
   const int jb = blockIdx.x;
   const int tr = tid >> 5, tq = tid & 31, tc = tq & 15;
   const bool isw = tq >= 16;
-  const int lane = tid & 63;
   const size_t base = (size_t)p * NB;
   const bool has_b = jb > 0;
   const size_t cb = (size_t)(p + jb) * NB;
-  if (tid < 2) bad_s[tid] = 0;
+  if (tid == 0) bad_s = INT_MAX;
   if (FUSED) {
     // step k's update of the two tiles: ta <- R(k,p), tb <- R(k,p+jb);
     // waves 0-3 form G(p,p) - R(k,p)^T R(k,p), waves 4-7 G(p,p+jb) - R(k,p)^T R(k,p+jb)
-    tile_to_lds<THR>(G, Np, k, p, ta);
-    if (has_b) tile_to_lds<THR>(G, Np, k, p + jb, tb);
-    __syncthreads();
+    // the R tiles and this thread's entries of G(p,p) or G(p,p+jb), all in flight together
     const bool second = tid >= 256;
-    C u[16], gv[16];
+    C rp[NB * NB / THR], rq[NB * NB / THR], u[16], gv[16];
+    tile_fetch<THR>(G, Np, k, p, rp);
+    if (has_b) tile_fetch<THR>(G, Np, k, p + jb, rq);
     int nn = 0;
-    if (!second) tile_product_t<C>(ta, ta, [&](int, int, C v) { u[nn++] = v; });
-    else if (has_b) tile_product_t<C>(ta, tb, [&](int, int, C v) { u[nn++] = v; });
-    nn = 0;
     if (!second) tile_product_t_index<C>([&](int r, int c) { gv[nn++] = G[(base + c) * Np + base + r]; });
     else if (has_b) tile_product_t_index<C>([&](int r, int c) { gv[nn++] = G[(cb + c) * Np + base + r]; });
+    tile_put<THR>(rp, ta);
+    if (has_b) tile_put<THR>(rq, tb);
+    __syncthreads();
+    nn = 0;
+    if (!second) tile_product_t<C>(ta, ta, [&](int, int, C v) { u[nn++] = v; });
+    else if (has_b) tile_product_t<C>(ta, tb, [&](int, int, C v) { u[nn++] = v; });
     __syncthreads();   // every wave is done reading the R tiles
     nn = 0;
     if (!second) {
@@ -1170,19 +1213,18 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
 #pragma unroll
     for (int y = 0; y < 4; ++y)
       blk[x][y] = isw ? (has_b ? tb[4 * tr + x][4 * tc + y] : (C)0) : ta[4 * tr + x][4 * tc + y];
-  __syncthreads();   // from here on `ta` collects the output tile
-  C (*stage)[NB + 1] = ta;
   const int col0 = (isw ? NB : 0) + 4 * tc;   // this block's columns in the slab
-  int bad = 0;
   for (int g = 0; g < NB / 4; ++g) {
     const int buf = g & 1;
     if (tr == g) {
-      const int src = (lane & 32) + g;       // the v-lane holding the diagonal block
+      // the v-lane holding the diagonal block: lane g of this half wave, the
+      // same for every active lane, so a register read of that lane suffices
+      const int src = ((g & 1) << 5) + g;
       C d[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) d[x][y] = __shfl(blk[x][y], src);
+        for (int y = 0; y < 4; ++y) d[x][y] = read_lane(blk[x][y], src);
       C rd[4][4], inv[4];
       int badrow = 0;
 #pragma unroll
@@ -1223,15 +1265,23 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          slab[buf][s][col0 + y] = blk[s][y];
-          if (isw == has_b) stage[4 * g + s][4 * tc + y] = blk[s][y];
-        }
-      if (badrow && tq == 0) bad_s[buf] = 4 * g + badrow;
+        for (int y = 0; y < 4; ++y) slab[buf][s][col0 + y] = blk[s][y];
+      // rows 4g.. of R in this block's four columns, straight to memory:
+      // G(p,p+jb) from the w-lanes, the upper part of R(p,p) into rdiag
+      // from the v-lanes (jb = 0)
+      if (isw == has_b && (isw || tc >= g)) {
+        C *dst = isw ? G + (cb + 4 * tc) * Np + base + 4 * g
+                     : rdiag + (size_t)p * NB * NB + (size_t)(4 * tc) * NB + 4 * g;
+        const size_t ld = isw ? (size_t)Np : (size_t)NB;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) store_col4(dst + y * ld, blk[0][y], blk[1][y], blk[2][y], blk[3][y]);
+      }
+      // a failed pivot is only recorded here: the elimination runs on (on
+      // NaN or Inf values, with no effect on control flow or addresses) and
+      // the flag is read once after the loop
+      if (badrow && tq == 0) atomicMin(&bad_s, 4 * g + badrow);
     }
     __syncthreads();
-    bad = bad_s[buf];   // uniform: every thread reads the same LDS word after the barrier
-    if (bad) break;
     if (tr > g) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -1248,27 +1298,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
       }
     }
   }
-  if (bad) {
-    if (tid == 0 && blockIdx.x == 0) atomicMin(info, p * NB + bad);
-    return;
-  }
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += THR) {
-    const int r = t % NB, c = t / NB;
-    if (has_b) G[(cb + c) * Np + base + r] = stage[r][c];
-    else if (r <= c) rdiag[(size_t)p * NB * NB + (size_t)c * NB + r] = stage[r][c];
-  }
-}
-
-// the diagonal tiles R(p,p) back into G (upper parts), one workgroup per tile
-template <typename C>
-__global__ __launch_bounds__(256) void k_chol_restore(int Np, C *G, const C *rdiag) {
-  const int p = blockIdx.x;
-  const size_t base = (size_t)p * NB;
-  for (int t = threadIdx.x; t < NB * NB; t += 256) {
-    const int r = t % NB, c = t / NB;
-    if (r <= c) G[(base + c) * Np + base + r] = rdiag[(size_t)p * NB * NB + t];
-  }
+  // uniform: every flag was set before the last group's barrier
+  const int bad = bad_s;
+  if (bad != INT_MAX && tid == 0 && blockIdx.x == 0) atomicMin(info, p * NB + bad);
 }
 
 template <typename C>
@@ -1281,7 +1313,6 @@ static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream
     TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, true>), dim3(grid), dim3(CHOL_THREADS), 0, st, k, N, Np, G,
                rdiag, info);
   }
-  TLS_LAUNCH(PC_PACK, k_chol_restore<C>, dim3(N), dim3(256), 0, st, Np, G, rdiag);
   return hipGetLastError();
 }
 hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st) {
@@ -1292,8 +1323,10 @@ hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int
 // --------------------------------------------------------------------------
 // packing into tiles of the storage precision, diagonal-tile inverses
 // --------------------------------------------------------------------------
+// upper tiles of R from G, the diagonal ones from rdiag when given (the
+// Cholesky steps leave them there; NULL: G holds them, as after the QR)
 template <typename C, typename S>
-__global__ void k_pack(int N, int Np, const C *G, S *tiles) {
+__global__ void k_pack(int N, int Np, const C *G, const C *rdiag, S *tiles) {
   const int l = blockIdx.x;
   int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= l) ++J;
@@ -1303,25 +1336,27 @@ __global__ void k_pack(int N, int Np, const C *G, S *tiles) {
   for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
     const int r = t % NB, c = t / NB;
     double v = 0;
-    if (I < J || r <= c) v = (double)G[((size_t)J * NB + c) * Np + (size_t)I * NB + r];
+    if (I < J) v = (double)G[((size_t)J * NB + c) * Np + (size_t)I * NB + r];
+    else if (r <= c) v = rdiag ? (double)rdiag[(size_t)I * NB * NB + t] : (double)G[((size_t)J * NB + c) * Np + (size_t)I * NB + r];
     T[t] = st_from<S>(v);
   }
 }
 template <typename C>
-static hipError_t pack_c(int N, int Np, const C *G, int storage, void *tiles, hipStream_t st) {
+static hipError_t pack_c(int N, int Np, const C *G, const C *rdiag, int storage, void *tiles, hipStream_t st) {
   const dim3 g(N * (N + 1) / 2);
   switch (storage) {
-    case TLS_FP64: TLS_LAUNCH(PC_PACK, (k_pack<C, double>), g, dim3(256), 0, st, N, Np, G, (double *)tiles); break;
-    case TLS_FP32: TLS_LAUNCH(PC_PACK, (k_pack<C, float>), g, dim3(256), 0, st, N, Np, G, (float *)tiles); break;
-    case TLS_FP16: TLS_LAUNCH(PC_PACK, (k_pack<C, half_t>), g, dim3(256), 0, st, N, Np, G, (half_t *)tiles); break;
-    default: TLS_LAUNCH(PC_PACK, (k_pack<C, bf16_t>), g, dim3(256), 0, st, N, Np, G, (bf16_t *)tiles); break;
+    case TLS_FP64: TLS_LAUNCH(PC_PACK, (k_pack<C, double>), g, dim3(256), 0, st, N, Np, G, rdiag, (double *)tiles); break;
+    case TLS_FP32: TLS_LAUNCH(PC_PACK, (k_pack<C, float>), g, dim3(256), 0, st, N, Np, G, rdiag, (float *)tiles); break;
+    case TLS_FP16: TLS_LAUNCH(PC_PACK, (k_pack<C, half_t>), g, dim3(256), 0, st, N, Np, G, rdiag, (half_t *)tiles); break;
+    default: TLS_LAUNCH(PC_PACK, (k_pack<C, bf16_t>), g, dim3(256), 0, st, N, Np, G, rdiag, (bf16_t *)tiles); break;
   }
   return hipGetLastError();
 }
-hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, int storage, void *tiles,
-                             hipStream_t st) {
-  if (compute == TLS_FP64) return pack_c<double>(N, Np, (const double *)G, storage, tiles, st);
-  return pack_c<float>(N, Np, (const float *)G, storage, tiles, st);
+hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, const void *rdiag, int storage,
+                             void *tiles, hipStream_t st) {
+  if (compute == TLS_FP64)
+    return pack_c<double>(N, Np, (const double *)G, (const double *)rdiag, storage, tiles, st);
+  return pack_c<float>(N, Np, (const float *)G, (const float *)rdiag, storage, tiles, st);
 }
 
 // inverse of each stored diagonal tile, computed in FP64 from the stored values

@@ -448,17 +448,14 @@ void prof_begin(int cls, hipStream_t st) {
   if (!g_prof.on) return;
   if (std::find(g_prof.side.begin(), g_prof.side.end(), st) != g_prof.side.end()) cls = PC_GATE;
   hipEvent_t e = prof_event();
-  if (!e) return;
-  hipEventRecord(e, st);
+  if (!e || hipEventRecord(e, st) != hipSuccess) return;   // this launch goes unrecorded
   g_prof.open_cls = cls;
   g_prof.open_ev = e;
 }
 void prof_end(hipStream_t st) {
   if (!g_prof.on || g_prof.open_cls < 0) return;
   hipEvent_t e = prof_event();
-  if (!e) return;
-  hipEventRecord(e, st);
-  g_prof.recs.push_back({g_prof.open_cls, g_prof.open_ev, e});
+  if (e && hipEventRecord(e, st) == hipSuccess) g_prof.recs.push_back({g_prof.open_cls, g_prof.open_ev, e});
   g_prof.open_cls = -1;
 }
 }  // namespace tls
@@ -889,9 +886,10 @@ FactorWs factor_ws_of(const tls_precond_s *P) {
 }
 
 // tiles of the storage precision, diagonal-tile inverses and the explicit
-// inverse from the factor R_hat in G
-tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, hipStream_t st) {
-  HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, uq, W.tiles, st));
+// inverse from the factor R_hat in G (the Cholesky steps leave its diagonal
+// tiles in W.rdiag: chol = 1)
+tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, int chol, hipStream_t st) {
+  HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, chol ? W.rdiag : nullptr, uq, W.tiles, st));
   HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
   P->storage = uq;
   P->xstorage = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
@@ -936,7 +934,7 @@ tls_status factor_qr_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, in
   HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
   HIPCHK(launch_qr_factor(A->m, (int)A->n, P->Np, A->format, A->ld, A->val, A->row_ptr, A->col_idx, W.d,
                           P->scaled, uq, compute, W.qrw, W.G, W.info, st));
-  TRY(finish_factor(P, W, uq, compute, st));      // enqueued before the pivot check
+  TRY(finish_factor(P, W, uq, compute, 0, st));   // enqueued before the pivot check
   if (gate) TRY(gate_start(P, W, *gate, st));
   int info = 0;
   const tls_status rs = read_factor_status(P, W, st, &info);
@@ -973,7 +971,7 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
     // packing, diagonal inverses and the explicit inverse are enqueued before
     // the breakdown flag is read (one synchronization); after a breakdown the
     // next attempt redoes them
-    TRY(finish_factor(P, W, uq, compute, st));
+    TRY(finish_factor(P, W, uq, compute, 1, st));
     if (gate) TRY(gate_start(P, W, *gate, st));
     int info = 0;
     const tls_status rs = read_factor_status(P, W, st, &info);
