@@ -89,6 +89,8 @@ hipError_t launch_fill_multi(const FillSet &F, hipStream_t st);
 hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st);
 hipError_t launch_round(const double *in, int64_t count, int q, double *out, hipStream_t st);
 hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st);
+// int32 entries the CSC build needs in its `fill` buffer for an m x n matrix
+size_t csc_fill_ints(int64_t m, int64_t n);
 hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
                             const int32_t *col_idx, const double *val, int32_t *col_ptr,
                             int32_t *row_idx, double *cval, int32_t *tmp_row, double *tmp_val,

@@ -173,11 +173,160 @@ __global__ void k_csc_rank(int64_t nnz, int n, const int32_t *col_ptr, const int
   cval[a + rank] = tmp_val[e];
 }
 
+// Block-segmented build (n <= CSC_HIST and nb * n <= CSC_BLK_MAX, nb row
+// blocks of CSC_HIST_ROWS rows): bc[b * n + c] holds the count of column c in
+// row block b, bo[b * n + c] the offset of that block's segment inside
+// column c. The segments of a column follow each other in row order, so an
+// entry's rank is found among the few entries of its own segment, and the
+// slots are claimed with LDS atomics instead of global ones. Every loop over
+// entries keeps CSC_BATCH independent loads in flight per thread.
+constexpr int64_t CSC_BLK_MAX = 1 << 20;
+constexpr int CSC_BATCH = 8;
+static bool csc_blocked(int64_t m, int64_t n) {
+  const int64_t nb = (m + CSC_HIST_ROWS - 1) / CSC_HIST_ROWS;
+  return n <= CSC_HIST && nb * n <= CSC_BLK_MAX;
+}
+size_t csc_fill_ints(int64_t m, int64_t n) {
+  const int64_t nb = std::max<int64_t>(1, (m + CSC_HIST_ROWS - 1) / CSC_HIST_ROWS);
+  return (size_t)std::max<int64_t>(1, csc_blocked(m, n) ? 2 * nb * n : n);
+}
+
+__global__ __launch_bounds__(1024) void k_csc_count_blk(int m, int n, const int32_t *row_ptr,
+                                                        const int32_t *col_idx, int32_t *bc) {
+  __shared__ int32_t h[CSC_HIST];
+  for (int c = threadIdx.x; c < n; c += 1024) h[c] = 0;
+  __syncthreads();
+  const int r0 = blockIdx.x * CSC_HIST_ROWS, r1 = min(m, r0 + CSC_HIST_ROWS);
+  const int e0 = row_ptr[r0], e1 = row_ptr[r1];
+  for (int e = e0 + threadIdx.x; e < e1; e += 1024 * CSC_BATCH) {
+    int ci[CSC_BATCH];
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u) ci[u] = (e + 1024 * u < e1) ? col_idx[e + 1024 * u] : -1;
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u)
+      if (ci[u] >= 0) atomicAdd(&h[ci[u]], 1);
+  }
+  __syncthreads();
+  int32_t *dst = bc + (size_t)blockIdx.x * n;
+  for (int c = threadIdx.x; c < n; c += 1024) dst[c] = h[c];
+}
+
+// one workgroup: per column the exclusive prefix of its block counts (into
+// bo) and its total, then col_ptr as the exclusive scan of the totals
+// (thread t owns a contiguous range of columns)
+__global__ __launch_bounds__(1024) void k_csc_scan_blk(int n, int nb, const int32_t *__restrict__ bc,
+                                                       int32_t *__restrict__ bo, int32_t *__restrict__ col_ptr) {
+  __shared__ int32_t s_tot[1024];
+  const int tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int a = min(n, tid * per), z = min(n, a + per);
+  int32_t sum = 0;
+  for (int c = a; c < z; ++c) {
+    int32_t run = 0;
+    for (int b0 = 0; b0 < nb; b0 += CSC_BATCH) {
+      int32_t v[CSC_BATCH];
+#pragma unroll
+      for (int u = 0; u < CSC_BATCH; ++u) v[u] = (b0 + u < nb) ? bc[(size_t)(b0 + u) * n + c] : 0;
+#pragma unroll
+      for (int u = 0; u < CSC_BATCH; ++u) {
+        if (b0 + u < nb) bo[(size_t)(b0 + u) * n + c] = run;
+        run += v[u];
+      }
+    }
+    col_ptr[c] = run;   // the column total until the scan below
+    sum += run;
+  }
+  s_tot[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the thread sums
+    const int32_t v = tid >= off ? s_tot[tid - off] : 0;
+    __syncthreads();
+    s_tot[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = s_tot[tid] - sum;
+  for (int c = a; c < z; ++c) {
+    const int32_t t = col_ptr[c];
+    col_ptr[c] = run;
+    run += t;
+  }
+  if (tid == 1023) col_ptr[n] = s_tot[1023];
+}
+
+// one workgroup per row block, one thread per row: each entry takes the next
+// free slot of its column's segment for this block (LDS counter)
+static_assert(CSC_HIST_ROWS == 1024, "k_csc_scatter_blk runs one thread per row of a block");
+__global__ __launch_bounds__(1024) void k_csc_scatter_blk(int m, int n, const int32_t *row_ptr,
+                                                          const int32_t *col_idx, const double *val,
+                                                          const int32_t *col_ptr, const int32_t *bo,
+                                                          int32_t *tmp_row, double *tmp_val) {
+  __shared__ int32_t base[CSC_HIST], used[CSC_HIST];
+  const int32_t *off = bo + (size_t)blockIdx.x * n;
+  for (int c = threadIdx.x; c < n; c += 1024) {
+    base[c] = col_ptr[c] + off[c];
+    used[c] = 0;
+  }
+  __syncthreads();
+  const int r = blockIdx.x * CSC_HIST_ROWS + threadIdx.x;   // CSC_HIST_ROWS == blockDim.x
+  if (r >= m) return;
+  const int e1 = row_ptr[r + 1];
+  for (int e = row_ptr[r]; e < e1; e += CSC_BATCH) {
+    int ci[CSC_BATCH];
+    double v[CSC_BATCH];
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u) {
+      ci[u] = (e + u < e1) ? col_idx[e + u] : -1;
+      v[u] = (e + u < e1) ? val[e + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u) {
+      if (ci[u] < 0) continue;
+      const int pos = base[ci[u]] + atomicAdd(&used[ci[u]], 1);
+      tmp_row[pos] = r;
+      tmp_val[pos] = v[u];
+    }
+  }
+}
+
+// one thread per CSC slot: its final position inside its block segment is
+// the number of entries of the segment with a smaller row
+__global__ void k_csc_rank_blk(int64_t nnz, int n, int nb, const int32_t *col_ptr, const int32_t *bo,
+                               const int32_t *tmp_row, const double *tmp_val, int32_t *row_idx,
+                               double *cval) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int lo = 0, hi = n;   // column of slot e: col_ptr[lo] <= e < col_ptr[lo + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col_ptr[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int r = tmp_row[e];
+  const int b = r / CSC_HIST_ROWS;
+  const int s0 = col_ptr[lo] + bo[(size_t)b * n + lo];
+  const int s1 = (b + 1 < nb) ? col_ptr[lo] + bo[(size_t)(b + 1) * n + lo] : col_ptr[lo + 1];
+  int rank = 0;
+  for (int t = s0; t < s1; ++t) rank += (tmp_row[t] < r);
+  row_idx[s0 + rank] = r;
+  cval[s0 + rank] = tmp_val[e];
+}
+
 hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
                             const int32_t *col_idx, const double *val, int32_t *col_ptr,
                             int32_t *row_idx, double *cval, int32_t *tmp_row, double *tmp_val,
                             int32_t *fill, hipStream_t st) {
   hipError_t e;
+  if (nnz == 0) return launch_fill_i32(col_ptr, 0, (size_t)n + 1, st);
+  if (csc_blocked(m, n)) {
+    const int nb = (m + CSC_HIST_ROWS - 1) / CSC_HIST_ROWS;
+    int32_t *bo = fill + (size_t)nb * n;
+    TLS_LAUNCH(PC_SETUP, k_csc_count_blk, dim3(nb), dim3(1024), 0, st, m, n, row_ptr, col_idx, fill);
+    TLS_LAUNCH(PC_SETUP, k_csc_scan_blk, dim3(1), dim3(1024), 0, st, n, nb, (const int32_t *)fill, bo, col_ptr);
+    TLS_LAUNCH(PC_SETUP, k_csc_scatter_blk, dim3(nb), dim3(CSC_HIST_ROWS), 0, st, m, n, row_ptr, col_idx, val,
+               col_ptr, (const int32_t *)bo, tmp_row, tmp_val);
+    TLS_LAUNCH(PC_SETUP, k_csc_rank_blk, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, n, nb,
+               col_ptr, (const int32_t *)bo, tmp_row, tmp_val, row_idx, cval);
+    return hipGetLastError();
+  }
   if ((e = launch_fill_i32(fill, 0, n, st)) != hipSuccess) return e;
   const unsigned ge = (unsigned)((nnz + 255) / 256);
   if (nnz > 0) {

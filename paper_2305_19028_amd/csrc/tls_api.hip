@@ -230,7 +230,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     W.cval = c.take<double>(nnz);
     W.tmp_row = c.take<int32_t>(nnz);
     W.tmp_val = c.take<double>(nnz);
-    W.fill = c.take<int32_t>(n);
+    W.fill = c.take<int32_t>(csc_fill_ints(m, n));
     W.valq = c.take<char>(nnz * 8);
     W.cvalq = c.take<char>(nnz * 8);
   }

@@ -57,6 +57,52 @@ def test_matvec(kind, m, n):
     assert np.allclose(z, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+def _csr_case(kind):
+    import scipy.sparse as sp
+    g = np.random.default_rng(11)
+    if kind == "workload":            # row blocks of 1024, ~5 entries per block and column
+        m, n, k = 20000, 2000, 200000
+    elif kind == "ragged":            # ragged last block, empty rows, one full column
+        m, n, k = 3001, 300, 18000
+    else:                             # more row blocks x columns than the segmented build takes
+        m, n, k = 1_100_000, 1000, 22000
+    rows, cols = g.integers(0, m, k), g.integers(0, n, k)
+    if kind == "ragged":
+        keep = (rows < 100) | (rows >= 500)
+        rows, cols = rows[keep], cols[keep]
+        rows, cols = np.concatenate([rows, np.arange(m)]), np.concatenate([cols, np.full(m, 11)])
+    A = sp.coo_matrix((g.standard_normal(rows.size), (rows, cols)), shape=(m, n)).tocsr()
+    A = (A + sp.eye(m, n, format="csr")).tocsr()     # full column rank
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("kind", ["workload", "ragged", "fallback"])
+def test_csc_copy_rmatvec(kind):
+    """A^T b through the CSC copy a factorization builds (row-block segments
+    with LDS slot counters, or the global-atomic build past its size limit):
+    equal to SciPy's product to rounding, and bit-identical across two
+    factorizations (rows sorted inside each column, so the summation order is
+    fixed)."""
+    tls = _tls()
+    A = _csr_case(kind)
+    m, n = A.shape
+    print(f"csc {kind} {m}x{n} nnz {A.nnz}", flush=True)
+    Ad = tls.csr(A.indptr, A.indices, A.data, m, n)
+    b = np.random.default_rng(3).standard_normal(m)
+    ref = A.T @ b
+    zs = []
+    for _ in range(2):
+        P, _ = tls.tls_factor_precond(Ad, "fp64")
+        zs.append(tls.tls_matvec(Ad, P, 1, b).cpu().numpy())
+    # both sums err by at most (column count) u |A|^T |b| each
+    kmax = int(np.diff(A.tocsc().indptr).max())
+    scale = abs(A).T @ np.abs(b)
+    assert np.all(np.abs(zs[0] - ref) <= 2 * kmax * 2.0 ** -53 * scale), np.max(np.abs(zs[0] - ref) / scale)
+    assert np.array_equal(zs[0].view(np.uint64), zs[1].view(np.uint64))
+
+
 def _tri(n, seed, cond=10.0):
     g = np.random.default_rng(seed)
     A = g.standard_normal((n + 20, n))
