@@ -74,15 +74,16 @@ def test_c3_planted_fp64(planted):
     assert es < 1e-10 and ex < 1e-10
 
 
-def test_c3_planted_mixed_gate_escalates(planted):
-    """BF16 requested with the gate on: the factor that is used carries the
-    a-posteriori certificate (Ritz values of R^{-T} A^T A R^{-1} within
-    [1/2, 3/2]; escalation if the BF16 one had failed), and the answer meets
-    1e-10."""
+@pytest.mark.parametrize("u_q", ["fp16", "bf16"])
+def test_c3_planted_mixed_gate_escalates(planted, u_q):
+    """FP16 or BF16 requested with the gate on: the factor that is used
+    carries the a-posteriori certificate (Ritz values of R^{-T} A^T A R^{-1}
+    within [1/2, 3/2]; escalation if the requested one had failed), and the
+    answer meets 1e-10."""
     tls = _tls()
     A, b, sig, x = planted
     Ad = tls.dense(A)
-    P, _ = tls.tls_factor_precond(Ad, "bf16")
+    P, _ = tls.tls_factor_precond(Ad, u_q)
     opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=2,
                             refine_sweeps=1)
     xs, s, st = tls.tls_rqi_solve(Ad, b, P, opts)
@@ -93,7 +94,7 @@ def test_c3_planted_mixed_gate_escalates(planted):
           f"[{g['quality_lo']:.3g}, {g['quality_hi']:.3g}] sigma {es:.2e} x {ex:.2e}", flush=True)
     if g["used"] != tls.PREC["fp64"]:
         assert g["verdict"] & 16 and 0.5 <= g["quality_lo"] and g["quality_hi"] <= 1.5
-    assert g["used"] == tls.PREC["bf16"] or g["escalations"] >= 1
+    assert g["used"] == tls.PREC[u_q] or g["escalations"] >= 1
     assert es < 1e-10 and ex < 1e-10
 
 
