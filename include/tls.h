@@ -75,10 +75,12 @@ typedef enum {
 } tls_status;
 
 /* The data matrix A (m x n, m > n). Dense: column-major, element (i, j) at
- * val[i + j*ld], ld >= m. CSR: row_ptr[m+1] (row_ptr[0] = 0, nondecreasing),
- * col_idx[nnz] in [0, n) strictly increasing within each row, val[nnz]. All
- * arrays are device memory owned by the caller and must stay valid and
- * unchanged while a preconditioner built from A is in use. */
+ * val[i + j*ld], ld >= m. CSR: row_ptr[m+1] (row_ptr[0] = 0, nondecreasing,
+ * row_ptr[m] = nnz), col_idx[nnz] in [0, n) strictly increasing within each
+ * row, val[nnz]. The CSR structure is not checked on the device (its
+ * indices address the CSC copy and LDS histograms): a violation is undefined
+ * behaviour. All arrays are device memory owned by the caller and must stay
+ * valid and unchanged while a preconditioner built from A is in use. */
 typedef struct {
   int32_t format;          /* tls_format */
   int32_t reserved;

@@ -98,6 +98,7 @@ __global__ void k_csc_count(int64_t nnz, const int32_t *col_idx, int32_t *cnt) {
 // nonzero bin to the global count once, instead of one global atomic per
 // entry on a few thousand addresses
 constexpr int CSC_HIST = 12288, CSC_HIST_ROWS = 1024;
+constexpr int CSC_BATCH = 8;   // independent loads in flight per thread in the entry loops
 __global__ __launch_bounds__(256) void k_csc_count_lds(int m, int n, const int32_t *row_ptr,
                                                        const int32_t *col_idx, int32_t *cnt) {
   __shared__ int32_t h[CSC_HIST];
@@ -105,7 +106,14 @@ __global__ __launch_bounds__(256) void k_csc_count_lds(int m, int n, const int32
   __syncthreads();
   const int r0 = blockIdx.x * CSC_HIST_ROWS, r1 = min(m, r0 + CSC_HIST_ROWS);
   const int e0 = row_ptr[r0], e1 = row_ptr[r1];
-  for (int e = e0 + threadIdx.x; e < e1; e += 256) atomicAdd(&h[col_idx[e]], 1);
+  for (int e = e0 + threadIdx.x; e < e1; e += 256 * CSC_BATCH) {
+    int ci[CSC_BATCH];
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u) ci[u] = (e + 256 * u < e1) ? col_idx[e + 256 * u] : -1;
+#pragma unroll
+    for (int u = 0; u < CSC_BATCH; ++u)
+      if (ci[u] >= 0) atomicAdd(&h[ci[u]], 1);
+  }
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += 256)
     if (h[c]) atomicAdd(&cnt[c], h[c]);
@@ -131,12 +139,12 @@ __global__ void k_scan(int n, const int32_t *cnt, int32_t *col_ptr) {
   for (int i = a; i < b; ++i) { col_ptr[i] = run; run += cnt[i]; }
 }
 
-// one thread per nonzero; its row by binary search in row_ptr
-// one thread per entry (its row by binary search in row_ptr, which stays
-// in L2): each entry takes the next free slot of its column in arbitrary
-// order; k_csc_rank orders the rows of each column after. One thread per
-// row instead chains a row's returning atomics and was slower (50 us
-// against 30 us at 20000 x 2000, 0.5%).
+// Global-atomic build (used past the segmented build's size limit): one
+// thread per entry (its row by binary search in row_ptr, which stays in L2)
+// takes the next free slot of its column in arbitrary order; k_csc_rank
+// orders the rows of each column after. With global counters, one thread
+// per row chains a row's returning atomics and was slower (50 us against
+// 30 us at 20000 x 2000, 0.5%).
 __global__ void k_csc_scatter(int m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                               const double *val, const int32_t *col_ptr, int32_t *fill,
                               int32_t *tmp_row, double *tmp_val) {
@@ -181,7 +189,6 @@ __global__ void k_csc_rank(int64_t nnz, int n, const int32_t *col_ptr, const int
 // slots are claimed with LDS atomics instead of global ones. Every loop over
 // entries keeps CSC_BATCH independent loads in flight per thread.
 constexpr int64_t CSC_BLK_MAX = 1 << 20;
-constexpr int CSC_BATCH = 8;
 static bool csc_blocked(int64_t m, int64_t n) {
   const int64_t nb = (m + CSC_HIST_ROWS - 1) / CSC_HIST_ROWS;
   return n <= CSC_HIST && nb * n <= CSC_BLK_MAX;
