@@ -19,8 +19,11 @@
  *  - Work is enqueued on the given stream. tls_factor_precond synchronizes
  *    it once per factorization attempt (breakdown and finite-input flags),
  *    and waits for the gate's runs only when a report is requested;
- *    tls_rqi_solve synchronizes it once per outer iteration (psi of eq. (4))
- *    and at the few decisions that need a value on the host; tls_pcg_step
+ *    tls_rqi_solve waits once per outer iteration for psi of eq. (4) (an
+ *    event behind its copy; unless strict_pd is set, the iteration's two
+ *    PCGTLS solves and update are enqueued before the wait, and the run
+ *    past the last iteration is discarded) and synchronizes at the few
+ *    decisions that need a value on the host; tls_pcg_step
  *    and tls_apply_precond are asynchronous unless a host trace is
  *    requested.
  *  - Every call returns a tls_status; no C++ exception crosses the ABI;
@@ -180,7 +183,8 @@ typedef struct {
   int32_t warm_used;       /* 1 when the warm-start step was kept                 */
   int32_t stopped;         /* 0 psi rule, 1 kmax, 2 fixed point (psi == 0 or psi
                               repeated exactly)                                   */
-  int32_t negative_delta;  /* PCGTLS steps that met delta_j < 0                   */
+  int32_t negative_delta;  /* PCGTLS steps that met delta_j < 0 in the last run
+                              enqueued (with the lookahead, the discarded one)  */
   int32_t refine_steps;    /* refinement RQI steps taken                          */
   int32_t clamped;         /* iterations whose shift was clamped                  */
   int32_t gate_async;      /* 1: the gate's Lanczos runs were still in flight when

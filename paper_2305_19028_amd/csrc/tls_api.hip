@@ -760,6 +760,9 @@ tls_status collect_cert(tls_precond_s *P) {
 // it lives until the process ends. Pinned host blocks for the gate's
 // read-back come from a per-device free list (allocated once, reused).
 constexpr size_t GATE_HOST_DOUBLES = 2 * (2 * LANCZOS_STEPS + 2) + (2 * QUALITY_STEPS + 2);
+// every block of the pool: the gate's read-back, or the solve's scalar
+// read-back (64 doubles and a flag)
+constexpr size_t PINNED_DOUBLES = GATE_HOST_DOUBLES > 72 ? GATE_HOST_DOUBLES : 72;
 std::mutex g_side_mu;
 std::map<int, hipStream_t> g_side_pool;
 std::map<int, std::vector<double *>> g_pinned_free;
@@ -790,7 +793,7 @@ hipError_t pinned_take(double **out, int *dev_out) {
     *out = fl.back();
     fl.pop_back();
   } else {
-    e = hipHostMalloc((void **)out, GATE_HOST_DOUBLES * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void **)out, PINNED_DOUBLES * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return e;
   }
   *dev_out = dev;
@@ -800,6 +803,34 @@ void pinned_give(double *p, int dev) {
   std::lock_guard<std::mutex> lk(g_side_mu);
   g_pinned_free[dev].push_back(p);
 }
+
+// a pinned block for the length of a solve; returned to the pool on every
+// exit (declare it before the event that guards copies into it, so that the
+// event is waited for first)
+struct PinnedBlock {
+  double *p = nullptr;
+  int dev = 0;
+  PinnedBlock() = default;
+  PinnedBlock(const PinnedBlock &) = delete;
+  PinnedBlock &operator=(const PinnedBlock &) = delete;
+  ~PinnedBlock() {
+    if (p) pinned_give(p, dev);
+  }
+};
+// an event recorded after copies into host memory; destruction waits for it,
+// so no copy is still in flight when its target is reused
+struct CopyEvent {
+  hipEvent_t e = nullptr;
+  CopyEvent() = default;
+  CopyEvent(const CopyEvent &) = delete;
+  CopyEvent &operator=(const CopyEvent &) = delete;
+  ~CopyEvent() {
+    if (e) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  }
+};
 
 }  // namespace
 
@@ -1661,18 +1692,44 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       if (plain_step) HIPCHK(launch_axpy_init(n, x, W.t1, W.scal, 0, st));   // x_1 = x_0 + sigma_0^2 u_0
 
       // ---- main loop -----------------------------------------------------------
+      // Lookahead: iteration k's two PCGTLS solves and its update are
+      // enqueued before the host waits for psi_k (read back into pinned
+      // memory behind an event), so the GPU works through the host's
+      // turnaround. They never touch the best iterate, which only the psi
+      // kernel writes, and x is reset to it after the loop, so a stop at k
+      // leaves the result unchanged. Off with strict_pd: a run past the stop
+      // must not turn delta_j <= 0 into an error of a finished solve.
+      PinnedBlock hb;
+      HIPCHK(pinned_take(&hb.p, &hb.dev));
+      CopyEvent hev;
+      HIPCHK(hipEventCreateWithFlags(&hev.e, hipEventDisableTiming));
+      double *const h = hb.p;                                  // 64 scalars
+      int *const bad_h = reinterpret_cast<int *>(hb.p + 64);   // finite-b flag
+      const bool ahead = !o->strict_pd;
+      // two PCGTLS solves with l = k (k+1 steps; at least min_inner_steps
+      // when asked), sharing the shift; the right-hand sides [-f, x] were
+      // written by the psi kernel; then the RQI update of x
+      auto inner = [&](int l) -> tls_status {
+        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, l, o->u_p, o->strict_pd, W.pcg, st));
+        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+        return TLS_OK;
+      };
       double best = std::numeric_limits<double>::infinity();
       int no_improve = 0, k = 0;
       S.stopped = 1;
-      double h[64];
       for (k = 1; k <= kmax; ++k) {
         TRY(evaluate(k, cap));
         if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
         const bool first = ls_deferred && k == 1;
         HIPCHK(hipMemcpyAsync(h, W.scal, (first ? 64 : 16) * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (first) HIPCHK(hipMemcpyAsync(&bad_b, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        if (first) HIPCHK(hipMemcpyAsync(bad_h, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(hev.e, st));
+        const int l = std::max(k, o->min_inner_steps);
+        const bool enq = ahead && k < kmax;
+        if (enq) TRY(inner(l));
+        HIPCHK(hipEventSynchronize(hev.e));
         if (first) {
+          bad_b = *bad_h;
           if (bad_b) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
           S.sigma_ls = std::sqrt(h[48]);
           rr0 = h[51];
@@ -1700,13 +1757,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         if (psi == 0.0 || (k > 1 && psi == S.psi[k - 2])) { S.stopped = 2; break; }
         if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
         if (k == kmax) break;
-        // two PCGTLS solves with l = k (k+1 steps; at least min_inner_steps
-        // when asked), sharing the shift; the right-hand sides [-f, x] were
-        // written by the psi kernel
-        const int l = std::max(k, o->min_inner_steps);
-        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, l, o->u_p, o->strict_pd, W.pcg, st));
+        if (!enq) TRY(inner(l));
         S.pcg_steps += l + 1;
-        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
       }
       // the returned iterate
       HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
