@@ -271,3 +271,27 @@ def test_deterministic_repeat():
         x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p="fp32", stop_patience=2))
         outs.append((x.cpu().numpy().tobytes(), sigma, tuple(st["psi"])))
     assert outs[0] == outs[1] == outs[2]
+
+
+@pytest.mark.parametrize("uq,up", [("fp16", "fp32"), ("fp64", "fp64")])
+def test_lookahead_changes_no_result(uq, up):
+    """The RQI loop enqueues each iteration's PCGTLS solves before it waits
+    for psi (lookahead), except under strict_pd. On a problem where no
+    delta_j <= 0 occurs, both give the same iterates bit for bit: the run
+    past the stop is discarded and x is reset to the best iterate."""
+    import torch
+    tls = _tls()
+    A, b, _, _ = tlsgen.sparse_scaled(5000, 400, 0.01, 4.0, 1e-4, seed=9)
+    Ad = tls.from_tlsgen(A)
+    outs = []
+    for strict in (0, 1):
+        P, _ = tls.tls_factor_precond(Ad, uq)
+        snaps = torch.zeros((40, 400), dtype=torch.float64, device="cuda")
+        x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p=up, stop_patience=2, strict_pd=strict,
+                                                                  refine_sweeps=1, x_snapshots=snaps))
+        k = st["iters"]
+        outs.append((x.cpu().numpy().tobytes(), sigma, tuple(st["psi"][:k]), k, st["k_best"], st["pcg_steps"],
+                     st["stopped"], snaps[:k].cpu().numpy().tobytes()))
+        print(f"{uq} strict_pd={strict}: iters {k} k_best {st['k_best']} pcg {st['pcg_steps']} "
+              f"sigma {sigma:.17g}", flush=True)
+    assert outs[0] == outs[1]
