@@ -1063,9 +1063,13 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     P->rep.requested = u_q;
     P->rep.method = method;
     P->rep.sigma_n_est = P->rep.sigma_1_est = std::numeric_limits<double>::quiet_NaN();
-    HIPCHK(launch_fill_i32(W.sync, 0, P->N + 8, stream));
-    // finite input check
-    HIPCHK(launch_fill_i32(W.flag, 0, 1, stream));
+    {
+      // the solve-sync counters and the finite-input flag, in one launch
+      FillSet F;
+      F.add_i32(W.sync, 0, P->N + 8);
+      F.add_i32(W.flag, 0, 1);
+      HIPCHK(launch_fill_multi(F, stream));
+    }
     const size_t nval = A->format == TLS_CSR ? (size_t)A->nnz : (size_t)A->ld * (size_t)(n - 1) + (size_t)A->m;
     HIPCHK(launch_check_finite(A->val, nval, W.flag, stream));
     // CSC copy and column norms
