@@ -1518,36 +1518,56 @@ hipError_t launch_pack_tiles(int N, int Np, int compute, const void *G, const vo
 // inverse of each stored diagonal tile, computed in FP64 from the stored values
 template <typename S>
 __global__ __launch_bounds__(1024) void k_diag_inverse(const S *tiles, double *dinv64, float *dinv32) {
-  // T X = I by backward substitution for all 64 columns at once: step l
-  // fixes row l of X (x_l = b_l / T_ll) and removes it from the rows above
-  // (b_i -= T_il x_l). Thread tid holds b_i(t) for t = tid % 64 and the four
-  // rows i = tid / 64 + 16 k in registers; row l of X goes through LDS, one
-  // barrier per step.
+  // X = T^{-1} for the upper triangular 64x64 tile T, by 16x16 blocks:
+  //  1. the four diagonal blocks at once by backward substitution (T_qq
+  //     X_qq = I, 16 steps with one barrier each; thread (q, i, t) holds
+  //     entry (i, t) of the right-hand side of block q), with the 64
+  //     reciprocal pivots computed once beforehand;
+  //  2. the blocks above the diagonal by block back-substitution, in order
+  //     of their distance d = J - I from the diagonal (all blocks of one
+  //     distance together): S = sum_{K = I+1..J} T_IK X_KJ, then
+  //     X_IJ = -X_II S (two barriers per distance).
   __shared__ double T[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
+  __shared__ double Sb[3][16][17];
+  __shared__ double rpiv[NB];
   const int I = blockIdx.x, tid = threadIdx.x;
   const S *src = tiles + ((size_t)I * (I + 1) / 2 + I) * NB * NB;
   for (int e = tid; e < NB * NB; e += 1024) {
     const int r = e % NB, c = e / NB;
     T[r][c] = cvt<double>(src[e]);
+    X[r][c] = 0.0;
   }
-  const int t = tid % NB, i0 = tid / NB;
-  double bv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) bv[k] = (i0 + 16 * k == t) ? 1.0 : 0.0;
   __syncthreads();
-  for (int l = NB - 1; l >= 0; --l) {
-    const double d = 1.0 / T[l][l];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i0 + 16 * k == l) X[l][t] = bv[k] * d;
+  if (tid < NB) rpiv[tid] = 1.0 / T[tid][tid];
+  __syncthreads();
+  {
+    const int q = tid >> 8, i = (tid >> 4) & 15, t = tid & 15, o = 16 * q;
+    double b = (i == t) ? 1.0 : 0.0;
+    for (int l = 15; l >= 0; --l) {
+      if (i == l) X[o + l][o + t] = b * rpiv[o + l];
+      __syncthreads();
+      const double xl = X[o + l][o + t];
+      if (i < l) b -= T[o + i][o + l] * xl;
+    }
+  }
+  for (int d = 1; d <= 3; ++d) {
+    const int active = (4 - d) * 256;   // blocks (Ib, Ib + d), 256 entries each
+    const int pr = tid >> 8, r = (tid >> 4) & 15, c = tid & 15;
+    const int ib = pr, jb = pr + d;
+    if (tid < active) {
+      double sacc = 0.0;
+      for (int k = 0; k < 16 * d; ++k) sacc += T[16 * ib + r][16 * (ib + 1) + k] * X[16 * (ib + 1) + k][16 * jb + c];
+      Sb[pr][r][c] = sacc;
+    }
     __syncthreads();
-    const double xl = X[l][t];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i0 + 16 * k < l) bv[k] -= T[i0 + 16 * k][l] * xl;
+    if (tid < active) {
+      double xacc = 0.0;
+      for (int k = r; k < 16; ++k) xacc += X[16 * ib + r][16 * ib + k] * Sb[pr][k][c];
+      X[16 * ib + r][16 * jb + c] = -xacc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double *o64 = dinv64 + (size_t)I * NB * NB;
   float *o32 = dinv32 + (size_t)I * NB * NB;
   for (int e = tid; e < NB * NB; e += 1024) {
