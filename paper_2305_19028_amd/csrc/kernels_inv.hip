@@ -230,14 +230,21 @@ __global__ __launch_bounds__(256) void k_inv_pack(int N, const C *W, SX *XR, SX 
   SX *xc = XC + xc_tile(J, I) * NB * NB;
   // both targets column-major within the tile (element (row, col) at
   // col * 64 + row), so that the apply kernels load one column of a tile,
-  // one row per lane, as 64 consecutive elements
+  // one row per lane, as 64 consecutive elements; the transposed copy goes
+  // through LDS so that both are written with consecutive addresses
+  __shared__ C tl[NB][NB + 1];
   for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
     const int r = t % NB, c = t / NB;
-    double v = (double)src[c * NB + r];   // X(I*64 + r, J*64 + c)
-    if (I == J && r > c) v = 0.0;
-    xr[c * NB + r] = st_from<SX>(v);
-    // X^T tile (J, I): element (row c, column r) = X(r, c)
-    xc[r * NB + c] = st_from<SX>(v);
+    C v = src[c * NB + r];   // X(I*64 + r, J*64 + c)
+    if (I == J && r > c) v = (C)0;
+    tl[r][c] = v;
+    xr[c * NB + r] = st_from<SX>((double)v);
+  }
+  __syncthreads();
+  // X^T tile (J, I): element (row c, column r) = X(r, c), at r * 64 + c
+  for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+    const int r = t / NB, c = t % NB;
+    xc[t] = st_from<SX>((double)tl[r][c]);
   }
 }
 
