@@ -26,8 +26,6 @@ that it follows):
 * ``mlp``          float64 forward, backward and Adam for the warm-start
                    network (project addition, not in the paper).
 * ``costmodel``    the operation-count model of Section 3.2.
-* ``philox``       Philox4x32-10 counter-based generator (Salmon et al.,
-                   SC'11) and Box-Muller, for GPU-generated inputs.
 
 Parity status of each routine is recorded in its module docstring.
 """

@@ -23,8 +23,10 @@ Reading: kappa_F(A) = ||A||_F ||A^+||_2 = ||A||_F / sigma'_n, the
 combination that appears in the bound on ||Delta||_2 (the product of
 ||Delta A||_F <~ gamma ||A||_F and ||R-hat^{-1}||_2 = 1/sigma'_n).
 
-Pins: tests/test_oracle_misc.py (constant-free magnitudes on the model
-problems against the values printed in Section 4).
+Pins: tests/test_oracle_misc.py (every bound in closed form on a diagonal
+A and on two columns at a given angle, where kappa, kappa_F, lambda_min(H),
+sigma'_n and sigma_{n+1} are known exactly; constant-free magnitudes on the
+model problems against the values printed in Section 4).
 """
 from __future__ import annotations
 

@@ -15,18 +15,25 @@ Readings of the paper (each listed in the design notes):
   as in eq. (2) and Algorithm 4.
 * the k-th RQI runs PCGTLS with l = k, i.e. j = 0..k, k+1 steps (Section 2
   and the cost model of Section 3.2 count k+1 steps).
-* the PCGTLS loop also ends when delta_j = 0; delta_j < 0 means the shifted
+* the PCGTLS loop ends when delta_j = 0 (as printed) and also when
+  eta_j = 0 or delta_j, alpha_j is not finite (the step would divide zero
+  by zero or carry an overflow into omega); delta_j < 0 means the shifted
   system lost positive definiteness: the loop continues as printed, or
   raises ``IndefiniteError`` when ``strict`` is set.
+* the initial step (Algorithm 4, lines 1-5) is in the working precision u
+  = float64: u_0 = R^{-1} R^{-T} x_0 with float64 solves on the given
+  factor, independent of u_p.
 * termination (eq. 4): stop when psi_{k+1} > psi_k (``stop_ge`` uses >= as
   in Example 2); ``patience`` p stops after p consecutive iterations that
   do not improve on the best psi; the iterate with the smallest psi is
   returned.
 
 Pins: tests/test_oracle_rqi.py (Algorithm 1 equivalence with exact inner
-solves, Algorithm 3 special cases sigma = 0 and l >= n, first-step
-beta = sigma_0^2, convergence to the SVD solution on the paper's
-fixtures and the small dense workload).
+solves, Algorithm 3 special cases sigma = 0 (float64 and float32) and
+l >= n, the end of the loop at an underflowed eta and at a non-finite
+delta, first-step beta = sigma_0^2, the first iterate independent of u_p
+and equal to an LU solve on A^T A, convergence to the SVD solution on the
+paper's fixtures and the small dense workload).
 """
 from __future__ import annotations
 
@@ -124,12 +131,17 @@ def pcgtls(solve_R: Callable, solve_RT: Callable, sigma2: float, f: np.ndarray,
     """Algorithm 3, l-step PCGTLS for (A^T A - sigma^2 I) w = f.
 
     CG on the preconditioned matrix C = I - sigma^2 R^{-T} R^{-1} with the
-    solution carried back as w = R^{-1} y. Iterations j = 0, 1, ..., l
-    while delta_j != 0. All vectors and scalars are held in ``dtype``.
+    solution carried back as w = R^{-1} y. Iterations j = 0, 1, ..., l.
+    All vectors and scalars are held in ``dtype``.
 
-    The printed loop condition is delta_j != 0 only; a negative delta_j
-    (the shifted system is indefinite) is counted in the trace and the
-    iteration continues, unless ``strict`` asks for ``IndefiniteError``."""
+    When the loop ends early. The printed condition is delta_j != 0. Step j
+    also does not run when eta_j = 0 (s_j = 0 in the working precision:
+    omega_j already solves the system, and the next beta would be 0/0), or
+    when delta_j or alpha_j = eta_j / delta_j is not a finite number. The
+    check comes before the step's update, so a step either runs whole or
+    not at all. A negative delta_j (the shifted system is indefinite) is
+    counted in the trace and the iteration continues, unless ``strict``
+    asks for ``IndefiniteError``."""
     dt = np.dtype(dtype)
     s2 = dt.type(sigma2)
     f = np.asarray(f, dtype=dt)
@@ -141,25 +153,32 @@ def pcgtls(solve_R: Callable, solve_RT: Callable, sigma2: float, f: np.ndarray,
     steps = 0
     negatives = 0
     for _ in range(l + 1):
+        if eta == 0:                                 # s_j = 0: nothing left to solve
+            break
         q = np.asarray(solve_R(p), dtype=dt)         # q_j = R^{-1} p_j
         delta = dt.type(p @ p) - s2 * dt.type(q @ q)  # delta_j = ||p||^2 - sigma^2 ||q||^2
         deltas.append(float(delta))
-        if delta == 0:
+        if delta == 0 or not np.isfinite(delta):
+            break
+        with np.errstate(over="ignore"):
+            alpha = eta / delta                      # alpha_j
+        if not np.isfinite(alpha):
             break
         if delta < 0:
             if strict:
                 raise IndefiniteError(f"delta_{steps} = {float(delta):.3e} <= 0")
             negatives += 1
-        alpha = eta / delta                          # alpha_j
         omega = omega + alpha * q                    # omega_{j+1}
         q = np.asarray(solve_RT(q), dtype=dt)        # q_j = R^{-T} q_j
         s = s - alpha * (p - s2 * q)                 # s_{j+1}
         eta_new = dt.type(s @ s)                     # eta_{j+1}
+        etas.append(float(eta_new))
+        steps += 1
+        if eta_new == 0:                             # beta_j and p_{j+1} are not needed
+            break
         beta = eta_new / eta                         # beta_j
         p = s + beta * p                             # p_{j+1}
         eta = eta_new
-        etas.append(float(eta))
-        steps += 1
     if trace:
         return omega, PCGTrace(etas, deltas, steps, negatives)
     return omega
@@ -244,7 +263,13 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
     else:
         x = np.asarray(x0, dtype=np.float64).copy()
     r0, sig0_2 = rayleigh(mv, b, x)
-    u0 = np.asarray(solve_R(solve_RT(np.asarray(x, dtype=prec_p))), dtype=np.float64)
+    # Algorithm 4 runs the initial solve A^T A u_0 = x_0 in the working
+    # precision u (float64) with the factor as given, whatever u_p is
+    if R is not None:
+        u_R, u_RT = _tri_solvers(R)
+    else:
+        u_R, u_RT = solve_R, solve_RT
+    u0 = np.asarray(u_R(u_RT(x)), dtype=np.float64)
     x = x + sig0_2 * u0
     pcg_total = 2
     best = (math.inf, None, None, 0)

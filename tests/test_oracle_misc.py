@@ -32,6 +32,62 @@ def test_constraint_magnitudes_match_printed(gen):
         assert constraints.UNIT_ROUNDOFF["fp16"] < bd.bound6
 
 
+def _diag_problem(s, beta, m):
+    # A = [diag(s); 0] (m x n) and b = beta e_{n+1}, orthogonal to range(A):
+    # the singular values of [A, b] are those of A plus beta, so with
+    # beta < min(s), sigma_{n+1} = beta and sigma'_n = min(s) in closed form
+    n = len(s)
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = s
+    b = np.zeros(m)
+    b[n] = beta
+    return A, b
+
+
+def test_constraint_bounds_closed_form_diagonal():
+    # every bound of Section 3.1 on a diagonal A, where kappa = s_max/s_min,
+    # kappa_F = ||s||/s_min and H = D^{-1} A^T A D^{-1} = I (lambda_min = 1)
+    s = np.array([4.0, 2.0, 1.0, 0.5, 0.25])
+    m, n, beta = 9, 5, 0.1
+    A, b = _diag_problem(s, beta, m)
+    bd = constraints.bounds(A, b)
+    kap, kapF = 16.0, math.sqrt(float(s @ s)) / 0.25
+    gap = 1.0 - (beta / 0.25) ** 2
+    want = dict(kappa=kap, kappa_F=kapF, sigma_n_A=0.25, sigma=beta,
+                qr_nonsingular=1.0 / (m * n ** 1.5 * kap),
+                qr_probabilistic=1.0 / (math.sqrt(m) * n ** 0.75 * kap),
+                bound5=1.0 / kap, wilkinson=1.0 / (20.0 * n ** 1.5 * kap ** 2),
+                chol=kap ** -2.0, hp=1.0 / ((2.0 + n) * (n + 1)), bound6=gap / kapF)
+    for key, v in want.items():
+        assert getattr(bd, key) == pytest.approx(v, rel=1e-13), key
+    # scaled: A D^{-1} = [I; 0] has kappa = 1 and kappa_F = sqrt(n); sigma'_n
+    # and sigma_{n+1} stay those of (A, b)
+    sc = constraints.bounds(A, b, scaled=True)
+    assert sc.kappa == pytest.approx(1.0, rel=1e-14) and sc.kappa_F == pytest.approx(math.sqrt(n), rel=1e-14)
+    assert sc.sigma_n_A == pytest.approx(0.25, rel=1e-14) and sc.bound6 == pytest.approx(gap / math.sqrt(n), rel=1e-13)
+
+
+@pytest.mark.parametrize("c", [0.3, 0.9, -0.99])
+def test_constraint_hp_closed_form_two_columns(c):
+    # columns e_1 and (c, sqrt(1 - c^2), 0...): A^T A = [[1, c], [c, 1]] is
+    # already scaled, lambda_min(H) = 1 - |c|, kappa(A)^2 = (1 + |c|)/(1 - |c|)
+    m = 6
+    A = np.zeros((m, 2))
+    A[0, 0] = 1.0
+    A[0, 1], A[1, 1] = c, math.sqrt(1 - c * c)
+    b = np.zeros(m)
+    b[3] = 0.01
+    bd = constraints.bounds(A, b)
+    lam = 1.0 - abs(c)
+    k2 = (1.0 + abs(c)) / (1.0 - abs(c))
+    assert bd.hp == pytest.approx(lam / ((2 * lam + 2) * 3), rel=1e-10)
+    assert bd.chol == pytest.approx(1.0 / k2, rel=1e-10)
+    assert bd.wilkinson == pytest.approx(1.0 / (20 * 2 ** 1.5 * k2), rel=1e-10)
+    assert bd.kappa == pytest.approx(math.sqrt(k2), rel=1e-10)
+    # sigma'_n = sqrt(1 - |c|), sigma_{n+1} = 0.01
+    assert bd.sigma_n_A == pytest.approx(math.sqrt(lam), rel=1e-10) and bd.sigma == pytest.approx(0.01, rel=1e-12)
+
+
 def test_unit_roundoffs_table2():
     u = constraints.UNIT_ROUNDOFF
     assert abs(u["fp16"] - 4.88e-4) < 0.01e-4

@@ -3,8 +3,13 @@
 * Algorithm 2 with exact inner solves is inverse iteration on
   B = [A b]^T [A b] at the Rayleigh quotient shift, i.e. Algorithm 1,
   normalised to last component -1.
-* Algorithm 3 at sigma = 0 returns R^{-1} R^{-T} f after one step; with
-  l >= n steps it returns the dense solve of (A^T A - sigma^2 I) w = f.
+* Algorithm 3 at sigma = 0 returns R^{-1} R^{-T} f after one step (in
+  float64 and, to float32 rounding, in float32); with l >= n steps it
+  returns the dense solve of (A^T A - sigma^2 I) w = f. A right-hand side
+  whose eta underflows to zero ends the loop without a 0/0.
+* Algorithm 4 runs lines 1-5 in precision u: x_1 does not depend on u_p
+  and equals x_0 + sigma_0^2 (A^T A)^{-1} x_0 solved by LU on the Gram
+  matrix.
 * The body of Algorithm 2 at shift 0 from x_LS gives beta = sigma_0^2
   (lines 1-5 are that body).
 * RQI-PCGTLS converges to the SVD solution on the small workloads.
@@ -51,8 +56,81 @@ def test_pcgtls_sigma_zero_is_two_triangular_solves():
     w, tr = rqi.pcgtls(sR, sRT, 0.0, f, l=5, trace=True)
     expect = sla.solve_triangular(R, sla.solve_triangular(R, f, trans="T"))
     assert np.allclose(w, expect, rtol=1e-13, atol=0)
-    # s_1 = 0 -> eta_1 = 0 -> p_1 = 0 -> delta_1 = 0 ends the loop
-    assert tr.steps == 1 and tr.eta[1] == 0.0 and tr.delta[1] == 0.0
+    # alpha_0 = eta_0 / delta_0 = 1 exactly (p_0 = s_0, C = I), so s_1 = 0
+    # and eta_1 = 0 end the loop after one step
+    assert tr.steps == 1 and tr.eta[1] == 0.0 and len(tr.delta) == 1
+
+
+def test_pcgtls_fp32_sigma_zero_is_two_triangular_solves():
+    # the same identity in float32: one step, and the result is R^{-1} R^{-T} f
+    # to float32 rounding of two triangular solves (relative error of order
+    # n u_32 kappa(R)^2; kappa(R) is small here)
+    A, b, _ = tlsgen.dense_gaussian(60, 12, seed=7)
+    R = rqi.cholesky_R(A)
+    sR, sRT = rqi._tri_solvers(R, np.float32)
+    f = np.random.default_rng(4).standard_normal(12)
+    with np.errstate(all="raise"):
+        w, tr = rqi.pcgtls(sR, sRT, 0.0, f, l=6, dtype=np.float32, trace=True)
+    assert w.dtype == np.float32
+    expect = sla.solve_triangular(R, sla.solve_triangular(R, f, trans="T"))
+    kap = np.linalg.cond(R)
+    u32 = 2.0 ** -24
+    err = np.linalg.norm(w.astype(np.float64) - expect) / np.linalg.norm(expect)
+    assert err <= 4 * 12 * u32 * kap ** 2, (err, kap)
+    assert err > 0                                  # it did run in float32
+    assert tr.steps == 1 and tr.eta[1] == 0.0
+
+
+def test_pcgtls_eta_underflow_ends_without_nan():
+    # R = 1e-3 I, f = 1e-27: in float32 s_0 = R^{-T} f = 1e-24 has squares
+    # below the smallest subnormal, so eta_0 = 0 while s_0 != 0, and
+    # q_0 = R^{-1} p_0 = 1e-21 gives delta_0 = -sigma^2 ||q_0||^2, a nonzero
+    # subnormal. Run as printed, alpha_0 = -0, eta_1 = 0 and beta_0 = 0/0 is
+    # NaN. With the eta check the loop ends at once and returns omega = 0,
+    # the initial iterate.
+    n = 8
+    R = 1e-3 * np.eye(n)
+    sR, sRT = rqi._tri_solvers(R, np.float32)
+    f = np.full(n, 1e-27)
+    q0 = np.float32(1e-21)
+    assert np.float32(1e-24) ** 2 == 0 and n * q0 * q0 > 0   # the premise, in float32
+    with np.errstate(divide="raise", invalid="raise"):
+        w, tr = rqi.pcgtls(sR, sRT, 0.5, f, l=4, dtype=np.float32, trace=True)
+    assert np.all(w == 0) and tr.steps == 0 and tr.eta == [0.0] and tr.delta == []
+    # in float64 the same right-hand side is an ordinary solve: C = I - 0.5e6 I
+    # is negative definite, so one step along p_0 solves it (delta_0 < 0)
+    w64, tr64 = rqi.pcgtls(*rqi._tri_solvers(R), 0.5, f, l=4, trace=True)
+    ref = np.linalg.solve(R.T @ R - 0.5 * np.eye(n), f)
+    assert np.allclose(w64, ref, rtol=1e-12, atol=0) and tr64.negatives >= 1
+
+
+def test_pcgtls_nonfinite_delta_ends_before_the_update():
+    # sigma^2 so large that ||q||^2 sigma^2 overflows float32: delta_0 = -inf,
+    # the step must not run (it would put NaN into omega)
+    n = 4
+    R = 1e-20 * np.eye(n)
+    sR, sRT = rqi._tri_solvers(R, np.float32)
+    with np.errstate(all="ignore"):
+        w, tr = rqi.pcgtls(sR, sRT, 1e30, np.ones(n), l=3, dtype=np.float32, trace=True)
+    assert np.all(w == 0) and tr.steps == 0 and len(tr.delta) == 1
+    assert not np.isfinite(tr.delta[0])
+
+
+@pytest.mark.parametrize("prec_p", [np.float32, np.float16])
+def test_mixed_first_step_is_in_working_precision(prec_p):
+    # Algorithm 4, line 5: A^T A u_0 = x_0 is solved in u, so the first
+    # iterate x_1 = x_0 + sigma_0^2 u_0 is the same for every u_p; it is
+    # checked here against the textbook step with an LU solve on A^T A
+    A, b, _ = tlsgen.dense_gaussian(120, 10, seed=12)
+    R = rqi.cholesky_R(A)
+    plain = rqi.rqi_pcgtls(A, b, R, kmax=2, patience=5)
+    mixed = rqi.rqi_pcgtls(A, b, R, kmax=2, patience=5, prec_p=prec_p)
+    assert np.array_equal(plain.x_hist[0], mixed.x_hist[0])
+    x0 = rqi.csne_ls(A, b, R)
+    r0 = b - A @ x0
+    sig0 = r0 @ r0 / (1 + x0 @ x0)
+    x1 = x0 + sig0 * np.linalg.solve(A.T @ A, x0)
+    assert np.linalg.norm(mixed.x_hist[0] - x1) / np.linalg.norm(x1) < 1e-13
 
 
 def test_pcgtls_full_steps_is_dense_solve():
