@@ -310,13 +310,17 @@ TLS_API tls_status tls_precond_export(const tls_precond P, double *R_host, doubl
 
 TLS_API size_t tls_pcg_workspace_size(const tls_precond P, int32_t nrhs, int32_t l);
 
-/* Run j = 0..l while delta_j != 0 on nrhs (1 or 2) right-hand sides sharing
- * sigma2. rhs and omega are n x nrhs column-major FP64 (device). u_p is the
- * arithmetic precision (TLS_FP64 or TLS_FP32). trace (host, may be NULL)
- * receives, per right-hand side r, 4*(l+2) doubles at offset 4*(l+2)*r:
+/* Run j = 0..l on nrhs (1 or 2) right-hand sides sharing sigma2. A
+ * right-hand side stops before step j when eta_j = 0 (its residual is zero in
+ * the working precision), or when delta_j = 0 (the printed condition) or
+ * delta_j or alpha_j = eta_j / delta_j is not finite; a step runs whole or
+ * not at all, so omega never takes a NaN from 0/0. rhs and omega are
+ * n x nrhs column-major FP64 (device). u_p is the arithmetic precision
+ * (TLS_FP64 or TLS_FP32). trace (host, may be NULL) receives, per
+ * right-hand side r, 4*(l+2) doubles at offset 4*(l+2)*r:
  * eta_0..eta_{l+1}, delta_0..delta_{l+1}, alpha_0.., beta_0.. (NaN where a
- * step did not run). delta_j < 0 is returned as TLS_ERR_INDEFINITE only when
- * strict_pd is set; otherwise the iteration continues as printed. */
+ * value was not formed). delta_j < 0 is returned as TLS_ERR_INDEFINITE only
+ * when strict_pd is set; otherwise the iteration continues as printed. */
 TLS_API tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs,
                         const double *rhs, double *omega, int32_t l, int32_t u_p,
                         int32_t strict_pd, void *ws, size_t ws_bytes,

@@ -349,7 +349,10 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
   __shared__ C s_v[NW][NR][NB];      // per-wave input block
   __shared__ C s_acc[NW][NR][NB];
   __shared__ C s_scal[NR][4];
-  __shared__ int s_live[NR], s_last, s_skip;
+  // s_live: step j-1 ran for this right-hand side (it is still iterating);
+  // s_run: step j runs (eta_j != 0 and, forward, delta_j and alpha_j finite
+  // and delta_j != 0)
+  __shared__ int s_live[NR], s_run[NR], s_last, s_skip;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
   const int I = blockIdx.x, sidx = ROW ? 0 : blockIdx.y, CH = ROW ? 1 : gridDim.y;
@@ -430,18 +433,27 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
   if constexpr (MODE == XB || MODE == XF) {
     if (w == 1) {
       for (int r = 0; r < NR; ++r) {
+        // eta_j = 0 ends the loop before step j (s_j = 0 in the working
+        // precision: omega_j already solves the system and beta_j would be
+        // 0/0); a step whose delta_j or alpha_j is zero or not finite does
+        // not run either, so omega never takes a NaN
         const C eta = xsum_parts(xpart_ptr(P.part, P.j, 0, r, NR, N), N);
         if constexpr (MODE == XB) {
           C beta = 0;
-          if (P.j > 0) beta = eta / xsum_parts(xpart_ptr(P.part, P.j - 1, 0, r, NR, N), N);
-          if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; }
+          if (P.j > 0) {
+            const C eta_prev = xsum_parts(xpart_ptr(P.part, P.j - 1, 0, r, NR, N), N);
+            if (eta_prev != (C)0) beta = eta / eta_prev;
+          }
+          if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; s_run[r] = (eta != (C)0); }
         } else {
           const C pp = xsum_parts(xpart_ptr(P.part, P.j, 1, r, NR, N), N);
           const C qq = xsum_parts(xpart_ptr(P.part, P.j, 2, r, NR, N), N);
           const C sig2 = (C)(*P.sigma2);
           const C delta = pp - sig2 * qq;
+          const C alpha = eta / delta;
           if (lane == 0) {
-            s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = eta / delta; s_scal[r][3] = sig2;
+            s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = alpha; s_scal[r][3] = sig2;
+            s_run[r] = (eta != (C)0) && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
           }
         }
       }
@@ -552,7 +564,7 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
       const C qv = e_ds * x;                          // q = D^{-1} X p
       C pv = e_p[r];
       if (P.j > 0) pv = e_s[r] + s_scal[r][1] * e_po[r];
-      if (s_live[r]) {
+      if (s_live[r] && s_run[r]) {
         P.q[vi] = qv;
         if (P.j > 0) p_cur[vi] = pv;
       }
@@ -562,9 +574,8 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
         xpart_ptr(P.part, P.j, 2, r, NR, N)[I] = qq;
       }
     } else {   // XF: x = t = X^T D^{-1} q
-      const C delta = s_scal[r][1];
       C sv = e_s[r];
-      if (s_live[r] && delta != (C)0) {
+      if (s_live[r] && s_run[r]) {
         P.w[vi] = e_w[r] + s_scal[r][2] * e_q[r];                 // omega_{j+1}
         sv = sv - s_scal[r][2] * (e_p[r] - s_scal[r][3] * x);     // s_{j+1}
         P.s[vi] = sv;
@@ -581,17 +592,17 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
       if constexpr (MODE == XB) {
         if (s_live[r]) {
           tr[0 * L2 + j] = (double)s_scal[r][0];
-          if (j > 0) tr[3 * L2 + j - 1] = (double)s_scal[r][1];
+          if (j > 0 && s_run[r]) tr[3 * L2 + j - 1] = (double)s_scal[r][1];
         }
       } else {
         const C delta = s_scal[r][1];
         const int was = (j > 0) ? P.done[(j - 1) * NR + r] : 0;
         int now = was;
         if (!was) {
-          tr[1 * L2 + j] = (double)delta;
-          if (delta != (C)0) tr[2 * L2 + j] = (double)s_scal[r][2];
-          if (delta == (C)0) now = 1;
-          if (delta < (C)0) {
+          if (s_scal[r][0] != (C)0) tr[1 * L2 + j] = (double)delta;
+          if (s_run[r]) tr[2 * L2 + j] = (double)s_scal[r][2];
+          if (!s_run[r]) now = 1;
+          if (s_run[r] && delta < (C)0) {
             P.neg[j * NR + r] = 1;
             if (P.strict) {
               now = 1;

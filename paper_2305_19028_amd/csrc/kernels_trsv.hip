@@ -84,7 +84,9 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
   __shared__ C s_part[4][NR][NB];
   __shared__ C s_rhs[NR][NB];
   __shared__ C s_scal[NR][4];
-  __shared__ int s_live[NR];
+  // s_live: step j-1 ran for this right-hand side; s_run: step j runs
+  // (eta_j != 0 and, forward, delta_j and alpha_j finite and delta_j != 0)
+  __shared__ int s_live[NR], s_run[NR];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
@@ -121,15 +123,17 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
     // ---- step-level scalars (identical in every workgroup) --------------
     if constexpr (MODE == PCG_B || MODE == PCG_F) {
       if (w == 0) {
+        // eta_j = 0 ends the loop before step j (beta_j would be 0/0);
+        // a step whose delta_j or alpha_j is zero or not finite does not run
         for (int r = 0; r < NR; ++r) {
           const C eta = sum_parts(part_ptr(P.part, P.j, 0, r, NR, N), N);
           if constexpr (MODE == PCG_B) {
             C beta = 0;
             if (P.j > 0) {
               const C eta_prev = sum_parts(part_ptr(P.part, P.j - 1, 0, r, NR, N), N);
-              beta = eta / eta_prev;
+              if (eta_prev != (C)0) beta = eta / eta_prev;
             }
-            if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; }
+            if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; s_run[r] = (eta != (C)0); }
           } else {
             const C pp = sum_parts(part_ptr(P.part, P.j, 1, r, NR, N), N);
             const C qq = sum_parts(part_ptr(P.part, P.j, 2, r, NR, N), N);
@@ -138,6 +142,7 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
             const C alpha = eta / delta;
             if (lane == 0) {
               s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = alpha; s_scal[r][3] = sig2;
+              s_run[r] = (eta != (C)0) && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
             }
           }
         }
@@ -205,15 +210,14 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
             y = (row < P.n) ? P.dscale[row] * (C)P.in[(size_t)r * P.ldi + row] : (C)0;
           } else if constexpr (MODE == PCG_B) {
             C pv = P.p[vi];
-            if (P.j > 0 && s_live[r]) {
+            if (P.j > 0 && s_live[r] && s_run[r]) {
               pv = P.s[vi] + s_scal[r][1] * pv;        // p_{j} = s_j + beta_{j-1} p_{j-1}
               P.p[vi] = pv;
             }
             y = pv;
           } else {  // PCG_F
             const C qv = P.q[vi];
-            const C delta = s_scal[r][1];
-            if (s_live[r] && delta != (C)0) P.w[vi] += s_scal[r][2] * qv;   // omega_{j+1}
+            if (s_live[r] && s_run[r]) P.w[vi] += s_scal[r][2] * qv;       // omega_{j+1}
             y = P.dscale[row] * qv;                                       // R^{-T} q = R_hat^{-T} D^{-1} q
           }
           s_rhs[r][lane] = y - (s_part[0][r][lane] + s_part[1][r][lane] + s_part[2][r][lane] +
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
           } else if constexpr (MODE == PCG_B) {
             const C qv = P.dscale[row] * x;        // q = R^{-1} p = D^{-1} R_hat^{-1} p
             const C pv = P.p[vi];
-            if (s_live[r]) P.q[vi] = qv;
+            if (s_live[r] && s_run[r]) P.q[vi] = qv;
             const C pp = wave_sum(pv * pv);
             const C qq = wave_sum(qv * qv);
             if (lane == 0) {
@@ -268,8 +272,7 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
             }
           } else {  // PCG_F: x = t = R^{-T} q
             C sv = P.s[vi];
-            const C delta = s_scal[r][1];
-            if (s_live[r] && delta != (C)0) {
+            if (s_live[r] && s_run[r]) {
               sv = sv - s_scal[r][2] * (P.p[vi] - s_scal[r][3] * x);   // s_{j+1}
               P.s[vi] = sv;
             }
@@ -286,17 +289,17 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
           if constexpr (MODE == PCG_B) {
             if (s_live[r]) {
               tr[0 * L2 + j] = (double)s_scal[r][0];
-              if (j > 0) tr[3 * L2 + j - 1] = (double)s_scal[r][1];
+              if (j > 0 && s_run[r]) tr[3 * L2 + j - 1] = (double)s_scal[r][1];
             }
           } else {
             const C delta = s_scal[r][1];
             const int was = (j > 0) ? P.done[(j - 1) * NR + r] : 0;
             int now = was;
             if (!was) {
-              tr[1 * L2 + j] = (double)delta;
-              if (delta != (C)0) tr[2 * L2 + j] = (double)s_scal[r][2];
-              if (delta == (C)0) now = 1;
-              if (delta < (C)0) {
+              if (s_scal[r][0] != (C)0) tr[1 * L2 + j] = (double)delta;
+              if (s_run[r]) tr[2 * L2 + j] = (double)s_scal[r][2];
+              if (!s_run[r]) now = 1;
+              if (s_run[r] && delta < (C)0) {
                 P.neg[j * NR + r] = 1;
                 if (P.strict) {
                   now = 1;

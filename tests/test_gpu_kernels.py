@@ -191,7 +191,33 @@ def test_pcg_sigma_zero_and_single_rhs(mode):
     out, tr = tls.tls_pcg_step(P, 0.0, f, 4, trace=True)
     ref = sla.solve_triangular(R, sla.solve_triangular(R, f, trans="T"))
     assert np.allclose(out.cpu().numpy()[0], ref, rtol=1e-12)
-    assert tr["delta"][0][1] == 0.0        # the loop ends at j = 1
+    # alpha_0 = 1 exactly (C = I), so eta_1 = 0 ends the loop before step 1:
+    # delta_1 is never formed
+    assert tr["eta"][0][1] == 0.0 and np.isnan(tr["delta"][0][1])
+
+
+@pytest.mark.parametrize("mode", ["inverse", "inverse_rows", "substitution"])
+def test_pcg_eta_underflow_ends_cleanly(mode):
+    # the oracle's float32 case: R = 1e-3 I, f = 1e-27. s_0 = 1e-24 squares
+    # below the smallest float32 subnormal, so eta_0 = 0 while s_0 != 0. Run
+    # as printed, the next beta is 0/0 and omega turns NaN; with the eta check
+    # the loop ends before step 0 and omega stays 0 (the oracle's result)
+    tls = _tls()
+    n = 8
+    R = 1e-3 * np.eye(n)
+    P = tls.tls_precond_import(R, None, "fp64")
+    P.set_apply(mode)
+    f = np.full((2, n), 1e-27)
+    sR, sRT = rqi._tri_solvers(R, np.float32)
+    with np.errstate(divide="raise", invalid="raise"):
+        w_ref, t_ref = rqi.pcgtls(sR, sRT, 0.5, f[0], l=4, dtype=np.float32, trace=True)
+    out, tr = tls.tls_pcg_step(P, 0.5, f, 4, "fp32", trace=True)
+    out = out.cpu().numpy()
+    assert t_ref.steps == 0 and np.all(w_ref == 0)
+    assert np.all(out == 0.0), out
+    for r in range(2):
+        assert tr["eta"][r][0] == 0.0 and np.all(np.isnan(tr["delta"][r]))
+        assert np.all(np.isnan(tr["alpha"][r]))
 
 
 @pytest.mark.parametrize("case", ["dense_small", "dense_ragged", "sparse"])
