@@ -326,6 +326,24 @@ TLS_API tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs
                         int32_t strict_pd, void *ws, size_t ws_bytes,
                         hipStream_t stream, double *trace);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as tls_pcg_step, with its workspace taken from a static device
+ * array of TLS_PCG_NOALLOC_MAX_BYTES per GPU instead of a caller workspace.
+ * The array is resolved to its device address on the first call on each
+ * device (that device current) and held until the process ends. The call
+ * allocates nothing itself (no hipMalloc/hipFree, no pinned memory); leave
+ * tls_profile_start off around it, since the profiler creates events.
+ * Calls whose tls_pcg_workspace_size(P, nrhs, l) exceeds the maximum return
+ * TLS_ERR_WORKSPACE (e.g. n <= 8192 with l <= 1024 fits). Every call on one
+ * GPU shares its array: calls that overlap in time on one GPU (two streams,
+ * two threads) race and must be serialized by the caller. The state that
+ * must start at zero is cleared by the call itself, on `stream`. */
+#define TLS_PCG_NOALLOC_MAX_BYTES ((size_t)16 << 20)
+TLS_API tls_status tls_pcg_step_noalloc(const tls_precond P, double sigma2, int32_t nrhs,
+                        const double *rhs, double *omega, int32_t l, int32_t u_p,
+                        int32_t strict_pd, hipStream_t stream, double *trace);
+
 /* out = R^{-1} in (trans = 0) or R^{-T} in (trans = 1) for nrhs column-major
  * FP64 vectors, computed in u_p (forward/backward substitution, Table 1). */
 TLS_API tls_status tls_apply_precond(const tls_precond P, int32_t trans, int32_t nrhs,

@@ -1118,6 +1118,41 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// static PCGTLS scratch for tls_pcg_step_noalloc (callers that cannot
+// allocate): one array per device, resolved once per device to its device
+// address. The host-side name `scratch` is only a stand-in for the symbol;
+// kernels and fills always get the resolved address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[TLS_PCG_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// address of the current device's copy of `scratch`, looked up with that
+// device current on its first use and kept for the life of the process
+tls_status pcg_scratch_of_current_device(void **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(TLS_ERR_ARG, "device ordinal %d beyond the %d the static scratch table holds", dev,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) return fail(TLS_ERR_HIP, "static scratch address not 256-byte aligned");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TLS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
@@ -1241,6 +1276,28 @@ tls_status tls_pcg_step(const tls_precond P, double sigma2, int32_t nrhs, const 
       }
     }
     return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
+tls_status tls_pcg_step_noalloc(const tls_precond P, double sigma2, int32_t nrhs, const double *rhs,
+                                double *omega, int32_t l, int32_t u_p, int32_t strict_pd,
+                                hipStream_t stream, double *trace) {
+  try {
+    if (!P) return fail(TLS_ERR_ARG, "P is NULL");
+    if (nrhs < 1 || nrhs > 2) return fail(TLS_ERR_ARG, "nrhs must be 1 or 2");
+    if (l < 0 || l > 4096) return fail(TLS_ERR_ARG, "l out of range");
+    const size_t need = tls_pcg_workspace_size(P, nrhs, l);
+    if (need > TLS_PCG_NOALLOC_MAX_BYTES)
+      return fail(TLS_ERR_WORKSPACE,
+                  "PCGTLS for n = %lld, nrhs = %d, l = %d needs %zu bytes of scratch; the static "
+                  "scratch holds %zu (use tls_pcg_step with a workspace)",
+                  (long long)P->n, (int)nrhs, (int)l, need, (size_t)TLS_PCG_NOALLOC_MAX_BYTES);
+    void *ws = nullptr;
+    TRY(pcg_scratch_of_current_device(&ws));
+    return tls_pcg_step(P, sigma2, nrhs, rhs, omega, l, u_p, strict_pd, ws,
+                        (size_t)TLS_PCG_NOALLOC_MAX_BYTES, stream, trace);
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
   }

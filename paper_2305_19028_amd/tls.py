@@ -146,6 +146,9 @@ _SIGS = {
     "tls_pcg_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
                                C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
                                C.c_void_p, C.c_void_p]),
+    "tls_pcg_step_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                       C.c_void_p]),
     "tls_apply_precond": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tls_matvec": (C.c_int, [C.POINTER(c_matrix), C.c_void_p, C.c_int32, C.c_void_p,
@@ -393,6 +396,25 @@ def tls_pcg_step(P: Precond, sigma2: float, rhs, l: int, u_p="fp64", strict=Fals
     _check(L.tls_pcg_step(P.handle, float(sigma2), nrhs, _ptr(R), _ptr(out), int(l), _prec(u_p),
                           int(strict), ws.ptr, ws.nbytes, _stream(),
                           tr.ctypes.data_as(C.c_void_p) if trace else None))
+    tdict = None
+    if trace:
+        tr = tr.reshape(nrhs, 4, l + 2)
+        tdict = {"eta": tr[:, 0], "delta": tr[:, 1], "alpha": tr[:, 2], "beta": tr[:, 3]}
+    return out, tdict
+
+
+def tls_pcg_step_noalloc(P: Precond, sigma2: float, rhs, l: int, u_p="fp64", strict=False,
+                         trace=False):
+    """tls_pcg_step with the library's static scratch in place of a workspace
+    (no device allocation inside the call). Returns (omega, trace dict or None)."""
+    n = P.n
+    R = _as_cols(rhs, n)
+    nrhs = R.shape[0]
+    out = _torch().empty_like(R)
+    tr = np.full(nrhs * 4 * (l + 2), np.nan) if trace else None
+    _check(lib().tls_pcg_step_noalloc(P.handle, float(sigma2), nrhs, _ptr(R), _ptr(out), int(l),
+                                      _prec(u_p), int(strict), _stream(),
+                                      tr.ctypes.data_as(C.c_void_p) if trace else None))
     tdict = None
     if trace:
         tr = tr.reshape(nrhs, 4, l + 2)
