@@ -3,24 +3,27 @@ mixed-precision path vs the plain FP64 GPU path, with the roofline of the
 dominant kernel and the CPU oracle timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                    [--workload sparse_20000x2000 | dense_planted_65536x4096]
+                    [--workload dense_65536x4096 | sparse_20000x2000 |
+                                dense_planted_65536x4096] [--sweep]
 
-Default workload: sparse CSR A 20000 x 2000 with 0.5% nonzeros at uniformly
-random positions, N(0,1) values times log-uniform column scales in
-[1, 1e4], b = A x_true + 1e-4 N(0,1) (seed 2000), resident on the device.
-Reference: the stored oracle answer (tests/golden/sparse_c2_ref.json).
-  plain FP64 path : u_q = FP64 factor, u_p = FP64 PCGTLS
-  mixed path      : u_q = FP16 factor (scaled), u_p = FP32 PCGTLS, FP64 outer,
-                    gate and certificate enforced, FP64 refinement sweep
-
-Second workload (not the default line): dense 65536 x 4096 with a planted
-SVD, sigma'_i geometric from 1 to 1e-3 and sigma_{n+1} = 3.9e-5 (exact
-reference by the closed form); mixed path with an FP16 factor from the
-matrix-core Gram (the BF16 factor is reported beside it).
+Default workload (the line): dense A 65536 x 4096 = Y diag(s) Z^T + E with
+single Householder reflectors Y, Z, s geometric from 1 to 1e-3, E of
+spectral size 1e-5, b = A x_true + 1e-5 N(0,1) (seed 3000), column-major
+FP64, resident on the device. Reference: the stored oracle answer
+(tests/golden/dense_c3_ref.json: plain float64 RQI-PCGTLS, long-double
+Newton polish and certificates, written by tests/golden/make_golden.py).
+  plain FP64 path : u_q = FP64 factor (FP64 matrix-core Gram), u_p = FP64
+  mixed path      : u_q = BF16 factor (BF16 matrix-core Gram, FP32 accumulation,
+                    scaled), u_p = FP32 PCGTLS, FP64 outer; gate and factor
+                    certificate enforced, FP64 refinement sweep
+Beside it: the FP16 and FP32 factors and the FP32 Householder QR factor on the
+same matrix, and the sparse 20000 x 2000 workload's two paths.
 
 One step = one whole solve: tls_factor_precond + tls_rqi_solve. Both paths
-use the same stopping rule (psi, patience 2); `value` is the time from the
-factorization's enqueue to the first iterate within 1e-10 of the reference.
+use the same stopping rule (psi, patience 2). `value` is the mixed path's
+time from the factorization's enqueue to the later of (a) the host's read of
+the first iterate within 1e-10 of the reference and (b) the host's read of
+the gate's verdict on the factor (the iterate is only usable from then on).
 """
 
 from __future__ import annotations
@@ -43,16 +46,26 @@ COPY_BYTES = 256 << 20
 TOL = 1e-10
 GATED = dict(gate_enforce=1, allow_escalate=1, refine_sweeps=1)
 WORKLOADS = {
+    "dense_65536x4096": {
+        "describe": "dense 65536x4096 = Y diag(s) Z^T + E, single Householder reflectors, s geometric "
+                    "1..1e-3, E spectral size 1e-5, b = A x_true + 1e-5 N(0,1), seed 3000",
+        "golden": "dense_c3_ref.json",
+        "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
+                  # BF16 Gram on the matrix cores with FP32 accumulation, FP32
+                  # Cholesky and PCGTLS, FP64 outer iteration; the gate checks
+                  # the factor per instance before its result is used
+                  "mixed": dict(u_q="bf16", u_p="fp32", opts=GATED)},
+        "dtype": "bf16 factor (MFMA Gram, f32 accumulation) / f32 PCG / f64 outer",
+        "variants": {"fp16_factor": dict(u_q="fp16", u_p="fp32", opts=GATED),
+                     "fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED),
+                     "qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
+    },
     "sparse_20000x2000": {
         "describe": "sparse CSR 20000x2000, 0.5% nnz, column scales logU[1,1e4], b noise 1e-4, seed 2000",
+        "golden": "sparse_c2_ref.json",
         "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
-                  # the gate (constraint checks and the factor certificate) runs per
-                  # instance before the FP16 factor is used; FP64 refinement on
                   "mixed": dict(u_q="fp16", u_p="fp32", opts=GATED)},
         "dtype": "f16 factor / f32 PCG / f64 outer",
-        # reported beside the line, not the headline: the FP32 factor (same
-        # FP32 Cholesky arithmetic, FP32 storage) needs fewer RQI iterations;
-        # the Householder QR factor (Section 3's choice) in FP16 and FP32
         "variants": {"fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED),
                      "qr_fp16": dict(u_q="fp16", u_p="fp32", opts=GATED, method="qr"),
                      "qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
@@ -62,13 +75,10 @@ WORKLOADS = {
         "paths": {"fp64": dict(u_q="fp64", u_p="fp64", opts={}),
                   "mixed": dict(u_q="fp16", u_p="fp32", opts=GATED)},
         "dtype": "f16 factor (MFMA Gram) / f32 PCG / f64 outer",
-        # BF16 (same matrix-core rate, 8 significand bits against 11) needs more RQIs
-        "variants": {"bf16_factor": dict(u_q="bf16", u_p="fp32", opts=GATED),
-                     "qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
+        "variants": {"bf16_factor": dict(u_q="bf16", u_p="fp32", opts=GATED)},
     },
 }
-WORKLOAD = "sparse_20000x2000"
-PATHS = WORKLOADS[WORKLOAD]["paths"]
+WORKLOAD = "dense_65536x4096"
 
 
 def parse():
@@ -77,9 +87,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the sparse 20000x2000 lines reported beside the headline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-only", action="store_true",
                     help="a few solves of each path, no CPU leg (for rocprofv3 runs)")
+    ap.add_argument("--paths", default=None,
+                    help="comma-separated paths/variants for --profile-only (default: all)")
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--sweep", action="store_true",
                     help="measured speedup over a size grid of dense planted-SVD problems "
@@ -87,16 +101,27 @@ def parse():
     return ap.parse_args()
 
 
+def golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        return json.load(f)
+
+
 def make_problem(workload):
-    """(A, b, x_ref, sigma_ref) of the workload."""
+    """(A, b, x_ref, sigma_ref, tol_x) of the workload; tol_x is 1e-10, or ten
+    times the attainable float64 accuracy u kappa_TLS where that is larger."""
     import tlsgen
+    if workload == "dense_planted_65536x4096":
+        A, b, x, s = planted_dense(65536, 4096, seed=3100)
+        return A, b, x, s, TOL
     if workload == "sparse_20000x2000":
         A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
-        with open(os.path.join(ROOT, "tests", "golden", "sparse_c2_ref.json")) as f:
-            ref = json.load(f)
-        return A, b, np.array(ref["x"]), float(ref["sigma"])
-    # v = (I - 2 w w^T) e_{n+1} is the right singular vector of sigma_{n+1}
-    return planted_dense(65536, 4096, seed=3100)
+    else:
+        A, b, _, _ = tlsgen.reflector_dense(65536, 4096, seed=3000)
+    ref = golden(WORKLOADS[workload]["golden"])
+    tol = TOL
+    if "bounds" in ref:
+        tol = max(TOL, 10 * ref["bounds"]["attainable_x"])
+    return A, b, np.array(ref["x"]), float(ref["sigma"]), tol
 
 
 def planted_dense(m, n, seed):
@@ -118,43 +143,30 @@ def sweep(tls, torch, steps, warmup):
     SWEEP, with the RQI counts r each needed (iterations up to the first
     iterate within tolerance), so the measured speedup can be set against
     the operation-count model of Section 3.2 at the same r."""
-    global PATHS
-    PATHS = WORKLOADS["dense_planted_65536x4096"]["paths"]
+    paths = WORKLOADS["dense_planted_65536x4096"]["paths"]
     for m, n in SWEEP:
         A, b, xref, sref = planted_dense(m, n, seed=3100 + n)
         Ad = tls.dense(A)
         bd = tls.device_vector(b)
-        snaps = torch.zeros((40, n), dtype=torch.float64, device="cuda")
         out = {"m": m, "n": n}
         for path in ("fp64", "mixed"):
-            for _ in range(warmup):
-                one_solve(tls, torch, Ad, bd, path)
-            ttts, rs, fs = [], [], []
-            for _ in range(steps):
-                P, x, sigma, st, tf, ts, rep = one_solve(tls, torch, Ad, bd, path, snaps)
-                xs = snaps[: st["iters"]].cpu().numpy()
-                k = next((k for k in range(st["iters"])
-                          if np.linalg.norm(xs[k] - xref) <= TOL * np.linalg.norm(xref)), None)
-                ttts.append(tf + st["t_ms"][k] if k is not None else float("nan"))
-                rs.append(k + 1 if k is not None else None)
-                fs.append(tf)
-            out[path] = {"time_to_tol_ms": statistics.median(ttts), "factor_ms": statistics.median(fs),
-                         "r": rs[-1], "err_sigma": abs(sigma - sref) / sref}
+            r = run_path(tls, torch, Ad, bd, paths[path], steps, warmup, xref, sref, TOL)
+            out[path] = {"time_to_tol_ms": r["time_to_tol_ms"], "factor_ms": r["factor_ms"],
+                         "r": r["r_first"], "err_sigma": r["err_sigma"]}
         out["speedup_time_to_tol"] = out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"]
         print(json.dumps({"sweep": "dense planted SVD, mixed = FP16 factor / FP32 PCG / gate", **out}),
               flush=True)
-        del Ad, bd, snaps
+        del Ad, bd
         torch.cuda.empty_cache()
 
 
-def one_solve(tls, torch, Ad, bd, path, snaps=None):
+def one_solve(tls, torch, Ad, bd, cfg, snaps=None):
     """Factor and solve. The gate of a low-precision factor is left running
-    on the library's side streams when the factorization call returns
+    on the library's side stream when the factorization call returns
     (wait_gate=False) and overlaps the solve, which reads its verdict before
-    it returns; so the factor time (the call plus the rest of its own stream)
-    excludes the gate and the solve time includes whatever of it was not
-    hidden."""
-    cfg = PATHS[path]
+    it returns (stats t_verdict_ms); so the factor time (the call plus the
+    rest of its own stream) excludes the gate and the solve time includes
+    whatever of it was not hidden."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     factor = tls.tls_factor_precond_qr if cfg.get("method") == "qr" else tls.tls_factor_precond
@@ -174,46 +186,62 @@ def rel_errs(x, sigma, xref, sref):
     return abs(sigma - sref) / sref, float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
 
 
-def run_path(tls, torch, Ad, bd, path, steps, warmup, xref, sref):
+def run_path(tls, torch, Ad, bd, cfg, steps, warmup, xref, sref, tol):
+    """Median times over `steps` solves after `warmup`. time_to_tol: factor
+    call + the later of the first iterate within tol and the gate's verdict;
+    first_crossing: the same without the verdict (labelled, not the line)."""
     n = Ad.n
     snaps = torch.zeros((40, n), dtype=torch.float64, device="cuda")
     for _ in range(warmup):
-        one_solve(tls, torch, Ad, bd, path)
-    totals, ttts, factors = [], [], []
+        one_solve(tls, torch, Ad, bd, cfg)
+    totals, ttts, firsts, factors, verdicts = [], [], [], [], []
     last = None
+    kstar = None
     for _ in range(steps):
-        P, x, sigma, st, tf, ts, rep = one_solve(tls, torch, Ad, bd, path, snaps)
+        P, x, sigma, st, tf, ts, rep = one_solve(tls, torch, Ad, bd, cfg, snaps)
         totals.append(tf + ts)
         factors.append(tf)
-        # first iterate whose x is within TOL (sigma at such an x is accurate to
+        verdicts.append(tf + st["t_verdict_ms"])
+        # first iterate whose x is within tol (sigma at such an x is accurate to
         # second order; the final sigma is checked separately)
         xs = snaps[: st["iters"]].cpu().numpy()
         kstar = None
+        nref = np.linalg.norm(xref)
         for k in range(st["iters"]):
-            if np.linalg.norm(xs[k] - xref) / np.linalg.norm(xref) <= TOL:
+            if np.linalg.norm(xs[k] - xref) <= tol * nref:
                 kstar = k
                 break
-        ttts.append(tf + st["t_ms"][kstar] if kstar is not None else float("nan"))
+        if kstar is None:
+            ttts.append(float("nan"))
+            firsts.append(float("nan"))
+        else:
+            firsts.append(tf + st["t_ms"][kstar])
+            ttts.append(tf + max(st["t_ms"][kstar], st["t_verdict_ms"]))
         last = (x.cpu().numpy(), sigma, st, rep)
     x, sigma, st, rep = last
     es, ex = rel_errs(x, sigma, xref, sref)
+    ok = all(math.isfinite(t) for t in ttts)
     return {
         "ms_median": statistics.median(totals), "ms_min": min(totals),
-        "time_to_tol_ms": statistics.median(ttts) if all(math.isfinite(t) for t in ttts) else None,
+        "time_to_tol_ms": statistics.median(ttts) if ok else None,
+        "time_to_tol_min_ms": min(ttts) if ok else None,
+        "first_crossing_ms": statistics.median(firsts) if ok else None,
+        "verdict_ms": statistics.median(verdicts) if cfg["u_q"] != "fp64" else None,
         "factor_ms": statistics.median(factors),
-        "rqi_iters": st["iters"], "pcg_steps": st["pcg_steps"], "k_best": st["k_best"],
+        "rqi_iters": st["iters"], "r_first": (kstar + 1) if kstar is not None else None,
+        "pcg_steps": st["pcg_steps"], "k_best": st["k_best"],
         "err_sigma": es, "err_x": ex, "gate_verdict": rep["verdict"],
-        "gate_async": st["gate_async"],
+        "gate_async": st["gate_async"], "u_q_used": rep.get("used"),
         "kappa_est": rep["kappa_est"],
     }
 
 
-def kernel_profile(tls, torch, Ad, bd, path, reps=3):
+def kernel_profile(tls, torch, Ad, bd, cfg, reps=3):
     """Per-kernel-class launch counts and average durations (HIP events on the
     launch stream), over `reps` full solves."""
     tls.tls_profile_start()
     for _ in range(reps):
-        one_solve(tls, torch, Ad, bd, path)
+        one_solve(tls, torch, Ad, bd, cfg)
     prof = tls.tls_profile_stop()
     return {k: {"launches": v[0] // reps, "ms_per_solve": v[1] / reps,
                 "avg_us": (v[1] / v[0] * 1e3) if v[0] else 0.0} for k, v in prof.items() if v[0]}
@@ -229,13 +257,16 @@ PEAKS = {  # MI355X published peaks
     "mfma_16": (2500.0, "TFLOP/s"),  # BF16 / FP16 dense matrix
 }
 SIZE = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+# working sets at or below this size can be served from the 256 MB
+# Infinity Cache: such kernels are reported against HBM peak and flagged
+MALL_BYTES = 256 << 20
 
 
-def class_work(cls, path, m, n, nnz, launches):
+def class_work(cls, cfg, m, n, nnz, launches):
     """Algorithmic work of one kernel class over one solve: (bound, amount in
-    bytes or flops, description). `launches` is the class's launch count per
-    solve (from the HIP-event profile). None for latency-only classes."""
-    cfg = PATHS[path]
+    bytes or flops, description, working-set bytes). `launches` is the
+    class's launch count per solve (from the HIP-event profile). None for
+    latency-only classes."""
     Np = -(-n // NB) * NB
     N = Np // NB
     tri = n * (n + 1) // 2
@@ -246,95 +277,225 @@ def class_work(cls, path, m, n, nnz, launches):
         # one application of X or X^T to the two PCG right-hand sides: the
         # triangle once, 2 vectors in and out, the fused scalar partials
         per = tri * bx + 2 * 2 * n * bp
-        return "hbm", per * launches, f"X triangle {tri}x{bx} B + 2-RHS vectors per launch"
+        return "hbm", per * launches, f"X triangle {tri}x{bx} B + 2-RHS vectors per launch", tri * bx
     if cls == "precond_apply":
         per = tri * bx + 2 * n * 8
-        return "hbm", per * launches, f"X triangle {tri}x{bx} B + FP64 vector in/out per launch"
+        return "hbm", per * launches, f"X triangle {tri}x{bx} B + FP64 vector in/out per launch", tri * bx
     if cls == "chol_panel":
         # the fused step launches (panel of block row k+1 beside the trailing
         # update of step k): the factorization's n_p^3/3 flops over its N launches
         Npad = N * NB
-        return alu, Npad ** 3 / 3 * launches / N, "Cholesky n_p^3/3 flops over its N step launches"
+        return alu, Npad ** 3 / 3 * launches / N, "Cholesky n_p^3/3 flops over its N step launches", None
     if cls == "invert":
-        return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches"
+        return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches", None
     dense = nnz == m * n
     if cls in ("residual", "gradient"):
         if dense:
-            return "hbm", (8 * m * n + 16 * m) * launches, "dense pass 8mn + 16m B"
+            return "hbm", (8 * m * n + 16 * m) * launches, "dense pass 8mn + 16m B", 8 * m * n
         per = 12 * nnz + 4 * (m + 1) + 8 * (m + n)
-        return "hbm", per * launches, "CSR/CSC pass 12 nnz + 4(m+1) + 8(m+n) B"
+        return "hbm", per * launches, "CSR/CSC pass 12 nnz + 4(m+1) + 8(m+n) B", per
     if cls == "gram":
         if dense:
             peak = "mfma_f64" if cfg["u_q"] == "fp64" else ("mfma_f32" if cfg["u_q"] == "fp32" else "mfma_16")
-            return peak, float(m) * n * (n + 1), "upper-half SYRK m n (n+1) flops"
+            return peak, float(m) * n * (n + 1), "upper-half SYRK m n (n+1) flops", None
         per = 12 * nnz + tri * (8 if cfg["u_q"] == "fp64" else 4)
-        return "hbm", per, "CSC read + Gram triangle write"
+        return "hbm", per, "CSC read + Gram triangle write", per
     return None
 
 
-# kernels (name in the profiler's records, source file) behind each class
+# kernels (name in the profiler's records, source file) behind each class,
+# and the committed PMC summary that holds their HBM bytes
 CLASS_KERNELS = {
-    "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
-              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
-              "invert": ("tls::k_inv_phase2", "kernels_inv")},
     "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
              "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
-             "invert": ("tls::k_inv_phase2", "kernels_inv")},
+             "residual": ("tls::k_residual_dense", "kernels_rqi"),
+             "gradient": ("void tls::k_gradient<false>", "kernels_rqi"),
+             "gram": ("void tls::k_gram_mfma<double, double>", "kernels_factor")},
+    "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
+              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
+              "residual": ("tls::k_residual_dense", "kernels_rqi"),
+              "gradient": ("void tls::k_gradient<false>", "kernels_rqi"),
+              "gram": ("void tls::k_gram_mfma16<tls::bf16_t>", "kernels_factor")},
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_20000x2000_hbm_traffic.md")
+TRAFFIC_FILES = {"sparse_20000x2000": "sparse_20000x2000_hbm_traffic.md",
+                 "dense_65536x4096": "dense_65536x4096_hbm_traffic.md"}
 
 
-def measured_traffic(cls, path):
+def measured_traffic(workload, cls, path):
     """HBM bytes per launch (read + written) from the committed PMC summary,
     or None when the kernel's source changed since the counters were taken."""
     import hashlib
     ent = CLASS_KERNELS.get(path, {}).get(cls)
-    if WORKLOAD != "sparse_20000x2000" or ent is None or not os.path.exists(TRAFFIC_FILE):
+    fname = TRAFFIC_FILES.get(workload)
+    if ent is None or fname is None:
         return None
-    txt = open(TRAFFIC_FILE).read()
+    path_f = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path_f):
+        return None
+    txt = open(path_f).read()
     blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
     name, src = ent
     with open(os.path.join(ROOT, "paper_2305_19028_amd", "csrc", src + ".hip"), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != blob["source"].get(src):
             return None
-    k = blob["kernels"].get(name)
+    k = next((v for key, v in blob["kernels"].items() if key.startswith(name)), None)
     return None if k is None else (k["read_kib"] + k["write_kib"]) * 1024.0
 
 
-def roofline_of(cls, path, m, n, nnz, entry):
-    w = class_work(cls, path, m, n, nnz, entry["launches"])
+def roofline_of(workload, cls, path, cfg, m, n, nnz, entry):
+    w = class_work(cls, cfg, m, n, nnz, entry["launches"])
     if w is None:
         return {"bound": "latency", "kernel": cls, "achieved": None, "peak": None, "unit": None,
                 "frac": None, "traffic": None, "avg_us": entry["avg_us"]}
-    bound, amount, what = w
+    bound, amount, what, wset = w
     peak, unit = PEAKS[bound]
     secs = entry["ms_per_solve"] * 1e-3
     achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
     kind = "hbm" if bound == "hbm" else ("mfma" if bound.startswith("mfma") else "alu")
-    return {"bound": kind, "kernel": cls, "achieved": achieved,
-            "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic(cls, path),
-            "avg_us": entry["avg_us"], "launches_per_solve": entry["launches"],
-            "work_per_launch": amount / max(entry["launches"], 1), "work": what}
+    out = {"bound": kind, "kernel": cls, "achieved": achieved,
+           "peak": peak, "unit": unit, "frac": achieved / peak,
+           "traffic": measured_traffic(workload, cls, path),
+           "avg_us": entry["avg_us"], "launches_per_solve": entry["launches"],
+           "work_per_launch": amount / max(entry["launches"], 1), "work": what}
+    if kind == "hbm" and wset is not None:
+        out["cache_resident"] = bool(wset <= MALL_BYTES)
+    return out
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    out = fn()
+    return out, (time.perf_counter() - t0) * 1e3
 
 
 def cpu_baseline(A, b, seconds):
     """The oracle's plain FP64 RQI-PCGTLS (NumPy/SciPy, multithreaded BLAS) on
-    the same workload, repeated for about `seconds` of wall time."""
-    from oracle import rqi
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    times = []
+    the same workload, by phase: the Gram matrix and its Cholesky factor
+    (oracle.rqi.cholesky_R), x_LS and the RQI loop to the psi rule
+    (oracle.rqi.rqi_pcgtls with that factor), and the long-double Newton
+    polish (oracle.polish). At all threads: whole solves, repeated while
+    they fit in `seconds`. At one thread: one solve with the Gram phase
+    timed on a row sample of A and scaled by the row count (the rest whole)."""
+    from oracle import polish, rqi
+    from threadpoolctl import threadpool_info, threadpool_limits
+    info = threadpool_info()
+    threads = max((p.get("num_threads", 1) for p in info), default=1)
+    api = ",".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info}))
+    m = A.shape[0]
+    runs = []
     t_end = time.perf_counter() + seconds
-    while time.perf_counter() < t_end or len(times) < 2:
-        t0 = time.perf_counter()
-        rqi.rqi_pcgtls(A, b, patience=2)
-        times.append((time.perf_counter() - t0) * 1e3)
-        if len(times) >= 200:
-            break
-    return {"value": statistics.median(times), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"{len(times)} full solves of the sparse 20000x2000 workload "
-                      f"(oracle.rqi.rqi_pcgtls: scipy Gram, LAPACK Cholesky, Algorithms 2+3 "
-                      f"in float64); median"}
+    while not runs or (time.perf_counter() < t_end and len(runs) < 20):
+        R, t_chol = _timed(lambda: rqi.cholesky_R(A))
+        res, t_rqi = _timed(lambda: rqi.rqi_pcgtls(A, b, R=R, patience=2))
+        runs.append((t_chol, t_rqi))
+    _, t_pol = _timed(lambda: polish.polish(A, b, res.x, steps=2))
+    print(f"# cpu oracle: {len(runs)} solves at {threads} threads", file=sys.stderr, flush=True)
+    med = lambda i: statistics.median(r[i] for r in runs)
+    allthr = {"gram_cholesky_ms": med(0), "xls_rqi_loop_ms": med(1), "polish_ms": t_pol,
+              "solve_ms": med(0) + med(1), "runs": len(runs)}
+    with threadpool_limits(limits=1):
+        rows = min(m, 8192)
+        Asub = np.asfortranarray(A[:rows])
+        _, t_g = _timed(lambda: rqi.gram(Asub))
+        t_gram1 = t_g * m / rows
+        G = rqi.gram(A) if rows == m else None
+        _, t_c1 = _timed(lambda: __import__("scipy.linalg").linalg.cholesky(
+            G if G is not None else R.T @ R, lower=False))
+        res1, t_rqi1 = _timed(lambda: rqi.rqi_pcgtls(A, b, R=R, patience=2))
+    print("# cpu oracle: one-thread phases done", file=sys.stderr, flush=True)
+    one = {"gram_cholesky_ms": t_gram1 + t_c1, "xls_rqi_loop_ms": t_rqi1,
+           "solve_ms": t_gram1 + t_c1 + t_rqi1,
+           "gram_sample": f"A^T A on the first {rows} of {m} rows, scaled by {m / rows:g}"}
+    return {"value": allthr["solve_ms"], "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"{len(runs)} whole solves at {threads} threads (oracle.rqi.cholesky_R + "
+                      f"oracle.rqi.rqi_pcgtls, float64, psi rule with patience 2), median; the "
+                      f"long-double polish once; at 1 thread one solve with the Gram phase on "
+                      f"{rows} rows scaled to {m}",
+            "blas": api, "cpu_count": os.cpu_count(), "rqi_iters": res.iters,
+            "phases_all_threads": allthr, "phases_one_thread": one,
+            "value_one_thread": one["solve_ms"]}
+
+
+def profile_only(tls, torch, Ad, bd, workload, steps, names=None):
+    # a plain device copy of known size first: it calibrates the HBM byte
+    # counters of the profiler against the bytes actually moved
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {COPY_BYTES} bytes", flush=True)
+    W = WORKLOADS[workload]
+    cfgs = {**W["paths"], **W.get("variants", {})}
+    for path in (names or cfgs):
+        for _ in range(max(steps, 1)):
+            one_solve(tls, torch, Ad, bd, cfgs[path])
+        torch.cuda.synchronize()
+        print(f"profiled {path}", flush=True)
+
+
+def measure_workload(tls, torch, workload, args, variants=True, profile=True):
+    """Both paths (and the variants) on one workload; returns (results, the
+    host problem, its shape)."""
+    W = WORKLOADS[workload]
+    A, b, xref, sref, tol = make_problem(workload)
+    Ad = tls.from_tlsgen(A)
+    bd = tls.device_vector(b)
+    dense = not hasattr(A, "row_ptr")
+    m, n = (A.shape if dense else (A.m, A.n))
+    nnz = m * n if dense else len(A.val)
+    print(f"# {workload}: tolerance on x {tol:.3g}", file=sys.stderr, flush=True)
+    res = {}
+    for path in ("fp64", "mixed"):
+        res[path] = run_path(tls, torch, Ad, bd, W["paths"][path], args.steps, args.warmup, xref, sref, tol)
+        print(f"# {workload} {path}: {res[path]}", file=sys.stderr, flush=True)
+    out = {"res": res, "variants": {}, "prof": None, "tol": tol, "shape": (m, n, nnz)}
+    for vname, vcfg in (W.get("variants", {}).items() if variants else []):
+        steps = args.steps if vcfg.get("method") != "qr" else max(2, args.steps // 3)
+        r = run_path(tls, torch, Ad, bd, vcfg, steps, min(args.warmup, 1), xref, sref, tol)
+        v = {"config": vcfg, "time_to_tol_ms": r["time_to_tol_ms"],
+             "first_crossing_ms": r["first_crossing_ms"], "verdict_ms": r["verdict_ms"],
+             "factor_ms": r["factor_ms"], "ms_median": r["ms_median"],
+             "rqi_iters": r["rqi_iters"], "r_first": r["r_first"], "gate_verdict": r["gate_verdict"],
+             "u_q_used": r["u_q_used"], "errors": {"sigma": r["err_sigma"], "x": r["err_x"]},
+             "speedup_vs_fp64_time_to_tol":
+                 (res["fp64"]["time_to_tol_ms"] / r["time_to_tol_ms"])
+                 if r["time_to_tol_ms"] and res["fp64"]["time_to_tol_ms"] else None}
+        if vcfg.get("method") == "qr":
+            # the QR factorization's kernels against the FP32 matrix-core peak
+            # (its products run on MFMA in FP32, or FP64 for an FP64 factor):
+            # Table 1's 2mn^2 - 2n^3/3 flops per factorization
+            qp = kernel_profile(tls, torch, Ad, bd, vcfg, reps=1).get("qr")
+            if qp:
+                fl = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+                peak = PEAKS["mfma_f64" if vcfg["u_q"] == "fp64" else "mfma_f32"][0]
+                ach = fl / (qp["ms_per_solve"] * 1e-3) / 1e12
+                v["qr_kernels"] = {"launches": qp["launches"], "ms": qp["ms_per_solve"], "flops": fl,
+                                   "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
+        out["variants"][vname] = v
+        print(f"# {workload} variant {vname}: {v}", file=sys.stderr, flush=True)
+    if profile:
+        out["prof"] = {p: kernel_profile(tls, torch, Ad, bd, W["paths"][p]) for p in ("fp64", "mixed")}
+        for path, pr in out["prof"].items():
+            for cls, e in pr.items():
+                r = roofline_of(workload, cls, path, W["paths"][path], m, n, nnz, e)
+                e["frac"] = r["frac"]
+                e["bound"] = r["bound"]
+                if "cache_resident" in r:
+                    e["cache_resident"] = r["cache_resident"]
+        print(f"# {workload} kernel classes (mixed): {out['prof']['mixed']}", file=sys.stderr, flush=True)
+    del Ad, bd
+    torch.cuda.empty_cache()
+    out["host"] = (A, b)
+    return out
+
+
+def speedups(res):
+    f, mx = res["fp64"], res["mixed"]
+    return {"time_to_tol": (f["time_to_tol_ms"] / mx["time_to_tol_ms"])
+            if mx["time_to_tol_ms"] and f["time_to_tol_ms"] else None,
+            "first_crossing": (f["first_crossing_ms"] / mx["first_crossing_ms"])
+            if mx["first_crossing_ms"] and f["first_crossing_ms"] else None,
+            "whole_solve": f["ms_median"] / mx["ms_median"]}
 
 
 def main():
@@ -348,92 +509,57 @@ def main():
     from paper_2305_19028_amd import tls
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    global WORKLOAD, PATHS
-    WORKLOAD = args.workload
-    PATHS = WORKLOADS[WORKLOAD]["paths"]
     if args.sweep:
         sweep(tls, torch, max(args.steps, 1) if args.steps != 10 else 3, args.warmup)
         return
-    A, b, xref, sref = make_problem(WORKLOAD)
-    Ad = tls.from_tlsgen(A)
-    bd = tls.device_vector(b)
-    dense = not hasattr(A, "row_ptr")
-
+    workload = args.workload
+    W = WORKLOADS[workload]
     if args.profile_only:
-        # a plain device copy of known size first: it calibrates the HBM byte
-        # counters of the profiler against the bytes actually moved
-        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"copied {COPY_BYTES} bytes", flush=True)
-        for vname, vcfg in WORKLOADS[WORKLOAD].get("variants", {}).items():
-            PATHS[vname] = vcfg
-        for path in ("fp64", "mixed", *WORKLOADS[WORKLOAD].get("variants", {})):
-            for _ in range(max(args.steps, 1)):
-                one_solve(tls, torch, Ad, bd, path)
-            torch.cuda.synchronize()
-            print(f"profiled {path}", flush=True)
+        A, b, _, _, _ = make_problem(workload)
+        Ad = tls.from_tlsgen(A)
+        bd = tls.device_vector(b)
+        profile_only(tls, torch, Ad, bd, workload, args.steps,
+                     args.paths.split(",") if args.paths else None)
         return
 
     print(f"# warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    res = {}
-    for path in ("fp64", "mixed"):
-        res[path] = run_path(tls, torch, Ad, bd, path, args.steps, args.warmup, xref, sref)
-        print(f"# {path}: {res[path]}", file=sys.stderr, flush=True)
-    variants = {}
-    for vname, vcfg in WORKLOADS[WORKLOAD].get("variants", {}).items():
-        PATHS[vname] = vcfg
-        r = run_path(tls, torch, Ad, bd, vname, args.steps, args.warmup, xref, sref)
-        variants[vname] = {"config": vcfg, "time_to_tol_ms": r["time_to_tol_ms"],
-                           "factor_ms": r["factor_ms"], "ms_median": r["ms_median"],
-                           "rqi_iters": r["rqi_iters"], "gate_verdict": r["gate_verdict"],
-                           "errors": {"sigma": r["err_sigma"], "x": r["err_x"]},
-                           "speedup_vs_fp64_time_to_tol":
-                               (res["fp64"]["time_to_tol_ms"] / r["time_to_tol_ms"])
-                               if r["time_to_tol_ms"] and res["fp64"]["time_to_tol_ms"] else None}
-        if vcfg.get("method") == "qr":
-            # the QR factorization's kernels against the FP32 matrix-core peak
-            # (its products run on MFMA in FP32, or FP64 for an FP64 factor):
-            # Table 1's 2mn^2 - 2n^3/3 flops per factorization
-            qp = kernel_profile(tls, torch, Ad, bd, vname, reps=2).get("qr")
-            mm, nn = (A.shape if dense else (A.m, A.n))
-            if qp:
-                fl = 2.0 * mm * nn * nn - 2.0 * nn ** 3 / 3.0
-                peak = PEAKS["mfma_f64" if vcfg["u_q"] == "fp64" else "mfma_f32"][0]
-                ach = fl / (qp["ms_per_solve"] * 1e-3) / 1e12
-                variants[vname]["qr_kernels"] = {
-                    "launches": qp["launches"], "ms": qp["ms_per_solve"], "flops": fl,
-                    "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
-        print(f"# variant {vname}: {variants[vname]}", file=sys.stderr, flush=True)
-    prof = {p: kernel_profile(tls, torch, Ad, bd, p) for p in ("fp64", "mixed")}
-    print(f"# kernel classes (mixed): {prof['mixed']}", file=sys.stderr, flush=True)
-
-    # dominant kernel class of the mixed path, and every class's fraction
-    m, n = (A.shape if dense else (A.m, A.n))
-    nnz = m * n if dense else len(A.val)
+    head = measure_workload(tls, torch, workload, args)
+    res, prof = head["res"], head["prof"]
+    m, n, nnz = head["shape"]
     # dominant kernel class on the caller's stream (the critical path): the
     # "gate" class holds the gate's Lanczos runs on the library's side
-    # streams, which overlap the solve
+    # stream, which overlap the solve
     pm = prof["mixed"]
     dom = max((k for k in pm if k != "gate"), key=lambda k: pm[k]["ms_per_solve"])
-    roof = roofline_of(dom, "mixed", m, n, nnz, pm[dom])
-    for path in prof:
-        for cls, e in prof[path].items():
-            r = roofline_of(cls, path, m, n, nnz, e)
-            e["frac"] = r["frac"]
-            e["bound"] = r["bound"]
+    roof = roofline_of(workload, dom, "mixed", W["paths"]["mixed"], m, n, nnz, pm[dom])
+
+    extra = {}
+    if not args.no_extra and workload != "sparse_20000x2000":
+        sp = measure_workload(tls, torch, "sparse_20000x2000", args, variants=False, profile=False)
+        extra["sparse_20000x2000"] = {
+            "describe": WORKLOADS["sparse_20000x2000"]["describe"],
+            "paths": WORKLOADS["sparse_20000x2000"]["paths"],
+            "time_to_tol_ms": {p: sp["res"][p]["time_to_tol_ms"] for p in sp["res"]},
+            "first_crossing_ms": {p: sp["res"][p]["first_crossing_ms"] for p in sp["res"]},
+            "verdict_ms": sp["res"]["mixed"]["verdict_ms"],
+            "ms_median": {p: sp["res"][p]["ms_median"] for p in sp["res"]},
+            "rqi_iters": {p: sp["res"][p]["rqi_iters"] for p in sp["res"]},
+            "errors": {p: {"sigma": sp["res"][p]["err_sigma"], "x": sp["res"][p]["err_x"]}
+                       for p in sp["res"]},
+            "speedup_vs_fp64": speedups(sp["res"])}
 
     cpu = None
-    if not args.no_cpu and not dense:
+    if not args.no_cpu:
+        A, b = head["host"]
         cpu = cpu_baseline(A, b, args.cpu_seconds)
 
     mixed = res["mixed"]
     ttt = mixed["time_to_tol_ms"]
     line = {
         "metric": "time to sigma_min/x_TLS at 1e-10 rel err, mixed vs FP64 GPU path; % roofline",
-        # time from the enqueue of the factorization to the first iterate within
-        # 1e-10 of the reference (first crossing); ms_per_step is the whole solve
+        # time from the enqueue of the factorization to the later of the first
+        # iterate within tolerance and the gate's verdict; ms_per_step is the
+        # whole solve
         "value": ttt if ttt is not None else mixed["ms_median"],
         "unit": "ms",
         "n_gpus": 1,
@@ -443,22 +569,26 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": WORKLOADS[WORKLOAD]["dtype"],
+        "dtype": W["dtype"],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[WORKLOAD]["describe"],
-                   "paths": {"mixed": PATHS["mixed"], "fp64": PATHS["fp64"]}},
+        "config": {"workload": workload, "describe": W["describe"],
+                   "tolerance_x": head["tol"],
+                   "paths": {"mixed": W["paths"]["mixed"], "fp64": W["paths"]["fp64"]}},
         "fp64_path_ms": res["fp64"]["ms_median"],
-        "speedup_vs_fp64": {
-            "time_to_tol": (res["fp64"]["time_to_tol_ms"] / ttt) if ttt and res["fp64"]["time_to_tol_ms"] else None,
-            "whole_solve": res["fp64"]["ms_median"] / mixed["ms_median"]},
-        "time_to_tol_ms": {"mixed": mixed["time_to_tol_ms"], "fp64": res["fp64"]["time_to_tol_ms"]},
+        "speedup_vs_fp64": speedups(res),
+        "time_to_tol_ms": {p: res[p]["time_to_tol_ms"] for p in res},
+        "first_crossing_ms": {p: res[p]["first_crossing_ms"] for p in res},
+        "verdict_ms": mixed["verdict_ms"],
         "errors": {p: {"sigma": res[p]["err_sigma"], "x": res[p]["err_x"]} for p in res},
         "rqi_iters": {p: res[p]["rqi_iters"] for p in res},
+        "r_first": {p: res[p]["r_first"] for p in res},
         "factor_ms": {p: res[p]["factor_ms"] for p in res},
-        "gate_async": {p: res[p]["gate_async"] for p in res},
-        "variants": variants,
+        "gate": {"verdict": mixed["gate_verdict"], "u_q_used": mixed["u_q_used"],
+                 "async": mixed["gate_async"]},
+        "variants": head["variants"],
         "roofline": roof,
         "kernel_classes": prof,
+        "extra_workloads": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -204,6 +204,10 @@ typedef struct {
   double sigma_final;      /* sigma after the compensated residual                 */
   double sigma_hat;        /* warm-start shift estimate (0 when none)              */
   double psi_warm, psi_plain; /* psi at the warm and at the plain x_1 (warm start)  */
+  double t_verdict_ms;     /* host time since the call began when the gate's
+                              verdict (constraint (6) and the factor certificate)
+                              was taken; an iterate is only usable from then on.
+                              0 when no gate ran                                  */
   float features[TLS_MLP_IN]; /* warm-start features (when computed)              */
 } tls_rqi_stats;
 

@@ -1638,6 +1638,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       if (!spec) {
         TRY(gate_finish(P));
         gate_decide(P, S.sigma_ls);
+        S.t_verdict_ms = ms_since(t0);
       }
       break;
     }
@@ -1803,6 +1804,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         if (spec && P->gate_pending && gate_ready(P)) {
           TRY(gate_finish(P));
           gate_decide(P, S.sigma_ls);
+          S.t_verdict_ms = ms_since(t0);
           if (!(P->rep.verdict & 16)) return TLS_OK;   // discarded below: escalation
         }
         if (h[1] != h[0]) S.clamped++;
@@ -1821,7 +1823,14 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         if (!enq) TRY(inner(l));
         S.pcg_steps += l + 1;
       }
-      // the returned iterate
+      // the returned iterate needs the gate's verdict: wait for runs still
+      // in flight now rather than after the refinement
+      if (spec && P->gate_pending) {
+        TRY(gate_finish(P));
+        gate_decide(P, S.sigma_ls);
+        S.t_verdict_ms = ms_since(t0);
+        if (!(P->rep.verdict & 16)) return TLS_OK;     // discarded below: escalation
+      }
       HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
 
       // ---- final FP64 refinement: RQI steps with explicit-operator PCG --------
@@ -1904,6 +1913,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       if (P->gate_pending) {
         TRY(gate_finish(P));
         gate_decide(P, S.sigma_ls);
+        S.t_verdict_ms = ms_since(t0);
       }
       if (!(P->rep.verdict & 16)) return resolve();
     }

@@ -90,7 +90,7 @@ class c_rqi_stats(C.Structure):
          ("sigma", C.c_double * MAX_ITERS), ("t_ms", C.c_double * MAX_ITERS),
          ("t_factor_ms", C.c_double), ("t_total_ms", C.c_double), ("sigma_final", C.c_double),
          ("sigma_hat", C.c_double), ("psi_warm", C.c_double), ("psi_plain", C.c_double),
-         ("features", C.c_float * MLP_IN)]
+         ("t_verdict_ms", C.c_double), ("features", C.c_float * MLP_IN)]
 
     def to_dict(self):
         k = self.iters
@@ -104,7 +104,7 @@ class c_rqi_stats(C.Structure):
             "t_factor_ms": self.t_factor_ms, "t_total_ms": self.t_total_ms,
             "sigma_final": self.sigma_final, "sigma_hat": self.sigma_hat,
             "psi_warm": self.psi_warm, "psi_plain": self.psi_plain,
-            "features": list(self.features),
+            "t_verdict_ms": self.t_verdict_ms, "features": list(self.features),
         }
 
 

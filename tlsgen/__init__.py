@@ -187,15 +187,20 @@ def reflector_dense(m: int = 65536, n: int = 4096, s_min: float = 1e-3,
     SZt = np.diag(s) - (2.0 / zz) * np.outer(s * z, z)          # n x n
     # A_clean = Y [SZ^T; 0] = [SZ^T; 0] - (2/yy) y (y[:n]^T SZ^T)
     w = (2.0 / yy) * (y[:n] @ SZt)                                # n
-    A = np.empty((m, n), order="F")
-    A[:] = -np.outer(y, w)
+    # -y w^T built as the transpose of the C-ordered (n, m) product: one
+    # allocation, already column-major (the same values as -outer(y, w))
+    A = np.multiply.outer(-w, y).T
     A[:n, :] += SZt
     b = A @ x + noise_b * g.standard_normal(m)
     scale = noise_A / (math.sqrt(m) + math.sqrt(n))
     chunk = max(1, (1 << 24) // m)
+    buf = np.empty((chunk, m))                  # reused for every column block
     for j0 in range(0, n, chunk):
         j1 = min(n, j0 + chunk)
-        A[:, j0:j1] += scale * g.standard_normal((j1 - j0, m)).T
+        blk = buf[: j1 - j0]
+        g.standard_normal(out=blk)
+        blk *= scale
+        A[:, j0:j1] += blk.T
     return A.astype(dtype, copy=False), b, x, s
 
 
