@@ -249,6 +249,20 @@ TLS_API tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t 
  * without its dense cast buffer, plus the QR working matrix, FP64-sized,
  * (m + Np - n) x Np with Np = 64 ceil(n / 64), and 8 KiB of reflector
  * scratch per 256 rows of it. */
+/* The Gram step alone (Section 2: the preconditioner is the Cholesky factor
+ * of A^T A; Section 3.1: two-sided diagonal scaling and rounding to u_q):
+ * G = Ahat^T Ahat with Ahat = fl_{u_q}(A D^{-1}), D = diag(||A e_j||_2)
+ * when scaling (else D = I, FP64 only), computed exactly as
+ * tls_factor_precond computes it before the Cholesky factorization: FP64
+ * matrix cores on A (u_q = FP64); FP32 matrix cores on an FP32 cast (FP32);
+ * 16-bit matrix cores with FP32 accumulation restarted every 128 rows and
+ * row segments added in FP64 (FP16, BF16). Dense A only. G (device, n x n
+ * column-major FP64) receives the upper triangle; the strict lower part is
+ * not written. d (device, n, may be NULL) receives the diagonal of D. The
+ * workspace is tls_factor_workspace_size(A, u_q) bytes. Asynchronous. */
+TLS_API tls_status tls_gram(const tls_matrix *A, int32_t u_q, int32_t scaling, double *G, double *d,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
 TLS_API size_t tls_factor_qr_workspace_size(const tls_matrix *A, int32_t u_q);
 
 /* Build R with R^T R ~ A^T A from the Householder QR of A (Section 3: the

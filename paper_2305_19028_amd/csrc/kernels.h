@@ -118,6 +118,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
 hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, const double *d,
                              int scaled, int q, int compute, void *G, hipStream_t st);
 hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st);
+hipError_t launch_gram_export(int n, int Np, int compute, const void *G, double *out, hipStream_t st);
 hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st);
 // blocked Cholesky of G in place (upper); rdiag: N 64x64 tiles of scratch
 // in the compute precision (the diagonal tiles while the steps run)

@@ -868,29 +868,34 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
   }
 }
 
-// ---- 16-bit inputs: K-split Gram --------------------------------------------
-// FP16 / BF16 inputs go through a separate kernel. The K range is cut into
-// segments of G16SEG rows and each (tile, segment) pair is its own workgroup
-// (8 segments x 528 tiles at 65536 x 4096 instead of 528 workgroups over 256
-// CUs). A segment's partial tile goes to a scratch buffer and a second
-// kernel sums the segments in FP64 in a fixed order. Workgroups run in
-// (tile, segment) order, tiles fastest, so the resident ones share a
-// segment (64 MB at n = 4096, held by the last-level cache). Two XCD-aware
-// orders were measured and dropped: each XCD taking a contiguous eighth of
-// the tiles in 8 x 8-panel blocks (the 32 workgroups of an XCD then share
-// about 15 panels through its L2) ran in the same time, and each XCD taking
-// its own segment was 10% slower; neither locality nor the layout of the
-// cast (column-major or chunk-major) moved the kernel, whose chunk loop waits
-// on the latency of its one chunk of register prefetch. Within a segment, 64-row
-// chunks (one 128-byte line per column) are double buffered in LDS with one
-// barrier per chunk: the global loads of chunk k+2 are issued while chunk k
-// feeds the MFMAs, and chunk k+1 is staged after them. The FP32 MFMA sums
-// are folded into FP64 every G16FOLD chunks (256 rows): on the scaled Gram
-// matrix of the 65536 x 4096 planted problem, whose smallest eigenvalue is
-// near 7e-5, FP32 sums over a whole segment moved the diagonal by about 1% of
-// it and took the BF16 path from 22 to 32 RQIs. The segment's FP64 sum is
-// stored in FP32 (at most 1/8 of a unit diagonal entry: 1e-8 absolute).
-constexpr int G16K = 64, G16SEG = 8192, G16RL = G16K + 8, G16FOLD = 4;
+// ---- 16-bit inputs: K-split Gram on paired tiles --------------------------
+// FP16 / BF16 inputs (and the two planes of the split BF16 input) go through
+// their own kernel. A workgroup of eight waves computes two upper 128 x 128
+// tiles of one tile column J, (I0, J) and (I0 + 1, J) with I0 even, over one
+// segment of the K range: three 128-column panels (J, I0, I0 + 1) per 64-row
+// chunk, so a chunk's 48 KB feed 4.2 MFLOP (twice the flops per byte of a
+// single tile). Each wave owns a 64 x 64 quarter of one tile (2 x 2
+// v_mfma_f32_32x32x16 blocks). Chunks are prefetched two ahead into
+// registers and double buffered in LDS, one barrier per chunk; with about
+// 110 KB of LDS and 200 VGPRs the kernel runs one workgroup (two waves per
+// SIMD) per CU, and the host picks the segment length so that the
+// (pair, segment) jobs fill whole rounds of the chip.
+//
+// Accumulation: the MFMA accumulates 128 rows (G16FOLD chunks) from zero,
+// and that partial is added into an FP32 sum with round-to-nearest. The
+// matrix cores' own running sum drifts with the number of accumulations
+// (over 8192 rows it moved the diagonal of the scaled 65536 x 4096 planted
+// Gram matrix, whose smallest eigenvalue is near 7e-5, by about 1% of that
+// eigenvalue and cost the BF16 path 10 RQIs); restarting it every 128 rows
+// bounds that drift, and the second level adds only rounding errors of
+// random sign. A segment's sum goes to a scratch tile; k_gram_reduce adds
+// the segments in FP64 in a fixed order.
+//
+// Work order: dispatch id L runs on XCD L mod 8; each XCD takes a contiguous
+// range of the (segment, pair) order, so the workgroups resident on one XCD
+// work on neighbouring pairs of one segment and share its panels in their L2.
+constexpr int G16K = 64, G16RL = G16K + 8, G16FOLD = 2, G16LANES = 512;
+constexpr int G16NV = 3 * GT * G16K * 2 / 16 / G16LANES;   // 16-byte loads per thread per chunk (6)
 
 // upper tile (I, J), I <= J, of linear index l = J (J + 1) / 2 + I
 __device__ inline void gram_tile_of(int l, int &I, int &J) {
@@ -900,8 +905,51 @@ __device__ inline void gram_tile_of(int l, int &I, int &J) {
   I = l - J * (J + 1) / 2;
 }
 
+// pairs in tile columns < J: ceil((j + 1) / 2) per column j
+__host__ __device__ inline int gram_pairs_before(int J) {
+  const int a = J >> 1;
+  return (J & 1) ? (a + 1) * (a + 1) : a * (a + 1);
+}
+__device__ inline void gram_pair_of(int p, int &I0, int &J) {
+  int j = (int)(2.0 * sqrt((double)p));
+  if (j > 0) --j;
+  while (gram_pairs_before(j + 1) <= p) ++j;
+  while (j > 0 && gram_pairs_before(j) > p) --j;
+  J = j;
+  I0 = 2 * (p - gram_pairs_before(j));
+}
+
 inline int64_t gram_rows_padded(int64_t m) { return ((m + G16K - 1) / G16K) * G16K; }
-inline int gram_segments(int64_t m) { return (int)((gram_rows_padded(m) + G16SEG - 1) / G16SEG); }
+
+struct GramPlan { int nseg, seglen, npairs; };
+// segment length (a multiple of 64 rows, at least 1024 unless m is smaller)
+// that minimises rounds x rows per round for one workgroup per CU
+static GramPlan gram_plan(int64_t m, int64_t n, int cus) {
+  const int64_t mp = gram_rows_padded(m);
+  const int NT = (int)((n + GT - 1) / GT);
+  GramPlan best{1, (int)mp, gram_pairs_before(NT)};
+  int64_t best_cost = LLONG_MAX;
+  for (int ns = 1; ns <= 64; ++ns) {
+    const int64_t len = ((mp + ns - 1) / ns + G16K - 1) / G16K * G16K;
+    if (ns > 1 && len < 1024) break;
+    const int used = (int)((mp + len - 1) / len);
+    if (used != ns) continue;
+    const int64_t jobs = (int64_t)best.npairs * ns;
+    const int64_t cost = (jobs + cus - 1) / cus * len;
+    if (cost < best_cost) { best_cost = cost; best.nseg = ns; best.seglen = (int)len; }
+  }
+  return best;
+}
+static int device_cus() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  return cus;
+}
+// the partial tiles are sized for the largest plan any device could pick
+static int gram_max_segments(int64_t m) { return std::max(1, (int)((gram_rows_padded(m) + 1023) / 1024)); }
 inline size_t gram_cast_only_bytes(int64_t m, int64_t n) {
   const int64_t n128 = ((n + GT - 1) / GT) * GT;
   return ((size_t)gram_rows_padded(m) * n128 * 4 + 255) / 256 * 256;   // FP32-sized
@@ -923,39 +971,48 @@ __global__ __launch_bounds__(256) void k_cast_blocked(int m, int n, int64_t ld, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_mfma16(int mp, const T *A, float *part, int NT) {
-  __shared__ __attribute__((aligned(16))) T Ps[2][GT][G16RL];   // output-column panel (J)
-  __shared__ __attribute__((aligned(16))) T Qs[2][GT][G16RL];   // output-row panel (I)
-  const int ntiles = NT * (NT + 1) / 2, l = blockIdx.x, seg = blockIdx.y;
-  int I, J;
-  gram_tile_of(l, I, J);
-  const bool diag = (I == J);
+__device__ inline g_f32x16 mfma16(uint4 a, uint4 b, g_f32x16 c) {
+  if constexpr (std::is_same<T, bf16_t>::value)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(g_bf16x8, a),
+                                                    __builtin_bit_cast(g_bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(g_f16x8, a),
+                                                   __builtin_bit_cast(g_f16x8, b), c, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(G16LANES) void k_gram_mfma16(int mp, const T *A, float *part, int NT,
+                                                          int seglen, int npairs, int nseg) {
+  // stage b holds panel J in rows 0..127, I0 in 128..255, I0 + 1 in 256..383
+  __shared__ __attribute__((aligned(16))) T S[2][3 * GT][G16RL];
+  const int ntiles = NT * (NT + 1) / 2;
+  // XCD-contiguous work order
+  const int total = npairs * nseg, L = blockIdx.x;
+  const int xcd = L & 7, k = L >> 3, q8 = total >> 3, r8 = total & 7;
+  const int Wl = xcd * q8 + min(xcd, r8) + k;
+  const int seg = Wl / npairs, p = Wl - seg * npairs;
+  int I0, J;
+  gram_pair_of(p, I0, J);
+  const int I1 = I0 + 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int r0 = I * GT, c0 = J * GT;
-  const int kbeg = seg * G16SEG;
-  const int nch = (min(mp, kbeg + G16SEG) - kbeg) / G16K;
-  uint4 pv[4], qv[4];
-  const size_t cstride = (size_t)NT * GT * G16K;          // elements per 64-row chunk
-  auto fetch = [&](int k0) {
-    const T *chunk = A + (size_t)(k0 / G16K) * cstride;
+  const int h = w >> 2, wr = (w >> 1) & 1, wc = w & 1;
+  const bool live = (h == 0) || (I1 <= J);          // tile (I0 + h, J) is an upper tile
+  const int kbeg = seg * seglen;
+  const int nch = (min(mp, kbeg + seglen) - kbeg) / G16K;
+  const size_t cstride = (size_t)NT * GT * G16K;     // elements per 64-row chunk
+  // thread tid moves 16 bytes of column (tid >> 3) + 64 (i & 1) of panel
+  // i >> 1 (J, I0, I0 + 1) at offset 8 (tid & 7) in load slot i = 0..5
+  const int colJ = J * GT, colI0 = I0 * GT, colI1 = min(I1, NT - 1) * GT;
+  const int crow = tid >> 3, coff = (tid & 7) * 8;
+  const T *gbase[G16NV];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = tid + 256 * i, c = v >> 3, o = (v & 7) * 8;
-      pv[i] = *(const uint4 *)(chunk + (size_t)(c0 + c) * G16K + o);
-      if (!diag) qv[i] = *(const uint4 *)(chunk + (size_t)(r0 + c) * G16K + o);
-    }
-  };
-  auto stage = [&](int b) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = tid + 256 * i, c = v >> 3, o = (v & 7) * 8;
-      *(uint4 *)&Ps[b][c][o] = pv[i];
-      if (!diag) *(uint4 *)&Qs[b][c][o] = qv[i];
-    }
-  };
+  for (int i = 0; i < G16NV; ++i) {
+    const int pn = i >> 1, c = crow + 64 * (i & 1);
+    gbase[i] = A + (size_t)kbeg * NT * GT + (size_t)((pn == 0 ? colJ : pn == 1 ? colI0 : colI1) + c) * G16K + coff;
+  }
+
   g_f32x16 acc[2][2];
-  double sum[2][2][16];
+  float sum[2][2][16];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -963,8 +1020,26 @@ __global__ __launch_bounds__(256) void k_gram_mfma16(int mp, const T *A, float *
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         acc[t][u][q] = 0.0f;
-        sum[t][u][q] = 0.0;
+        sum[t][u][q] = 0.0f;
       }
+  // register prefetch buffers (named, so that they stay in VGPRs)
+  uint4 a0, a1, a2, a3, a4, a5, b0, b1, b2, b3, b4, b5;
+#define G16_FETCH(X, ch)                                                          \
+  do {                                                                            \
+    const size_t off_ = (size_t)(ch) * cstride;                                   \
+    X##0 = *(const uint4 *)(gbase[0] + off_); X##1 = *(const uint4 *)(gbase[1] + off_); \
+    X##2 = *(const uint4 *)(gbase[2] + off_); X##3 = *(const uint4 *)(gbase[3] + off_); \
+    X##4 = *(const uint4 *)(gbase[4] + off_); X##5 = *(const uint4 *)(gbase[5] + off_); \
+  } while (0)
+#define G16_STAGE(X, b)                                                           \
+  do {                                                                            \
+    *(uint4 *)&S[b][0 * GT + crow][coff] = X##0;                                  \
+    *(uint4 *)&S[b][0 * GT + crow + 64][coff] = X##1;                             \
+    *(uint4 *)&S[b][1 * GT + crow][coff] = X##2;                                  \
+    *(uint4 *)&S[b][1 * GT + crow + 64][coff] = X##3;                             \
+    *(uint4 *)&S[b][2 * GT + crow][coff] = X##4;                                  \
+    *(uint4 *)&S[b][2 * GT + crow + 64][coff] = X##5;                             \
+  } while (0)
   auto fold = [&]() {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -972,49 +1047,61 @@ __global__ __launch_bounds__(256) void k_gram_mfma16(int mp, const T *A, float *
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          sum[t][u][q] += (double)acc[t][u][q];
+          sum[t][u][q] += acc[t][u][q];
           acc[t][u][q] = 0.0f;
         }
   };
-  if (nch > 0) {
-    fetch(kbeg);
-    stage(0);
-    if (nch > 1) fetch(kbeg + G16K);
-  }
-  __syncthreads();
-  for (int it = 0; it < nch; ++it) {
-    const int cur = it & 1;
-    const T (*P)[G16RL] = Ps[cur];
-    const T (*Q)[G16RL] = diag ? Ps[cur] : Qs[cur];
+  const int arow = wc * 64 + (lane & 31), brow = (1 + h) * GT + wr * 64 + (lane & 31);
+  const int koff = 8 * (lane >> 5);
+  auto compute = [&](int b) {
+    if (!live) return;
 #pragma unroll
     for (int s = 0; s < G16K / 16; ++s) {
-      uint4 a[2], b[2];
+      uint4 a[2], bb[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a[t] = *(const uint4 *)&P[wc * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
-        b[t] = *(const uint4 *)&Q[wr * 64 + t * 32 + (lane & 31)][s * 16 + 8 * (lane >> 5)];
+        a[t] = *(const uint4 *)&S[b][arow + t * 32][s * 16 + koff];
+        bb[t] = *(const uint4 *)&S[b][brow + t * 32][s * 16 + koff];
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if constexpr (std::is_same<T, bf16_t>::value)
-            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(g_bf16x8, a[t]), __builtin_bit_cast(g_bf16x8, b[u]), acc[t][u], 0, 0, 0);
-          else
-            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(g_f16x8, a[t]), __builtin_bit_cast(g_f16x8, b[u]), acc[t][u], 0, 0, 0);
-        }
+        for (int u = 0; u < 2; ++u) acc[t][u] = mfma16<T>(a[t], bb[u], acc[t][u]);
     }
+  };
+
+  // chunk c is prefetched into a* (c even) or b* (c odd). Iteration it
+  // computes chunk it from LDS buffer it & 1, stages chunk it + 1 into the
+  // other buffer (last read in iteration it - 1) and refills the registers
+  // it came from with chunk it + 3
+  if (nch > 0) G16_FETCH(a, 0);
+  if (nch > 1) G16_FETCH(b, 1);
+  if (nch > 0) G16_STAGE(a, 0);
+  if (nch > 2) G16_FETCH(a, 2);
+  __syncthreads();
+  for (int it = 0; it < nch; it += 2) {
+    compute(0);
     if (it + 1 < nch) {
-      stage(cur ^ 1);                       // chunk it+1: its buffer was last read in iteration it-1
-      if (it + 2 < nch) fetch(kbeg + (it + 2) * G16K);
+      G16_STAGE(b, 1);
+      if (it + 3 < nch) G16_FETCH(b, it + 3);
     }
     if ((it + 1) % G16FOLD == 0) fold();
     __syncthreads();
+    if (it + 1 >= nch) break;
+    compute(1);
+    if (it + 2 < nch) {
+      G16_STAGE(a, 0);
+      if (it + 4 < nch) G16_FETCH(a, it + 4);
+    }
+    if ((it + 2) % G16FOLD == 0) fold();
+    __syncthreads();
   }
+#undef G16_FETCH
+#undef G16_STAGE
   fold();
-  // partial tile, column-major inside the tile: part[seg][pos][c_local][r_local]
+  if (!live) return;
+  // partial tile, column-major inside the tile: part[seg][l][c_local][r_local]
+  const int l = J * (J + 1) / 2 + I0 + h;
   float *dst = part + ((size_t)seg * ntiles + l) * GT * GT;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -1024,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma16(int mp, const T *A, float *
       for (int q = 0; q < 16; ++q) {
         const int cl = wc * 64 + t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
         const int rl = wr * 64 + u * 32 + (lane & 31);
-        dst[cl * GT + rl] = (float)sum[t][u][q];
+        dst[cl * GT + rl] = sum[t][u][q];
       }
 }
 
@@ -1046,7 +1133,7 @@ size_t gram_cast_bytes(int64_t m, int64_t n) {
   const int64_t NT = (n + GT - 1) / GT;
   // the cast (room for the widest low-precision input, FP32) and the
   // segment partials of the 16-bit kernel
-  return gram_cast_only_bytes(m, n) + (size_t)gram_segments(m) * (NT * (NT + 1) / 2) * GT * GT * 4;
+  return gram_cast_only_bytes(m, n) + (size_t)gram_max_segments(m) * (NT * (NT + 1) / 2) * GT * GT * 4;
 }
 
 hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
@@ -1060,10 +1147,12 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
   }
   const int mp = (int)gram_rows_padded(m);
   const int n128 = NT * GT;
-  const int ntiles = NT * (NT + 1) / 2, nseg = gram_segments(m);
+  const int ntiles = NT * (NT + 1) / 2;
+  const GramPlan gp = gram_plan(m, n, device_cus());
+  const int nseg = gp.nseg;
   float *part = (float *)((char *)cast + gram_cast_only_bytes(m, n));
   const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
-  const dim3 g16((unsigned)ntiles, (unsigned)nseg);
+  const dim3 g16((unsigned)(gp.npairs * nseg));
   switch (q) {
     case TLS_FP32:
       TLS_LAUNCH(PC_GRAM, k_cast_dense<float>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (float *)cast);
@@ -1073,18 +1162,34 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
     case TLS_FP16:
       TLS_LAUNCH(PC_GRAM, k_cast_blocked<half_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  (half_t *)cast);
-      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(256), 0, st, mp, (const half_t *)cast, part, NT);
+      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(G16LANES), 0, st, mp, (const half_t *)cast, part, NT,
+                 gp.seglen, gp.npairs, nseg);
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
     default:
       TLS_LAUNCH(PC_GRAM, k_cast_blocked<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  (bf16_t *)cast);
-      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(256), 0, st, mp, (const bf16_t *)cast, part, NT);
+      TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)cast, part, NT,
+                 gp.seglen, gp.npairs, nseg);
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
   }
+  return hipGetLastError();
+}
+
+// the upper triangle of G (Np x Np, compute precision) into out (n x n FP64)
+template <typename C>
+__global__ void k_gram_export(int n, int Np, const C *G, double *out) {
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) out[(size_t)j * n + i] = (double)G[(size_t)j * Np + i];
+}
+hipError_t launch_gram_export(int n, int Np, int compute, const void *G, double *out, hipStream_t st) {
+  if (compute == TLS_FP64)
+    TLS_LAUNCH(PC_GRAM, k_gram_export<double>, dim3(n), dim3(256), 0, st, n, Np, (const double *)G, out);
+  else
+    TLS_LAUNCH(PC_GRAM, k_gram_export<float>, dim3(n), dim3(256), 0, st, n, Np, (const float *)G, out);
   return hipGetLastError();
 }
 

@@ -1155,6 +1155,36 @@ tls_status pcg_scratch_of_current_device(void **out) {
 
 extern "C" {
 
+tls_status tls_gram(const tls_matrix *A, int32_t u_q, int32_t scaling, double *G, double *d, void *ws,
+                    size_t ws_bytes, hipStream_t stream) {
+  try {
+    TRY(check_matrix(A));
+    TRY(check_prec(u_q, "u_q"));
+    if (A->format == TLS_CSR) return fail(TLS_ERR_ARG, "tls_gram takes a dense A");
+    if (!G) return fail(TLS_ERR_ARG, "G is NULL");
+    if (!scaling && u_q != TLS_FP64) return fail(TLS_ERR_ARG, "unscaled Gram matrices are FP64 only");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    const size_t need = tls_factor_workspace_size(A, u_q);
+    if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "Gram workspace %zu < %zu bytes", ws_bytes, need);
+    Carver c(ws);
+    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64, 0);
+    tls_precond_s P{};
+    const int n = (int)A->n;
+    P.n = n;
+    P.Np = ceil_div(n, NB) * NB;
+    P.N = P.Np / NB;
+    P.scaled = scaling ? 1 : 0;
+    HIPCHK(launch_colnorms_dense((int)A->m, n, A->ld, A->val, W.d, stream));
+    const int compute = (u_q == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+    TRY(form_gram(A, &P, W, u_q, compute, stream));
+    HIPCHK(launch_gram_export(n, P.Np, compute, W.G, G, stream));
+    if (d) HIPCHK(hipMemcpyAsync(d, W.d, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    return TLS_OK;
+  } catch (...) {
+    return fail(TLS_ERR_ARG, "unexpected C++ exception");
+  }
+}
+
 tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
                               int32_t allow_escalate, void *ws, size_t ws_bytes,
                               hipStream_t stream, tls_precond *out, tls_gate_report *rep) {

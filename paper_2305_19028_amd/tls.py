@@ -131,6 +131,8 @@ _SIGS = {
     "tls_factor_precond": (C.c_int, [C.POINTER(c_matrix), C.c_int32, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p),
                                      C.POINTER(c_gate_report)]),
+    "tls_gram": (C.c_int, [C.POINTER(c_matrix), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_size_t, C.c_void_p]),
     "tls_factor_qr_workspace_size": (C.c_size_t, [C.POINTER(c_matrix), C.c_int32]),
     "tls_factor_precond_qr": (C.c_int, [C.POINTER(c_matrix), C.c_int32, C.c_int32, C.c_int32,
                                         C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p),
@@ -329,6 +331,22 @@ def tls_factor_precond(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False
     L = lib()
     return _factor(L.tls_factor_workspace_size, L.tls_factor_precond, A, u_q, scaling,
                    allow_escalate, wait_gate)
+
+
+def tls_gram(A: Matrix, u_q="fp64", scaling=True):
+    """The Gram matrix the factorization forms (see tls.h): returns (G upper
+    triangle as an n x n float64 tensor, lower part zero; d)."""
+    torch = _torch()
+    L = lib()
+    nb = L.tls_factor_workspace_size(C.byref(A.c), _prec(u_q))
+    if nb == 0:
+        _check(-1)
+    ws = Workspace(nb)
+    G = torch.zeros((A.n, A.n), dtype=torch.float64, device="cuda")   # column-major = G^T row-major
+    d = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    _check(L.tls_gram(C.byref(A.c), _prec(u_q), int(bool(scaling)), _ptr(G), _ptr(d), ws.ptr, ws.nbytes,
+                      _stream()))
+    return G.t(), d
 
 
 def tls_factor_precond_qr(A: Matrix, u_q="fp64", scaling=True, allow_escalate=False, wait_gate=True):

@@ -45,6 +45,40 @@ def test_gram_tiles_against_oracle(u_q, shape):
     assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
 
 
+@pytest.mark.parametrize("u_q", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", [(70, 3), (300, 64), (3000, 300), (4097, 129), (9000, 520),
+                                   (20000, 200), (40000, 700)])
+def test_gram_elementwise_against_oracle(u_q, shape):
+    """The Gram step alone (tls_gram) against the oracle's Gram matrix of its
+    own rounding of A D^{-1}, entry by entry. The 16-bit products are exact
+    in FP32; what remains is the FP32 accumulation (the matrix cores' sums
+    restarted every 128 rows, at most a few dozen FP32 additions per entry
+    over a segment) and the final FP32 rounding, so every entry is within
+    100 u_32 of the oracle's, relative to (|Ahat|^T |Ahat|)_ij. Shapes cover
+    ragged m (partial 64-row chunks), ragged n (partial 128-column tiles), an
+    odd number of tile columns (a pair whose second tile is below the
+    diagonal or past the last column) and several row segments."""
+    tls = _tls()
+    m, n = shape
+    print(f"gram elementwise {u_q} {shape}", flush=True)
+    A, _, _ = tlsgen.dense_gaussian(m, n, seed=7 + n)
+    A = A * np.exp(np.random.default_rng(n).uniform(-3, 3, n))      # spread column scales
+    G, d = tls.tls_gram(tls.dense(A), u_q)
+    G = G.cpu().numpy()
+    d = d.cpu().numpy()
+    d_or = np.linalg.norm(A, axis=0)
+    assert np.allclose(d, d_or, rtol=1e-14, atol=0)
+    Ah = A * (1.0 / d_or) if u_q == "fp64" else lowprec.round_to(A * (1.0 / d_or), u_q)
+    H = Ah.T @ Ah
+    W = np.abs(Ah).T @ np.abs(Ah)
+    iu = np.triu_indices(n)
+    u = 2.0 ** -53 if u_q == "fp64" else 2.0 ** -24
+    k = 4 * np.sqrt(m) if u_q == "fp64" else 100.0
+    err = np.abs(G[iu] - H[iu]) / W[iu]
+    assert np.max(err) <= k * u, (np.max(err) / u, np.unravel_index(np.argmax(err), err.shape))
+    assert np.all(np.tril(G, -1) == 0)
+
+
 def _planted_c3(seed=3100):
     # the configuration's spectrum: sigma'_i geometric from 1 to 1e-3, and a
     # planted smallest singular value of [A, b] at 3.9e-5
