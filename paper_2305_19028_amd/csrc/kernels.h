@@ -97,6 +97,10 @@ hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
                             int32_t *fill, hipStream_t st);
 hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
                                hipStream_t st);
+// row-major copy At (stride ldr) of a dense column-major A, column norms d and
+// the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
+hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
+                                double *colsq, double *d, int *flag, hipStream_t st);
 hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
                                  hipStream_t st);
 // scaling vectors: dinv = 1/d (or ones when unscaled), both precisions, padded to Np
@@ -153,6 +157,10 @@ struct MatView {
   // CSC copy (CSR only)
   const int32_t *col_ptr, *row_idx;
   const double *cval;
+  // row-major copy of a dense A (row stride ldr, a multiple of 64, zero
+  // padded), made by the factorization; nullptr when absent
+  const double *at;
+  int64_t ldr;
 };
 
 // r = b - A x; per-block partial sums of r.r and b.r written to part[2*blocks]
@@ -164,6 +172,21 @@ hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream
 hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st);
 // f = -A^T r - shift x with shift read from scal; partial f.f per block
 int rmatvec_blocks(const MatView &A);
+// one pass over the row-major copy (A.at): r = b - A x (b or x may be NULL
+// for 0), residual partials in the k_residual_dense layout (part_r, may be
+// NULL) and rowpass_partials(A) partial n-vectors of A^T r in ppart
+int rowpass_groups(int64_t m, int cus);
+int rowpass_blocks(int64_t m, int cus);
+int rowpass_partials(const MatView &A);
+hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
+                          double *ppart, hipStream_t st);
+// y = s * sum of the partial n-vectors
+hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st);
+// f = -A^T r - mu x from the partials (gradient_rows_blocks(n) partial pairs)
+int gradient_rows_blocks(int n);
+hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
+                                double *f, double *part, const double *part_r, int nb_r, double cap,
+                                hipStream_t st);
 hipError_t launch_gradient(const MatView &A, const double *r, const double *x, double *scal,
                            double *f, double *part, const double *part_r, int nb_r, double cap,
                            hipStream_t st);

@@ -418,6 +418,61 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
   s = wave_sum(s);
   if (lane == 0) d[j] = sqrt(s);
 }
+// Row-major working copy of a dense column-major A (row stride ldr >= n, a
+// multiple of 64, padding columns zero), with the column sums of squares of
+// each 64-row block (colsq[block][j]) and the finite-input flag, in one pass:
+// a 64 x 64 tile per workgroup is read column by column (512-byte loads),
+// transposed through LDS and written row by row
+__global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr,
+                                                       double *At, double *colsq, int *flag) {
+  __shared__ double tile[64][65];
+  const int I = blockIdx.x, J = blockIdx.y;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = I * 64 + lane;
+  int bad = 0;
+#pragma unroll 4
+  for (int cc = 0; cc < 64; cc += 4) {
+    const int c = cc + w, j = J * 64 + c;
+    double v = 0.0;
+    if (i < m && j < n) v = __builtin_nontemporal_load(A + (size_t)j * ld + i);
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    bad |= ((u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull);
+    tile[c][lane] = v;
+    const double sq = wave_sum(v * v);
+    if (lane == 0 && j < n) colsq[(size_t)I * n + j] = sq;
+  }
+  if (__any(bad) && lane == 0) atomicOr(flag, 1);
+  __syncthreads();
+  const int j = J * 64 + lane;
+  if (j >= ldr) return;
+#pragma unroll 4
+  for (int rr = 0; rr < 64; rr += 4) {
+    const int r = I * 64 + rr + w;
+    if (r < m) At[(size_t)r * ldr + j] = (j < n) ? tile[lane][rr + w] : 0.0;
+  }
+}
+// d_j = sqrt(sum over the row blocks of colsq), in block order
+__global__ void k_colnorms_parts(int n, int nblk, const double *colsq, double *d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  int b = 0;
+  for (; b + 4 <= nblk; b += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] += colsq[(size_t)(b + u) * n + j];
+  }
+  for (; b < nblk; ++b) c[0] += colsq[(size_t)b * n + j];
+  d[j] = sqrt((c[0] + c[1]) + (c[2] + c[3]));
+}
+hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
+                                double *colsq, double *d, int *flag, hipStream_t st) {
+  const int nblk = (m + 63) / 64;
+  TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(nblk, (unsigned)(ldr / 64)), dim3(256), 0, st, m, n, ld, A, ldr, At,
+             colsq, flag);
+  TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nblk, colsq, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
                                hipStream_t st) {
   TLS_LAUNCH(PC_SETUP, k_colnorms_csc, dim3((n + 3) / 4), dim3(256), 0, st, n, col_ptr, cval, d);

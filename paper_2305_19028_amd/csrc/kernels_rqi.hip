@@ -11,6 +11,8 @@
 //   0 sigma^2   1 shift mu   2 ||x||^2   3 r^T r   4 b^T r   5 g (at mu)
 //   6 ||f||^2 (at mu)   7 psi   8 best psi   9 is-best flag   10 z^T f
 //   11 z^T x   12 beta   13 f^T x   14 shift cap   15 iteration count
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -98,6 +100,142 @@ __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_
   const double rr = block_sum(rv * rv, sc);
   const double br = block_sum(bv * rv, sc + 4);
   if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
+}
+
+// ---------------------------------------------------------------------------
+// One pass over the row-major copy of a dense A: r = b - A x and A^T r
+// ---------------------------------------------------------------------------
+// Algorithm 2 forms r_k = b - A x_k and then f_k = -A^T r_k - sigma_k^2 x_k.
+// A^T r = sum_i a_i r_i, and r_i needs row a_i alone, so a pass that holds
+// row a_i once can form r_i and add a_i r_i to a running A^T r: one read of A
+// per outer step instead of two. A wave owns a row at a time (lane l holds
+// columns l + 64 t, 64 t < ldr); x and the wave's share of A^T r stay in its
+// registers. A workgroup of RR_WAVES waves takes `groups` consecutive 64-row
+// groups (wave w: rows 8w..8w+7 of each group), joins its waves' A^T r in
+// wave order through LDS and writes one partial n-vector; per 64-row group it
+// writes (r^T r, b^T r) in the layout of k_residual_dense (the same number of
+// partials, ceil(m / 64)). b == nullptr means b = 0 (r = -A x), x ==
+// nullptr means x = 0 (r = b): the pass then gives -A^T A x or A^T b.
+constexpr int RR_WAVES = 4, RR_MAXG = 64, RR_RPW = 64 / RR_WAVES;
+
+template <int TT>
+__global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, int64_t ldr, const double *At,
+                                                                const double *b, const double *x, double *r,
+                                                                double *part_r, int groups, double *ppart) {
+  __shared__ double sx[TT * 64], sp[TT * 64];
+  __shared__ double srr[RR_WAVES][RR_MAXG], sbr[RR_WAVES][RR_MAXG];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nt = (int)(ldr >> 6);                    // 64-column stripes of a row (<= TT)
+  for (int j = threadIdx.x; j < TT * 64; j += RR_WAVES * 64) sx[j] = (x && j < n) ? x[j] : 0.0;
+  __syncthreads();
+  double pr[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) pr[t] = 0.0;
+  const int g0 = blockIdx.x * groups;
+  for (int q = 0; q < groups; ++q) {
+    double rr = 0.0, br = 0.0;
+    for (int k = 0; k < RR_RPW; ++k) {
+      const int i = (g0 + q) * 64 + RR_RPW * w + k;
+      if (i >= m) break;
+      const double *row = At + (size_t)i * ldr + lane;
+      double a[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) a[t] = (t < nt) ? __builtin_nontemporal_load(row + 64 * t) : 0.0;
+      double dot = 0.0;
+      if (x) {
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < TT; ++t) c[t & 3] += a[t] * sx[lane + 64 * t];
+        dot = wave_sum((c[0] + c[1]) + (c[2] + c[3]));
+      }
+      const double bi = b ? b[i] : 0.0;
+      const double ri = bi - dot;
+      if (r && lane == 0) r[i] = ri;
+      rr += ri * ri;
+      br += bi * ri;
+#pragma unroll
+      for (int t = 0; t < TT; ++t) pr[t] += a[t] * ri;
+    }
+    if (lane == 0) { srr[w][q] = rr; sbr[w][q] = br; }
+  }
+  // the waves' A^T r joined in wave order
+  for (int q = 0; q < RR_WAVES; ++q) {
+    if (w == q) {
+#pragma unroll
+      for (int t = 0; t < TT; ++t)
+        if (t < nt) sp[lane + 64 * t] = (q == 0) ? pr[t] : sp[lane + 64 * t] + pr[t];
+    }
+    __syncthreads();
+  }
+  double *dst = ppart + (size_t)blockIdx.x * n;
+  for (int j = threadIdx.x; j < n; j += RR_WAVES * 64) dst[j] = sp[j];
+  if (part_r) {
+    for (int q = threadIdx.x; q < groups; q += RR_WAVES * 64) {
+      const int gq = g0 + q;
+      if (gq * 64 >= m) break;
+      double rr = 0.0, br = 0.0;
+      for (int v = 0; v < RR_WAVES; ++v) { rr += srr[v][q]; br += sbr[v][q]; }
+      part_r[2 * gq] = rr;
+      part_r[2 * gq + 1] = br;
+    }
+  }
+}
+
+// 64-row groups per workgroup of the row pass: about one workgroup per CU
+int rowpass_groups(int64_t m, int cus) {
+  const int64_t ng = (m + 63) / 64;
+  return (int)std::min<int64_t>(RR_MAXG, std::max<int64_t>(1, (ng + cus - 1) / cus));
+}
+int rowpass_blocks(int64_t m, int cus) {
+  const int64_t ng = (m + 63) / 64;
+  const int gpw = rowpass_groups(m, cus);
+  return (int)((ng + gpw - 1) / gpw);
+}
+static int rowpass_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0, v = 0;
+    cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  return cus;
+}
+int rowpass_partials(const MatView &A) { return rowpass_blocks(A.m, rowpass_cus()); }
+
+hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
+                          double *ppart, hipStream_t st) {
+  const int cus = rowpass_cus();
+  const int groups = rowpass_groups(A.m, cus), blocks = rowpass_blocks(A.m, cus);
+  const int nt = (int)(A.ldr >> 6);
+  const dim3 g(blocks), t(RR_WAVES * 64);
+  if (nt <= 16)
+    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<16>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
+  else if (nt <= 32)
+    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<32>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
+  else
+    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<64>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
+  return hipGetLastError();
+}
+
+// y = s * (sum of the row workgroups' partials), in a fixed order
+__global__ __launch_bounds__(256) void k_rowpass_sum(int n, int G, const double *ppart, double s, double *y) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  int g = 0;
+  for (; g + 4 <= G; g += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] += ppart[(size_t)(g + u) * n + j];
+  }
+  for (; g < G; ++g) c[0] += ppart[(size_t)g * n + j];
+  y[j] = s * ((c[0] + c[1]) + (c[2] + c[3]));
+}
+hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st) {
+  TLS_LAUNCH(PC_GRADIENT, k_rowpass_sum, dim3((A.n + 255) / 256), dim3(256), 0, st, A.n, rowpass_partials(A),
+             ppart, s, y);
+  return hipGetLastError();
 }
 
 hipError_t launch_residual(const MatView &A, const double *b, const double *x, double *r,
@@ -255,6 +393,44 @@ hipError_t launch_gradient(const MatView &A, const double *r, const double *x, d
   else
     TLS_LAUNCH(PC_GRADIENT, k_gradient<true>, g, dim3(256), 0, st, A.m, A.n, (int64_t)0, nullptr,
                        A.col_ptr, A.row_idx, A.cval, r, x, scal, f, part, part_r, nb_r, cap);
+  return hipGetLastError();
+}
+
+// f = -A^T r - mu x from the row pass's partial A^T r (fixed order over its
+// workgroups), with per-block partials of f.f and f.x as k_gradient writes them
+__global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
+                                                       double *scal, double *f, double *part,
+                                                       const double *part_r, int nb_r, double cap) {
+  __shared__ double sc[8], sff[8];
+  const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  double fv = 0.0, xv = 0.0;
+  if (j < n) {
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    int g = 0;
+    for (; g + 4 <= G; g += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] += ppart[(size_t)(g + u) * n + j];
+    }
+    for (; g < G; ++g) c[0] += ppart[(size_t)g * n + j];
+    const double atr = (c[0] + c[1]) + (c[2] + c[3]);
+    xv = x[j];
+    fv = -atr - mu * xv;
+    f[j] = fv;
+  }
+  const double ff = block_sum(fv * fv, sff);
+  const double fx = block_sum(fv * xv, sff + 4);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ff;
+    part[2 * blockIdx.x + 1] = fx;
+  }
+}
+int gradient_rows_blocks(int n) { return (n + 255) / 256; }
+hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
+                                double *f, double *part, const double *part_r, int nb_r, double cap,
+                                hipStream_t st) {
+  TLS_LAUNCH(PC_GRADIENT, k_gradient_rows, dim3(gradient_rows_blocks(A.n)), dim3(256), 0, st, A.n,
+             rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap);
   return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ struct tls_precond_s {
   double *d = nullptr;
   int32_t *col_ptr = nullptr, *row_idx = nullptr;
   double *cval = nullptr;
+  double *at = nullptr;            // row-major copy of a dense A (stride ldr), or NULL
+  int64_t ldr = 0;
   tls_gate_report rep{};
   void *xr = nullptr, *xc = nullptr;   // explicit inverse tiles
   int xstorage = TLS_FP64;
@@ -106,6 +108,7 @@ struct tls_precond_s {
   void *fws_base = nullptr;       // the factor workspace (re-carved on demand)
   int64_t fws_m = 0;
   int fws_cast = 0;               // the factor workspace holds a cast buffer
+  int fws_rows = 0;               // ... and the row-major copy of a dense A
   int method = 0;                 // 0 Cholesky of the Gram matrix, 1 Householder QR of A
   int have_sigma_n = 0, have_kappa = 0;
   double smin_s = 0, smax_s = 0;   // Lanczos extremes of sigma(A D^{-1})
@@ -156,6 +159,8 @@ MatView make_view(const tls_matrix *A, const tls_precond_s *P) {
     V.col_ptr = P->col_ptr;
     V.row_idx = P->row_idx;
     V.cval = P->cval;
+    V.at = P->at;
+    V.ldr = P->ldr;
   }
   return V;
 }
@@ -210,11 +215,22 @@ struct FactorWs {
   // the certificate's own buffers (it runs concurrently with the estimates)
   int *qsync, *qcnt;
   double *qpart, *qlz, *qlzs;
+  // row-major copy of a dense A (rows of stride ldr), its column-norm scratch
+  // and the certificate's row-pass partials; NULL unless made
+  double *at, *colsq, *qppart;
+  int64_t ldr;
 };
+
+// dense A whose rows fit the row pass's registers (n <= 4096) get a
+// row-major working copy: every product with A in the outer iteration, the
+// certificate and the refinement is then one pass over it
+inline bool use_rowcopy(int format, int64_t n) { return format == TLS_DENSE_COLMAJOR && n <= 4096; }
+inline int64_t rowcopy_ld(int64_t n) { return (n + 63) / 64 * 64; }
 constexpr int LANCZOS_STEPS = 8;
 constexpr int QUALITY_STEPS = 6;
 
-FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast, int qr = 0) {
+FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, int cast, int qr = 0,
+                      int rows = 0) {
   const int Np = ceil_div(n, NB) * NB, N = Np / NB;
   FactorWs W{};
   W.tiles = c.take<char>((size_t)N * (N + 1) / 2 * NB * NB * 8);
@@ -260,6 +276,18 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   // low-precision copy of a dense A for the matrix-core Gram
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
   W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
+  W.at = W.colsq = W.qppart = nullptr;
+  W.ldr = 0;
+  if (rows && use_rowcopy(format, n)) {
+    MatView V{};
+    V.format = format;
+    V.m = (int)m;
+    V.n = (int)n;
+    W.ldr = rowcopy_ld(n);
+    W.at = c.take<double>((size_t)m * W.ldr);
+    W.colsq = c.take<double>((size_t)((m + 63) / 64) * n);
+    W.qppart = c.take<double>((size_t)rowpass_partials(V) * n);
+  }
   return W;
 }
 
@@ -520,7 +548,7 @@ size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q) {
   (void)u_q;
   if (check_matrix(A) != TLS_OK) return 0;
   Carver c(nullptr);
-  carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64);
+  carve_factor(c, A->m, A->n, A->nnz, A->format, u_q != TLS_FP64, 0, 1);
   return c.size();
 }
 
@@ -528,7 +556,7 @@ size_t tls_factor_qr_workspace_size(const tls_matrix *A, int32_t u_q) {
   (void)u_q;
   if (check_matrix(A) != TLS_OK) return 0;
   Carver c(nullptr);
-  carve_factor(c, A->m, A->n, A->nnz, A->format, 0, 1);
+  carve_factor(c, A->m, A->n, A->nnz, A->format, 0, 1, 1);
   return c.size();
 }
 
@@ -731,8 +759,13 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
   }
   for (int k = 0; k < K; ++k) {
     TRY(apply_R(&Q, 0, 1, inb, tmp, TLS_FP64, S, st));     // R^{-1} v
-    HIPCHK(launch_matvec(V, tmp, W.tm, st));                 // A R^{-1} v
-    HIPCHK(launch_rmatvec(V, W.tm, tn, st));                 // A^T A R^{-1} v
+    if (V.at) {                                              // A^T A R^{-1} v in one pass
+      HIPCHK(launch_rowpass(V, nullptr, tmp, nullptr, nullptr, W.qppart, st));
+      HIPCHK(launch_rowpass_sum(V, W.qppart, -1.0, tn, st));
+    } else {
+      HIPCHK(launch_matvec(V, tmp, W.tm, st));               // A R^{-1} v
+      HIPCHK(launch_rmatvec(V, W.tm, tn, st));               // A^T A R^{-1} v
+    }
     TRY(apply_R(&Q, 1, 1, tn, outb, TLS_FP64, S, st));     // R^{-T} A^T A R^{-1} v
     HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
   }
@@ -913,7 +946,7 @@ void gate_decide(tls_precond_s *P, double sigma_ls) {
 
 FactorWs factor_ws_of(const tls_precond_s *P) {
   Carver c(P->fws_base);
-  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format, P->fws_cast, P->method);
+  return carve_factor(c, P->fws_m, P->n, P->nnz, P->format, P->fws_cast, P->method, P->fws_rows);
 }
 
 // tiles of the storage precision, diagonal-tile inverses and the explicit
@@ -1036,7 +1069,7 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "factor workspace %zu < %zu bytes", ws_bytes, need);
     const int cast = (u_q != TLS_FP64) && !method;
     Carver c(ws);
-    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, cast, method);
+    FactorWs W = carve_factor(c, A->m, A->n, A->nnz, A->format, cast, method, 1);
     auto *P = new (std::nothrow) tls_precond_s();
     if (!P) return fail(TLS_ERR_ARG, "out of host memory");
     std::unique_ptr<tls_precond_s> guard(P);
@@ -1058,6 +1091,7 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     P->fws_base = ws;
     P->fws_m = A->m;
     P->fws_cast = cast;
+    P->fws_rows = 1;
     P->method = method;
     P->rep = tls_gate_report{};
     P->rep.requested = u_q;
@@ -1071,9 +1105,14 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       HIPCHK(launch_fill_multi(F, stream));
     }
     const size_t nval = A->format == TLS_CSR ? (size_t)A->nnz : (size_t)A->ld * (size_t)(n - 1) + (size_t)A->m;
-    HIPCHK(launch_check_finite(A->val, nval, W.flag, stream));
-    // CSC copy and column norms
-    if (A->format == TLS_CSR) {
+    if (!W.at) HIPCHK(launch_check_finite(A->val, nval, W.flag, stream));
+    // CSC copy and column norms (dense: the row-major copy, its column norms
+    // and the finite-input flag in one pass)
+    if (W.at) {
+      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.colsq, W.d, W.flag, stream));
+      P->at = W.at;
+      P->ldr = W.ldr;
+    } else if (A->format == TLS_CSR) {
       HIPCHK(launch_csc_build((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, A->val, W.col_ptr,
                               W.row_idx, W.cval, W.tmp_row, W.tmp_val, W.fill, stream));
       HIPCHK(launch_colnorms_csc(n, W.col_ptr, W.cval, W.d, stream));
@@ -1374,6 +1413,7 @@ namespace {
 
 struct RqiWs {
   double *r, *f, *xbest, *rhs, *wu, *t1, *t2, *part, *scal, *rec;
+  double *ppart;                         // row-pass partials (dense A with a row-major copy)
   double *rr, *rz, *rp, *rq, *rt, *rs;   // refinement PCG: residual, M r, direction, K p, A p, scalars
   PcgWs pcg;
 };
@@ -1402,6 +1442,7 @@ RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s
   W.rt = c.take<double>(2 * m);
   W.rs = c.take<double>(16);
   W.pcg = carve_pcg(c, P->Np, P->N, 2, L);
+  W.ppart = P->at ? c.take<double>((size_t)rowpass_partials(V) * n) : nullptr;
   return W;
 }
 
@@ -1561,7 +1602,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     const int n = (int)A->n;
     const int m = (int)A->m;
     const MatView V = make_view(A, P);
-    const int nb_r = matvec_blocks(V), nb_f = rmatvec_blocks(V);
+    const int nb_r = matvec_blocks(V), nb_f = V.at ? gradient_rows_blocks(n) : rmatvec_blocks(V);
     tls_rqi_stats local{};
     tls_rqi_stats &S = stats ? *stats : local;
     std::memset(&S, 0, sizeof S);
@@ -1586,9 +1627,30 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     // the smallest so far): three launches
     double *part_f = W.part + 2 * (size_t)nb_r;
     auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
-      HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
-      HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
+      if (V.at) {   // r and A^T r in one pass over the row-major copy
+        HIPCHK(launch_rowpass(V, b, xv, W.r, W.part, W.ppart, st));
+        HIPCHK(launch_gradient_rows(V, W.ppart, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
+      } else {
+        HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
+        HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
+      }
       HIPCHK(launch_outer_psi(n, xv, W.f, part_f, nb_f, W.scal, k, W.rec, W.rhs, W.xbest, st));
+      return TLS_OK;
+    };
+    // out = A^T (b - A xv) (xv NULL: A^T b), with r = b - A xv and its
+    // partials in W.r, W.part when xv is given
+    auto atr_pass = [&](const double *xv, double *out) -> tls_status {
+      if (V.at) {
+        HIPCHK(launch_rowpass(V, b, xv, xv ? W.r : nullptr, xv ? W.part : nullptr, W.ppart, st));
+        HIPCHK(launch_rowpass_sum(V, W.ppart, 1.0, out, st));
+      } else {
+        if (xv) {
+          HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
+          HIPCHK(launch_rmatvec(V, W.r, out, st));
+        } else {
+          HIPCHK(launch_rmatvec(V, b, out, st));
+        }
+      }
       return TLS_OK;
     };
     auto evaluate = [&](int k, double cap) -> tls_status { return evaluate_at(x, k, cap); };
@@ -1597,7 +1659,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     double rr0 = 0.0;
     bool spec = false, ls_deferred = false;
     for (;;) {
-      HIPCHK(launch_rmatvec(V, b, W.t1, st));                       // A^T b
+      TRY(atr_pass(nullptr, W.t1));                                 // A^T b
       if (o->mlp_theta || o->sigma0_hint > 0 || o->features) {
         DotPairs D{};
         D.a[0] = D.b[0] = b; D.len[0] = m;
@@ -1606,8 +1668,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       }
       TRY(solve_normal(P, W.t1, x, W.t2, W.pcg, st));               // x = R^{-1} R^{-T} A^T b
       for (int c2 = 0; c2 < o->ls_corrections; ++c2) {               // corrected semi-normal equations
-        HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
-        HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
+        TRY(atr_pass(x, W.t1));
         TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
         HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
       }
@@ -1617,8 +1678,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         // certificate per correction)
         S.ls_refined = 1;
         for (int c2 = 0; c2 < 64; ++c2) {
-          HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
-          HIPCHK(launch_rmatvec(V, W.r, W.t1, st));
+          TRY(atr_pass(x, W.t1));
           TRY(solve_normal(P, W.t1, W.rhs, W.t2, W.pcg, st));
           HIPCHK(launch_add_f64(x, W.rhs, (size_t)n, st));
           DotPairs D{};
@@ -1632,7 +1692,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
           if (!(dd[0] > 1e-16 * dd[1])) break;
         }
       }
-      HIPCHK(launch_residual(V, b, x, W.r, W.part, st));             // r_0
+      if (V.at) HIPCHK(launch_rowpass(V, b, x, W.r, W.part, W.ppart, st));   // r_0
+      else HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       // nothing before the first psi read-back needs sigma_0 on the host
       // unless a warm start, the shift clamp or a waiting gate does: then
@@ -1895,8 +1956,13 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
             if (rzj[0] <= 1e-26 * rz0[0] && rzj[4] <= 1e-26 * rz0[4]) break;
           }
           for (int q = 0; q < 2; ++q) {                         // K p = A^T (A p) - mu p
-            HIPCHK(launch_matvec(V, W.rp + (size_t)q * n, W.rt + (size_t)q * m, st));
-            HIPCHK(launch_rmatvec(V, W.rt + (size_t)q * m, W.rq + (size_t)q * n, st));
+            if (V.at) {                                         // A^T A p in one pass
+              HIPCHK(launch_rowpass(V, nullptr, W.rp + (size_t)q * n, nullptr, nullptr, W.ppart, st));
+              HIPCHK(launch_rowpass_sum(V, W.ppart, -1.0, W.rq + (size_t)q * n, st));
+            } else {
+              HIPCHK(launch_matvec(V, W.rp + (size_t)q * n, W.rt + (size_t)q * m, st));
+              HIPCHK(launch_rmatvec(V, W.rt + (size_t)q * m, W.rq + (size_t)q * n, st));
+            }
           }
           HIPCHK(launch_ref_step1(n, 2, W.scal, W.wu, W.rr, W.rp, W.rq, W.rs, st));
           TRY(apply_R(P, 1, 2, W.rr, W.rq, TLS_FP64, W.pcg, st));
