@@ -56,7 +56,8 @@ WORKLOADS = {
                   # the factor per instance before its result is used
                   "mixed": dict(u_q="bf16", u_p="fp32", opts=GATED)},
         "dtype": "bf16 factor (MFMA Gram, f32 accumulation) / f32 PCG / f64 outer",
-        "variants": {"fp16_factor": dict(u_q="fp16", u_p="fp32", opts=GATED),
+        "variants": {"bf16x3_factor": dict(u_q="bf16x3", u_p="fp32", opts=GATED),
+                     "fp16_factor": dict(u_q="fp16", u_p="fp32", opts=GATED),
                      "fp32_factor": dict(u_q="fp32", u_p="fp32", opts=GATED),
                      "qr_fp32": dict(u_q="fp32", u_p="fp32", opts=GATED, method="qr")},
     },

@@ -58,7 +58,13 @@ extern "C" {
 #endif
 
 /* Precisions (Table 2, plus bfloat16, which the paper does not use). */
-typedef enum { TLS_FP64 = 0, TLS_FP32 = 1, TLS_FP16 = 2, TLS_BF16 = 3 } tls_prec;
+/* TLS_BF16X3 (factor precision only, Cholesky route): each entry a of the
+ * scaled A D^{-1} is split into two BF16 numbers, hi = bf16(a) and
+ * lo = bf16(a - hi); the Gram matrix is hi^T hi + hi^T lo + lo^T hi on the
+ * BF16 matrix cores with FP32 accumulation (lo^T lo, below 2^-16 relative,
+ * is dropped) and the factor is computed and stored in FP32. Its unit
+ * roundoff for the constraints of Section 3.1 is taken as 2^-16. */
+typedef enum { TLS_FP64 = 0, TLS_FP32 = 1, TLS_FP16 = 2, TLS_BF16 = 3, TLS_BF16X3 = 4 } tls_prec;
 
 /* Storage format of A. */
 typedef enum { TLS_DENSE_COLMAJOR = 0, TLS_CSR = 1 } tls_format;
@@ -119,14 +125,19 @@ typedef struct {
                               filled by tls_rqi_solve, which knows b             */
   double u_q;              /* unit roundoff of the precision finally used        */
   double ctilde_min;       /* lambda_min estimate of C = I - s0^2 R^{-T}R^{-1}   */
-  double quality_lo;       /* extreme Ritz values of R^{-T} A^T A R^{-1} (FP64   */
-  double quality_hi;       /* products with A): the a-posteriori certificate     */
+  double quality_lo;       /* extreme Ritz values of R^{-T} A^T A R^{-1}: the    */
+  double quality_hi;       /* a-posteriori certificate (products with A in FP64
+                              arithmetic, on an FP32 copy of a dense A)          */
+  double cert_margin;      /* the window [1/2, 3/2] is narrowed by this much on
+                              each side: the bound on what the FP32 copy of A
+                              can move the Ritz values (0 for FP64 products)   */
   int32_t requested;       /* tls_prec asked for                                 */
   int32_t used;            /* tls_prec actually used (after escalation)          */
   int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,
                               3: (6) holds, 4: a-posteriori certificate holds:
-                              quality_lo >= 1/2 and quality_hi <= 3/2 (the
-                              factor is within 50% of A^T A in every direction),
+                              quality_lo - cert_margin >= 1/2 and quality_hi +
+                              cert_margin <= 3/2 (the factor is within 50% of
+                              A^T A in every direction),
                               5: the solve's sigma lies below the estimate of
                               sigma'_n (the smallest-root check)               */
   int32_t escalations;     /* times u_q was raised                               */

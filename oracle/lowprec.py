@@ -18,7 +18,8 @@ at the smallest subnormal and overflow to infinity.
 
 Pins: tests/test_oracle_misc.py (rounding against numpy's float16
 cast, which is IEEE RNE, against exhaustive bf16 neighbours, and the
-backward-error size of the scaled factor).
+backward-error size of the scaled factor; the split pair against its
+defining bounds |x - hi - lo| <= 2^-8 |x - hi| <= 2^-16 |x|).
 """
 from __future__ import annotations
 
@@ -51,6 +52,23 @@ def round_to(x, fmt: str) -> np.ndarray:
     keep = ~nz                      # zeros keep their sign; Inf and NaN pass through
     out[keep] = x[keep]
     return out
+
+
+def split_bf16(x):
+    """The split BF16 pair of each value: hi = bf16(x), lo = bf16(x - hi)
+    (x - hi is exact in float64). hi + lo carries x to 2^-16 relative
+    (two 8-bit significands), the representation of the project's split BF16
+    Gram matrix (a project addition; the paper's u_q is a single format).
+    Returns (hi, lo) as float64."""
+    x = np.asarray(x, dtype=np.float64)
+    hi = round_to(x, "bf16")
+    return hi, round_to(x - hi, "bf16")
+
+
+def split_gram(Ah_hi, Ah_lo):
+    """hi^T hi + hi^T lo + lo^T hi in float64 (lo^T lo is dropped): the Gram
+    matrix the split BF16 route forms, up to its FP32 accumulation."""
+    return Ah_hi.T @ Ah_hi + Ah_hi.T @ Ah_lo + Ah_lo.T @ Ah_hi
 
 
 def column_norms(A) -> np.ndarray:

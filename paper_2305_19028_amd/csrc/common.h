@@ -92,9 +92,15 @@ __device__ inline double quantize(double v, int q) {
     case TLS_FP64: return v;
     case TLS_FP32: return (double)__builtin_bit_cast(float, f64_to_f32_bits(v));
     case TLS_FP16: return (double)f16_bits_to_float(f64_to_f16_bits(v));
+    case TLS_BF16X3: {                 // hi + lo, each rounded to BF16 (exact in FP32)
+      const double hi = (double)bf16_bits_to_float(f64_to_bf16_bits(v));
+      return hi + (double)bf16_bits_to_float(f64_to_bf16_bits(v - hi));
+    }
     default: return (double)bf16_bits_to_float(f64_to_bf16_bits(v));
   }
 }
+// storage precision of the factor computed at factor precision q
+inline int storage_of(int q) { return q == TLS_BF16X3 ? TLS_FP32 : q; }
 
 template <typename S> constexpr int prec_of();
 template <> constexpr int prec_of<double>() { return TLS_FP64; }
@@ -109,6 +115,7 @@ inline double unit_roundoff(int p) {
     case TLS_FP64: return 1.1102230246251565e-16;   // 2^-53
     case TLS_FP32: return 5.9604644775390625e-08;   // 2^-24
     case TLS_FP16: return 4.8828125e-04;            // 2^-11
+    case TLS_BF16X3: return 1.52587890625e-05;      // split BF16 pair: 2^-16
     default: return 3.90625e-03;                    // bf16: 2^-8
   }
 }

@@ -100,7 +100,7 @@ hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval
 // row-major copy At (stride ldr) of a dense column-major A, column norms d and
 // the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                double *colsq, double *d, int *flag, hipStream_t st);
+                                float *At32, double *colsq, double *d, int *flag, hipStream_t st);
 hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
                                  hipStream_t st);
 // scaling vectors: dinv = 1/d (or ones when unscaled), both precisions, padded to Np
@@ -160,6 +160,7 @@ struct MatView {
   // row-major copy of a dense A (row stride ldr, a multiple of 64, zero
   // padded), made by the factorization; nullptr when absent
   const double *at;
+  const float *at32;   // its FP32 rounding (the certificate's products), or nullptr
   int64_t ldr;
 };
 
@@ -178,8 +179,10 @@ int rmatvec_blocks(const MatView &A);
 int rowpass_groups(int64_t m, int cus);
 int rowpass_blocks(int64_t m, int cus);
 int rowpass_partials(const MatView &A);
+// row stride of the copy the row pass reads (1024, 2048, 3072 or 4096 columns)
+int64_t rowpass_ld(int64_t n);
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                          double *ppart, hipStream_t st);
+                          double *ppart, hipStream_t st, int f32 = 0);
 // y = s * sum of the partial n-vectors
 hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st);
 // f = -A^T r - mu x from the partials (gradient_rows_blocks(n) partial pairs)

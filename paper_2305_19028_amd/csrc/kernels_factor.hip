@@ -424,7 +424,7 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
 // a 64 x 64 tile per workgroup is read column by column (512-byte loads),
 // transposed through LDS and written row by row
 __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr,
-                                                       double *At, double *colsq, int *flag) {
+                                                       double *At, float *At32, double *colsq, int *flag) {
   __shared__ double tile[64][65];
   const int I = blockIdx.x, J = blockIdx.y;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -448,7 +448,11 @@ __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld,
 #pragma unroll 4
   for (int rr = 0; rr < 64; rr += 4) {
     const int r = I * 64 + rr + w;
-    if (r < m) At[(size_t)r * ldr + j] = (j < n) ? tile[lane][rr + w] : 0.0;
+    if (r < m) {
+      const double v = (j < n) ? tile[lane][rr + w] : 0.0;
+      At[(size_t)r * ldr + j] = v;
+      if (At32) At32[(size_t)r * ldr + j] = (float)v;
+    }
   }
 }
 // d_j = sqrt(sum over the row blocks of colsq), in block order
@@ -465,10 +469,10 @@ __global__ void k_colnorms_parts(int n, int nblk, const double *colsq, double *d
   d[j] = sqrt((c[0] + c[1]) + (c[2] + c[3]));
 }
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                double *colsq, double *d, int *flag, hipStream_t st) {
+                                float *At32, double *colsq, double *d, int *flag, hipStream_t st) {
   const int nblk = (m + 63) / 64;
   TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(nblk, (unsigned)(ldr / 64)), dim3(256), 0, st, m, n, ld, A, ldr, At,
-             colsq, flag);
+             At32, colsq, flag);
   TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nblk, colsq, d);
   return hipGetLastError();
 }
@@ -1170,6 +1174,165 @@ __global__ __launch_bounds__(G16LANES) void k_gram_mfma16(int mp, const T *A, fl
       }
 }
 
+// ---- split BF16 inputs: a = hi + lo ------------------------------------------
+// Each entry a of A D^{-1} is carried as hi = bf16(a) and lo = bf16(a - hi)
+// (a - hi is exact in FP64), two planes in the chunk-major layout of the
+// 16-bit cast. The Gram matrix is hi^T hi + hi^T lo + lo^T hi: three BF16
+// MFMAs into one FP32 accumulator per block step, so the factor sees the
+// entries to 2^-16 relative (hi + lo) at the BF16 matrix-core rate. The kernel is
+// the paired-tile kernel above with 32-row half chunks (the two planes of
+// three panels fill 123 KB of LDS double buffered) and the same two-level
+// accumulation (the MFMA partial restarted every 128 rows).
+__global__ __launch_bounds__(256) void k_cast_split(int m, int n, int64_t ld, const double *A, const double *d,
+                                                   int scaled, int mp, int n128, bf16_t *hi, bf16_t *lo) {
+  const int c = blockIdx.y;
+  const double sc = (c < n && scaled) ? 1.0 / d[c] : 1.0;
+  const double *col = A + (size_t)c * ld;
+  for (int r = blockIdx.x * 1024 + threadIdx.x; r < min(mp, (int)(blockIdx.x + 1) * 1024); r += 256) {
+    const double v = (r < m && c < n) ? col[r] * sc : 0.0;
+    const uint16_t h = f64_to_bf16_bits(v);
+    const double vh = (double)bf16_bits_to_float(h);
+    const size_t o = ((size_t)(r / G16K) * n128 + c) * G16K + (r % G16K);
+    hi[o] = bf16_t{h};
+    lo[o] = bf16_t{f64_to_bf16_bits(v - vh)};
+  }
+}
+
+constexpr int G3K = 32, G3RL = G3K + 8, G3FOLD = 4;   // half chunks; fold every 128 rows
+
+__global__ __launch_bounds__(G16LANES) void k_gram_mfma16x3(int mp, const bf16_t *Ahi, const bf16_t *Alo,
+                                                            float *part, int NT, int seglen, int npairs,
+                                                            int nseg) {
+  // stage b: rows 0..127 panel J hi, 128..255 J lo, 256.. I0 hi, I0 lo, I0+1 hi, I0+1 lo
+  __shared__ __attribute__((aligned(16))) bf16_t S[2][6 * GT][G3RL];
+  const int ntiles = NT * (NT + 1) / 2;
+  const int total = npairs * nseg, L = blockIdx.x;
+  const int xcd = L & 7, k = L >> 3, q8 = total >> 3, r8 = total & 7;
+  const int Wl = xcd * q8 + min(xcd, r8) + k;
+  const int seg = Wl / npairs, p = Wl - seg * npairs;
+  int I0, J;
+  gram_pair_of(p, I0, J);
+  const int I1 = I0 + 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int h = w >> 2, wr = (w >> 1) & 1, wc = w & 1;
+  const bool live = (h == 0) || (I1 <= J);
+  const int kbeg = seg * seglen;
+  const int nhc = 2 * ((min(mp, kbeg + seglen) - kbeg) / G16K);    // 32-row half chunks
+  const size_t cstride = (size_t)NT * GT * G16K;                    // elements per 64-row chunk
+  // load slot i (0..5): panel i >> 1, plane i & 1; thread tid moves 16 bytes
+  // (part tid & 3 of the 32-row segment) of column tid >> 2
+  const int colJ = J * GT, colI0 = I0 * GT, colI1 = min(I1, NT - 1) * GT;
+  const int ccol = tid >> 2, cpart = (tid & 3) * 8;
+  const bf16_t *gbase[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int pn = i >> 1;
+    const bf16_t *plane = (i & 1) ? Alo : Ahi;
+    gbase[i] = plane + (size_t)kbeg * NT * GT + (size_t)((pn == 0 ? colJ : pn == 1 ? colI0 : colI1) + ccol) * G16K +
+               cpart;
+  }
+  g_f32x16 acc[2][2];
+  float sum[2][2][16];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        acc[t][u][q] = 0.0f;
+        sum[t][u][q] = 0.0f;
+      }
+  uint4 a0, a1, a2, a3, a4, a5, b0, b1, b2, b3, b4, b5;
+  // half chunk hc: 64-row chunk hc >> 1, rows 32 (hc & 1) onwards
+#define G3_FETCH(X, hc)                                                                       \
+  do {                                                                                        \
+    const size_t off_ = (size_t)((hc) >> 1) * cstride + (size_t)((hc) & 1) * G3K;             \
+    X##0 = *(const uint4 *)(gbase[0] + off_); X##1 = *(const uint4 *)(gbase[1] + off_);       \
+    X##2 = *(const uint4 *)(gbase[2] + off_); X##3 = *(const uint4 *)(gbase[3] + off_);       \
+    X##4 = *(const uint4 *)(gbase[4] + off_); X##5 = *(const uint4 *)(gbase[5] + off_);       \
+  } while (0)
+#define G3_STAGE(X, b)                                                                        \
+  do {                                                                                        \
+    *(uint4 *)&S[b][0 * GT + ccol][cpart] = X##0; *(uint4 *)&S[b][1 * GT + ccol][cpart] = X##1; \
+    *(uint4 *)&S[b][2 * GT + ccol][cpart] = X##2; *(uint4 *)&S[b][3 * GT + ccol][cpart] = X##3; \
+    *(uint4 *)&S[b][4 * GT + ccol][cpart] = X##4; *(uint4 *)&S[b][5 * GT + ccol][cpart] = X##5; \
+  } while (0)
+  auto fold = [&]() {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          sum[t][u][q] += acc[t][u][q];
+          acc[t][u][q] = 0.0f;
+        }
+  };
+  // A operand: panel J (hi rows 0.., lo rows 128..); B operand: panel I0 + h
+  const int arow = wc * 64 + (lane & 31), brow = (2 + 2 * h) * GT + wr * 64 + (lane & 31);
+  const int koff = 8 * (lane >> 5);
+  auto compute = [&](int b) {
+    if (!live) return;
+#pragma unroll
+    for (int s = 0; s < G3K / 16; ++s) {
+      uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ah[t] = *(const uint4 *)&S[b][arow + t * 32][s * 16 + koff];
+        al[t] = *(const uint4 *)&S[b][GT + arow + t * 32][s * 16 + koff];
+        bh[t] = *(const uint4 *)&S[b][brow + t * 32][s * 16 + koff];
+        bl[t] = *(const uint4 *)&S[b][GT + brow + t * 32][s * 16 + koff];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          acc[t][u] = mfma16<bf16_t>(ah[t], bh[u], acc[t][u]);
+          acc[t][u] = mfma16<bf16_t>(ah[t], bl[u], acc[t][u]);
+          acc[t][u] = mfma16<bf16_t>(al[t], bh[u], acc[t][u]);
+        }
+    }
+  };
+  if (nhc > 0) G3_FETCH(a, 0);
+  if (nhc > 1) G3_FETCH(b, 1);
+  if (nhc > 0) G3_STAGE(a, 0);
+  if (nhc > 2) G3_FETCH(a, 2);
+  __syncthreads();
+  for (int it = 0; it < nhc; it += 2) {
+    compute(0);
+    if (it + 1 < nhc) {
+      G3_STAGE(b, 1);
+      if (it + 3 < nhc) G3_FETCH(b, it + 3);
+    }
+    if ((it + 1) % G3FOLD == 0) fold();
+    __syncthreads();
+    if (it + 1 >= nhc) break;
+    compute(1);
+    if (it + 2 < nhc) {
+      G3_STAGE(a, 0);
+      if (it + 4 < nhc) G3_FETCH(a, it + 4);
+    }
+    if ((it + 2) % G3FOLD == 0) fold();
+    __syncthreads();
+  }
+#undef G3_FETCH
+#undef G3_STAGE
+  fold();
+  if (!live) return;
+  const int l = J * (J + 1) / 2 + I0 + h;
+  float *dst = part + ((size_t)seg * ntiles + l) * GT * GT;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int cl = wc * 64 + t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int rl = wr * 64 + u * 32 + (lane & 31);
+        dst[cl * GT + rl] = sum[t][u][q];
+      }
+}
+
 // G (upper, column-major, FP32) = sum over segments of the partial tiles,
 // added in FP64 in segment order
 __global__ __launch_bounds__(256) void k_gram_reduce(const float *part, int nseg, int NT, int Np, float *G) {
@@ -1222,6 +1385,15 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
+    case TLS_BF16X3: {
+      bf16_t *hi = (bf16_t *)cast, *lo = hi + (size_t)mp * n128;
+      TLS_LAUNCH(PC_GRAM, k_cast_split, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128, hi, lo);
+      TLS_LAUNCH(PC_GRAM, k_gram_mfma16x3, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)hi, (const bf16_t *)lo,
+                 part, NT, gp.seglen, gp.npairs, nseg);
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+                 (float *)G);
+      break;
+    }
     default:
       TLS_LAUNCH(PC_GRAM, k_cast_blocked<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  (bf16_t *)cast);

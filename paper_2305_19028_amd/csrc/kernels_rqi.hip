@@ -118,14 +118,25 @@ __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_
 // nullptr means x = 0 (r = b): the pass then gives -A^T A x or A^T b.
 constexpr int RR_WAVES = 4, RR_MAXG = 64, RR_RPW = 64 / RR_WAVES;
 
-template <int TT>
-__global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, int64_t ldr, const double *At,
+typedef double rp_d2 __attribute__((ext_vector_type(2)));
+typedef float rp_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = rp_d2; static constexpr int N = 2; };
+template <> struct Vec16<float> { using type = rp_f4; static constexpr int N = 4; };
+template <typename V> __device__ inline double vget(const V &v, int k) { return (double)v[k]; }
+
+// TT: columns per lane (the row stride ldr is 64 TT, padded with zeros).
+// Lane l reads 16 bytes at a time: columns 64 VN s + VN l + v (v < VN) of
+// load s, so that one load instruction of a wave moves 1 KB of the row.
+template <int TT, typename T>
+__global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, int64_t ldr, const T *At,
                                                                 const double *b, const double *x, double *r,
                                                                 double *part_r, int groups, double *ppart) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::N, NS = TT / VN;       // elements per load, loads per row
   __shared__ double sx[TT * 64], sp[TT * 64];
   __shared__ double srr[RR_WAVES][RR_MAXG], sbr[RR_WAVES][RR_MAXG];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nt = (int)(ldr >> 6);                    // 64-column stripes of a row (<= TT)
   for (int j = threadIdx.x; j < TT * 64; j += RR_WAVES * 64) sx[j] = (x && j < n) ? x[j] : 0.0;
   __syncthreads();
   double pr[TT];
@@ -137,15 +148,17 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
     for (int k = 0; k < RR_RPW; ++k) {
       const int i = (g0 + q) * 64 + RR_RPW * w + k;
       if (i >= m) break;
-      const double *row = At + (size_t)i * ldr + lane;
-      double a[TT];
+      const V *row = (const V *)(At + (size_t)i * ldr) + lane;
+      V a[NS];
 #pragma unroll
-      for (int t = 0; t < TT; ++t) a[t] = (t < nt) ? __builtin_nontemporal_load(row + 64 * t) : 0.0;
+      for (int s = 0; s < NS; ++s) a[s] = __builtin_nontemporal_load(row + 64 * s);
       double dot = 0.0;
       if (x) {
         double c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < TT; ++t) c[t & 3] += a[t] * sx[lane + 64 * t];
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int v = 0; v < VN; ++v) c[(s * VN + v) & 3] += vget(a[s], v) * sx[64 * VN * s + VN * lane + v];
         dot = wave_sum((c[0] + c[1]) + (c[2] + c[3]));
       }
       const double bi = b ? b[i] : 0.0;
@@ -154,7 +167,9 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
       rr += ri * ri;
       br += bi * ri;
 #pragma unroll
-      for (int t = 0; t < TT; ++t) pr[t] += a[t] * ri;
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int v = 0; v < VN; ++v) pr[s * VN + v] += vget(a[s], v) * ri;
     }
     if (lane == 0) { srr[w][q] = rr; sbr[w][q] = br; }
   }
@@ -162,8 +177,12 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
   for (int q = 0; q < RR_WAVES; ++q) {
     if (w == q) {
 #pragma unroll
-      for (int t = 0; t < TT; ++t)
-        if (t < nt) sp[lane + 64 * t] = (q == 0) ? pr[t] : sp[lane + 64 * t] + pr[t];
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+          const int c = 64 * VN * s + VN * lane + v;
+          sp[c] = (q == 0) ? pr[s * VN + v] : sp[c] + pr[s * VN + v];
+        }
     }
     __syncthreads();
   }
@@ -203,20 +222,44 @@ static int rowpass_cus() {
   return cus;
 }
 int rowpass_partials(const MatView &A) { return rowpass_blocks(A.m, rowpass_cus()); }
+int64_t rowpass_ld(int64_t n) {
+  const int64_t t = (n + 63) / 64;
+  return 64 * (t <= 16 ? 16 : t <= 32 ? 32 : t <= 48 ? 48 : 64);
+}
 
-hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                          double *ppart, hipStream_t st) {
+template <typename T>
+static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, const double *x, double *r,
+                             double *part_r, double *ppart, hipStream_t st) {
   const int cus = rowpass_cus();
   const int groups = rowpass_groups(A.m, cus), blocks = rowpass_blocks(A.m, cus);
-  const int nt = (int)(A.ldr >> 6);
+  const int nt = (int)(A.ldr >> 6);    // the copy's stride is 64 TT (rowpass_ld)
   const dim3 g(blocks), t(RR_WAVES * 64);
-  if (nt <= 16)
-    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<16>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
-  else if (nt <= 32)
-    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<32>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
-  else
-    TLS_LAUNCH(PC_RESIDUAL, k_resgrad_rows<64>, g, t, 0, st, A.m, A.n, A.ldr, A.at, b, x, r, part_r, groups, ppart);
+  switch (nt) {
+    case 16:
+      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<16, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart);
+      break;
+    case 32:
+      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<32, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart);
+      break;
+    case 48:
+      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<48, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart);
+      break;
+    case 64:
+      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<64, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
+                          double *ppart, hipStream_t st, int f32) {
+  if (f32 && A.at32) return rowpass_go<float>(A, A.at32, b, x, r, part_r, ppart, st);
+  return rowpass_go<double>(A, A.at, b, x, r, part_r, ppart, st);
 }
 
 // y = s * (sum of the row workgroups' partials), in a fixed order

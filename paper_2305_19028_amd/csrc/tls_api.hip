@@ -90,6 +90,7 @@ struct tls_precond_s {
   int64_t n = 0;
   int N = 0, Np = 0;
   int storage = TLS_FP64, requested = TLS_FP64, scaled = 0, format = TLS_DENSE_COLMAJOR;
+  int uq = TLS_FP64;               // factor precision (storage_of(uq) == storage)
   int64_t m = 0, nnz = 0;
   void *tiles = nullptr;
   double *dinv64 = nullptr;
@@ -100,6 +101,7 @@ struct tls_precond_s {
   int32_t *col_ptr = nullptr, *row_idx = nullptr;
   double *cval = nullptr;
   double *at = nullptr;            // row-major copy of a dense A (stride ldr), or NULL
+  float *at32 = nullptr;           // its FP32 rounding (the certificate's products)
   int64_t ldr = 0;
   tls_gate_report rep{};
   void *xr = nullptr, *xc = nullptr;   // explicit inverse tiles
@@ -160,6 +162,7 @@ MatView make_view(const tls_matrix *A, const tls_precond_s *P) {
     V.row_idx = P->row_idx;
     V.cval = P->cval;
     V.at = P->at;
+    V.at32 = P->at32;
     V.ldr = P->ldr;
   }
   return V;
@@ -183,7 +186,7 @@ tls_status check_matrix(const tls_matrix *A) {
 }
 
 tls_status check_prec(int p, const char *what) {
-  if (p < TLS_FP64 || p > TLS_BF16) return fail(TLS_ERR_ARG, "invalid precision %d for %s", p, what);
+  if (p < TLS_FP64 || p > TLS_BF16X3) return fail(TLS_ERR_ARG, "invalid precision %d for %s", p, what);
   return TLS_OK;
 }
 
@@ -218,6 +221,7 @@ struct FactorWs {
   // row-major copy of a dense A (rows of stride ldr), its column-norm scratch
   // and the certificate's row-pass partials; NULL unless made
   double *at, *colsq, *qppart;
+  float *at32;
   int64_t ldr;
 };
 
@@ -225,7 +229,7 @@ struct FactorWs {
 // row-major working copy: every product with A in the outer iteration, the
 // certificate and the refinement is then one pass over it
 inline bool use_rowcopy(int format, int64_t n) { return format == TLS_DENSE_COLMAJOR && n <= 4096; }
-inline int64_t rowcopy_ld(int64_t n) { return (n + 63) / 64 * 64; }
+inline int64_t rowcopy_ld(int64_t n) { return rowpass_ld(n); }
 constexpr int LANCZOS_STEPS = 8;
 constexpr int QUALITY_STEPS = 6;
 
@@ -277,6 +281,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
   W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
   W.at = W.colsq = W.qppart = nullptr;
+  W.at32 = nullptr;
   W.ldr = 0;
   if (rows && use_rowcopy(format, n)) {
     MatView V{};
@@ -285,6 +290,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     V.n = (int)n;
     W.ldr = rowcopy_ld(n);
     W.at = c.take<double>((size_t)m * W.ldr);
+    W.at32 = c.take<float>((size_t)m * W.ldr);
     W.colsq = c.take<double>((size_t)((m + 63) / 64) * n);
     W.qppart = c.take<double>((size_t)rowpass_partials(V) * n);
   }
@@ -611,8 +617,8 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
 
 // the factor as the gate's runs apply it: a view that owns no events, with
 // the row GEMV of the explicit inverse (one workgroup per 64-row block) so
-// that the runs, when they overlap a solve, hold about N CUs instead of the
-// whole chip
+// that a run on the side stream, overlapping a solve, holds about N CUs
+// instead of the whole chip
 tls_precond_s gate_view(const tls_precond_s *P) {
   tls_precond_s Q = *P;
   Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;
@@ -715,7 +721,7 @@ tls_status collect_pair(tls_precond_s *P) {
   R.bound_chol = 1.0 / (kap * kap);
   R.bound_wilkinson = 1.0 / (20.0 * std::pow(n, 1.5) * kap * kap);
   R.bound_hp = R.lam_min_H / ((2.0 * R.lam_min_H + n) * (n + 1.0));
-  R.u_q = unit_roundoff(P->storage);
+  R.u_q = unit_roundoff(P->uq);
   int v = R.verdict & ~(1 | 2 | 4);
   if (R.u_q < R.bound5) v |= 1;
   if (R.u_q < R.bound_chol) v |= 2;
@@ -729,7 +735,7 @@ tls_status collect_pair(tls_precond_s *P) {
 // M = R^{-T} A^T A R^{-1} after QUALITY_STEPS Lanczos steps (products with A
 // and the applications of R in FP64). M = I for the exact factor. Its
 // buffers are its own, so it may run beside enqueue_pair.
-tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
+tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st, int on_main) {
   const int n = (int)P->n, Np = P->Np;
   const int K = std::min(QUALITY_STEPS, n);
   double *Vb = W.qlz;                                 // [K+1][Np]
@@ -744,7 +750,8 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
   S.cpart = W.qpart;
   S.cnt = W.qcnt;
   double *ab = W.qlzs;
-  const tls_precond_s Q = gate_view(P);
+  tls_precond_s Q = gate_view(P);
+  if (on_main) Q.apply_mode = P->apply_mode;   // the whole chip is the run's
   const double v0 = 1.0 / std::sqrt((double)n);
   {
     FillSet F;
@@ -760,7 +767,7 @@ tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStre
   for (int k = 0; k < K; ++k) {
     TRY(apply_R(&Q, 0, 1, inb, tmp, TLS_FP64, S, st));     // R^{-1} v
     if (V.at) {                                              // A^T A R^{-1} v in one pass
-      HIPCHK(launch_rowpass(V, nullptr, tmp, nullptr, nullptr, W.qppart, st));
+      HIPCHK(launch_rowpass(V, nullptr, tmp, nullptr, nullptr, W.qppart, st, 1));
       HIPCHK(launch_rowpass_sum(V, W.qppart, -1.0, tn, st));
     } else {
       HIPCHK(launch_matvec(V, tmp, W.tm, st));               // A R^{-1} v
@@ -891,8 +898,15 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   P->gate_pending = 1;
   tls_status s0 = enqueue_pair(P, W, P->side);
   hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
-  tls_status s1 = enqueue_cert(P, W, V, P->side);
-  hipError_t e1 = hipEventRecord(P->ev_cert, P->side);
+  // the certificate of a dense A runs on the caller's stream, before the
+  // solve: its six passes over the FP32 row copy would otherwise share HBM
+  // and CUs with the solve's passes, which are just as bandwidth-bound, and
+  // both would finish late. A sparse A's certificate (latency-bound
+  // launches, like the solve's) stays on the side stream.
+  const bool main_cert = V.at != nullptr;
+  hipStream_t cs = main_cert ? st : P->side;
+  tls_status s1 = enqueue_cert(P, W, V, cs, main_cert ? 1 : 0);
+  hipError_t e1 = hipEventRecord(P->ev_cert, cs);
   if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
     (void)hipStreamSynchronize(P->side);
     P->gate_pending = 0;
@@ -941,7 +955,18 @@ void gate_decide(tls_precond_s *P, double sigma_ls) {
   R.bound6 = (1.0 - ratio) / R.kappaF_est;
   R.verdict &= ~(8 | 16);
   if (R.u_q < R.bound6) R.verdict |= 8;
-  if (R.quality_lo >= 0.5 && R.quality_hi <= 1.5) R.verdict |= 16;
+  // the certificate's products used the FP32 copy of a dense A: with
+  // |A - A32| <= 2^-24 |A| entrywise, ||(A - A32) R^{-1}|| <= 2^-24
+  // || |A| D^{-1} ||_F ||R_hat^{-1}|| = 2^-24 sqrt(n) / sigma_min(R_hat) =: e,
+  // which moves the eigenvalues of R^{-T} A^T A R^{-1} by at most
+  // 2 e sqrt(quality_hi) + e^2; doubled, since sigma_min(R_hat) is itself
+  // a Lanczos estimate from above
+  R.cert_margin = 0.0;
+  if (P->at32 && P->smin_s > 0) {
+    const double e = std::ldexp(1.0, -24) * std::sqrt((double)P->n) / P->smin_s;
+    R.cert_margin = 2.0 * (2.0 * e * std::sqrt(std::max(R.quality_hi, 1.0)) + e * e);
+  }
+  if (R.quality_lo - R.cert_margin >= 0.5 && R.quality_hi + R.cert_margin <= 1.5) R.verdict |= 16;
 }
 
 FactorWs factor_ws_of(const tls_precond_s *P) {
@@ -953,11 +978,13 @@ FactorWs factor_ws_of(const tls_precond_s *P) {
 // inverse from the factor R_hat in G (the Cholesky steps leave its diagonal
 // tiles in W.rdiag: chol = 1)
 tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, int chol, hipStream_t st) {
-  HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, chol ? W.rdiag : nullptr, uq, W.tiles, st));
-  HIPCHK(launch_diag_inverse(P->N, uq, W.tiles, W.dinv64, W.dinv32, st));
-  P->storage = uq;
-  P->xstorage = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
-  HIPCHK(launch_invert(P->N, uq, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr, W.xc, st));
+  const int sq = storage_of(uq);   // the split BF16 factor is stored in FP32
+  HIPCHK(launch_pack_tiles(P->N, P->Np, compute, W.G, chol ? W.rdiag : nullptr, sq, W.tiles, st));
+  HIPCHK(launch_diag_inverse(P->N, sq, W.tiles, W.dinv64, W.dinv32, st));
+  P->storage = sq;
+  P->uq = uq;
+  P->xstorage = (sq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
+  HIPCHK(launch_invert(P->N, sq, W.tiles, W.dinv64, (double *)W.G, W.yinv, P->xstorage, W.xr, W.xc, st));
   P->xr = W.xr;
   P->xc = W.xc;
   return TLS_OK;
@@ -1065,6 +1092,7 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     if (!out) return fail(TLS_ERR_ARG, "out is NULL");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (!scaling && u_q != TLS_FP64) return fail(TLS_ERR_ARG, "unscaled factorization is FP64 only");
+    if (method && u_q == TLS_BF16X3) return fail(TLS_ERR_ARG, "the split BF16 precision is a Gram (Cholesky) route only");
     const size_t need = method ? tls_factor_qr_workspace_size(A, u_q) : tls_factor_workspace_size(A, u_q);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "factor workspace %zu < %zu bytes", ws_bytes, need);
     const int cast = (u_q != TLS_FP64) && !method;
@@ -1109,8 +1137,10 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     // CSC copy and column norms (dense: the row-major copy, its column norms
     // and the finite-input flag in one pass)
     if (W.at) {
-      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.colsq, W.d, W.flag, stream));
+      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.at32, W.colsq, W.d, W.flag,
+                                  stream));
       P->at = W.at;
+      P->at32 = W.at32;
       P->ldr = W.ldr;
     } else if (A->format == TLS_CSR) {
       HIPCHK(launch_csc_build((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, A->val, W.col_ptr,
@@ -1143,10 +1173,10 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       }
       if (s != TLS_ERR_NOT_SPD || !allow_escalate || uq == TLS_FP64) return s;
       // escalate: BF16 -> FP16 -> FP32 -> FP64
-      uq = (uq == TLS_BF16) ? TLS_FP16 : (uq == TLS_FP16) ? TLS_FP32 : TLS_FP64;
+      uq = (uq == TLS_BF16) ? TLS_FP16 : (uq == TLS_FP16 || uq == TLS_BF16X3) ? TLS_FP32 : TLS_FP64;
       P->rep.escalations++;
     }
-    P->rep.used = P->storage;
+    P->rep.used = P->uq;
     if (rep) *rep = P->rep;
     *out = guard.release();
     return TLS_OK;
@@ -1241,6 +1271,7 @@ tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_h
   try {
     if (n <= 0 || !R_host || !out) return fail(TLS_ERR_ARG, "bad arguments to tls_precond_import");
     TRY(check_prec(storage, "storage"));
+    if (storage == TLS_BF16X3) return fail(TLS_ERR_ARG, "TLS_BF16X3 is a factor precision, not a storage format");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     const size_t need = tls_precond_import_workspace_size(n);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "import workspace %zu < %zu bytes", ws_bytes, need);
@@ -1251,6 +1282,7 @@ tls_status tls_precond_import(int64_t n, const double *R_host, const double *d_h
     P->Np = ceil_div(n, NB) * NB;
     P->N = P->Np / NB;
     P->storage = storage;
+    P->uq = storage;
     P->requested = storage;
     P->scaled = d_host ? 1 : 0;
     P->tiles = W.tiles;
@@ -1742,14 +1774,15 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
                     "(Ritz values of R^-T A^T A R^-1 in [%.3g, %.3g]; (6) bound %.3g)", R.u_q,
                     R.quality_lo, R.quality_hi, R.bound6);
       const auto tf = clk::now();
-      const int next = (P->storage == TLS_BF16) ? TLS_FP16 : (P->storage == TLS_FP16) ? TLS_FP32 : TLS_FP64;
+      const int next = (P->uq == TLS_BF16) ? TLS_FP16
+                       : (P->uq == TLS_FP16 || P->uq == TLS_BF16X3) ? TLS_FP32 : TLS_FP64;
       FactorWs FW = factor_ws_of(P);
       int bd = 0;
       TRY(gate_finish(P));   // its runs read the factor that is replaced now
       TRY(factor_once(A, P, FW, next, st, &bd, next != TLS_FP64 ? &V : nullptr));
       if (next == TLS_FP64) P->have_kappa = P->have_sigma_n = P->have_quality = 0;
       R.escalations++;
-      R.used = P->storage;
+      R.used = P->uq;
       S.t_factor_ms += ms_since(tf);
       return TLS_OK;
     };

@@ -25,7 +25,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libtls.so")
 
-PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "bf16x3": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
 DENSE, CSR_FMT = 0, 1
 MAX_ITERS = 256
@@ -57,7 +57,7 @@ class c_gate_report(C.Structure):
     _fields_ = [(k, C.c_double) for k in (
         "kappa_est", "kappaF_est", "sigma_n_est", "sigma_1_est", "lam_min_H", "bound5",
         "bound_chol", "bound_wilkinson", "bound_hp", "bound6", "u_q", "ctilde_min",
-        "quality_lo", "quality_hi")] + \
+        "quality_lo", "quality_hi", "cert_margin")] + \
         [(k, C.c_int32) for k in ("requested", "used", "verdict", "escalations",
                                   "chol_retries", "lanczos_steps", "method", "reserved")]
 

@@ -45,7 +45,7 @@ def test_gram_tiles_against_oracle(u_q, shape):
     assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
 
 
-@pytest.mark.parametrize("u_q", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("u_q", ["fp64", "fp32", "fp16", "bf16", "bf16x3"])
 @pytest.mark.parametrize("shape", [(70, 3), (300, 64), (3000, 300), (4097, 129), (9000, 520),
                                    (20000, 200), (40000, 700)])
 def test_gram_elementwise_against_oracle(u_q, shape):
@@ -68,9 +68,20 @@ def test_gram_elementwise_against_oracle(u_q, shape):
     d = d.cpu().numpy()
     d_or = np.linalg.norm(A, axis=0)
     assert np.allclose(d, d_or, rtol=1e-14, atol=0)
-    Ah = A * (1.0 / d_or) if u_q == "fp64" else lowprec.round_to(A * (1.0 / d_or), u_q)
-    H = Ah.T @ Ah
-    W = np.abs(Ah).T @ np.abs(Ah)
+    if u_q == "bf16x3":
+        # the split pair: hi^T hi + hi^T lo + lo^T hi in three BF16 products
+        hi, lo = lowprec.split_bf16(A * (1.0 / d_or))
+        H = lowprec.split_gram(hi, lo)
+        W = lowprec.split_gram(np.abs(hi), np.abs(lo))
+        # and within 3 2^-16 of the Gram matrix of A D^{-1} itself
+        As = A * (1.0 / d_or)
+        Wa = np.abs(As).T @ np.abs(As)
+        iu = np.triu_indices(n)
+        assert np.all(np.abs(G[iu] - (As.T @ As)[iu]) <= (3 * 2.0 ** -16 + 200 * 2.0 ** -24) * Wa[iu])
+    else:
+        Ah = A * (1.0 / d_or) if u_q == "fp64" else lowprec.round_to(A * (1.0 / d_or), u_q)
+        H = Ah.T @ Ah
+        W = np.abs(Ah).T @ np.abs(Ah)
     iu = np.triu_indices(n)
     u = 2.0 ** -53 if u_q == "fp64" else 2.0 ** -24
     k = 4 * np.sqrt(m) if u_q == "fp64" else 100.0
@@ -148,3 +159,48 @@ def test_c3_reflector_fp64_normal_equations():
     scale = np.linalg.norm(A.T @ (A @ x)) + np.linalg.norm(A.T @ b)
     assert np.linalg.norm(res) / scale < 1e-11
     assert abs(s * s - (r @ r) / (1 + x @ x)) / (s * s) < 1e-9
+
+
+@pytest.fixture(scope="module")
+def reflector():
+    import json
+    import os
+    print("reflector 65536 x 4096 (seed 3000): generating", flush=True)
+    A, b, _, _ = tlsgen.reflector_dense(65536, 4096, seed=3000)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "dense_c3_ref.json")) as f:
+        ref = json.load(f)
+    return A, b, ref
+
+
+@pytest.mark.parametrize("u_q", ["fp64", "bf16", "fp16", "bf16x3"])
+def test_c3_reflector_against_oracle(reflector, u_q):
+    """The configured dense workload (its own generator, with the 1e-5
+    perturbation of A) through the paths the benchmark times: FP64, and the
+    BF16, FP16 and split-BF16 factors with FP32 PCGTLS, the gate and the
+    refinement. Against the stored oracle answer (plain float64 RQI-PCGTLS
+    with long-double Newton polish): x and sigma within 1e-10 relative (the
+    attainable float64 accuracy is u kappa_TLS = 1.2e-13 for x and
+    u sigma_1([A,b]) / sigma = 4.8e-11 for sigma, both recorded with the
+    reference); the factor that was used carries the certificate."""
+    tls = _tls()
+    A, b, ref = reflector
+    print(f"c3 reflector {u_q}", flush=True)
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, u_q)
+    if u_q == "fp64":
+        opts = tls.default_opts(stop_patience=2)
+    else:
+        opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=2,
+                                refine_sweeps=1)
+    xs, s, st = tls.tls_rqi_solve(Ad, tls.device_vector(b), P, opts)
+    xr = np.array(ref["x"])
+    ex = np.linalg.norm(xs.cpu().numpy() - xr) / np.linalg.norm(xr)
+    es = abs(s - ref["sigma"]) / ref["sigma"]
+    g = P.info()["gate"]
+    print(f"{u_q}: iters {st['iters']} sigma {es:.2e} x {ex:.2e} used {g['used']} "
+          f"quality [{g['quality_lo']:.4g}, {g['quality_hi']:.4g}]", flush=True)
+    assert ref["bounds"]["attainable_x"] < 1e-11 and ref["bounds"]["attainable_sigma"] < 1e-10
+    assert ex < 1e-10 and es < 1e-10
+    if u_q != "fp64":
+        assert g["used"] == tls.PREC[u_q]
+        assert g["verdict"] & 16 and 0.5 <= g["quality_lo"] and g["quality_hi"] <= 1.5

@@ -247,7 +247,7 @@ def test_factor_matches_cholesky(case, u_q):
 
 
 @pytest.mark.parametrize("case", ["dense", "sparse"])
-@pytest.mark.parametrize("u_q", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("u_q", ["fp32", "fp16", "bf16", "bf16x3"])
 def test_low_precision_factor_and_gate(case, u_q):
     from oracle import constraints
     tls = _tls()
@@ -262,13 +262,15 @@ def test_low_precision_factor_and_gate(case, u_q):
         Af = A.to_dense()
     P, rep = tls.tls_factor_precond(Ad, u_q)
     Rh, d = tls.tls_precond_export(P)
-    u = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[u_q]
+    u = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "bf16x3": 2.0 ** -16}[u_q]
     # the stored factor is a u_q-accurate Cholesky factor of the scaled Gram matrix
     H = (Af / d).T @ (Af / d)
     err = np.linalg.norm(Rh.T @ Rh - H, 2) / np.linalg.norm(H, 2)
     assert err < 30 * u, err
-    # stored values are representable in u_q
-    assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, u_q)))
+    # stored values are representable in the storage format (the split BF16
+    # factor is computed and stored in FP32)
+    store = "fp32" if u_q == "bf16x3" else u_q
+    assert np.array_equal(Rh, np.triu(lowprec.round_to(Rh, store)))
     assert rep["used"] == tls.PREC[u_q]
     # Lanczos estimates against the exact singular values
     ex = constraints.bounds(Af, b, scaled=True)

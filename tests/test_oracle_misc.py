@@ -195,3 +195,33 @@ def test_polish_refines_x():
     x1, sig = polish.polish(A, b, x0)
     assert np.linalg.norm(x1 - sol.x) / np.linalg.norm(sol.x) < 1e-13
     assert abs(sig - sol.sigma) / sol.sigma < 1e-14
+
+
+def test_split_bf16_pair_bounds():
+    # the split pair by its definition: hi is x rounded to bf16 (8
+    # significant bits, unit roundoff 2^-8), lo is the remainder rounded to
+    # bf16, so |x - hi| <= 2^-8 |x| and |x - hi - lo| <= 2^-8 |x - hi| (normal range)
+    g = np.random.default_rng(3)
+    x = g.standard_normal(20000) * 10.0 ** g.uniform(-20, 20, 20000)
+    hi, lo = lowprec.split_bf16(x)
+    assert np.array_equal(hi, lowprec.round_to(x, "bf16"))
+    assert np.array_equal(lo, lowprec.round_to(lo, "bf16"))
+    assert np.all(np.abs(x - hi) <= 2.0 ** -8 * np.abs(x))
+    assert np.all(np.abs(x - hi - lo) <= 2.0 ** -8 * np.abs(x - hi))
+    assert np.all(np.abs(x - hi - lo) <= 2.0 ** -16 * np.abs(x))
+    # a worked case: 1 + 3 2^-9 lies between the bf16 neighbours 1 and
+    # 1 + 2^-7, nearer the upper; the remainder -2^-9 is a bf16 number
+    h1, l1 = lowprec.split_bf16(np.array([1.0 + 3 * 2.0 ** -9]))
+    assert h1[0] == 1.0 + 2.0 ** -7 and l1[0] == -(2.0 ** -9) and h1[0] + l1[0] == 1.0 + 3 * 2.0 ** -9
+
+
+def test_split_gram_drops_only_lo_lo():
+    g = np.random.default_rng(5)
+    A = g.standard_normal((300, 7))
+    hi, lo = lowprec.split_bf16(A)
+    full = (hi + lo).T @ (hi + lo)
+    assert np.allclose(lowprec.split_gram(hi, lo) + lo.T @ lo, full, rtol=0, atol=1e-12 * np.abs(full).max())
+    # and the pair's Gram matrix is within 3 2^-16 (relative to |A|^T |A|) of
+    # A^T A: twice the representation error and the dropped lo^T lo
+    W = np.abs(A).T @ np.abs(A)
+    assert np.all(np.abs(lowprec.split_gram(hi, lo) - A.T @ A) <= 3 * 2.0 ** -16 * W)
