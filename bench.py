@@ -290,9 +290,17 @@ def class_work(cls, cfg, m, n, nnz, launches):
     if cls == "invert":
         return alu, n ** 3 / 3 * launches / 10, "triangular inverse n^3/3 over its launches", None
     dense = nnz == m * n
+    if cls == "residual" and dense:
+        # one pass over the row-major FP64 copy: r = b - A x and A^T r together
+        return "hbm", (8 * m * n + 16 * m) * launches, "dense pass 8mn + 16m B (r and A^T r in one pass)", 8 * m * n
+    if cls == "gradient" and dense:
+        # the sum of the row pass's per-workgroup partial n-vectors
+        groups = -(-m // 64)
+        per_wg = -(-groups // 256)
+        blocks = -(-groups // per_wg)
+        per = 8 * blocks * n + 24 * n
+        return "hbm", per * launches, "row-pass partials 8 n G + 24 n B", per
     if cls in ("residual", "gradient"):
-        if dense:
-            return "hbm", (8 * m * n + 16 * m) * launches, "dense pass 8mn + 16m B", 8 * m * n
         per = 12 * nnz + 4 * (m + 1) + 8 * (m + n)
         return "hbm", per * launches, "CSR/CSC pass 12 nnz + 4(m+1) + 8(m+n) B", per
     if cls == "gram":

@@ -430,15 +430,19 @@ __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld,
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = I * 64 + lane;
   int bad = 0;
-#pragma unroll 4
-  for (int cc = 0; cc < 64; cc += 4) {
-    const int c = cc + w, j = J * 64 + c;
-    double v = 0.0;
-    if (i < m && j < n) v = __builtin_nontemporal_load(A + (size_t)j * ld + i);
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {        // the thread's 16 loads in flight together
+    const int j = J * 64 + 4 * q + w;
+    v[q] = (i < m && j < n) ? __builtin_nontemporal_load(A + (size_t)j * ld + i) : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = 4 * q + w, j = J * 64 + c;
+    const uint64_t u = __builtin_bit_cast(uint64_t, v[q]);
     bad |= ((u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull);
-    tile[c][lane] = v;
-    const double sq = wave_sum(v * v);
+    tile[c][lane] = v[q];
+    const double sq = wave_sum(v[q] * v[q]);
     if (lane == 0 && j < n) colsq[(size_t)I * n + j] = sq;
   }
   if (__any(bad) && lane == 0) atomicOr(flag, 1);
@@ -1334,16 +1338,41 @@ __global__ __launch_bounds__(G16LANES) void k_gram_mfma16x3(int mp, const bf16_t
 }
 
 // G (upper, column-major, FP32) = sum over segments of the partial tiles,
-// added in FP64 in segment order
+// added in FP64 in segment order. Grid (tiles, 4): a workgroup takes a
+// quarter of a tile, a thread four consecutive entries (16-byte loads) in
+// four places, with the segment loads of each group issued before the adds.
 __global__ __launch_bounds__(256) void k_gram_reduce(const float *part, int nseg, int NT, int Np, float *G) {
   const int l = blockIdx.x, ntiles = NT * (NT + 1) / 2;
   int I, J;
   gram_tile_of(l, I, J);
-  for (int e = threadIdx.x; e < GT * GT; e += 256) {
-    double sum = 0.0;
-    for (int k = 0; k < nseg; ++k) sum += (double)part[((size_t)k * ntiles + l) * GT * GT + e];
+  const size_t sstride = (size_t)ntiles * GT * GT;      // floats between segments
+  const float *base = part + (size_t)l * GT * GT;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = blockIdx.y * (GT * GT / 4) + i * 1024 + threadIdx.x * 4;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= nseg; k += 4) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = *(const float4 *)(base + (size_t)(k + u) * sstride + e);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s0 += (double)v[u].x; s1 += (double)v[u].y; s2 += (double)v[u].z; s3 += (double)v[u].w;
+      }
+    }
+    for (; k < nseg; ++k) {
+      const float4 v = *(const float4 *)(base + (size_t)k * sstride + e);
+      s0 += (double)v.x; s1 += (double)v.y; s2 += (double)v.z; s3 += (double)v.w;
+    }
     const int c = J * GT + e / GT, r = I * GT + e % GT;
-    if (r <= c && c < Np) G[(size_t)c * Np + r] = (float)sum;
+    if (c < Np) {
+      float *g = G + (size_t)c * Np + r;
+      if (r + 0 <= c) g[0] = (float)s0;
+      if (r + 1 <= c) g[1] = (float)s1;
+      if (r + 2 <= c) g[2] = (float)s2;
+      if (r + 3 <= c) g[3] = (float)s3;
+    }
   }
 }
 
@@ -1382,7 +1411,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                  (half_t *)cast);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(G16LANES), 0, st, mp, (const half_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
-      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
     case TLS_BF16X3: {
@@ -1390,7 +1419,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       TLS_LAUNCH(PC_GRAM, k_cast_split, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128, hi, lo);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16x3, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)hi, (const bf16_t *)lo,
                  part, NT, gp.seglen, gp.npairs, nseg);
-      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
     }
@@ -1399,7 +1428,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                  (bf16_t *)cast);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
-      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
                  (float *)G);
       break;
   }

@@ -229,26 +229,26 @@ int64_t rowpass_ld(int64_t n) {
 
 template <typename T>
 static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, const double *x, double *r,
-                             double *part_r, double *ppart, hipStream_t st) {
+                             double *part_r, double *ppart, hipStream_t st, int cls) {
   const int cus = rowpass_cus();
   const int groups = rowpass_groups(A.m, cus), blocks = rowpass_blocks(A.m, cus);
   const int nt = (int)(A.ldr >> 6);    // the copy's stride is 64 TT (rowpass_ld)
   const dim3 g(blocks), t(RR_WAVES * 64);
   switch (nt) {
     case 16:
-      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<16, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+      TLS_LAUNCH(cls, (k_resgrad_rows<16, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
                  ppart);
       break;
     case 32:
-      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<32, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+      TLS_LAUNCH(cls, (k_resgrad_rows<32, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
                  ppart);
       break;
     case 48:
-      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<48, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+      TLS_LAUNCH(cls, (k_resgrad_rows<48, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
                  ppart);
       break;
     case 64:
-      TLS_LAUNCH(PC_RESIDUAL, (k_resgrad_rows<64, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+      TLS_LAUNCH(cls, (k_resgrad_rows<64, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
                  ppart);
       break;
     default:
@@ -258,8 +258,9 @@ static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, con
 }
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
                           double *ppart, hipStream_t st, int f32) {
-  if (f32 && A.at32) return rowpass_go<float>(A, A.at32, b, x, r, part_r, ppart, st);
-  return rowpass_go<double>(A, A.at, b, x, r, part_r, ppart, st);
+  // the FP32 passes are the certificate's: profiled with the gate's Lanczos
+  if (f32 && A.at32) return rowpass_go<float>(A, A.at32, b, x, r, part_r, ppart, st, PC_LANCZOS);
+  return rowpass_go<double>(A, A.at, b, x, r, part_r, ppart, st, PC_RESIDUAL);
 }
 
 // y = s * (sum of the row workgroups' partials), in a fixed order

@@ -1137,10 +1137,12 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     // CSC copy and column norms (dense: the row-major copy, its column norms
     // and the finite-input flag in one pass)
     if (W.at) {
-      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.at32, W.colsq, W.d, W.flag,
+      // the FP32 copy serves the certificate of a low-precision factor only
+      float *at32 = (u_q != TLS_FP64) ? W.at32 : nullptr;
+      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, at32, W.colsq, W.d, W.flag,
                                   stream));
       P->at = W.at;
-      P->at32 = W.at32;
+      P->at32 = at32;
       P->ldr = W.ldr;
     } else if (A->format == TLS_CSR) {
       HIPCHK(launch_csc_build((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, A->val, W.col_ptr,
