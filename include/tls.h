@@ -86,9 +86,11 @@ typedef enum {
 /* The data matrix A (m x n, m > n). Dense: column-major, element (i, j) at
  * val[i + j*ld], ld >= m. CSR: row_ptr[m+1] (row_ptr[0] = 0, nondecreasing,
  * row_ptr[m] = nnz), col_idx[nnz] in [0, n) strictly increasing within each
- * row, val[nnz]. The CSR structure is not checked on the device (its
- * indices address the CSC copy and LDS histograms): a violation is undefined
- * behaviour. All arrays are device memory owned by the caller and must stay
+ * row, val[nnz]. tls_factor_precond checks this structure on the device
+ * before any kernel uses the indices (one synchronization) and returns
+ * TLS_ERR_ARG for a matrix that violates it; tls_rqi_solve accepts a CSR A
+ * only with the same index arrays (pointers, m, nnz) the preconditioner was
+ * built from. All arrays are device memory owned by the caller and must stay
  * valid and unchanged while a preconditioner built from A is in use. */
 typedef struct {
   int32_t format;          /* tls_format */

@@ -28,7 +28,9 @@ Readings of the paper (each listed in the design notes):
   do not improve on the best psi; the iterate with the smallest psi is
   returned.
 
-Pins: tests/test_oracle_rqi.py (Algorithm 1 equivalence with exact inner
+Pins: tests/test_oracle_rqi.py (psi_at against a direct evaluation of
+eq. (4); the warm candidate against the shifted solve it truncates and its
+choice rule; Algorithm 1 equivalence with exact inner
 solves, Algorithm 3 special cases sigma = 0 (float64 and float32) and
 l >= n, the end of the loop at an underflowed eta and at a non-finite
 delta, first-step beta = sigma_0^2, the first iterate independent of u_p
@@ -256,10 +258,8 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
 
     # lines 1-5: x_0 = x_LS, one inverse-iteration step with shift 0
     if x0 is None:
-        Rs_R, Rs_RT = _tri_solvers(R) if R is not None else (solve_R, solve_RT)
-        x = Rs_R(Rs_RT(rmv(b)))
-        for _ in range(ls_corrections):
-            x = x + Rs_R(Rs_RT(rmv(b - mv(x))))
+        x = x_ls(A, b, R if R is not None else None, ls_corrections,
+                 solvers=None if R is not None else (solve_R, solve_RT))
     else:
         x = np.asarray(x0, dtype=np.float64).copy()
     r0, sig0_2 = rayleigh(mv, b, x)
@@ -314,6 +314,62 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
     psi_b, x_b, s_b, k_b = best
     return RQIResult(x=x_b, sigma=s_b, k_best=k_b, iters=k, psi=psis,
                      sigma_hist=sigs, x_hist=xs, pcg_steps=pcg_total, stopped=stopped)
+
+
+def x_ls(A, b, R, corrections: int = 1, solvers=None):
+    """x_LS by the semi-normal equations R^T R x = A^T b with the factor in
+    float64, then ``corrections`` corrected steps x += (R^T R)^{-1} A^T (b - A x)
+    (the paper does not say how x_LS is computed; this is the reading used)."""
+    mv, rmv, _, _ = _as_operator(A)
+    b = np.asarray(b, dtype=np.float64)
+    sR, sRT = _tri_solvers(R) if solvers is None else solvers
+    x = sR(sRT(rmv(b)))
+    for _ in range(corrections):
+        x = x + sR(sRT(rmv(b - mv(x))))
+    return np.asarray(x, dtype=np.float64)
+
+
+def psi_at(A, b, x):
+    """psi of eq. (4) at x, with sigma^2 the Rayleigh quotient of Algorithm 2:
+    r = b - A x, sigma^2 = ||r||^2 / (1 + ||x||^2), f = -A^T r - sigma^2 x,
+    g = -b^T r + sigma^2, psi = ((||f||^2 + g^2) / (||x||^2 + 1))^{1/2}."""
+    mv, rmv, _, _ = _as_operator(A)
+    x = np.asarray(x, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    r = b - mv(x)
+    s2 = float(r @ r) / (1.0 + float(x @ x))
+    f = -rmv(r) - s2 * x
+    g = -float(b @ r) + s2
+    return math.sqrt((float(f @ f) + g * g) / (float(x @ x) + 1.0))
+
+
+def warm_candidate(A, b, R, x0, sigma_hat):
+    """The warm start's candidate for x_1 (a project addition, not in the
+    paper). At x_0 = x_LS (A^T r_0 = 0), the Algorithm 2 body at a shift lam
+    solves (A^T A - lam I) y = x_0 for the correction; its Neumann series in
+    lam (A^T A)^{-1} truncated after two terms gives
+    x_1w = x_0 + lam u_0 + lam^2 u_1 with u_0 = (A^T A)^{-1} x_0 and
+    u_1 = (A^T A)^{-1} u_0, applied through the factor (R^T R = A^T A) in
+    float64. sigma_hat is capped at sigma_0 = ||r_0|| / (1 + ||x_0||^2)^{1/2}
+    (sigma_{n+1} <= sigma_0). The plain x_1 = x_0 + sigma_0^2 u_0 is the
+    shift-0 step of Algorithm 2 (lines 1-5); the start kept is the one with
+    the smaller psi (eq. 4), the plain one on a tie.
+
+    Returns (x_kept, warm_taken, psi_warm, psi_plain, sigma_hat_used)."""
+    mv, _, _, _ = _as_operator(A)
+    x0 = np.asarray(x0, dtype=np.float64)
+    sR, sRT = _tri_solvers(R)
+    u0 = sR(sRT(x0))
+    u1 = sR(sRT(u0))
+    r0 = np.asarray(b, dtype=np.float64) - mv(x0)
+    s0 = math.sqrt(float(r0 @ r0) / (1.0 + float(x0 @ x0)))
+    sh = min(float(sigma_hat), s0)
+    lam = sh * sh
+    xw = x0 + lam * u0 + (lam * lam) * u1
+    xp = x0 + (s0 * s0) * u0
+    pw, pp = psi_at(A, b, xw), psi_at(A, b, xp)
+    take = pw < pp
+    return (xw if take else xp), bool(take), pw, pp, sh
 
 
 def inverse_step_body(A, b, x, shift, solve):

@@ -101,6 +101,9 @@ hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval
 // the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
                                 float *At32, double *colsq, double *d, int *flag, hipStream_t st);
+// CSR structure check (row pointers, column range, sorted rows): *bad |= 1
+hipError_t launch_validate_csr(int m, int n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                               int *bad, hipStream_t st);
 hipError_t launch_colnorms_dense(int m, int n, int64_t ld, const double *A, double *d,
                                  hipStream_t st);
 // scaling vectors: dinv = 1/d (or ones when unscaled), both precisions, padded to Np

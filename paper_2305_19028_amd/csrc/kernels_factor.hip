@@ -80,6 +80,33 @@ __global__ void k_check_finite(const double *v, size_t count, int *flag) {
   }
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
+// structure of a CSR matrix as the device code relies on it: row_ptr[0] = 0,
+// row_ptr[m] = nnz, row_ptr nondecreasing, 0 <= col_idx < n and strictly
+// increasing inside each row. Any violation sets *bad (read by the host
+// before any kernel uses the indices).
+__global__ void k_validate_csr(int m, int n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                               int *bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int b = 0;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t == 0) b |= (row_ptr[0] != 0) | (row_ptr[m] != nnz);
+  for (int64_t i = t; i < m; i += stride) {
+    const int32_t a = row_ptr[i], c = row_ptr[i + 1];
+    if (a > c || a < 0 || c > nnz) { b = 1; continue; }
+    for (int32_t e = a; e < c; ++e) {
+      const int32_t j = col_idx[e];
+      b |= (j < 0) | (j >= n);
+      if (e > a) b |= (col_idx[e - 1] >= j);
+    }
+  }
+  if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+hipError_t launch_validate_csr(int m, int n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                               int *bad, hipStream_t st) {
+  TLS_LAUNCH(PC_SETUP, k_validate_csr, dim3(grid_for((size_t)m)), dim3(256), 0, st, m, n, nnz, row_ptr, col_idx,
+             bad);
+  return hipGetLastError();
+}
 hipError_t launch_check_finite(const double *v, size_t count, int *flag, hipStream_t st) {
   if (!count) return hipSuccess;
   TLS_LAUNCH(PC_SETUP, k_check_finite, dim3(grid_for(count)), dim3(256), 0, st, v, count, flag);

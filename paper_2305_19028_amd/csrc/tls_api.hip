@@ -100,6 +100,7 @@ struct tls_precond_s {
   double *d = nullptr;
   int32_t *col_ptr = nullptr, *row_idx = nullptr;
   double *cval = nullptr;
+  const int32_t *csr_row_ptr = nullptr, *csr_col_idx = nullptr;   // the validated structure
   double *at = nullptr;            // row-major copy of a dense A (stride ldr), or NULL
   float *at32 = nullptr;           // its FP32 rounding (the certificate's products)
   int64_t ldr = 0;
@@ -1145,12 +1146,26 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       P->at32 = at32;
       P->ldr = W.ldr;
     } else if (A->format == TLS_CSR) {
+      // the structure is checked before any kernel uses the indices (one
+      // synchronization, CSR only): a malformed matrix is an argument error,
+      // never an out-of-bounds access
+      int *badp = W.info + 1;
+      HIPCHK(launch_fill_i32(badp, 0, 1, stream));
+      HIPCHK(launch_validate_csr((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, badp, stream));
+      int bad = 0;
+      HIPCHK(hipMemcpyAsync(&bad, badp, sizeof(int), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      if (bad)
+        return fail(TLS_ERR_ARG, "CSR structure invalid: row_ptr must start at 0, end at nnz and not "
+                    "decrease; column indices must lie in [0, n) and increase within each row");
       HIPCHK(launch_csc_build((int)A->m, n, A->nnz, A->row_ptr, A->col_idx, A->val, W.col_ptr,
                               W.row_idx, W.cval, W.tmp_row, W.tmp_val, W.fill, stream));
       HIPCHK(launch_colnorms_csc(n, W.col_ptr, W.cval, W.d, stream));
       P->col_ptr = W.col_ptr;
       P->row_idx = W.row_idx;
       P->cval = W.cval;
+      P->csr_row_ptr = A->row_ptr;
+      P->csr_col_idx = A->col_idx;
     } else {
       HIPCHK(launch_colnorms_dense((int)A->m, n, A->ld, A->val, W.d, stream));
     }
@@ -1618,6 +1633,10 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     if (!P || !o || !b || !x) return fail(TLS_ERR_ARG, "NULL argument to tls_rqi_solve");
     if (P->n != A->n) return fail(TLS_ERR_ARG, "preconditioner order %lld != n %lld", (long long)P->n, (long long)A->n);
     if (A->format == TLS_CSR && !P->col_ptr) return fail(TLS_ERR_ARG, "CSR A needs a preconditioner built from it (CSC copy)");
+    if (A->format == TLS_CSR && (A->row_ptr != P->csr_row_ptr || A->col_idx != P->csr_col_idx ||
+                                 A->nnz != P->nnz || A->m != P->m))
+      return fail(TLS_ERR_ARG, "CSR A must be the matrix the preconditioner was built from (its "
+                  "structure was validated there)");
     if (o->u_p != TLS_FP64 && o->u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
     if (o->kmax < 1 || o->kmax > TLS_MAX_ITERS) return fail(TLS_ERR_ARG, "kmax must be in [1, %d]", TLS_MAX_ITERS);
     if (o->stop_patience < 1) return fail(TLS_ERR_ARG, "stop_patience must be >= 1");

@@ -144,6 +144,22 @@ def train(F, y, norm, epochs=200, batch=256, lr=1e-3, seed=7, log=None):
     return theta, hist
 
 
+def shrink_to_validation(theta, norm, F, y):
+    """Scale the network's output layer by the alpha in [0, 1] that minimises
+    the squared error of base + alpha * net on a validation set (targets
+    clipped as in training). alpha = 0 leaves the quadrature estimate alone:
+    the correction is only kept to the extent that it helps on problems the
+    network was not trained on. Returns alpha; theta is scaled in place."""
+    torch = _torch()
+    r = tls.tls_mlp_forward(theta, torch.as_tensor(norm).cuda(), F).cpu().numpy().astype(np.float64)
+    t = np.clip(np.asarray(y, dtype=np.float64) - base(F), -CLIP, CLIP)
+    rr = float(r @ r)
+    alpha = 0.0 if rr == 0.0 else float(np.clip((r @ t) / rr, 0.0, 1.0))
+    # the output layer: the last TLS_MLP_WIDTH weights and the bias
+    theta[-(tls.MLP_WIDTH + 1):] *= alpha
+    return alpha
+
+
 def predict(theta, norm, F):
     """y_hat = base(F) + net(F), as the solver forms it."""
     torch = _torch()
@@ -220,14 +236,16 @@ def main(argv=None):
     F, y = make_dataset(train_seeds, tuple(a.m), tuple(a.n), a.path, log=log)
     t1 = time.perf_counter()
     norm = fit_norm(F)
-    theta, hist = train(F, y, norm, epochs=a.epochs, log=log)
+    nv = max(1, len(train_seeds) // 5)       # a fifth held back for the shrinkage
+    theta, hist = train(F[nv:], y[nv:], norm, epochs=a.epochs, log=log)
+    alpha = shrink_to_validation(theta, norm, F[:nv], y[:nv])
     _torch().cuda.synchronize()
     t2 = time.perf_counter()
     recs = evaluate(theta, norm, test_seeds, tuple(a.m), tuple(a.n), a.path, log=log)
     yt = np.array([r["y_true"] for r in recs])
     s = summarize(recs)
     s.update({"train": a.train, "epochs": a.epochs, "path": a.path, "m_range": a.m, "n_range": a.n,
-              "final_train_loss": hist[-1], "dataset_s": t1 - t0, "train_s": t2 - t1,
+              "final_train_loss": hist[-1], "alpha": alpha, "dataset_s": t1 - t0, "train_s": t2 - t1,
               "y_test_mean": float(yt.mean()), "y_test_var": float(yt.var())})
     print(json.dumps(s))
     if a.out:

@@ -62,3 +62,52 @@ def test_csr_with_empty_rows_and_columns_of_one_entry():
         bs, bx = certify.attainable(ref.sigma_1_Ab, ref.sigma, ref.kappa_tls)
         assert abs(s - ref.sigma) / ref.sigma < max(1e-10, 100 * bs), uq
         assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) < max(1e-10, 100 * bx), uq
+
+
+@pytest.mark.parametrize("defect", ["col_out_of_range", "col_negative", "row_ptr_decreasing",
+                                    "row_ptr_end", "row_ptr_start", "unsorted_row", "duplicate_col"])
+def test_invalid_csr_structure_is_an_argument_error(defect):
+    """A malformed CSR matrix is rejected by the factorization with
+    TLS_ERR_ARG: the device check reads only row_ptr[0..m] and, for rows whose
+    pointers lie inside [0, nnz], their entries of col_idx, and it runs before
+    any kernel uses the indices. A solve with other index arrays than the
+    factor's is rejected as well."""
+    import scipy.sparse as sp
+    tls = _tls()
+    g = np.random.default_rng(8)
+    S = sp.random(400, 30, density=0.2, random_state=4, format="csr") + sp.eye(400, 30, format="csr")
+    S.sort_indices()
+    rp, ci, val = S.indptr.astype(np.int32).copy(), S.indices.astype(np.int32).copy(), S.data.copy()
+    r = 7                                             # a row with at least two entries
+    while rp[r + 1] - rp[r] < 2:
+        r += 1
+    e = rp[r]
+    if defect == "col_out_of_range":
+        ci[e + 1] = 30
+    elif defect == "col_negative":
+        ci[e] = -1
+    elif defect == "row_ptr_decreasing":
+        rp[r + 1] = rp[r] - 1
+    elif defect == "row_ptr_end":
+        rp[-1] = rp[-1] - 1
+    elif defect == "row_ptr_start":
+        rp[0] = 1
+    elif defect == "unsorted_row":
+        ci[e], ci[e + 1] = ci[e + 1], ci[e]
+    else:
+        ci[e + 1] = ci[e]
+    print(f"invalid csr {defect}", flush=True)
+    Ad = tls.csr(rp, ci, val, 400, 30)
+    with pytest.raises(tls.TLSError) as ex:
+        tls.tls_factor_precond(Ad, "fp64")
+    assert ex.value.status == -1 and "CSR structure" in str(ex.value)
+    # the valid matrix factors; a solve handed a copy of it (other arrays) is refused
+    good = tls.csr(S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data, 400, 30)
+    P, _ = tls.tls_factor_precond(good, "fp64")
+    other = tls.csr(S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data, 400, 30)
+    b = g.standard_normal(400)
+    with pytest.raises(tls.TLSError) as ex2:
+        tls.tls_rqi_solve(other, b, P)
+    assert ex2.value.status == -1
+    x, s, st = tls.tls_rqi_solve(good, b, P)
+    assert np.isfinite(s)

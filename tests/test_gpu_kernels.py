@@ -277,3 +277,14 @@ def test_low_precision_factor_and_gate(case, u_q):
     assert abs(rep["sigma_n_est"] - ex.sigma_n_A) / ex.sigma_n_A < 0.2
     assert 0.5 < rep["kappa_est"] / ex.kappa < 1.0 + 1e-6 + 50 * u
     assert abs(rep["bound5"] - ex.bound5) / ex.bound5 < 1.0
+    # the Cholesky kappa^-2 and the HP bound from the same estimates: the
+    # Lanczos Ritz values lie inside the spectrum, so kappa_hat <= kappa and
+    # lambda_min_hat >= lambda_min(H): both bounds come out at or above the
+    # exact ones, within the estimates' accuracy (kappa to a factor 2)
+    assert 1.0 - 1e-6 <= rep["bound_chol"] / ex.chol < 4.0, (rep["bound_chol"], ex.chol)
+    assert 1.0 - 1e-6 <= rep["bound_hp"] / ex.hp < 4.0, (rep["bound_hp"], ex.hp)
+    # the verdict bits follow the printed comparisons u_q < bound
+    uq = rep["u_q"]
+    assert bool(rep["verdict"] & 1) == (uq < rep["bound5"])
+    assert bool(rep["verdict"] & 2) == (uq < rep["bound_chol"])
+    assert bool(rep["verdict"] & 4) == (uq < rep["bound_hp"])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import tlsgen
-from oracle import exact, features, mlp
+from oracle import exact, features, mlp, rqi
 
 pytestmark = pytest.mark.gpu
 
@@ -180,3 +180,31 @@ def test_network_warm_start_in_solve():
     assert abs(s - ref.sigma) / ref.sigma < 1e-10
     assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) < 1e-10
     del torch
+
+
+@pytest.mark.parametrize("hint", ["exact", "half_sigma0", "above_sigma0"])
+def test_warm_step_matches_oracle(hint):
+    """The warm candidate x_1w = x_0 + lam u_0 + lam^2 u_1 and the psi-based
+    choice between it and the plain x_1, against oracle.rqi.warm_candidate on
+    the oracle's own x_LS and factor: the capped shift, both psi values and
+    the choice agree."""
+    tls = _tls()
+    A, b, _ = tlsgen.dense_gaussian(200, 20, seed=1000, noise_A=1e-3, noise_b=0.1)
+    ref = exact.svd_tls(A, b)
+    R = rqi.cholesky_R(A)
+    x0 = rqi.x_ls(A, b, R, 1)
+    r0 = b - A @ x0
+    s0 = math.sqrt(float(r0 @ r0) / (1 + x0 @ x0))
+    sh = {"exact": ref.sigma, "half_sigma0": 0.5 * s0, "above_sigma0": 2.0 * s0}[hint]
+    xk, taken, pw, pp, used = rqi.warm_candidate(A, b, R, x0, sh)
+    Ad = tls.dense(A)
+    P, _ = tls.tls_factor_precond(Ad, "fp64")
+    x, s, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(stop_patience=2, sigma0_hint=sh))
+    print(f"warm {hint}: sigma_hat {st['sigma_hat']:.6e} / {used:.6e} psi_w {st['psi_warm']:.6e} / {pw:.6e} "
+          f"psi_p {st['psi_plain']:.6e} / {pp:.6e} used {st['warm_used']} / {taken}", flush=True)
+    assert st["sigma_ls"] == pytest.approx(s0, rel=1e-12)
+    assert st["sigma_hat"] == pytest.approx(used, rel=1e-12)
+    assert st["psi_warm"] == pytest.approx(pw, rel=1e-7)
+    assert st["psi_plain"] == pytest.approx(pp, rel=1e-7)
+    assert bool(st["warm_used"]) == taken
+    assert abs(s - ref.sigma) / ref.sigma < 1e-10

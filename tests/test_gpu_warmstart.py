@@ -18,8 +18,9 @@ def test_trained_network_gain():
     assert np.all(np.isfinite(F)) and np.all(y <= 0) and np.all(np.isfinite(y))
     norm = ws.fit_norm(F)
     print("warm start: training", flush=True)
-    theta, hist = ws.train(F, y, norm, epochs=150, batch=64, lr=1e-3)
-    assert hist[-1] < 0.5 * hist[0]
+    theta, hist = ws.train(F[56:], y[56:], norm, epochs=150, batch=64, lr=1e-3)
+    assert hist[-1] < 0.75 * hist[0]          # training lowers the loss
+    alpha = ws.shrink_to_validation(theta, norm, F[:56], y[:56])
     print("warm start: held-out evaluation", flush=True)
     test_seeds = range(10 ** 6, 10 ** 6 + 32)
     recs = ws.evaluate(theta, norm, test_seeds, mr, nr, path="fp64")
@@ -32,14 +33,23 @@ def test_trained_network_gain():
     mse_const = float(np.mean((yt[sel] - y.mean()) ** 2))      # best constant from training
     mse_first = float(np.mean((ws.base(Ft) - yt)[sel] ** 2))   # quadrature estimate alone
     s = ws.summarize(recs)
-    s.update({"resolvable": int(sel.sum()), "mse_net": mse_net, "mse_const": mse_const, "mse_quadrature": mse_first})
+    s.update({"resolvable": int(sel.sum()), "mse_net": mse_net, "mse_const": mse_const,
+              "mse_quadrature": mse_first, "alpha": alpha})
     print("warm start summary:", json.dumps(s), flush=True)
-    # the network explains most of the variance of the relative gap, and its
-    # correction does not make the quadrature estimate worse
+    # the estimate explains most of the variance of the relative gap, and the
+    # network's correction (shrunk on held-back training problems) does not
+    # make the quadrature estimate worse on held-out ones
     assert mse_net < 0.5 * mse_const
-    assert mse_net <= 2.0 * mse_first + 0.05
-    # the warm solves return the plain method's answer
+    assert mse_net <= mse_first * (1 + 1e-6) + 1e-4
+    # the warm solves return the plain method's answer ...
     plain_err = max(r["plain"]["err_sigma"] for r in recs)
     warm_err = max(r["warm"]["err_sigma"] for r in recs)
     assert warm_err <= max(1e-10, 10 * plain_err)
     assert s["warm"]["reached_tol"] >= s["plain"]["reached_tol"]
+    # ... and what it changes is measured: the mean first RQI within 1e-10 of
+    # the plain answer and the time to it, warm against plain. On this
+    # distribution the gaps are small and RQI converges from either start in
+    # about as many iterations: the warm start saves no RQIs (at most a
+    # quarter of one more on average is accepted) and costs the features,
+    # the inference and a second psi evaluation
+    assert s["warm"]["mean_k_tol"] <= s["plain"]["mean_k_tol"] + 0.25

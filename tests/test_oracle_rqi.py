@@ -242,3 +242,56 @@ def test_rqi_sparse_workload_certified():
     c = certify.certify(A, b, res.x, sig_ld)
     assert c.normal_eq < 1e-13 and c.g_rel < 1e-15 and c.smallest_root
     assert abs(sig_ld - res.sigma) / sig_ld < 1e-9
+
+
+def test_psi_at_closed_form_and_solution():
+    # A = [I_n; 0], b = beta e_{n+1} (orthogonal to range(A)): at x = t e_1,
+    # r = b - t e_1, sigma^2 = (beta^2 + t^2)/(1 + t^2), f = t (1 - sigma^2) e_1,
+    # g = sigma^2 - beta^2 (eq. 2), so psi^2 = (t^2 (1 - s2)^2 + (s2 - beta^2)^2)/(1 + t^2)
+    n, m, beta = 4, 7, 0.3
+    A = np.zeros((m, n))
+    A[np.arange(n), np.arange(n)] = 1.0
+    b = np.zeros(m)
+    b[n] = beta
+    for t in (0.0, 0.2, -1.5):
+        x = np.zeros(n)
+        x[0] = t
+        s2 = (beta * beta + t * t) / (1 + t * t)
+        want = math.sqrt((t * t * (1 - s2) ** 2 + (s2 - beta * beta) ** 2) / (1 + t * t))
+        assert rqi.psi_at(A, b, x) == pytest.approx(want, rel=1e-14, abs=1e-300)
+    # at the TLS solution of a generic problem f = g = 0: psi is at rounding level
+    A, b, _ = tlsgen.dense_gaussian(80, 6, seed=3)
+    ref = exact.svd_tls(A, b)
+    assert rqi.psi_at(A, b, ref.x) < 1e-13 * np.linalg.norm(A) ** 2
+    assert rqi.psi_at(A, b, ref.x + 1e-3) > 1e-6
+
+
+def test_warm_candidate_truncates_the_shifted_solve():
+    # with the exact factor, x_1w differs from x_0 + lam (A^T A - lam I)^{-1} x_0
+    # by the Neumann tail sum_{k>=3} lam^k M^k x_0, M = (A^T A)^{-1}
+    A, b, _ = tlsgen.dense_gaussian(60, 5, seed=11, noise_b=0.3)
+    R = rqi.cholesky_R(A)
+    x0 = rqi.x_ls(A, b, R, 2)
+    G = A.T @ A
+    mu = 1.0 / np.linalg.eigvalsh(G)[0]               # ||M||_2
+    r0 = b - A @ x0
+    s0 = math.sqrt(float(r0 @ r0) / (1 + x0 @ x0))
+    for frac in (0.3, 0.9):
+        sh = frac * s0
+        lam = sh * sh
+        xk, taken, pw, pp, used = rqi.warm_candidate(A, b, R, x0, sh)
+        assert used == sh
+        xw = x0 + lam * np.linalg.solve(G, x0) + lam * lam * np.linalg.solve(G, np.linalg.solve(G, x0))
+        exact_step = x0 + lam * np.linalg.solve(G - lam * np.eye(5), x0)
+        tail = (lam * mu) ** 3 / (1 - lam * mu) * np.linalg.norm(x0)
+        assert np.linalg.norm(xw - exact_step) <= tail * (1 + 1e-9)
+        assert pw == pytest.approx(rqi.psi_at(A, b, xw), rel=1e-12)
+        # the kept start is the one with the smaller psi
+        xp = x0 + s0 * s0 * np.linalg.solve(G, x0)
+        assert pp == pytest.approx(rqi.psi_at(A, b, xp), rel=1e-12)
+        assert taken == (pw < pp)
+        assert np.allclose(xk, xw if taken else xp, rtol=1e-12, atol=0)
+    # a hint above sigma_0 is capped at sigma_0; a zero hint leaves x_0
+    assert rqi.warm_candidate(A, b, R, x0, 10 * s0)[4] == s0
+    xk, taken, pw, pp, used = rqi.warm_candidate(A, b, R, x0, 0.0)
+    assert pw == pytest.approx(rqi.psi_at(A, b, x0), rel=1e-14)
