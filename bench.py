@@ -315,16 +315,26 @@ def class_work(cls, cfg, m, n, nnz, launches):
 # kernels (name in the profiler's records, source file) behind each class,
 # and the committed PMC summary that holds their HBM bytes
 CLASS_KERNELS = {
-    "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
-             "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
-             "residual": ("tls::k_residual_dense", "kernels_rqi"),
-             "gradient": ("void tls::k_gradient<false>", "kernels_rqi"),
-             "gram": ("void tls::k_gram_mfma<double, double>", "kernels_factor")},
-    "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
-              "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
-              "residual": ("tls::k_residual_dense", "kernels_rqi"),
-              "gradient": ("void tls::k_gradient<false>", "kernels_rqi"),
-              "gram": ("void tls::k_gram_mfma16<tls::bf16_t>", "kernels_factor")},
+    "dense": {
+        "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
+                 "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
+                 "residual": ("void tls::k_resgrad_rows<64, double>", "kernels_rqi"),
+                 "gradient": ("tls::k_gradient_rows", "kernels_rqi"),
+                 "gram": ("void tls::k_gram_mfma<double, double>", "kernels_factor")},
+        "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
+                  "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
+                  "residual": ("void tls::k_resgrad_rows<64, double>", "kernels_rqi"),
+                  "gradient": ("tls::k_gradient_rows", "kernels_rqi"),
+                  "gram": ("void tls::k_gram_mfma16<tls::bf16_t>", "kernels_factor")}},
+    "sparse": {
+        "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
+                 "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
+                 "residual": ("tls::k_residual_csr", "kernels_rqi"),
+                 "gradient": ("tls::k_rmatvec_csc", "kernels_rqi")},
+        "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
+                  "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
+                  "residual": ("tls::k_residual_csr", "kernels_rqi"),
+                  "gradient": ("tls::k_rmatvec_csc", "kernels_rqi")}},
 }
 TRAFFIC_FILES = {"sparse_20000x2000": "sparse_20000x2000_hbm_traffic.md",
                  "dense_65536x4096": "dense_65536x4096_hbm_traffic.md"}
@@ -334,7 +344,8 @@ def measured_traffic(workload, cls, path):
     """HBM bytes per launch (read + written) from the committed PMC summary,
     or None when the kernel's source changed since the counters were taken."""
     import hashlib
-    ent = CLASS_KERNELS.get(path, {}).get(cls)
+    fmt = "sparse" if workload.startswith("sparse") else "dense"
+    ent = CLASS_KERNELS[fmt].get(path, {}).get(cls)
     fname = TRAFFIC_FILES.get(workload)
     if ent is None or fname is None:
         return None

@@ -131,8 +131,9 @@ typedef struct {
   double quality_hi;       /* a-posteriori certificate (products with A in FP64
                               arithmetic, on an FP32 copy of a dense A)          */
   double cert_margin;      /* the window [1/2, 3/2] is narrowed by this much on
-                              each side: the bound on what the FP32 copy of A
-                              can move the Ritz values (0 for FP64 products)   */
+                              each side: 0.05 for the Ritz values lying inside
+                              the spectrum, plus the bound on what the FP32
+                              copy of a dense A can move them                  */
   int32_t requested;       /* tls_prec asked for                                 */
   int32_t used;            /* tls_prec actually used (after escalation)          */
   int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,

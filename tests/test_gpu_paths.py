@@ -5,6 +5,7 @@ import json
 import os
 
 import numpy as np
+import scipy.linalg as sla
 import pytest
 
 import tlsgen
@@ -295,3 +296,64 @@ def test_lookahead_changes_no_result(uq, up):
         print(f"{uq} strict_pd={strict}: iters {k} k_best {st['k_best']} pcg {st['pcg_steps']} "
               f"sigma {sigma:.17g}", flush=True)
     assert outs[0] == outs[1]
+
+
+_CERT_CACHE = {}
+
+
+def _cert_problem(workload):
+    if workload not in _CERT_CACHE:
+        _CERT_CACHE.clear()
+        if workload.startswith("sparse"):
+            A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+            S = A.to_scipy()
+            G = (S.T @ S).toarray()
+        else:
+            A, b, _, _ = tlsgen.reflector_dense(65536, 4096, seed=3000)
+            G = A.T @ A
+        _CERT_CACHE[workload] = (A, b, G)
+    return _CERT_CACHE[workload]
+
+
+def _exact_cert_spectrum(G, Rh, d):
+    # M = R^{-T} A^T A R^{-1} with R = R_hat D: the certificate's operator,
+    # its extreme eigenvalues from the FP64 Gram matrix of the scaled A
+    H = G / np.outer(d, d)
+    Y = sla.solve_triangular(Rh, H, trans="T", lower=False)
+    M = sla.solve_triangular(Rh, Y.T, trans="T", lower=False)
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    return float(ev[0]), float(ev[-1])
+
+
+@pytest.mark.parametrize("u_q", ["fp16", "bf16", "bf16x3"])
+@pytest.mark.parametrize("workload", ["sparse_20000x2000", "dense_65536x4096"])
+def test_certificate_against_exact_spectrum(workload, u_q):
+    """The factor certificate (six Lanczos steps on R^{-T} A^T A R^{-1}) on the
+    benchmark workloads' low-precision factors, against the exact extreme
+    eigenvalues of that operator (dense eigenvalues on the host): the Ritz
+    interval lies inside the spectrum up to the stated margin, and the
+    certificate accepts only factors whose exact spectrum lies in [1/2, 3/2]."""
+    tls = _tls()
+    print(f"certificate {workload} {u_q}", flush=True)
+    A, b, G = _cert_problem(workload)
+    Ad = tls.from_tlsgen(A)
+    P, rep = tls.tls_factor_precond(Ad, u_q)
+    # the solve fills in the b-dependent bits and the verdict
+    opts = tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=0, stop_patience=2)
+    try:
+        tls.tls_rqi_solve(Ad, tls.device_vector(b), P, opts)
+    except tls.TLSError as e:
+        assert e.status == -4            # TLS_ERR_PRECISION: the certificate refused the factor
+    g = P.info()["gate"]
+    Rh, d = tls.tls_precond_export(P)
+    lo, hi = _exact_cert_spectrum(G, Rh, d)
+    mg = g["cert_margin"]
+    print(f"{workload} {u_q}: Ritz [{g['quality_lo']:.6f}, {g['quality_hi']:.6f}] exact [{lo:.6f}, {hi:.6f}] "
+          f"margin {mg:.2e} verdict {g['verdict']}", flush=True)
+    # Ritz values of the operator lie inside its spectrum (up to the rounding
+    # of the FP32 copy the products used, bounded by the margin), and within
+    # the Ritz allowance (0.05) of its extremes
+    assert lo - mg - 1e-6 <= g["quality_lo"] and g["quality_hi"] <= hi + mg + 1e-6
+    assert g["quality_lo"] - lo <= 0.05 and hi - g["quality_hi"] <= 0.05
+    if g["verdict"] & 16:
+        assert 0.5 <= lo and hi <= 1.5, (lo, hi)

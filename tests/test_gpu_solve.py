@@ -78,8 +78,8 @@ def test_rqi_fp64_iterates_match_oracle(case):
     sigma_k and psi_k come from r = b - A x, whose float64 rounding error is
     about u (||b|| + ||A||_F ||x||) (the Rayleigh quotient's attainable
     accuracy, u sigma_1 / sigma): sigma_k agrees to 30 times that relative
-    to ||r_k|| (and to 1e-12 at least), psi_k to 1e-6 relative while it is
-    above 100 times its own rounding level u ||A||_F (||b|| + ||A||_F ||x||)."""
+    to ||r_k|| (and to 1e-12 at least), psi_k to 1e-6 relative or ten times
+    its own rounding level u ||A||_F (||b|| + ||A||_F ||x||)."""
     import torch
     tls = _tls()
     A, b = _iterate_cases()[case]()
@@ -107,8 +107,7 @@ def test_rqi_fp64_iterates_match_oracle(case):
               f"{o.psi[k]:.3e} (floor {psi_floor:.1e})", flush=True)
         assert dx <= 1e-11, (k, dx)
         assert ds <= tol_s, (k, ds, tol_s)
-        if o.psi[k] > 100 * psi_floor:
-            assert abs(st["psi"][k] - o.psi[k]) <= 1e-6 * o.psi[k], (k, st["psi"][k], o.psi[k])
+        assert abs(st["psi"][k] - o.psi[k]) <= max(1e-6 * o.psi[k], 10 * psi_floor), (k, st["psi"][k], o.psi[k])
     assert kk >= 2
 
 
