@@ -163,7 +163,8 @@ typedef struct {
   int32_t kmax;            /* maximum RQI iterations, 1..TLS_MAX_ITERS            */
   int32_t stop_patience;   /* psi rule (eq. 4): stop after this many iterations
                               without a new smallest psi; 1 = stop at the first
-                              increase, as printed                                  */
+                              increase, as printed. The loop also ends when psi
+                              is 0 or exactly repeats the previous psi          */
   int32_t stop_ge;         /* 1: psi_{k+1} >= psi_k also counts (Example 2)      */
   int32_t ls_corrections;  /* corrections of x_LS by semi-normal equations        */
   int32_t strict_pd;       /* 1: delta_j <= 0 in PCGTLS is an error              */
@@ -183,6 +184,13 @@ typedef struct {
   double shift_clamp_tau;  /* tau of the clamp (0 < tau < 1)                       */
   double sigma0_hint;      /* warm start from a given shift estimate sigma_hat
                               (<= 0: none; ignored when mlp_theta is set)         */
+  double psi_tie;          /* the returned iterate is the latest x_k whose psi_k
+                              is within this factor (>= 1; default 4) of the
+                              smallest psi seen up to k: psi values that close
+                              sit at the rounding floor of eq. (4), where psi no
+                              longer tells iterates apart but RQI's iterates
+                              still converge. 1 = the last one that attained the
+                              minimum. A value below 1 is TLS_ERR_ARG.            */
   double *x_snapshots;     /* device, optional (kmax * n): x_k at each psi_k       */
   const float *mlp_theta;  /* device, optional: warm-start network parameters
                               (TLS_MLP_PARAMS floats); NULL = plain LS start      */

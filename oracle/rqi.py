@@ -25,8 +25,14 @@ Readings of the paper (each listed in the design notes):
   factor, independent of u_p.
 * termination (eq. 4): stop when psi_{k+1} > psi_k (``stop_ge`` uses >= as
   in Example 2); ``patience`` p stops after p consecutive iterations that
-  do not improve on the best psi; the iterate with the smallest psi is
-  returned.
+  do not improve on the smallest psi; the loop also ends when psi is 0 or
+  exactly repeats the previous psi (the iterate no longer moves).
+* the returned iterate (the paper does not say which): the latest x_k
+  whose psi_k is within a factor ``psi_tie`` (4) of the smallest psi seen
+  up to k. psi values that close are at the rounding floor of eq. (4),
+  where psi stops telling iterates apart while RQI's iterates still
+  converge; a real divergence raises psi by more. psi_tie = 1 returns the
+  last iterate that attained the minimum.
 
 Pins: tests/test_oracle_rqi.py (psi_at against a direct evaluation of
 eq. (4); the warm candidate against the shifted solve it truncates and its
@@ -208,7 +214,7 @@ def csne_ls(A, b, R, corrections: int = 1) -> np.ndarray:
 
 @dataclasses.dataclass
 class RQIResult:
-    x: np.ndarray             # iterate with the smallest psi
+    x: np.ndarray             # the returned iterate (latest within psi_tie of the smallest psi)
     sigma: float              # its Rayleigh quotient sqrt
     k_best: int
     iters: int                # RQI iterations performed (k of the last psi)
@@ -216,7 +222,7 @@ class RQIResult:
     sigma_hist: list          # sigma_k, k = 1..iters
     x_hist: list              # x_k, k = 1..iters (x_k that gave psi_k)
     pcg_steps: int
-    stopped: str              # "psi", "kmax", "converged"
+    stopped: str              # "psi", "kmax", "converged" (psi 0 or repeated)
 
 
 def rayleigh(A_mv, b, x):
@@ -228,7 +234,7 @@ def rayleigh(A_mv, b, x):
 def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
                stop_ge: bool = False, prec_p=np.float64, steps_rule=None,
                ls_corrections: int = 1, shift_clamp: float | None = None,
-               solvers=None, record: bool = True) -> RQIResult:
+               solvers=None, record: bool = True, psi_tie: float = 4.0) -> RQIResult:
     """RQI-PCGTLS (Algorithm 2 with Algorithm 3 inner solves).
 
     The working precision u is float64 throughout; ``prec_p`` is the
@@ -240,7 +246,10 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
     ``steps_rule(k)`` gives l for the k-th RQI (default l = k: k+1 steps).
     ``shift_clamp``: if given (a value mu_max), the shift used in the k-th
     iteration is min(sigma_k^2, mu_max) (a deviation for starts that violate
-    the positive definiteness assumption; off by default)."""
+    the positive definiteness assumption; off by default).
+    ``psi_tie`` (>= 1): which iterate is returned (see the module notes)."""
+    if not psi_tie >= 1.0:
+        raise ValueError("psi_tie must be >= 1")
     mv, rmv, m, n = _as_operator(A)
     b = np.asarray(b, dtype=np.float64)
     if R is None and solvers is None:
@@ -273,6 +282,7 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
     x = x + sig0_2 * u0
     pcg_total = 2
     best = (math.inf, None, None, 0)
+    psi_min = math.inf
     psis, sigs, xs = [], [], []
     no_improve = 0
     stopped = "kmax"
@@ -292,13 +302,14 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
         sigs.append(math.sqrt(sig2))
         if record:
             xs.append(x.copy())
-        prev_best = best[0]
-        if psi < prev_best:
+        if k == 1 or psi <= psi_tie * psi_min:      # the latest iterate within the band
             best = (psi, x.copy(), math.sqrt(sig2), k)
+        if psi < psi_min:
+            psi_min = psi
             no_improve = 0
-        elif (psi >= prev_best) if stop_ge else (psi > prev_best):
+        elif (psi >= psi_min) if stop_ge else (psi > psi_min):
             no_improve += 1
-        if psi == 0.0:
+        if psi == 0.0 or (k > 1 and psi == psis[-2]):
             stopped = "converged"
             break
         if no_improve >= patience:

@@ -205,7 +205,7 @@ struct OuterScalars;   // device struct, see kernels_rqi.hip
 hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_r, double *scal,
                            double clamp_max, hipStream_t st);
 hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
-                            double *scal, int k, double *rec, double *rhs, double *xbest,
+                            double *scal, int k, double *rec, double *rhs, double *xbest, double tie,
                             hipStream_t st);
 hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st);
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,

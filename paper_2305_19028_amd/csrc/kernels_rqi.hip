@@ -514,11 +514,13 @@ hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_
   return hipGetLastError();
 }
 
-// psi_k from the gradient partials; best-psi bookkeeping; record (sigma, psi, mu)
+// psi_k from the gradient partials; record (sigma, psi, mu); the returned
+// iterate: x_k is kept (copied to xbest) when psi_k is within the factor tie
+// of the smallest psi before it (k = 1 always); slot S_BEST holds that minimum
 __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, int nb_f,
                                                    double *scal, int k, double *rec,
                                                    const double *x, const double *f, double *rhs,
-                                                   double *xbest) {
+                                                   double *xbest, double tie) {
   __shared__ double sc[8];
   __shared__ int s_best;
   const double ff = sum_pairs(part_f, nb_f, 0, sc);
@@ -530,12 +532,12 @@ __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, 
     const double gs = -br + sig2;
     const double psi = sqrt((ffs + gs * gs) / (xx + 1.0));
     const double best = scal[S_BEST];
-    const int isbest = (k == 1) || (psi < best);
+    const int isbest = (k == 1) || (psi <= tie * best);
     scal[S_FF] = ff;
     scal[S_FX] = fx;
     scal[S_PSI] = psi;
     scal[S_ISBEST] = isbest ? 1.0 : 0.0;
-    if (isbest) scal[S_BEST] = psi;
+    if (k == 1 || psi < best) scal[S_BEST] = psi;
     scal[S_K] = (double)k;
     rec[4 * (k - 1) + 0] = sig2;
     rec[4 * (k - 1) + 1] = psi;
@@ -553,10 +555,10 @@ __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, 
   }
 }
 hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
-                            double *scal, int k, double *rec, double *rhs, double *xbest,
+                            double *scal, int k, double *rec, double *rhs, double *xbest, double tie,
                             hipStream_t st) {
   TLS_LAUNCH(PC_SCALARS, k_outer_psi, dim3(1), dim3(256), 0, st, n, part_f, nb_f, scal, k, rec, x, f,
-             rhs, xbest);
+             rhs, xbest, tie);
   return hipGetLastError();
 }
 

@@ -546,6 +546,7 @@ void tls_default_opts(tls_rqi_opts *o) {
   o->gate_enforce = 0;
   o->shift_clamp_tau = 0.9;
   o->sigma0_hint = -1.0;
+  o->psi_tie = 4.0;
   o->x_snapshots = nullptr;
   o->features = 0;
   o->mlp_theta = nullptr;
@@ -1645,6 +1646,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     if (o->u_p != TLS_FP64 && o->u_p != TLS_FP32) return fail(TLS_ERR_ARG, "u_p must be FP64 or FP32");
     if (o->kmax < 1 || o->kmax > TLS_MAX_ITERS) return fail(TLS_ERR_ARG, "kmax must be in [1, %d]", TLS_MAX_ITERS);
     if (o->stop_patience < 1) return fail(TLS_ERR_ARG, "stop_patience must be >= 1");
+    if (!(o->psi_tie >= 1.0) || !std::isfinite(o->psi_tie)) return fail(TLS_ERR_ARG, "psi_tie must be a finite value >= 1");
     if (o->refine_sweeps < 0 || o->refine_sweeps > 4) return fail(TLS_ERR_ARG, "refine_sweeps must be in [0, 4]");
     if (o->refine_sweeps > 0 && o->refine_pcg_steps < 1) return fail(TLS_ERR_ARG, "refine_pcg_steps must be >= 1");
     if (o->mlp_theta && !o->mlp_norm) return fail(TLS_ERR_ARG, "mlp_theta needs mlp_norm");
@@ -1692,7 +1694,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
         HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
       }
-      HIPCHK(launch_outer_psi(n, xv, W.f, part_f, nb_f, W.scal, k, W.rec, W.rhs, W.xbest, st));
+      HIPCHK(launch_outer_psi(n, xv, W.f, part_f, nb_f, W.scal, k, W.rec, W.rhs, W.xbest, o->psi_tie, st));
       return TLS_OK;
     };
     // out = A^T (b - A xv) (xv NULL: A^T b), with r = b - A xv and its
@@ -1959,9 +1961,11 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         }
         if (h[1] != h[0]) S.clamped++;
         if (!std::isfinite(psi)) return fail(TLS_ERR_NO_CONVERGENCE, "psi became non-finite at k = %d", k);
-        if (psi < best) {          // the psi kernel has copied x to xbest
+        // the psi kernel has copied x to xbest when psi is within psi_tie of
+        // the smallest psi before it (best): the latest such iterate is returned
+        if (k == 1 || psi <= o->psi_tie * best) S.k_best = k;
+        if (psi < best) {
           best = psi;
-          S.k_best = k;
           no_improve = 0;
         } else if (o->stop_ge ? (psi >= best) : (psi > best)) {
           ++no_improve;
@@ -2030,13 +2034,13 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         }
         HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
         S.refine_steps++;
-        // keep the refined iterate only if psi improves
+        // keep the refined iterate under the same rule as the loop's (the psi
+        // kernel has already copied it to xbest when it qualifies)
         TRY(evaluate(kmax + 1 + sw, cap));
         HIPCHK(hipMemcpyAsync(h, W.scal, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (h[7] < best) {
-          best = h[7];
-          HIPCHK(launch_copy_f64(W.xbest, x, (size_t)n, st));
+        if (h[7] <= o->psi_tie * best) {
+          best = std::min(best, h[7]);
         } else {
           HIPCHK(launch_copy_f64(x, W.xbest, (size_t)n, st));
           break;

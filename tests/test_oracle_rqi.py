@@ -295,3 +295,25 @@ def test_warm_candidate_truncates_the_shifted_solve():
     assert rqi.warm_candidate(A, b, R, x0, 10 * s0)[4] == s0
     xk, taken, pw, pp, used = rqi.warm_candidate(A, b, R, x0, 0.0)
     assert pw == pytest.approx(rqi.psi_at(A, b, x0), rel=1e-14)
+
+
+@pytest.mark.parametrize("tie", [1.0, 4.0])
+def test_returned_iterate_rule(tie):
+    """The returned iterate is the latest x_k with psi_k within the factor
+    psi_tie of the smallest psi before it (k = 1 always); with a patience of
+    3 on a paper fixture the run goes past the float64 floor, where several
+    iterates qualify, and every one of them is a converged iterate: the
+    returned x matches the SVD solution to the attainable accuracy."""
+    A, b = tlsgen.paper_random()[:2]
+    ref = exact.svd_tls(A, b)
+    o = rqi.rqi_pcgtls(A, b, patience=3, kmax=30, psi_tie=tie)
+    psi = o.psi
+    kept = [k for k in range(1, o.iters + 1) if k == 1 or psi[k - 1] <= tie * min(psi[: k - 1])]
+    assert o.k_best == kept[-1]
+    assert np.array_equal(o.x, o.x_hist[o.k_best - 1])
+    # never before the last iterate that attained the minimum
+    assert o.k_best >= max(k for k in range(1, o.iters + 1) if psi[k - 1] == min(psi))
+    bs, bx = certify.attainable(ref.sigma_1_Ab, ref.sigma, ref.kappa_tls)
+    assert np.linalg.norm(o.x - ref.x) / np.linalg.norm(ref.x) < max(1e-12, 100 * bx)
+    with pytest.raises(ValueError):
+        rqi.rqi_pcgtls(A, b, psi_tie=0.5)
