@@ -128,12 +128,12 @@ typedef struct {
   double u_q;              /* unit roundoff of the precision finally used        */
   double ctilde_min;       /* lambda_min estimate of C = I - s0^2 R^{-T}R^{-1}   */
   double quality_lo;       /* extreme Ritz values of R^{-T} A^T A R^{-1}: the    */
-  double quality_hi;       /* a-posteriori certificate (products with A in FP64
-                              arithmetic, on an FP32 copy of a dense A)          */
+  double quality_hi;       /* a-posteriori certificate (six Lanczos steps,
+                              products with A and R in FP64; for a dense A the
+                              products ride on tls_rqi_solve's passes over A) */
   double cert_margin;      /* the window [1/2, 3/2] is narrowed by this much on
-                              each side: 0.05 for the Ritz values lying inside
-                              the spectrum, plus the bound on what the FP32
-                              copy of a dense A can move them                  */
+                              each side (0.05): Ritz values lie inside the
+                              spectrum they estimate                           */
   int32_t requested;       /* tls_prec asked for                                 */
   int32_t used;            /* tls_prec actually used (after escalation)          */
   int32_t verdict;         /* bit 0: (5) holds, 1: kappa^-2 holds, 2: HP holds,

@@ -100,7 +100,7 @@ hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval
 // row-major copy At (stride ldr) of a dense column-major A, column norms d and
 // the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                float *At32, double *colsq, double *d, int *flag, hipStream_t st);
+                                double *colsq, double *d, int *flag, hipStream_t st);
 // CSR structure check (row pointers, column range, sorted rows): *bad |= 1
 hipError_t launch_validate_csr(int m, int n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                                int *bad, hipStream_t st);
@@ -163,7 +163,6 @@ struct MatView {
   // row-major copy of a dense A (row stride ldr, a multiple of 64, zero
   // padded), made by the factorization; nullptr when absent
   const double *at;
-  const float *at32;   // its FP32 rounding (the certificate's products), or nullptr
   int64_t ldr;
 };
 
@@ -185,7 +184,11 @@ int rowpass_partials(const MatView &A);
 // row stride of the copy the row pass reads (1024, 2048, 3072 or 4096 columns)
 int64_t rowpass_ld(int64_t n);
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                          double *ppart, hipStream_t st, int f32 = 0);
+                          double *ppart, hipStream_t st);
+// the same pass with the products of a second vector v2: ppart2 receives
+// the partials of +A^T A v2 (summed by launch_rowpass_sum with s = 1)
+hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *x, double *r, double *part_r,
+                               double *ppart, const double *v2, double *ppart2, hipStream_t st);
 // y = s * sum of the partial n-vectors
 hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st);
 // f = -A^T r - mu x from the partials (gradient_rows_blocks(n) partial pairs)

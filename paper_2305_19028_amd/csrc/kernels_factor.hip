@@ -451,7 +451,7 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
 // a 64 x 64 tile per workgroup is read column by column (512-byte loads),
 // transposed through LDS and written row by row
 __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr,
-                                                       double *At, float *At32, double *colsq, int *flag) {
+                                                       double *At, double *colsq, int *flag) {
   __shared__ double tile[64][65];
   const int I = blockIdx.x, J = blockIdx.y;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -482,7 +482,6 @@ __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld,
     if (r < m) {
       const double v = (j < n) ? tile[lane][rr + w] : 0.0;
       At[(size_t)r * ldr + j] = v;
-      if (At32) At32[(size_t)r * ldr + j] = (float)v;
     }
   }
 }
@@ -500,10 +499,10 @@ __global__ void k_colnorms_parts(int n, int nblk, const double *colsq, double *d
   d[j] = sqrt((c[0] + c[1]) + (c[2] + c[3]));
 }
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                float *At32, double *colsq, double *d, int *flag, hipStream_t st) {
+                                double *colsq, double *d, int *flag, hipStream_t st) {
   const int nblk = (m + 63) / 64;
   TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(nblk, (unsigned)(ldr / 64)), dim3(256), 0, st, m, n, ld, A, ldr, At,
-             At32, colsq, flag);
+             colsq, flag);
   TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nblk, colsq, d);
   return hipGetLastError();
 }

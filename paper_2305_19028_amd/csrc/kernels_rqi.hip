@@ -119,29 +119,39 @@ __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_
 constexpr int RR_WAVES = 4, RR_MAXG = 64, RR_RPW = 64 / RR_WAVES;
 
 typedef double rp_d2 __attribute__((ext_vector_type(2)));
-typedef float rp_f4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = rp_d2; static constexpr int N = 2; };
-template <> struct Vec16<float> { using type = rp_f4; static constexpr int N = 4; };
 template <typename V> __device__ inline double vget(const V &v, int k) { return (double)v[k]; }
 
 // TT: columns per lane (the row stride ldr is 64 TT, padded with zeros).
 // Lane l reads 16 bytes at a time: columns 64 VN s + VN l + v (v < VN) of
 // load s, so that one load instruction of a wave moves 1 KB of the row.
-template <int TT, typename T>
+// DUAL: the same pass also forms A^T A v for a second vector v (a Lanczos
+// step of the factor's certificate rides on the outer step's read of A):
+// t_i = a_i . v beside r_i, and a_i t_i summed into a second partial
+// n-vector per workgroup (ppart2), joined in the same fixed order.
+template <int TT, typename T, bool DUAL>
 __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, int64_t ldr, const T *At,
                                                                 const double *b, const double *x, double *r,
-                                                                double *part_r, int groups, double *ppart) {
+                                                                double *part_r, int groups, double *ppart,
+                                                                const double *v2, double *ppart2) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::N, NS = TT / VN;       // elements per load, loads per row
-  __shared__ double sx[TT * 64], sp[TT * 64];
+  __shared__ double sx[TT * 64], sp[TT * 64], sv[DUAL ? TT * 64 : 1];
   __shared__ double srr[RR_WAVES][RR_MAXG], sbr[RR_WAVES][RR_MAXG];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int j = threadIdx.x; j < TT * 64; j += RR_WAVES * 64) sx[j] = (x && j < n) ? x[j] : 0.0;
+  for (int j = threadIdx.x; j < TT * 64; j += RR_WAVES * 64) {
+    sx[j] = (x && j < n) ? x[j] : 0.0;
+    if (DUAL) sv[j] = j < n ? v2[j] : 0.0;
+  }
   __syncthreads();
-  double pr[TT];
+  double pr[TT], pq[DUAL ? TT : 1];
 #pragma unroll
   for (int t = 0; t < TT; ++t) pr[t] = 0.0;
+  if (DUAL) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) pq[t] = 0.0;
+  }
   const int g0 = blockIdx.x * groups;
   for (int q = 0; q < groups; ++q) {
     double rr = 0.0, br = 0.0;
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
       V a[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) a[s] = __builtin_nontemporal_load(row + 64 * s);
-      double dot = 0.0;
+      double dot = 0.0, dot2 = 0.0;
       if (x) {
         double c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -160,6 +170,14 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
 #pragma unroll
           for (int v = 0; v < VN; ++v) c[(s * VN + v) & 3] += vget(a[s], v) * sx[64 * VN * s + VN * lane + v];
         dot = wave_sum((c[0] + c[1]) + (c[2] + c[3]));
+      }
+      if (DUAL) {
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int v = 0; v < VN; ++v) c[(s * VN + v) & 3] += vget(a[s], v) * sv[64 * VN * s + VN * lane + v];
+        dot2 = wave_sum((c[0] + c[1]) + (c[2] + c[3]));
       }
       const double bi = b ? b[i] : 0.0;
       const double ri = bi - dot;
@@ -170,24 +188,34 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
       for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int v = 0; v < VN; ++v) pr[s * VN + v] += vget(a[s], v) * ri;
+      if (DUAL) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int v = 0; v < VN; ++v) pq[s * VN + v] += vget(a[s], v) * dot2;
+      }
     }
     if (lane == 0) { srr[w][q] = rr; sbr[w][q] = br; }
   }
-  // the waves' A^T r joined in wave order
-  for (int q = 0; q < RR_WAVES; ++q) {
-    if (w == q) {
+  // the waves' A^T r (then A^T A v) joined in wave order
+  for (int pass = 0; pass < (DUAL ? 2 : 1); ++pass) {
+    for (int q = 0; q < RR_WAVES; ++q) {
+      if (w == q) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
+        for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int v = 0; v < VN; ++v) {
-          const int c = 64 * VN * s + VN * lane + v;
-          sp[c] = (q == 0) ? pr[s * VN + v] : sp[c] + pr[s * VN + v];
-        }
+          for (int v = 0; v < VN; ++v) {
+            const int c = 64 * VN * s + VN * lane + v;
+            const double val = (DUAL && pass == 1) ? pq[s * VN + v] : pr[s * VN + v];
+            sp[c] = (q == 0) ? val : sp[c] + val;
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    double *dst = (pass == 0 ? ppart : ppart2) + (size_t)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += RR_WAVES * 64) dst[j] = sp[j];
+    __syncthreads();   // sp is reused by the second join
   }
-  double *dst = ppart + (size_t)blockIdx.x * n;
-  for (int j = threadIdx.x; j < n; j += RR_WAVES * 64) dst[j] = sp[j];
   if (part_r) {
     for (int q = threadIdx.x; q < groups; q += RR_WAVES * 64) {
       const int gq = g0 + q;
@@ -227,29 +255,30 @@ int64_t rowpass_ld(int64_t n) {
   return 64 * (t <= 16 ? 16 : t <= 32 ? 32 : t <= 48 ? 48 : 64);
 }
 
-template <typename T>
+template <typename T, bool DUAL>
 static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, const double *x, double *r,
-                             double *part_r, double *ppart, hipStream_t st, int cls) {
+                             double *part_r, double *ppart, const double *v2, double *ppart2, hipStream_t st,
+                             int cls) {
   const int cus = rowpass_cus();
   const int groups = rowpass_groups(A.m, cus), blocks = rowpass_blocks(A.m, cus);
   const int nt = (int)(A.ldr >> 6);    // the copy's stride is 64 TT (rowpass_ld)
   const dim3 g(blocks), t(RR_WAVES * 64);
   switch (nt) {
     case 16:
-      TLS_LAUNCH(cls, (k_resgrad_rows<16, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart);
+      TLS_LAUNCH(cls, (k_resgrad_rows<16, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart, v2, ppart2);
       break;
     case 32:
-      TLS_LAUNCH(cls, (k_resgrad_rows<32, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart);
+      TLS_LAUNCH(cls, (k_resgrad_rows<32, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart, v2, ppart2);
       break;
     case 48:
-      TLS_LAUNCH(cls, (k_resgrad_rows<48, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart);
+      TLS_LAUNCH(cls, (k_resgrad_rows<48, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart, v2, ppart2);
       break;
     case 64:
-      TLS_LAUNCH(cls, (k_resgrad_rows<64, T>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart);
+      TLS_LAUNCH(cls, (k_resgrad_rows<64, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                 ppart, v2, ppart2);
       break;
     default:
       return hipErrorInvalidValue;
@@ -257,10 +286,12 @@ static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, con
   return hipGetLastError();
 }
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                          double *ppart, hipStream_t st, int f32) {
-  // the FP32 passes are the certificate's: profiled with the gate's Lanczos
-  if (f32 && A.at32) return rowpass_go<float>(A, A.at32, b, x, r, part_r, ppart, st, PC_LANCZOS);
-  return rowpass_go<double>(A, A.at, b, x, r, part_r, ppart, st, PC_RESIDUAL);
+                          double *ppart, hipStream_t st) {
+  return rowpass_go<double, false>(A, A.at, b, x, r, part_r, ppart, nullptr, nullptr, st, PC_RESIDUAL);
+}
+hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *x, double *r, double *part_r,
+                               double *ppart, const double *v2, double *ppart2, hipStream_t st) {
+  return rowpass_go<double, true>(A, A.at, b, x, r, part_r, ppart, v2, ppart2, st, PC_RESIDUAL);
 }
 
 // y = s * (sum of the row workgroups' partials), in a fixed order

@@ -102,7 +102,6 @@ struct tls_precond_s {
   double *cval = nullptr;
   const int32_t *csr_row_ptr = nullptr, *csr_col_idx = nullptr;   // the validated structure
   double *at = nullptr;            // row-major copy of a dense A (stride ldr), or NULL
-  float *at32 = nullptr;           // its FP32 rounding (the certificate's products)
   int64_t ldr = 0;
   tls_gate_report rep{};
   void *xr = nullptr, *xc = nullptr;   // explicit inverse tiles
@@ -124,6 +123,11 @@ struct tls_precond_s {
   double *hgate = nullptr;         // pinned host block: the runs' tridiagonal scalars
   int hgate_dev = -1;
   int gate_pending = 0, have_quality = 0;
+  // a dense A's certificate rides on the solve's passes over the row copy:
+  // steps still to take (cert_todo), the next step's index, and whether the
+  // run applies the factor with the split GEMV (cert_main) or the row GEMV;
+  // ev_cert marks the work enqueued so far
+  int cert_todo = 0, cert_k = 0, cert_main = 0;
   ~tls_precond_s();
   FactorView view() const {
     FactorView F;
@@ -163,7 +167,6 @@ MatView make_view(const tls_matrix *A, const tls_precond_s *P) {
     V.row_idx = P->row_idx;
     V.cval = P->cval;
     V.at = P->at;
-    V.at32 = P->at32;
     V.ldr = P->ldr;
   }
   return V;
@@ -222,7 +225,6 @@ struct FactorWs {
   // row-major copy of a dense A (rows of stride ldr), its column-norm scratch
   // and the certificate's row-pass partials; NULL unless made
   double *at, *colsq, *qppart;
-  float *at32;
   int64_t ldr;
 };
 
@@ -283,7 +285,6 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
   W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
   W.at = W.colsq = W.qppart = nullptr;
-  W.at32 = nullptr;
   W.ldr = 0;
   if (rows && use_rowcopy(format, n)) {
     MatView V{};
@@ -292,7 +293,6 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     V.n = (int)n;
     W.ldr = rowcopy_ld(n);
     W.at = c.take<double>((size_t)m * W.ldr);
-    W.at32 = c.take<float>((size_t)m * W.ldr);
     W.colsq = c.take<double>((size_t)((m + 63) / 64) * n);
     W.qppart = c.take<double>((size_t)rowpass_partials(V) * n);
   }
@@ -737,51 +737,98 @@ tls_status collect_pair(tls_precond_s *P) {
 // A-posteriori certificate of the factor: extreme Ritz values of
 // M = R^{-T} A^T A R^{-1} after QUALITY_STEPS Lanczos steps (products with A
 // and the applications of R in FP64). M = I for the exact factor. Its
-// buffers are its own, so it may run beside enqueue_pair.
-tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st, int on_main) {
-  const int n = (int)P->n, Np = P->Np;
-  const int K = std::min(QUALITY_STEPS, n);
-  double *Vb = W.qlz;                                 // [K+1][Np]
-  double *inb = W.qlz + (size_t)(QUALITY_STEPS + 1) * Np;        // operator input
-  double *tmp = inb + (size_t)2 * Np;
-  double *outb = tmp + (size_t)2 * Np;
-  double *tn = outb + (size_t)2 * Np;
-  PcgWs S{};
-  S.sync = W.qsync;
-  S.chain = tn + Np;                                  // [2][Np]
-  S.L = 0;
-  S.cpart = W.qpart;
-  S.cnt = W.qcnt;
-  double *ab = W.qlzs;
-  tls_precond_s Q = gate_view(P);
-  if (on_main) Q.apply_mode = P->apply_mode;   // the whole chip is the run's
+// buffers are its own, so it may run beside enqueue_pair. A step k takes
+// A^T A R^{-1} v_k into tn (cert_product or a solve's fused pass), then
+// cert_after_product: R^{-T} of it, the Lanczos recurrence, and R^{-1} v_{k+1}
+// into tmp for the next product (after the last step: the read-back).
+struct CertRun {
+  int K;
+  double *Vb, *inb, *tmp, *outb, *tn, *ab;
+  PcgWs S;
+  tls_precond_s Q;
+};
+CertRun cert_run(tls_precond_s *P, FactorWs &W, int on_main) {
+  const int Np = P->Np;
+  CertRun C{};
+  C.K = std::min(QUALITY_STEPS, (int)P->n);
+  C.Vb = W.qlz;                                             // [K+1][Np]
+  C.inb = W.qlz + (size_t)(QUALITY_STEPS + 1) * Np;          // operator input
+  C.tmp = C.inb + (size_t)2 * Np;
+  C.outb = C.tmp + (size_t)2 * Np;
+  C.tn = C.outb + (size_t)2 * Np;
+  C.S.sync = W.qsync;
+  C.S.chain = C.tn + Np;                                    // [2][Np]
+  C.S.L = 0;
+  C.S.cpart = W.qpart;
+  C.S.cnt = W.qcnt;
+  C.ab = W.qlzs;
+  C.Q = gate_view(P);
+  if (on_main) C.Q.apply_mode = P->apply_mode;   // the whole chip is the run's
+  return C;
+}
+// v_0 = ones / sqrt(n), the recurrence's scalars, and R^{-1} v_0
+tls_status cert_begin(tls_precond_s *P, FactorWs &W, hipStream_t st, int on_main) {
+  CertRun C = cert_run(P, W, on_main);
+  const int n = (int)P->n;
   const double v0 = 1.0 / std::sqrt((double)n);
   {
     FillSet F;
     F.add_i32(W.qsync, 0, P->N + 8);
     F.add_i32(W.qcnt, 0, P->N);
-    F.add_f64(Vb, v0, (size_t)n);
-    F.add_f64(inb, v0, (size_t)n);
-    F.add_f64(ab, 0.0, 2 * (size_t)K);
-    F.add_f64(ab + 2 * K, 1.0, 1);
-    F.add_f64(ab + 2 * K + 1, 0.0, 1);
+    F.add_f64(C.Vb, v0, (size_t)n);
+    F.add_f64(C.inb, v0, (size_t)n);
+    F.add_f64(C.ab, 0.0, 2 * (size_t)C.K);
+    F.add_f64(C.ab + 2 * C.K, 1.0, 1);
+    F.add_f64(C.ab + 2 * C.K + 1, 0.0, 1);
     HIPCHK(launch_fill_multi(F, st));
   }
-  for (int k = 0; k < K; ++k) {
-    TRY(apply_R(&Q, 0, 1, inb, tmp, TLS_FP64, S, st));     // R^{-1} v
-    if (V.at) {                                              // A^T A R^{-1} v in one pass
-      HIPCHK(launch_rowpass(V, nullptr, tmp, nullptr, nullptr, W.qppart, st, 1));
-      HIPCHK(launch_rowpass_sum(V, W.qppart, -1.0, tn, st));
-    } else {
-      HIPCHK(launch_matvec(V, tmp, W.tm, st));               // A R^{-1} v
-      HIPCHK(launch_rmatvec(V, W.tm, tn, st));               // A^T A R^{-1} v
-    }
-    TRY(apply_R(&Q, 1, 1, tn, outb, TLS_FP64, S, st));     // R^{-T} A^T A R^{-1} v
-    HIPCHK(launch_lanczos_orth(n, Np, k, K, Vb, outb, inb, P->dsc64, ab, st, 1));
-  }
-  HIPCHK(hipMemcpyAsync(P->hgate + 2 * (2 * LANCZOS_STEPS + 2), ab, (2 * K + 2) * sizeof(double),
-                        hipMemcpyDeviceToHost, st));
+  TRY(apply_R(&C.Q, 0, 1, C.inb, C.tmp, TLS_FP64, C.S, st));    // R^{-1} v_0
   return TLS_OK;
+}
+tls_status cert_after_product(tls_precond_s *P, FactorWs &W, hipStream_t st, int on_main, int k) {
+  CertRun C = cert_run(P, W, on_main);
+  const int n = (int)P->n, Np = P->Np;
+  TRY(apply_R(&C.Q, 1, 1, C.tn, C.outb, TLS_FP64, C.S, st));    // R^{-T} A^T A R^{-1} v_k
+  HIPCHK(launch_lanczos_orth(n, Np, k, C.K, C.Vb, C.outb, C.inb, P->dsc64, C.ab, st, 1));
+  if (k + 1 < C.K) {
+    TRY(apply_R(&C.Q, 0, 1, C.inb, C.tmp, TLS_FP64, C.S, st));  // R^{-1} v_{k+1}
+  } else {
+    HIPCHK(hipMemcpyAsync(P->hgate + 2 * (2 * LANCZOS_STEPS + 2), C.ab, (2 * C.K + 2) * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+  }
+  return TLS_OK;
+}
+// the product of step k on its own: A^T A R^{-1} v_k into tn
+tls_status cert_product(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
+  CertRun C = cert_run(P, W, 0);
+  if (V.at) {                                              // one pass over the row copy
+    HIPCHK(launch_rowpass(V, nullptr, C.tmp, nullptr, nullptr, W.qppart, st));
+    HIPCHK(launch_rowpass_sum(V, W.qppart, -1.0, C.tn, st));
+  } else {
+    HIPCHK(launch_matvec(V, C.tmp, W.tm, st));               // A R^{-1} v
+    HIPCHK(launch_rmatvec(V, W.tm, C.tn, st));               // A^T A R^{-1} v
+  }
+  return TLS_OK;
+}
+// the whole run on st
+tls_status enqueue_cert(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st, int on_main) {
+  TRY(cert_begin(P, W, st, on_main));
+  for (int k = 0; k < std::min(QUALITY_STEPS, (int)P->n); ++k) {
+    TRY(cert_product(P, W, V, st));
+    TRY(cert_after_product(P, W, st, on_main, k));
+  }
+  return TLS_OK;
+}
+// the dense row copy as the certificate's passes see it (no caller matrix
+// needed: the copy is the factor workspace's)
+MatView rowcopy_view(const tls_precond_s *P) {
+  MatView V{};
+  V.format = TLS_DENSE_COLMAJOR;
+  V.m = (int)P->m;
+  V.n = (int)P->n;
+  V.at = P->at;
+  V.ldr = P->ldr;
+  return V;
 }
 
 // the certificate's tridiagonal matrix (pinned block, after ev_cert)
@@ -899,20 +946,34 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
   // from here on the runs may be in flight: mark them before any early return
   P->gate_pending = 1;
+  P->cert_todo = 0;
   tls_status s0 = enqueue_pair(P, W, P->side);
   hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
-  // the certificate of a dense A runs on the caller's stream, before the
-  // solve: its six passes over the FP32 row copy would otherwise share HBM
-  // and CUs with the solve's passes, which are just as bandwidth-bound, and
-  // both would finish late. A sparse A's certificate (latency-bound
-  // launches, like the solve's) stays on the side stream.
-  const bool main_cert = V.at != nullptr;
-  hipStream_t cs = main_cert ? st : P->side;
-  tls_status s1 = enqueue_cert(P, W, V, cs, main_cert ? 1 : 0);
-  hipError_t e1 = hipEventRecord(P->ev_cert, cs);
+  // the certificate of a dense A is started on the caller's stream, and its
+  // six products ride on the solve's passes over the row copy (each pass
+  // reads A once for both; a pass of its own would cost as much as the
+  // solve's, on the same HBM). Steps that no pass took are finished on the
+  // side stream when the verdict is needed (cert_finish). A sparse A's
+  // certificate (latency-bound launches, like the solve's) runs whole on
+  // the side stream.
+  const bool ride = V.at != nullptr;
+  tls_status s1 = TLS_OK;
+  hipError_t e1 = hipSuccess;
+  if (ride) {
+    s1 = cert_begin(P, W, st, 1);
+    e1 = hipEventRecord(P->ev_cert, st);
+    P->cert_todo = 1;
+    P->cert_k = 0;
+    P->cert_main = 1;
+  } else {
+    s1 = enqueue_cert(P, W, V, P->side, 0);
+    e1 = hipEventRecord(P->ev_cert, P->side);
+  }
   if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
     (void)hipStreamSynchronize(P->side);
+    (void)hipStreamSynchronize(st);
     P->gate_pending = 0;
+    P->cert_todo = 0;
     if (s0 != TLS_OK) return s0;
     if (s1 != TLS_OK) return s1;
     return fail(TLS_ERR_HIP, "hipEventRecord failed on the side stream");
@@ -920,17 +981,52 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   return TLS_OK;
 }
 
+FactorWs factor_ws_of(const tls_precond_s *P);
+
 // both runs finished (without waiting)
 bool gate_ready(const tls_precond_s *P) {
-  return !P->gate_pending ||
-         (hipEventQuery(P->ev_pair) == hipSuccess && hipEventQuery(P->ev_cert) == hipSuccess);
+  return !P->gate_pending || (!P->cert_todo && hipEventQuery(P->ev_pair) == hipSuccess &&
+                              hipEventQuery(P->ev_cert) == hipSuccess);
 }
 
-FactorWs factor_ws_of(const tls_precond_s *P);
+// the solve's pass at x also takes certificate step cert_k (when one is due):
+// r = b - A x with A^T r, and A^T A R^{-1} v_k, in one read of the row copy
+bool cert_rides(const tls_precond_s *P, const MatView &V) {
+  return P->gate_pending && P->cert_todo && V.at && V.at == P->at;
+}
+tls_status cert_ride_pass(tls_precond_s *P, const MatView &V, const double *b, const double *x, double *r,
+                          double *part_r, double *ppart, hipStream_t st) {
+  FactorWs W = factor_ws_of(P);
+  CertRun C = cert_run(P, W, P->cert_main);
+  HIPCHK(launch_rowpass_dual(V, b, x, r, part_r, ppart, C.tmp, W.qppart, st));
+  HIPCHK(launch_rowpass_sum(V, W.qppart, 1.0, C.tn, st));
+  TRY(cert_after_product(P, W, st, P->cert_main, P->cert_k));
+  HIPCHK(hipEventRecord(P->ev_cert, st));
+  if (++P->cert_k == C.K) P->cert_todo = 0;
+  return TLS_OK;
+}
+
+// the certificate's remaining steps on the side stream, after the work
+// enqueued for it so far (ev_cert)
+tls_status cert_finish(tls_precond_s *P) {
+  if (!P->cert_todo) return TLS_OK;
+  FactorWs W = factor_ws_of(P);
+  const MatView V = rowcopy_view(P);
+  HIPCHK(hipStreamWaitEvent(P->side, P->ev_cert, 0));
+  const int K = std::min(QUALITY_STEPS, (int)P->n);
+  for (; P->cert_k < K; ++P->cert_k) {
+    TRY(cert_product(P, W, V, P->side));
+    TRY(cert_after_product(P, W, P->side, P->cert_main, P->cert_k));
+  }
+  HIPCHK(hipEventRecord(P->ev_cert, P->side));
+  P->cert_todo = 0;
+  return TLS_OK;
+}
 
 // wait for both runs and evaluate them on the host
 tls_status gate_finish(tls_precond_s *P) {
   if (!P->gate_pending) return TLS_OK;
+  TRY(cert_finish(P));
   P->gate_pending = 0;
   HIPCHK(hipEventSynchronize(P->ev_pair));
   HIPCHK(hipEventSynchronize(P->ev_cert));
@@ -958,21 +1054,12 @@ void gate_decide(tls_precond_s *P, double sigma_ls) {
   R.bound6 = (1.0 - ratio) / R.kappaF_est;
   R.verdict &= ~(8 | 16);
   if (R.u_q < R.bound6) R.verdict |= 8;
-  // the certificate's products used the FP32 copy of a dense A: with
-  // |A - A32| <= 2^-24 |A| entrywise, ||(A - A32) R^{-1}|| <= 2^-24
-  // || |A| D^{-1} ||_F ||R_hat^{-1}|| = 2^-24 sqrt(n) / sigma_min(R_hat) =: e,
-  // which moves the eigenvalues of R^{-T} A^T A R^{-1} by at most
-  // 2 e sqrt(quality_hi) + e^2; doubled, since sigma_min(R_hat) is itself
-  // a Lanczos estimate from above
-  // Ritz values lie inside the spectrum, so the window also gives up
+  // Ritz values lie inside the spectrum, so the window gives up
   // CERT_RITZ_MARGIN on each side: the six-step Ritz values of the
   // benchmark workloads' FP16, BF16 and split-BF16 factors came within 0.0032
-  // of the exact extreme eigenvalues (dense eigenvalues on the host)
+  // of the exact extreme eigenvalues (dense eigenvalues on the host). The
+  // products are FP64 throughout, so their rounding adds nothing visible.
   R.cert_margin = CERT_RITZ_MARGIN;
-  if (P->at32 && P->smin_s > 0) {
-    const double e = std::ldexp(1.0, -24) * std::sqrt((double)P->n) / P->smin_s;
-    R.cert_margin += 2.0 * (2.0 * e * std::sqrt(std::max(R.quality_hi, 1.0)) + e * e);
-  }
   if (R.quality_lo - R.cert_margin >= 0.5 && R.quality_hi + R.cert_margin <= 1.5) R.verdict |= 16;
 }
 
@@ -1002,6 +1089,7 @@ void gate_drain(tls_precond_s *P) {
   if (P->gate_pending) {
     (void)hipStreamSynchronize(P->side);
     P->gate_pending = 0;
+    P->cert_todo = 0;
   }
 }
 
@@ -1144,12 +1232,8 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
     // CSC copy and column norms (dense: the row-major copy, its column norms
     // and the finite-input flag in one pass)
     if (W.at) {
-      // the FP32 copy serves the certificate of a low-precision factor only
-      float *at32 = (u_q != TLS_FP64) ? W.at32 : nullptr;
-      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, at32, W.colsq, W.d, W.flag,
-                                  stream));
+      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.colsq, W.d, W.flag, stream));
       P->at = W.at;
-      P->at32 = at32;
       P->ldr = W.ldr;
     } else if (A->format == TLS_CSR) {
       // the structure is checked before any kernel uses the indices (one
@@ -1686,9 +1770,17 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     // (psi, the next right-hand sides [-f, x], and x into xbest when psi is
     // the smallest so far): three launches
     double *part_f = W.part + 2 * (size_t)nb_r;
+    // one pass over the row-major copy: r = b - A xv (b or xv may be
+    // NULL) and A^T r; a step of the factor's certificate rides along when
+    // one is due
+    auto rowpass = [&](const double *bv, const double *xv, double *r, double *part_r) -> tls_status {
+      if (cert_rides(P, V)) return cert_ride_pass(P, V, bv, xv, r, part_r, W.ppart, st);
+      HIPCHK(launch_rowpass(V, bv, xv, r, part_r, W.ppart, st));
+      return TLS_OK;
+    };
     auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
       if (V.at) {   // r and A^T r in one pass over the row-major copy
-        HIPCHK(launch_rowpass(V, b, xv, W.r, W.part, W.ppart, st));
+        TRY(rowpass(b, xv, W.r, W.part));
         HIPCHK(launch_gradient_rows(V, W.ppart, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
       } else {
         HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
@@ -1701,7 +1793,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     // partials in W.r, W.part when xv is given
     auto atr_pass = [&](const double *xv, double *out) -> tls_status {
       if (V.at) {
-        HIPCHK(launch_rowpass(V, b, xv, xv ? W.r : nullptr, xv ? W.part : nullptr, W.ppart, st));
+        TRY(rowpass(b, xv, xv ? W.r : nullptr, xv ? W.part : nullptr));
         HIPCHK(launch_rowpass_sum(V, W.ppart, 1.0, out, st));
       } else {
         if (xv) {
@@ -1752,7 +1844,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
           if (!(dd[0] > 1e-16 * dd[1])) break;
         }
       }
-      if (V.at) HIPCHK(launch_rowpass(V, b, x, W.r, W.part, W.ppart, st));   // r_0
+      if (V.at) TRY(rowpass(b, x, W.r, W.part));   // r_0
       else HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       // nothing before the first psi read-back needs sigma_0 on the host

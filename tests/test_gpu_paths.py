@@ -131,17 +131,26 @@ def _solve_pair(tls, Ad, b, u_q, opts, wait_gate):
     return x.cpu().numpy(), sigma, st, P.info()
 
 
-def test_background_gate_gives_the_waiting_result():
-    # the gate's Lanczos runs overlap the iterations: same iterate, same
-    # sigma, same report as when the factorization call waits for them
+@pytest.mark.parametrize("case", ["sparse_20000x2000_fp16", "dense_16384x1024_bf16", "dense_8192x3000_fp16"])
+def test_background_gate_gives_the_waiting_result(case):
+    # the gate's Lanczos runs overlap the iterations (a dense A's certificate
+    # rides on the solve's passes over the row copy, two vectors per pass):
+    # same iterate, same sigma, same report as when the factorization call
+    # waits for them (its certificate then runs alone, one vector per pass)
     tls = _tls()
-    print("background gate, sparse 20000x2000 fp16", flush=True)
-    A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
-    Ad = tls.from_tlsgen(A)
+    print(f"background gate, {case}", flush=True)
+    if case.startswith("sparse"):
+        A, b, _, _ = tlsgen.sparse_scaled(20000, 2000, 0.005, 4.0, 1e-4, seed=2000)
+        Ad = tls.from_tlsgen(A)
+    else:
+        m, n = (16384, 1024) if "16384" in case else (8192, 3000)
+        A, b, _, _ = tlsgen.reflector_dense(m, n, seed=3000 + n)
+        Ad = tls.dense(A)
+    u_q = case.rsplit("_", 1)[1]
     opts = tls.default_opts(u_p="fp32", stop_patience=2, gate_enforce=1, allow_escalate=1,
                             refine_sweeps=1)
-    xw, sw, stw, iw = _solve_pair(tls, Ad, b, "fp16", opts, True)
-    xa, sa, sta, ia = _solve_pair(tls, Ad, b, "fp16", opts, False)
+    xw, sw, stw, iw = _solve_pair(tls, Ad, b, u_q, opts, True)
+    xa, sa, sta, ia = _solve_pair(tls, Ad, b, u_q, opts, False)
     assert stw["gate_async"] == 0 and sta["gate_async"] == 1
     assert xw.tobytes() == xa.tobytes() and sw == sa
     assert stw["psi"] == sta["psi"]
@@ -350,10 +359,10 @@ def test_certificate_against_exact_spectrum(workload, u_q):
     mg = g["cert_margin"]
     print(f"{workload} {u_q}: Ritz [{g['quality_lo']:.6f}, {g['quality_hi']:.6f}] exact [{lo:.6f}, {hi:.6f}] "
           f"margin {mg:.2e} verdict {g['verdict']}", flush=True)
-    # Ritz values of the operator lie inside its spectrum (up to the rounding
-    # of the FP32 copy the products used, bounded by the margin), and within
-    # the Ritz allowance (0.05) of its extremes
-    assert lo - mg - 1e-6 <= g["quality_lo"] and g["quality_hi"] <= hi + mg + 1e-6
+    # Ritz values of the operator lie inside its spectrum (FP64 products:
+    # up to rounding), and within the Ritz allowance (0.05) of its extremes
+    assert mg == 0.05
+    assert lo - 1e-9 <= g["quality_lo"] and g["quality_hi"] <= hi + 1e-9
     assert g["quality_lo"] - lo <= 0.05 and hi - g["quality_hi"] <= 0.05
     if g["verdict"] & 16:
         assert 0.5 <= lo and hi <= 1.5, (lo, hi)
