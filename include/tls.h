@@ -351,8 +351,10 @@ TLS_API tls_status tls_precond_export(const tls_precond P, double *R_host, doubl
 TLS_API size_t tls_pcg_workspace_size(const tls_precond P, int32_t nrhs, int32_t l);
 
 /* Run j = 0..l on nrhs (1 or 2) right-hand sides sharing sigma2. A
- * right-hand side stops before step j when eta_j = 0 (its residual is zero in
- * the working precision), or when delta_j = 0 (the printed condition) or
+ * right-hand side stops before step j when eta_j = 0 or, for j > 0,
+ * eta_j <= u_p^2 eta_0 (2^-48 in FP32, 2^-106 in FP64: its residual is zero
+ * in the working precision relative to the first), or when delta_j = 0 (the
+ * printed condition) or
  * delta_j or alpha_j = eta_j / delta_j is not finite; a step runs whole or
  * not at all, so omega never takes a NaN from 0/0. rhs and omega are
  * n x nrhs column-major FP64 (device). u_p is the arithmetic precision

@@ -17,7 +17,8 @@ Readings of the paper (each listed in the design notes):
   and the cost model of Section 3.2 count k+1 steps).
 * the PCGTLS loop ends when delta_j = 0 (as printed) and also when
   eta_j = 0 or delta_j, alpha_j is not finite (the step would divide zero
-  by zero or carry an overflow into omega); delta_j < 0 means the shifted
+  by zero or carry an overflow into omega), or when eta_j <= u_p^2 eta_0
+  (s_j is zero in the working precision relative to s_0); delta_j < 0 means the shifted
   system lost positive definiteness: the loop continues as printed, or
   raises ``IndefiniteError`` when ``strict`` is set.
 * the initial step (Algorithm 4, lines 1-5) is in the working precision u
@@ -135,7 +136,8 @@ class PCGTrace:
 
 
 def pcgtls(solve_R: Callable, solve_RT: Callable, sigma2: float, f: np.ndarray,
-           l: int, dtype=np.float64, trace: bool = False, strict: bool = False):
+           l: int, dtype=np.float64, trace: bool = False, strict: bool = False,
+           eta_floor: float | None = None):
     """Algorithm 3, l-step PCGTLS for (A^T A - sigma^2 I) w = f.
 
     CG on the preconditioned matrix C = I - sigma^2 R^{-T} R^{-1} with the
@@ -145,9 +147,12 @@ def pcgtls(solve_R: Callable, solve_RT: Callable, sigma2: float, f: np.ndarray,
     When the loop ends early. The printed condition is delta_j != 0. Step j
     also does not run when eta_j = 0 (s_j = 0 in the working precision:
     omega_j already solves the system, and the next beta would be 0/0), or
-    when delta_j or alpha_j = eta_j / delta_j is not a finite number. The
-    check comes before the step's update, so a step either runs whole or
-    not at all. A negative delta_j (the shifted system is indefinite) is
+    when delta_j or alpha_j = eta_j / delta_j is not a finite number, or
+    (j > 0) when eta_j <= eta_floor eta_0: s_j is then zero in the working
+    precision relative to s_0 and further steps only add rounding to omega.
+    eta_floor defaults to u_p^2 of ``dtype`` (2^-48 for float32, 2^-106 for
+    float64); 0 turns that test off. The check comes before the step's
+    update, so a step either runs whole or not at all. A negative delta_j (the shifted system is indefinite) is
     counted in the trace and the iteration continues, unless ``strict``
     asks for ``IndefiniteError``."""
     dt = np.dtype(dtype)
@@ -160,8 +165,11 @@ def pcgtls(solve_R: Callable, solve_RT: Callable, sigma2: float, f: np.ndarray,
     etas, deltas = [float(eta)], []
     steps = 0
     negatives = 0
+    if eta_floor is None:
+        eta_floor = 2.0 ** -48 if dt == np.float32 else 2.0 ** -106
+    floor = dt.type(eta_floor) * eta                 # eta_floor eta_0 (0: off)
     for _ in range(l + 1):
-        if eta == 0:                                 # s_j = 0: nothing left to solve
+        if eta == 0 or (steps > 0 and eta <= floor):  # s_j = 0 in the working precision
             break
         q = np.asarray(solve_R(p), dtype=dt)         # q_j = R^{-1} p_j
         delta = dt.type(p @ p) - s2 * dt.type(q @ q)  # delta_j = ||p||^2 - sigma^2 ||q||^2
@@ -234,7 +242,8 @@ def rayleigh(A_mv, b, x):
 def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
                stop_ge: bool = False, prec_p=np.float64, steps_rule=None,
                ls_corrections: int = 1, shift_clamp: float | None = None,
-               solvers=None, record: bool = True, psi_tie: float = 4.0) -> RQIResult:
+               solvers=None, record: bool = True, psi_tie: float = 4.0,
+               eta_floor: float | None = None) -> RQIResult:
     """RQI-PCGTLS (Algorithm 2 with Algorithm 3 inner solves).
 
     The working precision u is float64 throughout; ``prec_p`` is the
@@ -262,7 +271,8 @@ def rqi_pcgtls(A, b, R=None, *, x0=None, kmax: int = 100, patience: int = 1,
         steps_rule = lambda k: k
 
     def inner(sig2, rhs, l):
-        w = pcgtls(solve_R, solve_RT, sig2, np.asarray(rhs, dtype=prec_p), l, dtype=prec_p)
+        w = pcgtls(solve_R, solve_RT, sig2, np.asarray(rhs, dtype=prec_p), l, dtype=prec_p,
+                   eta_floor=eta_floor)
         return np.asarray(w, dtype=np.float64)
 
     # lines 1-5: x_0 = x_LS, one inverse-iteration step with shift 0

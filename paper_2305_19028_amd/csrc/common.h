@@ -132,6 +132,13 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// PCGTLS (Algorithm 3) does not run step j > 0 once eta_j <= u_p^2 eta_0:
+// the preconditioned residual s_j is then zero in the working precision
+// relative to s_0, and further steps only add rounding to omega
+template <typename C> __host__ __device__ constexpr C pcg_eta_floor();
+template <> __host__ __device__ constexpr float pcg_eta_floor<float>() { return 0x1p-48f; }
+template <> __host__ __device__ constexpr double pcg_eta_floor<double>() { return 0x1p-106; }
+
 // 1/sqrt(p) from the hardware estimate refined by one Newton step
 // y <- y (3 - p y^2) / 2 (relative error about the square of the estimate's)
 __device__ inline float rsqrt_nr(float p) {

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
   // s_live: step j-1 ran for this right-hand side (it is still iterating);
   // s_run: step j runs (eta_j != 0 and, forward, delta_j and alpha_j finite
   // and delta_j != 0)
-  __shared__ int s_live[NR], s_run[NR], s_last, s_skip;
+  __shared__ int s_live[NR], s_run[NR], s_floor[NR], s_last, s_skip;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
   const int I = blockIdx.x, sidx = ROW ? 0 : blockIdx.y, CH = ROW ? 1 : gridDim.y;
@@ -433,18 +433,25 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
   if constexpr (MODE == XB || MODE == XF) {
     if (w == 1) {
       for (int r = 0; r < NR; ++r) {
-        // eta_j = 0 ends the loop before step j (s_j = 0 in the working
-        // precision: omega_j already solves the system and beta_j would be
-        // 0/0); a step whose delta_j or alpha_j is zero or not finite does
-        // not run either, so omega never takes a NaN
+        // eta_j = 0, or eta_j <= u_p^2 eta_0 for j > 0, ends the loop before
+        // step j (s_j = 0 in the working precision: omega_j already solves
+        // the system, and at eta_j = 0 beta_j would be 0/0); a step whose
+        // delta_j or alpha_j is zero or not finite does not run either, so
+        // omega never takes a NaN
         const C eta = xsum_parts(xpart_ptr(P.part, P.j, 0, r, NR, N), N);
+        const C eta0 = (P.j > 0) ? xsum_parts(xpart_ptr(P.part, 0, 0, r, NR, N), N) : eta;
+        const bool at_floor = P.j > 0 && eta <= pcg_eta_floor<C>() * eta0;
         if constexpr (MODE == XB) {
           C beta = 0;
           if (P.j > 0) {
             const C eta_prev = xsum_parts(xpart_ptr(P.part, P.j - 1, 0, r, NR, N), N);
             if (eta_prev != (C)0) beta = eta / eta_prev;
           }
-          if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; s_run[r] = (eta != (C)0); }
+          if (lane == 0) {
+            s_scal[r][0] = eta; s_scal[r][1] = beta;
+            s_run[r] = (eta != (C)0) && !at_floor;
+            s_floor[r] = at_floor;
+          }
         } else {
           const C pp = xsum_parts(xpart_ptr(P.part, P.j, 1, r, NR, N), N);
           const C qq = xsum_parts(xpart_ptr(P.part, P.j, 2, r, NR, N), N);
@@ -453,7 +460,8 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
           const C alpha = eta / delta;
           if (lane == 0) {
             s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = alpha; s_scal[r][3] = sig2;
-            s_run[r] = (eta != (C)0) && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
+            s_run[r] = (eta != (C)0) && !at_floor && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
+            s_floor[r] = at_floor;
           }
         }
       }
@@ -599,7 +607,7 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
         const int was = (j > 0) ? P.done[(j - 1) * NR + r] : 0;
         int now = was;
         if (!was) {
-          if (s_scal[r][0] != (C)0) tr[1 * L2 + j] = (double)delta;
+          if (s_scal[r][0] != (C)0 && !s_floor[r]) tr[1 * L2 + j] = (double)delta;
           if (s_run[r]) tr[2 * L2 + j] = (double)s_scal[r][2];
           if (!s_run[r]) now = 1;
           if (s_run[r] && delta < (C)0) {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
   __shared__ C s_scal[NR][4];
   // s_live: step j-1 ran for this right-hand side; s_run: step j runs
   // (eta_j != 0 and, forward, delta_j and alpha_j finite and delta_j != 0)
-  __shared__ int s_live[NR], s_run[NR];
+  __shared__ int s_live[NR], s_run[NR], s_floor[NR];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
@@ -123,17 +123,24 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
     // ---- step-level scalars (identical in every workgroup) --------------
     if constexpr (MODE == PCG_B || MODE == PCG_F) {
       if (w == 0) {
-        // eta_j = 0 ends the loop before step j (beta_j would be 0/0);
-        // a step whose delta_j or alpha_j is zero or not finite does not run
+        // eta_j = 0, or eta_j <= u_p^2 eta_0 for j > 0, ends the loop before
+        // step j (at eta_j = 0 beta_j would be 0/0); a step whose delta_j or
+        // alpha_j is zero or not finite does not run
         for (int r = 0; r < NR; ++r) {
           const C eta = sum_parts(part_ptr(P.part, P.j, 0, r, NR, N), N);
+          const C eta0 = (P.j > 0) ? sum_parts(part_ptr(P.part, 0, 0, r, NR, N), N) : eta;
+          const bool at_floor = P.j > 0 && eta <= pcg_eta_floor<C>() * eta0;
           if constexpr (MODE == PCG_B) {
             C beta = 0;
             if (P.j > 0) {
               const C eta_prev = sum_parts(part_ptr(P.part, P.j - 1, 0, r, NR, N), N);
               if (eta_prev != (C)0) beta = eta / eta_prev;
             }
-            if (lane == 0) { s_scal[r][0] = eta; s_scal[r][1] = beta; s_run[r] = (eta != (C)0); }
+            if (lane == 0) {
+              s_scal[r][0] = eta; s_scal[r][1] = beta;
+              s_run[r] = (eta != (C)0) && !at_floor;
+              s_floor[r] = at_floor;
+            }
           } else {
             const C pp = sum_parts(part_ptr(P.part, P.j, 1, r, NR, N), N);
             const C qq = sum_parts(part_ptr(P.part, P.j, 2, r, NR, N), N);
@@ -142,7 +149,8 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
             const C alpha = eta / delta;
             if (lane == 0) {
               s_scal[r][0] = eta; s_scal[r][1] = delta; s_scal[r][2] = alpha; s_scal[r][3] = sig2;
-              s_run[r] = (eta != (C)0) && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
+              s_run[r] = (eta != (C)0) && !at_floor && (delta != (C)0) && isfinite(delta) && isfinite(alpha);
+              s_floor[r] = at_floor;
             }
           }
         }
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(WG) void k_trsv(TrsvParams<S, C> P) {
             const int was = (j > 0) ? P.done[(j - 1) * NR + r] : 0;
             int now = was;
             if (!was) {
-              if (s_scal[r][0] != (C)0) tr[1 * L2 + j] = (double)delta;
+              if (s_scal[r][0] != (C)0 && !s_floor[r]) tr[1 * L2 + j] = (double)delta;
               if (s_run[r]) tr[2 * L2 + j] = (double)s_scal[r][2];
               if (!s_run[r]) now = 1;
               if (s_run[r] && delta < (C)0) {

@@ -317,3 +317,23 @@ def test_returned_iterate_rule(tie):
     assert np.linalg.norm(o.x - ref.x) / np.linalg.norm(ref.x) < max(1e-12, 100 * bx)
     with pytest.raises(ValueError):
         rqi.rqi_pcgtls(A, b, psi_tie=0.5)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_pcgtls_precision_floor_exit(dtype):
+    """The loop stops before step j > 0 once eta_j <= u_p^2 eta_0: on a
+    well-preconditioned shifted system (sigma far below sigma'_n) that
+    happens after a few steps, and the steps it skips change omega by no
+    more than the working precision (the run without the test, to l = 40,
+    agrees to a few u_p)."""
+    A, b, _ = tlsgen.dense_gaussian(600, 60, seed=11)
+    R = rqi.cholesky_R(A)
+    sR, sRT = rqi._tri_solvers(R, dtype)
+    s_n = np.linalg.svd(A, compute_uv=False)[-1]
+    f = np.random.default_rng(5).standard_normal(60)
+    w, t = rqi.pcgtls(sR, sRT, (0.3 * s_n) ** 2, f.astype(dtype), 40, dtype=dtype, trace=True)
+    w0, t0 = rqi.pcgtls(sR, sRT, (0.3 * s_n) ** 2, f.astype(dtype), 40, dtype=dtype, trace=True, eta_floor=0.0)
+    u = float(np.finfo(dtype).eps) / 2
+    assert t.steps < t0.steps
+    assert t.eta[t.steps] <= u * u * t.eta[0] < t.eta[t.steps - 1]
+    assert np.linalg.norm(w.astype(np.float64) - w0) <= 20 * u * np.linalg.norm(w0)
