@@ -99,6 +99,8 @@ hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval
                                hipStream_t st);
 // row-major copy At (stride ldr) of a dense column-major A, column norms d and
 // the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
+// doubles of the column-norm scratch launch_rowcopy_dense needs (colsq)
+size_t rowcopy_colsq_doubles(int64_t m, int64_t n);
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
                                 double *colsq, double *d, int *flag, hipStream_t st);
 // CSR structure check (row pointers, column range, sorted rows): *bad |= 1

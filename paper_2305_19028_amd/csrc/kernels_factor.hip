@@ -498,12 +498,37 @@ __global__ void k_colnorms_parts(int n, int nblk, const double *colsq, double *d
   for (; b < nblk; ++b) c[0] += colsq[(size_t)b * n + j];
   d[j] = sqrt((c[0] + c[1]) + (c[2] + c[3]));
 }
+// the sums of colsq over slices of COLSQ_SLICE row blocks (slice s into
+// out[s][j]), so that the final sum reads few partials per column and the
+// long reduction is spread over the chip
+constexpr int COLSQ_SLICE = 64;
+__global__ void k_colnorms_slices(int n, int nblk, const double *colsq, double *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, sl = blockIdx.y;
+  if (j >= n) return;
+  const int b0 = sl * COLSQ_SLICE, b1 = min(nblk, b0 + COLSQ_SLICE);
+  double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = b0;
+  for (; b + 8 <= b1; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] += colsq[(size_t)(b + u) * n + j];
+  }
+  for (; b < b1; ++b) c[0] += colsq[(size_t)b * n + j];
+  out[(size_t)sl * n + j] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+}
+size_t rowcopy_colsq_doubles(int64_t m, int64_t n) {
+  const int64_t nblk = (m + 63) / 64;
+  return (size_t)(nblk + (nblk + COLSQ_SLICE - 1) / COLSQ_SLICE) * (size_t)n;
+}
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
                                 double *colsq, double *d, int *flag, hipStream_t st) {
   const int nblk = (m + 63) / 64;
   TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(nblk, (unsigned)(ldr / 64)), dim3(256), 0, st, m, n, ld, A, ldr, At,
              colsq, flag);
-  TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nblk, colsq, d);
+  // the slice sums go after the nblk rows of block sums (rowcopy_colsq_doubles)
+  const int nsl = (nblk + COLSQ_SLICE - 1) / COLSQ_SLICE;
+  double *sl = colsq + (size_t)nblk * n;
+  TLS_LAUNCH(PC_SETUP, k_colnorms_slices, dim3((n + 255) / 256, nsl), dim3(256), 0, st, n, nblk, colsq, sl);
+  TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nsl, sl, d);
   return hipGetLastError();
 }
 
@@ -1047,16 +1072,56 @@ inline size_t gram_cast_only_bytes(int64_t m, int64_t n) {
 // the 16-bit cast in chunk-major order: out[((r / 64) n128 + c) 64 + r % 64]
 // = round(A(r, c) / d_c), zero padding. A 64-row chunk of all columns is
 // contiguous, so a panel's chunk is 16 KB in one piece for the Gram kernel
-template <typename T>
-__global__ __launch_bounds__(256) void k_cast_blocked(int m, int n, int64_t ld, const double *A, const double *d,
-                                                     int scaled, int mp, int n128, T *out) {
-  const int c = blockIdx.y;
-  const double sc = (c < n && scaled) ? 1.0 / d[c] : 1.0;
-  const double *col = A + (size_t)c * ld;
-  for (int r = blockIdx.x * 1024 + threadIdx.x; r < min(mp, (int)(blockIdx.x + 1) * 1024); r += 256) {
-    const double v = (r < m && c < n) ? col[r] * sc : 0.0;
-    out[((size_t)(r / G16K) * n128 + c) * G16K + (r % G16K)] = cast_bits<T>(v);
+// A D^{-1} rounded to 16 bits in the chunk-major layout the Gram kernels
+// read: element (r, c) at ((r / 64) n128 + c) 64 + r % 64. A workgroup
+// takes one 64-row chunk of 32 consecutive columns, whose output is one
+// contiguous 4 KB run (8 KB for SPLIT); a thread takes 8 consecutive rows of
+// one column: four 16-byte loads of 2 doubles each (8 threads read a
+// column's 512 contiguous bytes) and one 16-byte store of 8 values.
+// SPLIT: the pair hi = bf16(v), lo = bf16(v - hi) into out and lo.
+template <typename T> __device__ inline uint16_t bits16(double v);
+template <> __device__ inline uint16_t bits16<half_t>(double v) { return f64_to_f16_bits(v); }
+template <> __device__ inline uint16_t bits16<bf16_t>(double v) { return f64_to_bf16_bits(v); }
+typedef double cast_d2 __attribute__((ext_vector_type(2)));
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(256) void k_cast_rows8(int m, int n, int64_t ld, const double *A, const double *d,
+                                                  int scaled, int mp, int n128, T *out, T *lo) {
+  const int c = blockIdx.y * 32 + (threadIdx.x >> 3);
+  const int r0 = blockIdx.x * G16K + (threadIdx.x & 7) * 8;
+  if (r0 >= mp || c >= n128) return;
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = 0.0;
+  if (c < n) {
+    const double sc = scaled ? 1.0 / d[c] : 1.0;
+    const double *src = A + (size_t)c * ld + r0;
+    if (r0 + 8 <= m && ((uintptr_t)src & 15) == 0) {
+      cast_d2 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = __builtin_nontemporal_load((const cast_d2 *)src + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { v[2 * u] = q[u][0]; v[2 * u + 1] = q[u][1]; }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < m) ? src[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] *= sc;
   }
+  uint32_t wh[4], wl[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const uint16_t h0 = bits16<T>(v[2 * u]), h1 = bits16<T>(v[2 * u + 1]);
+    wh[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    if constexpr (SPLIT) {
+      const uint16_t l0 = f64_to_bf16_bits(v[2 * u] - (double)bf16_bits_to_float(h0));
+      const uint16_t l1 = f64_to_bf16_bits(v[2 * u + 1] - (double)bf16_bits_to_float(h1));
+      wl[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+  }
+  const size_t o = ((size_t)(r0 / G16K) * n128 + c) * G16K + (r0 % G16K);
+  *reinterpret_cast<uint4 *>(out + o) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+  if constexpr (SPLIT) *reinterpret_cast<uint4 *>(lo + o) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
 }
 
 template <typename T>
@@ -1207,27 +1272,13 @@ __global__ __launch_bounds__(G16LANES) void k_gram_mfma16(int mp, const T *A, fl
 // ---- split BF16 inputs: a = hi + lo ------------------------------------------
 // Each entry a of A D^{-1} is carried as hi = bf16(a) and lo = bf16(a - hi)
 // (a - hi is exact in FP64), two planes in the chunk-major layout of the
-// 16-bit cast. The Gram matrix is hi^T hi + hi^T lo + lo^T hi: three BF16
-// MFMAs into one FP32 accumulator per block step, so the factor sees the
-// entries to 2^-16 relative (hi + lo) at the BF16 matrix-core rate. The kernel is
-// the paired-tile kernel above with 32-row half chunks (the two planes of
-// three panels fill 123 KB of LDS double buffered) and the same two-level
-// accumulation (the MFMA partial restarted every 128 rows).
-__global__ __launch_bounds__(256) void k_cast_split(int m, int n, int64_t ld, const double *A, const double *d,
-                                                   int scaled, int mp, int n128, bf16_t *hi, bf16_t *lo) {
-  const int c = blockIdx.y;
-  const double sc = (c < n && scaled) ? 1.0 / d[c] : 1.0;
-  const double *col = A + (size_t)c * ld;
-  for (int r = blockIdx.x * 1024 + threadIdx.x; r < min(mp, (int)(blockIdx.x + 1) * 1024); r += 256) {
-    const double v = (r < m && c < n) ? col[r] * sc : 0.0;
-    const uint16_t h = f64_to_bf16_bits(v);
-    const double vh = (double)bf16_bits_to_float(h);
-    const size_t o = ((size_t)(r / G16K) * n128 + c) * G16K + (r % G16K);
-    hi[o] = bf16_t{h};
-    lo[o] = bf16_t{f64_to_bf16_bits(v - vh)};
-  }
-}
-
+// 16-bit cast (k_cast_rows8 with SPLIT). The Gram matrix is
+// hi^T hi + hi^T lo + lo^T hi: three BF16 MFMAs into one FP32 accumulator per
+// block step, so the factor sees the entries to 2^-16 relative (hi + lo) at
+// the BF16 matrix-core rate. The kernel is the paired-tile kernel above with
+// 32-row half chunks (the two planes of three panels fill 123 KB of LDS
+// double buffered) and the same two-level accumulation (the MFMA partial
+// restarted every 128 rows).
 constexpr int G3K = 32, G3RL = G3K + 8, G3FOLD = 4;   // half chunks; fold every 128 rows
 
 __global__ __launch_bounds__(G16LANES) void k_gram_mfma16x3(int mp, const bf16_t *Ahi, const bf16_t *Alo,
@@ -1425,6 +1476,8 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
   const int nseg = gp.nseg;
   float *part = (float *)((char *)cast + gram_cast_only_bytes(m, n));
   const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
+  static_assert(G16K == 64, "k_cast_rows8 takes 64-row chunks");
+  const dim3 g8((unsigned)(mp / G16K), (unsigned)(n128 / 32));
   const dim3 g16((unsigned)(gp.npairs * nseg));
   switch (q) {
     case TLS_FP32:
@@ -1433,8 +1486,8 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                  (const float *)cast, Np, (float *)G, d, 0);
       break;
     case TLS_FP16:
-      TLS_LAUNCH(PC_GRAM, k_cast_blocked<half_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
-                 (half_t *)cast);
+      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<half_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+                 (half_t *)cast, (half_t *)nullptr);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(G16LANES), 0, st, mp, (const half_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
@@ -1442,7 +1495,8 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       break;
     case TLS_BF16X3: {
       bf16_t *hi = (bf16_t *)cast, *lo = hi + (size_t)mp * n128;
-      TLS_LAUNCH(PC_GRAM, k_cast_split, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128, hi, lo);
+      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<bf16_t, true>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+                 hi, lo);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16x3, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)hi, (const bf16_t *)lo,
                  part, NT, gp.seglen, gp.npairs, nseg);
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,
@@ -1450,8 +1504,8 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       break;
     }
     default:
-      TLS_LAUNCH(PC_GRAM, k_cast_blocked<bf16_t>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
-                 (bf16_t *)cast);
+      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<bf16_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+                 (bf16_t *)cast, (bf16_t *)nullptr);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
       TLS_LAUNCH(PC_GRAM, k_gram_reduce, dim3(ntiles, 4), dim3(256), 0, st, (const float *)part, nseg, NT, Np,

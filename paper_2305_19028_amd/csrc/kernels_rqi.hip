@@ -294,21 +294,36 @@ hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *
   return rowpass_go<double, true>(A, A.at, b, x, r, part_r, ppart, v2, ppart2, st, PC_RESIDUAL);
 }
 
+// The sum of the row pass's G partial n-vectors for the 64 columns of one
+// workgroup: wave w (lane = column) sums the w-th quarter of the partials
+// with eight loads in flight, and the quarters are added in wave order
+// (a fixed order: the result is the same on every call).
+__device__ inline double partials_sum64(int n, int G, const double *ppart, int j, double *sq /* [4][64] */) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = (G + 3) / 4, g0 = w * q, g1 = min(G, g0 + q);
+  double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < n) {
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] += ppart[(size_t)(g + u) * n + j];
+    }
+    for (; g < g1; ++g) c[0] += ppart[(size_t)g * n + j];
+  }
+  sq[w * 64 + lane] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+  __syncthreads();
+  return (sq[lane] + sq[64 + lane]) + (sq[128 + lane] + sq[192 + lane]);
+}
+
 // y = s * (sum of the row workgroups' partials), in a fixed order
 __global__ __launch_bounds__(256) void k_rowpass_sum(int n, int G, const double *ppart, double s, double *y) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  double c[4] = {0.0, 0.0, 0.0, 0.0};
-  int g = 0;
-  for (; g + 4 <= G; g += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] += ppart[(size_t)(g + u) * n + j];
-  }
-  for (; g < G; ++g) c[0] += ppart[(size_t)g * n + j];
-  y[j] = s * ((c[0] + c[1]) + (c[2] + c[3]));
+  __shared__ double sq[256];
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const double v = partials_sum64(n, G, ppart, j, sq);
+  if (threadIdx.x < 64 && j < n) y[j] = s * v;
 }
 hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st) {
-  TLS_LAUNCH(PC_GRADIENT, k_rowpass_sum, dim3((A.n + 255) / 256), dim3(256), 0, st, A.n, rowpass_partials(A),
+  TLS_LAUNCH(PC_GRADIENT, k_rowpass_sum, dim3((A.n + 63) / 64), dim3(256), 0, st, A.n, rowpass_partials(A),
              ppart, s, y);
   return hipGetLastError();
 }
@@ -476,19 +491,12 @@ hipError_t launch_gradient(const MatView &A, const double *r, const double *x, d
 __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
                                                        double *scal, double *f, double *part,
                                                        const double *part_r, int nb_r, double cap) {
-  __shared__ double sc[8], sff[8];
+  __shared__ double sc[8], sff[8], sq[256];
   const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const double atr = partials_sum64(n, G, ppart, j, sq);
   double fv = 0.0, xv = 0.0;
-  if (j < n) {
-    double c[4] = {0.0, 0.0, 0.0, 0.0};
-    int g = 0;
-    for (; g + 4 <= G; g += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] += ppart[(size_t)(g + u) * n + j];
-    }
-    for (; g < G; ++g) c[0] += ppart[(size_t)g * n + j];
-    const double atr = (c[0] + c[1]) + (c[2] + c[3]);
+  if (threadIdx.x < 64 && j < n) {
     xv = x[j];
     fv = -atr - mu * xv;
     f[j] = fv;
@@ -500,7 +508,7 @@ __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const doubl
     part[2 * blockIdx.x + 1] = fx;
   }
 }
-int gradient_rows_blocks(int n) { return (n + 255) / 256; }
+int gradient_rows_blocks(int n) { return (n + 63) / 64; }
 hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
                                 double *f, double *part, const double *part_r, int nb_r, double cap,
                                 hipStream_t st) {

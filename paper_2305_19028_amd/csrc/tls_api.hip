@@ -118,16 +118,16 @@ struct tls_precond_s {
   double lnd[4] = {0, 0, 0, 0};    // min, max, mean, std of ln d_j (warm-start features)
   // the gate's two Lanczos runs (estimates, certificate) on the library's
   // side streams: fork point, completion of each run, pending until collected
-  hipEvent_t ev_fork = nullptr, ev_pair = nullptr, ev_cert = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_pair = nullptr, ev_cert = nullptr, ev_ride = nullptr;
   hipStream_t side = nullptr;
+  hipStream_t side2 = nullptr;     // a dense A's certificate work between passes
   double *hgate = nullptr;         // pinned host block: the runs' tridiagonal scalars
   int hgate_dev = -1;
   int gate_pending = 0, have_quality = 0;
   // a dense A's certificate rides on the solve's passes over the row copy:
-  // steps still to take (cert_todo), the next step's index, and whether the
-  // run applies the factor with the split GEMV (cert_main) or the row GEMV;
-  // ev_cert marks the work enqueued so far
-  int cert_todo = 0, cert_k = 0, cert_main = 0;
+  // steps still to take (cert_todo) and the next step's index; its work
+  // between passes runs on side2 and ev_cert marks the last of it
+  int cert_todo = 0, cert_k = 0;
   ~tls_precond_s();
   FactorView view() const {
     FactorView F;
@@ -293,7 +293,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     V.n = (int)n;
     W.ldr = rowcopy_ld(n);
     W.at = c.take<double>((size_t)m * W.ldr);
-    W.colsq = c.take<double>((size_t)((m + 63) / 64) * n);
+    W.colsq = c.take<double>(rowcopy_colsq_doubles(m, n));
     W.qppart = c.take<double>((size_t)rowpass_partials(V) * n);
   }
   return W;
@@ -624,7 +624,8 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
 // instead of the whole chip
 tls_precond_s gate_view(const tls_precond_s *P) {
   tls_precond_s Q = *P;
-  Q.ev_fork = Q.ev_pair = Q.ev_cert = nullptr;
+  // the copy owns nothing: its destructor must release none of P's handles
+  Q.ev_fork = Q.ev_pair = Q.ev_cert = Q.ev_ride = nullptr;
   Q.hgate = nullptr;
   Q.gate_pending = 0;
   if (Q.xr && Q.xc) Q.apply_mode = 2;
@@ -854,20 +855,22 @@ constexpr size_t GATE_HOST_DOUBLES = 2 * (2 * LANCZOS_STEPS + 2) + (2 * QUALITY_
 // read-back (64 doubles and a flag)
 constexpr size_t PINNED_DOUBLES = GATE_HOST_DOUBLES > 72 ? GATE_HOST_DOUBLES : 72;
 std::mutex g_side_mu;
-std::map<int, hipStream_t> g_side_pool;
+std::map<std::pair<int, int>, hipStream_t> g_side_pool;
 std::map<int, std::vector<double *>> g_pinned_free;
 
-hipError_t side_stream(hipStream_t *out) {
+// side stream `which` (0: the gate's estimates and a sparse certificate,
+// 1: a dense certificate's work between the solve's passes)
+hipError_t side_stream(hipStream_t *out, int which = 0) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(g_side_mu);
-  auto it = g_side_pool.find(dev);
+  auto it = g_side_pool.find({dev, which});
   if (it == g_side_pool.end()) {
     hipStream_t a = nullptr;
     e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
-    it = g_side_pool.emplace(dev, a).first;
+    it = g_side_pool.emplace(std::make_pair(dev, which), a).first;
     prof_note_side_stream(a);
   }
   *out = it->second;
@@ -925,8 +928,11 @@ struct CopyEvent {
 }  // namespace
 
 tls_precond_s::~tls_precond_s() {
-  if (gate_pending) (void)hipStreamSynchronize(side);
-  for (hipEvent_t e : {ev_fork, ev_pair, ev_cert})
+  if (gate_pending) {
+    (void)hipStreamSynchronize(side);
+    if (side2) (void)hipStreamSynchronize(side2);
+  }
+  for (hipEvent_t e : {ev_fork, ev_pair, ev_cert, ev_ride})
     if (e) (void)hipEventDestroy(e);
   if (hgate) pinned_give(hgate, hgate_dev);
 }
@@ -937,9 +943,10 @@ namespace {
 // the other on the side stream: the estimates, then the certificate (run
 // side by side with each other they slowed the solve's iterations more)
 tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
-  HIPCHK(side_stream(&P->side));
+  HIPCHK(side_stream(&P->side, 0));
+  HIPCHK(side_stream(&P->side2, 1));
   if (!P->hgate) HIPCHK(pinned_take(&P->hgate, &P->hgate_dev));
-  for (hipEvent_t *e : {&P->ev_fork, &P->ev_pair, &P->ev_cert})
+  for (hipEvent_t *e : {&P->ev_fork, &P->ev_pair, &P->ev_cert, &P->ev_ride})
     if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   P->have_kappa = P->have_sigma_n = P->have_quality = 0;
   HIPCHK(hipEventRecord(P->ev_fork, st));
@@ -947,8 +954,6 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   // from here on the runs may be in flight: mark them before any early return
   P->gate_pending = 1;
   P->cert_todo = 0;
-  tls_status s0 = enqueue_pair(P, W, P->side);
-  hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
   // the certificate of a dense A is started on the caller's stream, and its
   // six products ride on the solve's passes over the row copy (each pass
   // reads A once for both; a pass of its own would cost as much as the
@@ -960,17 +965,22 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   tls_status s1 = TLS_OK;
   hipError_t e1 = hipSuccess;
   if (ride) {
-    s1 = cert_begin(P, W, st, 1);
+    s1 = cert_begin(P, W, st, 0);
     e1 = hipEventRecord(P->ev_cert, st);
     P->cert_todo = 1;
     P->cert_k = 0;
-    P->cert_main = 1;
-  } else {
+  }
+  // the estimates on the side stream (after the caller's stream work above,
+  // so that the factor's stream never waits for these launches)
+  tls_status s0 = enqueue_pair(P, W, P->side);
+  hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
+  if (!ride) {
     s1 = enqueue_cert(P, W, V, P->side, 0);
     e1 = hipEventRecord(P->ev_cert, P->side);
   }
   if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
     (void)hipStreamSynchronize(P->side);
+    (void)hipStreamSynchronize(P->side2);
     (void)hipStreamSynchronize(st);
     P->gate_pending = 0;
     P->cert_todo = 0;
@@ -990,35 +1000,40 @@ bool gate_ready(const tls_precond_s *P) {
 }
 
 // the solve's pass at x also takes certificate step cert_k (when one is due):
-// r = b - A x with A^T r, and A^T A R^{-1} v_k, in one read of the row copy
+// r = b - A x with A^T r, and A^T A R^{-1} v_k, in one read of the row copy.
+// The step's other work (R^{-T}, the recurrence, R^{-1} v_{k+1}) runs on
+// side2 beside the solve's own kernels; the next riding pass waits for it.
 bool cert_rides(const tls_precond_s *P, const MatView &V) {
   return P->gate_pending && P->cert_todo && V.at && V.at == P->at;
 }
 tls_status cert_ride_pass(tls_precond_s *P, const MatView &V, const double *b, const double *x, double *r,
                           double *part_r, double *ppart, hipStream_t st) {
   FactorWs W = factor_ws_of(P);
-  CertRun C = cert_run(P, W, P->cert_main);
+  CertRun C = cert_run(P, W, 0);
+  HIPCHK(hipStreamWaitEvent(st, P->ev_cert, 0));       // R^{-1} v_k and the partials' buffer
   HIPCHK(launch_rowpass_dual(V, b, x, r, part_r, ppart, C.tmp, W.qppart, st));
-  HIPCHK(launch_rowpass_sum(V, W.qppart, 1.0, C.tn, st));
-  TRY(cert_after_product(P, W, st, P->cert_main, P->cert_k));
-  HIPCHK(hipEventRecord(P->ev_cert, st));
+  HIPCHK(hipEventRecord(P->ev_ride, st));
+  HIPCHK(hipStreamWaitEvent(P->side2, P->ev_ride, 0));
+  HIPCHK(launch_rowpass_sum(V, W.qppart, 1.0, C.tn, P->side2));
+  TRY(cert_after_product(P, W, P->side2, 0, P->cert_k));
+  HIPCHK(hipEventRecord(P->ev_cert, P->side2));
   if (++P->cert_k == C.K) P->cert_todo = 0;
   return TLS_OK;
 }
 
-// the certificate's remaining steps on the side stream, after the work
-// enqueued for it so far (ev_cert)
+// the certificate's remaining steps on side2, after the work enqueued for it
+// so far (ev_cert)
 tls_status cert_finish(tls_precond_s *P) {
   if (!P->cert_todo) return TLS_OK;
   FactorWs W = factor_ws_of(P);
   const MatView V = rowcopy_view(P);
-  HIPCHK(hipStreamWaitEvent(P->side, P->ev_cert, 0));
+  HIPCHK(hipStreamWaitEvent(P->side2, P->ev_cert, 0));
   const int K = std::min(QUALITY_STEPS, (int)P->n);
   for (; P->cert_k < K; ++P->cert_k) {
-    TRY(cert_product(P, W, V, P->side));
-    TRY(cert_after_product(P, W, P->side, P->cert_main, P->cert_k));
+    TRY(cert_product(P, W, V, P->side2));
+    TRY(cert_after_product(P, W, P->side2, 0, P->cert_k));
   }
-  HIPCHK(hipEventRecord(P->ev_cert, P->side));
+  HIPCHK(hipEventRecord(P->ev_cert, P->side2));
   P->cert_todo = 0;
   return TLS_OK;
 }
@@ -1088,6 +1103,7 @@ tls_status finish_factor(tls_precond_s *P, FactorWs &W, int uq, int compute, int
 void gate_drain(tls_precond_s *P) {
   if (P->gate_pending) {
     (void)hipStreamSynchronize(P->side);
+    (void)hipStreamSynchronize(P->side2);
     P->gate_pending = 0;
     P->cert_todo = 0;
   }
@@ -1563,7 +1579,7 @@ RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s
   V.format = format;   // the block counts of the row passes depend on it
   V.m = (int)m;
   V.n = (int)n;
-  const int nb = std::max(matvec_blocks(V), rmatvec_blocks(V)) + 1;
+  const int nb = std::max({matvec_blocks(V), rmatvec_blocks(V), gradient_rows_blocks((int)n)}) + 1;
   W.r = c.take<double>(m);
   W.f = c.take<double>(n);
   W.xbest = c.take<double>(n);
