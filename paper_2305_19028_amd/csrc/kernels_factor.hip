@@ -1074,10 +1074,9 @@ inline size_t gram_cast_only_bytes(int64_t m, int64_t n) {
 // contiguous, so a panel's chunk is 16 KB in one piece for the Gram kernel
 // A D^{-1} rounded to 16 bits in the chunk-major layout the Gram kernels
 // read: element (r, c) at ((r / 64) n128 + c) 64 + r % 64. A workgroup
-// takes one 64-row chunk of 32 consecutive columns, whose output is one
-// contiguous 4 KB run (8 KB for SPLIT); a thread takes 8 consecutive rows of
-// one column: four 16-byte loads of 2 doubles each (8 threads read a
-// column's 512 contiguous bytes) and one 16-byte store of 8 values.
+// takes 2048 consecutive rows of one column (one 16 KB run of A: runs of a
+// few columns each, 512 KB apart, read slower); a thread takes 8 of them:
+// four 16-byte loads of 2 doubles each and one 16-byte store of 8 values.
 // SPLIT: the pair hi = bf16(v), lo = bf16(v - hi) into out and lo.
 template <typename T> __device__ inline uint16_t bits16(double v);
 template <> __device__ inline uint16_t bits16<half_t>(double v) { return f64_to_f16_bits(v); }
@@ -1086,9 +1085,9 @@ typedef double cast_d2 __attribute__((ext_vector_type(2)));
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k_cast_rows8(int m, int n, int64_t ld, const double *A, const double *d,
                                                   int scaled, int mp, int n128, T *out, T *lo) {
-  const int c = blockIdx.y * 32 + (threadIdx.x >> 3);
-  const int r0 = blockIdx.x * G16K + (threadIdx.x & 7) * 8;
-  if (r0 >= mp || c >= n128) return;
+  const int c = blockIdx.y;
+  const int r0 = (blockIdx.x * 256 + threadIdx.x) * 8;
+  if (r0 >= mp) return;
   double v[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) v[u] = 0.0;
@@ -1476,8 +1475,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
   const int nseg = gp.nseg;
   float *part = (float *)((char *)cast + gram_cast_only_bytes(m, n));
   const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
-  static_assert(G16K == 64, "k_cast_rows8 takes 64-row chunks");
-  const dim3 g8((unsigned)(mp / G16K), (unsigned)(n128 / 32));
+  const dim3 g8((unsigned)((mp + 2047) / 2048), (unsigned)n128);
   const dim3 g16((unsigned)(gp.npairs * nseg));
   switch (q) {
     case TLS_FP32:
