@@ -247,11 +247,29 @@ def dense(A, device="cuda") -> Matrix:
     return Matrix(c, (At,), m, n, DENSE)
 
 
-def csr(row_ptr, col_idx, val, m, n, device="cuda") -> Matrix:
+def dense_t(At) -> Matrix:
+    """A dense m x n matrix given as its transpose At (an n x m row-major
+    float64 device tensor, i.e. A column-major with ld = m); no copy."""
     torch = _torch()
-    rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int32)).to(device)
-    ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32)).to(device)
-    va = torch.as_tensor(np.asarray(val, dtype=np.float64)).to(device)
+    if not (isinstance(At, torch.Tensor) and At.is_cuda and At.dtype == torch.float64 and At.is_contiguous()):
+        raise TypeError("dense_t needs a contiguous float64 device tensor")
+    n, m = At.shape
+    c = c_matrix(DENSE, 0, m, n, m, 0, At.data_ptr(), None, None)
+    return Matrix(c, (At,), m, n, DENSE)
+
+
+def csr(row_ptr, col_idx, val, m, n, device="cuda") -> Matrix:
+    """CSR m x n with int32 indices and float64 values (numpy arrays or
+    torch tensors; device tensors of the right types are used in place)."""
+    torch = _torch()
+
+    def dev(v, npdt, tdt):
+        if isinstance(v, torch.Tensor):
+            return v.to(device=device, dtype=tdt).contiguous()
+        return torch.as_tensor(np.asarray(v, dtype=npdt)).to(device)
+    rp = dev(row_ptr, np.int32, torch.int32)
+    ci = dev(col_idx, np.int32, torch.int32)
+    va = dev(val, np.float64, torch.float64)
     c = c_matrix(CSR_FMT, 0, m, n, 0, int(ci.numel()), va.data_ptr(), rp.data_ptr(), ci.data_ptr())
     return Matrix(c, (rp, ci, va), m, n, CSR_FMT)
 

@@ -12,6 +12,14 @@ forward/backward/Adam kernels, and the evaluation compares plain and warm
 solves of held-out problems, each judged against the plain solve's answer.
 
     python -m paper_2305_19028_amd.warmstart --train 2000 --test 256
+
+At the configured scale (20000 training problems, 512 held out, m up to
+50000 and n up to 5000) the problems are drawn on the device and the
+training set is made in parts:
+
+    python -m paper_2305_19028_amd.warmstart --device-gen --train 10000 --save-data part0.npz
+    python -m paper_2305_19028_amd.warmstart --device-gen --train 10000 --seed0 10000 --save-data part1.npz
+    python -m paper_2305_19028_amd.warmstart --device-gen --load-data part0.npz part1.npz --test 512
 """
 from __future__ import annotations
 
@@ -34,12 +42,22 @@ def _torch():
     return torch
 
 
-def _problem(seed, m_range, n_range):
+def _problem(seed, m_range, n_range, device_gen=False):
+    """A problem from the host generator, or (device_gen) drawn on the
+    device from the same recipe (tlsgen.device): the only practical way to
+    make tens of thousands of problems up to 50000 x 5000."""
+    if device_gen:
+        from tlsgen import device
+        return device.warmstart_problem(seed, m_range=m_range, n_range=n_range)
     import tlsgen
     return tlsgen.warmstart_problem(seed, m_range=m_range, n_range=n_range)
 
 
 def _device_problem(p):
+    if "At" in p:
+        return tls.dense_t(p["At"]), p["b"]
+    if "row_ptr" in p:
+        return tls.csr(p["row_ptr"], p["col_idx"], p["val"], p["m"], p["n"]), p["b"]
     if p["kind"] == "dense":
         A = tls.dense(np.asfortranarray(p["A"]))
     else:
@@ -81,11 +99,12 @@ def base(F):
     return np.asarray(F, dtype=np.float64)[:, 31]
 
 
-def make_dataset(seeds, m_range=(5000, 50000), n_range=(500, 5000), path="fp64", log=None):
+def make_dataset(seeds, m_range=(5000, 50000), n_range=(500, 5000), path="fp64", log=None,
+                 device_gen=False):
     """Features and labels y = ln(1 - sigma_final^2 / sigma_0^2) from plain solves."""
     F, y = [], []
     for i, s in enumerate(seeds):
-        p = _problem(s, m_range, n_range)
+        p = _problem(s, m_range, n_range, device_gen)
         A, b = _device_problem(p)
         _, sigma, st, _, _ = solve(A, b, path, features=True)
         F.append(np.array(st["features"], dtype=np.float32))
@@ -175,14 +194,14 @@ def _first_crossing(snaps, iters, xref, tol):
 
 
 def evaluate(theta, norm, seeds, m_range=(5000, 50000), n_range=(500, 5000), path="mixed",
-             tol=1e-10, log=None):
+             tol=1e-10, log=None, device_gen=False):
     """Plain vs warm solves of held-out problems. The plain FP64 solve's answer
     judges both; returns a list of per-problem records."""
     torch = _torch()
     nd = torch.as_tensor(norm).cuda()
     out = []
     for i, s in enumerate(seeds):
-        p = _problem(s, m_range, n_range)
+        p = _problem(s, m_range, n_range, device_gen)
         A, b = _device_problem(p)
         xref, sref, _, _, _ = solve(A, b, "fp64")
         rec = {"seed": s, "kind": p["kind"], "m": p["m"], "n": p["n"]}
@@ -228,23 +247,41 @@ def main(argv=None):
     ap.add_argument("--n", type=int, nargs=2, default=(500, 5000))
     ap.add_argument("--path", default="mixed", choices=sorted(PATHS))
     ap.add_argument("--out", default=None)
+    ap.add_argument("--device-gen", action="store_true",
+                    help="draw the problems on the device (tlsgen.device)")
+    ap.add_argument("--seed0", type=int, default=0, help="first training seed")
+    ap.add_argument("--save-data", default=None, help="write the training set (npz) and stop")
+    ap.add_argument("--load-data", nargs="*", default=None, help="training sets (npz) instead of solving")
     a = ap.parse_args(argv)
     log = sys.stderr
-    train_seeds = list(range(a.train))
+    train_seeds = list(range(a.seed0, a.seed0 + a.train))
     test_seeds = list(range(10 ** 6, 10 ** 6 + a.test))
     t0 = time.perf_counter()
-    F, y = make_dataset(train_seeds, tuple(a.m), tuple(a.n), a.path, log=log)
+    if a.load_data:
+        parts = [np.load(f) for f in a.load_data]
+        F = np.concatenate([q["F"] for q in parts])
+        y = np.concatenate([q["y"] for q in parts])
+        a.train = int(F.shape[0])
+    else:
+        F, y = make_dataset(train_seeds, tuple(a.m), tuple(a.n), a.path, log=log, device_gen=a.device_gen)
+    if a.save_data:
+        np.savez(a.save_data, F=F, y=y, seeds=np.array(train_seeds))
+        print(json.dumps({"saved": a.save_data, "problems": int(F.shape[0]),
+                          "seconds": time.perf_counter() - t0}))
+        return
     t1 = time.perf_counter()
     norm = fit_norm(F)
-    nv = max(1, len(train_seeds) // 5)       # a fifth held back for the shrinkage
+    nv = max(1, int(F.shape[0]) // 5)       # a fifth held back for the shrinkage
     theta, hist = train(F[nv:], y[nv:], norm, epochs=a.epochs, log=log)
     alpha = shrink_to_validation(theta, norm, F[:nv], y[:nv])
     _torch().cuda.synchronize()
     t2 = time.perf_counter()
-    recs = evaluate(theta, norm, test_seeds, tuple(a.m), tuple(a.n), a.path, log=log)
+    recs = evaluate(theta, norm, test_seeds, tuple(a.m), tuple(a.n), a.path, log=log,
+                    device_gen=a.device_gen)
     yt = np.array([r["y_true"] for r in recs])
     s = summarize(recs)
     s.update({"train": a.train, "epochs": a.epochs, "path": a.path, "m_range": a.m, "n_range": a.n,
+              "device_gen": a.device_gen,
               "final_train_loss": hist[-1], "alpha": alpha, "dataset_s": t1 - t0, "train_s": t2 - t1,
               "y_test_mean": float(yt.mean()), "y_test_var": float(yt.var())})
     print(json.dumps(s))

@@ -53,3 +53,31 @@ def test_trained_network_gain():
     # quarter of one more on average is accepted) and costs the features,
     # the inference and a second psi evaluation
     assert s["warm"]["mean_k_tol"] <= s["plain"]["mean_k_tol"] + 0.25
+
+
+def test_device_generated_problems_solve():
+    """Problems drawn on the device (tlsgen.device, the generator of the
+    configured 20000-problem set) go through the solver in place and give
+    the SVD answer of the same matrix."""
+    import torch
+    import tlsgen
+    from tlsgen import device
+    from oracle import certify, exact
+    from paper_2305_19028_amd import tls, warmstart as ws
+    for seed in range(3):
+        p = device.warmstart_problem(seed, m_range=(1000, 3000), n_range=(40, 150))
+        print(f"device problem {seed}: {p['kind']} {p['m']} x {p['n']}", flush=True)
+        A, b = ws._device_problem(p)
+        if p["kind"] == "dense":
+            Ah = p["At"].cpu().numpy().T
+        else:
+            Ah = tlsgen.CSR(p["m"], p["n"], p["row_ptr"].cpu().numpy(), p["col_idx"].cpu().numpy(),
+                            p["val"].cpu().numpy()).to_dense()
+        ref = exact.svd_tls(Ah, b.cpu().numpy())
+        x, sigma, st, _, _ = ws.solve(A, b, "fp64")
+        # within 100 times the attainable float64 accuracy (u sigma_1 / sigma
+        # for sigma, u kappa_TLS for x; small-noise problems have a small sigma)
+        bs, bx = certify.attainable(ref.sigma_1_Ab, ref.sigma, ref.kappa_tls)
+        assert abs(sigma - ref.sigma) / ref.sigma < max(1e-10, 100 * bs)
+        assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) < max(1e-10, 100 * bx)
+        torch.cuda.synchronize()
