@@ -939,9 +939,9 @@ tls_precond_s::~tls_precond_s() {
 
 namespace {
 
-// the gate's Lanczos runs after everything enqueued on st so far, one after
-// the other on the side stream: the estimates, then the certificate (run
-// side by side with each other they slowed the solve's iterations more)
+// the gate's Lanczos runs after everything enqueued on st so far: the
+// estimates on the side stream, the certificate beside them on side2 (a
+// sparse A) or riding on the solve's passes (a dense A with a row copy)
 tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream_t st) {
   HIPCHK(side_stream(&P->side, 0));
   HIPCHK(side_stream(&P->side2, 1));
@@ -971,12 +971,15 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
     P->cert_k = 0;
   }
   // the estimates on the side stream (after the caller's stream work above,
-  // so that the factor's stream never waits for these launches)
+  // so that the factor's stream never waits for these launches); a sparse
+  // certificate beside them on side2, so that the verdict waits for the
+  // longer of the two runs rather than their sum
   tls_status s0 = enqueue_pair(P, W, P->side);
   hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
   if (!ride) {
-    s1 = enqueue_cert(P, W, V, P->side, 0);
-    e1 = hipEventRecord(P->ev_cert, P->side);
+    hipError_t ew = hipStreamWaitEvent(P->side2, P->ev_fork, 0);
+    s1 = (ew == hipSuccess) ? enqueue_cert(P, W, V, P->side2, 0) : fail(TLS_ERR_HIP, "hipStreamWaitEvent failed");
+    e1 = hipEventRecord(P->ev_cert, P->side2);
   }
   if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
     (void)hipStreamSynchronize(P->side);
