@@ -147,18 +147,20 @@ def sweep(tls, torch, steps, warmup):
     SWEEP, with the RQI counts r each needed (iterations up to the first
     iterate within tolerance), so the measured speedup can be set against
     the operation-count model of Section 3.2 at the same r."""
-    paths = WORKLOADS["dense_planted_65536x4096"]["paths"]
+    W = WORKLOADS["dense_planted_65536x4096"]
+    paths = {"fp64": W["paths"]["fp64"], "fp16": W["paths"]["mixed"], "bf16": W["variants"]["bf16_factor"]}
     for m, n in SWEEP:
         A, b, xref, sref = planted_dense(m, n, seed=3100 + n)
         Ad = tls.dense(A)
         bd = tls.device_vector(b)
         out = {"m": m, "n": n}
-        for path in ("fp64", "mixed"):
-            r = run_path(tls, torch, Ad, bd, paths[path], steps, warmup, xref, sref, TOL)
+        for path, cfg in paths.items():
+            r = run_path(tls, torch, Ad, bd, cfg, steps, warmup, xref, sref, TOL)
             out[path] = {"time_to_tol_ms": r["time_to_tol_ms"], "factor_ms": r["factor_ms"],
                          "r": r["r_first"], "err_sigma": r["err_sigma"]}
-        out["speedup_time_to_tol"] = out["fp64"]["time_to_tol_ms"] / out["mixed"]["time_to_tol_ms"]
-        print(json.dumps({"sweep": "dense planted SVD, mixed = FP16 factor / FP32 PCG / gate", **out}),
+        for path in ("fp16", "bf16"):
+            out["speedup_" + path] = out["fp64"]["time_to_tol_ms"] / out[path]["time_to_tol_ms"]
+        print(json.dumps({"sweep": "dense planted SVD, FP16 / BF16 factor, FP32 PCG, gate", **out}),
               flush=True)
         del Ad, bd
         torch.cuda.empty_cache()
