@@ -654,6 +654,11 @@ tls_status enqueue_pair(tls_precond_s *P, FactorWs &W, hipStream_t st) {
   S.cnt = W.cnt;
   double *ab = W.lzs;                                 // [2][2K+2]
   tls_precond_s Q = gate_view(P);
+  // a sparse A's solve is latency-bound launches too: there the estimates
+  // take the split GEMV (the whole chip, 7 instead of 17 us per apply at
+  // n = 2000) and the verdict comes earlier; beside a dense solve's
+  // bandwidth-bound passes they keep the row GEMV (about N CUs)
+  if (P->format == TLS_CSR) Q.apply_mode = P->apply_mode;
   Q.dsc64 = ones;                                     // apply R_hat alone
   // v_0 = ones/sqrt(n) for both runs; operator input [v0, D^{-1} v0]
   const double v0 = 1.0 / std::sqrt((double)n);
@@ -978,7 +983,7 @@ tls_status gate_start(tls_precond_s *P, FactorWs &W, const MatView &V, hipStream
   hipError_t e0 = hipEventRecord(P->ev_pair, P->side);
   if (!ride) {
     hipError_t ew = hipStreamWaitEvent(P->side2, P->ev_fork, 0);
-    s1 = (ew == hipSuccess) ? enqueue_cert(P, W, V, P->side2, 0) : fail(TLS_ERR_HIP, "hipStreamWaitEvent failed");
+    s1 = (ew == hipSuccess) ? enqueue_cert(P, W, V, P->side2, 1) : fail(TLS_ERR_HIP, "hipStreamWaitEvent failed");
     e1 = hipEventRecord(P->ev_cert, P->side2);
   }
   if (e0 != hipSuccess || e1 != hipSuccess || s0 != TLS_OK || s1 != TLS_OK) {
