@@ -139,13 +139,14 @@ template <typename C> __host__ __device__ constexpr C pcg_eta_floor();
 template <> __host__ __device__ constexpr float pcg_eta_floor<float>() { return 0x1p-48f; }
 template <> __host__ __device__ constexpr double pcg_eta_floor<double>() { return 0x1p-106; }
 
-// 1/sqrt(p) from the hardware estimate refined by one Newton step
-// y <- y (3 - p y^2) / 2 (relative error about the square of the estimate's)
-__device__ inline float rsqrt_nr(float p) {
-  const float y = __builtin_amdgcn_rsqf(p);
-  return y * (1.5f - 0.5f * p * y * y);
-}
-__device__ inline double rsqrt_nr(double p) {
+// 1/sqrt(p) for the Cholesky pivots. FP32: the hardware reciprocal square
+// root alone (within about one unit in the last place, the size of the
+// factorization's own rounding). FP64: the hardware estimate refined by one
+// Newton step y <- y (3 - p y^2) / 2 (relative error about the square of the
+// estimate's). For p <= 0 or NaN both give NaN or Inf, and p times the
+// result is NaN.
+__device__ inline float chol_rsqrt(float p) { return __builtin_amdgcn_rsqf(p); }
+__device__ inline double chol_rsqrt(double p) {
   const double y = __builtin_amdgcn_rsq(p);
   return y * (1.5 - 0.5 * p * y * y);
 }

@@ -1701,11 +1701,16 @@ __device__ inline double read_lane(double v, int src) {
 // registers of the lane that holds it, factors it (redundantly in each lane,
 // so all lanes agree bit for bit), turns its four rows into rows of R and
 // publishes them in a double-buffered LDS slab; after one barrier the rows
-// below take the rank-4 update. One barrier per four columns; a failed pivot
-// is checked once, after the last group (the rows already written are then
-// of no use: the factorization is reported as failed). Each owning lane
-// writes its finished rows straight to memory as pieces of four column
-// entries, so no output tile is staged.
+// below take the rank-4 update. One barrier per four columns. A row group's
+// registers are final once its own group is done (no later group updates
+// them), so every lane writes its rows to memory after the loop, as pieces of
+// four column entries, and no store or flag sits on the elimination's chain.
+// A failed pivot (not positive, or NaN) leaves a NaN on its diagonal entry of
+// R (the reciprocal square root of a value <= 0 is NaN or Inf, times the
+// value is NaN) and the NaN runs on through every later pivot, so the first
+// diagonal entry of R that is not positive names the first failed pivot; the
+// diagonal lanes check theirs after the loop (the rows written are then of no
+// use: the factorization is reported as failed).
 // R(p,p) goes to rdiag (tile p, column-major), not to G: the other panel
 // workgroups of the launch still read G(p,p). The packing kernel takes the
 // diagonal tiles from rdiag.
@@ -1716,7 +1721,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
   __shared__ C ta[NB][NB + 1];     // R(k, .) operand / staged G(p,p)
   __shared__ C tb[NB][NB + 1];     // R(k, .) operand / staged G(p,p+j)
   __shared__ C slab[2][4][2 * NB];
-  __shared__ int bad_s;      // first failed pivot of the tile (1-based), INT_MAX while none
   const int tid = threadIdx.x;
   const int p = FUSED ? k + 1 : k;
   if (FUSED && (int)blockIdx.x >= N - p) {
@@ -1755,7 +1759,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
   const size_t base = (size_t)p * NB;
   const bool has_b = jb > 0;
   const size_t cb = (size_t)(p + jb) * NB;
-  if (tid == 0) bad_s = INT_MAX;
   if (FUSED) {
     // step k's update of the two tiles: ta <- R(k,p), tb <- R(k,p+jb);
     // waves 0-3 form G(p,p) - R(k,p)^T R(k,p), waves 4-7 G(p,p+jb) - R(k,p)^T R(k,p+jb)
@@ -1821,12 +1824,10 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
 #pragma unroll
         for (int y = 0; y < 4; ++y) d[x][y] = read_lane(blk[x][y], src);
       C rd[4][4], inv[4];
-      int badrow = 0;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const C pv = d[s][s];
-        if (!(pv > (C)0) && !badrow) badrow = s + 1;
-        inv[s] = rsqrt_nr(pv);         // one instruction plus a Newton step on the chain
+        inv[s] = chol_rsqrt(pv);
         const C rs = pv * inv[s];
 #pragma unroll
         for (int t = 0; t < 4; ++t) rd[s][t] = (t == s) ? rs : (t > s ? d[s][t] * inv[s] : (C)0);
@@ -1861,20 +1862,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int y = 0; y < 4; ++y) slab[buf][s][col0 + y] = blk[s][y];
-      // rows 4g.. of R in this block's four columns, straight to memory:
-      // G(p,p+jb) from the w-lanes, the upper part of R(p,p) into rdiag
-      // from the v-lanes (jb = 0)
-      if (isw == has_b && (isw || tc >= g)) {
-        C *dst = isw ? G + (cb + 4 * tc) * Np + base + 4 * g
-                     : rdiag + (size_t)p * NB * NB + (size_t)(4 * tc) * NB + 4 * g;
-        const size_t ld = isw ? (size_t)Np : (size_t)NB;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) store_col4(dst + y * ld, blk[0][y], blk[1][y], blk[2][y], blk[3][y]);
-      }
-      // a failed pivot is only recorded here: the elimination runs on (on
-      // NaN or Inf values, with no effect on control flow or addresses) and
-      // the flag is read once after the loop
-      if (badrow && tq == 0) atomicMin(&bad_s, 4 * g + badrow);
     }
     __syncthreads();
     if (tr > g) {
@@ -1893,9 +1880,20 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
       }
     }
   }
-  // uniform: every flag was set before the last group's barrier
-  const int bad = bad_s;
-  if (bad != INT_MAX && tid == 0 && blockIdx.x == 0) atomicMin(info, p * NB + bad);
+  // rows 4tr.. of R in this block's four columns: G(p,p+jb) from the w-lanes,
+  // the upper part of R(p,p) into rdiag from the v-lanes (jb = 0)
+  if (isw == has_b && (isw || tc >= tr)) {
+    C *dst = isw ? G + (cb + 4 * tc) * Np + base + 4 * tr
+                 : rdiag + (size_t)p * NB * NB + (size_t)(4 * tc) * NB + 4 * tr;
+    const size_t ld = isw ? (size_t)Np : (size_t)NB;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) store_col4(dst + y * ld, blk[0][y], blk[1][y], blk[2][y], blk[3][y]);
+  }
+  if (blockIdx.x == 0 && !isw && tc == tr) {
+    int s = 0;
+    while (s < 4 && blk[s][s] > (C)0) ++s;
+    if (s < 4) atomicMin(info, p * NB + 4 * tr + s + 1);
+  }
 }
 
 template <typename C>

@@ -271,6 +271,26 @@ def test_failure_statuses():
         tls.tls_pcg_step(P, 1.0, f, 5, u_p="fp16")
 
 
+@pytest.mark.parametrize("u_q", ["fp64", "fp32"])
+@pytest.mark.parametrize("cols", [(0,), (131,), (300, 399), (383,), (257, 131)])
+def test_cholesky_breakdown_column(u_q, cols):
+    """Zero columns make the Gram matrix singular: the first zero column j has
+    an exactly zero pivot (every entry of its row of R before j is zero), and
+    the breakdown reports j, the first failed pivot, whatever tile (128
+    columns), group of four columns and position within the group it falls
+    in, and whatever later pivots fail too. Unscaled FP64, and scaled in
+    FP32, where 0/0 in A D^{-1} makes the column NaN."""
+    tls = _tls()
+    print(f"breakdown {u_q} {cols}", flush=True)
+    A, _, _ = tlsgen.dense_gaussian(1200, 400, seed=9)
+    for c in cols:
+        A[:, c] = 0.0
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_factor_precond(tls.dense(A), u_q, scaling=(u_q != "fp64"))
+    assert e.value.status == -3
+    assert f"column {min(cols)}" in str(e.value), str(e.value)
+
+
 def test_deterministic_repeat():
     tls = _tls()
     A, b, _, _ = tlsgen.sparse_scaled(5000, 400, 0.01, 4.0, 1e-4, seed=9)
