@@ -180,7 +180,16 @@ typedef struct {
                               steps); 0 = l = k as in Algorithm 2. For starts
                               far above sigma_{n+1}, where k + 1 steps leave the
                               early Newton systems unsolved (0..4096)            */
-  int32_t reserved;
+  int32_t step_margin;     /* PCGTLS steps launched per run beyond those the
+                              latest run read back executed (default 2; 0 =
+                              launch all l + 1). Algorithm 3 ends a run early
+                              at its exits, and the steps after its end cost a
+                              short launch each; a run that ends within
+                              e + step_margin steps is unchanged by the cap,
+                              one that would run longer stops there (within
+                              Algorithm 2's at most k + 1 steps), and a run
+                              that used every step it was given lifts the cap
+                              for the next (0..4096)                             */
   double shift_clamp_tau;  /* tau of the clamp (0 < tau < 1)                       */
   double sigma0_hint;      /* warm start from a given shift estimate sigma_hat
                               (<= 0: none; ignored when mlp_theta is set)         */
@@ -201,7 +210,8 @@ typedef struct {
 typedef struct {
   int32_t iters;           /* number of psi_k evaluated (k = 1..iters)            */
   int32_t k_best;          /* k of the returned iterate (smallest psi)            */
-  int32_t pcg_steps;       /* PCGTLS steps executed (per right-hand side)         */
+  int32_t pcg_steps;       /* PCGTLS steps launched per right-hand side (a run
+                              executes fewer when it ends at its exits)          */
   int32_t warm_used;       /* 1 when the warm-start step was kept                 */
   int32_t stopped;         /* 0 psi rule, 1 kmax, 2 fixed point (psi == 0 or psi
                               repeated exactly)                                   */

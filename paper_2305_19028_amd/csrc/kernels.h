@@ -214,7 +214,8 @@ hipError_t launch_outer_psi(int n, const double *x, const double *f, const doubl
                             hipStream_t st);
 hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs, hipStream_t st);
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
-                             const double *scal, double *xbest, double *xsnap, hipStream_t st);
+                             const double *scal, double *xbest, double *xsnap, const int *done,
+                             int nsteps, hipStream_t st);
 hipError_t launch_axpy_init(int n, double *x, const double *u, const double *scal, int which,
                             hipStream_t st);
 hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);

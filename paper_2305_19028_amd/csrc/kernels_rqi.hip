@@ -19,7 +19,7 @@
 namespace tls {
 
 enum { S_SIG2 = 0, S_MU, S_XX, S_RR, S_BR, S_G, S_FF, S_PSI, S_BEST, S_ISBEST, S_ZF, S_ZX,
-       S_BETA, S_FX, S_CAP, S_K };
+       S_BETA, S_FX, S_CAP, S_K, S_STEPS };
 
 constexpr int RES_ROWS = 256;   // rows per workgroup of the CSR residual pass
 // dense row products: 64 rows per workgroup, the columns split over 16 waves
@@ -614,10 +614,13 @@ hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs,
 }
 
 // z = x + omega, beta = (z^T f - g)/(z^T x + 1), x <- z + beta u; keeps the
-// best iterate and an optional snapshot of x_k first
+// best iterate and an optional snapshot of x_k first. With done != NULL (the
+// step flags of the two PCGTLS runs just finished, nsteps of them launched)
+// it also records how many steps the longer run executed: a run's first
+// step flagged done is the one its exits skipped.
 __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const double *wu,
                                                      const double *f, double *scal, double *xbest,
-                                                     double *xsnap) {
+                                                     double *xsnap, const int *done, int nsteps) {
   __shared__ double sc[32];
   const bool isbest = scal[S_ISBEST] != 0.0;
   double zf = 0, zx = 0;
@@ -642,12 +645,24 @@ __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const dou
     const double z = x[i] + wu[i];
     x[i] = z + beta * wu[n + i];
   }
-  if (threadIdx.x == 0) { scal[S_ZF] = tzf; scal[S_ZX] = tzx; scal[S_BETA] = beta; }
+  if (threadIdx.x == 0) {
+    scal[S_ZF] = tzf; scal[S_ZX] = tzx; scal[S_BETA] = beta;
+    if (done) {
+      int used = 0;
+      for (int r = 0; r < 2; ++r) {
+        int e = 0;
+        while (e < nsteps && !done[2 * e + r]) ++e;
+        used = e > used ? e : used;
+      }
+      scal[S_STEPS] = (double)used;
+    }
+  }
 }
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
-                             const double *scal, double *xbest, double *xsnap, hipStream_t st) {
+                             const double *scal, double *xbest, double *xsnap, const int *done,
+                             int nsteps, hipStream_t st) {
   TLS_LAUNCH(PC_SCALARS, k_rqi_update, dim3(1), dim3(1024), 0, st, n, x, omega_u, f, (double *)scal,
-                     xbest, xsnap);
+                     xbest, xsnap, done, nsteps);
   return hipGetLastError();
 }
 

@@ -547,6 +547,7 @@ void tls_default_opts(tls_rqi_opts *o) {
   o->shift_clamp_tau = 0.9;
   o->sigma0_hint = -1.0;
   o->psi_tie = 4.0;
+  o->step_margin = 2;
   o->x_snapshots = nullptr;
   o->features = 0;
   o->mlp_theta = nullptr;
@@ -1760,6 +1761,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     if (o->mlp_theta && !o->mlp_norm) return fail(TLS_ERR_ARG, "mlp_theta needs mlp_norm");
     if (o->min_inner_steps < 0 || o->min_inner_steps > 4096)
       return fail(TLS_ERR_ARG, "min_inner_steps must be in [0, 4096]");
+    if (o->step_margin < 0 || o->step_margin > 4096)
+      return fail(TLS_ERR_ARG, "step_margin must be in [0, 4096]");
     if (!ws || ((uintptr_t)ws & 255)) return fail(TLS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     const size_t need = tls_rqi_workspace_size(A, P, o);
     if (ws_bytes < need) return fail(TLS_ERR_WORKSPACE, "RQI workspace %zu < %zu bytes", ws_bytes, need);
@@ -2036,14 +2039,26 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       double *const h = hb.p;                                  // 64 scalars
       int *const bad_h = reinterpret_cast<int *>(hb.p + 64);   // finite-b flag
       const bool ahead = !o->strict_pd;
-      // two PCGTLS solves with l = k (k+1 steps; at least min_inner_steps
-      // when asked), sharing the shift; the right-hand sides [-f, x] were
-      // written by the psi kernel; then the RQI update of x
-      auto inner = [&](int l) -> tls_status {
-        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, l, o->u_p, o->strict_pd, W.pcg, st));
-        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+      // two PCGTLS solves with l = k (at most k+1 steps; at least
+      // min_inner_steps when asked), sharing the shift; the right-hand sides
+      // [-f, x] were written by the psi kernel; then the RQI update of x,
+      // which also records the steps the runs executed (scalar S_STEPS)
+      auto inner = [&](int steps) -> tls_status {
+        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, steps - 1, o->u_p, o->strict_pd, W.pcg, st));
+        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, W.pcg.done, steps, st));
         return TLS_OK;
       };
+      // Steps launched per run. A run that ends at its exits (Algorithm 3:
+      // eta = 0, the precision floor, delta = 0) leaves the steps after its
+      // last one with nothing to do, but each still costs a launch that
+      // reads the done flags. Once the host has read that a run ended after
+      // e of the steps it was given, later runs are given e + step_margin
+      // (never more than k + 1): a run that ends within them is unchanged,
+      // and one that does not stops after them, which Algorithm 2's bound of
+      // at most k + 1 steps allows; a run that used every step it was given
+      // lifts the cap again.
+      std::vector<int> launched((size_t)kmax + 2, 0);
+      int step_cap = std::numeric_limits<int>::max();
       double best = std::numeric_limits<double>::infinity();
       int no_improve = 0, k = 0;
       S.stopped = 1;
@@ -2051,13 +2066,22 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         TRY(evaluate(k, cap));
         if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
         const bool first = ls_deferred && k == 1;
-        HIPCHK(hipMemcpyAsync(h, W.scal, (first ? 64 : 16) * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h, W.scal, (first ? 64 : 17) * sizeof(double), hipMemcpyDeviceToHost, st));
         if (first) HIPCHK(hipMemcpyAsync(bad_h, W.pcg.done, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(hev.e, st));
         const int l = std::max(k, o->min_inner_steps);
         const bool enq = ahead && k < kmax;
-        if (enq) TRY(inner(l));
+        auto steps_k = [&]() {
+          return (int)std::min<long long>((long long)l + 1, step_cap);
+        };
+        int steps = 0;
+        if (enq) TRY(inner(steps = steps_k()));
         HIPCHK(hipEventSynchronize(hev.e));
+        if (k >= 2 && launched[k - 1] > 0 && o->step_margin > 0) {
+          // the runs of iteration k - 1 finished before psi_k was formed
+          const int used = (int)h[16];
+          step_cap = used < launched[k - 1] ? used + o->step_margin : std::numeric_limits<int>::max();
+        }
         if (first) {
           bad_b = *bad_h;
           if (bad_b) return fail(TLS_ERR_NONFINITE, "b contains NaN or Inf");
@@ -2090,8 +2114,9 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         if (psi == 0.0 || (k > 1 && psi == S.psi[k - 2])) { S.stopped = 2; break; }
         if (no_improve >= o->stop_patience) { S.stopped = 0; break; }
         if (k == kmax) break;
-        if (!enq) TRY(inner(l));
-        S.pcg_steps += l + 1;
+        if (!enq) TRY(inner(steps = steps_k()));
+        launched[k] = steps;
+        S.pcg_steps += steps;
       }
       // the returned iterate needs the gate's verdict: wait for runs still
       // in flight now rather than after the refinement
@@ -2148,7 +2173,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
           TRY(apply_R(P, 0, 2, W.rq, W.rz, TLS_FP64, W.pcg, st));
           HIPCHK(launch_ref_step2(n, 2, W.rr, W.rz, W.rp, W.rs, 0, st));
         }
-        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, st));
+        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, nullptr, 0, st));
         S.refine_steps++;
         // keep the refined iterate under the same rule as the loop's (the psi
         // kernel has already copied it to xbest when it qualifies)

@@ -74,7 +74,7 @@ class c_rqi_opts(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "u_p", "kmax", "stop_patience", "stop_ge", "ls_corrections", "strict_pd",
         "shift_clamp", "refine_sweeps", "refine_pcg_steps", "allow_escalate",
-        "gate_enforce", "features", "min_inner_steps", "reserved")] + \
+        "gate_enforce", "features", "min_inner_steps", "step_margin")] + \
         [("shift_clamp_tau", C.c_double), ("sigma0_hint", C.c_double), ("psi_tie", C.c_double),
          ("x_snapshots", C.c_void_p), ("mlp_theta", C.c_void_p), ("mlp_norm", C.c_void_p)]
 

@@ -291,6 +291,40 @@ def test_cholesky_breakdown_column(u_q, cols):
     assert f"column {min(cols)}" in str(e.value), str(e.value)
 
 
+@pytest.mark.parametrize("case", ["sparse_fp16", "dense_bf16", "dense_fp16", "dense_fp64"])
+def test_step_cap_changes_no_result(case):
+    """Runs of PCGTLS that end at their exits (Algorithm 3) within the steps
+    the cap gives them are unchanged by it: with step_margin 2 (the default)
+    and 0 (every run given k + 1 steps) the iterates x_k, psi_k, sigma_k and
+    the answer agree bit for bit, and once runs end early fewer steps are
+    launched."""
+    import torch
+    tls = _tls()
+    print(f"step cap {case}", flush=True)
+    if case == "sparse_fp16":
+        A, b, _, _ = tlsgen.sparse_scaled(5000, 400, 0.01, 4.0, 1e-4, seed=9)
+        Ad, uq, up = tls.from_tlsgen(A), "fp16", "fp32"
+    else:
+        A, b, _ = tlsgen.dense_gaussian(2000, 150, seed=31)
+        uq = case.split("_")[1]
+        Ad, up = tls.dense(A), ("fp64" if uq == "fp64" else "fp32")
+    n = Ad.n
+    outs = []
+    for margin in (0, 2):
+        P, _ = tls.tls_factor_precond(Ad, uq)
+        snaps = torch.zeros((40, n), dtype=torch.float64, device="cuda")
+        x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p=up, stop_patience=3, kmax=30,
+                                                                  x_snapshots=snaps, step_margin=margin))
+        k = st["iters"]
+        print(f"margin {margin}: iters {k} pcg steps launched {st['pcg_steps']}", flush=True)
+        outs.append((x.cpu().numpy().tobytes(), sigma, tuple(st["psi"][:k]), tuple(st["sigma"][:k]), k,
+                     st["k_best"], snaps[:k].cpu().numpy().tobytes(), st["pcg_steps"]))
+    assert outs[0][:-1] == outs[1][:-1]
+    assert outs[1][-1] <= outs[0][-1]
+    if case != "sparse_fp16":
+        assert outs[1][-1] < outs[0][-1]
+
+
 def test_deterministic_repeat():
     tls = _tls()
     A, b, _, _ = tlsgen.sparse_scaled(5000, 400, 0.01, 4.0, 1e-4, seed=9)
@@ -317,8 +351,11 @@ def test_lookahead_changes_no_result(uq, up):
     for strict in (0, 1):
         P, _ = tls.tls_factor_precond(Ad, uq)
         snaps = torch.zeros((40, 400), dtype=torch.float64, device="cuda")
+        # step_margin 0: every run is given k + 1 steps, so the count of steps
+        # launched does not depend on when the host read the previous ones
         x, sigma, st = tls.tls_rqi_solve(Ad, b, P, tls.default_opts(u_p=up, stop_patience=2, strict_pd=strict,
-                                                                  refine_sweeps=1, x_snapshots=snaps))
+                                                                  refine_sweeps=1, x_snapshots=snaps,
+                                                                  step_margin=0))
         k = st["iters"]
         outs.append((x.cpu().numpy().tobytes(), sigma, tuple(st["psi"][:k]), k, st["k_best"], st["pcg_steps"],
                      st["stopped"], snaps[:k].cpu().numpy().tobytes()))
