@@ -97,12 +97,16 @@ hipError_t launch_csc_build(int m, int n, int64_t nnz, const int32_t *row_ptr,
                             int32_t *fill, hipStream_t st);
 hipError_t launch_colnorms_csc(int n, const int32_t *col_ptr, const double *cval, double *d,
                                hipStream_t st);
-// row-major copy At (stride ldr) of a dense column-major A, column norms d and
-// the finite-input flag in one pass (colsq: ceil(m/64) x n doubles of scratch)
-// doubles of the column-norm scratch launch_rowcopy_dense needs (colsq)
-size_t rowcopy_colsq_doubles(int64_t m, int64_t n);
+// column norms d of a dense column-major A and the finite-input flag (any
+// NaN or Inf among its m x n entries) in one read of A; part holds
+// colsq_dense_doubles(m, n) doubles of scratch
+size_t colsq_dense_doubles(int64_t m, int64_t n);
+hipError_t launch_colsq_dense(int m, int n, int64_t ld, const double *A, double *part, double *d, int *flag,
+                              hipStream_t st);
+// row-major copy At (stride ldr, a multiple of 64, padding columns zero) of a
+// dense column-major A
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                double *colsq, double *d, int *flag, hipStream_t st);
+                                hipStream_t st);
 // CSR structure check (row pointers, column range, sorted rows): *bad |= 1
 hipError_t launch_validate_csr(int m, int n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                                int *bad, hipStream_t st);
@@ -131,7 +135,10 @@ hipError_t launch_gram_export(int n, int Np, int compute, const void *G, double 
 hipError_t launch_gram_shift(int n, int Np, int compute, void *G, double shift, hipStream_t st);
 // blocked Cholesky of G in place (upper); rdiag: N 64x64 tiles of scratch
 // in the compute precision (the diagonal tiles while the steps run)
-hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st);
+// narrow (optional) is recorded on st before the first launch of the chain
+// whose grid leaves most of the chip free (at the end if none does)
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st,
+                           hipEvent_t narrow = nullptr);
 // Householder QR (kernels_qr.hip): bytes of the working matrix (FP64-sized,
 // m_pad x Np, m_pad = m + Np - n) and of all QR scratch; R goes to G
 // (column-major Np x Np, compute precision) with a nonnegative diagonal,

@@ -446,42 +446,38 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
   if (lane == 0) d[j] = sqrt(s);
 }
 // Row-major working copy of a dense column-major A (row stride ldr >= n, a
-// multiple of 64, padding columns zero), with the column sums of squares of
-// each 64-row block (colsq[block][j]) and the finite-input flag, in one pass:
-// a 64 x 64 tile per workgroup is read column by column (512-byte loads),
-// transposed through LDS and written row by row
+// multiple of 64, padding columns zero): 64 x 64 tiles, each read column by
+// column (512-byte loads), transposed through LDS and written row by row.
+// A bounded grid walks the tiles (row-block major, so neighbouring
+// workgroups write neighbouring pieces of the same rows): the copy runs
+// beside the factorization's narrow launches and must leave them CUs and
+// LDS, which a grid of one workgroup per tile, queued behind each other,
+// would not.
+constexpr int ROWCOPY_WGS = 512;
 __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr,
-                                                       double *At, double *colsq, int *flag) {
+                                                       double *At) {
   __shared__ double tile[64][65];
-  const int I = blockIdx.x, J = blockIdx.y;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = I * 64 + lane;
-  int bad = 0;
-  double v[16];
+  const int nJ = (int)(ldr / 64);
+  const int64_t ntiles = (int64_t)((m + 63) / 64) * nJ;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int I = (int)(t / nJ), J = (int)(t % nJ);
+    const int i = I * 64 + lane;
+    double v[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {        // the thread's 16 loads in flight together
-    const int j = J * 64 + 4 * q + w;
-    v[q] = (i < m && j < n) ? __builtin_nontemporal_load(A + (size_t)j * ld + i) : 0.0;
-  }
+    for (int q = 0; q < 16; ++q) {        // the thread's 16 loads in flight together
+      const int j = J * 64 + 4 * q + w;
+      v[q] = (i < m && j < n) ? __builtin_nontemporal_load(A + (size_t)j * ld + i) : 0.0;
+    }
+    __syncthreads();                      // the previous tile's reads of LDS are done
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = 4 * q + w, j = J * 64 + c;
-    const uint64_t u = __builtin_bit_cast(uint64_t, v[q]);
-    bad |= ((u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull);
-    tile[c][lane] = v[q];
-    const double sq = wave_sum(v[q] * v[q]);
-    if (lane == 0 && j < n) colsq[(size_t)I * n + j] = sq;
-  }
-  if (__any(bad) && lane == 0) atomicOr(flag, 1);
-  __syncthreads();
-  const int j = J * 64 + lane;
-  if (j >= ldr) return;
+    for (int q = 0; q < 16; ++q) tile[4 * q + w][lane] = v[q];
+    __syncthreads();
+    const int j = J * 64 + lane;          // < ldr
 #pragma unroll 4
-  for (int rr = 0; rr < 64; rr += 4) {
-    const int r = I * 64 + rr + w;
-    if (r < m) {
-      const double v = (j < n) ? tile[lane][rr + w] : 0.0;
-      At[(size_t)r * ldr + j] = v;
+    for (int rr = 0; rr < 64; rr += 4) {
+      const int r = I * 64 + rr + w;
+      if (r < m) At[(size_t)r * ldr + j] = (j < n) ? tile[lane][rr + w] : 0.0;
     }
   }
 }
@@ -515,20 +511,66 @@ __global__ void k_colnorms_slices(int n, int nblk, const double *colsq, double *
   for (; b < b1; ++b) c[0] += colsq[(size_t)b * n + j];
   out[(size_t)sl * n + j] = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
 }
-size_t rowcopy_colsq_doubles(int64_t m, int64_t n) {
-  const int64_t nblk = (m + 63) / 64;
-  return (size_t)(nblk + (nblk + COLSQ_SLICE - 1) / COLSQ_SLICE) * (size_t)n;
+// Column sums of squares of a dense column-major A over slabs of CS_ROWS
+// rows (part[s][j]) and the finite-input flag, in one read of A's m rows:
+// each wave streams CS_ROWS consecutive entries of one column (32 loads of
+// 512 bytes in flight per wave)
+constexpr int CS_ROWS = 2048;
+__global__ __launch_bounds__(256) void k_colsq_dense(int m, int n, int64_t ld, const double *A, double *part,
+                                                     int *flag) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + w;
+  if (j >= n) return;   // uniform per wave; no barrier below
+  const int nslab = (m + CS_ROWS - 1) / CS_ROWS;
+  int bad = 0;
+  for (int S = blockIdx.y; S < nslab; S += gridDim.y) {
+    const int64_t r0 = (int64_t)S * CS_ROWS;
+    const double *col = A + (size_t)j * ld + r0;
+    const int rows = (int)min((int64_t)CS_ROWS, (int64_t)m - r0);
+    double v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int i = lane + 64 * q;
+      v[q] = i < rows ? __builtin_nontemporal_load(col + i) : 0.0;
+    }
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const uint64_t u = __builtin_bit_cast(uint64_t, v[q]);
+      bad |= ((u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull);
+      s[q & 3] += v[q] * v[q];
+    }
+    const double t = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+    if (lane == 0) part[(size_t)S * n + j] = t;
+  }
+  if (__any(bad) && lane == 0) atomicOr(flag, 1);
+}
+size_t colsq_dense_doubles(int64_t m, int64_t n) {
+  const int64_t ns = std::max<int64_t>(1, (m + CS_ROWS - 1) / CS_ROWS);
+  return (size_t)(ns + (ns + COLSQ_SLICE - 1) / COLSQ_SLICE) * (size_t)n;
+}
+hipError_t launch_colsq_dense(int m, int n, int64_t ld, const double *A, double *part, double *d, int *flag,
+                              hipStream_t st) {
+  const int ns = std::max(1, (m + CS_ROWS - 1) / CS_ROWS);
+  TLS_LAUNCH(PC_SETUP, k_colsq_dense, dim3((n + 3) / 4, std::min(ns, 65535)), dim3(256), 0, st, m, n, ld, A,
+             part, flag);
+  if (ns <= COLSQ_SLICE) {
+    TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, ns, part, d);
+  } else {
+    // the slice sums go after the ns rows of slab sums (colsq_dense_doubles)
+    const int nsl = (ns + COLSQ_SLICE - 1) / COLSQ_SLICE;
+    double *sl = part + (size_t)ns * n;
+    TLS_LAUNCH(PC_SETUP, k_colnorms_slices, dim3((n + 255) / 256, nsl), dim3(256), 0, st, n, ns, part, sl);
+    TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nsl, sl, d);
+  }
+  return hipGetLastError();
 }
 hipError_t launch_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr, double *At,
-                                double *colsq, double *d, int *flag, hipStream_t st) {
-  const int nblk = (m + 63) / 64;
-  TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(nblk, (unsigned)(ldr / 64)), dim3(256), 0, st, m, n, ld, A, ldr, At,
-             colsq, flag);
-  // the slice sums go after the nblk rows of block sums (rowcopy_colsq_doubles)
-  const int nsl = (nblk + COLSQ_SLICE - 1) / COLSQ_SLICE;
-  double *sl = colsq + (size_t)nblk * n;
-  TLS_LAUNCH(PC_SETUP, k_colnorms_slices, dim3((n + 255) / 256, nsl), dim3(256), 0, st, n, nblk, colsq, sl);
-  TLS_LAUNCH(PC_SETUP, k_colnorms_parts, dim3((n + 255) / 256), dim3(256), 0, st, n, nsl, sl, d);
+                                hipStream_t st) {
+  const int64_t ntiles = (int64_t)((m + 63) / 64) * (ldr / 64);
+  const int grid = (int)std::min<int64_t>(ntiles, ROWCOPY_WGS);
+  if (grid == 0) return hipSuccess;
+  TLS_LAUNCH(PC_SETUP, k_rowcopy_dense, dim3(grid), dim3(256), 0, st, m, n, ld, A, ldr, At);
   return hipGetLastError();
 }
 
@@ -1896,21 +1938,30 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
   }
 }
 
+// launches with at most this many workgroups leave most of the chip free
+constexpr int CHOL_NARROW_GRID = 256;
 template <typename C>
-static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream_t st) {
+static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream_t st, hipEvent_t narrow) {
   TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, false>), dim3(N), dim3(CHOL_THREADS), 0, st, 0, N, Np, G, rdiag,
              info);
   for (int k = 0; k + 1 < N; ++k) {
     const int M = N - k - 2;   // trailing block rows of the update role
     const int grid = (N - k - 1) + M * (M + 1) / 2;
+    if (narrow && grid <= CHOL_NARROW_GRID) {
+      const hipError_t e = hipEventRecord(narrow, st);
+      if (e != hipSuccess) return e;
+      narrow = nullptr;
+    }
     TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, true>), dim3(grid), dim3(CHOL_THREADS), 0, st, k, N, Np, G,
                rdiag, info);
   }
+  if (narrow) return hipEventRecord(narrow, st);
   return hipGetLastError();
 }
-hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st) {
-  if (compute == TLS_FP64) return cholesky_t<double>(N, Np, (double *)G, (double *)rdiag, info, st);
-  return cholesky_t<float>(N, Np, (float *)G, (float *)rdiag, info, st);
+hipError_t launch_cholesky(int N, int Np, int compute, void *G, void *rdiag, int *info, hipStream_t st,
+                           hipEvent_t narrow) {
+  if (compute == TLS_FP64) return cholesky_t<double>(N, Np, (double *)G, (double *)rdiag, info, st, narrow);
+  return cholesky_t<float>(N, Np, (float *)G, (float *)rdiag, info, st, narrow);
 }
 
 // --------------------------------------------------------------------------

@@ -119,6 +119,13 @@ struct tls_precond_s {
   // the gate's two Lanczos runs (estimates, certificate) on the library's
   // side streams: fork point, completion of each run, pending until collected
   hipEvent_t ev_fork = nullptr, ev_pair = nullptr, ev_cert = nullptr, ev_ride = nullptr;
+  // a dense A's row-major copy is made on side2 beside the Cholesky: its
+  // source until it is enqueued (rc_todo), and ev_rows marks its end while
+  // the caller's stream has not yet been made to wait for it (rc_inflight)
+  const double *rc_src = nullptr;
+  int64_t rc_ld = 0;
+  int rc_todo = 0, rc_inflight = 0;
+  hipEvent_t ev_rows = nullptr;
   hipStream_t side = nullptr;
   hipStream_t side2 = nullptr;     // a dense A's certificate work between passes
   double *hgate = nullptr;         // pinned host block: the runs' tridiagonal scalars
@@ -286,6 +293,7 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
   W.at = W.colsq = W.qppart = nullptr;
   W.ldr = 0;
+  if (rows && format == TLS_DENSE_COLMAJOR) W.colsq = c.take<double>(colsq_dense_doubles(m, n));
   if (rows && use_rowcopy(format, n)) {
     MatView V{};
     V.format = format;
@@ -293,7 +301,6 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
     V.n = (int)n;
     W.ldr = rowcopy_ld(n);
     W.at = c.take<double>((size_t)m * W.ldr);
-    W.colsq = c.take<double>(rowcopy_colsq_doubles(m, n));
     W.qppart = c.take<double>((size_t)rowpass_partials(V) * n);
   }
   return W;
@@ -626,7 +633,8 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
 tls_precond_s gate_view(const tls_precond_s *P) {
   tls_precond_s Q = *P;
   // the copy owns nothing: its destructor must release none of P's handles
-  Q.ev_fork = Q.ev_pair = Q.ev_cert = Q.ev_ride = nullptr;
+  Q.ev_fork = Q.ev_pair = Q.ev_cert = Q.ev_ride = Q.ev_rows = nullptr;
+  Q.rc_todo = Q.rc_inflight = 0;
   Q.hgate = nullptr;
   Q.gate_pending = 0;
   if (Q.xr && Q.xc) Q.apply_mode = 2;
@@ -938,7 +946,8 @@ tls_precond_s::~tls_precond_s() {
     (void)hipStreamSynchronize(side);
     if (side2) (void)hipStreamSynchronize(side2);
   }
-  for (hipEvent_t e : {ev_fork, ev_pair, ev_cert, ev_ride})
+  if (rc_inflight && side2) (void)hipStreamSynchronize(side2);   // a factorization that failed midway
+  for (hipEvent_t e : {ev_fork, ev_pair, ev_cert, ev_ride, ev_rows})
     if (e) (void)hipEventDestroy(e);
   if (hgate) pinned_give(hgate, hgate_dev);
 }
@@ -1162,9 +1171,38 @@ tls_status factor_qr_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, in
 // breakdown flag is read, so that their enqueueing overlaps the factor's last
 // kernels; after a breakdown they are drained and started again with the
 // next attempt
+// The row-major copy of a dense A (read by every pass of the solve, not by
+// the factorization) is made once, on side2, beside the narrow tail of the
+// Cholesky chain and the inverse: launches of few workgroups that leave HBM
+// and most CUs idle (beside the wide early launches it would slow the
+// chain's trailing updates). The caller's stream waits for it before the
+// factorization's status is read, so the call returns with the copy made.
+// The fork event was recorded on st by launch_cholesky.
+tls_status start_rowcopy(tls_precond_s *P) {
+  P->rc_todo = 0;
+  HIPCHK(side_stream(&P->side2, 1));
+  HIPCHK(hipStreamWaitEvent(P->side2, P->ev_rows, 0));
+  P->rc_inflight = 1;
+  HIPCHK(launch_rowcopy_dense((int)P->m, (int)P->n, P->rc_ld, P->rc_src, P->ldr, P->at, P->side2));
+  HIPCHK(hipEventRecord(P->ev_rows, P->side2));
+  return TLS_OK;
+}
+tls_status join_rowcopy(tls_precond_s *P, hipStream_t st) {
+  if (!P->rc_inflight) return TLS_OK;
+  HIPCHK(hipStreamWaitEvent(st, P->ev_rows, 0));
+  P->rc_inflight = 0;
+  return TLS_OK;
+}
+
 tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
                        hipStream_t st, int *breakdown, const MatView *gate) {
-  if (P->method == 1) return factor_qr_once(A, P, W, uq, st, breakdown, gate);
+  if (P->method == 1) {
+    if (P->rc_todo) {
+      P->rc_todo = 0;
+      HIPCHK(launch_rowcopy_dense((int)P->m, (int)P->n, P->rc_ld, P->rc_src, P->ldr, P->at, st));
+    }
+    return factor_qr_once(A, P, W, uq, st, breakdown, gate);
+  }
   const int compute = (uq == TLS_FP64) ? TLS_FP64 : TLS_FP32;
   const int n = (int)A->n;
   *breakdown = 0;
@@ -1178,11 +1216,15 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
       P->rep.chol_retries = attempt;
     }
     HIPCHK(launch_fill_i32(W.info, INT32_MAX, 1, st));
-    HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.rdiag, W.info, st));
+    const bool fork = P->rc_todo;
+    if (fork && !P->ev_rows) HIPCHK(hipEventCreateWithFlags(&P->ev_rows, hipEventDisableTiming));
+    HIPCHK(launch_cholesky(P->N, P->Np, compute, W.G, W.rdiag, W.info, st, fork ? P->ev_rows : nullptr));
+    if (fork) TRY(start_rowcopy(P));
     // packing, diagonal inverses and the explicit inverse are enqueued before
     // the breakdown flag is read (one synchronization); after a breakdown the
     // next attempt redoes them
     TRY(finish_factor(P, W, uq, compute, 1, st));
+    TRY(join_rowcopy(P, st));
     if (gate) TRY(gate_start(P, W, *gate, st));
     int info = 0;
     const tls_status rs = read_factor_status(P, W, st, &info);
@@ -1196,10 +1238,6 @@ tls_status factor_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int u
 }
 
 }  // namespace
-
-extern "C" {
-
-}  // extern "C"
 
 namespace {
 
@@ -1252,15 +1290,20 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       F.add_i32(W.flag, 0, 1);
       HIPCHK(launch_fill_multi(F, stream));
     }
-    const size_t nval = A->format == TLS_CSR ? (size_t)A->nnz : (size_t)A->ld * (size_t)(n - 1) + (size_t)A->m;
-    if (!W.at) HIPCHK(launch_check_finite(A->val, nval, W.flag, stream));
-    // CSC copy and column norms (dense: the row-major copy, its column norms
-    // and the finite-input flag in one pass)
-    if (W.at) {
-      HIPCHK(launch_rowcopy_dense((int)A->m, n, A->ld, A->val, W.ldr, W.at, W.colsq, W.d, W.flag, stream));
-      P->at = W.at;
-      P->ldr = W.ldr;
-    } else if (A->format == TLS_CSR) {
+    // column norms: dense, with the finite-input flag in one read of A (the
+    // row-major copy for the solve follows the Gram matrix: start_rowcopy);
+    // CSR, from the CSC copy
+    if (A->format == TLS_DENSE_COLMAJOR) {
+      HIPCHK(launch_colsq_dense((int)A->m, n, A->ld, A->val, W.colsq, W.d, W.flag, stream));
+      if (W.at) {
+        P->at = W.at;
+        P->ldr = W.ldr;
+        P->rc_src = A->val;
+        P->rc_ld = A->ld;
+        P->rc_todo = 1;
+      }
+    } else {
+      HIPCHK(launch_check_finite(A->val, (size_t)A->nnz, W.flag, stream));
       // the structure is checked before any kernel uses the indices (one
       // synchronization, CSR only): a malformed matrix is an argument error,
       // never an out-of-bounds access
@@ -1281,8 +1324,6 @@ tls_status factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling, int
       P->cval = W.cval;
       P->csr_row_ptr = A->row_ptr;
       P->csr_col_idx = A->col_idx;
-    } else {
-      HIPCHK(launch_colnorms_dense((int)A->m, n, A->ld, A->val, W.d, stream));
     }
     HIPCHK(launch_scale_vectors(n, P->Np, W.d, P->scaled, W.dsc64, W.dsc32, stream));
     // ||A||_F^2 and the statistics of ln d_j for the solve; they and the
