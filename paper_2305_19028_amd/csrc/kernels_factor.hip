@@ -1111,58 +1111,59 @@ inline size_t gram_cast_only_bytes(int64_t m, int64_t n) {
   return ((size_t)gram_rows_padded(m) * n128 * 4 + 255) / 256 * 256;   // FP32-sized
 }
 
-// the 16-bit cast in chunk-major order: out[((r / 64) n128 + c) 64 + r % 64]
-// = round(A(r, c) / d_c), zero padding. A 64-row chunk of all columns is
-// contiguous, so a panel's chunk is 16 KB in one piece for the Gram kernel
 // A D^{-1} rounded to 16 bits in the chunk-major layout the Gram kernels
-// read: element (r, c) at ((r / 64) n128 + c) 64 + r % 64. A workgroup
-// takes 2048 consecutive rows of one column (one 16 KB run of A: runs of a
-// few columns each, 512 KB apart, read slower); a thread takes 8 of them:
-// four 16-byte loads of 2 doubles each and one 16-byte store of 8 values.
+// read: element (r, c) at ((r / 64) n128 + c) 64 + r % 64, zero padding (so
+// a 64-row chunk of all columns is contiguous, and a panel's chunk is 16 KB
+// in one piece for the Gram kernel). A wave takes CAST_ROWS consecutive rows
+// of one column: 32 loads of 512 contiguous bytes in flight per wave (the
+// access that streams A at close to the HBM rate), the rounded values
+// through LDS, then 16-byte stores of 8 consecutive rows (each 64-row chunk
+// of the column is 128 contiguous bytes of the output).
 // SPLIT: the pair hi = bf16(v), lo = bf16(v - hi) into out and lo.
 template <typename T> __device__ inline uint16_t bits16(double v);
 template <> __device__ inline uint16_t bits16<half_t>(double v) { return f64_to_f16_bits(v); }
 template <> __device__ inline uint16_t bits16<bf16_t>(double v) { return f64_to_bf16_bits(v); }
-typedef double cast_d2 __attribute__((ext_vector_type(2)));
+constexpr int CAST_ROWS = 2048;
 template <typename T, bool SPLIT>
-__global__ __launch_bounds__(256) void k_cast_rows8(int m, int n, int64_t ld, const double *A, const double *d,
-                                                  int scaled, int mp, int n128, T *out, T *lo) {
-  const int c = blockIdx.y;
-  const int r0 = (blockIdx.x * 256 + threadIdx.x) * 8;
-  if (r0 >= mp) return;
-  double v[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) v[u] = 0.0;
+__global__ __launch_bounds__(256) void k_cast16(int m, int n, int64_t ld, const double *A, const double *d,
+                                                int scaled, int mp, int n128, T *out, T *lo) {
+  __shared__ __align__(16) uint16_t sh[4][CAST_ROWS];
+  __shared__ __align__(16) uint16_t sl[SPLIT ? 4 : 1][SPLIT ? CAST_ROWS : 8];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.y * 4 + w;                 // < n128
+  const int rb = blockIdx.x * CAST_ROWS;            // < mp
+  double v[32];
   if (c < n) {
     const double sc = scaled ? 1.0 / d[c] : 1.0;
-    const double *src = A + (size_t)c * ld + r0;
-    if (r0 + 8 <= m && ((uintptr_t)src & 15) == 0) {
-      cast_d2 q[4];
+    const double *src = A + (size_t)c * ld + rb;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) q[u] = __builtin_nontemporal_load((const cast_d2 *)src + u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) { v[2 * u] = q[u][0]; v[2 * u + 1] = q[u][1]; }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < m) ? src[u] : 0.0;
+    for (int q = 0; q < 32; ++q) {
+      const int i = lane + 64 * q;
+      v[q] = (rb + i < m) ? __builtin_nontemporal_load(src + i) : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] *= sc;
-  }
-  uint32_t wh[4], wl[4];
+    for (int q = 0; q < 32; ++q) v[q] *= sc;
+  } else {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const uint16_t h0 = bits16<T>(v[2 * u]), h1 = bits16<T>(v[2 * u + 1]);
-    wh[u] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    if constexpr (SPLIT) {
-      const uint16_t l0 = f64_to_bf16_bits(v[2 * u] - (double)bf16_bits_to_float(h0));
-      const uint16_t l1 = f64_to_bf16_bits(v[2 * u + 1] - (double)bf16_bits_to_float(h1));
-      wl[u] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    for (int q = 0; q < 32; ++q) v[q] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    const uint16_t h = bits16<T>(v[q]);
+    sh[w][lane + 64 * q] = h;
+    if constexpr (SPLIT) sl[w][lane + 64 * q] = f64_to_bf16_bits(v[q] - (double)bf16_bits_to_float(h));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < CAST_ROWS / 512; ++t) {
+    const int p = lane + 64 * t;                    // 8 rows: rb + 8p ..
+    const int r = rb + 8 * p;
+    if (r < mp) {                                   // mp is a multiple of 64
+      const size_t o = ((size_t)(r / G16K) * n128 + c) * G16K + (r % G16K);
+      *reinterpret_cast<uint4 *>(out + o) = *reinterpret_cast<const uint4 *>(&sh[w][8 * p]);
+      if constexpr (SPLIT) *reinterpret_cast<uint4 *>(lo + o) = *reinterpret_cast<const uint4 *>(&sl[w][8 * p]);
     }
   }
-  const size_t o = ((size_t)(r0 / G16K) * n128 + c) * G16K + (r0 % G16K);
-  *reinterpret_cast<uint4 *>(out + o) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
-  if constexpr (SPLIT) *reinterpret_cast<uint4 *>(lo + o) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
 }
 
 template <typename T>
@@ -1313,7 +1314,7 @@ __global__ __launch_bounds__(G16LANES) void k_gram_mfma16(int mp, const T *A, fl
 // ---- split BF16 inputs: a = hi + lo ------------------------------------------
 // Each entry a of A D^{-1} is carried as hi = bf16(a) and lo = bf16(a - hi)
 // (a - hi is exact in FP64), two planes in the chunk-major layout of the
-// 16-bit cast (k_cast_rows8 with SPLIT). The Gram matrix is
+// 16-bit cast (k_cast16 with SPLIT). The Gram matrix is
 // hi^T hi + hi^T lo + lo^T hi: three BF16 MFMAs into one FP32 accumulator per
 // block step, so the factor sees the entries to 2^-16 relative (hi + lo) at
 // the BF16 matrix-core rate. The kernel is the paired-tile kernel above with
@@ -1517,7 +1518,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
   const int nseg = gp.nseg;
   float *part = (float *)((char *)cast + gram_cast_only_bytes(m, n));
   const dim3 gc((unsigned)((mp + 1023) / 1024), (unsigned)n128);
-  const dim3 g8((unsigned)((mp + 2047) / 2048), (unsigned)n128);
+  const dim3 g8((unsigned)((mp + CAST_ROWS - 1) / CAST_ROWS), (unsigned)(n128 / 4));
   const dim3 g16((unsigned)(gp.npairs * nseg));
   switch (q) {
     case TLS_FP32:
@@ -1526,7 +1527,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
                  (const float *)cast, Np, (float *)G, d, 0);
       break;
     case TLS_FP16:
-      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<half_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+      TLS_LAUNCH(PC_GRAM, (k_cast16<half_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  (half_t *)cast, (half_t *)nullptr);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<half_t>, g16, dim3(G16LANES), 0, st, mp, (const half_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
@@ -1535,7 +1536,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       break;
     case TLS_BF16X3: {
       bf16_t *hi = (bf16_t *)cast, *lo = hi + (size_t)mp * n128;
-      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<bf16_t, true>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+      TLS_LAUNCH(PC_GRAM, (k_cast16<bf16_t, true>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  hi, lo);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16x3, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)hi, (const bf16_t *)lo,
                  part, NT, gp.seglen, gp.npairs, nseg);
@@ -1544,7 +1545,7 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
       break;
     }
     default:
-      TLS_LAUNCH(PC_GRAM, (k_cast_rows8<bf16_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
+      TLS_LAUNCH(PC_GRAM, (k_cast16<bf16_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,
                  (bf16_t *)cast, (bf16_t *)nullptr);
       TLS_LAUNCH(PC_GRAM, k_gram_mfma16<bf16_t>, g16, dim3(G16LANES), 0, st, mp, (const bf16_t *)cast, part, NT,
                  gp.seglen, gp.npairs, nseg);
