@@ -118,14 +118,16 @@ __global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_
 // nullptr means x = 0 (r = b): the pass then gives -A^T A x or A^T b.
 constexpr int RR_WAVES = 4, RR_MAXG = 64, RR_RPW = 64 / RR_WAVES;
 
-typedef double rp_d2 __attribute__((ext_vector_type(2)));
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using type = rp_d2; static constexpr int N = 2; };
-template <typename V> __device__ inline double vget(const V &v, int k) { return (double)v[k]; }
+template <typename T> struct RowLoad;
+template <> struct RowLoad<double> { using type = double; static constexpr int N = 1; };
+__device__ inline double vget(double v, int) { return v; }
 
 // TT: columns per lane (the row stride ldr is 64 TT, padded with zeros).
-// Lane l reads 16 bytes at a time: columns 64 VN s + VN l + v (v < VN) of
-// load s, so that one load instruction of a wave moves 1 KB of the row.
+// Lane l reads VN elements at a time: columns 64 VN s + VN l + v (v < VN) of
+// load s, so that one load instruction of a wave moves 64 VN contiguous
+// elements of the row. VN = 1 (8-byte loads, 512 bytes per instruction):
+// on the 65536 x 4096 copy the pass takes 317 us against 334 us with
+// 16-byte loads (a timing probe of the kernel alone).
 // DUAL: the same pass also forms A^T A v for a second vector v (a Lanczos
 // step of the factor's certificate rides on the outer step's read of A):
 // t_i = a_i . v beside r_i, and a_i t_i summed into a second partial
@@ -135,8 +137,8 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
                                                                 const double *b, const double *x, double *r,
                                                                 double *part_r, int groups, double *ppart,
                                                                 const double *v2, double *ppart2) {
-  using V = typename Vec16<T>::type;
-  constexpr int VN = Vec16<T>::N, NS = TT / VN;       // elements per load, loads per row
+  using V = typename RowLoad<T>::type;
+  constexpr int VN = RowLoad<T>::N, NS = TT / VN;     // elements per load, loads per row
   __shared__ double sx[TT * 64], sp[TT * 64], sv[DUAL ? TT * 64 : 1];
   __shared__ double srr[RR_WAVES][RR_MAXG], sbr[RR_WAVES][RR_MAXG];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
