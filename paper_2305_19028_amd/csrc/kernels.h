@@ -195,16 +195,23 @@ int64_t rowpass_ld(int64_t n);
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
                           double *ppart, hipStream_t st);
 // the same pass with the products of a second vector v2: ppart2 receives
-// the partials of +A^T A v2 (summed by launch_rowpass_sum with s = 1)
+// the partials of +A^T A v2 (summed by launch_rowpass_sum with s = 1), and
+// t_out (optional, m) the products A v2
 hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                               double *ppart, const double *v2, double *ppart2, hipStream_t st);
+                               double *ppart, const double *v2, double *ppart2, hipStream_t st,
+                               double *t_out = nullptr);
 // y = s * sum of the partial n-vectors
 hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st);
 // f = -A^T r - mu x from the partials (gradient_rows_blocks(n) partial pairs)
 int gradient_rows_blocks(int n);
+// ppart2 (optional): A^T r = sum(ppart) - sigma_0^2 sum(ppart2), sigma_0^2 as
+// launch_shift_residual kept it
 hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
                                 double *f, double *part, const double *part_r, int nb_r, double cap,
-                                hipStream_t st);
+                                hipStream_t st, const double *ppart2 = nullptr);
+// r <- r - sigma_0^2 t (t = A u_0, sigma_0^2 = scal[0]) with the residual partials
+hipError_t launch_shift_residual(int m, const double *b, double *r, const double *t, double *scal,
+                                 double *part_r, hipStream_t st);
 hipError_t launch_gradient(const MatView &A, const double *r, const double *x, double *scal,
                            double *f, double *part, const double *part_r, int nb_r, double cap,
                            hipStream_t st);

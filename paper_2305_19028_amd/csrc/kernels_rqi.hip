@@ -19,7 +19,7 @@
 namespace tls {
 
 enum { S_SIG2 = 0, S_MU, S_XX, S_RR, S_BR, S_G, S_FF, S_PSI, S_BEST, S_ISBEST, S_ZF, S_ZX,
-       S_BETA, S_FX, S_CAP, S_K, S_STEPS };
+       S_BETA, S_FX, S_CAP, S_K, S_STEPS, S_SHIFT0 };
 
 constexpr int RES_ROWS = 256;   // rows per workgroup of the CSR residual pass
 // dense row products: 64 rows per workgroup, the columns split over 16 waves
@@ -129,14 +129,16 @@ __device__ inline double vget(double v, int) { return v; }
 // on the 65536 x 4096 copy the pass takes 317 us against 334 us with
 // 16-byte loads (a timing probe of the kernel alone).
 // DUAL: the same pass also forms A^T A v for a second vector v (a Lanczos
-// step of the factor's certificate rides on the outer step's read of A):
-// t_i = a_i . v beside r_i, and a_i t_i summed into a second partial
-// n-vector per workgroup (ppart2), joined in the same fixed order.
+// step of the factor's certificate rides on the outer step's read of A, or
+// the first RQI step's u_0): t_i = a_i . v beside r_i (written to t_out when
+// given), and a_i t_i summed into a second partial n-vector per workgroup
+// (ppart2), joined in the same fixed order.
 template <int TT, typename T, bool DUAL>
 __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, int64_t ldr, const T *At,
                                                                 const double *b, const double *x, double *r,
                                                                 double *part_r, int groups, double *ppart,
-                                                                const double *v2, double *ppart2) {
+                                                                const double *v2, double *ppart2,
+                                                                double *t_out) {
   using V = typename RowLoad<T>::type;
   constexpr int VN = RowLoad<T>::N, NS = TT / VN;     // elements per load, loads per row
   __shared__ double sx[TT * 64], sp[TT * 64], sv[DUAL ? TT * 64 : 1];
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
       const double bi = b ? b[i] : 0.0;
       const double ri = bi - dot;
       if (r && lane == 0) r[i] = ri;
+      if (DUAL && t_out && lane == 0) t_out[i] = dot2;
       rr += ri * ri;
       br += bi * ri;
 #pragma unroll
@@ -259,8 +262,8 @@ int64_t rowpass_ld(int64_t n) {
 
 template <typename T, bool DUAL>
 static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, const double *x, double *r,
-                             double *part_r, double *ppart, const double *v2, double *ppart2, hipStream_t st,
-                             int cls) {
+                             double *part_r, double *ppart, const double *v2, double *ppart2, double *t_out,
+                             hipStream_t st, int cls) {
   const int cus = rowpass_cus();
   const int groups = rowpass_groups(A.m, cus), blocks = rowpass_blocks(A.m, cus);
   const int nt = (int)(A.ldr >> 6);    // the copy's stride is 64 TT (rowpass_ld)
@@ -268,19 +271,19 @@ static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, con
   switch (nt) {
     case 16:
       TLS_LAUNCH(cls, (k_resgrad_rows<16, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart, v2, ppart2);
+                 ppart, v2, ppart2, t_out);
       break;
     case 32:
       TLS_LAUNCH(cls, (k_resgrad_rows<32, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart, v2, ppart2);
+                 ppart, v2, ppart2, t_out);
       break;
     case 48:
       TLS_LAUNCH(cls, (k_resgrad_rows<48, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart, v2, ppart2);
+                 ppart, v2, ppart2, t_out);
       break;
     case 64:
       TLS_LAUNCH(cls, (k_resgrad_rows<64, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart, v2, ppart2);
+                 ppart, v2, ppart2, t_out);
       break;
     default:
       return hipErrorInvalidValue;
@@ -289,11 +292,11 @@ static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, con
 }
 hipError_t launch_rowpass(const MatView &A, const double *b, const double *x, double *r, double *part_r,
                           double *ppart, hipStream_t st) {
-  return rowpass_go<double, false>(A, A.at, b, x, r, part_r, ppart, nullptr, nullptr, st, PC_RESIDUAL);
+  return rowpass_go<double, false>(A, A.at, b, x, r, part_r, ppart, nullptr, nullptr, nullptr, st, PC_RESIDUAL);
 }
 hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *x, double *r, double *part_r,
-                               double *ppart, const double *v2, double *ppart2, hipStream_t st) {
-  return rowpass_go<double, true>(A, A.at, b, x, r, part_r, ppart, v2, ppart2, st, PC_RESIDUAL);
+                               double *ppart, const double *v2, double *ppart2, hipStream_t st, double *t_out) {
+  return rowpass_go<double, true>(A, A.at, b, x, r, part_r, ppart, v2, ppart2, t_out, st, PC_RESIDUAL);
 }
 
 // The sum of the row pass's G partial n-vectors for the 64 columns of one
@@ -490,13 +493,20 @@ hipError_t launch_gradient(const MatView &A, const double *r, const double *x, d
 
 // f = -A^T r - mu x from the row pass's partial A^T r (fixed order over its
 // workgroups), with per-block partials of f.f and f.x as k_gradient writes them
+// With ppart2 (the first step after a merged pass): A^T r = (sum of ppart)
+// - scal[S_SHIFT0] (sum of ppart2), i.e. A^T r_0 - sigma_0^2 A^T A u_0.
 __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
                                                        double *scal, double *f, double *part,
-                                                       const double *part_r, int nb_r, double cap) {
+                                                       const double *part_r, int nb_r, double cap,
+                                                       const double *ppart2) {
   __shared__ double sc[8], sff[8], sq[256];
   const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const double atr = partials_sum64(n, G, ppart, j, sq);
+  double atr = partials_sum64(n, G, ppart, j, sq);
+  if (ppart2) {
+    __syncthreads();   // sq is reused
+    atr -= scal[S_SHIFT0] * partials_sum64(n, G, ppart2, j, sq);
+  }
   double fv = 0.0, xv = 0.0;
   if (threadIdx.x < 64 && j < n) {
     xv = x[j];
@@ -513,9 +523,36 @@ __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const doubl
 int gradient_rows_blocks(int n) { return (n + 63) / 64; }
 hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
                                 double *f, double *part, const double *part_r, int nb_r, double cap,
-                                hipStream_t st) {
+                                hipStream_t st, const double *ppart2) {
   TLS_LAUNCH(PC_GRADIENT, k_gradient_rows, dim3(gradient_rows_blocks(A.n)), dim3(256), 0, st, A.n,
-             rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap);
+             rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap, ppart2);
+  return hipGetLastError();
+}
+
+// r_1 = r_0 - sigma_0^2 t with t = A u_0 (x_1 = x_0 + sigma_0^2 u_0, so this
+// is b - A x_1), in place, with the per-64-row partials of r.r and b.r in
+// the row pass's layout; sigma_0^2 (scal[S_SIG2]) is kept in scal[S_SHIFT0]
+// for the gradient's A^T r_1
+__global__ __launch_bounds__(64) void k_shift_residual(int m, const double *b, double *r, const double *t,
+                                                       double *scal, double *part_r) {
+  const double c = scal[S_SIG2];
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  double ri = 0.0, bi = 0.0;
+  if (i < m) {
+    bi = b[i];
+    ri = r[i] - c * t[i];
+    r[i] = ri;
+  }
+  const double rr = wave_sum(ri * ri), br = wave_sum(bi * ri);
+  if (threadIdx.x == 0) {
+    part_r[2 * blockIdx.x] = rr;
+    part_r[2 * blockIdx.x + 1] = br;
+    if (blockIdx.x == 0) scal[S_SHIFT0] = c;
+  }
+}
+hipError_t launch_shift_residual(int m, const double *b, double *r, const double *t, double *scal,
+                                 double *part_r, hipStream_t st) {
+  TLS_LAUNCH(PC_GRADIENT, k_shift_residual, dim3((m + 63) / 64), dim3(64), 0, st, m, b, r, t, scal, part_r);
   return hipGetLastError();
 }
 

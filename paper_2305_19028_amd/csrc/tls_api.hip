@@ -1619,6 +1619,7 @@ namespace {
 struct RqiWs {
   double *r, *f, *xbest, *rhs, *wu, *t1, *t2, *part, *scal, *rec;
   double *ppart;                         // row-pass partials (dense A with a row-major copy)
+  double *ppart2, *tu;                   // the merged first step: A^T A u_0 partials, A u_0
   double *rr, *rz, *rp, *rq, *rt, *rs;   // refinement PCG: residual, M r, direction, K p, A p, scalars
   PcgWs pcg;
 };
@@ -1648,6 +1649,8 @@ RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s
   W.rs = c.take<double>(16);
   W.pcg = carve_pcg(c, P->Np, P->N, 2, L);
   W.ppart = P->at ? c.take<double>((size_t)rowpass_partials(V) * n) : nullptr;
+  W.ppart2 = P->at ? c.take<double>((size_t)rowpass_partials(V) * n) : nullptr;
+  W.tu = P->at ? c.take<double>((size_t)m) : nullptr;
   return W;
 }
 
@@ -1874,8 +1877,21 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       return TLS_OK;
     };
     auto evaluate = [&](int k, double cap) -> tls_status { return evaluate_at(x, k, cap); };
+    // Algorithm 2's first step at x_1 = x_0 + sigma_0^2 u_0 from the merged
+    // pass at x_0: r_1 = r_0 - sigma_0^2 A u_0 and A^T r_1 = A^T r_0 -
+    // sigma_0^2 A^T A u_0 (the same quantities, formed from products of A
+    // already taken), then the gradient and psi as in evaluate_at
+    auto evaluate_merged = [&](double cap) -> tls_status {
+      HIPCHK(launch_shift_residual(m, b, W.r, W.tu, W.scal, W.part, st));
+      HIPCHK(launch_gradient_rows(V, W.ppart, x, W.scal, W.f, part_f, W.part, nb_r, cap, st, W.ppart2));
+      HIPCHK(launch_outer_psi(n, x, W.f, part_f, nb_f, W.scal, 1, W.rec, W.rhs, W.xbest, o->psi_tie, st));
+      return TLS_OK;
+    };
 
     // ---- lines 1-5: x_0 = x_LS, sigma_0, u_0, x_1; the b-dependent gate ---
+    // dense A with the row copy and the plain start: the pass at x_0 also
+    // takes u_0, so that the first step needs no pass of its own
+    const bool merged = V.at != nullptr && !o->mlp_theta && !(o->sigma0_hint > 0);
     double rr0 = 0.0;
     bool spec = false, ls_deferred = false;
     for (;;) {
@@ -1912,8 +1928,17 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
           if (!(dd[0] > 1e-16 * dd[1])) break;
         }
       }
-      if (V.at) TRY(rowpass(b, x, W.r, W.part));   // r_0
-      else HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+      if (merged) {
+        // u_0 first, then one pass for r_0 = b - A x_0, A^T r_0, A u_0 and
+        // A^T A u_0: r_1 and A^T r_1 at x_1 = x_0 + sigma_0^2 u_0 follow
+        // from them without a pass of their own (evaluate_merged)
+        TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));             // A^T A u_0 = x_0
+        HIPCHK(launch_rowpass_dual(V, b, x, W.r, W.part, W.ppart, W.t1, W.ppart2, st, W.tu));
+      } else if (V.at) {
+        TRY(rowpass(b, x, W.r, W.part));   // r_0
+      } else {
+        HIPCHK(launch_residual(V, b, x, W.r, W.part, st));
+      }
       HIPCHK(launch_outer_rq(n, x, W.part, nb_r, W.scal, 0.0, st));  // sigma_0^2
       // nothing before the first psi read-back needs sigma_0 on the host
       // unless a warm start, the shift clamp or a waiting gate does: then
@@ -2007,7 +2032,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     // verdict is read when its runs are done (polled at each psi read-back,
     // awaited at the end) and a failed certificate discards the result
     auto body = [&]() -> tls_status {
-      TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));               // A^T A u_0 = x_0
+      if (!merged) TRY(solve_normal(P, x, W.t1, W.t2, W.pcg, st));  // A^T A u_0 = x_0
       const bool warm = o->mlp_theta != nullptr || o->sigma0_hint > 0;
       bool plain_step = true;
       if (warm || o->features) {
@@ -2104,7 +2129,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       int no_improve = 0, k = 0;
       S.stopped = 1;
       for (k = 1; k <= kmax; ++k) {
-        TRY(evaluate(k, cap));
+        if (k == 1 && merged) TRY(evaluate_merged(cap));
+        else TRY(evaluate(k, cap));
         if (o->x_snapshots) HIPCHK(launch_copy_f64(o->x_snapshots + (size_t)(k - 1) * n, x, (size_t)n, st));
         const bool first = ls_deferred && k == 1;
         HIPCHK(hipMemcpyAsync(h, W.scal, (first ? 64 : 17) * sizeof(double), hipMemcpyDeviceToHost, st));
