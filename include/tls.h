@@ -181,7 +181,7 @@ typedef struct {
                               far above sigma_{n+1}, where k + 1 steps leave the
                               early Newton systems unsolved (0..4096)            */
   int32_t step_margin;     /* PCGTLS steps launched per run beyond those the
-                              latest run read back executed (default 2; 0 =
+                              latest run read back executed (default 1; 0 =
                               launch all l + 1). Algorithm 3 ends a run early
                               at its exits, and the steps after its end cost a
                               short launch each; a run that ends within

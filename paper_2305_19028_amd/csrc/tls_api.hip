@@ -554,7 +554,7 @@ void tls_default_opts(tls_rqi_opts *o) {
   o->shift_clamp_tau = 0.9;
   o->sigma0_hint = -1.0;
   o->psi_tie = 4.0;
-  o->step_margin = 2;
+  o->step_margin = 1;
   o->x_snapshots = nullptr;
   o->features = 0;
   o->mlp_theta = nullptr;
@@ -2160,7 +2160,13 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         S.psi[k - 1] = psi;
         S.sigma[k - 1] = std::sqrt(sig2);
         S.t_ms[k - 1] = ms_since(t0);
-        if (spec && P->gate_pending && gate_ready(P)) {
+        // the verdict is read as soon as its runs are done; once a dense A's
+        // certificate has taken its last pass, the host waits for that
+        // step's remaining work on side2 here (the GPU meanwhile runs the
+        // PCGTLS solves already enqueued) instead of polling again an
+        // iteration later
+        const bool cert_enqueued = V.at && V.at == P->at && !P->cert_todo;
+        if (spec && P->gate_pending && (cert_enqueued || gate_ready(P))) {
           TRY(gate_finish(P));
           gate_decide(P, S.sigma_ls);
           S.t_verdict_ms = ms_since(t0);
