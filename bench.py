@@ -142,14 +142,16 @@ def planted_dense(m, n, seed):
 SWEEP = [(8192, 512), (16384, 1024), (32768, 2048), (65536, 4096)]
 
 
-def sweep(tls, torch, steps, warmup):
-    """Time to 1e-10 of the FP64 and the mixed (FP16 factor) paths over
-    SWEEP, with the RQI counts r each needed (iterations up to the first
-    iterate within tolerance), so the measured speedup can be set against
-    the operation-count model of Section 3.2 at the same r."""
+def sweep(tls, torch, steps, warmup, sizes=SWEEP, emit=True):
+    """Time to 1e-10 of the FP64 and the mixed (FP16 and BF16 factor) paths
+    over the sizes, with the RQI counts r each needed (iterations up to the
+    first iterate within tolerance), so the measured speedup can be set
+    against the operation-count model of Section 3.2 at the same r. Prints
+    one JSON line per size (emit) and returns the records."""
     W = WORKLOADS["dense_planted_65536x4096"]
     paths = {"fp64": W["paths"]["fp64"], "fp16": W["paths"]["mixed"], "bf16": W["variants"]["bf16_factor"]}
-    for m, n in SWEEP:
+    records = []
+    for m, n in sizes:
         A, b, xref, sref = planted_dense(m, n, seed=3100 + n)
         Ad = tls.dense(A)
         bd = tls.device_vector(b)
@@ -160,10 +162,13 @@ def sweep(tls, torch, steps, warmup):
                          "r": r["r_first"], "err_sigma": r["err_sigma"]}
         for path in ("fp16", "bf16"):
             out["speedup_" + path] = out["fp64"]["time_to_tol_ms"] / out[path]["time_to_tol_ms"]
-        print(json.dumps({"sweep": "dense planted SVD, FP16 / BF16 factor, FP32 PCG, gate", **out}),
-              flush=True)
+        if emit:
+            print(json.dumps({"sweep": "dense planted SVD, FP16 / BF16 factor, FP32 PCG, gate", **out}),
+                  flush=True)
+        records.append(out)
         del Ad, bd
         torch.cuda.empty_cache()
+    return records
 
 
 def one_solve(tls, torch, Ad, bd, cfg, snaps=None):
@@ -573,6 +578,13 @@ def main():
                        for p in sp["res"]},
             "speedup_vs_fp64": speedups(sp["res"])}
 
+    # the measured-vs-modeled sweep at the three smaller sizes (the largest,
+    # 65536 x 4096, is the headline workload's own shape)
+    sweep_rec = None
+    if not args.no_extra:
+        print("# sweep", file=sys.stderr, flush=True)
+        sweep_rec = sweep(tls, torch, 3, 1, sizes=SWEEP[:3], emit=False)
+
     cpu = None
     if not args.no_cpu:
         A, b = head["host"]
@@ -614,6 +626,10 @@ def main():
         "roofline": roof,
         "kernel_classes": prof,
         "extra_workloads": extra,
+        "sweep": {"describe": "dense planted SVD (sigma' 1 to 1e-3, sigma_{n+1} = 3.9e-5, m = 16 n), "
+                              "FP64 / FP16 / BF16 factor with FP32 PCGTLS and the gate, 3 solves each; "
+                              "r = RQIs to the first iterate within 1e-10",
+                  "sizes": sweep_rec} if sweep_rec is not None else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
