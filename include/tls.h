@@ -172,7 +172,9 @@ typedef struct {
   int32_t refine_sweeps;   /* final FP64 refinement RQI steps (explicit operator) */
   int32_t refine_pcg_steps;/* maximum PCG steps per refinement solve (it stops
                               earlier once r^T M r has fallen by 1e-26)           */
-  int32_t allow_escalate;  /* raise u_q when the b-dependent gate (6) fails       */
+  int32_t allow_escalate;  /* raise u_q when the gate's certificate fails, or when
+                              a gated solve on a low-precision factor ends
+                              without convergence (see tls_rqi_solve)           */
   int32_t gate_enforce;    /* 1: run the b-dependent gate                         */
   int32_t features;        /* 1: compute the warm-start features (stats.features)
                               even when no warm start is requested                */
@@ -443,6 +445,10 @@ TLS_API size_t tls_rqi_workspace_size(const tls_matrix *A, const tls_precond P,
  * sigma_{n+1} from above (stats.ls_refined). A problem whose own sigma_LS
  * exceeds sigma'_n is not helped by the second start (the shift clamp is the
  * remedy there), and keeps the first result.
+ * A gated solve on a low-precision factor that reaches kmax before the psi
+ * rule fires (TLS_ERR_NO_CONVERGENCE) escalates too when opts.allow_escalate
+ * is set: a factor whose error exceeds the relative gap between sigma_{n+1}
+ * and sigma'_n cannot steer RQI to the smallest root.
  *
  * Warm start (project addition; opts.mlp_theta or opts.sigma0_hint). After
  * x_0 = x_LS, u_0 = (R^T R)^{-1} x_0 and sigma_0 (the quantities of the

@@ -83,23 +83,39 @@ __global__ __launch_bounds__(1024) void k_residual_dense(int m, int n, int64_t l
   if (lane == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
 }
 
-__global__ __launch_bounds__(256) void k_residual_csr(int m, const int32_t *row_ptr,
-                                                      const int32_t *col_idx, const double *val,
-                                                      const double *b, const double *x, double *r,
-                                                      double *part) {
-  __shared__ double sc[8];
-  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
-  double rv = 0, bv = 0;
+// CSR: RES_ROWS rows per workgroup, RES_LANES lanes per row (a row's
+// entries taken RES_LANES at a time, then joined across its lanes in a
+// fixed order), so that each lane's chain of dependent loads is a quarter
+// of the row
+constexpr int RES_LANES = 4;
+__global__ __launch_bounds__(RES_ROWS * RES_LANES) void k_residual_csr(int m, const int32_t *row_ptr,
+                                                                       const int32_t *col_idx, const double *val,
+                                                                       const double *b, const double *x, double *r,
+                                                                       double *part) {
+  __shared__ double s_rr[RES_ROWS * RES_LANES / 64], s_br[RES_ROWS * RES_LANES / 64];
+  const int t = threadIdx.x, sub = t % RES_LANES;
+  const int i = blockIdx.x * RES_ROWS + t / RES_LANES;
+  double acc = 0.0;
   if (i < m) {
-    double acc = 0;
-    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += val[e] * x[col_idx[e]];
+    for (int e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += RES_LANES) acc += val[e] * x[col_idx[e]];
+  }
+#pragma unroll
+  for (int off = 1; off < RES_LANES; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  double rv = 0, bv = 0;
+  if (i < m && sub == 0) {
     bv = b[i];
     rv = bv - acc;
     r[i] = rv;
   }
-  const double rr = block_sum(rv * rv, sc);
-  const double br = block_sum(bv * rv, sc + 4);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = rr; part[2 * blockIdx.x + 1] = br; }
+  const double rr = wave_sum(rv * rv), br = wave_sum(bv * rv);
+  if ((t & 63) == 0) { s_rr[t >> 6] = rr; s_br[t >> 6] = br; }
+  __syncthreads();
+  if (t == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int q = 0; q < RES_ROWS * RES_LANES / 64; ++q) { a0 += s_rr[q]; a1 += s_br[q]; }
+    part[2 * blockIdx.x] = a0;
+    part[2 * blockIdx.x + 1] = a1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,7 +356,7 @@ hipError_t launch_residual(const MatView &A, const double *b, const double *x, d
     TLS_LAUNCH(PC_RESIDUAL, k_residual_dense, g, dim3(RD_ROWS * RD_WAVES), 0, st, A.m, A.n, A.ld, A.val, b,
                x, r, part);
   else
-    TLS_LAUNCH(PC_RESIDUAL, k_residual_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
+    TLS_LAUNCH(PC_RESIDUAL, k_residual_csr, g, dim3(RES_ROWS * RES_LANES), 0, st, A.m, A.row_ptr, A.col_idx, A.val, b, x,
                        r, part);
   return hipGetLastError();
 }

@@ -2281,6 +2281,16 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         return fail(TLS_ERR_NO_CONVERGENCE, "kmax = %d reached before the psi rule fired", kmax);
       return TLS_OK;
     };
+    // a solve on a low-precision factor that ends without convergence (kmax
+    // before the psi rule) under the gate: the factor could not separate
+    // sigma_{n+1} from its neighbours (the operator R^T R - sigma^2 I is off
+    // by about u_q in every direction, more than a narrow gap), so with
+    // allow_escalate the next precision solves again
+    auto settle = [&](tls_status s) -> tls_status {
+      if (s == TLS_ERR_NO_CONVERGENCE && o->gate_enforce && o->allow_escalate && P->storage != TLS_FP64)
+        return resolve();
+      return s;
+    };
     const tls_status bs = body();
     if (spec) {
       if (P->gate_pending) {
@@ -2306,11 +2316,11 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
         S = S_first;
         S.ls_refined = -refined;
         if (sigma) *sigma = S.sigma_final;
-        return bs;
+        return settle(bs);
       }
-      return b1;
+      return settle(b1);
     }
-    return bs;
+    return settle(bs);
   } catch (...) {
     return fail(TLS_ERR_ARG, "unexpected C++ exception");
   }
