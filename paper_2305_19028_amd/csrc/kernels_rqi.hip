@@ -371,13 +371,19 @@ __global__ __launch_bounds__(1024) void k_matvec_dense(int m, int n, int64_t ld,
   const double ax = dense_row_join(p, red);
   if (w == 0 && i < m) y[i] = ax;
 }
-__global__ void k_matvec_csr(int m, const int32_t *row_ptr, const int32_t *col_idx,
-                             const double *val, const double *x, double *y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double acc = 0;
-  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += val[e] * x[col_idx[e]];
-  y[i] = acc;
+// CSR: RES_LANES lanes per row, as in k_residual_csr
+__global__ __launch_bounds__(RES_ROWS * RES_LANES) void k_matvec_csr(int m, const int32_t *row_ptr,
+                                                                     const int32_t *col_idx, const double *val,
+                                                                     const double *x, double *y) {
+  const int t = threadIdx.x, sub = t % RES_LANES;
+  const int i = blockIdx.x * RES_ROWS + t / RES_LANES;
+  double acc = 0.0;
+  if (i < m) {
+    for (int e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += RES_LANES) acc += val[e] * x[col_idx[e]];
+  }
+#pragma unroll
+  for (int off = 1; off < RES_LANES; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (i < m && sub == 0) y[i] = acc;
 }
 // A^T x: one wave per column (dense) / per CSC column
 __global__ void k_rmatvec_dense(int m, int n, int64_t ld, const double *A, const double *x, double *y) {
@@ -410,7 +416,8 @@ hipError_t launch_matvec(const MatView &A, const double *x, double *y, hipStream
   if (A.format == TLS_DENSE_COLMAJOR)
     TLS_LAUNCH(PC_RESIDUAL, k_matvec_dense, g, dim3(RD_ROWS * RD_WAVES), 0, st, A.m, A.n, A.ld, A.val, x, y);
   else
-    TLS_LAUNCH(PC_RESIDUAL, k_matvec_csr, g, dim3(256), 0, st, A.m, A.row_ptr, A.col_idx, A.val, x, y);
+    TLS_LAUNCH(PC_RESIDUAL, k_matvec_csr, g, dim3(RES_ROWS * RES_LANES), 0, st, A.m, A.row_ptr, A.col_idx, A.val,
+               x, y);
   return hipGetLastError();
 }
 hipError_t launch_rmatvec(const MatView &A, const double *x, double *y, hipStream_t st) {
