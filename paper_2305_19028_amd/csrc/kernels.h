@@ -209,6 +209,13 @@ int gradient_rows_blocks(int n);
 hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
                                 double *f, double *part, const double *part_r, int nb_r, double cap,
                                 hipStream_t st, const double *ppart2 = nullptr);
+// the same with psi_k (launch_outer_psi's work) taken by the last of its
+// workgroups to finish; *cnt counts arrivals (zero before the first launch,
+// left at zero)
+hipError_t launch_gradient_rows_psi(const MatView &A, const double *ppart, const double *x, double *scal,
+                                    double *f, double *part, const double *part_r, int nb_r, double cap,
+                                    const double *ppart2, int *cnt, int k, double *rec, double *rhs,
+                                    double *xbest, double tie, hipStream_t st);
 // r <- r - sigma_0^2 t (t = A u_0, sigma_0^2 = scal[0]) with the residual partials
 hipError_t launch_shift_residual(int m, const double *b, double *r, const double *t, double *scal,
                                  double *part_r, hipStream_t st);
@@ -230,6 +237,10 @@ hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs,
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
                              const double *scal, double *xbest, double *xsnap, const int *done,
                              int nsteps, hipStream_t st);
+// the same on the PCGTLS state itself: omega and u are rows 0 and Np of w,
+// in the compute precision of the runs (no FP64 copy first)
+hipError_t launch_rqi_update_pcg(int n, double *x, int compute, const void *w, int Np, const double *f,
+                                 const double *scal, const int *done, int nsteps, hipStream_t st);
 hipError_t launch_axpy_init(int n, double *x, const double *u, const double *scal, int which,
                             hipStream_t st);
 hipError_t launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);

@@ -437,8 +437,9 @@ __device__ inline double sum_pairs(const double *part, int nb, int which, double
 // sigma^2 = rr / (1 + x^T x), the clamped shift mu and g = -b^T r + mu from the
 // residual partials (every workgroup of the gradient computes the same values
 // in the same order; workgroup 0 records them)
-__device__ inline double rq_scalars(int n, const double *x, const double *part_r, int nb_r,
-                                    double *scal, double cap, double *sc) {
+struct RqScalars { double sig2, mu, xx, br; };
+__device__ inline RqScalars rq_scalars(int n, const double *x, const double *part_r, int nb_r,
+                                       double *scal, double cap, double *sc) {
   double xx = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) xx += x[i] * x[i];
   xx = block_sum(xx, sc);
@@ -455,7 +456,7 @@ __device__ inline double rq_scalars(int n, const double *x, const double *part_r
     scal[S_G] = -br + mu;
     scal[S_CAP] = cap;
   }
-  return mu;
+  return RqScalars{sig2, mu, xx, br};
 }
 
 template <bool CSC>
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(256) void k_gradient(int m, int n, int64_t ld, cons
                                                   double cap) {
   __shared__ double sff[4], sfx[4];
   __shared__ double sc[8];
-  const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
+  const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc).mu;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + w;
   double fv = 0, xv = 0;
@@ -514,16 +515,19 @@ hipError_t launch_gradient(const MatView &A, const double *r, const double *x, d
   return hipGetLastError();
 }
 
+__device__ inline void psi_step(int n, const double *part_f, int nb_f, double *scal, int k, double *rec,
+                                const double *x, const double *f, double *rhs, double *xbest, double tie,
+                                RqScalars q, double *sc, int *s_best);
+
 // f = -A^T r - mu x from the row pass's partial A^T r (fixed order over its
 // workgroups), with per-block partials of f.f and f.x as k_gradient writes them
 // With ppart2 (the first step after a merged pass): A^T r = (sum of ppart)
 // - scal[S_SHIFT0] (sum of ppart2), i.e. A^T r_0 - sigma_0^2 A^T A u_0.
-__global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
-                                                       double *scal, double *f, double *part,
-                                                       const double *part_r, int nb_r, double cap,
-                                                       const double *ppart2) {
-  __shared__ double sc[8], sff[8], sq[256];
-  const double mu = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
+__device__ inline RqScalars gradient_rows_body(int n, int G, const double *ppart, const double *x,
+                                               double *scal, double *f, double *part,
+                                               const double *part_r, int nb_r, double cap,
+                                               const double *ppart2, double *sc, double *sff, double *sq) {
+  const RqScalars q = rq_scalars(n, x, part_r, nb_r, scal, cap, sc);
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   double atr = partials_sum64(n, G, ppart, j, sq);
   if (ppart2) {
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const doubl
   double fv = 0.0, xv = 0.0;
   if (threadIdx.x < 64 && j < n) {
     xv = x[j];
-    fv = -atr - mu * xv;
+    fv = -atr - q.mu * xv;
     f[j] = fv;
   }
   const double ff = block_sum(fv * fv, sff);
@@ -542,6 +546,37 @@ __global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const doubl
     part[2 * blockIdx.x] = ff;
     part[2 * blockIdx.x + 1] = fx;
   }
+  return q;
+}
+__global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
+                                                       double *scal, double *f, double *part,
+                                                       const double *part_r, int nb_r, double cap,
+                                                       const double *ppart2) {
+  __shared__ double sc[8], sff[8], sq[256];
+  (void)gradient_rows_body(n, G, ppart, x, scal, f, part, part_r, nb_r, cap, ppart2, sc, sff, sq);
+}
+// The same, with psi_k formed by the last workgroup to finish (the work of
+// k_outer_psi, without a launch of its own): every workgroup publishes its f
+// and partials with a release fence before it counts itself in *cnt; the
+// last one acquires them, resets the count and takes the step. Every
+// workgroup forms the Rayleigh-quotient scalars identically, so the last one
+// uses its own.
+__global__ __launch_bounds__(256) void k_gradient_rows_psi(int n, int G, const double *ppart, const double *x,
+                                                           double *scal, double *f, double *part,
+                                                           const double *part_r, int nb_r, double cap,
+                                                           const double *ppart2, int *cnt, int k, double *rec,
+                                                           double *rhs, double *xbest, double tie) {
+  __shared__ double sc[8], sff[8], sq[256];
+  __shared__ int s_last, s_best;
+  const RqScalars q = gradient_rows_body(n, G, ppart, x, scal, f, part, part_r, nb_r, cap, ppart2, sc, sff, sq);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(cnt, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x == 0) *cnt = 0;
+  psi_step(n, part, (int)gridDim.x, scal, k, rec, x, f, rhs, xbest, tie, q, sc, &s_best);
 }
 int gradient_rows_blocks(int n) { return (n + 63) / 64; }
 hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
@@ -549,6 +584,15 @@ hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const dou
                                 hipStream_t st, const double *ppart2) {
   TLS_LAUNCH(PC_GRADIENT, k_gradient_rows, dim3(gradient_rows_blocks(A.n)), dim3(256), 0, st, A.n,
              rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap, ppart2);
+  return hipGetLastError();
+}
+hipError_t launch_gradient_rows_psi(const MatView &A, const double *ppart, const double *x, double *scal,
+                                    double *f, double *part, const double *part_r, int nb_r, double cap,
+                                    const double *ppart2, int *cnt, int k, double *rec, double *rhs,
+                                    double *xbest, double tie, hipStream_t st) {
+  TLS_LAUNCH(PC_GRADIENT, k_gradient_rows_psi, dim3(gradient_rows_blocks(A.n)), dim3(256), 0, st, A.n,
+             rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap, ppart2, cnt, k, rec, rhs, xbest,
+             tie);
   return hipGetLastError();
 }
 
@@ -618,16 +662,13 @@ hipError_t launch_outer_rq(int n, const double *x, const double *part_r, int nb_
 // psi_k from the gradient partials; record (sigma, psi, mu); the returned
 // iterate: x_k is kept (copied to xbest) when psi_k is within the factor tie
 // of the smallest psi before it (k = 1 always); slot S_BEST holds that minimum
-__global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, int nb_f,
-                                                   double *scal, int k, double *rec,
-                                                   const double *x, const double *f, double *rhs,
-                                                   double *xbest, double tie) {
-  __shared__ double sc[8];
-  __shared__ int s_best;
+__device__ inline void psi_step(int n, const double *part_f, int nb_f, double *scal, int k, double *rec,
+                                const double *x, const double *f, double *rhs, double *xbest, double tie,
+                                RqScalars q, double *sc, int *s_best) {
   const double ff = sum_pairs(part_f, nb_f, 0, sc);
   const double fx = sum_pairs(part_f, nb_f, 1, sc + 4);
   if (threadIdx.x == 0) {
-    const double sig2 = scal[S_SIG2], mu = scal[S_MU], xx = scal[S_XX], br = scal[S_BR];
+    const double sig2 = q.sig2, mu = q.mu, xx = q.xx, br = q.br;
     const double dm = sig2 - mu;   // f at sigma^2 = f_mu - (sigma^2 - mu) x
     const double ffs = (dm == 0.0) ? ff : fmax(0.0, ff - 2.0 * dm * fx + dm * dm * xx);
     const double gs = -br + sig2;
@@ -644,16 +685,25 @@ __global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, 
     rec[4 * (k - 1) + 1] = psi;
     rec[4 * (k - 1) + 2] = mu;
     rec[4 * (k - 1) + 3] = isbest;
-    s_best = isbest;
+    *s_best = isbest;
   }
   __syncthreads();
   // the next PCGTLS right-hand sides [-f, x], and the best iterate so far
-  const bool keep = s_best && xbest;
+  const bool keep = *s_best && xbest;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double xi = x[i];
     if (rhs) { rhs[i] = -f[i]; rhs[n + i] = xi; }
     if (keep) xbest[i] = xi;
   }
+}
+__global__ __launch_bounds__(256) void k_outer_psi(int n, const double *part_f, int nb_f,
+                                                   double *scal, int k, double *rec,
+                                                   const double *x, const double *f, double *rhs,
+                                                   double *xbest, double tie) {
+  __shared__ double sc[8];
+  __shared__ int s_best;
+  const RqScalars q{scal[S_SIG2], scal[S_MU], scal[S_XX], scal[S_BR]};
+  psi_step(n, part_f, nb_f, scal, k, rec, x, f, rhs, xbest, tie, q, sc, &s_best);
 }
 hipError_t launch_outer_psi(int n, const double *x, const double *f, const double *part_f, int nb_f,
                             double *scal, int k, double *rec, double *rhs, double *xbest, double tie,
@@ -679,8 +729,11 @@ hipError_t launch_make_rhs(int n, const double *f, const double *x, double *rhs,
 // best iterate and an optional snapshot of x_k first. With done != NULL (the
 // step flags of the two PCGTLS runs just finished, nsteps of them launched)
 // it also records how many steps the longer run executed: a run's first
-// step flagged done is the one its exits skipped.
-__global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const double *wu,
+// step flagged done is the one its exits skipped. omega and u are read in
+// the precision PCGTLS kept them (rows 0 and ldw of wu), so no conversion
+// launch precedes the update.
+template <typename WT>
+__global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const WT *wu, int ldw,
                                                      const double *f, double *scal, double *xbest,
                                                      double *xsnap, const int *done, int nsteps) {
   __shared__ double sc[32];
@@ -690,7 +743,7 @@ __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const dou
     const double xv = x[i];
     if (xbest && isbest) xbest[i] = xv;
     if (xsnap) xsnap[i] = xv;
-    const double z = xv + wu[i];
+    const double z = xv + (double)wu[i];
     zf += z * f[i];
     zx += z * xv;
   }
@@ -704,8 +757,8 @@ __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const dou
   for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { tzf += sc[i]; tzx += sc[16 + i]; }
   const double beta = (tzf - scal[S_G]) / (tzx + 1.0);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double z = x[i] + wu[i];
-    x[i] = z + beta * wu[n + i];
+    const double z = x[i] + (double)wu[i];
+    x[i] = z + beta * (double)wu[ldw + i];
   }
   if (threadIdx.x == 0) {
     scal[S_ZF] = tzf; scal[S_ZX] = tzx; scal[S_BETA] = beta;
@@ -723,8 +776,18 @@ __global__ __launch_bounds__(1024) void k_rqi_update(int n, double *x, const dou
 hipError_t launch_rqi_update(int n, double *x, const double *omega_u, const double *f,
                              const double *scal, double *xbest, double *xsnap, const int *done,
                              int nsteps, hipStream_t st) {
-  TLS_LAUNCH(PC_SCALARS, k_rqi_update, dim3(1), dim3(1024), 0, st, n, x, omega_u, f, (double *)scal,
+  TLS_LAUNCH(PC_SCALARS, k_rqi_update<double>, dim3(1), dim3(1024), 0, st, n, x, omega_u, n, f, (double *)scal,
                      xbest, xsnap, done, nsteps);
+  return hipGetLastError();
+}
+hipError_t launch_rqi_update_pcg(int n, double *x, int compute, const void *w, int Np, const double *f,
+                                 const double *scal, const int *done, int nsteps, hipStream_t st) {
+  if (compute == TLS_FP64)
+    TLS_LAUNCH(PC_SCALARS, k_rqi_update<double>, dim3(1), dim3(1024), 0, st, n, x, (const double *)w, Np, f,
+               (double *)scal, (double *)nullptr, (double *)nullptr, done, nsteps);
+  else
+    TLS_LAUNCH(PC_SCALARS, k_rqi_update<float>, dim3(1), dim3(1024), 0, st, n, x, (const float *)w, Np, f,
+               (double *)scal, (double *)nullptr, (double *)nullptr, done, nsteps);
   return hipGetLastError();
 }
 

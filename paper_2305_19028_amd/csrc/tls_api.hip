@@ -417,7 +417,7 @@ tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, con
     HIPCHK(launch_precond(P, compute, 3 /* q = R^{-1} p */, nrhs, B, st));
     HIPCHK(launch_precond(P, compute, 4 /* R^{-T} q, s update */, nrhs, B, st));
   }
-  HIPCHK(launch_pcg_finish(compute, W.w, omega, (int)P->n, P->Np, nrhs, st));
+  if (omega) HIPCHK(launch_pcg_finish(compute, W.w, omega, (int)P->n, P->Np, nrhs, st));
   (void)N;
   return TLS_OK;
 }
@@ -1620,6 +1620,7 @@ struct RqiWs {
   double *r, *f, *xbest, *rhs, *wu, *t1, *t2, *part, *scal, *rec;
   double *ppart;                         // row-pass partials (dense A with a row-major copy)
   double *ppart2, *tu;                   // the merged first step: A^T A u_0 partials, A u_0
+  int *gcnt;                             // arrival count of the gradient's workgroups (psi in the last)
   double *rr, *rz, *rp, *rq, *rt, *rs;   // refinement PCG: residual, M r, direction, K p, A p, scalars
   PcgWs pcg;
 };
@@ -1651,6 +1652,7 @@ RqiWs carve_rqi(Carver &c, int format, int64_t m, int64_t n, const tls_precond_s
   W.ppart = P->at ? c.take<double>((size_t)rowpass_partials(V) * n) : nullptr;
   W.ppart2 = P->at ? c.take<double>((size_t)rowpass_partials(V) * n) : nullptr;
   W.tu = P->at ? c.take<double>((size_t)m) : nullptr;
+  W.gcnt = c.take<int>(64);
   return W;
 }
 
@@ -1829,6 +1831,7 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       F.add_i32(W.pcg.cnt, 0, P->N);
       F.add_f64(W.scal, 0.0, 48);
       F.add_i32(W.pcg.done, 0, 1);
+      F.add_i32(W.gcnt, 0, 1);
       HIPCHK(launch_fill_multi(F, st));
     }
     // finite b: the flag is read back with sigma_0 below (NaN or Inf on the
@@ -1850,13 +1853,14 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       return TLS_OK;
     };
     auto evaluate_at = [&](const double *xv, int k, double cap) -> tls_status {
-      if (V.at) {   // r and A^T r in one pass over the row-major copy
+      if (V.at) {   // r and A^T r in one pass over the row-major copy; psi in the gradient's last workgroup
         TRY(rowpass(b, xv, W.r, W.part));
-        HIPCHK(launch_gradient_rows(V, W.ppart, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
-      } else {
-        HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
-        HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
+        HIPCHK(launch_gradient_rows_psi(V, W.ppart, xv, W.scal, W.f, part_f, W.part, nb_r, cap, nullptr,
+                                        W.gcnt, k, W.rec, W.rhs, W.xbest, o->psi_tie, st));
+        return TLS_OK;
       }
+      HIPCHK(launch_residual(V, b, xv, W.r, W.part, st));
+      HIPCHK(launch_gradient(V, W.r, xv, W.scal, W.f, part_f, W.part, nb_r, cap, st));
       HIPCHK(launch_outer_psi(n, xv, W.f, part_f, nb_f, W.scal, k, W.rec, W.rhs, W.xbest, o->psi_tie, st));
       return TLS_OK;
     };
@@ -1883,8 +1887,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
     // already taken), then the gradient and psi as in evaluate_at
     auto evaluate_merged = [&](double cap) -> tls_status {
       HIPCHK(launch_shift_residual(m, b, W.r, W.tu, W.scal, W.part, st));
-      HIPCHK(launch_gradient_rows(V, W.ppart, x, W.scal, W.f, part_f, W.part, nb_r, cap, st, W.ppart2));
-      HIPCHK(launch_outer_psi(n, x, W.f, part_f, nb_f, W.scal, 1, W.rec, W.rhs, W.xbest, o->psi_tie, st));
+      HIPCHK(launch_gradient_rows_psi(V, W.ppart, x, W.scal, W.f, part_f, W.part, nb_r, cap, W.ppart2, W.gcnt,
+                                      1, W.rec, W.rhs, W.xbest, o->psi_tie, st));
       return TLS_OK;
     };
 
@@ -2110,8 +2114,8 @@ tls_status rqi_solve_from(const tls_matrix *A, const double *b, tls_precond P, c
       // [-f, x] were written by the psi kernel; then the RQI update of x,
       // which also records the steps the runs executed (scalar S_STEPS)
       auto inner = [&](int steps) -> tls_status {
-        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, W.wu, steps - 1, o->u_p, o->strict_pd, W.pcg, st));
-        HIPCHK(launch_rqi_update(n, x, W.wu, W.f, W.scal, nullptr, nullptr, W.pcg.done, steps, st));
+        TRY(pcg_run(P, W.scal + 1, 2, W.rhs, nullptr, steps - 1, o->u_p, o->strict_pd, W.pcg, st));
+        HIPCHK(launch_rqi_update_pcg(n, x, o->u_p, W.pcg.w, P->Np, W.f, W.scal, W.pcg.done, steps, st));
         return TLS_OK;
       };
       // Steps launched per run. A run that ends at its exits (Algorithm 3:
