@@ -329,12 +329,12 @@ CLASS_KERNELS = {
         "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
                  "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
                  "residual": ("void tls::k_resgrad_rows<64, double, false>", "kernels_rqi"),
-                 "gradient": ("tls::k_gradient_rows", "kernels_rqi"),
+                 "gradient": ("tls::k_gradient_rows_psi", "kernels_rqi"),
                  "gram": ("void tls::k_gram_mfma<double, double>", "kernels_factor")},
         "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
                   "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
                   "residual": ("void tls::k_resgrad_rows<64, double, false>", "kernels_rqi"),
-                  "gradient": ("tls::k_gradient_rows", "kernels_rqi"),
+                  "gradient": ("tls::k_gradient_rows_psi", "kernels_rqi"),
                   "gram": ("void tls::k_gram_mfma16<tls::bf16_t>", "kernels_factor")}},
     "sparse": {
         "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
