@@ -263,14 +263,20 @@ TLS_API size_t tls_factor_workspace_size(const tls_matrix *A, int32_t u_q);
  * the A-only constraints of Section 3.1 (verdict bits 1, 2, 4), and 6 steps
  * on R^{-T} A^T A R^{-1}, whose extreme Ritz values (quality_lo, quality_hi)
  * are the a-posteriori certificate of the factor read by tls_rqi_solve.
- * They run one after the other. With rep != NULL (host) the call waits for both
+ * The estimates run on a library side stream; the certificate runs beside
+ * them on a second one (CSR) or rides on the solve's passes over the row
+ * copy (dense, n <= 4096). With rep != NULL (host) the call waits for both
  * and fills *rep. With rep == NULL it returns while they may still run:
  * tls_rqi_solve then overlaps them with its iterations, and
  * tls_precond_info (with a report requested), tls_rqi_solve and
  * tls_precond_destroy wait for them; A and ws must stay valid until then.
  * allow_escalate applies to Cholesky breakdown (TLS_ERR_NOT_SPD): after the
  * diagonal shifts 2^j n u_q (j = 0, 1, 2) the factor is recomputed in the
- * next higher precision. On success *out (host) receives a handle to
+ * next higher precision. A dense A with n <= 4096 also gets a row-major
+ * FP64 copy in ws (read by every pass of the solve), made on the second
+ * side stream beside the tail of the Cholesky chain; the call's stream
+ * waits for it before the factorization's status is read, so it is
+ * complete when the call returns. On success *out (host) receives a handle to
  * destroy with tls_precond_destroy. ws must hold
  * tls_factor_workspace_size() bytes. */
 TLS_API tls_status tls_factor_precond(const tls_matrix *A, int32_t u_q, int32_t scaling,
