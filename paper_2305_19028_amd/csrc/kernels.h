@@ -204,14 +204,11 @@ hipError_t launch_rowpass_dual(const MatView &A, const double *b, const double *
 hipError_t launch_rowpass_sum(const MatView &A, const double *ppart, double s, double *y, hipStream_t st);
 // f = -A^T r - mu x from the partials (gradient_rows_blocks(n) partial pairs)
 int gradient_rows_blocks(int n);
-// ppart2 (optional): A^T r = sum(ppart) - sigma_0^2 sum(ppart2), sigma_0^2 as
-// launch_shift_residual kept it
-hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
-                                double *f, double *part, const double *part_r, int nb_r, double cap,
-                                hipStream_t st, const double *ppart2 = nullptr);
-// the same with psi_k (launch_outer_psi's work) taken by the last of its
-// workgroups to finish; *cnt counts arrivals (zero before the first launch,
-// left at zero)
+// f = -A^T r - mu x from the row pass's partials with psi_k (launch_outer_psi's
+// work) taken by the last of its workgroups to finish; ppart2 (optional):
+// A^T r = sum(ppart) - sigma_0^2 sum(ppart2), sigma_0^2 as
+// launch_shift_residual kept it; *cnt counts arrivals (zero before the first
+// launch, left at zero)
 hipError_t launch_gradient_rows_psi(const MatView &A, const double *ppart, const double *x, double *scal,
                                     double *f, double *part, const double *part_r, int nb_r, double cap,
                                     const double *ppart2, int *cnt, int k, double *rec, double *rhs,

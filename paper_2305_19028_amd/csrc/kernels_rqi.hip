@@ -548,14 +548,7 @@ __device__ inline RqScalars gradient_rows_body(int n, int G, const double *ppart
   }
   return q;
 }
-__global__ __launch_bounds__(256) void k_gradient_rows(int n, int G, const double *ppart, const double *x,
-                                                       double *scal, double *f, double *part,
-                                                       const double *part_r, int nb_r, double cap,
-                                                       const double *ppart2) {
-  __shared__ double sc[8], sff[8], sq[256];
-  (void)gradient_rows_body(n, G, ppart, x, scal, f, part, part_r, nb_r, cap, ppart2, sc, sff, sq);
-}
-// The same, with psi_k formed by the last workgroup to finish (the work of
+// The gradient with psi_k formed by the last workgroup to finish (the work of
 // k_outer_psi, without a launch of its own): every workgroup publishes its f
 // and partials with a release fence before it counts itself in *cnt; the
 // last one acquires them, resets the count and takes the step. Every
@@ -579,13 +572,6 @@ __global__ __launch_bounds__(256) void k_gradient_rows_psi(int n, int G, const d
   psi_step(n, part, (int)gridDim.x, scal, k, rec, x, f, rhs, xbest, tie, q, sc, &s_best);
 }
 int gradient_rows_blocks(int n) { return (n + 63) / 64; }
-hipError_t launch_gradient_rows(const MatView &A, const double *ppart, const double *x, double *scal,
-                                double *f, double *part, const double *part_r, int nb_r, double cap,
-                                hipStream_t st, const double *ppart2) {
-  TLS_LAUNCH(PC_GRADIENT, k_gradient_rows, dim3(gradient_rows_blocks(A.n)), dim3(256), 0, st, A.n,
-             rowpass_partials(A), ppart, x, scal, f, part, part_r, nb_r, cap, ppart2);
-  return hipGetLastError();
-}
 hipError_t launch_gradient_rows_psi(const MatView &A, const double *ppart, const double *x, double *scal,
                                     double *f, double *part, const double *part_r, int nb_r, double cap,
                                     const double *ppart2, int *cnt, int k, double *rec, double *rhs,
