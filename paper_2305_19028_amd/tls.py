@@ -247,14 +247,18 @@ def dense(A, device="cuda") -> Matrix:
     return Matrix(c, (At,), m, n, DENSE)
 
 
-def dense_t(At) -> Matrix:
-    """A dense m x n matrix given as its transpose At (an n x m row-major
-    float64 device tensor, i.e. A column-major with ld = m); no copy."""
+def dense_t(At, m=None) -> Matrix:
+    """A dense m x n matrix given as its transpose At (an n x ld row-major
+    float64 device tensor, i.e. A column-major with leading dimension ld);
+    m (default ld) rows of each column are A's, the rest padding; no copy."""
     torch = _torch()
     if not (isinstance(At, torch.Tensor) and At.is_cuda and At.dtype == torch.float64 and At.is_contiguous()):
         raise TypeError("dense_t needs a contiguous float64 device tensor")
-    n, m = At.shape
-    c = c_matrix(DENSE, 0, m, n, m, 0, At.data_ptr(), None, None)
+    n, ld = At.shape
+    m = ld if m is None else int(m)
+    if not 0 < m <= ld:
+        raise ValueError("need 0 < m <= ld")
+    c = c_matrix(DENSE, 0, m, n, ld, 0, At.data_ptr(), None, None)
     return Matrix(c, (At,), m, n, DENSE)
 
 

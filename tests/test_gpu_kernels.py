@@ -220,6 +220,38 @@ def test_pcg_eta_underflow_ends_cleanly(mode):
         assert np.all(np.isnan(tr["alpha"][r]))
 
 
+@pytest.mark.parametrize("u_q", ["fp64", "bf16"])
+def test_tall_dense_column_norms(u_q):
+    """A dense A taller than 64 slabs of 2048 rows (140001 rows: the norm
+    pass's slab sums are reduced in two levels, the last slab ragged), with
+    leading dimension > m: the scaling d matches the column norms to 1e-14,
+    the FP64 factor the LAPACK Cholesky of the scaled Gram matrix, and a NaN
+    in the padding rows between columns (not part of A) is ignored while one
+    inside A is reported."""
+    tls = _tls()
+    import torch
+    m, n, ld = 140001, 40, 140003
+    print(f"tall dense {u_q}", flush=True)
+    A, _, _ = tlsgen.dense_gaussian(m, n, seed=17)
+    A = A * np.exp(np.random.default_rng(2).uniform(-2, 2, n))
+    buf = np.full((n, ld), np.nan)            # column-major with NaN padding rows
+    buf[:, :m] = A.T
+    dev = torch.from_numpy(buf).cuda()
+    Ad = tls.dense_t(dev, m)
+    P, _ = tls.tls_factor_precond(Ad, u_q)
+    Rh, d = tls.tls_precond_export(P)
+    dref = np.linalg.norm(A, axis=0)
+    assert np.allclose(d, dref, rtol=1e-14, atol=0)
+    if u_q == "fp64":
+        H = (A / dref).T @ (A / dref)
+        assert np.max(np.abs(Rh - sla.cholesky(H, lower=False))) < 1e-11
+    buf[5, 1000] = np.nan                     # inside A: column 5, row 1000
+    dev2 = torch.from_numpy(buf).cuda()
+    with pytest.raises(tls.TLSError) as e:
+        tls.tls_factor_precond(tls.dense_t(dev2, m), u_q)
+    assert e.value.status == -9
+
+
 @pytest.mark.parametrize("case", ["dense_small", "dense_ragged", "sparse"])
 @pytest.mark.parametrize("u_q", ["fp64"])
 def test_factor_matches_cholesky(case, u_q):
