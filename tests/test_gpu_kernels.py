@@ -225,14 +225,15 @@ def test_tall_dense_column_norms(u_q):
     """A dense A taller than 64 slabs of 2048 rows (140001 rows: the norm
     pass's slab sums are reduced in two levels, the last slab ragged), with
     leading dimension > m: the scaling d matches the column norms to 1e-14,
-    the FP64 factor the LAPACK Cholesky of the scaled Gram matrix, and a NaN
-    in the padding rows between columns (not part of A) is ignored while one
-    inside A is reported."""
+    the FP64 factor the LAPACK Cholesky of the scaled Gram matrix, the solve
+    (over the row-major copy made from the padded buffer) the SVD answer to
+    1e-10, and a NaN in the padding rows between columns (not part of A) is
+    ignored while one inside A is reported."""
     tls = _tls()
     import torch
     m, n, ld = 140001, 40, 140003
     print(f"tall dense {u_q}", flush=True)
-    A, _, _ = tlsgen.dense_gaussian(m, n, seed=17)
+    A, b, _ = tlsgen.dense_gaussian(m, n, seed=17)
     A = A * np.exp(np.random.default_rng(2).uniform(-2, 2, n))
     buf = np.full((n, ld), np.nan)            # column-major with NaN padding rows
     buf[:, :m] = A.T
@@ -245,6 +246,16 @@ def test_tall_dense_column_norms(u_q):
     if u_q == "fp64":
         H = (A / dref).T @ (A / dref)
         assert np.max(np.abs(Rh - sla.cholesky(H, lower=False))) < 1e-11
+    # the solve reads the row-major copy made from the padded buffer
+    from oracle import exact
+    ref = exact.svd_tls(A, b)
+    opts = tls.default_opts(stop_patience=2) if u_q == "fp64" else \
+        tls.default_opts(u_p="fp32", gate_enforce=1, allow_escalate=1, stop_patience=2, refine_sweeps=1)
+    x, sigma, st = tls.tls_rqi_solve(Ad, b, P, opts)
+    es = abs(sigma - ref.sigma) / ref.sigma
+    ex = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    print(f"solve: sigma {es:.2e} x {ex:.2e} iters {st['iters']}", flush=True)
+    assert es < 1e-10 and ex < 1e-10
     buf[5, 1000] = np.nan                     # inside A: column 5, row 1000
     dev2 = torch.from_numpy(buf).cuda()
     with pytest.raises(tls.TLSError) as e:
