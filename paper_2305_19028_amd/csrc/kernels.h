@@ -56,6 +56,7 @@ struct SolveBufs {
   int ldi = 0, ldo = 0;   // stride between right-hand sides of in/out (0: n)
   void *cpart;   // chunk partials of the inverse-apply kernels
   int *cnt;      // per-block arrival counters (zero between launches)
+  int clear_flags = 0;   // the PCG init launch of the X application also clears done, neg and trace
 };
 
 // ---- kernels_trsv.hip ------------------------------------------------------

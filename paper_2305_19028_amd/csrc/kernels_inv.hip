@@ -317,6 +317,7 @@ struct XParams {
   C *cpart;             // [N][CH][NR][64]
   int *cnt;             // [N]
   int *status;
+  int clear_flags;      // XF0: clear done, neg (0) and trace (NaN) for the run
 };
 
 template <typename C>
@@ -356,6 +357,15 @@ __global__ __launch_bounds__(ROW ? 64 * XW : 64 * XS) void k_xapply(XParams<SX, 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int N = P.N, Np = P.Np;
   const int I = blockIdx.x, sidx = ROW ? 0 : blockIdx.y, CH = ROW ? 1 : gridDim.y;
+  if constexpr (MODE == XF0) {
+    // the run's step flags and trace start cleared (no step of this launch
+    // reads them; the steps that do come after it on the stream)
+    if (P.clear_flags && I == 0 && sidx == 0) {
+      const int L2 = P.L + 2;
+      for (int t = threadIdx.x; t < L2 * NR; t += blockDim.x) { P.done[t] = 0; P.neg[t] = 0; }
+      for (int t = threadIdx.x; t < NR * 4 * L2; t += blockDim.x) P.trace[t] = __longlong_as_double(0x7ff8000000000000ll);
+    }
+  }
   // pbuf of the current p (step j) and of the previous one
   C *p_cur = (P.j & 1) ? P.pb1 : P.pb0;
   C *p_old = (P.j & 1) ? P.pb0 : P.pb1;
@@ -696,6 +706,7 @@ static hipError_t x_dispatch(const FactorView &F, int mode, int trans, int nrhs,
     P.cpart = (C *)B.cpart;
     P.cnt = B.cnt;
     P.status = B.sync + F.N + 3;
+    P.clear_flags = B.clear_flags;
     const int CH = F.xrow ? 0 : (F.N + P.chunk - 1) / P.chunk;
     return x_mode<SX, C>(mode, trans, nrhs, P, CH, st);
   };

@@ -399,7 +399,10 @@ tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, con
                    double *omega, int l, int compute, int strict, PcgWs &W, hipStream_t st) {
   if (l + 1 > W.L + 1) return fail(TLS_ERR_WORKSPACE, "PCG workspace sized for l <= %d", W.L);
   const int N = P->N;
-  {
+  // the X application's init launch clears the run's flags itself; the
+  // triangular-solve route takes a fill launch first
+  const bool xclear = P->apply_mode != 1 && P->xr;
+  if (!xclear) {
     FillSet F;
     F.add_i32(W.done, 0, (size_t)(W.L + 2) * nrhs);
     F.add_i32(W.neg, 0, (size_t)(W.L + 2) * nrhs);
@@ -411,7 +414,9 @@ tls_status pcg_run(const tls_precond_s *P, const double *sig2_dev, int nrhs, con
   B.strict = strict;
   B.in = rhs;
   B.j = 0;
+  B.clear_flags = xclear ? 1 : 0;
   HIPCHK(launch_precond(P, compute, 2 /* init: s_0 = R^{-T} f */, nrhs, B, st));
+  B.clear_flags = 0;
   for (int j = 0; j <= l; ++j) {
     B.j = j;
     HIPCHK(launch_precond(P, compute, 3 /* q = R^{-1} p */, nrhs, B, st));
