@@ -340,11 +340,13 @@ CLASS_KERNELS = {
         "fp64": {"chol_panel": ("void tls::k_chol_step<double, true>", "kernels_factor"),
                  "pcg_step": ("void tls::k_xapply<double, double, 2, 3, 0, 0>", "kernels_inv"),
                  "residual": ("tls::k_residual_csr", "kernels_rqi"),
-                 "gradient": ("void tls::k_gradient<true>", "kernels_rqi")},
+                 "gradient": ("void tls::k_gradient<true>", "kernels_rqi"),
+                 "gram": ("void tls::k_gram_sparse<double>", "kernels_factor")},
         "mixed": {"chol_panel": ("void tls::k_chol_step<float, true>", "kernels_factor"),
                   "pcg_step": ("void tls::k_xapply<float, float, 2, 3, 0, 0>", "kernels_inv"),
                   "residual": ("tls::k_residual_csr", "kernels_rqi"),
-                  "gradient": ("void tls::k_gradient<true>", "kernels_rqi")}},
+                  "gradient": ("void tls::k_gradient<true>", "kernels_rqi"),
+                  "gram": ("void tls::k_gram_sparse<float>", "kernels_factor")}},
 }
 TRAFFIC_FILES = {"sparse_20000x2000": "sparse_20000x2000_hbm_traffic.md",
                  "dense_65536x4096": "dense_65536x4096_hbm_traffic.md"}

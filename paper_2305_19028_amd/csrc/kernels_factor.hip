@@ -453,7 +453,7 @@ __global__ void k_colnorms_dense(int m, int n, int64_t ld, const double *A, doub
 // beside the factorization's narrow launches and must leave them CUs and
 // LDS, which a grid of one workgroup per tile, queued behind each other,
 // would not.
-constexpr int ROWCOPY_WGS = 512;
+constexpr int ROWCOPY_WGS = 256;
 __global__ __launch_bounds__(256) void k_rowcopy_dense(int m, int n, int64_t ld, const double *A, int64_t ldr,
                                                        double *At) {
   __shared__ double tile[64][65];
@@ -1939,8 +1939,12 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_step(int k, int N, int Np
   }
 }
 
-// launches with at most this many workgroups leave most of the chip free
-constexpr int CHOL_NARROW_GRID = 256;
+// the row copy starts beside the first Cholesky launch of at most this many
+// workgroups: on 4096 columns that is the last 32 of 64 block rows, whose
+// launches are bound by the panel's latency, not by the update's tiles;
+// starting it beside wider launches slows their updates, later leaves the
+// copy running when the factor is done
+constexpr int CHOL_NARROW_GRID = 528;
 template <typename C>
 static hipError_t cholesky_t(int N, int Np, C *G, C *rdiag, int *info, hipStream_t st, hipEvent_t narrow) {
   TLS_LAUNCH(PC_CHOL_PANEL, (k_chol_step<C, false>), dim3(N), dim3(CHOL_THREADS), 0, st, 0, N, Np, G, rdiag,

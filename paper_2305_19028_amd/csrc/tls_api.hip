@@ -1177,10 +1177,10 @@ tls_status factor_qr_once(const tls_matrix *A, tls_precond_s *P, FactorWs &W, in
 // kernels; after a breakdown they are drained and started again with the
 // next attempt
 // The row-major copy of a dense A (read by every pass of the solve, not by
-// the factorization) is made once, on side2, beside the narrow tail of the
-// Cholesky chain and the inverse: launches of few workgroups that leave HBM
-// and most CUs idle (beside the wide early launches it would slow the
-// chain's trailing updates). The caller's stream waits for it before the
+// the factorization) is made once, on side2, beside the second half of the
+// Cholesky chain and the inverse: launches bound by the panel's latency,
+// which leave HBM and most CUs idle (beside the wide early launches it would
+// slow the chain's trailing updates). The caller's stream waits for it before the
 // factorization's status is read, so the call returns with the copy made.
 // The fork event was recorded on st by launch_cholesky.
 tls_status start_rowcopy(tls_precond_s *P) {
