@@ -127,8 +127,10 @@ hipError_t launch_gram_sparse(int m, int n, int Np, const int32_t *row_ptr, cons
                               const void *valq, const int32_t *col_ptr, const int32_t *row_idx,
                               const void *cvalq, int compute, void *G, hipStream_t st);
 size_t gram_cast_bytes(int64_t m, int64_t n);
+// FP64 partial tiles of the FP64 / FP32 Gram's row segments (0: one segment)
+size_t gram_part64_bytes(int64_t m, int64_t n);
 hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
-                            int scaled, int q, void *cast, void *G, hipStream_t st);
+                            int scaled, int q, void *cast, void *G, void *gpart, hipStream_t st);
 hipError_t launch_gram_dense(int m, int n, int Np, int64_t ld, const double *A, const double *d,
                              int scaled, int q, int compute, void *G, hipStream_t st);
 hipError_t launch_gram_pad(int n, int Np, int compute, void *G, hipStream_t st);

@@ -848,15 +848,22 @@ __global__ __launch_bounds__(256) void k_cast_dense(int m, int n, int64_t ld, co
 }
 
 
+// Grid: (segment, tile) jobs, tile l = J (J + 1) / 2 + I of the upper 128 x
+// 128 tiles, rows [seg seglen, (seg + 1) seglen) of A. One segment: the
+// tile goes to G. Several: the workgroup writes its unscaled FP64 sums to
+// part (tile-major, 128 x 128 per job, column c - c0 at stride 128) and
+// k_gram_reduce64 adds the segments in order.
 template <typename T, typename C>
 __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, const T *A, int Np, C *G,
-                                                   const double *d, int scaled) {
+                                                   const double *d, int scaled, int seglen, int nseg,
+                                                   double *part) {
   constexpr bool F64 = std::is_same<T, double>::value;
   constexpr int PADE = 16 / (int)sizeof(T);
   constexpr int RL = GKC + PADE;                     // LDS row length (elements)
   __shared__ __attribute__((aligned(16))) T Ps[GT][RL];   // output-column panel (J)
   __shared__ __attribute__((aligned(16))) T Qs[GT][RL];   // output-row panel (I)
-  const int l = blockIdx.x;
+  const int ntl = (int)gridDim.x / nseg;
+  const int l = (int)blockIdx.x % ntl, seg = (int)blockIdx.x / ntl;
   int J = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
   while ((J + 1) * (J + 2) / 2 <= l) ++J;
   while (J * (J + 1) / 2 > l) --J;
@@ -950,10 +957,12 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
           }
     }
   };
-  const int kend = F64 ? m : ((m + GKC - 1) / GKC) * GKC;
+  // segments are whole GKC-row chunks, so only the last one can be ragged
+  const int kall = F64 ? m : ((m + GKC - 1) / GKC) * GKC;
+  const int kbeg = seg * seglen, kend = min(kall, kbeg + seglen);
   int chunk = 0;
-  fetch(0);
-  for (int k0 = 0; k0 < kend; k0 += GKC) {
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GKC) {
     if (++chunk == FLUSH) { flush(); chunk = 0; }
     __syncthreads();                 // previous chunk fully consumed
     stage();
@@ -1002,7 +1011,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
         for (int q = 0; q < 4; ++q) {
           const int c = c0 + wc * 64 + t * 16 + 4 * q + (lane >> 4);
           const int r = r0 + wr * 64 + u * 16 + (lane & 15);
-          if (r <= c && c < Np) {
+          if (nseg > 1) {
+            part[(size_t)blockIdx.x * GT * GT + (size_t)(c - c0) * GT + (r - r0)] = acc64[t][u][q];
+          } else if (r <= c && c < Np) {
             // FP64 reads A unscaled: H = D^{-1} (A^T A) D^{-1} on output
             double v = acc64[t][u][q];
             if (scaled && c < n) v *= (1.0 / d[r]) * (1.0 / d[c]);
@@ -1019,7 +1030,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int m, int n, int64_t ld, con
         for (int q = 0; q < 16; ++q) {
           const int c = c0 + wc * 64 + t * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
           const int r = r0 + wr * 64 + u * 32 + (lane & 31);
-          if (r <= c && c < Np) G[(size_t)c * Np + r] = (C)sum64[t][u][q];
+          if (nseg > 1) part[(size_t)blockIdx.x * GT * GT + (size_t)(c - c0) * GT + (r - r0)] = sum64[t][u][q];
+          else if (r <= c && c < Np) G[(size_t)c * Np + r] = (C)sum64[t][u][q];
         }
   }
 }
@@ -1495,6 +1507,63 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const float *part, int nseg
   }
 }
 
+// the FP64 / FP32 Gram's segments: FP64 partial tiles, added in segment
+// order; the FP64 input's scaling H = D^{-1} (A^T A) D^{-1} is applied here
+template <typename C>
+__global__ __launch_bounds__(256) void k_gram_reduce64(const double *part, int nseg, int NT, int n, int Np, C *G,
+                                                       const double *d, int scaled) {
+  const int l = blockIdx.x, ntiles = NT * (NT + 1) / 2;
+  int I, J;
+  gram_tile_of(l, I, J);
+  const size_t sstride = (size_t)ntiles * GT * GT;
+  const double *base = part + (size_t)l * GT * GT;
+  const int e0 = blockIdx.y * (GT * GT / 4);
+  for (int e = e0 + threadIdx.x; e < e0 + GT * GT / 4; e += 256) {
+    double v = 0.0;
+    for (int k = 0; k < nseg; ++k) v += base[(size_t)k * sstride + e];
+    const int c = J * GT + e / GT, r = I * GT + e % GT;
+    if (r <= c && c < Np) {
+      if (scaled && c < n) v *= (1.0 / d[r]) * (1.0 / d[c]);
+      G[(size_t)c * Np + r] = (C)v;
+    }
+  }
+}
+
+// The FP64 / FP32 kernel holds two workgroups per CU (about 200 VGPRs per
+// wave, 70 KB of LDS): with one workgroup per 128 x 128 tile over all m rows,
+// 528 tiles (n = 4096) fill 512 slots once and then 16 of them, and 36 tiles
+// (n = 1024) hold a seventh of the chip. The rows are cut into segments
+// (whole 64-row multiples, at least 1024 rows) so that the jobs fill whole
+// rounds of the slots, within a budget for the partial tiles.
+constexpr size_t GRAM64_PART_BYTES = 640ull << 20;
+static int gram64_seg_cap(int64_t m, int64_t n) {
+  const int64_t NT = (n + GT - 1) / GT;
+  const size_t per = (size_t)(NT * (NT + 1) / 2) * GT * GT * 8;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)(GRAM64_PART_BYTES / per), gram_max_segments(m)));
+}
+size_t gram_part64_bytes(int64_t m, int64_t n) {
+  const int cap = gram64_seg_cap(m, n);
+  const int64_t NT = (n + GT - 1) / GT;
+  return cap > 1 ? (size_t)cap * (NT * (NT + 1) / 2) * GT * GT * 8 : 0;
+}
+struct Gram64Plan { int nseg, seglen; };
+static Gram64Plan gram64_plan(int64_t m, int64_t n, int cus, bool have_part) {
+  const int64_t kall = ((m + GKC - 1) / GKC) * GKC;
+  const int64_t NT = (n + GT - 1) / GT, ntiles = NT * (NT + 1) / 2, slots = 2 * (int64_t)cus;
+  Gram64Plan best{1, (int)kall};
+  if (!have_part) return best;
+  int64_t best_cost = LLONG_MAX;
+  const int cap = gram64_seg_cap(m, n);
+  for (int ns = 1; ns <= cap; ++ns) {
+    const int64_t len = ((kall + ns - 1) / ns + 63) / 64 * 64;
+    if (ns > 1 && len < 1024) break;
+    if ((kall + len - 1) / len != ns) continue;
+    const int64_t cost = (ntiles * ns + slots - 1) / slots * len;
+    if (cost < best_cost) { best_cost = cost; best.nseg = ns; best.seglen = (int)len; }
+  }
+  return best;
+}
+
 size_t gram_cast_bytes(int64_t m, int64_t n) {
   const int64_t NT = (n + GT - 1) / GT;
   // the cast (room for the widest low-precision input, FP32) and the
@@ -1503,12 +1572,18 @@ size_t gram_cast_bytes(int64_t m, int64_t n) {
 }
 
 hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, const double *d,
-                            int scaled, int q, void *cast, void *G, hipStream_t st) {
+                            int scaled, int q, void *cast, void *G, void *gpart, hipStream_t st) {
   const int NT = (n + GT - 1) / GT;
-  const dim3 g((unsigned)(NT * (NT + 1) / 2));
+  const Gram64Plan g64 = gram64_plan(m, n, device_cus(), gpart != nullptr);
+  const dim3 g((unsigned)(NT * (NT + 1) / 2 * g64.nseg));
+  const dim3 gr((unsigned)(NT * (NT + 1) / 2), 4);
+  double *p64 = (double *)gpart;
   if (q == TLS_FP64) {
     TLS_LAUNCH(PC_GRAM, (k_gram_mfma<double, double>), g, dim3(256), 0, st, m, n, ld, A, Np, (double *)G,
-               d, scaled);
+               d, scaled, g64.seglen, g64.nseg, p64);
+    if (g64.nseg > 1)
+      TLS_LAUNCH(PC_GRAM, k_gram_reduce64<double>, gr, dim3(256), 0, st, p64, g64.nseg, NT, n, Np, (double *)G,
+                 d, scaled);
     return hipGetLastError();
   }
   const int mp = (int)gram_rows_padded(m);
@@ -1524,7 +1599,10 @@ hipError_t launch_gram_mfma(int m, int n, int Np, int64_t ld, const double *A, c
     case TLS_FP32:
       TLS_LAUNCH(PC_GRAM, k_cast_dense<float>, gc, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, (float *)cast);
       TLS_LAUNCH(PC_GRAM, (k_gram_mfma<float, float>), g, dim3(256), 0, st, m, n, (int64_t)mp,
-                 (const float *)cast, Np, (float *)G, d, 0);
+                 (const float *)cast, Np, (float *)G, d, 0, g64.seglen, g64.nseg, p64);
+      if (g64.nseg > 1)
+        TLS_LAUNCH(PC_GRAM, k_gram_reduce64<float>, gr, dim3(256), 0, st, p64, g64.nseg, NT, n, Np, (float *)G,
+                   d, 0);
       break;
     case TLS_FP16:
       TLS_LAUNCH(PC_GRAM, (k_cast16<half_t, false>), g8, dim3(256), 0, st, m, n, ld, A, d, scaled, mp, n128,

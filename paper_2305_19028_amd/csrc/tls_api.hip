@@ -225,6 +225,7 @@ struct FactorWs {
   int *cnt;        // per-block arrival counters of internal applies
   double *tm;      // m-vector (products with A in the certificate)
   void *cast;      // dense A rounded to u_q (matrix-core Gram input), or NULL
+  void *gpart;     // FP64 partial tiles of the FP64 / FP32 Gram's row segments, or NULL
   void *qrw;       // Householder QR working matrix and reflector scratch, or NULL
   // the certificate's own buffers (it runs concurrently with the estimates)
   int *qsync, *qcnt;
@@ -290,6 +291,10 @@ FactorWs carve_factor(Carver &c, int64_t m, int64_t n, int64_t nnz, int format, 
   W.qlzs = c.take<double>(2 * QUALITY_STEPS + 8);
   // low-precision copy of a dense A for the matrix-core Gram
   W.cast = (cast && format == TLS_DENSE_COLMAJOR) ? c.take<char>(gram_cast_bytes(m, n)) : nullptr;
+  {
+    const size_t gp = format == TLS_DENSE_COLMAJOR ? gram_part64_bytes(m, n) : 0;
+    W.gpart = gp ? c.take<char>(gp) : nullptr;
+  }
   W.qrw = qr ? c.take<char>(qr_work_bytes(m, (int)n)) : nullptr;
   W.at = W.colsq = W.qppart = nullptr;
   W.ldr = 0;
@@ -625,7 +630,7 @@ tls_status form_gram(const tls_matrix *A, tls_precond_s *P, FactorWs &W, int uq,
   } else {
     if (uq != TLS_FP64 && !W.cast)
       return fail(TLS_ERR_WORKSPACE, "factor workspace sized for FP64 cannot hold a u_q = %d cast of A", uq);
-    HIPCHK(launch_gram_mfma((int)A->m, n, Np, A->ld, A->val, W.d, P->scaled, uq, W.cast, W.G, st));
+    HIPCHK(launch_gram_mfma((int)A->m, n, Np, A->ld, A->val, W.d, P->scaled, uq, W.cast, W.G, W.gpart, st));
   }
   HIPCHK(launch_gram_pad(n, Np, compute, W.G, st));
   return TLS_OK;
