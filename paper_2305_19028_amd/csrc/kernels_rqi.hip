@@ -249,6 +249,109 @@ __global__ __launch_bounds__(RR_WAVES * 64) void k_resgrad_rows(int m, int n, in
   }
 }
 
+// The DUAL pass over a 4096-column copy. One wave per row would hold the
+// row (64 values per lane) and both accumulators (A^T r and A^T A v, 64
+// each): more than a wave's 256 VGPRs, so the compiler parks values in AGPRs
+// and the pass runs about 20 % slower than the plain one. Here two waves
+// share a row, wave h of a pair holding columns 2048 h + lane + 64 t
+// (t < 32): 32 values and 2 x 32 accumulators per lane, two waves per SIMD.
+// The pair's partial dot products meet in a double-buffered LDS slot, one
+// barrier per row step (every wave runs the same number of steps, past the
+// last row with zeros). Rows, partial layout and join order are those of
+// k_resgrad_rows: pair p takes rows 16 p .. 16 p + 15 of each 64-row group.
+constexpr int R2_WAVES = 8, R2_TH = 32;
+__global__ __launch_bounds__(R2_WAVES * 64) void k_resgrad_rows_dual64(int m, int n, int64_t ldr, const double *At,
+                                                                       const double *b, const double *x, double *r,
+                                                                       double *part_r, int groups, double *ppart,
+                                                                       const double *v2, double *ppart2,
+                                                                       double *t_out) {
+  __shared__ double sx[64 * 64], sv[64 * 64], sp[64 * 64];
+  __shared__ double sd[2][RR_WAVES][2][2];   // [buffer][pair][half][x, v]
+  __shared__ double srr[RR_WAVES][RR_MAXG], sbr[RR_WAVES][RR_MAXG];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, pair = w >> 1, h = w & 1;
+  for (int j = threadIdx.x; j < 64 * 64; j += R2_WAVES * 64) {
+    sx[j] = (x && j < n) ? x[j] : 0.0;
+    sv[j] = j < n ? v2[j] : 0.0;
+  }
+  __syncthreads();
+  const int c0 = 2048 * h + lane;          // this lane's first column
+  double pr[R2_TH], pq[R2_TH];
+#pragma unroll
+  for (int t = 0; t < R2_TH; ++t) { pr[t] = 0.0; pq[t] = 0.0; }
+  const int g0 = blockIdx.x * groups;
+  int step = 0;
+  for (int q = 0; q < groups; ++q) {
+    double rr = 0.0, br = 0.0;
+    for (int k = 0; k < RR_RPW; ++k, ++step) {
+      const int i = (g0 + q) * 64 + RR_RPW * pair + k;
+      const bool live = i < m;
+      const double *row = At + (size_t)(live ? i : 0) * ldr + c0;
+      double a[R2_TH];
+#pragma unroll
+      for (int t = 0; t < R2_TH; ++t) a[t] = live ? __builtin_nontemporal_load(row + 64 * t) : 0.0;
+      double c[4] = {0.0, 0.0, 0.0, 0.0}, e[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < R2_TH; ++t) {
+        c[t & 3] += a[t] * sx[c0 + 64 * t];
+        e[t & 3] += a[t] * sv[c0 + 64 * t];
+      }
+      const double px = wave_sum((c[0] + c[1]) + (c[2] + c[3]));
+      const double pv = wave_sum((e[0] + e[1]) + (e[2] + e[3]));
+      const int buf = step & 1;
+      if (lane == 0) { sd[buf][pair][h][0] = px; sd[buf][pair][h][1] = pv; }
+      __syncthreads();
+      // both waves of the pair add the halves in the same order
+      const double dot = sd[buf][pair][0][0] + sd[buf][pair][1][0];
+      const double dot2 = sd[buf][pair][0][1] + sd[buf][pair][1][1];
+      if (live) {
+        const double bi = b ? b[i] : 0.0;
+        const double ri = bi - dot;
+        if (h == 0) {
+          if (lane == 0) {
+            if (r) r[i] = ri;
+            if (t_out) t_out[i] = dot2;
+          }
+          rr += ri * ri;
+          br += bi * ri;
+        }
+#pragma unroll
+        for (int t = 0; t < R2_TH; ++t) {
+          pr[t] += a[t] * ri;
+          pq[t] += a[t] * dot2;
+        }
+      }
+    }
+    if (h == 0 && lane == 0) { srr[pair][q] = rr; sbr[pair][q] = br; }
+  }
+  // the pairs' A^T r (then A^T A v) joined in pair order
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int p = 0; p < RR_WAVES; ++p) {
+      if (pair == p) {
+#pragma unroll
+        for (int t = 0; t < R2_TH; ++t) {
+          const int col = c0 + 64 * t;
+          const double val = pass ? pq[t] : pr[t];
+          sp[col] = (p == 0) ? val : sp[col] + val;
+        }
+      }
+      __syncthreads();
+    }
+    double *dst = (pass == 0 ? ppart : ppart2) + (size_t)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += R2_WAVES * 64) dst[j] = sp[j];
+    __syncthreads();
+  }
+  if (part_r) {
+    for (int q = threadIdx.x; q < groups; q += R2_WAVES * 64) {
+      const int gq = g0 + q;
+      if (gq * 64 >= m) break;
+      double rr = 0.0, br = 0.0;
+      for (int v = 0; v < RR_WAVES; ++v) { rr += srr[v][q]; br += sbr[v][q]; }
+      part_r[2 * gq] = rr;
+      part_r[2 * gq + 1] = br;
+    }
+  }
+}
+
 // 64-row groups per workgroup of the row pass: about one workgroup per CU
 int rowpass_groups(int64_t m, int cus) {
   const int64_t ng = (m + 63) / 64;
@@ -298,8 +401,13 @@ static hipError_t rowpass_go(const MatView &A, const T *at, const double *b, con
                  ppart, v2, ppart2, t_out);
       break;
     case 64:
-      TLS_LAUNCH(cls, (k_resgrad_rows<64, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
-                 ppart, v2, ppart2, t_out);
+      if constexpr (DUAL && std::is_same<T, double>::value) {
+        TLS_LAUNCH(cls, k_resgrad_rows_dual64, g, dim3(R2_WAVES * 64), 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r,
+                   groups, ppart, v2, ppart2, t_out);
+      } else {
+        TLS_LAUNCH(cls, (k_resgrad_rows<64, T, DUAL>), g, t, 0, st, A.m, A.n, A.ldr, at, b, x, r, part_r, groups,
+                   ppart, v2, ppart2, t_out);
+      }
       break;
     default:
       return hipErrorInvalidValue;
